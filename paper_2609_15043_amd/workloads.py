@@ -1,0 +1,247 @@
+"""Synthetic argon ICP workloads for the RZ PIC/MCC step.
+
+This module only describes inputs: grid sizes, geometry tags, material maps,
+gas and species data, cross-section coefficients and the prescribed external
+azimuthal field.  It holds none of the method's arithmetic (no weighting, no
+push, no collision or field-solve step), so both the HIP path and the CPU
+oracle may read it.
+
+Workload recipes (the paper's GEC application, Sec. 3.4 and its conditions
+table, fixes density scale n0 = 1e16 m^-3 and argon gas; the cells below are
+synthetic stand-ins for the GEC cell, whose coil geometry is not tabulated):
+
+* ``small``  : cylinder R = 0.1 m, z = 0.1 m on 32 x 64 cells (N_r x N_z),
+  1e5 electrons + 1e5 Ar+, argon 10 mTorr / 300 K, dt = 5e-11 s, 200 steps,
+  prescribed E_theta phasor of one analytic current loop (a = 0.06 m,
+  1 cm above the top wall, 10 A peak), grounded walls.
+* ``cell``   : chamber R = 0.15 m, z = 0.2 m on 128 x 256 cells, quartz
+  window (eps_r = 3.8, 13 cells ~ 1 cm) on top of the plasma region
+  z < 0.15 m, vacuum compartment with a 5-turn planar coil, 2e6 + 2e6
+  particles, argon 20 mTorr, dt = 1/(2000 f).
+* ``large``  : same geometry on 256 x 512 cells, 3.2e7 + 3.2e7 particles,
+  argon 50 mTorr.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+from scipy import special
+
+# CODATA 2018 exact / recommended values (SI).
+QE = 1.602176634e-19
+ME = 9.1093837015e-31
+KB = 1.380649e-23
+AMU = 1.66053906660e-27
+EPS0 = 8.8541878128e-12
+MU0 = 1.25663706212e-6
+M_AR = 39.948 * AMU
+TORR = 101325.0 / 760.0
+
+ELECTRON, ION = 0, 1
+
+# Cross-section model kinds understood by both implementations.
+XS_ANALYTIC = 0   # smooth analytic fits (coefficients below)
+XS_CONSTANT = 1   # energy-independent cross sections (pins)
+
+
+@dataclasses.dataclass
+class CrossSections:
+    """Coefficients of the smooth analytic e-Ar and Ar+-Ar fits.
+
+    electrons, energy eps in eV, x = eps / threshold:
+      elastic     sig = el_a * (1 + eps/el_b)^(-1/2)
+      excitation  sig = exc_a * 4 (x-1)/x^2   for x > 1 (threshold exc_th)
+      ionization  sig = iz_a  * 4 (x-1)/x^2   for x > 1 (threshold iz_th)
+    ions, centre-of-mass energy eps_cm in eV:
+      elastic     sig = iel_a * (1 + eps_cm)^(-iel_p)
+      charge exch sig = icx_a * (1 + eps_cm)^(-icx_p)
+    With kind == XS_CONSTANT every sigma is its ``*_a`` value (thresholds
+    still apply to excitation / ionization).
+    """
+    kind: int = XS_ANALYTIC
+    el_a: float = 1.0e-19
+    el_b: float = 10.0
+    exc_a: float = 1.0e-20
+    exc_th: float = 11.5
+    iz_a: float = 3.0e-20
+    iz_th: float = 15.76
+    iel_a: float = 3.0e-19
+    iel_p: float = 0.2
+    icx_a: float = 5.0e-19
+    icx_p: float = 0.1
+    e_cap_ev: float = 1000.0      # electron energy range scanned for nu_max
+    i_gcap: float = 2.0e4         # ion relative-speed range scanned (m/s)
+    nu_margin: float = 1.01
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    nr: int
+    nz: int
+    rmax: float
+    zmax: float
+    zp: float                     # top of the particle region (a grid line)
+    dt: float
+    freq: float
+    nsteps: int
+    pressure_pa: float
+    tgas_k: float
+    n0: float
+    np_init: tuple                # (electrons, ions)
+    temp_ev: tuple                # (Te, Ti) of the initial Maxwellians
+    seed: int
+    eps_cell: np.ndarray          # (nz, nr) relative permittivity per cell
+    node_tag: np.ndarray          # (nz+1, nr+1) int32: -1 free, 0 grounded, k>=1 turn k
+    ec: np.ndarray                # (nz+1, nr+1) E_c of the azimuthal field (V/m)
+    es_sto: np.ndarray            # (nz+1, nr+1) stored sine array = -E_s (V/m)
+    turn_vc: np.ndarray           # (N,) V_c,k of the turn potentials (V)
+    turn_vs: np.ndarray           # (N,) V_s,k
+    bfield: tuple = (0.0, 0.0, 0.0)   # uniform (B_r, B_theta, B_z), tests only
+    xs: CrossSections = dataclasses.field(default_factory=CrossSections)
+    capacity_factor: float = 1.25
+
+    # derived, descriptive only
+    @property
+    def dr(self):
+        return self.rmax / self.nr
+
+    @property
+    def dz(self):
+        return self.zmax / self.nz
+
+    @property
+    def ip(self):
+        return int(round(self.zp / self.dz))
+
+    @property
+    def window(self):
+        return self.ip < self.nz
+
+    @property
+    def nturns(self):
+        return int(len(self.turn_vc))
+
+    @property
+    def ngas(self):
+        return self.pressure_pa / (KB * self.tgas_k)
+
+    @property
+    def tgas_ev(self):
+        return KB * self.tgas_k / QE
+
+    @property
+    def mass(self):
+        return (ME, M_AR)
+
+    @property
+    def charge(self):
+        return (-QE, QE)
+
+    @property
+    def weight(self):
+        vol = math.pi * self.rmax ** 2 * self.zp
+        return tuple(self.n0 * vol / n for n in self.np_init)
+
+    @property
+    def capacity(self):
+        return tuple(int(self.capacity_factor * n) + 4096 for n in self.np_init)
+
+    @property
+    def nodes(self):
+        return (self.nz + 1) * (self.nr + 1)
+
+
+def loop_field(nr, nz, rmax, zmax, a, z_loop, current, freq):
+    """E_c and stored -E_s of one circular current loop in free space.
+
+    The loop carries I(t) = current * cos(wt).  Its vector potential is the
+    textbook closed form with complete elliptic integrals; the induced field
+    phasor is -i w A_theta, i.e. E_c = 0 and stored sine array = -w A_theta.
+    """
+    R = np.arange(nr + 1) * (rmax / nr)
+    z = np.arange(nz + 1) * (zmax / nz)
+    Z, RR = np.meshgrid(z, R, indexing="ij")
+    A = np.zeros_like(RR)
+    m = RR > 0
+    k2 = 4 * a * RR[m] / ((a + RR[m]) ** 2 + (Z[m] - z_loop) ** 2)
+    k = np.sqrt(k2)
+    K = special.ellipk(k2)
+    E = special.ellipe(k2)
+    A[m] = MU0 * current / (math.pi * k) * np.sqrt(a / RR[m]) * ((1 - k2 / 2) * K - E)
+    w = 2 * math.pi * freq
+    return np.zeros_like(A), -w * A
+
+
+def small(seed=0, n_per_species=100_000, nsteps=200) -> Workload:
+    nr, nz, rmax, zmax = 32, 64, 0.1, 0.1
+    ec, es = loop_field(nr, nz, rmax, zmax, a=0.06, z_loop=0.11, current=10.0, freq=13.56e6)
+    tag = np.full((nz + 1, nr + 1), -1, np.int32)
+    tag[0, :] = 0
+    tag[nz, :] = 0
+    tag[:, nr] = 0
+    return Workload(
+        name="small", nr=nr, nz=nz, rmax=rmax, zmax=zmax, zp=zmax, dt=5e-11, freq=13.56e6,
+        nsteps=nsteps, pressure_pa=10e-3 * TORR, tgas_k=300.0, n0=1e16,
+        np_init=(n_per_species, n_per_species), temp_ev=(3.0, 0.026), seed=seed,
+        eps_cell=np.ones((nz, nr)), node_tag=tag, ec=ec, es_sto=es,
+        turn_vc=np.zeros(0), turn_vs=np.zeros(0))
+
+
+def _coil_cell(nr, nz, n_per_species, pressure_mtorr, name, seed, nsteps, coil_current=5.0,
+               v_feed=300.0):
+    """Chamber R = 0.15 m, z = 0.2 m: plasma z < 0.15 m, quartz window
+    0.15 m .. 0.15 m + 13 * 0.78125 mm, 5 planar turns in the vacuum
+    compartment above, grounded side wall, bottom and lid."""
+    rmax, zmax, freq = 0.15, 0.2, 13.56e6
+    dr, dz = rmax / nr, zmax / nz
+    ip = int(round(0.15 / dz))
+    iw = int(round((0.15 + 13 * 0.2 / 256) / dz))      # window top
+    eps = np.ones((nz, nr))
+    eps[ip:iw, :] = 3.8
+    tag = np.full((nz + 1, nr + 1), -1, np.int32)
+    tag[0, :] = 0
+    tag[nz, :] = 0
+    tag[:, nr] = 0
+    # turn k: nodes within +-1.2 mm radially and +-0.8 mm axially of the
+    # turn centre (R_k = 17 k coarse-cell widths, z_c = 213 coarse rows).
+    rc = [17 * k * (0.15 / 128) for k in range(1, 6)]
+    zc = 213 * (0.2 / 256)
+    R = np.arange(nr + 1) * dr
+    z = np.arange(nz + 1) * dz
+    for k, r0 in enumerate(rc, start=1):
+        jj = np.nonzero(np.abs(R - r0) <= 1.2e-3 + 1e-12)[0]
+        ii = np.nonzero(np.abs(z - zc) <= 0.8e-3 + 1e-12)[0]
+        tag[np.ix_(ii, jj)] = k
+    ec = np.zeros((nz + 1, nr + 1))
+    es = np.zeros((nz + 1, nr + 1))
+    for r0 in rc:
+        c, s = loop_field(nr, nz, rmax, zmax, a=r0, z_loop=zc, current=coil_current, freq=freq)
+        ec += c
+        es += s
+    # the free-space loop field is set to zero on metal and on the turn
+    # nodes themselves (where the closed form is singular); particles never
+    # reach either.
+    ec[tag >= 0] = 0.0
+    es[tag >= 0] = 0.0
+    vfeed = v_feed * np.array([(5 - k) / 5 + 0.2 for k in range(5)])
+    return Workload(
+        name=name, nr=nr, nz=nz, rmax=rmax, zmax=zmax, zp=ip * dz, dt=1.0 / (2000 * freq),
+        freq=freq, nsteps=nsteps, pressure_pa=pressure_mtorr * 1e-3 * TORR, tgas_k=300.0,
+        n0=1e16, np_init=(n_per_species, n_per_species), temp_ev=(3.0, 0.026), seed=seed,
+        eps_cell=eps, node_tag=tag, ec=ec, es_sto=es,
+        turn_vc=vfeed, turn_vs=np.zeros(5))
+
+
+def cell(seed=0, n_per_species=2_000_000, nsteps=20_000) -> Workload:
+    return _coil_cell(128, 256, n_per_species, 20.0, "cell", seed, nsteps)
+
+
+def large(seed=0, n_per_species=32_000_000, nsteps=4_000) -> Workload:
+    return _coil_cell(256, 512, n_per_species, 50.0, "large", seed, nsteps)
+
+
+def by_name(name, **kw) -> Workload:
+    return {"small": small, "cell": cell, "large": large}[name](**kw)

@@ -1,0 +1,387 @@
+"""Pins of the oracle's particle part against closed forms, invariants and an
+independent library generator (no GPU).
+
+Each test targets a plausible mistake: a wrong Philox round or key schedule,
+a wrong loading law, a sign or index slip in the kick, the move/rotation, the
+radial weights, the current deposit, or the collision laws.
+"""
+import math
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+from oracle import pic
+from paper_2609_15043_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+# ---------------------------------------------------------------------------
+# Philox4x32-10
+# ---------------------------------------------------------------------------
+def _rocrand_pin_binary(tmp_path_factory):
+    out = tmp_path_factory.mktemp("pin") / "philox_pin"
+    hipcc = "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available for the rocRAND library pin")
+    subprocess.check_call([hipcc, "-O1", "--offload-arch=gfx950", "-o", str(out),
+                           os.path.join(ROOT, "tests", "philox_rocrand_pin.cpp")])
+    return str(out)
+
+
+def test_philox_matches_rocrand_library(tmp_path_factory):
+    """The oracle's Philox4x32-10 equals rocRAND's engine on 20000 random
+    (counter, key) pairs: an independent implementation of the same
+    published generator (Salmon et al. SC'11)."""
+    exe = _rocrand_pin_binary(tmp_path_factory)
+    rng = np.random.default_rng(12345)
+    n = 20000
+    ctr = rng.integers(0, 2 ** 32, size=(n, 4), dtype=np.uint64).astype(np.uint32)
+    key = rng.integers(0, 2 ** 32, size=(n, 2), dtype=np.uint64).astype(np.uint32)
+    # a few structured cases: zero, all-ones, the counters the method uses
+    ctr[:4] = [[0, 0, 0, 0], [0xFFFFFFFF] * 4, [7, 123, 1, 0], [99, 0, 0, 0]]
+    key[:4] = [[0, 0], [0xFFFFFFFF] * 2, [0, 1], [3, 0]]
+    text = "\n".join(" ".join(str(int(v)) for v in list(c) + list(k)) for c, k in zip(ctr, key))
+    res = subprocess.run([exe], input=text.encode(), stdout=subprocess.PIPE, check=True)
+    ref = np.array(res.stdout.split(), dtype=np.uint64).reshape(n, 4).astype(np.uint32)
+    got = np.empty_like(ref)
+    # group by key for the oracle call
+    for i in range(n):
+        got[i] = pic.philox(ctr[i:i + 1], key[i])[0]
+    assert np.array_equal(got, ref)
+
+
+def test_philox_uniformity():
+    """Output words are uniform (chi-square over 256 bins) and each bit is
+    balanced, for consecutive particle ids at one step."""
+    n = 200_000
+    ctr = np.zeros((n, 4), np.uint32)
+    ctr[:, 0] = np.arange(n)
+    ctr[:, 1] = 17
+    ctr[:, 2] = 1
+    out = pic.philox(ctr, (0, 0))
+    for w in range(4):
+        h = np.bincount(out[:, w] >> 24, minlength=256)
+        e = n / 256
+        chi2 = ((h - e) ** 2 / e).sum()
+        assert chi2 < 255 + 6 * math.sqrt(2 * 255)
+        bits = ((out[:, w][:, None] >> np.arange(32, dtype=np.uint32)) & 1).mean(0)
+        assert np.all(np.abs(bits - 0.5) < 6 * 0.5 / math.sqrt(n))
+
+
+# ---------------------------------------------------------------------------
+# Loading
+# ---------------------------------------------------------------------------
+def test_load_uniform_in_volume_and_maxwellian():
+    wl = W.small(n_per_species=200_000)
+    P = pic.load_species(wl, 0)
+    n = P.n
+    # (R/Rmax)^2 and z/zp are U(0,1): compare the empirical CDF (KS)
+    for u in ((P.R / wl.rmax) ** 2, P.z / wl.zp):
+        us = np.sort(u)
+        d = np.max(np.abs(us - (np.arange(1, n + 1) - 0.5) / n))
+        assert d < 1.63 / math.sqrt(n)          # 1% KS critical value
+    vth = math.sqrt(wl.temp_ev[0] * W.QE / W.ME)
+    for v in (P.vr, P.vt, P.vz):
+        assert abs(v.mean()) < 5 * vth / math.sqrt(n)
+        assert abs(v.var() / vth ** 2 - 1) < 5 * math.sqrt(2 / n)
+    # independence of the components
+    assert abs(np.corrcoef(P.vr, P.vz)[0, 1]) < 5 / math.sqrt(n)
+    assert np.array_equal(P.id, np.arange(n, dtype=np.uint32))
+
+
+# ---------------------------------------------------------------------------
+# Push
+# ---------------------------------------------------------------------------
+def _parts(R, z, vr, vt, vz):
+    P = pic.Particles(len(R))
+    P.R[:], P.z[:], P.vr[:], P.vt[:], P.vz[:] = R, z, vr, vt, vz
+    P.id[:] = np.arange(len(R))
+    return P
+
+
+def test_leapfrog_uniform_ez_closed_form():
+    """Uniform E_z, B = 0, no radial motion: the leapfrog gives
+    z^n = z0 + n v0 dt + (q/m) E dt^2 n (n+1) / 2 exactly."""
+    g = pic.make_grid(8, 64, 0.1, 1.0)
+    dt, E = 1e-9, 250.0
+    S = pic.make_species(-W.QE, W.ME, 1.0, dt)
+    R0 = np.array([0.01, 0.05, 0.07])
+    z0 = np.array([0.40, 0.5, 0.6])
+    v0 = np.array([1e5, -2e5, 0.0])
+    P = _parts(R0, z0, 0 * R0, 0 * R0, v0)
+    qm = -W.QE / W.ME
+    for n in range(1, 41):
+        pic.gather_push_raw(g, S, P, 0.0, E, 0.0)
+        ref = z0 + n * v0 * dt + qm * E * dt * dt * n * (n + 1) / 2
+        np.testing.assert_allclose(P.z, ref, rtol=1e-13, atol=1e-15)
+        np.testing.assert_allclose(P.R, R0, rtol=1e-15)
+        np.testing.assert_allclose(P.vz, v0 + qm * E * dt * n, rtol=1e-13)
+
+
+def test_straight_line_through_axis():
+    """E = B = 0: the Cartesian move and the velocity rotation keep the
+    particle on the straight line, R(t) = |x0 + v t| in the plane, also
+    when the path passes next to the axis."""
+    g = pic.make_grid(16, 16, 0.2, 0.2)
+    dt = 1e-8
+    R0 = np.array([0.05, 0.03, 0.08])
+    vx = np.array([-1e5, -4e4, 3e4])       # radial (x) component at t = 0
+    vy = np.array([2e3, -1e3, 5e4])        # azimuthal (y) component at t = 0
+    P = _parts(R0, np.full(3, 0.1), vx, vy, np.zeros(3))
+    S = pic.make_species(W.QE, W.M_AR, 1.0, dt)
+    for n in range(1, 81):
+        pic.gather_push_raw(g, S, P, 0.0, 0.0, 0.0)
+        x = R0 + vx * n * dt
+        y = vy * n * dt
+        np.testing.assert_allclose(P.R, np.hypot(x, y), rtol=1e-12, atol=1e-15)
+        # speed is conserved and (vr, vt) is the same Cartesian vector seen
+        # from the particle's current azimuth
+        np.testing.assert_allclose(np.hypot(P.vr, P.vt), np.hypot(vx, vy), rtol=1e-13)
+        vr_ref = (vx * x + vy * y) / np.hypot(x, y)
+        np.testing.assert_allclose(P.vr, vr_ref, rtol=1e-11, atol=1e-9)
+
+
+def test_boris_rotation_angle_uniform_b():
+    """Uniform B along z, E = 0: each step rotates the velocity about B by
+    exactly -2 atan(q B dt / 2m) (Boris); |v| is conserved."""
+    g = pic.make_grid(16, 16, 0.2, 0.2)
+    dt, B = 2e-11, 0.01
+    q, m = -W.QE, W.ME
+    S = pic.make_species(q, m, 1.0, dt, b=(0.0, 0.0, B))
+    P = _parts(np.array([0.1]), np.array([0.1]), np.array([3e5]), np.array([1e5]), np.array([2e5]))
+    ang = -2 * math.atan(q * B * dt / (2 * m))
+    # Track the Cartesian velocity: the frame turns by atan2(Y, X) each move.
+    psi = 0.0
+    v_cart = np.array([3e5, 1e5])
+    for _ in range(50):
+        R, vr, vt = P.R[0], P.vr[0], P.vt[0]
+        pic.gather_push_raw(g, S, P, 0.0, 0.0, 0.0)
+        # the kicked velocity before the frame rotation, in the old frame
+        c, s = math.cos(ang), math.sin(ang)
+        v_rot = np.array([c * vr - s * vt, s * vr + c * vt])
+        X, Y = R + v_rot[0] * dt, v_rot[1] * dt
+        dpsi = math.atan2(Y, X)
+        cs, sn = math.cos(dpsi), math.sin(dpsi)
+        np.testing.assert_allclose([P.vr[0], P.vt[0]],
+                                   [cs * v_rot[0] + sn * v_rot[1], -sn * v_rot[0] + cs * v_rot[1]],
+                                   rtol=1e-12, atol=1e-6)
+        psi += dpsi
+    np.testing.assert_allclose(P.vz[0], 2e5, rtol=1e-14)
+    np.testing.assert_allclose(math.hypot(P.vr[0], P.vt[0]), math.hypot(3e5, 1e5), rtol=1e-13)
+
+
+def test_energy_identity_and_current_deposit():
+    """B = 0: per particle (m/2)(|v+|^2 - |v-|^2) = q dt E.vbar exactly, and
+    sum_nodes I E_theta = sum_p q w vbar_theta E_theta,p (the current is
+    deposited with the gather weights)."""
+    rng = np.random.default_rng(3)
+    g = pic.make_grid(12, 20, 0.12, 0.2)
+    shape = (21, 13)
+    Er, Ez, Et = (rng.normal(0, 1e3, shape) for _ in range(3))
+    n = 5000
+    R = 0.12 * np.sqrt(rng.random(n)) * 0.999
+    z = 0.2 * rng.random(n)
+    v = rng.normal(0, 3e5, (n, 3))
+    P = _parts(R, z, v[:, 0], v[:, 1], v[:, 2])
+    dt, q, m, w = 1e-11, -W.QE, W.ME, 3.0e7
+    S = pic.make_species(q, m, w, dt)
+    # the field at each particle, from the oracle's own weights (expected)
+    j = np.minimum((R / g.dr).astype(int), 11)
+    i = np.minimum((z / g.dz).astype(int), 19)
+    wr1 = (R ** 2 - (j * g.dr) ** 2) / (((j + 1) * g.dr) ** 2 - (j * g.dr) ** 2)
+    wz1 = z / g.dz - i
+    def at(F):
+        return ((1 - wz1) * (1 - wr1) * F[i, j] + (1 - wz1) * wr1 * F[i, j + 1]
+                + wz1 * (1 - wr1) * F[i + 1, j] + wz1 * wr1 * F[i + 1, j + 1])
+    Ep = np.stack([at(Er), at(Et), at(Ez)], 1)
+    v_old = v.copy()
+    I, surf, ab = pic.gather_push_raw(g, S, P, Er, Ez, Et)
+    v_new_local = v_old + (q / m) * Ep * dt            # B = 0: the kick is linear
+    vbar = 0.5 * (v_old + v_new_local)
+    lhs = 0.5 * m * ((v_new_local ** 2).sum(1) - (v_old ** 2).sum(1))
+    rhs = q * dt * (Ep * vbar).sum(1)
+    np.testing.assert_allclose(lhs, rhs, rtol=1e-9, atol=1e-30)
+    # the deposited current carries exactly the E_theta work
+    work_nodes = np.sum(I * Et)
+    work_parts = np.sum(q * w * vbar[:, 1] * Ep[:, 1] * (ab >= 0))
+    assert abs(work_nodes - work_parts) <= 1e-12 * np.sum(np.abs(q * w * vbar[:, 1] * Ep[:, 1]))
+    # speeds after the move are those of the kick (rotation preserves |v|)
+    np.testing.assert_allclose(np.sqrt(P.vr ** 2 + P.vt ** 2 + P.vz ** 2),
+                               np.sqrt((v_new_local ** 2).sum(1)), rtol=1e-13)
+
+
+def test_window_surface_charge_and_absorption():
+    """Particles leaving through z = zp with a window leave q w on the window
+    row at the crossing radius; through other walls they just vanish."""
+    g = pic.make_grid(10, 20, 0.1, 0.2, zp=0.15, window=True)
+    dt = 1e-9
+    q, w = W.QE, 2.0
+    S = pic.make_species(q, W.M_AR, w, dt)
+    P = _parts(np.array([0.03, 0.05, 0.099, 0.02]), np.array([0.1499, 0.001, 0.1, 0.149]),
+               np.array([0.0, 0.0, 4e6, 1e6]), np.array([0.0, 0.0, 0.0, 0.0]),
+               np.array([1e6, -2e6, 0.0, 1e6]))
+    I, surf, ab = pic.gather_push_raw(g, S, P, 0.0, 0.0, 0.0)
+    assert list(ab) == [2, 1, 1, 2]
+    assert list(P.alive) == [0, 0, 0, 0]
+    assert surf.sum() == pytest.approx(2 * q * w, rel=1e-14)
+    assert np.all(surf[np.arange(21) != 15] == 0)
+    # crossing radius of particle 3: R = 0.02 + 1e6 * t*, t* = (0.15 - 0.149)/1e6
+    Rs = 0.02 + 1e6 * (0.001 / 1e6)
+    jj = int(Rs / g.dr)
+    w1 = (Rs ** 2 - (jj * g.dr) ** 2) / (((jj + 1) * g.dr) ** 2 - (jj * g.dr) ** 2)
+    expect = np.zeros(11)
+    expect[3] += q * w          # particle 0 crosses exactly at node R = 0.03
+    expect[jj] += q * w * (1 - w1)
+    expect[jj + 1] += q * w * w1
+    np.testing.assert_allclose(surf[15], expect, rtol=1e-12, atol=1e-30)
+
+
+# ---------------------------------------------------------------------------
+# Deposit
+# ---------------------------------------------------------------------------
+def test_deposit_conserves_charge_and_uniform_load_is_flat():
+    """sum_nodes Q = sum_p q w (exact to rounding); a uniform-in-volume load
+    gives a flat density Q_node / V_node, V_node = pi dz (R_{j+1}^2 -
+    R_{j-1}^2)/2 (pi dR^2 dz/2 on the axis), within 4 sigma per node."""
+    wl = W.small(n_per_species=400_000)
+    P = pic.load_species(wl, 1)
+    g = pic.make_grid(wl.nr, wl.nz, wl.rmax, wl.zmax)
+    qw = 1.0
+    Q = pic.deposit_raw(g, P, qw)
+    assert Q.sum() == pytest.approx(P.n * qw, rel=1e-13)
+    dr, dz = wl.dr, wl.dz
+    R = np.arange(wl.nr + 1) * dr
+    Vr = np.empty(wl.nr + 1)
+    Vr[0] = math.pi * dr * dr / 2
+    Vr[1:-1] = math.pi * (R[2:] ** 2 - R[:-2] ** 2) / 2
+    Vr[-1] = math.pi * (R[-1] ** 2 - R[-2] ** 2) / 2
+    Vz = np.full(wl.nz + 1, dz)
+    Vz[0] = Vz[-1] = dz / 2
+    V = Vz[:, None] * Vr[None, :]
+    n_mean = P.n / (math.pi * wl.rmax ** 2 * wl.zmax)
+    inner = (slice(1, -1), slice(0, -1))
+    expect = n_mean * V[inner]
+    # a node's count is a sum of Bernoulli-weighted contributions: var <= mean
+    z = (Q[inner] - expect) / np.sqrt(expect)
+    assert np.max(np.abs(z)) < 5.0
+    assert abs(z.mean()) < 5.0 / math.sqrt(z.size)
+
+
+# ---------------------------------------------------------------------------
+# MCC
+# ---------------------------------------------------------------------------
+def _gas(wl):
+    return pic.gas_struct(wl)
+
+
+def test_null_collision_threshold_and_numax():
+    """T = floor(P_null 2^32) with P_null = 1 - exp(-nu_max dt); nu_max is
+    1.01 x the maximum of n_g sigma_T v over the scanned range, which for
+    constant sigma sits at the range's end."""
+    wl = W.small()
+    wl.xs = W.CrossSections(kind=W.XS_CONSTANT)
+    nu, pn, th = pic.null_setup(wl, nscan=1000)
+    vmax = math.sqrt(2 * wl.xs.e_cap_ev * W.QE / W.ME)
+    sig = wl.xs.el_a + wl.xs.exc_a + wl.xs.iz_a
+    assert nu[0] == pytest.approx(1.01 * wl.ngas * sig * vmax, rel=1e-12)
+    assert nu[1] == pytest.approx(1.01 * wl.ngas * (wl.xs.iel_a + wl.xs.icx_a) * wl.xs.i_gcap, rel=1e-12)
+    assert pn[0] == pytest.approx(-math.expm1(-nu[0] * wl.dt), rel=1e-12)
+    assert th[0] == math.floor(pn[0] * 2 ** 32)
+
+
+def test_mcc_event_counts_constant_sigma():
+    """Constant sigma: candidates ~ Binomial(N, P_null); given a candidate the
+    process j happens with probability nu_j / nu_max (nu_j = n_g sigma_j v)."""
+    wl = W.small()
+    wl.xs = W.CrossSections(kind=W.XS_CONSTANT)
+    nu, pn, th = pic.null_setup(wl)
+    n = 400_000
+    rng = np.random.default_rng(5)
+    speed = np.full(n, math.sqrt(2 * 20.0 * W.QE / W.ME))    # 20 eV: all 3 processes open
+    d = rng.normal(size=(n, 3))
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    P = _parts(np.full(n, 0.05), np.full(n, 0.05), speed * d[:, 0], speed * d[:, 1], speed * d[:, 2])
+    cnt, births = pic.mcc_raw(0, 0, 7, pic.xs_struct(wl.xs), _gas(wl), nu[0], th[0], P)
+    p = th[0] / 2 ** 32
+    assert abs(cnt[0] - n * p) < 5 * math.sqrt(n * p * (1 - p))
+    for k, s in ((1, wl.xs.el_a), (2, wl.xs.exc_a), (3, wl.xs.iz_a)):
+        q = wl.ngas * s * speed[0] / nu[0]
+        assert abs(cnt[k] - cnt[0] * q) < 5 * math.sqrt(cnt[0] * q * (1 - q))
+    assert len(births["parent"]) == cnt[3]
+    assert cnt[4] == 0
+
+
+def test_mcc_electron_energy_laws():
+    """Excitation removes exactly E_exc; ionization conserves
+    eps - E_iz = eps_primary + eps_secondary; elastic loses the fraction
+    (2m/M)(1 - cos chi), so eps' lies in [eps (1 - 4m/M), eps]."""
+    wl = W.small()
+    nu, pn, th = pic.null_setup(wl)
+    n = 300_000
+    rng = np.random.default_rng(11)
+    eps0 = rng.uniform(16.0, 80.0, n)
+    speed = np.sqrt(2 * eps0 * W.QE / W.ME)
+    d = rng.normal(size=(n, 3))
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    v0 = speed[:, None] * d
+    P = _parts(np.full(n, 0.05), np.full(n, 0.05), v0[:, 0], v0[:, 1], v0[:, 2])
+    cnt, births = pic.mcc_raw(0, 3, 9, pic.xs_struct(wl.xs), _gas(wl), nu[0], 2 ** 32 - 1, P)
+    eps0 = 0.5 * W.ME * (v0 ** 2).sum(1) / W.QE
+    eps1 = 0.5 * W.ME * (P.vr ** 2 + P.vt ** 2 + P.vz ** 2) / W.QE
+    changed = np.any(np.stack([P.vr, P.vt, P.vz], 1) != v0, axis=1)
+    # identify the process of each changed particle by its energy change
+    exc = np.isclose(eps0 - eps1, wl.xs.exc_th, rtol=0, atol=1e-9)
+    assert exc.sum() == cnt[2]
+    par = births["parent"]
+    esec = 0.5 * W.ME * (births["ve"] ** 2).sum(1) / W.QE
+    np.testing.assert_allclose(eps1[par] + esec, eps0[par] - wl.xs.iz_th, rtol=1e-12)
+    el = changed & ~exc
+    el[par] = False
+    assert el.sum() == cnt[1]
+    ratio = eps1[el] / eps0[el]
+    assert ratio.max() <= 1 + 1e-12
+    assert ratio.min() >= 1 - 4 * W.ME / W.M_AR - 1e-12
+    # new ions are room-temperature Maxwellians at the parent's position
+    vi = births["vi"]
+    vg2 = wl.tgas_ev * W.QE / W.M_AR
+    assert abs(vi.var() / vg2 - 1) < 6 * math.sqrt(2 / vi.size)
+
+
+def test_mcc_ion_elastic_conserves_momentum_and_energy():
+    """Ar+-Ar elastic: isotropic in the centre-of-mass frame, so
+    |v_i' - v_cm| = |g| / 2 and the ion + neutral momentum and energy are
+    unchanged; charge exchange takes the neutral's velocity."""
+    wl = W.small()
+    xs = W.CrossSections(kind=W.XS_CONSTANT, icx_a=1e-30)   # elastic only
+    nu, pn, th = pic.null_setup(W.Workload(**{**wl.__dict__, "xs": xs}))
+    n = 50_000
+    rng = np.random.default_rng(2)
+    v0 = rng.normal(0, 3e3, (n, 3))
+    P = _parts(np.full(n, 0.05), np.full(n, 0.05), v0[:, 0], v0[:, 1], v0[:, 2])
+    P.id[:] = np.arange(n)
+    cnt, _ = pic.mcc_raw(1, 0, 4, pic.xs_struct(xs), _gas(wl), nu[1], 2 ** 32 - 1, P)
+    # neutral partner velocity: Box-Muller of block (id, step, 2, 0), words (0,1),(2,3)
+    ctr = np.zeros((n, 4), np.uint32)
+    ctr[:, 0] = np.arange(n)
+    ctr[:, 1] = 4
+    ctr[:, 2] = 2
+    b = pic.philox(ctr, (0, 1)).astype(np.float64)
+    u = (b + 0.5) / 2 ** 32
+    vg = math.sqrt(wl.tgas_ev * W.QE / W.M_AR)
+    r01 = np.sqrt(-2 * np.log(u[:, 0]))
+    r23 = np.sqrt(-2 * np.log(u[:, 2]))
+    vn = vg * np.stack([r01 * np.cos(2 * np.pi * u[:, 1]), r01 * np.sin(2 * np.pi * u[:, 1]),
+                        r23 * np.cos(2 * np.pi * u[:, 3])], 1)
+    v1 = np.stack([P.vr, P.vt, P.vz], 1)
+    moved = np.any(v1 != v0, axis=1)
+    assert moved.sum() == cnt[1]
+    vcm = 0.5 * (v0 + vn)
+    g = np.linalg.norm(v0 - vn, axis=1)
+    np.testing.assert_allclose(np.linalg.norm(v1 - vcm, axis=1)[moved], 0.5 * g[moved], rtol=1e-10)
+    vn1 = 2 * vcm - v1
+    e0 = (v0 ** 2).sum(1) + (vn ** 2).sum(1)
+    e1 = (v1 ** 2).sum(1) + (vn1 ** 2).sum(1)
+    np.testing.assert_allclose(e1[moved], e0[moved], rtol=1e-10)
