@@ -99,6 +99,19 @@ static void iso_dir(uint32_t a, uint32_t b, double d[3])
     d[2] = ct;
 }
 
+/* Gap to the next null-collision candidate.  Candidates of one particle
+ * form a Bernoulli process in the step index with probability P per step,
+ * so the gaps are i.i.d. Geometric(P) on {1, 2, ...}:
+ * G = 1 + floor(log(u) / log(1 - P)), with lq = log(1 - P) < 0. */
+static int64_t geo_gap(uint32_t x, double lq)
+{
+    double g = floor(log(u01(x)) / lq);
+    if (g > 2.0e9) g = 2.0e9;
+    return 1 + (int64_t)g;
+}
+
+static int32_t clamp_step(int64_t s) { return s > 2147483647 ? 2147483647 : (int32_t)s; }
+
 /* ---------------------------------------------------------------------- */
 /* Geometry and parameters                                                 */
 /* ---------------------------------------------------------------------- */
@@ -150,8 +163,11 @@ static void weights(const ora_grid *g, double R, double z, int *j, int *i, doubl
 /* ---------------------------------------------------------------------- */
 /* Loading: uniform in volume, Maxwellian velocities                       */
 /* ---------------------------------------------------------------------- */
+/* next[p]: the first null-collision candidate step, G - 1 from word 2 of
+ * the second load block (lq = log(1 - P_null) of this species). */
 void ora_load(int64_t n, uint32_t seed, int sp, double rmax, double zlo, double zhi, double vth,
-              double *R, double *z, double *vr, double *vt, double *vz, uint32_t *id)
+              double lq, double *R, double *z, double *vr, double *vt, double *vz, uint32_t *id,
+              int32_t *next)
 {
     for (int64_t p = 0; p < n; ++p) {
         uint32_t a[4], b[4];
@@ -166,6 +182,7 @@ void ora_load(int64_t n, uint32_t seed, int sp, double rmax, double zlo, double 
         vt[p] = vth * g1;
         vz[p] = vth * g2;
         id[p] = (uint32_t)p;
+        next[p] = clamp_step(geo_gap(b[2], lq) - 1);
     }
 }
 
@@ -318,10 +335,10 @@ void ora_sigma_i(const ora_xs *x, double ecm, double sig[2])
 }
 
 /* Maximum total collision frequency over the scanned range (times the
- * margin), the null-collision probability per step and its 32-bit integer
- * threshold.  out_nu[2], out_p[2], out_t[2] for (electron, ion). */
+ * margin), the null-collision probability per step and log(1 - P).
+ * out_nu[2], out_p[2], out_lq[2] for (electron, ion). */
 void ora_null_setup(const ora_xs *x, const ora_gas *gs, double dt, int64_t nscan,
-                    double *out_nu, double *out_p, uint32_t *out_t)
+                    double *out_nu, double *out_p, double *out_lq)
 {
     double best_e = 0.0, best_i = 0.0;
     for (int64_t k = 0; k <= nscan; ++k) {
@@ -341,8 +358,8 @@ void ora_null_setup(const ora_xs *x, const ora_gas *gs, double dt, int64_t nscan
     out_nu[0] = best_e * x->nu_margin;
     out_nu[1] = best_i * x->nu_margin;
     for (int s = 0; s < 2; ++s) {
-        out_p[s] = 1.0 - exp(-out_nu[s] * dt);
-        out_t[s] = (uint32_t)floor(out_p[s] * 4294967296.0);
+        out_p[s] = -expm1(-out_nu[s] * dt);
+        out_lq[s] = -out_nu[s] * dt;   /* log(1 - P) = -nu_max dt exactly */
     }
 }
 
@@ -350,7 +367,10 @@ void ora_null_setup(const ora_xs *x, const ora_gas *gs, double dt, int64_t nscan
 /* Null-collision MCC on v^{n+1/2}                                          */
 /* ---------------------------------------------------------------------- */
 /*
- * Electron-neutral (neutral at rest): candidate iff x0 < T; then
+ * A particle is a candidate at step n iff next[p] == n; its block
+ * (id, n, 1, 0) then gives the next gap from word x0 (next = n + G).
+ *
+ * Electron-neutral (neutral at rest): at a candidate,
  * R = u(x1) nu_max against the cumulative nu_el, nu_exc, nu_iz; every real
  * collision picks an isotropic lab direction from (x2, x3).  Ionization
  * shares eps - E_iz uniformly (block purpose 2, word 0), the secondary's
@@ -358,29 +378,32 @@ void ora_null_setup(const ora_xs *x, const ora_gas *gs, double dt, int64_t nscan
  * Maxwellian from block purpose 3.
  *
  * Ion-neutral: neutral velocity from block purpose 2 (Box-Muller of words
- * 0,1 and 2,3); candidate iff x0 < T; R = u(x1) nu_max against nu_el,
+ * 0,1 and 2,3); at a candidate R = u(x1) nu_max against nu_el,
  * nu_cx with g = |v_i - v_n|; charge exchange takes the neutral velocity,
  * elastic scattering is isotropic in the centre-of-mass frame.
  *
  * counts[0..3]: candidates, process 1, process 2, process 3 (ions: no 3rd);
  * counts[4]: candidates whose total frequency exceeded nu_max.
- * Births (electrons only) go to the b_* arrays, at most bcap of them;
- * returns the number of births or -1 on overflow.
+ * Births (electrons only) go to the b_* arrays, at most bcap of them; a
+ * newborn's first candidate is step + G with G from word 3 of block
+ * purpose 2 (electron, lq_e) or 3 (ion, lq_i).  Returns the number of
+ * births or -1 on overflow.
  */
 int64_t ora_mcc(int sp, uint32_t seed, uint32_t step, const ora_xs *x, const ora_gas *gs,
-                double numax, uint32_t thresh, int64_t n,
+                double numax, double lq, double lq_ion, int64_t n,
                 const double *R, const double *z, double *vr, double *vt, double *vz,
-                const uint32_t *id, const int32_t *alive,
+                const uint32_t *id, const int32_t *alive, int32_t *next,
                 int64_t bcap, uint32_t *b_parent, double *b_R, double *b_z,
-                double *b_ve, double *b_vi, int64_t *counts)
+                double *b_ve, double *b_vi, int32_t *b_next, int64_t *counts)
 {
     int64_t nb = 0;
     const double vg = sqrt(gs->tgas_ev * gs->qe / gs->mi);
     for (int64_t p = 0; p < n; ++p) {
         if (!alive[p]) continue;
+        if (next[p] != (int32_t)step) continue;
         uint32_t b0[4];
         draw(seed, sp, id[p], step, 1u, b0);
-        if (b0[0] >= thresh) continue;
+        next[p] = clamp_step((int64_t)step + geo_gap(b0[0], lq));
         counts[0]++;
         double v[3] = {vr[p], vt[p], vz[p]};
         if (sp == 0) {
@@ -433,6 +456,8 @@ int64_t ora_mcc(int sp, uint32_t seed, uint32_t step, const ora_xs *x, const ora
                 b_vi[3 * nb + 0] = vg * g0;
                 b_vi[3 * nb + 1] = vg * g1;
                 b_vi[3 * nb + 2] = vg * g2;
+                b_next[2 * nb + 0] = clamp_step((int64_t)step + geo_gap(b2[3], lq));
+                b_next[2 * nb + 1] = clamp_step((int64_t)step + geo_gap(b3[3], lq_ion));
                 nb++;
             }
         } else {

@@ -90,8 +90,8 @@ def lib():
             build()
         L = ctypes.CDLL(path)
         L.ora_philox_many.argtypes = [_I64, ctypes.POINTER(_U32), _U32, _U32, ctypes.POINTER(_U32)]
-        L.ora_load.argtypes = [_I64, _U32, ctypes.c_int, _D, _D, _D, _D] + \
-            [ctypes.POINTER(_D)] * 5 + [ctypes.POINTER(_U32)]
+        L.ora_load.argtypes = [_I64, _U32, ctypes.c_int, _D, _D, _D, _D, _D] + \
+            [ctypes.POINTER(_D)] * 5 + [ctypes.POINTER(_U32), ctypes.POINTER(_I32)]
         L.ora_gather_push.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Species), _I64] + \
             [ctypes.POINTER(_D)] * 5 + [ctypes.POINTER(_I32)] * 2 + [ctypes.POINTER(_D)] * 5
         L.ora_deposit.argtypes = [ctypes.POINTER(Grid), _I64, ctypes.POINTER(_D), ctypes.POINTER(_D),
@@ -99,13 +99,13 @@ def lib():
         L.ora_sigma_e.argtypes = [ctypes.POINTER(XS), _D, ctypes.POINTER(_D)]
         L.ora_sigma_i.argtypes = [ctypes.POINTER(XS), _D, ctypes.POINTER(_D)]
         L.ora_null_setup.argtypes = [ctypes.POINTER(XS), ctypes.POINTER(Gas), _D, _I64,
-                                     ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_U32)]
-        L.ora_mcc.argtypes = [ctypes.c_int, _U32, _U32, ctypes.POINTER(XS), ctypes.POINTER(Gas), _D, _U32,
+                                     ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_D)]
+        L.ora_mcc.argtypes = [ctypes.c_int, _U32, _U32, ctypes.POINTER(XS), ctypes.POINTER(Gas), _D, _D, _D,
                               _I64, ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_D),
                               ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_U32),
-                              ctypes.POINTER(_I32), _I64, ctypes.POINTER(_U32), ctypes.POINTER(_D),
-                              ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_D),
-                              ctypes.POINTER(_I64)]
+                              ctypes.POINTER(_I32), ctypes.POINTER(_I32), _I64, ctypes.POINTER(_U32),
+                              ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_D),
+                              ctypes.POINTER(_I32), ctypes.POINTER(_I64)]
         L.ora_mcc.restype = _I64
         _LIB = L
     return _LIB
@@ -138,14 +138,17 @@ def gas_struct(wl):
     return g
 
 
-def null_setup(wl, nscan=200_000):
-    """(nu_max[2], P_null[2], threshold[2]) for electrons and ions."""
+NSCAN = 200_000
+
+
+def null_setup(wl, nscan=NSCAN):
+    """(nu_max[2], P_null[2], log(1 - P_null)[2]) for electrons and ions."""
     nu = np.zeros(2)
     pn = np.zeros(2)
-    th = np.zeros(2, np.uint32)
+    lq = np.zeros(2)
     x, g = xs_struct(wl.xs), gas_struct(wl)
-    lib().ora_null_setup(ctypes.byref(x), ctypes.byref(g), wl.dt, nscan, _p(nu, _D), _p(pn, _D), _p(th, _U32))
-    return nu, pn, th
+    lib().ora_null_setup(ctypes.byref(x), ctypes.byref(g), wl.dt, nscan, _p(nu, _D), _p(pn, _D), _p(lq, _D))
+    return nu, pn, lq
 
 
 def sigma_e(xs, eps):
@@ -172,12 +175,13 @@ class Particles:
         self.vz = np.zeros(n)
         self.id = np.zeros(n, np.uint32)
         self.alive = np.ones(n, np.int32)
+        self.next = np.zeros(n, np.int32)
 
     @property
     def n(self):
         return len(self.R)
 
-    def append(self, R, z, v, ids):
+    def append(self, R, z, v, ids, nxt):
         self.R = np.concatenate([self.R, R])
         self.z = np.concatenate([self.z, z])
         self.vr = np.concatenate([self.vr, v[:, 0]])
@@ -185,26 +189,29 @@ class Particles:
         self.vz = np.concatenate([self.vz, v[:, 2]])
         self.id = np.concatenate([self.id, ids.astype(np.uint32)])
         self.alive = np.concatenate([self.alive, np.ones(len(R), np.int32)])
+        self.next = np.concatenate([self.next, nxt.astype(np.int32)])
 
     def compact(self):
         m = self.alive.astype(bool)
-        for k in ("R", "z", "vr", "vt", "vz", "id", "alive"):
+        for k in ("R", "z", "vr", "vt", "vz", "id", "alive", "next"):
             setattr(self, k, getattr(self, k)[m].copy())
 
     def live(self):
         """Dict of the live particles, sorted by id."""
         m = self.alive.astype(bool)
         o = np.argsort(self.id[m], kind="stable")
-        return {k: getattr(self, k)[m][o] for k in ("id", "R", "z", "vr", "vt", "vz")}
+        return {k: getattr(self, k)[m][o] for k in ("id", "R", "z", "vr", "vt", "vz", "next")}
 
 
-def load_species(wl, s):
+def load_species(wl, s, lq=None):
     from paper_2609_15043_amd import workloads as W
+    if lq is None:
+        lq = null_setup(wl)[2][s]
     n = wl.np_init[s]
     P = Particles(n)
     vth = math.sqrt(wl.temp_ev[s] * W.QE / wl.mass[s])
-    lib().ora_load(n, _U32(wl.seed), s, wl.rmax, 0.0, wl.zp, vth, _p(P.R, _D), _p(P.z, _D), _p(P.vr, _D),
-                   _p(P.vt, _D), _p(P.vz, _D), _p(P.id, _U32))
+    lib().ora_load(n, _U32(wl.seed), s, wl.rmax, 0.0, wl.zp, vth, float(lq), _p(P.R, _D), _p(P.z, _D),
+                   _p(P.vr, _D), _p(P.vt, _D), _p(P.vz, _D), _p(P.id, _U32), _p(P.next, _I32))
     return P
 
 
@@ -428,13 +435,13 @@ class OraclePIC:
                 S.b[c] = wl.bfield[c]
             self.sp.append(S)
         self.nrf, self.closed = n_rf(wl.freq, wl.dt)
-        self.numax, self.pnull, self.thresh = null_setup(wl)
+        self.numax, self.pnull, self.lq = null_setup(wl)
         self.xs, self.gas = xs_struct(wl.xs), gas_struct(wl)
         shape = (wl.nz + 1, wl.nr + 1)
         self.shape = shape
         self.poisson = Poisson(wl.nr, wl.nz, wl.dr, wl.dz, wl.eps_cell, wl.node_tag, W.EPS0)
         self.surf = np.zeros(shape)
-        self.parts = [load_species(wl, s) if load else Particles(0) for s in range(2)]
+        self.parts = [load_species(wl, s, self.lq[s]) if load else Particles(0) for s in range(2)]
         self.next_id = [wl.np_init[0], wl.np_init[1]]
         self.counts = np.zeros((2, 5), np.int64)
         self.n = 0
@@ -477,26 +484,27 @@ class OraclePIC:
             bp = np.zeros(bcap, np.uint32)
             bR, bz = np.zeros(bcap), np.zeros(bcap)
             bve, bvi = np.zeros((bcap, 3)), np.zeros((bcap, 3))
+            bnx = np.zeros((bcap, 2), np.int32)
             cnt = np.zeros(5, np.int64)
             nb = lib().ora_mcc(s, _U32(self.wl.seed), _U32(n), ctypes.byref(self.xs), ctypes.byref(self.gas),
-                               float(self.numax[s]), _U32(int(self.thresh[s])), P.n, _p(P.R, _D),
+                               float(self.numax[s]), float(self.lq[s]), float(self.lq[1]), P.n, _p(P.R, _D),
                                _p(P.z, _D), _p(P.vr, _D), _p(P.vt, _D), _p(P.vz, _D), _p(P.id, _U32),
-                               _p(P.alive, _I32), bcap, _p(bp, _U32), _p(bR, _D), _p(bz, _D),
-                               _p(bve, _D), _p(bvi, _D), _p(cnt, _I64))
+                               _p(P.alive, _I32), _p(P.next, _I32), bcap, _p(bp, _U32), _p(bR, _D),
+                               _p(bz, _D), _p(bve, _D), _p(bvi, _D), _p(bnx, _I32), _p(cnt, _I64))
             if nb < 0:
                 raise RuntimeError("oracle birth buffer overflow")
             self.counts[s] += cnt
-            births.append((bp[:nb], bR[:nb], bz[:nb], bve[:nb], bvi[:nb]))
+            births.append((bp[:nb], bR[:nb], bz[:nb], bve[:nb], bvi[:nb], bnx[:nb]))
         # births: electron-impact ionization only; ids in order of parent id
-        bp, bR, bz, bve, bvi = births[0]
+        bp, bR, bz, bve, bvi, bnx = births[0]
         o = np.argsort(bp, kind="stable")
-        bp, bR, bz, bve, bvi = bp[o], bR[o], bz[o], bve[o], bvi[o]
+        bp, bR, bz, bve, bvi, bnx = bp[o], bR[o], bz[o], bve[o], bvi[o], bnx[o]
         nb = len(bp)
         if nb:
             ide = np.arange(self.next_id[0], self.next_id[0] + nb, dtype=np.uint64)
             idi = np.arange(self.next_id[1], self.next_id[1] + nb, dtype=np.uint64)
-            self.parts[0].append(bR, bz, bve, ide)
-            self.parts[1].append(bR.copy(), bz.copy(), bvi, idi)
+            self.parts[0].append(bR, bz, bve, ide, bnx[:, 0])
+            self.parts[1].append(bR.copy(), bz.copy(), bvi, idi, bnx[:, 1])
             self.next_id[0] += nb
             self.next_id[1] += nb
         self.last_births = (bp, ide if nb else np.zeros(0), idi if nb else np.zeros(0))
@@ -573,17 +581,20 @@ def deposit_raw(grid, P, qw):
     return Q
 
 
-def mcc_raw(sp, seed, step, xs, gas, numax, thresh, P, bcap=None):
-    """MCC on Particles P in place; returns (counts[5], births dict)."""
+def mcc_raw(sp, seed, step, xs, gas, numax, lq, lq_ion, P, bcap=None):
+    """MCC on Particles P in place at step `step` (candidates: P.next ==
+    step); returns (counts[5], births dict)."""
     bcap = bcap or max(16, P.n)
     bp = np.zeros(bcap, np.uint32)
     bR, bz = np.zeros(bcap), np.zeros(bcap)
     bve, bvi = np.zeros((bcap, 3)), np.zeros((bcap, 3))
+    bnx = np.zeros((bcap, 2), np.int32)
     cnt = np.zeros(5, np.int64)
     nb = lib().ora_mcc(sp, _U32(seed), _U32(step), ctypes.byref(xs), ctypes.byref(gas), float(numax),
-                       _U32(int(thresh)), P.n, _p(P.R, _D), _p(P.z, _D), _p(P.vr, _D), _p(P.vt, _D),
-                       _p(P.vz, _D), _p(P.id, _U32), _p(P.alive, _I32), bcap, _p(bp, _U32), _p(bR, _D),
-                       _p(bz, _D), _p(bve, _D), _p(bvi, _D), _p(cnt, _I64))
+                       float(lq), float(lq_ion), P.n, _p(P.R, _D), _p(P.z, _D), _p(P.vr, _D), _p(P.vt, _D),
+                       _p(P.vz, _D), _p(P.id, _U32), _p(P.alive, _I32), _p(P.next, _I32), bcap,
+                       _p(bp, _U32), _p(bR, _D), _p(bz, _D), _p(bve, _D), _p(bvi, _D), _p(bnx, _I32),
+                       _p(cnt, _I64))
     if nb < 0:
         raise RuntimeError("birth buffer overflow")
-    return cnt, dict(parent=bp[:nb], R=bR[:nb], z=bz[:nb], ve=bve[:nb], vi=bvi[:nb])
+    return cnt, dict(parent=bp[:nb], R=bR[:nb], z=bz[:nb], ve=bve[:nb], vi=bvi[:nb], next=bnx[:nb])

@@ -277,41 +277,70 @@ def _gas(wl):
     return pic.gas_struct(wl)
 
 
-def test_null_collision_threshold_and_numax():
-    """T = floor(P_null 2^32) with P_null = 1 - exp(-nu_max dt); nu_max is
-    1.01 x the maximum of n_g sigma_T v over the scanned range, which for
-    constant sigma sits at the range's end."""
+def test_null_collision_setup():
+    """nu_max is 1.01 x the maximum of n_g sigma_T v over the scanned range
+    (for constant sigma: the range's end); P_null = 1 - exp(-nu_max dt) and
+    log(1 - P_null) = -nu_max dt."""
     wl = W.small()
     wl.xs = W.CrossSections(kind=W.XS_CONSTANT)
-    nu, pn, th = pic.null_setup(wl, nscan=1000)
+    nu, pn, lq = pic.null_setup(wl, nscan=1000)
     vmax = math.sqrt(2 * wl.xs.e_cap_ev * W.QE / W.ME)
     sig = wl.xs.el_a + wl.xs.exc_a + wl.xs.iz_a
     assert nu[0] == pytest.approx(1.01 * wl.ngas * sig * vmax, rel=1e-12)
     assert nu[1] == pytest.approx(1.01 * wl.ngas * (wl.xs.iel_a + wl.xs.icx_a) * wl.xs.i_gcap, rel=1e-12)
-    assert pn[0] == pytest.approx(-math.expm1(-nu[0] * wl.dt), rel=1e-12)
-    assert th[0] == math.floor(pn[0] * 2 ** 32)
+    assert pn[0] == pytest.approx(1 - math.exp(-nu[0] * wl.dt), rel=1e-12)
+    assert lq[0] == pytest.approx(math.log1p(-pn[0]), rel=1e-12)
+
+
+def test_candidate_schedule_is_a_bernoulli_process():
+    """Candidate steps drawn as Geometric(P) gaps make every step a candidate
+    with probability P, independently: after loading, the first candidate
+    step k has P (1-P)^k; over many steps the candidate count per step is
+    Binomial(N, P), and a particle's gaps have mean 1/P."""
+    wl = W.small(n_per_species=200_000)
+    nu, pn, lq = pic.null_setup(wl)
+    P = pic.load_species(wl, 0, lq[0])
+    p = pn[0]
+    n = P.n
+    for k in (0, 1, 10, 100):
+        c = np.sum(P.next == k)
+        e = n * p * (1 - p) ** k
+        assert abs(c - e) < 5 * math.sqrt(e)
+    # run the schedule (velocities frozen: cross sections only pick the
+    # process, not the candidate) and count candidates per step
+    xs = pic.xs_struct(wl.xs)
+    gas = pic.gas_struct(wl)
+    counts = []
+    for step in range(200):
+        cnt, _ = pic.mcc_raw(0, wl.seed, step, xs, gas, nu[0], lq[0], lq[1], P)
+        counts.append(cnt[0])
+    counts = np.array(counts)
+    assert abs(counts.mean() - n * p) < 5 * math.sqrt(n * p / len(counts))
+    assert abs(counts.var() / (n * p * (1 - p)) - 1) < 0.35
+    assert np.all(P.next >= 200)
 
 
 def test_mcc_event_counts_constant_sigma():
-    """Constant sigma: candidates ~ Binomial(N, P_null); given a candidate the
-    process j happens with probability nu_j / nu_max (nu_j = n_g sigma_j v)."""
+    """Constant sigma: given a candidate the process j happens with
+    probability nu_j / nu_max (nu_j = n_g sigma_j v)."""
     wl = W.small()
     wl.xs = W.CrossSections(kind=W.XS_CONSTANT)
-    nu, pn, th = pic.null_setup(wl)
+    nu, pn, lq = pic.null_setup(wl)
     n = 400_000
     rng = np.random.default_rng(5)
     speed = np.full(n, math.sqrt(2 * 20.0 * W.QE / W.ME))    # 20 eV: all 3 processes open
     d = rng.normal(size=(n, 3))
     d /= np.linalg.norm(d, axis=1)[:, None]
     P = _parts(np.full(n, 0.05), np.full(n, 0.05), speed * d[:, 0], speed * d[:, 1], speed * d[:, 2])
-    cnt, births = pic.mcc_raw(0, 0, 7, pic.xs_struct(wl.xs), _gas(wl), nu[0], th[0], P)
-    p = th[0] / 2 ** 32
-    assert abs(cnt[0] - n * p) < 5 * math.sqrt(n * p * (1 - p))
+    P.next[:] = 7
+    cnt, births = pic.mcc_raw(0, 0, 7, pic.xs_struct(wl.xs), _gas(wl), nu[0], lq[0], lq[1], P)
+    assert cnt[0] == n
     for k, s in ((1, wl.xs.el_a), (2, wl.xs.exc_a), (3, wl.xs.iz_a)):
         q = wl.ngas * s * speed[0] / nu[0]
-        assert abs(cnt[k] - cnt[0] * q) < 5 * math.sqrt(cnt[0] * q * (1 - q))
+        assert abs(cnt[k] - n * q) < 5 * math.sqrt(n * q * (1 - q))
     assert len(births["parent"]) == cnt[3]
     assert cnt[4] == 0
+    assert np.all(P.next > 7)
 
 
 def test_mcc_electron_energy_laws():
@@ -319,7 +348,7 @@ def test_mcc_electron_energy_laws():
     eps - E_iz = eps_primary + eps_secondary; elastic loses the fraction
     (2m/M)(1 - cos chi), so eps' lies in [eps (1 - 4m/M), eps]."""
     wl = W.small()
-    nu, pn, th = pic.null_setup(wl)
+    nu, pn, lq = pic.null_setup(wl)
     n = 300_000
     rng = np.random.default_rng(11)
     eps0 = rng.uniform(16.0, 80.0, n)
@@ -328,7 +357,8 @@ def test_mcc_electron_energy_laws():
     d /= np.linalg.norm(d, axis=1)[:, None]
     v0 = speed[:, None] * d
     P = _parts(np.full(n, 0.05), np.full(n, 0.05), v0[:, 0], v0[:, 1], v0[:, 2])
-    cnt, births = pic.mcc_raw(0, 3, 9, pic.xs_struct(wl.xs), _gas(wl), nu[0], 2 ** 32 - 1, P)
+    P.next[:] = 9
+    cnt, births = pic.mcc_raw(0, 3, 9, pic.xs_struct(wl.xs), _gas(wl), nu[0], lq[0], lq[1], P)
     eps0 = 0.5 * W.ME * (v0 ** 2).sum(1) / W.QE
     eps1 = 0.5 * W.ME * (P.vr ** 2 + P.vt ** 2 + P.vz ** 2) / W.QE
     changed = np.any(np.stack([P.vr, P.vt, P.vz], 1) != v0, axis=1)
@@ -356,13 +386,14 @@ def test_mcc_ion_elastic_conserves_momentum_and_energy():
     unchanged; charge exchange takes the neutral's velocity."""
     wl = W.small()
     xs = W.CrossSections(kind=W.XS_CONSTANT, icx_a=1e-30)   # elastic only
-    nu, pn, th = pic.null_setup(W.Workload(**{**wl.__dict__, "xs": xs}))
+    nu, pn, lq = pic.null_setup(W.Workload(**{**wl.__dict__, "xs": xs}))
     n = 50_000
     rng = np.random.default_rng(2)
     v0 = rng.normal(0, 3e3, (n, 3))
     P = _parts(np.full(n, 0.05), np.full(n, 0.05), v0[:, 0], v0[:, 1], v0[:, 2])
     P.id[:] = np.arange(n)
-    cnt, _ = pic.mcc_raw(1, 0, 4, pic.xs_struct(xs), _gas(wl), nu[1], 2 ** 32 - 1, P)
+    P.next[:] = 4
+    cnt, _ = pic.mcc_raw(1, 0, 4, pic.xs_struct(xs), _gas(wl), nu[1], lq[1], lq[1], P)
     # neutral partner velocity: Box-Muller of block (id, step, 2, 0), words (0,1),(2,3)
     ctr = np.zeros((n, 4), np.uint32)
     ctr[:, 0] = np.arange(n)
