@@ -1,0 +1,272 @@
+/*
+ * phasorpic: the per-timestep axisymmetric (z, R) PIC/MCC cycle of the
+ * phasor-PIC method (Chen et al., "Phasor-particle-in-cell algorithm for
+ * bidirectional external-circuit coupling of inductively coupled plasma"),
+ * as HIP kernels for MI355X (gfx950) behind a plain C ABI.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Every call returns a pic_status (int32_t); PIC_OK == 0.  Argument errors
+ *   are reported synchronously.  Work is enqueued asynchronously on the HIP
+ *   stream given to pic_init; errors raised on the device (capacity
+ *   overflow, solver non-convergence) surface at the next synchronising
+ *   call (pic_sync, the getters, circuit_period_update) and then stick
+ *   until pic_clear_error.  pic_last_error() explains the last failure.
+ * - Grid: nr x nz cells; node (i, j) sits at z = i dz, R = j dR with
+ *   dz = zmax / nz, dR = rmax / nr; node arrays are (nz+1) x (nr+1), R index
+ *   fastest (linear index i * (nr+1) + j); cell arrays are nz x nr.
+ * - Species 0 are electrons, species 1 Ar+ ions.  Particles live in the box
+ *   0 <= R < rmax, 0 <= z < zp with zp = ip dz.
+ * - Memory: the caller owns all device memory.  pic_workspace_bytes() sizes
+ *   one device buffer that the caller allocates (e.g. a torch uint8 tensor)
+ *   and passes to pic_init; the library carves every device array it uses
+ *   out of it and never frees it.  Host pointers in pic_config are read
+ *   during pic_init only.  The opaque pic_ctx is host memory owned by the
+ *   library and released by pic_destroy.
+ * - Threading: one host thread per context; a context is not thread-safe.
+ * - Step order of one PIC step n (the paper's workflow, Sec. 2.5):
+ *       pic_gather_push(n); harmonic_accumulate(n); mcc_collide(n);
+ *       pic_deposit(n+1); [circuit_period_update() when (n+1) % N_RF == 0];
+ *       poisson_solve_rz(n+1, ...)
+ */
+#ifndef PHASORPIC_H
+#define PHASORPIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pic_status;
+
+enum {
+    PIC_OK = 0,
+    PIC_EINVAL = -1,    /* bad configuration, shape or argument */
+    PIC_ENOMEM = -2,    /* workspace, particle or birth capacity too small */
+    PIC_EDEVICE = -3,   /* HIP runtime error */
+    PIC_ENOTCONV = -4,  /* Poisson multigrid missed rtol within max_cycles */
+    PIC_EPHASE = -5,    /* phase closure or sample count != N_RF: update rejected */
+    PIC_ESTATE = -6     /* call-order violation */
+};
+
+enum { PIC_FP64 = 0, PIC_MIXED = 1 };
+
+/* grids readable with pic_get_grid (all FP64 node arrays) */
+enum {
+    PIC_GRID_PHI = 0,      /* electrostatic potential phi^n (V) */
+    PIC_GRID_CHARGE = 1,   /* node charge of the last pic_deposit, incl. window charge (C) */
+    PIC_GRID_CURRENT = 2,  /* azimuthal node current I^n = sum q w vbar_theta W (A m) */
+    PIC_GRID_ER = 3,       /* staged E_r of the last pic_gather_push (V/m) */
+    PIC_GRID_EZ = 4,       /* staged E_z (V/m) */
+    PIC_GRID_ETHETA = 5,   /* staged E_theta(t_n) (V/m) */
+    PIC_GRID_SURFACE = 6,  /* accumulated window surface charge (C) */
+    PIC_GRID_JC = 7,       /* running sum of I^n cos(theta_n) of the open period */
+    PIC_GRID_JS = 8        /* running sum of I^n sin(theta_n) of the open period */
+};
+
+typedef struct pic_config {
+    /* grid */
+    int32_t nr, nz;          /* cells in R and z; multigrid wants both even, ideally 2^k */
+    int32_t ip;              /* node row of the top of the particle region */
+    int32_t window;          /* 1: charge leaving through row ip stays there (dielectric) */
+    double rmax, zmax;       /* m */
+    /* time: N_RF = nint(1 / (freq dt)) (Sec. 2.1, Eq. nrf) */
+    double dt, freq;
+    /* arithmetic: PIC_FP64, or PIC_MIXED (int cell + FP32 offsets and velocities) */
+    int32_t precision;
+    uint32_t seed;           /* Philox key word 0; key word 1 is the species */
+    /* species: charge (C), mass (kg), macro weight, initial temperature (eV) */
+    double q[2], m[2], w[2], temp_ev[2];
+    int64_t np_init[2];      /* particles loaded by pic_init (if load != 0) */
+    int64_t capacity[2];     /* particle slots per species */
+    double bfield[3];        /* uniform (B_r, B_theta, B_z) in the Boris rotation (T) */
+    /* gas and cross sections */
+    double ngas;             /* neutral density (m^-3) */
+    double tgas_ev;          /* neutral temperature (eV) */
+    double qe;               /* elementary charge, for eV conversions */
+    double eps0;             /* vacuum permittivity used by the Poisson operator */
+    int32_t xs_kind;         /* 0 smooth analytic fits, 1 constant cross sections */
+    int32_t nscan;           /* points of the nu_max scan */
+    /* el_a el_b exc_a exc_th iz_a iz_th iel_a iel_p icx_a icx_p e_cap_ev i_gcap nu_margin */
+    double xs[13];
+    /* geometry and materials (host arrays, copied by pic_init) */
+    int32_t nturns;          /* coil turns with Dirichlet potentials */
+    int32_t fuse;            /* 1: pic_gather_push runs the fused push+MCC+deposit pass */
+    const double *eps_cell;  /* nz*nr relative permittivity */
+    const int32_t *node_tag; /* (nz+1)*(nr+1): -1 free, 0 grounded, k >= 1 turn k */
+    const double *ec;        /* node E_c of the azimuthal field (V/m); NULL = 0 */
+    const double *es_sto;    /* node stored sine array (= -E_s) (V/m); NULL = 0 */
+    const double *turn_vc;   /* nturns: V_c,k of the turn potentials (V) */
+    const double *turn_vs;   /* nturns: V_s,k */
+    /* Poisson multigrid and scheduling */
+    double mg_rtol;          /* residual tolerance relative to the equation's scale */
+    int32_t mg_max_cycles;   /* V-cycles per solve at most */
+    int32_t sort_every;      /* steps between cell sorts of the particle arrays (>= 1) */
+    int32_t load;            /* 1: load the initial uniform Maxwellian plasma */
+    int32_t birth_capacity;  /* ionization events buffered per step */
+} pic_config;
+
+typedef struct pic_solve_info {
+    int32_t cycles;          /* V-cycles run by the last solve */
+    int32_t converged;       /* 1 if rel_residual <= rtol */
+    double rel_residual;     /* max |residual| / equation scale after the last cycle */
+} pic_solve_info;
+
+typedef struct pic_stats {
+    int64_t slots[2];        /* particle slots in use (live + not yet compacted) */
+    int64_t live[2];         /* live particles */
+    int64_t next_id[2];      /* next particle id per species */
+    int64_t candidates[2];   /* MCC candidates since init */
+    int64_t events[2][3];    /* real collisions by process since init */
+    int64_t births;          /* ionization births since init */
+    int64_t absorbed[2];     /* particles absorbed since init */
+    int64_t over_numax[2];   /* candidates whose total frequency exceeded nu_max */
+    int64_t window_out;      /* deposit contributions outside the LDS window (fallback atomics) */
+    int64_t samples;         /* harmonic samples in the open period */
+    int32_t nrf;             /* N_RF */
+    int32_t phase_closed;    /* Eq. phaseclosure holds */
+    double numax[2];         /* null-collision frequency per species (1/s) */
+    double pnull[2];         /* null-collision probability per step */
+    double pind_sum;         /* open-period sum of sum_nodes I E_theta (W) */
+    double qc[16], qs[16];   /* open-period sums of Q_k cos, Q_k sin (first 16 turns) */
+    double wk[16];           /* open-period trapezoid sums of V dQ (first 16 turns) */
+    double qk[16];           /* Q_k of the last Poisson solve (C) */
+    /* HIP-event timing since pic_timing(ctx, 1) (milliseconds, launches) */
+    double pass_ms;          /* particle pass of both species (pic_gather_push's main launches) */
+    int64_t pass_count;
+    double poisson_ms;       /* whole poisson_solve_rz */
+    int64_t poisson_count;
+    double sort_ms;          /* cell sorts of both species */
+    int64_t sort_count;
+    int64_t mg_cycles;       /* V-cycles of the last solve */
+    double mg_rel;           /* its final relative residual */
+} pic_stats;
+
+typedef struct pic_ctx pic_ctx;
+
+/* Bytes of device workspace pic_init needs for this configuration. */
+pic_status pic_workspace_bytes(const pic_config *cfg, size_t *bytes);
+
+/* Validates the configuration (grid, tags, phase closure flag, species),
+ * carves the workspace, sets up the null-collision constants, loads the
+ * plasma when cfg->load (uniform in volume, Maxwellian, Philox-keyed by
+ * particle id), sorts it by cell, deposits rho^0 and solves phi^0.
+ * Follows Sec. 2.1 (time structure), Sec. 2.3 (Poisson problem) and the
+ * workflow's initialisation (Sec. 2.5).  workspace: device pointer of at
+ * least pic_workspace_bytes(cfg) bytes; stream: a hipStream_t (NULL = the
+ * default stream).  On success *out owns a new context. */
+pic_status pic_init(const pic_config *cfg, void *workspace, size_t workspace_bytes, void *stream,
+                    pic_ctx **out);
+
+/* Step n, particle part: stages E_r, E_z from phi^n and E_theta(t_n) =
+ * E_c cos th_n - E_s^sto sin th_n (Eq. et_reconstruct), gathers at x^n with
+ * R^2-linear radial and linear axial weights, Boris-pushes v^{n-1/2} ->
+ * v^{n+1/2}, moves to x^{n+1} in the particle's Cartesian plane and rotates
+ * (v_r, v_theta) back, deposits the azimuthal current I^n with the gather
+ * weights and vbar_theta = (v^{n-1/2} + v^{n+1/2})/2, and removes particles
+ * that leave the box (window crossings leave their charge on row ip).
+ * With cfg->fuse the same pass also runs the collisions and the charge
+ * deposit of the new positions.  Requires n == last step + 1 (first n = 0);
+ * sorts the arrays by cell first when n % sort_every == 0. */
+pic_status pic_gather_push(pic_ctx *ctx, int64_t n);
+
+/* Null-collision MCC of step n on v^{n+1/2} at x^{n+1}: particles whose
+ * candidate step is n draw Philox4x32-10 block (id, n, 1, 0) keyed by
+ * (seed, species), select elastic / excitation / ionization (electrons) or
+ * elastic / charge exchange (ions) against nu_max, and schedule their next
+ * candidate.  Ionization births are appended in parent-id order.  Capacity
+ * overflow -> PIC_ENOMEM at the next sync. */
+pic_status mcc_collide(pic_ctx *ctx, int64_t n);
+
+/* Node charge rho^{n1} at x^{n1}: q w times the gather weights, summed in
+ * exact 64-bit fixed point, plus the accumulated window surface charge. */
+pic_status pic_deposit(pic_ctx *ctx, int64_t n1);
+
+/* FP64 geometric multigrid solve of the finite-volume RZ Poisson problem
+ * sum_f eps0 eps_f A_f (phi_p - phi_nb) / d_f = Q_p (Eqs. poisson with
+ * chi = 0, epseff, areas; Neumann axis, Eq. axis_electrostatic_bc) with
+ * Dirichlet 0 on grounded nodes and phi_k(t_n) = V_c,k cos th_n +
+ * V_s,k sin th_n on turn k (Eq. dirichlet), warm-started from the last
+ * phi.  Then the turn charges Q_k(t_n) from the operator's face fluxes
+ * (Eq. facecharge).  rtol <= 0 / max_cycles <= 0 take the config values.
+ * info (nullable): when given the call synchronises and fills it;
+ * PIC_ENOTCONV if rtol was not met. */
+pic_status poisson_solve_rz(pic_ctx *ctx, int64_t n, double rtol, int32_t max_cycles,
+                            pic_solve_info *info);
+
+/* Period accumulation of step n (Eqs. fourier, pind, pcap): J_c += I^n
+ * cos th_n, J_s += I^n sin th_n on nodes, Q_c,k / Q_s,k with Q_k(t_n),
+ * P_ind sum of sum_nodes I^n E_theta(t_n), the trapezoid of V_k dQ_k and the
+ * sample count; FP64 with compensated (Neumaier) sums.  Must follow
+ * pic_gather_push(n); calling it twice for one step is PIC_ESTATE. */
+pic_status harmonic_accumulate(pic_ctx *ctx, int64_t n);
+
+/* Closed-period report (Eqs. fourier, icap, pind, pcap, pcap_phasor). */
+typedef struct pic_period_report {
+    int32_t accepted;        /* 0: sample count != N_RF, nothing changed */
+    int32_t samples;
+    double p_ind;            /* W */
+    double p_cap;            /* W, periodic trapezoid */
+    double p_cap_ph;         /* W, phasor cross-check */
+    double qc[16], qs[16];   /* charge harmonics Q_c,k, Q_s,k */
+    double icap_re[16], icap_im[16];  /* I_cap,k = w Q_s,k + i w Q_c,k */
+} pic_period_report;
+
+/* Closes the RF period: synchronises, requires exactly N_RF samples
+ * (otherwise PIC_EPHASE and the accumulators are kept), finalises the
+ * harmonics and powers into *report, copies J_c, J_s (x 2/N_RF) into the
+ * caller's host arrays jc, js when non-NULL, optionally installs the next
+ * period's turn voltages (new_vc, new_vs, nturns each; NULL keeps them) and
+ * azimuthal field (new_ec, new_es_sto node arrays; NULL keeps them), and
+ * resets the accumulators. */
+pic_status circuit_period_update(pic_ctx *ctx, const double *new_vc, const double *new_vs,
+                                 const double *new_ec, const double *new_es_sto,
+                                 pic_period_report *report, double *jc, double *js);
+
+/* Synchronise the stream and report any sticky device-side error. */
+pic_status pic_sync(pic_ctx *ctx);
+pic_status pic_clear_error(pic_ctx *ctx);
+
+/* Host copies of one species' live particles (synchronising), in the
+ * oracle's representation: R, z (m), v_r, v_theta, v_z (m/s), id, next
+ * candidate step; arrays of capacity cap; *count receives the live count
+ * (PIC_ENOMEM if it exceeds cap; any pointer may be NULL). */
+pic_status pic_get_particles(pic_ctx *ctx, int32_t species, int64_t cap, double *R, double *z,
+                             double *vr, double *vt, double *vz, uint32_t *id, int32_t *next,
+                             int64_t *count);
+
+/* Replace one species' particles (host arrays of length n) and re-sort.
+ * next_id becomes max(id) + 1 unless a larger value is already set. */
+pic_status pic_set_particles(pic_ctx *ctx, int32_t species, int64_t n, const double *R,
+                             const double *z, const double *vr, const double *vt, const double *vz,
+                             const uint32_t *id, const int32_t *next);
+
+/* Make n the next step for pic_gather_push (restart from a saved state,
+ * or a test that starts mid-period). */
+pic_status pic_set_step(pic_ctx *ctx, int64_t n);
+
+/* Replace phi (host node array); the next pic_gather_push stages from it. */
+pic_status pic_set_phi(pic_ctx *ctx, const double *phi);
+
+/* Copy one FP64 node grid (PIC_GRID_*) to host (synchronising). */
+pic_status pic_get_grid(pic_ctx *ctx, int32_t which, double *out);
+
+/* Enable (1) or disable (0) HIP-event timing of the particle pass, the
+ * Poisson solve and the sort on the context's stream; enabling resets the
+ * totals reported in pic_stats. */
+pic_status pic_timing(pic_ctx *ctx, int32_t enable);
+
+/* Counters and open-period accumulators (synchronising). */
+pic_status pic_get_stats(pic_ctx *ctx, pic_stats *out);
+
+/* Release the context (not the caller's workspace). */
+void pic_destroy(pic_ctx *ctx);
+
+const char *pic_last_error(const pic_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PHASORPIC_H */

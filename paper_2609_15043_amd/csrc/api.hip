@@ -1,0 +1,1443 @@
+// Host side of the phasorpic C ABI: configuration checks, workspace
+// carving, null-collision constants, the multigrid hierarchy of the
+// finite-volume RZ Poisson operator, and the per-call kernel orchestration.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/phasorpic.h"
+#include "kernels.h"
+#include "launch.h"
+
+using namespace pic;
+
+namespace {
+
+constexpr double TWO_PI = 6.283185307179586476925287;
+
+// Bump allocator over the caller's workspace (dry run when base == nullptr).
+struct Carver {
+    uint8_t *base;
+    size_t off = 0;
+    template <typename U> U *take(size_t count)
+    {
+        off = (off + 255) & ~size_t(255);
+        U *p = base ? reinterpret_cast<U *>(base + off) : nullptr;
+        off += count * sizeof(U);
+        return p;
+    }
+};
+
+template <typename T> void carve_parts(Carver &c, Parts<T> &p, int64_t cap)
+{
+    p.cell = c.take<int32_t>(cap);
+    p.dr = c.take<T>(cap);
+    p.dz = c.take<T>(cap);
+    p.vr = c.take<T>(cap);
+    p.vt = c.take<T>(cap);
+    p.vz = c.take<T>(cap);
+    p.id = c.take<uint32_t>(cap);
+    p.next = c.take<int32_t>(cap);
+}
+
+template <typename T> void carve_births(Carver &c, Births<T> &b, int cap)
+{
+    b.parent = c.take<uint32_t>(cap);
+    b.cell = c.take<int32_t>(cap);
+    b.dr = c.take<T>(cap);
+    b.dz = c.take<T>(cap);
+    b.ve = c.take<T>(3 * (size_t)cap);
+    b.vi = c.take<T>(3 * (size_t)cap);
+    b.next = c.take<int32_t>(2 * (size_t)cap);
+    b.count = c.take<int32_t>(1);
+    b.cap = cap;
+}
+
+struct HostLevel {
+    int nr, nz;
+    std::vector<double> eps;   // nz * nr
+    std::vector<uint8_t> dir;  // nodes
+};
+
+int64_t ceil_log2(double x)
+{
+    int64_t k = 0;
+    while (std::ldexp(1.0, (int)k) < x) ++k;
+    return k;
+}
+
+}  // namespace
+
+struct pic_ctx {
+    pic_config cfg{};
+    std::vector<double> eps_cell, ec, es, vc, vs;
+    std::vector<int32_t> tag;
+    hipStream_t stream = nullptr;
+    GridC g{};
+    bool mixed = false;
+    int nrf = 0;
+    bool closed = false;
+    std::string err;
+    int64_t last_push = -1;
+    int64_t last_harm = -1;
+    int64_t last_mcc = -1;
+    bool pushed_since_sort = false;
+
+    // particles (ping-pong per species)
+    Parts<float> pf[2][2];
+    Parts<double> pd[2][2];
+    int cur[2] = {0, 0};
+    Births<float> bf{};
+    Births<double> bd{};
+    CandQueue cq[2]{};
+    int64_t *ctl = nullptr;      // count[2], count_old[2], next_id[2], nlive, pad
+    unsigned long long *stats = nullptr;
+    int32_t *errw = nullptr;
+    int32_t *hist = nullptr, *cursor = nullptr;
+    int64_t *live_index = nullptr;
+    double *stage = nullptr;     // 5 doubles + id + next per staged particle
+    int64_t stage_cap = 0;
+
+    // grids
+    void *ef = nullptr;
+    long long *accJ = nullptr, *accQ = nullptr;
+    double *accS = nullptr;
+    double *phi = nullptr, *Q = nullptr, *I = nullptr, *d_ec = nullptr, *d_es = nullptr;
+    int32_t *d_tag = nullptr;
+    double *d_vc = nullptr, *d_vs = nullptr;
+    double *Jc = nullptr, *Jcc = nullptr, *Js = nullptr, *Jsc = nullptr, *hpartial = nullptr;
+    HarmState *harm = nullptr;
+
+    // multigrid
+    MGLevels lv{};
+    int lb = 0;
+    MGState *mgs = nullptr;
+    double *mgpartial = nullptr;
+    double *pr = nullptr, *pz = nullptr, *pp = nullptr, *pAp = nullptr;   // CG vectors
+    double *phi_prev = nullptr;   // phi of the previous solve (initial-guess extrapolation)
+    bool have_prev = false;
+    int64_t last_solve = -2;
+    // adaptive iteration budget: each solve's state lands in pinned host
+    // memory asynchronously; the next solve budgets the recent count + 2
+    MGState *mg_host = nullptr;   // pinned ring
+    int mg_ring = 0;
+    int mg_budget = 8;
+    int64_t mg_unconverged = 0;
+    int32_t *fp = nullptr, *fq = nullptr, *fk = nullptr;
+    double *fc = nullptr, *Qk = nullptr;
+    int nfaces = 0;
+
+    // HIP-event timing: ring of (start, stop) pairs per timed region
+    struct Timer {
+        static constexpr int RING = 64;
+        hipEvent_t ev[RING][2]{};
+        int head = 0, pending = 0;
+        double ms = 0.0;
+        int64_t count = 0;
+    };
+    bool timing = false;
+    Timer t_pass, t_poisson, t_sort;
+
+    // constants
+    SpeciesC sc[2]{};
+    MccC mc{};
+    double qscale = 1.0, jscale = 1.0;
+    double numax[2]{}, pnull[2]{}, lq[2]{};
+};
+
+static void timer_start(pic_ctx &c, pic_ctx::Timer &t)
+{
+    if (!c.timing) return;
+    auto &e = t.ev[t.head];
+    if (!e[0]) {
+        (void)hipEventCreate(&e[0]);
+        (void)hipEventCreate(&e[1]);
+    }
+    if (t.pending == pic_ctx::Timer::RING) {   // oldest pair still unread: read it now
+        float ms = 0.f;
+        (void)hipEventSynchronize(e[1]);
+        (void)hipEventElapsedTime(&ms, e[0], e[1]);
+        t.ms += ms;
+        t.count += 1;
+        t.pending -= 1;
+    }
+    (void)hipEventRecord(e[0], c.stream);
+}
+
+static void timer_stop(pic_ctx &c, pic_ctx::Timer &t)
+{
+    if (!c.timing) return;
+    (void)hipEventRecord(t.ev[t.head][1], c.stream);
+    t.head = (t.head + 1) % pic_ctx::Timer::RING;
+    t.pending += 1;
+}
+
+static void timer_drain(pic_ctx::Timer &t)
+{
+    const int R = pic_ctx::Timer::RING;
+    for (int k = t.pending; k > 0; --k) {
+        auto &e = t.ev[(t.head - k + R) % R];
+        float ms = 0.f;
+        (void)hipEventSynchronize(e[1]);
+        (void)hipEventElapsedTime(&ms, e[0], e[1]);
+        t.ms += ms;
+        t.count += 1;
+    }
+    t.pending = 0;
+}
+
+static pic_status fail(pic_ctx *c, pic_status s, const char *fmt, ...)
+{
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return s;
+}
+
+static hipError_t cpy(hipStream_t st, void *dst, const void *src, size_t bytes, hipMemcpyKind kind)
+{
+    hipError_t e = hipMemcpyAsync(dst, src, bytes, kind, st);
+    return e != hipSuccess ? e : hipStreamSynchronize(st);
+}
+
+static hipError_t mset(hipStream_t st, void *dst, int v, size_t bytes)
+{
+    hipError_t e = hipMemsetAsync(dst, v, bytes, st);
+    return e != hipSuccess ? e : hipStreamSynchronize(st);
+}
+
+#define HIPCHK(ctx, expr)                                                                              \
+    do {                                                                                               \
+        hipError_t e_ = (expr);                                                                        \
+        if (e_ != hipSuccess) return fail(ctx, PIC_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));   \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Geometry: finite-volume conductances of the RZ Poisson operator on a level
+// (face areas of the axisymmetric control volumes, face permittivity = mean
+// of the cells sharing the face), and the Dirichlet structure.
+// ---------------------------------------------------------------------------
+struct Coeffs {
+    std::vector<double> cw, ce, cs, cn, cc;
+};
+
+static Coeffs assemble(int nr, int nz, double dr, double dz, const std::vector<double> &eps, double eps0)
+{
+    const int nr1 = nr + 1, nodes = (nz + 1) * nr1;
+    Coeffs c;
+    c.cw.assign(nodes, 0.0);
+    c.ce.assign(nodes, 0.0);
+    c.cs.assign(nodes, 0.0);
+    c.cn.assign(nodes, 0.0);
+    c.cc.assign(nodes, 0.0);
+    auto cell_eps = [&](int i, int j, double &sum, int &cnt) {
+        if (i >= 0 && i < nz && j >= 0 && j < nr) {
+            sum += eps[(size_t)i * nr + j];
+            ++cnt;
+        }
+    };
+    for (int i = 0; i <= nz; ++i) {
+        for (int j = 0; j <= nr; ++j) {
+            const int n = i * nr1 + j;
+            const double R = j * dr;
+            if (j < nr) {   // face between (i, j) and (i, j+1)
+                const double h = std::min((double)nz * dz, i * dz + 0.5 * dz) - std::max(0.0, i * dz - 0.5 * dz);
+                const double area = TWO_PI * (R + 0.5 * dr) * h;
+                double s = 0.0;
+                int k = 0;
+                cell_eps(i - 1, j, s, k);
+                cell_eps(i, j, s, k);
+                const double cf = eps0 * (s / k) * area / dr;
+                c.ce[n] = cf;
+                c.cw[n + 1] = cf;
+            }
+            if (i < nz) {   // face between (i, j) and (i+1, j)
+                const double lo = std::max(0.0, R - 0.5 * dr), hi = std::min((double)nr * dr, R + 0.5 * dr);
+                const double area = 0.5 * TWO_PI * (hi * hi - lo * lo);
+                double s = 0.0;
+                int k = 0;
+                cell_eps(i, j - 1, s, k);
+                cell_eps(i, j, s, k);
+                const double cf = eps0 * (s / k) * area / dz;
+                c.cn[n] = cf;
+                c.cs[n + nr1] = cf;
+            }
+        }
+    }
+    for (int n = 0; n < nodes; ++n) c.cc[n] = c.cw[n] + c.ce[n] + c.cs[n] + c.cn[n];
+    return c;
+}
+
+// Galerkin coarse operator A_c = P^T A P of a 9-point (or 5-point, as 9-point
+// with zero corners) fine operator, P bilinear and zero on fine Dirichlet
+// nodes.  Entry k = 3 (di + 1) + (dj + 1) of node n sits at a[k * nodes + n].
+// A coarse node none of whose interpolation support is free becomes a
+// Dirichlet (fixed-zero) node.
+struct Stencil9 {
+    int nr, nz;
+    std::vector<double> a;
+    std::vector<uint8_t> dir;
+};
+
+static Stencil9 galerkin(const Stencil9 &F)
+{
+    Stencil9 C;
+    C.nr = F.nr / 2;
+    C.nz = F.nz / 2;
+    const int nr1f = F.nr + 1, nr1c = C.nr + 1;
+    const size_t nf = (size_t)(F.nz + 1) * nr1f, nc = (size_t)(C.nz + 1) * nr1c;
+    C.a.assign(9 * nc, 0.0);
+    std::vector<uint8_t> support(nc, 0);
+    auto interp = [](int i, int *idx, double *w) {
+        if (i % 2 == 0) {
+            idx[0] = i / 2;
+            w[0] = 1.0;
+            return 1;
+        }
+        idx[0] = (i - 1) / 2;
+        idx[1] = (i + 1) / 2;
+        w[0] = w[1] = 0.5;
+        return 2;
+    };
+    for (int i = 0; i <= F.nz; ++i)
+        for (int j = 0; j <= F.nr; ++j) {
+            const size_t p = (size_t)i * nr1f + j;
+            if (F.dir[p]) continue;
+            int Ii[2], Jj[2];
+            double wi[2], wj[2];
+            const int ni = interp(i, Ii, wi), nj = interp(j, Jj, wj);
+            for (int a = 0; a < ni; ++a)
+                for (int b = 0; b < nj; ++b) support[(size_t)Ii[a] * nr1c + Jj[b]] = 1;
+            for (int k = 0; k < 9; ++k) {
+                const int di = k / 3 - 1, dj = k % 3 - 1;
+                const int i2 = i + di, j2 = j + dj;
+                if (i2 < 0 || i2 > F.nz || j2 < 0 || j2 > F.nr) continue;
+                const size_t q = (size_t)i2 * nr1f + j2;
+                if (F.dir[q]) continue;
+                const double v = F.a[(size_t)k * nf + p];
+                if (v == 0.0) continue;
+                int I2[2], J2[2];
+                double w2i[2], w2j[2];
+                const int mi = interp(i2, I2, w2i), mj = interp(j2, J2, w2j);
+                for (int a = 0; a < ni; ++a)
+                    for (int b = 0; b < nj; ++b)
+                        for (int c2 = 0; c2 < mi; ++c2)
+                            for (int d2 = 0; d2 < mj; ++d2) {
+                                const int oi = I2[c2] - Ii[a], oj = J2[d2] - Jj[b];
+                                const size_t row = (size_t)Ii[a] * nr1c + Jj[b];
+                                C.a[(size_t)((oi + 1) * 3 + (oj + 1)) * nc + row] += wi[a] * wj[b] * v * w2i[c2] * w2j[d2];
+                            }
+            }
+        }
+    C.dir.assign(nc, 0);
+    for (size_t n = 0; n < nc; ++n)
+        if (!support[n]) {
+            C.dir[n] = 1;
+            for (int k = 0; k < 9; ++k) C.a[(size_t)k * nc + n] = k == 4 ? 1.0 : 0.0;
+        }
+    return C;
+}
+
+// ---------------------------------------------------------------------------
+// Null-collision constants: nu_max = margin * max over the scanned range of
+// n_g sigma_T v (electrons: energy 0..e_cap; ions: relative speed 0..g_cap),
+// P_null = 1 - exp(-nu_max dt), log(1 - P_null) = -nu_max dt.
+// ---------------------------------------------------------------------------
+static double host_threshold_shape(double eps, double th)
+{
+    if (eps <= th) return 0.0;
+    const double x = eps / th;
+    return 4.0 * (x - 1.0) / (x * x);
+}
+
+static void null_constants(const pic_config &c, double numax[2], double pnull[2], double lq[2])
+{
+    const double *x = c.xs;
+    double be = 0.0, bi = 0.0;
+    const int N = c.nscan > 0 ? c.nscan : 200000;
+    for (int k = 0; k <= N; ++k) {
+        const double eps = x[10] * (double)k / (double)N;
+        double sel, sex, siz;
+        if (c.xs_kind == 1) {
+            sel = x[0];
+            sex = eps > x[3] ? x[2] : 0.0;
+            siz = eps > x[5] ? x[4] : 0.0;
+        } else {
+            sel = x[0] / std::sqrt(1.0 + eps / x[1]);
+            sex = x[2] * host_threshold_shape(eps, x[3]);
+            siz = x[4] * host_threshold_shape(eps, x[5]);
+        }
+        const double v = std::sqrt(2.0 * eps * c.qe / c.m[0]);
+        be = std::max(be, c.ngas * (sel + sex + siz) * v);
+        const double gr = x[11] * (double)k / (double)N;
+        const double ecm = 0.25 * c.m[1] * gr * gr / c.qe;
+        double iel, icx;
+        if (c.xs_kind == 1) {
+            iel = x[6];
+            icx = x[8];
+        } else {
+            iel = x[6] * std::pow(1.0 + ecm, -x[7]);
+            icx = x[8] * std::pow(1.0 + ecm, -x[9]);
+        }
+        bi = std::max(bi, c.ngas * (iel + icx) * gr);
+    }
+    numax[0] = be * x[12];
+    numax[1] = bi * x[12];
+    for (int s = 0; s < 2; ++s) {
+        pnull[s] = -std::expm1(-numax[s] * c.dt);
+        lq[s] = -numax[s] * c.dt;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Workspace layout (shared by the size query and pic_init)
+// ---------------------------------------------------------------------------
+static int mg_levels(int nr, int nz)
+{
+    int n = 1;
+    while (nr % 2 == 0 && nz % 2 == 0 && std::min(nr, nz) >= 4 && n < MAX_LEVELS) {
+        nr /= 2;
+        nz /= 2;
+        ++n;
+    }
+    return n;
+}
+
+static void layout(pic_ctx &c, Carver &cv)
+{
+    const pic_config &f = c.cfg;
+    const int nodes = (f.nz + 1) * (f.nr + 1), ncells = f.nz * f.nr;
+    for (int s = 0; s < 2; ++s)
+        for (int b = 0; b < 2; ++b) {
+            if (c.mixed)
+                carve_parts(cv, c.pf[s][b], f.capacity[s]);
+            else
+                carve_parts(cv, c.pd[s][b], f.capacity[s]);
+        }
+    const int bcap = f.birth_capacity > 0 ? f.birth_capacity : 65536;
+    if (c.mixed)
+        carve_births(cv, c.bf, bcap);
+    else
+        carve_births(cv, c.bd, bcap);
+    for (int s = 0; s < 2; ++s) {
+        const double expect = c.pnull[s] * (double)f.capacity[s];
+        const int64_t qc = std::min<int64_t>(f.capacity[s], (int64_t)(4.0 * expect + 16.0 * std::sqrt(expect + 1.0)) + 4096);
+        c.cq[s].cap = (int32_t)qc;
+        c.cq[s].idx = cv.take<int32_t>(qc);
+        c.cq[s].count = cv.take<int32_t>(1);
+    }
+    c.ctl = cv.take<int64_t>(8);
+    c.stats = cv.take<unsigned long long>(ST_NSTAT);
+    c.errw = cv.take<int32_t>(1);
+    c.hist = cv.take<int32_t>(ncells + 1);
+    c.cursor = cv.take<int32_t>(ncells + 1);
+    const int64_t capmax = std::max(f.capacity[0], f.capacity[1]);
+    c.live_index = cv.take<int64_t>(capmax);
+    c.stage_cap = std::min<int64_t>(capmax, 1 << 20);
+    c.stage = cv.take<double>(6 * (size_t)c.stage_cap);
+    c.ef = c.mixed ? (void *)cv.take<float4>(nodes) : (void *)cv.take<double4>(nodes);
+    c.accJ = cv.take<long long>(2 * (size_t)nodes);
+    c.accQ = cv.take<long long>(2 * (size_t)nodes);
+    c.accS = cv.take<double>(2 * (size_t)nodes);
+    c.phi = cv.take<double>(nodes);
+    c.Q = cv.take<double>(nodes);
+    c.I = cv.take<double>(nodes);
+    c.d_ec = cv.take<double>(nodes);
+    c.d_es = cv.take<double>(nodes);
+    c.d_tag = cv.take<int32_t>(nodes);
+    c.d_vc = cv.take<double>(MAX_TURNS);
+    c.d_vs = cv.take<double>(MAX_TURNS);
+    c.Jc = cv.take<double>(nodes);
+    c.Jcc = cv.take<double>(nodes);
+    c.Js = cv.take<double>(nodes);
+    c.Jsc = cv.take<double>(nodes);
+    c.hpartial = cv.take<double>(harmonic_blocks(nodes));
+    c.harm = cv.take<HarmState>(1);
+    // multigrid: level 0 holds the CG correction (z) and residual (r)
+    const int nl = mg_levels(f.nr, f.nz);
+    c.lv.n = nl;
+    c.pr = cv.take<double>(nodes);
+    c.pz = cv.take<double>(nodes);
+    c.pp = cv.take<double>(nodes);
+    c.pAp = cv.take<double>(nodes);
+    int nr = f.nr, nz = f.nz;
+    for (int l = 0; l < nl; ++l) {
+        MGLevel &L = c.lv.L[l];
+        L.nr = nr;
+        L.nz = nz;
+        L.nr1 = nr + 1;
+        L.nodes = (nz + 1) * (nr + 1);
+        L.nine = l > 0;
+        L.phi = l == 0 ? c.pz : cv.take<double>(L.nodes);
+        L.rhs = l == 0 ? c.pr : cv.take<double>(L.nodes);
+        if (l == 0) {
+            L.cw = cv.take<double>(L.nodes);
+            L.ce = cv.take<double>(L.nodes);
+            L.cs = cv.take<double>(L.nodes);
+            L.cn = cv.take<double>(L.nodes);
+            L.cc = cv.take<double>(L.nodes);
+            L.a = nullptr;
+        } else {
+            L.cw = L.ce = L.cs = L.cn = L.cc = nullptr;
+            L.a = cv.take<double>(9 * (size_t)L.nodes);
+        }
+        L.dir = cv.take<uint8_t>(L.nodes);
+        nr /= 2;
+        nz /= 2;
+    }
+    c.phi_prev = cv.take<double>(nodes);
+    {
+        const MGLevel &Lc = c.lv.L[nl - 1];
+        c.lv.coarse_inv = cv.take<double>((size_t)Lc.nodes * Lc.nodes);
+    }
+    c.mgs = cv.take<MGState>(1);
+    c.mgpartial = cv.take<double>(pcg_partial_size(nodes));
+    // face list upper bound: 4 faces per turn node
+    int nturn_nodes = 0;
+    if (!c.tag.empty())
+        for (int32_t t : c.tag) nturn_nodes += t >= 1;
+    const int fmax = 4 * nturn_nodes + 1;
+    c.fp = cv.take<int32_t>(fmax);
+    c.fq = cv.take<int32_t>(fmax);
+    c.fk = cv.take<int32_t>(fmax);
+    c.fc = cv.take<double>(fmax);
+    c.Qk = cv.take<double>(MAX_TURNS);
+}
+
+static pic_status check_config(const pic_config *f, pic_ctx *c)
+{
+    if (!f) return fail(c, PIC_EINVAL, "null config");
+    if (f->nr < 2 || f->nz < 2) return fail(c, PIC_EINVAL, "grid too small (%d x %d)", f->nr, f->nz);
+    if (f->ip < 1 || f->ip > f->nz) return fail(c, PIC_EINVAL, "ip = %d outside 1..nz", f->ip);
+    if (!(f->rmax > 0) || !(f->zmax > 0) || !(f->dt > 0) || !(f->freq > 0))
+        return fail(c, PIC_EINVAL, "rmax, zmax, dt, freq must be positive");
+    if (f->precision != PIC_FP64 && f->precision != PIC_MIXED) return fail(c, PIC_EINVAL, "bad precision");
+    for (int s = 0; s < 2; ++s) {
+        if (f->capacity[s] < 1 || f->capacity[s] >= (int64_t)1 << 31)
+            return fail(c, PIC_EINVAL, "capacity[%d] outside 1 .. 2^31-1", s);
+        if (f->load && f->np_init[s] > f->capacity[s]) return fail(c, PIC_ENOMEM, "np_init > capacity");
+        if (!(f->m[s] > 0)) return fail(c, PIC_EINVAL, "mass must be positive");
+    }
+    if (f->nturns < 0 || f->nturns > MAX_TURNS) return fail(c, PIC_EINVAL, "nturns outside 0..%d", MAX_TURNS);
+    if (f->nturns > 0 && (!f->turn_vc || !f->turn_vs)) return fail(c, PIC_EINVAL, "turn voltages missing");
+    if (!f->eps_cell || !f->node_tag) return fail(c, PIC_EINVAL, "eps_cell and node_tag are required");
+    if (f->sort_every < 1) return fail(c, PIC_EINVAL, "sort_every must be >= 1");
+    if (f->birth_capacity < 0) return fail(c, PIC_EINVAL, "birth_capacity < 0");
+    return PIC_OK;
+}
+
+static pic_status prepare_host(pic_ctx &c, const pic_config *f)
+{
+    c.cfg = *f;
+    c.mixed = f->precision == PIC_MIXED;
+    const int nodes = (f->nz + 1) * (f->nr + 1), ncells = f->nz * f->nr;
+    c.eps_cell.assign(f->eps_cell, f->eps_cell + ncells);
+    c.tag.assign(f->node_tag, f->node_tag + nodes);
+    c.ec.assign(nodes, 0.0);
+    c.es.assign(nodes, 0.0);
+    if (f->ec) c.ec.assign(f->ec, f->ec + nodes);
+    if (f->es_sto) c.es.assign(f->es_sto, f->es_sto + nodes);
+    c.vc.assign(MAX_TURNS, 0.0);
+    c.vs.assign(MAX_TURNS, 0.0);
+    for (int k = 0; k < f->nturns; ++k) {
+        c.vc[k] = f->turn_vc[k];
+        c.vs[k] = f->turn_vs[k];
+    }
+    for (int n = 0; n < nodes; ++n)
+        if (c.tag[n] > f->nturns || c.tag[n] < -1) return fail(&c, PIC_EINVAL, "node tag %d invalid", c.tag[n]);
+    // the particle box must be free of Dirichlet nodes inside (rows 1..ip-1, cols 0..nr-1)
+    for (int i = 1; i < f->ip; ++i)
+        for (int j = 0; j < f->nr; ++j)
+            if (c.tag[i * (f->nr + 1) + j] != -1)
+                return fail(&c, PIC_EINVAL, "Dirichlet node (%d, %d) inside the particle region", i, j);
+    c.g.nr = f->nr;
+    c.g.nz = f->nz;
+    c.g.nr1 = f->nr + 1;
+    c.g.nodes = nodes;
+    c.g.ncells = ncells;
+    c.g.ip = f->ip;
+    c.g.window = f->window;
+    c.g.dr = f->rmax / f->nr;
+    c.g.dz = f->zmax / f->nz;
+    c.g.inv_nr = 1.0f / (float)f->nr;
+    if ((int64_t)f->nr * f->nz >= (1 << 22)) return fail(&c, PIC_EINVAL, "grid too large (nr nz >= 2^22)");
+    null_constants(*f, c.numax, c.pnull, c.lq);
+    const double nf = 1.0 / (f->freq * f->dt);
+    c.nrf = (int)std::lround(nf);
+    c.closed = std::fabs(f->freq * f->dt * c.nrf - 1.0) < 1e-10;
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_workspace_bytes(const pic_config *cfg, size_t *bytes)
+{
+    if (!bytes) return PIC_EINVAL;
+    pic_ctx c;
+    pic_status st = check_config(cfg, &c);
+    if (st) return st;
+    st = prepare_host(c, cfg);
+    if (st) return st;
+    Carver cv{nullptr};
+    layout(c, cv);
+    *bytes = cv.off + 256;
+    return PIC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Templated orchestration
+// ---------------------------------------------------------------------------
+template <typename T> static Parts<T> &parts(pic_ctx &c, int s, int b);
+template <> Parts<float> &parts<float>(pic_ctx &c, int s, int b) { return c.pf[s][b]; }
+template <> Parts<double> &parts<double>(pic_ctx &c, int s, int b) { return c.pd[s][b]; }
+template <typename T> static Births<T> &births(pic_ctx &c);
+template <> Births<float> &births<float>(pic_ctx &c) { return c.bf; }
+template <> Births<double> &births<double>(pic_ctx &c) { return c.bd; }
+
+template <typename T> static PassArgs<T> pass_args(pic_ctx &c, int s, int64_t step)
+{
+    PassArgs<T> a{};
+    a.p = parts<T>(c, s, c.cur[s]);
+    a.q = c.cq[s];
+    a.count = c.ctl + s;
+    a.ef = reinterpret_cast<const typename Field4<T>::type *>(c.ef);
+    a.accJ = c.accJ + (size_t)s * c.g.nodes;
+    a.accQ = c.accQ + (size_t)s * c.g.nodes;
+    a.accS = c.accS + (size_t)s * c.g.nodes;
+    a.stats = c.stats;
+    a.err = c.errw;
+    a.g = c.g;
+    a.sc = c.sc[s];
+    a.mc = c.mc;
+    a.b = births<T>(c);
+    a.step = (int32_t)step;
+    return a;
+}
+
+template <typename T> static void sort_species(pic_ctx &c, int s)
+{
+    const int from = c.cur[s], to = 1 - from;
+    timer_start(c, c.t_sort);
+    launch_sort<T>(parts<T>(c, s, from), parts<T>(c, s, to), c.ctl + s, c.ctl + 2 + s, c.hist, c.cursor, c.g.ncells,
+                   c.cfg.capacity[s], c.stream);
+    timer_stop(c, c.t_sort);
+    c.cur[s] = to;
+}
+
+template <typename T> static void stage(pic_ctx &c, int64_t n)
+{
+    const double th = TWO_PI * (double)(n % c.nrf) / (double)c.nrf;
+    launch_stage<T>(c.phi, c.d_ec, c.d_es, std::cos(th), std::sin(th),
+                    reinterpret_cast<typename Field4<T>::type *>(c.ef), c.accJ, c.accQ, true, c.g, c.stream);
+}
+
+template <typename T> static void run_pass(pic_ctx &c, int64_t n, bool push, bool depq)
+{
+    const bool timed = push;
+    if (timed) timer_start(c, c.t_pass);
+    for (int s = 0; s < 2; ++s) launch_pass<T>(pass_args<T>(c, s, n), c.cfg.capacity[s], push, depq, c.stream);
+    if (timed) timer_stop(c, c.t_pass);
+}
+
+template <typename T> static void run_collide(pic_ctx &c, int64_t n)
+{
+    for (int s = 0; s < 2; ++s) launch_collide<T>(pass_args<T>(c, s, n), c.stream);
+}
+
+template <typename T> static void run_births(pic_ctx &c, bool deposit)
+{
+    launch_births<T>(births<T>(c), parts<T>(c, 0, c.cur[0]), parts<T>(c, 1, c.cur[1]), c.ctl, c.ctl + 4,
+                     c.cfg.capacity[0], c.cfg.capacity[1], c.accQ, c.accQ + c.g.nodes, deposit, c.qscale, c.g,
+                     c.errw, c.stats, c.stream);
+}
+
+static void finalize_charge(pic_ctx &c)
+{
+    const pic_config &f = c.cfg;
+    launch_finalize_q(c.accQ, c.accS, f.q[0] * f.w[0] / c.qscale, f.q[1] * f.w[1] / c.qscale,
+                      f.q[0] * f.w[0], f.q[1] * f.w[1], c.Q, c.g.nodes, c.stream);
+}
+
+// V-cycle on the correction: two red-black sweeps on the 5-point fine
+// level, one four-colour sweep on the Galerkin levels, exact coarsest solve.
+static void vcycle(pic_ctx &c)
+{
+    for (int l = 0; l < c.lb; ++l) {
+        const int nc = c.lv.L[l].nine ? 4 : 2;
+        const int nu = l == 0 ? 2 : 1;
+        for (int k = 0; k < nu; ++k)
+            for (int col = 0; col < nc; ++col) launch_mg_smooth(c.lv.L[l], col, c.mgs, c.stream);
+        launch_mg_restrict(c.lv.L[l], c.lv.L[l + 1], c.mgs, c.stream);
+    }
+    launch_mg_bottom(c.lv, c.lb, c.lb == 0 ? 2 : 1, c.lb == 0 ? 2 : 1, 0, c.mgs, c.stream);
+    for (int l = c.lb - 1; l >= 0; --l) {
+        launch_mg_prolong(c.lv.L[l], c.lv.L[l + 1], c.mgs, c.stream);
+        const int nc = c.lv.L[l].nine ? 4 : 2;
+        const int nu = l == 0 ? 2 : 1;
+        for (int k = 0; k < nu; ++k)
+            for (int col = nc - 1; col >= 0; --col) launch_mg_smooth(c.lv.L[l], col, c.mgs, c.stream);
+    }
+}
+
+// Preconditioned CG on the free nodes (x = phi, b = node charge), one
+// V-cycle per iteration; scalars stay on the device.
+static pic_status solve(pic_ctx &c, int64_t n, double rtol, int max_cycles, pic_solve_info *info, bool full = false)
+{
+    const double th = TWO_PI * (double)(n % c.nrf) / (double)c.nrf;
+    timer_start(c, c.t_poisson);
+    const MGLevel &L0 = c.lv.L[0];
+    const PCGVec v{c.phi, c.Q, c.pr, c.pz, c.pp, c.pAp};
+    // budget from the latest finished solves (pinned ring, read without waiting)
+    int budget = max_cycles;
+    if (!info && !full && c.mg_host) {
+        int seen = 0;
+        bool short_run = false;
+        for (int k = 0; k < 4; ++k) {
+            const volatile MGState *h = c.mg_host + k;
+            if (h->ticket == 0xFFFFFFFFu) continue;   // never written
+            seen = std::max(seen, (int)h->cycles);
+            if (!h->done) short_run = true;
+        }
+        if (short_run) {
+            c.mg_budget = std::min(max_cycles, c.mg_budget + 4);
+        } else if (seen > 0) {
+            c.mg_budget = std::min(max_cycles, seen + 2);
+        }
+        budget = std::max(2, std::min(max_cycles, c.mg_budget));
+    }
+    // extrapolate only across consecutive steps of a running sequence
+    const bool extrap = c.have_prev && n == c.last_solve + 1 && !full && !info;
+    launch_pcg_begin(L0, v, c.d_tag, c.d_vc, c.d_vs, std::cos(th), std::sin(th), c.mgs, c.phi_prev, extrap, c.stream);
+    c.have_prev = true;
+    c.last_solve = n;
+    launch_pcg_resid(L0, v, c.mgs, c.mgpartial, rtol, c.stream);
+    for (int k = 0; k < budget; ++k) {
+        vcycle(c);
+        launch_pcg_rz(L0, v, c.mgs, c.mgpartial, c.stream);
+        launch_pcg_p(L0, v, c.mgs, c.stream);
+        launch_pcg_matvec(L0, v, c.mgs, c.mgpartial, c.stream);
+        launch_pcg_update(L0, v, c.mgs, c.mgpartial, rtol, c.stream);
+    }
+    if (c.cfg.nturns > 0)
+        launch_face_charge(c.phi, c.fp, c.fq, c.fk, c.fc, c.nfaces, c.Qk, c.cfg.nturns, c.stream);
+    timer_stop(c, c.t_poisson);
+    if (c.mg_host) {
+        (void)hipMemcpyAsync(c.mg_host + c.mg_ring, c.mgs, sizeof(MGState), hipMemcpyDeviceToHost, c.stream);
+        c.mg_ring = (c.mg_ring + 1) % 4;
+    }
+    if (info) {
+        MGState s;
+        HIPCHK(&c, hipMemcpyAsync(&s, c.mgs, sizeof s, hipMemcpyDeviceToHost, c.stream));
+        HIPCHK(&c, hipStreamSynchronize(c.stream));
+        info->cycles = s.cycles;
+        info->converged = s.done;
+        info->rel_residual = s.rel;
+        if (!s.done) return fail(&c, PIC_ENOTCONV, "multigrid-CG: rel residual %.3e after %d iterations", s.rel,
+                                 s.cycles);
+    }
+    return PIC_OK;
+}
+
+template <typename T> static pic_status init_impl(pic_ctx &c)
+{
+    const pic_config &f = c.cfg;
+    hipStream_t st = c.stream;
+    const int nodes = c.g.nodes;
+    // zero every counter / accumulator region
+    HIPCHK(&c, hipMemsetAsync(c.ctl, 0, 8 * sizeof(int64_t), st));
+    HIPCHK(&c, hipMemsetAsync(c.stats, 0, ST_NSTAT * sizeof(unsigned long long), st));
+    HIPCHK(&c, hipMemsetAsync(c.errw, 0, sizeof(int32_t), st));
+    HIPCHK(&c, hipMemsetAsync(c.hist, 0, (c.g.ncells + 1) * sizeof(int32_t), st));
+    HIPCHK(&c, hipMemsetAsync(births<T>(c).count, 0, sizeof(int32_t), st));
+    for (int s2 = 0; s2 < 2; ++s2) HIPCHK(&c, hipMemsetAsync(c.cq[s2].count, 0, sizeof(int32_t), st));
+    HIPCHK(&c, hipMemsetAsync(c.accS, 0, 2 * (size_t)nodes * sizeof(double), st));
+    HIPCHK(&c, hipMemsetAsync(c.phi, 0, nodes * sizeof(double), st));
+    HIPCHK(&c, hipMemsetAsync(c.I, 0, nodes * sizeof(double), st));
+    HIPCHK(&c, hipMemsetAsync(c.Jc, 0, nodes * sizeof(double), st));
+    HIPCHK(&c, hipMemsetAsync(c.Jcc, 0, nodes * sizeof(double), st));
+    HIPCHK(&c, hipMemsetAsync(c.Js, 0, nodes * sizeof(double), st));
+    HIPCHK(&c, hipMemsetAsync(c.Jsc, 0, nodes * sizeof(double), st));
+    HIPCHK(&c, hipMemsetAsync(c.harm, 0, sizeof(HarmState), st));
+    HIPCHK(&c, hipMemsetAsync(c.Qk, 0, MAX_TURNS * sizeof(double), st));
+    HIPCHK(&c, hipMemsetAsync(c.mgs, 0, sizeof(MGState), st));
+    HIPCHK(&c, hipMemcpyAsync(c.d_ec, c.ec.data(), nodes * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(&c, hipMemcpyAsync(c.d_es, c.es.data(), nodes * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(&c, hipMemcpyAsync(c.d_tag, c.tag.data(), nodes * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    HIPCHK(&c, hipMemcpyAsync(c.d_vc, c.vc.data(), MAX_TURNS * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(&c, hipMemcpyAsync(c.d_vs, c.vs.data(), MAX_TURNS * sizeof(double), hipMemcpyHostToDevice, st));
+
+    // multigrid hierarchy: finite-volume fine operator, Galerkin coarse levels
+    {
+        const Coeffs co = assemble(f.nr, f.nz, c.g.dr, c.g.dz, c.eps_cell, f.eps0);
+        std::vector<uint8_t> dir(nodes);
+        for (int n = 0; n < nodes; ++n) dir[n] = c.tag[n] >= 0;
+        // turn face list (Eq. facecharge): faces from a turn-k node to a node outside turn k
+        {
+            std::vector<int32_t> hp, hq, hk;
+            std::vector<double> hc;
+            const int nr1 = f.nr + 1;
+            for (int n = 0; n < nodes; ++n) {
+                const int k = c.tag[n];
+                if (k < 1) continue;
+                const int i = n / nr1, j = n - i * nr1;
+                const int nb[4] = {j > 0 ? n - 1 : -1, j < f.nr ? n + 1 : -1, i > 0 ? n - nr1 : -1,
+                                   i < f.nz ? n + nr1 : -1};
+                const double cf[4] = {co.cw[n], co.ce[n], co.cs[n], co.cn[n]};
+                for (int q = 0; q < 4; ++q) {
+                    if (nb[q] < 0 || c.tag[nb[q]] == k || cf[q] == 0.0) continue;
+                    hp.push_back(n);
+                    hq.push_back(nb[q]);
+                    hk.push_back(k - 1);
+                    hc.push_back(cf[q]);
+                }
+            }
+            c.nfaces = (int)hp.size();
+            if (c.nfaces) {
+                HIPCHK(&c, cpy(c.stream, c.fp, hp.data(), hp.size() * 4, hipMemcpyHostToDevice));
+                HIPCHK(&c, cpy(c.stream, c.fq, hq.data(), hq.size() * 4, hipMemcpyHostToDevice));
+                HIPCHK(&c, cpy(c.stream, c.fk, hk.data(), hk.size() * 4, hipMemcpyHostToDevice));
+                HIPCHK(&c, cpy(c.stream, c.fc, hc.data(), hc.size() * 8, hipMemcpyHostToDevice));
+            }
+        }
+        MGLevel &L0 = c.lv.L[0];
+        const size_t nb = (size_t)nodes * sizeof(double);
+        HIPCHK(&c, cpy(c.stream, (void *)L0.cw, co.cw.data(), nb, hipMemcpyHostToDevice));
+        HIPCHK(&c, cpy(c.stream, (void *)L0.ce, co.ce.data(), nb, hipMemcpyHostToDevice));
+        HIPCHK(&c, cpy(c.stream, (void *)L0.cs, co.cs.data(), nb, hipMemcpyHostToDevice));
+        HIPCHK(&c, cpy(c.stream, (void *)L0.cn, co.cn.data(), nb, hipMemcpyHostToDevice));
+        HIPCHK(&c, cpy(c.stream, (void *)L0.cc, co.cc.data(), nb, hipMemcpyHostToDevice));
+        HIPCHK(&c, cpy(c.stream, (void *)L0.dir, dir.data(), nodes, hipMemcpyHostToDevice));
+        Stencil9 S;
+        S.nr = f.nr;
+        S.nz = f.nz;
+        S.dir = dir;
+        S.a.assign(9 * (size_t)nodes, 0.0);
+        for (int n = 0; n < nodes; ++n) {
+            S.a[(size_t)4 * nodes + n] = co.cc[n];
+            S.a[(size_t)3 * nodes + n] = -co.cw[n];
+            S.a[(size_t)5 * nodes + n] = -co.ce[n];
+            S.a[(size_t)1 * nodes + n] = -co.cs[n];
+            S.a[(size_t)7 * nodes + n] = -co.cn[n];
+        }
+        for (int l = 1; l < c.lv.n; ++l) {
+            S = galerkin(S);
+            MGLevel &L = c.lv.L[l];
+            HIPCHK(&c, cpy(c.stream, (void *)L.a, S.a.data(), S.a.size() * sizeof(double), hipMemcpyHostToDevice));
+            HIPCHK(&c, cpy(c.stream, (void *)L.dir, S.dir.data(), S.dir.size(), hipMemcpyHostToDevice));
+            HIPCHK(&c, mset(c.stream, L.phi, 0, (size_t)L.nodes * sizeof(double)));
+            HIPCHK(&c, mset(c.stream, L.rhs, 0, (size_t)L.nodes * sizeof(double)));
+        }
+        for (double *v : {c.pr, c.pz, c.pp, c.pAp, c.phi_prev}) HIPCHK(&c, mset(c.stream, v, 0, nb));
+        // dense inverse of the coarsest level (Gauss-Jordan, partial pivoting); rows and
+        // columns of its Dirichlet nodes are zero so their correction stays 0
+        {
+            const int m = (S.nz + 1) * (S.nr + 1), nr1 = S.nr + 1;
+            std::vector<double> A((size_t)m * m, 0.0), Inv((size_t)m * m, 0.0);
+            for (int n = 0; n < m; ++n) {
+                const int i = n / nr1, j = n - i * nr1;
+                for (int k = 0; k < 9; ++k) {
+                    const int di = k / 3 - 1, dj = k % 3 - 1;
+                    if (i + di < 0 || i + di > S.nz || j + dj < 0 || j + dj > S.nr) continue;
+                    A[(size_t)n * m + (n + di * nr1 + dj)] = S.a[(size_t)k * m + n];
+                }
+                Inv[(size_t)n * m + n] = 1.0;
+            }
+            for (int col = 0; col < m; ++col) {
+                int piv = col;
+                for (int r = col + 1; r < m; ++r)
+                    if (std::fabs(A[(size_t)r * m + col]) > std::fabs(A[(size_t)piv * m + col])) piv = r;
+                if (A[(size_t)piv * m + col] == 0.0) return fail(&c, PIC_EINVAL, "singular coarsest multigrid level");
+                if (piv != col)
+                    for (int k = 0; k < m; ++k) {
+                        std::swap(A[(size_t)piv * m + k], A[(size_t)col * m + k]);
+                        std::swap(Inv[(size_t)piv * m + k], Inv[(size_t)col * m + k]);
+                    }
+                const double d = A[(size_t)col * m + col];
+                for (int k = 0; k < m; ++k) {
+                    A[(size_t)col * m + k] /= d;
+                    Inv[(size_t)col * m + k] /= d;
+                }
+                for (int r = 0; r < m; ++r) {
+                    if (r == col) continue;
+                    const double f2 = A[(size_t)r * m + col];
+                    if (f2 == 0.0) continue;
+                    for (int k = 0; k < m; ++k) {
+                        A[(size_t)r * m + k] -= f2 * A[(size_t)col * m + k];
+                        Inv[(size_t)r * m + k] -= f2 * Inv[(size_t)col * m + k];
+                    }
+                }
+            }
+            for (int n = 0; n < m; ++n)
+                if (S.dir[n])
+                    for (int k = 0; k < m; ++k) Inv[(size_t)n * m + k] = Inv[(size_t)k * m + n] = 0.0;
+            HIPCHK(&c, cpy(c.stream, (void *)c.lv.coarse_inv, Inv.data(), Inv.size() * sizeof(double),
+                           hipMemcpyHostToDevice));
+        }
+    }
+    c.lb = 0;
+    while (c.lb < c.lv.n - 1 && c.lv.L[c.lb].nodes > 2200) ++c.lb;
+
+    // fixed-point scales
+    const double cells = (double)f.nr * f.ip;
+    const double ppc = (double)std::max(f.capacity[0], f.capacity[1]) / std::max(1.0, cells);
+    const int64_t kq = 62 - ceil_log2(256.0 * ppc + 1024.0);
+    c.qscale = std::ldexp(1.0, (int)kq);
+    c.jscale = std::ldexp(1.0, (int)(kq - 6));
+
+    // species and collision constants (null-collision constants: prepare_host)
+    for (int s = 0; s < 2; ++s) {
+        SpeciesC &sc = c.sc[s];
+        sc.s = s;
+        sc.h = 0.5 * f.q[s] / f.m[s] * f.dt;
+        sc.dtr = f.dt / c.g.dr;
+        sc.dtz = f.dt / c.g.dz;
+        double t2 = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            sc.bt[k] = sc.h * f.bfield[k];
+            t2 += sc.bt[k] * sc.bt[k];
+        }
+        for (int k = 0; k < 3; ++k) sc.bs[k] = 2.0 * sc.bt[k] / (1.0 + t2);
+        sc.has_b = t2 > 0.0;
+        sc.jscale = c.jscale;
+        sc.qscale = c.qscale;
+        sc.vref = std::sqrt(std::max(f.temp_ev[s], 1e-3) * f.qe / f.m[s]);
+        sc.inv_vref = 1.0 / sc.vref;
+    }
+    c.mc.seed = f.seed;
+    c.mc.xs_kind = f.xs_kind;
+    for (int s = 0; s < 2; ++s) {
+        c.mc.numax[s] = c.numax[s];
+        c.mc.lq[s] = c.lq[s];
+    }
+    c.mc.ngas = f.ngas;
+    c.mc.qe = f.qe;
+    c.mc.me = f.m[0];
+    c.mc.mi = f.m[1];
+    c.mc.vg = std::sqrt(f.tgas_ev * f.qe / f.m[1]);
+    for (int k = 0; k < 13; ++k) c.mc.xs[k] = f.xs[k];
+
+    // plasma
+    if (f.load) {
+        for (int s = 0; s < 2; ++s) {
+            const double vth = std::sqrt(f.temp_ev[s] * f.qe / f.m[s]);
+            launch_load<T>(parts<T>(c, s, c.cur[s]), f.np_init[s], f.seed, s, f.rmax, f.ip * c.g.dz, vth, c.lq[s],
+                           c.g, st);
+        }
+        int64_t h[8] = {f.np_init[0], f.np_init[1], 0, 0, f.np_init[0], f.np_init[1], 0, 0};
+        HIPCHK(&c, hipMemcpyAsync(c.ctl, h, sizeof h, hipMemcpyHostToDevice, st));
+        HIPCHK(&c, hipStreamSynchronize(st));
+        for (int s = 0; s < 2; ++s) sort_species<T>(c, s);
+    }
+    stage<T>(c, 0);
+    run_pass<T>(c, 0, false, true);
+    finalize_charge(c);
+    pic_status s = solve(c, 0, f.mg_rtol, f.mg_max_cycles, nullptr, true);
+    if (s) return s;
+    HIPCHK(&c, hipStreamSynchronize(st));
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_init(const pic_config *cfg, void *workspace, size_t workspace_bytes, void *stream,
+                               pic_ctx **out)
+{
+    if (!out) return PIC_EINVAL;
+    *out = nullptr;
+    pic_ctx *c = new pic_ctx();
+    pic_status st = check_config(cfg, c);
+    if (!st) st = prepare_host(*c, cfg);
+    if (st) {
+        delete c;
+        return st;
+    }
+    Carver dry{nullptr};
+    layout(*c, dry);
+    if (!workspace || workspace_bytes < dry.off) {
+        delete c;
+        return PIC_ENOMEM;
+    }
+    Carver cv{reinterpret_cast<uint8_t *>(workspace)};
+    layout(*c, cv);
+    c->stream = reinterpret_cast<hipStream_t>(stream);
+    if (hipHostMalloc((void **)&c->mg_host, 4 * sizeof(MGState), hipHostMallocDefault) == hipSuccess) {
+        for (int k = 0; k < 4; ++k) {
+            std::memset(c->mg_host + k, 0, sizeof(MGState));
+            c->mg_host[k].ticket = 0xFFFFFFFFu;
+        }
+    } else {
+        c->mg_host = nullptr;
+    }
+    st = c->mixed ? init_impl<float>(*c) : init_impl<double>(*c);
+    if (st) {
+        pic_destroy(c);
+        return st;
+    }
+    *out = c;
+    return PIC_OK;
+}
+
+static pic_status sticky(pic_ctx *c)
+{
+    int32_t e = 0;
+    HIPCHK(c, hipMemcpyAsync(&e, c->errw, sizeof e, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (e & ERR_BIRTH_OVERFLOW) return fail(c, PIC_ENOMEM, "birth buffer overflow (raise birth_capacity)");
+    if (e & ERR_CAPACITY) return fail(c, PIC_ENOMEM, "particle capacity exceeded");
+    if (e & ERR_QUEUE_OVERFLOW) return fail(c, PIC_ENOMEM, "collision-candidate queue overflow");
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_gather_push(pic_ctx *c, int64_t n)
+{
+    if (!c) return PIC_EINVAL;
+    if (n != c->last_push + 1) return fail(c, PIC_ESTATE, "pic_gather_push(%lld) after step %lld", (long long)n,
+                                           (long long)c->last_push);
+    if (n > 2147483000ll) return fail(c, PIC_EINVAL, "step index too large");
+    const bool fuse = c->cfg.fuse != 0;
+    if (c->mixed) {
+        if (n % c->cfg.sort_every == 0 && n > 0) {
+            sort_species<float>(*c, 0);
+            sort_species<float>(*c, 1);
+        }
+        stage<float>(*c, n);
+        run_pass<float>(*c, n, true, fuse);
+    } else {
+        if (n % c->cfg.sort_every == 0 && n > 0) {
+            sort_species<double>(*c, 0);
+            sort_species<double>(*c, 1);
+        }
+        stage<double>(*c, n);
+        run_pass<double>(*c, n, true, fuse);
+    }
+    c->last_push = n;
+    return hipGetLastError() == hipSuccess ? PIC_OK : fail(c, PIC_EDEVICE, "kernel launch failed");
+}
+
+extern "C" pic_status mcc_collide(pic_ctx *c, int64_t n)
+{
+    if (!c) return PIC_EINVAL;
+    if (n != c->last_push || c->last_mcc == n) return fail(c, PIC_ESTATE, "mcc_collide(%lld) out of order", (long long)n);
+    const bool fuse = c->cfg.fuse != 0;
+    if (c->mixed) {
+        run_collide<float>(*c, n);
+        run_births<float>(*c, fuse);
+    } else {
+        run_collide<double>(*c, n);
+        run_births<double>(*c, fuse);
+    }
+    c->last_mcc = n;
+    return hipGetLastError() == hipSuccess ? PIC_OK : fail(c, PIC_EDEVICE, "kernel launch failed");
+}
+
+extern "C" pic_status pic_deposit(pic_ctx *c, int64_t n1)
+{
+    if (!c) return PIC_EINVAL;
+    if (n1 != c->last_push + 1 || c->last_mcc != c->last_push)
+        return fail(c, PIC_ESTATE, "pic_deposit(%lld) out of order", (long long)n1);
+    if (!c->cfg.fuse) {
+        if (c->mixed)
+            run_pass<float>(*c, n1 - 1, false, true);
+        else
+            run_pass<double>(*c, n1 - 1, false, true);
+    }
+    finalize_charge(*c);
+    return hipGetLastError() == hipSuccess ? PIC_OK : fail(c, PIC_EDEVICE, "kernel launch failed");
+}
+
+extern "C" pic_status poisson_solve_rz(pic_ctx *c, int64_t n, double rtol, int32_t max_cycles, pic_solve_info *info)
+{
+    if (!c) return PIC_EINVAL;
+    if (rtol <= 0) rtol = c->cfg.mg_rtol;
+    if (max_cycles <= 0) max_cycles = c->cfg.mg_max_cycles;
+    return solve(*c, n, rtol, max_cycles, info);
+}
+
+extern "C" pic_status harmonic_accumulate(pic_ctx *c, int64_t n)
+{
+    if (!c) return PIC_EINVAL;
+    if (n != c->last_push || c->last_harm == n)
+        return fail(c, PIC_ESTATE, "harmonic_accumulate(%lld) out of order", (long long)n);
+    const pic_config &f = c->cfg;
+    const double th = TWO_PI * (double)(n % c->nrf) / (double)c->nrf;
+    const double cj0 = f.q[0] * f.w[0] * c->sc[0].vref / c->jscale, cj1 = f.q[1] * f.w[1] * c->sc[1].vref / c->jscale;
+    launch_harmonic(c->accJ, cj0, cj1, c->d_ec, c->d_es, std::cos(th), std::sin(th), c->I, c->Jc, c->Jcc, c->Js,
+                    c->Jsc, c->hpartial, c->harm, c->Qk, c->d_vc, c->d_vs, f.nturns, c->g.nodes, c->stream);
+    c->last_harm = n;
+    return hipGetLastError() == hipSuccess ? PIC_OK : fail(c, PIC_EDEVICE, "kernel launch failed");
+}
+
+extern "C" pic_status circuit_period_update(pic_ctx *c, const double *new_vc, const double *new_vs,
+                                            const double *new_ec, const double *new_es, pic_period_report *rep,
+                                            double *jc, double *js)
+{
+    if (!c) return PIC_EINVAL;
+    pic_status st = sticky(c);
+    if (st) return st;
+    HarmState h;
+    HIPCHK(c, cpy(c->stream, &h, c->harm, sizeof h, hipMemcpyDeviceToHost));
+    const int N = c->nrf, K = c->cfg.nturns;
+    if (rep) {
+        std::memset(rep, 0, sizeof *rep);
+        rep->samples = h.samples;
+    }
+    if (!c->closed) return fail(c, PIC_EPHASE, "phase closure |f dt N_RF - 1| >= 1e-10: period update rejected");
+    if (h.samples != N) return fail(c, PIC_EPHASE, "%d samples in the period, N_RF = %d: update rejected", h.samples, N);
+    const double w = TWO_PI * c->cfg.freq;
+    if (rep) {
+        rep->accepted = 1;
+        rep->p_ind = (h.pind + h.pind_c) / N;
+        double wsum = 0.0, pph = 0.0;
+        for (int k = 0; k < K; ++k) {
+            const double Wk = (h.w[k] + h.w_c[k]) + 0.5 * (h.v_first[k] + h.v_prev[k]) * (h.q_first[k] - h.q_prev[k]);
+            wsum += Wk;
+            const double qc = 2.0 / N * (h.qc[k] + h.qc_c[k]), qs = 2.0 / N * (h.qs[k] + h.qs_c[k]);
+            rep->qc[k] = qc;
+            rep->qs[k] = qs;
+            rep->icap_re[k] = w * qs;
+            rep->icap_im[k] = w * qc;
+            // 1/2 Re( V conj(I) ), V = Vc - i Vs
+            pph += 0.5 * (c->vc[k] * rep->icap_re[k] - c->vs[k] * rep->icap_im[k]);
+        }
+        rep->p_cap = c->cfg.freq * wsum;
+        rep->p_cap_ph = pph;
+    }
+    const int nodes = c->g.nodes;
+    if (jc || js) {
+        std::vector<double> a(nodes), b(nodes);
+        if (jc) {
+            HIPCHK(c, cpy(c->stream, a.data(), c->Jc, nodes * 8, hipMemcpyDeviceToHost));
+            HIPCHK(c, cpy(c->stream, b.data(), c->Jcc, nodes * 8, hipMemcpyDeviceToHost));
+            for (int n = 0; n < nodes; ++n) jc[n] = 2.0 / N * (a[n] + b[n]);
+        }
+        if (js) {
+            HIPCHK(c, cpy(c->stream, a.data(), c->Js, nodes * 8, hipMemcpyDeviceToHost));
+            HIPCHK(c, cpy(c->stream, b.data(), c->Jsc, nodes * 8, hipMemcpyDeviceToHost));
+            for (int n = 0; n < nodes; ++n) js[n] = 2.0 / N * (a[n] + b[n]);
+        }
+    }
+    if (new_vc)
+        for (int k = 0; k < K; ++k) c->vc[k] = new_vc[k];
+    if (new_vs)
+        for (int k = 0; k < K; ++k) c->vs[k] = new_vs[k];
+    HIPCHK(c, cpy(c->stream, c->d_vc, c->vc.data(), MAX_TURNS * 8, hipMemcpyHostToDevice));
+    HIPCHK(c, cpy(c->stream, c->d_vs, c->vs.data(), MAX_TURNS * 8, hipMemcpyHostToDevice));
+    if (new_ec) {
+        c->ec.assign(new_ec, new_ec + nodes);
+        HIPCHK(c, cpy(c->stream, c->d_ec, new_ec, nodes * 8, hipMemcpyHostToDevice));
+    }
+    if (new_es) {
+        c->es.assign(new_es, new_es + nodes);
+        HIPCHK(c, cpy(c->stream, c->d_es, new_es, nodes * 8, hipMemcpyHostToDevice));
+    }
+    HIPCHK(c, mset(c->stream, c->Jc, 0, nodes * 8));
+    HIPCHK(c, mset(c->stream, c->Jcc, 0, nodes * 8));
+    HIPCHK(c, mset(c->stream, c->Js, 0, nodes * 8));
+    HIPCHK(c, mset(c->stream, c->Jsc, 0, nodes * 8));
+    HIPCHK(c, mset(c->stream, c->harm, 0, sizeof(HarmState)));
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_sync(pic_ctx *c)
+{
+    if (!c) return PIC_EINVAL;
+    return sticky(c);
+}
+
+extern "C" pic_status pic_clear_error(pic_ctx *c)
+{
+    if (!c) return PIC_EINVAL;
+    HIPCHK(c, hipMemsetAsync(c->errw, 0, sizeof(int32_t), c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->err.clear();
+    return PIC_OK;
+}
+
+template <typename T>
+static pic_status get_parts(pic_ctx *c, int s, int64_t cap, double *R, double *z, double *vr, double *vt, double *vz,
+                            uint32_t *id, int32_t *next, int64_t *count)
+{
+    hipStream_t st = c->stream;
+    const Parts<T> &p = parts<T>(*c, s, c->cur[s]);
+    launch_live_index(p.cell, c->ctl + s, c->live_index, c->ctl + 6, st);
+    int64_t slots = 0, nlive = 0;
+    HIPCHK(c, hipMemcpyAsync(&slots, c->ctl + s, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipMemcpyAsync(&nlive, c->ctl + 6, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    if (count) *count = nlive;
+    if (nlive > cap) return fail(c, PIC_ENOMEM, "%lld live particles > cap %lld", (long long)nlive, (long long)cap);
+    // chunks of slots whose live particles fit the staging area
+    int64_t k0 = 0;
+    std::vector<int64_t> idx(2);
+    while (k0 < slots) {
+        const int64_t k1 = std::min(slots, k0 + c->stage_cap);
+        int64_t lo = 0, hi = 0;
+        HIPCHK(c, cpy(c->stream, &lo, c->live_index + k0, 8, hipMemcpyDeviceToHost));
+        if (k1 < slots)
+            HIPCHK(c, cpy(c->stream, &hi, c->live_index + k1, 8, hipMemcpyDeviceToHost));
+        else
+            hi = nlive;
+        const int64_t m = hi - lo;
+        // shift the index so this chunk writes at 0 .. m
+        double *sR = c->stage, *sz = sR + c->stage_cap, *svr = sz + c->stage_cap, *svt = svr + c->stage_cap,
+               *svz = svt + c->stage_cap;
+        uint32_t *sid = reinterpret_cast<uint32_t *>(svz + c->stage_cap);
+        int32_t *snx = reinterpret_cast<int32_t *>(sid + c->stage_cap);
+        Parts<T> q = p;
+        q.cell += k0;
+        q.dr += k0;
+        q.dz += k0;
+        q.vr += k0;
+        q.vt += k0;
+        q.vz += k0;
+        q.id += k0;
+        q.next += k0;
+        // temporary count = chunk length in ctl[7]
+        const int64_t len = k1 - k0;
+        HIPCHK(c, cpy(c->stream, c->ctl + 7, &len, 8, hipMemcpyHostToDevice));
+        // rebased index: live_index[k0 + k] - lo
+        std::vector<int64_t> li(len);
+        HIPCHK(c, cpy(c->stream, li.data(), c->live_index + k0, len * 8, hipMemcpyDeviceToHost));
+        for (auto &v : li) v -= lo;
+        HIPCHK(c, cpy(c->stream, c->live_index + k0, li.data(), len * 8, hipMemcpyHostToDevice));
+        launch_unplace<T>(q, c->ctl + 7, len, c->live_index + k0, sR, sz, svr, svt, svz, sid, snx, c->g, st);
+        HIPCHK(c, hipStreamSynchronize(st));
+        if (m > 0) {
+            if (R) HIPCHK(c, cpy(c->stream, R + lo, sR, m * 8, hipMemcpyDeviceToHost));
+            if (z) HIPCHK(c, cpy(c->stream, z + lo, sz, m * 8, hipMemcpyDeviceToHost));
+            if (vr) HIPCHK(c, cpy(c->stream, vr + lo, svr, m * 8, hipMemcpyDeviceToHost));
+            if (vt) HIPCHK(c, cpy(c->stream, vt + lo, svt, m * 8, hipMemcpyDeviceToHost));
+            if (vz) HIPCHK(c, cpy(c->stream, vz + lo, svz, m * 8, hipMemcpyDeviceToHost));
+            if (id) HIPCHK(c, cpy(c->stream, id + lo, sid, m * 4, hipMemcpyDeviceToHost));
+            if (next) HIPCHK(c, cpy(c->stream, next + lo, snx, m * 4, hipMemcpyDeviceToHost));
+        }
+        k0 = k1;
+    }
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_get_particles(pic_ctx *c, int32_t s, int64_t cap, double *R, double *z, double *vr,
+                                        double *vt, double *vz, uint32_t *id, int32_t *next, int64_t *count)
+{
+    if (!c || s < 0 || s > 1) return PIC_EINVAL;
+    pic_status st = sticky(c);
+    if (st) return st;
+    return c->mixed ? get_parts<float>(c, s, cap, R, z, vr, vt, vz, id, next, count)
+                    : get_parts<double>(c, s, cap, R, z, vr, vt, vz, id, next, count);
+}
+
+template <typename T>
+static pic_status set_parts(pic_ctx *c, int s, int64_t n, const double *R, const double *z, const double *vr,
+                            const double *vt, const double *vz, const uint32_t *id, const int32_t *next)
+{
+    hipStream_t st = c->stream;
+    Parts<T> p = parts<T>(*c, s, c->cur[s]);
+    uint32_t maxid = 0;
+    for (int64_t k = 0; k < n; ++k) maxid = std::max(maxid, id[k]);
+    for (int64_t k0 = 0; k0 < n; k0 += c->stage_cap) {
+        const int64_t m = std::min(c->stage_cap, n - k0);
+        double *sR = c->stage, *sz = sR + c->stage_cap, *svr = sz + c->stage_cap, *svt = svr + c->stage_cap,
+               *svz = svt + c->stage_cap;
+        uint32_t *sid = reinterpret_cast<uint32_t *>(svz + c->stage_cap);
+        int32_t *snx = reinterpret_cast<int32_t *>(sid + c->stage_cap);
+        HIPCHK(c, cpy(c->stream, sR, R + k0, m * 8, hipMemcpyHostToDevice));
+        HIPCHK(c, cpy(c->stream, sz, z + k0, m * 8, hipMemcpyHostToDevice));
+        HIPCHK(c, cpy(c->stream, svr, vr + k0, m * 8, hipMemcpyHostToDevice));
+        HIPCHK(c, cpy(c->stream, svt, vt + k0, m * 8, hipMemcpyHostToDevice));
+        HIPCHK(c, cpy(c->stream, svz, vz + k0, m * 8, hipMemcpyHostToDevice));
+        HIPCHK(c, cpy(c->stream, sid, id + k0, m * 4, hipMemcpyHostToDevice));
+        HIPCHK(c, cpy(c->stream, snx, next + k0, m * 4, hipMemcpyHostToDevice));
+        Parts<T> q = p;
+        q.cell += k0;
+        q.dr += k0;
+        q.dz += k0;
+        q.vr += k0;
+        q.vt += k0;
+        q.vz += k0;
+        q.id += k0;
+        q.next += k0;
+        launch_place<T>(q, m, sR, sz, svr, svt, svz, sid, snx, c->g, st);
+        HIPCHK(c, hipStreamSynchronize(st));
+    }
+    int64_t h[2];
+    HIPCHK(c, cpy(c->stream, h, c->ctl + 4, 16, hipMemcpyDeviceToHost));
+    h[s] = std::max<int64_t>(h[s], (int64_t)maxid + 1);
+    HIPCHK(c, cpy(c->stream, c->ctl + 4, h, 16, hipMemcpyHostToDevice));
+    HIPCHK(c, cpy(c->stream, c->ctl + s, &n, 8, hipMemcpyHostToDevice));
+    sort_species<T>(*c, s);
+    HIPCHK(c, hipStreamSynchronize(st));
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_set_particles(pic_ctx *c, int32_t s, int64_t n, const double *R, const double *z,
+                                        const double *vr, const double *vt, const double *vz, const uint32_t *id,
+                                        const int32_t *next)
+{
+    if (!c || s < 0 || s > 1 || n < 0) return PIC_EINVAL;
+    if (n > c->cfg.capacity[s]) return fail(c, PIC_ENOMEM, "n > capacity");
+    if (n > 0 && (!R || !z || !vr || !vt || !vz || !id || !next)) return fail(c, PIC_EINVAL, "null array");
+    const double zp = c->g.ip * c->g.dz, rmax = c->cfg.rmax;
+    for (int64_t k = 0; k < n; ++k)
+        if (!(R[k] >= 0 && R[k] < rmax && z[k] >= 0 && z[k] < zp))
+            return fail(c, PIC_EINVAL, "particle %lld outside the particle region", (long long)k);
+    return c->mixed ? set_parts<float>(c, s, n, R, z, vr, vt, vz, id, next)
+                    : set_parts<double>(c, s, n, R, z, vr, vt, vz, id, next);
+}
+
+extern "C" pic_status pic_set_step(pic_ctx *c, int64_t n)
+{
+    if (!c || n < 0) return PIC_EINVAL;
+    c->last_push = n - 1;
+    c->last_mcc = n - 1;
+    c->last_harm = n - 1;
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_set_phi(pic_ctx *c, const double *phi)
+{
+    if (!c || !phi) return PIC_EINVAL;
+    c->have_prev = false;
+    HIPCHK(c, hipMemcpyAsync(c->phi, phi, c->g.nodes * 8, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return PIC_OK;
+}
+
+template <typename T> static void field_component(pic_ctx *c, int comp, double *out)
+{
+    std::vector<typename Field4<T>::type> f(c->g.nodes);
+    (void)cpy(c->stream, f.data(), c->ef, f.size() * sizeof(f[0]), hipMemcpyDeviceToHost);
+    for (int n = 0; n < c->g.nodes; ++n) out[n] = comp == 0 ? (double)f[n].x : comp == 1 ? (double)f[n].y : (double)f[n].z;
+}
+
+extern "C" pic_status pic_get_grid(pic_ctx *c, int32_t which, double *out)
+{
+    if (!c || !out) return PIC_EINVAL;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const int nodes = c->g.nodes;
+    switch (which) {
+    case PIC_GRID_PHI: HIPCHK(c, cpy(c->stream, out, c->phi, nodes * 8, hipMemcpyDeviceToHost)); break;
+    case PIC_GRID_CHARGE: HIPCHK(c, cpy(c->stream, out, c->Q, nodes * 8, hipMemcpyDeviceToHost)); break;
+    case PIC_GRID_CURRENT: HIPCHK(c, cpy(c->stream, out, c->I, nodes * 8, hipMemcpyDeviceToHost)); break;
+    case PIC_GRID_ER:
+    case PIC_GRID_EZ:
+    case PIC_GRID_ETHETA:
+        if (c->mixed)
+            field_component<float>(c, which - PIC_GRID_ER, out);
+        else
+            field_component<double>(c, which - PIC_GRID_ER, out);
+        break;
+    case PIC_GRID_SURFACE: {
+        std::vector<double> a(2 * (size_t)nodes);
+        HIPCHK(c, cpy(c->stream, a.data(), c->accS, a.size() * 8, hipMemcpyDeviceToHost));
+        const pic_config &f = c->cfg;
+        for (int n = 0; n < nodes; ++n) out[n] = f.q[0] * f.w[0] * a[n] + f.q[1] * f.w[1] * a[nodes + n];
+        break;
+    }
+    case PIC_GRID_JC:
+    case PIC_GRID_JS: {
+        std::vector<double> a(nodes), b(nodes);
+        HIPCHK(c, cpy(c->stream, a.data(), which == PIC_GRID_JC ? c->Jc : c->Js, nodes * 8, hipMemcpyDeviceToHost));
+        HIPCHK(c, cpy(c->stream, b.data(), which == PIC_GRID_JC ? c->Jcc : c->Jsc, nodes * 8, hipMemcpyDeviceToHost));
+        for (int n = 0; n < nodes; ++n) out[n] = a[n] + b[n];
+        break;
+    }
+    default: return fail(c, PIC_EINVAL, "unknown grid %d", which);
+    }
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_timing(pic_ctx *c, int32_t enable)
+{
+    if (!c) return PIC_EINVAL;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (auto *t : {&c->t_pass, &c->t_poisson, &c->t_sort}) {
+        timer_drain(*t);
+        t->ms = 0.0;
+        t->count = 0;
+    }
+    c->timing = enable != 0;
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_get_stats(pic_ctx *c, pic_stats *o)
+{
+    if (!c || !o) return PIC_EINVAL;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    std::memset(o, 0, sizeof *o);
+    for (auto *t : {&c->t_pass, &c->t_poisson, &c->t_sort}) timer_drain(*t);
+    o->pass_ms = c->t_pass.ms;
+    o->pass_count = c->t_pass.count;
+    o->poisson_ms = c->t_poisson.ms;
+    o->poisson_count = c->t_poisson.count;
+    o->sort_ms = c->t_sort.ms;
+    o->sort_count = c->t_sort.count;
+    {
+        MGState ms;
+        HIPCHK(c, cpy(c->stream, &ms, c->mgs, sizeof ms, hipMemcpyDeviceToHost));
+        o->mg_cycles = ms.cycles;
+        o->mg_rel = ms.rel;
+    }
+    int64_t ctl[8];
+    unsigned long long st[ST_NSTAT];
+    HIPCHK(c, cpy(c->stream, ctl, c->ctl, sizeof ctl, hipMemcpyDeviceToHost));
+    HIPCHK(c, cpy(c->stream, st, c->stats, sizeof st, hipMemcpyDeviceToHost));
+    for (int s = 0; s < 2; ++s) {
+        o->slots[s] = ctl[s];
+        o->next_id[s] = ctl[4 + s];
+        const int32_t *cell = c->mixed ? c->pf[s][c->cur[s]].cell : c->pd[s][c->cur[s]].cell;
+        HIPCHK(c, hipMemsetAsync(c->ctl + 6, 0, 8, c->stream));
+        launch_count_live(cell, c->ctl + s, reinterpret_cast<unsigned long long *>(c->ctl + 6), c->stream);
+        int64_t nl = 0;
+        HIPCHK(c, hipMemcpyAsync(&nl, c->ctl + 6, 8, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        o->live[s] = nl;
+        o->candidates[s] = (int64_t)st[ST_CAND0 + s];
+        o->absorbed[s] = (int64_t)st[ST_ABS0 + s];
+        o->over_numax[s] = (int64_t)st[ST_OVER0 + s];
+        o->numax[s] = c->numax[s];
+        o->pnull[s] = c->pnull[s];
+    }
+    o->events[0][0] = (int64_t)st[ST_EV00];
+    o->events[0][1] = (int64_t)st[ST_EV01];
+    o->events[0][2] = (int64_t)st[ST_EV02];
+    o->events[1][0] = (int64_t)st[ST_EV10];
+    o->events[1][1] = (int64_t)st[ST_EV11];
+    o->births = (int64_t)st[ST_BIRTHS];
+    o->window_out = (int64_t)st[ST_WINOUT];
+    HarmState h;
+    HIPCHK(c, cpy(c->stream, &h, c->harm, sizeof h, hipMemcpyDeviceToHost));
+    o->samples = h.samples;
+    o->nrf = c->nrf;
+    o->phase_closed = c->closed ? 1 : 0;
+    o->pind_sum = h.pind + h.pind_c;
+    double qk[MAX_TURNS];
+    HIPCHK(c, cpy(c->stream, qk, c->Qk, sizeof qk, hipMemcpyDeviceToHost));
+    for (int k = 0; k < MAX_TURNS; ++k) {
+        o->qc[k] = h.qc[k] + h.qc_c[k];
+        o->qs[k] = h.qs[k] + h.qs_c[k];
+        o->wk[k] = h.w[k] + h.w_c[k];
+        o->qk[k] = qk[k];
+    }
+    return PIC_OK;
+}
+
+extern "C" void pic_destroy(pic_ctx *c)
+{
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    for (auto *t : {&c->t_pass, &c->t_poisson, &c->t_sort})
+        for (auto &e : t->ev)
+            for (auto &x : e)
+                if (x) (void)hipEventDestroy(x);
+    if (c->mg_host) (void)hipHostFree(c->mg_host);
+    delete c;
+}
+
+extern "C" const char *pic_last_error(const pic_ctx *c) { return c ? c->err.c_str() : "null context"; }

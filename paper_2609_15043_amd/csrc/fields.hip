@@ -1,0 +1,554 @@
+// Grid kernels of the RZ PIC/MCC step: field staging for the gather, node
+// charge / current from the fixed-point accumulators, the per-step period
+// accumulation, the FP64 geometric multigrid for the finite-volume RZ
+// Poisson problem, and the turn charges from the operator's face fluxes.
+#include "kernels.h"
+#include "launch.h"
+
+namespace pic {
+
+// ---------------------------------------------------------------------------
+// Staging: E_r, E_z = -grad phi (central inside, one-sided at the box edges,
+// E_r = 0 on the axis) and E_theta(t_n) = E_c cos th - E_s^sto sin th, packed
+// per node for the gather; the step's deposit accumulators are cleared.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_stage(const double *phi, const double *ec, const double *es, double cs, double sn,
+                        typename Field4<T>::type *ef, long long *accJ, long long *accQ, int clear_q, GridC g)
+{
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= g.nodes) return;
+    const int i = n / g.nr1, j = n - i * g.nr1;
+    double ez, er;
+    if (i == 0)
+        ez = -(phi[n + g.nr1] - phi[n]) / g.dz;
+    else if (i == g.nz)
+        ez = -(phi[n] - phi[n - g.nr1]) / g.dz;
+    else
+        ez = -(phi[n + g.nr1] - phi[n - g.nr1]) / (2.0 * g.dz);
+    if (j == 0)
+        er = 0.0;
+    else if (j == g.nr)
+        er = -(phi[n] - phi[n - 1]) / g.dr;
+    else
+        er = -(phi[n + 1] - phi[n - 1]) / (2.0 * g.dr);
+    const double et = ec[n] * cs - es[n] * sn;
+    typename Field4<T>::type f;
+    f.x = (T)er;
+    f.y = (T)ez;
+    f.z = (T)et;
+    f.w = (T)0;
+    ef[n] = f;
+    accJ[n] = 0;
+    accJ[g.nodes + n] = 0;
+    if (clear_q) {
+        accQ[n] = 0;
+        accQ[g.nodes + n] = 0;
+    }
+}
+
+// node charge = sum_s q_s w_s (accQ_s / 2^kQ + accS_s)
+__global__ void k_finalize_q(const long long *accQ, const double *accS, double cq0, double cq1, double cs0,
+                             double cs1, double *Q, int nodes)
+{
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= nodes) return;
+    Q[n] = (cq0 * (double)accQ[n] + cq1 * (double)accQ[nodes + n]) + (cs0 * accS[n] + cs1 * accS[nodes + n]);
+}
+
+__device__ __forceinline__ void neumaier(double &sum, double &comp, double x)
+{
+    const double t = sum + x;
+    if (fabs(sum) >= fabs(x))
+        comp += (sum - t) + x;
+    else
+        comp += (x - t) + sum;
+    sum = t;
+}
+
+// ---------------------------------------------------------------------------
+// Per-step period accumulation (compensated FP64).  The last block to
+// finish reduces the inductive-power partials in block order and updates
+// the turn sums, so the result does not depend on block scheduling.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_harmonic(const long long *accJ, double cj0, double cj1, const double *ec,
+                                                  const double *es, double cs, double sn, double *I, double *Jc,
+                                                  double *Jcc, double *Js, double *Jsc, double *partial,
+                                                  HarmState *h, const double *Qk, const double *vc,
+                                                  const double *vs, int nturns, int nodes)
+{
+    __shared__ double red[256];
+    __shared__ bool last;
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    double pw = 0.0;
+    if (n < nodes) {
+        const double cur = cj0 * (double)accJ[n] + cj1 * (double)accJ[nodes + n];
+        I[n] = cur;
+        const double et = ec[n] * cs - es[n] * sn;
+        pw = cur * et;
+        double a = Jc[n], ac = Jcc[n];
+        neumaier(a, ac, cur * cs);
+        Jc[n] = a;
+        Jcc[n] = ac;
+        double b = Js[n], bc = Jsc[n];
+        neumaier(b, bc, cur * sn);
+        Js[n] = b;
+        Jsc[n] = bc;
+    }
+    red[threadIdx.x] = pw;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[blockIdx.x] = red[0];
+        __threadfence();
+        const unsigned t = atomicAdd(&h->ticket, 1u);
+        last = t == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    {
+        double acc = 0.0;
+        for (unsigned b = threadIdx.x; b < gridDim.x; b += 256) acc += partial[b];
+        red[threadIdx.x] = acc;
+    }
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    neumaier(h->pind, h->pind_c, red[0]);
+    for (int k = 0; k < nturns; ++k) {
+        const double V = vc[k] * cs + vs[k] * sn;
+        const double q = Qk[k];
+        neumaier(h->qc[k], h->qc_c[k], q * cs);
+        neumaier(h->qs[k], h->qs_c[k], q * sn);
+        if (h->samples == 0) {
+            h->v_first[k] = V;
+            h->q_first[k] = q;
+        } else {
+            neumaier(h->w[k], h->w_c[k], 0.5 * (V + h->v_prev[k]) * (q - h->q_prev[k]));
+        }
+        h->v_prev[k] = V;
+        h->q_prev[k] = q;
+    }
+    h->samples += 1;
+    h->ticket = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Multigrid on a vertex-centred hierarchy (factor-2 coarsening), used as
+// the preconditioner of a conjugate-gradient solve.  Level 0 smooths with
+// red-black Gauss-Seidel (5-point), the Galerkin levels with four-colour
+// Gauss-Seidel (9-point); restriction is P^T, prolongation bilinear P,
+// both skipping Dirichlet nodes; the coarse operators are P^T A P.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double apply_op(const MGLevel &L, const double *x, int n, int i, int j)
+{
+    if (!L.nine) {
+        double a = L.cc[n] * x[n];
+        if (j > 0) a -= L.cw[n] * x[n - 1];
+        if (j < L.nr) a -= L.ce[n] * x[n + 1];
+        if (i > 0) a -= L.cs[n] * x[n - L.nr1];
+        if (i < L.nz) a -= L.cn[n] * x[n + L.nr1];
+        return a;
+    }
+    double a = 0.0;
+#pragma unroll
+    for (int di = -1; di <= 1; ++di) {
+        if (i + di < 0 || i + di > L.nz) continue;
+#pragma unroll
+        for (int dj = -1; dj <= 1; ++dj) {
+            if (j + dj < 0 || j + dj > L.nr) continue;
+            a += L.a[(size_t)((di + 1) * 3 + dj + 1) * L.nodes + n] * x[n + di * L.nr1 + dj];
+        }
+    }
+    return a;
+}
+
+__device__ __forceinline__ double resid(const MGLevel &L, int n, int i, int j)
+{
+    if (L.dir[n]) return 0.0;
+    return L.rhs[n] - apply_op(L, L.phi, n, i, j);
+}
+
+__device__ __forceinline__ int colour_of(const MGLevel &L, int i, int j)
+{
+    return L.nine ? ((i & 1) << 1) | (j & 1) : ((i + j) & 1);
+}
+
+__device__ __forceinline__ void op_smooth(const MGLevel &L, int color, int t0, int st)
+{
+    for (int n = t0; n < L.nodes; n += st) {
+        const int i = n / L.nr1, j = n - i * L.nr1;
+        if (colour_of(L, i, j) != color || L.dir[n]) continue;
+        double diag;
+        if (!L.nine) {
+            diag = L.cc[n];
+        } else {
+            diag = L.a[(size_t)4 * L.nodes + n];
+        }
+        // x_n <- x_n + (rhs - A x)_n / diag
+        L.phi[n] += (L.rhs[n] - apply_op(L, L.phi, n, i, j)) / diag;
+    }
+}
+
+__device__ __forceinline__ void op_restrict(const MGLevel &F, const MGLevel &C, int t0, int st)
+{
+    for (int n = t0; n < C.nodes; n += st) {
+        const int I = n / C.nr1, J = n - I * C.nr1;
+        C.phi[n] = 0.0;
+        if (C.dir[n]) {
+            C.rhs[n] = 0.0;
+            continue;
+        }
+        double s = 0.0;
+        for (int di = -1; di <= 1; ++di) {
+            const int i = 2 * I + di;
+            if (i < 0 || i > F.nz) continue;
+            const double wi = di == 0 ? 1.0 : 0.5;
+            for (int dj = -1; dj <= 1; ++dj) {
+                const int j = 2 * J + dj;
+                if (j < 0 || j > F.nr) continue;
+                const double wj = dj == 0 ? 1.0 : 0.5;
+                s += wi * wj * resid(F, i * F.nr1 + j, i, j);
+            }
+        }
+        C.rhs[n] = s;
+    }
+}
+
+__device__ __forceinline__ void op_prolong(const MGLevel &F, const MGLevel &C, int t0, int st)
+{
+    for (int n = t0; n < F.nodes; n += st) {
+        if (F.dir[n]) continue;
+        const int i = n / F.nr1, j = n - i * F.nr1;
+        const int I = i >> 1, J = j >> 1;
+        const int c = I * C.nr1 + J;
+        double v;
+        if (!(i & 1) && !(j & 1))
+            v = C.phi[c];
+        else if (!(i & 1))
+            v = 0.5 * (C.phi[c] + C.phi[c + 1]);
+        else if (!(j & 1))
+            v = 0.5 * (C.phi[c] + C.phi[c + C.nr1]);
+        else
+            v = 0.25 * (C.phi[c] + C.phi[c + 1] + C.phi[c + C.nr1] + C.phi[c + C.nr1 + 1]);
+        F.phi[n] += v;
+    }
+}
+
+__global__ void k_mg_smooth(MGLevel L, int color, const MGState *st)
+{
+    if (st->done) return;
+    op_smooth(L, color, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+}
+
+__global__ void k_mg_restrict(MGLevel F, MGLevel C, const MGState *st)
+{
+    if (st->done) return;
+    op_restrict(F, C, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+}
+
+__global__ void k_mg_prolong(MGLevel F, MGLevel C, const MGState *st)
+{
+    if (st->done) return;
+    op_prolong(F, C, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+}
+
+// Levels lb .. nl-1 as one V-cycle in a single workgroup.
+__global__ __launch_bounds__(1024) void k_mg_bottom(MGLevels lv, int lb, int nu1, int nu2, int nbottom,
+                                                    const MGState *st)
+{
+    if (st->done) return;
+    const int t = threadIdx.x, S = blockDim.x;
+    const int nl = lv.n;
+    for (int l = lb; l < nl - 1; ++l) {
+        const int nc = lv.L[l].nine ? 4 : 2;
+        for (int k = 0; k < nu1; ++k)
+            for (int c = 0; c < nc; ++c) {
+                op_smooth(lv.L[l], c, t, S);
+                __syncthreads();
+            }
+        op_restrict(lv.L[l], lv.L[l + 1], t, S);
+        __syncthreads();
+    }
+    {
+        // exact solve on the coarsest level: phi = A^-1 rhs (dense, precomputed)
+        const MGLevel &L = lv.L[nl - 1];
+        for (int r = t; r < L.nodes; r += S) {
+            double acc = 0.0;
+            for (int k = 0; k < L.nodes; ++k) acc += lv.coarse_inv[(size_t)r * L.nodes + k] * L.rhs[k];
+            L.phi[r] = acc;
+        }
+        __syncthreads();
+    }
+    for (int l = nl - 2; l >= lb; --l) {
+        op_prolong(lv.L[l], lv.L[l + 1], t, S);
+        __syncthreads();
+        const int nc = lv.L[l].nine ? 4 : 2;
+        for (int k = 0; k < nu2; ++k)
+            for (int c = nc - 1; c >= 0; --c) {
+                op_smooth(lv.L[l], c, t, S);
+                __syncthreads();
+            }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Conjugate gradient on the free nodes of level 0, preconditioned by one
+// V-cycle.  Scalars (r.z, alpha, beta, norms) stay on the device; every
+// kernel returns at once after convergence, so the host can enqueue a
+// fixed budget of iterations without synchronising.  Reductions go through
+// per-block partials summed in block order by the last block.
+// ---------------------------------------------------------------------------
+template <int NV>
+__device__ __forceinline__ bool block_reduce_last(double (&v)[NV], double *partial, MGState *st, bool is_max)
+{
+    __shared__ double red[NV][256];
+    __shared__ bool last;
+    auto op = [is_max](double x, double y) { return is_max ? fmax(x, y) : x + y; };
+    for (int q = 0; q < NV; ++q) red[q][threadIdx.x] = v[q];
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off)
+            for (int q = 0; q < NV; ++q) red[q][threadIdx.x] = op(red[q][threadIdx.x], red[q][threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        for (int q = 0; q < NV; ++q) partial[NV * blockIdx.x + q] = red[q][0];
+        __threadfence();
+        last = atomicAdd(&st->ticket, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!last) return false;
+    __threadfence();
+    // the last block: strided sums of the partials, then a fixed tree
+    for (int q = 0; q < NV; ++q) {
+        double acc = 0.0;
+        for (unsigned b = threadIdx.x; b < gridDim.x; b += 256) acc = op(acc, partial[NV * b + q]);
+        red[q][threadIdx.x] = acc;
+    }
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off)
+            for (int q = 0; q < NV; ++q) red[q][threadIdx.x] = op(red[q][threadIdx.x], red[q][threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return false;
+    for (int q = 0; q < NV; ++q) v[q] = red[q][0];
+    st->ticket = 0;
+    return true;
+}
+
+// Dirichlet values (turn k nodes: phi_k(t_n)); free nodes start from the
+// linear extrapolation 2 phi^n - phi^{n-1} when `extrap` (prev keeps phi^n);
+// state reset.
+__global__ void k_pcg_begin(MGLevel L, PCGVec v, const int32_t *tag, const double *vc, const double *vs, double cs,
+                            double sn, MGState *st, double *prev, int extrap)
+{
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n == 0) {
+        st->done = 0;
+        st->cycles = 0;
+        st->ticket = 0;
+        st->rz = 0.0;
+        st->beta = 0.0;
+    }
+    if (n >= L.nodes) return;
+    const int k = tag[n];
+    if (k >= 1) {
+        v.x[n] = vc[k - 1] * cs + vs[k - 1] * sn;
+    } else if (k < 0) {
+        const double cur = v.x[n];
+        if (extrap) v.x[n] = 2.0 * cur - prev[n];
+        prev[n] = cur;
+    }
+}
+
+// r = b - A x on free nodes (0 on Dirichlet), z = 0, norms
+__global__ __launch_bounds__(256) void k_pcg_resid(MGLevel L, PCGVec v, MGState *st, double *partial, double rtol)
+{
+    double m[2] = {0.0, 0.0};
+    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < L.nodes; n += gridDim.x * blockDim.x) {
+        v.z[n] = 0.0;
+        v.p[n] = 0.0;
+        if (L.dir[n]) {
+            v.r[n] = 0.0;
+            continue;
+        }
+        const int i = n / L.nr1, j = n - i * L.nr1;
+        const double r = v.b[n] - apply_op(L, v.x, n, i, j);
+        v.r[n] = r;
+        m[0] = fmax(m[0], fabs(r));
+        m[1] = fmax(m[1], fmax(fabs(v.b[n]), fabs(L.cc[n] * v.x[n])));
+    }
+    if (block_reduce_last<2>(m, partial, st, true)) {
+        st->scale = m[1] > 0.0 ? m[1] : 1.0;
+        st->rel = m[0] / st->scale;
+        if (m[0] == 0.0 || st->rel <= rtol) st->done = 1;
+    }
+}
+
+// rz_new = r.z ; beta = rz_new / rz_old (0 on the first iteration)
+__global__ __launch_bounds__(256) void k_pcg_rz(MGLevel L, PCGVec v, MGState *st, double *partial)
+{
+    if (st->done) return;
+    double s[1] = {0.0};
+    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < L.nodes; n += gridDim.x * blockDim.x)
+        s[0] += v.r[n] * v.z[n];
+    if (block_reduce_last<1>(s, partial, st, false)) {
+        st->beta = st->cycles == 0 || st->rz == 0.0 ? 0.0 : s[0] / st->rz;
+        st->rz = s[0];
+    }
+}
+
+// p = z + beta p
+__global__ void k_pcg_p(MGLevel L, PCGVec v, const MGState *st)
+{
+    if (st->done) return;
+    const double beta = st->beta;
+    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < L.nodes; n += gridDim.x * blockDim.x)
+        v.p[n] = v.z[n] + beta * v.p[n];
+}
+
+// Ap = A p on free nodes; alpha = rz / (p.Ap)
+__global__ __launch_bounds__(256) void k_pcg_matvec(MGLevel L, PCGVec v, MGState *st, double *partial)
+{
+    if (st->done) return;
+    double s[1] = {0.0};
+    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < L.nodes; n += gridDim.x * blockDim.x) {
+        double ap = 0.0;
+        if (!L.dir[n]) {
+            const int i = n / L.nr1, j = n - i * L.nr1;
+            ap = apply_op(L, v.p, n, i, j);
+        }
+        v.Ap[n] = ap;
+        s[0] += v.p[n] * ap;
+    }
+    if (block_reduce_last<1>(s, partial, st, false)) st->alpha = s[0] != 0.0 ? st->rz / s[0] : 0.0;
+}
+
+// x += alpha p, r -= alpha Ap, z = 0; convergence check
+__global__ __launch_bounds__(256) void k_pcg_update(MGLevel L, PCGVec v, MGState *st, double *partial, double rtol)
+{
+    if (st->done) return;
+    const double alpha = st->alpha;
+    double m[1] = {0.0};
+    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < L.nodes; n += gridDim.x * blockDim.x) {
+        v.z[n] = 0.0;
+        if (L.dir[n]) continue;
+        v.x[n] += alpha * v.p[n];
+        const double r = v.r[n] - alpha * v.Ap[n];
+        v.r[n] = r;
+        m[0] = fmax(m[0], fabs(r));
+    }
+    if (block_reduce_last<1>(m, partial, st, true)) {
+        st->cycles += 1;
+        st->rel = m[0] / st->scale;
+        if (m[0] == 0.0 || st->rel <= rtol) st->done = 1;
+    }
+}
+
+// Q_k = sum over faces (turn-k node p, outside node q) of c (phi_p - phi_q)
+__global__ void k_face_charge(const double *phi, const int32_t *fp, const int32_t *fq, const int32_t *fk,
+                              const double *fc, int nfaces, double *Qk, int nturns)
+{
+    if (threadIdx.x != 0) return;
+    for (int k = 0; k < nturns; ++k) Qk[k] = 0.0;
+    for (int f = 0; f < nfaces; ++f) Qk[fk[f]] += fc[f] * (phi[fp[f]] - phi[fq[f]]);
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+template <typename T>
+void launch_stage(const double *phi, const double *ec, const double *es, double cs, double sn,
+                  typename Field4<T>::type *ef, long long *accJ, long long *accQ, bool clear_q, const GridC &g,
+                  hipStream_t st)
+{
+    hipLaunchKernelGGL(k_stage<T>, dim3(nblk(g.nodes, 256)), dim3(256), 0, st, phi, ec, es, cs, sn, ef, accJ, accQ,
+                       clear_q ? 1 : 0, g);
+}
+template void launch_stage<float>(const double *, const double *, const double *, double, double, float4 *,
+                                  long long *, long long *, bool, const GridC &, hipStream_t);
+template void launch_stage<double>(const double *, const double *, const double *, double, double, double4 *,
+                                   long long *, long long *, bool, const GridC &, hipStream_t);
+
+void launch_finalize_q(const long long *accQ, const double *accS, double cq0, double cq1, double cs0, double cs1,
+                       double *Q, int nodes, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_finalize_q, dim3(nblk(nodes, 256)), dim3(256), 0, st, accQ, accS, cq0, cq1, cs0, cs1, Q,
+                       nodes);
+}
+
+void launch_harmonic(const long long *accJ, double cj0, double cj1, const double *ec, const double *es, double cs,
+                     double sn, double *I, double *Jc, double *Jcc, double *Js, double *Jsc, double *partial,
+                     HarmState *h, const double *Qk, const double *vc, const double *vs, int nturns, int nodes,
+                     hipStream_t st)
+{
+    hipLaunchKernelGGL(k_harmonic, dim3(nblk(nodes, 256)), dim3(256), 0, st, accJ, cj0, cj1, ec, es, cs, sn, I, Jc,
+                       Jcc, Js, Jsc, partial, h, Qk, vc, vs, nturns, nodes);
+}
+
+int harmonic_blocks(int nodes) { return (int)nblk(nodes, 256); }
+
+static unsigned mg_grid(int work) { return nblk(work, 256) < 2048 ? nblk(work, 256) : 2048; }
+static unsigned red_grid(int work) { return nblk(work, 256) < 1024 ? nblk(work, 256) : 1024; }
+int pcg_partial_size(int nodes) { return 2 * (int)red_grid(nodes); }
+
+void launch_mg_smooth(const MGLevel &L, int color, const MGState *st, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_mg_smooth, dim3(mg_grid(L.nodes)), dim3(256), 0, s, L, color, st);
+}
+void launch_mg_restrict(const MGLevel &F, const MGLevel &C, const MGState *st, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_mg_restrict, dim3(mg_grid(C.nodes)), dim3(256), 0, s, F, C, st);
+}
+void launch_mg_prolong(const MGLevel &F, const MGLevel &C, const MGState *st, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_mg_prolong, dim3(mg_grid(F.nodes)), dim3(256), 0, s, F, C, st);
+}
+void launch_mg_bottom(const MGLevels &lv, int lb, int nu1, int nu2, int nbottom, const MGState *st, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_mg_bottom, dim3(1), dim3(1024), 0, s, lv, lb, nu1, nu2, nbottom, st);
+}
+void launch_pcg_begin(const MGLevel &L, const PCGVec &v, const int32_t *tag, const double *vc, const double *vs,
+                      double cs, double sn, MGState *st, double *prev, bool extrap, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pcg_begin, dim3(nblk(L.nodes, 256)), dim3(256), 0, s, L, v, tag, vc, vs, cs, sn, st, prev,
+                       extrap ? 1 : 0);
+}
+void launch_pcg_resid(const MGLevel &L, const PCGVec &v, MGState *st, double *partial, double rtol, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pcg_resid, dim3(red_grid(L.nodes)), dim3(256), 0, s, L, v, st, partial, rtol);
+}
+void launch_pcg_rz(const MGLevel &L, const PCGVec &v, MGState *st, double *partial, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pcg_rz, dim3(red_grid(L.nodes)), dim3(256), 0, s, L, v, st, partial);
+}
+void launch_pcg_p(const MGLevel &L, const PCGVec &v, const MGState *st, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pcg_p, dim3(mg_grid(L.nodes)), dim3(256), 0, s, L, v, st);
+}
+void launch_pcg_matvec(const MGLevel &L, const PCGVec &v, MGState *st, double *partial, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pcg_matvec, dim3(red_grid(L.nodes)), dim3(256), 0, s, L, v, st, partial);
+}
+void launch_pcg_update(const MGLevel &L, const PCGVec &v, MGState *st, double *partial, double rtol, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pcg_update, dim3(red_grid(L.nodes)), dim3(256), 0, s, L, v, st, partial, rtol);
+}
+void launch_face_charge(const double *phi, const int32_t *fp, const int32_t *fq, const int32_t *fk, const double *fc,
+                        int nfaces, double *Qk, int nturns, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_face_charge, dim3(1), dim3(64), 0, s, phi, fp, fq, fk, fc, nfaces, Qk, nturns);
+}
+
+}  // namespace pic

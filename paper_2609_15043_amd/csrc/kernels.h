@@ -1,0 +1,151 @@
+// Kernel argument blocks and launch entry points shared between the
+// kernel translation units and the host library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device.h"
+
+namespace pic {
+
+// LDS deposit window (nodes) of one particle block: whole node rows around
+// the block's middle particle, so particles that drifted a few cells since
+// the last sort still land in LDS.  FP32 window values: 4096 nodes; FP64: 2048.
+template <typename T> struct Win {
+    static constexpr int N = sizeof(T) == 4 ? 4096 : 2048;
+};
+constexpr int BLOCK = 256;
+constexpr int PPT = 16;                 // particles per thread per pass block
+constexpr int CHUNK = BLOCK * PPT;      // particles per pass block
+
+// Counter slots (int64) in the device statistics block.
+enum StatSlot {
+    ST_CAND0 = 0, ST_CAND1,
+    ST_EV00, ST_EV01, ST_EV02,          // electron elastic, excitation, ionization
+    ST_EV10, ST_EV11, ST_EV12,          // ion elastic, charge exchange, (unused)
+    ST_BIRTHS,
+    ST_ABS0, ST_ABS1,
+    ST_OVER0, ST_OVER1,
+    ST_WINOUT,
+    ST_NSTAT
+};
+
+// Device flags (int32) of the error word.
+enum ErrFlag { ERR_BIRTH_OVERFLOW = 1, ERR_CAPACITY = 2, ERR_MG_NOTCONV = 4, ERR_QUEUE_OVERFLOW = 8 };
+
+struct GridC {
+    int nr, nz, nr1, nodes, ncells, ip, window;
+    double dr, dz;
+    float inv_nr;      // 1 / nr, for the cell -> (i, j) split
+};
+
+// cell -> (i, j) with i = floor(cell / nr): (cell + 1/2) / nr is at least
+// 1/(2 nr) from an integer and the FP32 product errs by < nz 2^-23, so the
+// truncation is exact while nz nr < 2^22 (checked on the host).
+__device__ __forceinline__ void split_cell(const GridC &g, int cell, int &i, int &j)
+{
+    i = (int)(((float)cell + 0.5f) * g.inv_nr);
+    j = cell - i * g.nr;
+}
+
+struct SpeciesC {
+    int s;
+    double h;          // (q/m) dt / 2
+    double dtr, dtz;   // dt / dR, dt / dz
+    int has_b;
+    double bt[3], bs[3];  // Boris t and s vectors
+    double jscale;     // fixed-point scale of vbar W / vref
+    double qscale;     // fixed-point scale of W
+    double vref;
+    double inv_vref;
+};
+
+struct MccC {
+    uint32_t seed;
+    int xs_kind;
+    double numax[2];
+    double lq[2];      // log(1 - P_null) = -nu_max dt
+    double ngas, qe, me, mi, vg;
+    double xs[13];
+};
+
+// Birth records (structure of arrays), one per ionization event.
+template <typename T> struct Births {
+    uint32_t *parent;
+    int32_t *cell;
+    T *dr, *dz;
+    T *ve;             // 3 per record
+    T *vi;             // 3 per record
+    int32_t *next;     // 2 per record (electron, ion)
+    int32_t *count;    // device counter
+    int32_t cap;
+};
+
+// Queue of this step's null-collision candidates of one species (indices
+// into its particle arrays), filled by the streaming pass.
+struct CandQueue {
+    int32_t *idx;
+    int32_t *count;
+    int32_t cap;
+};
+
+template <typename T> struct PassArgs {
+    Parts<T> p;
+    CandQueue q;
+    const int64_t *count;              // slots in use of this species
+    const typename Field4<T>::type *ef;
+    long long *accJ;                   // this species' current accumulator
+    long long *accQ;                   // this species' charge accumulator
+    double *accS;                      // this species' window charge (weights, FP64)
+    unsigned long long *stats;
+    int32_t *err;
+    GridC g;
+    SpeciesC sc;
+    MccC mc;
+    Births<T> b;
+    int32_t step;
+};
+
+// One multigrid level (device arrays).  Level 0 is the 5-point finite-
+// volume operator (A x)_p = cc x_p - cw x_W - ce x_E - cs x_S - cn x_N; the
+// coarser levels are Galerkin products P^T A P with 9-point stencils
+// (A x)_p = sum_k a[k][p] x_{p + off(k)}, k = 3 (di + 1) + (dj + 1).
+struct MGLevel {
+    int nr, nz, nr1, nodes;
+    int nine;
+    double *phi, *rhs;       // correction and its right-hand side
+    const double *cw, *ce, *cs, *cn, *cc;
+    const double *a;         // 9 * nodes (nine == 1)
+    const uint8_t *dir;      // 1: Dirichlet (correction fixed at 0)
+};
+
+constexpr int MAX_LEVELS = 14;
+struct MGLevels {
+    int n;
+    MGLevel L[MAX_LEVELS];
+    const double *coarse_inv;   // dense inverse of the coarsest operator (free rows / columns)
+};
+
+// Device-resident state of one preconditioned-CG solve.
+struct MGState {
+    int32_t done;
+    int32_t cycles;          // CG iterations (one V-cycle each)
+    uint32_t ticket;
+    int32_t pad;
+    double rel;              // max |r| / scale
+    double scale;            // max(|b|, |diag x|) at the start of the solve
+    double rz, alpha, beta;
+};
+
+constexpr int MAX_TURNS = 16;
+// Open-period accumulators (compensated sums: value + correction).
+struct HarmState {
+    uint32_t ticket;
+    int32_t samples;
+    double pind, pind_c;
+    double qc[MAX_TURNS], qc_c[MAX_TURNS], qs[MAX_TURNS], qs_c[MAX_TURNS];
+    double w[MAX_TURNS], w_c[MAX_TURNS];
+    double v_first[MAX_TURNS], q_first[MAX_TURNS], v_prev[MAX_TURNS], q_prev[MAX_TURNS];
+};
+
+}  // namespace pic

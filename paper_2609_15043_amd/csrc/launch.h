@@ -1,0 +1,63 @@
+// Host-side launchers of the kernels (implemented next to the kernels).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.h"
+
+namespace pic {
+
+template <typename T>
+void launch_load(const Parts<T> &p, int64_t n, uint32_t seed, int s, double rmax, double zp, double vth, double lq,
+                 const GridC &g, hipStream_t st);
+template <typename T>
+void launch_place(const Parts<T> &p, int64_t n, const double *R, const double *z, const double *vr,
+                  const double *vt, const double *vz, const uint32_t *id, const int32_t *next, const GridC &g,
+                  hipStream_t st);
+template <typename T>
+void launch_unplace(const Parts<T> &p, const int64_t *count, int64_t cap, const int64_t *index, double *R, double *z,
+                    double *vr, double *vt, double *vz, uint32_t *id, int32_t *next, const GridC &g, hipStream_t st);
+void launch_count_live(const int32_t *cell, const int64_t *count, unsigned long long *out, hipStream_t st);
+void launch_live_index(const int32_t *cell, const int64_t *count, int64_t *index, int64_t *nlive, hipStream_t st);
+template <typename T>
+void launch_pass(const PassArgs<T> &a, int64_t cap, bool push, bool depq, hipStream_t st);
+template <typename T> void launch_collide(const PassArgs<T> &a, hipStream_t st);
+template <typename T>
+void launch_births(const Births<T> &b, const Parts<T> &pe, const Parts<T> &pi, int64_t *count, int64_t *next_id,
+                   int64_t cap_e, int64_t cap_i, long long *accQe, long long *accQi, bool deposit, double qscale,
+                   const GridC &g, int32_t *err, unsigned long long *stats, hipStream_t st);
+template <typename T>
+void launch_sort(const Parts<T> &src, const Parts<T> &dst, int64_t *count, int64_t *count_old, int32_t *hist,
+                 int32_t *cursor, int ncells, int64_t cap, hipStream_t st);
+
+template <typename T>
+void launch_stage(const double *phi, const double *ec, const double *es, double cs, double sn,
+                  typename Field4<T>::type *ef, long long *accJ, long long *accQ, bool clear_q, const GridC &g,
+                  hipStream_t st);
+void launch_finalize_q(const long long *accQ, const double *accS, double cq0, double cq1, double cs0, double cs1,
+                       double *Q, int nodes, hipStream_t st);
+void launch_harmonic(const long long *accJ, double cj0, double cj1, const double *ec, const double *es, double cs,
+                     double sn, double *I, double *Jc, double *Jcc, double *Js, double *Jsc, double *partial,
+                     HarmState *h, const double *Qk, const double *vc, const double *vs, int nturns, int nodes,
+                     hipStream_t st);
+int harmonic_blocks(int nodes);
+
+struct PCGVec {
+    double *x, *b, *r, *z, *p, *Ap;
+};
+int pcg_partial_size(int nodes);
+void launch_mg_smooth(const MGLevel &L, int color, const MGState *st, hipStream_t s);
+void launch_mg_restrict(const MGLevel &F, const MGLevel &C, const MGState *st, hipStream_t s);
+void launch_mg_prolong(const MGLevel &F, const MGLevel &C, const MGState *st, hipStream_t s);
+void launch_mg_bottom(const MGLevels &lv, int lb, int nu1, int nu2, int nbottom, const MGState *st, hipStream_t s);
+void launch_pcg_begin(const MGLevel &L, const PCGVec &v, const int32_t *tag, const double *vc, const double *vs,
+                      double cs, double sn, MGState *st, double *prev, bool extrap, hipStream_t s);
+void launch_pcg_resid(const MGLevel &L, const PCGVec &v, MGState *st, double *partial, double rtol, hipStream_t s);
+void launch_pcg_rz(const MGLevel &L, const PCGVec &v, MGState *st, double *partial, hipStream_t s);
+void launch_pcg_p(const MGLevel &L, const PCGVec &v, const MGState *st, hipStream_t s);
+void launch_pcg_matvec(const MGLevel &L, const PCGVec &v, MGState *st, double *partial, hipStream_t s);
+void launch_pcg_update(const MGLevel &L, const PCGVec &v, MGState *st, double *partial, double rtol, hipStream_t s);
+void launch_face_charge(const double *phi, const int32_t *fp, const int32_t *fq, const int32_t *fk, const double *fc,
+                        int nfaces, double *Qk, int nturns, hipStream_t s);
+
+}  // namespace pic

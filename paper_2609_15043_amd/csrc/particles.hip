@@ -1,0 +1,934 @@
+// Particle kernels of the RZ PIC/MCC step: loading, the gather / Boris push
+// / move / current deposit pass (optionally fused with the collisions and
+// the charge deposit), ionization births, and the counting sort by cell.
+//
+// Data layout: structure of arrays per species (cell index, in-cell offsets,
+// velocity, id, next collision-candidate step), kept sorted by cell every
+// few steps so that the 64 lanes of a wave stream contiguous memory and
+// mostly share one cell.  Deposits are reduced across the wave (segmented
+// by cell), accumulated in an LDS window of node values per block, and
+// flushed with one 64-bit fixed-point atomic per touched node.
+#include "kernels.h"
+#include "launch.h"
+
+namespace pic {
+
+constexpr double PI = 3.141592653589793238462643;
+
+// ---------------------------------------------------------------------------
+// Small FP64 helpers of the collision model
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double above_threshold(double eps, double th)
+{
+    if (eps <= th) return 0.0;
+    const double x = eps / th;
+    return 4.0 * (x - 1.0) / (x * x);
+}
+
+// e-Ar: elastic, excitation, ionization cross sections at energy eps (eV)
+__device__ __forceinline__ void sigma_electron(const MccC &m, double eps, double &sel, double &sex, double &siz)
+{
+    if (m.xs_kind == 1) {
+        sel = m.xs[0];
+        sex = eps > m.xs[3] ? m.xs[2] : 0.0;
+        siz = eps > m.xs[5] ? m.xs[4] : 0.0;
+        return;
+    }
+    sel = m.xs[0] / sqrt(1.0 + eps / m.xs[1]);
+    sex = m.xs[2] * above_threshold(eps, m.xs[3]);
+    siz = m.xs[4] * above_threshold(eps, m.xs[5]);
+}
+
+// Ar+-Ar: elastic and charge exchange at centre-of-mass energy (eV)
+__device__ __forceinline__ void sigma_ion(const MccC &m, double ecm, double &sel, double &scx)
+{
+    if (m.xs_kind == 1) {
+        sel = m.xs[6];
+        scx = m.xs[8];
+        return;
+    }
+    sel = m.xs[6] * pow(1.0 + ecm, -m.xs[7]);
+    scx = m.xs[8] * pow(1.0 + ecm, -m.xs[9]);
+}
+
+// step of the next candidate after a draw at `step`: step + G,
+// G = 1 + floor(log u / log(1 - P)), clamped to int32
+__device__ __forceinline__ int32_t next_candidate(int64_t step, uint32_t x, double lq)
+{
+    double g = floor(log(unit(x)) / lq);
+    g = fmin(g, 2.0e9);
+    const int64_t s = step + 1 + (int64_t)g;
+    return s > 2147483647ll ? 2147483647 : (int32_t)s;
+}
+
+__device__ __forceinline__ void isotropic(uint32_t a, uint32_t b, double d[3])
+{
+    const double ct = 1.0 - 2.0 * unit(a);
+    const double st = sqrt(fmax(0.0, 1.0 - ct * ct));
+    double sp, cp;
+    sincos(2.0 * PI * unit(b), &sp, &cp);
+    d[0] = st * cp;
+    d[1] = st * sp;
+    d[2] = ct;
+}
+
+__device__ __forceinline__ void normal_pair(uint32_t a, uint32_t b, double &g0, double &g1)
+{
+    const double r = sqrt(-2.0 * log(unit(a)));
+    double s, c;
+    sincos(2.0 * PI * unit(b), &s, &c);
+    g0 = r * c;
+    g1 = r * s;
+}
+
+// (R, z) in metres -> (cell, offsets); R and z are inside the box
+template <typename T>
+__device__ __forceinline__ void place(const GridC &g, double R, double z, int32_t &cell, T &dr, T &dz)
+{
+    const double x = R / g.dr, y = z / g.dz;
+    int j = (int)floor(x), i = (int)floor(y);
+    j = min(max(j, 0), g.nr - 1);
+    i = min(max(i, 0), g.nz - 1);
+    double a = x - j, b = y - i;
+    T ta = (T)a, tb = (T)b;
+    if (ta >= (T)1) ta = (T)0.9999999;
+    if (tb >= (T)1) tb = (T)0.9999999;
+    cell = i * g.nr + j;
+    dr = ta;
+    dz = tb;
+}
+
+// ---------------------------------------------------------------------------
+// Loading: uniform in volume (R = Rmax sqrt(u)), Maxwellian velocities,
+// Philox blocks (id, 0, 0, 0) and (id, 0, 1, 0) keyed by (seed, species).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_load(Parts<T> p, int64_t n, uint32_t seed, int s, double rmax, double zp, double vth,
+                       double lq, GridC g)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const U4 a = philox10(U4{(uint32_t)k, 0u, 0u, 0u}, seed, (uint32_t)s);
+    const U4 b = philox10(U4{(uint32_t)k, 0u, 1u, 0u}, seed, (uint32_t)s);
+    const double R = rmax * sqrt(unit(a.x));
+    const double z = zp * unit(a.y);
+    double g0, g1, g2, g3;
+    normal_pair(a.z, a.w, g0, g1);
+    normal_pair(b.x, b.y, g2, g3);
+    int32_t cell;
+    T dr, dz;
+    place<T>(g, R, z, cell, dr, dz);
+    p.cell[k] = cell;
+    p.dr[k] = dr;
+    p.dz[k] = dz;
+    p.vr[k] = (T)(vth * g0);
+    p.vt[k] = (T)(vth * g1);
+    p.vz[k] = (T)(vth * g2);
+    p.id[k] = (uint32_t)k;
+    p.next[k] = next_candidate(-1, b.z, lq);   // first candidate: G - 1
+}
+
+// Host-given particles (R, z in metres) -> store
+template <typename T>
+__global__ void k_place(Parts<T> p, int64_t n, const double *R, const double *z, const double *vr,
+                        const double *vt, const double *vz, const uint32_t *id, const int32_t *next, GridC g)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    int32_t cell;
+    T dr, dz;
+    place<T>(g, R[k], z[k], cell, dr, dz);
+    p.cell[k] = cell;
+    p.dr[k] = dr;
+    p.dz[k] = dz;
+    p.vr[k] = (T)vr[k];
+    p.vt[k] = (T)vt[k];
+    p.vz[k] = (T)vz[k];
+    p.id[k] = id[k];
+    p.next[k] = next[k];
+}
+
+// store -> host representation (only live particles, order of the store)
+template <typename T>
+__global__ void k_unplace(Parts<T> p, const int64_t *count, const int64_t *live_index, double *R, double *z,
+                          double *vr, double *vt, double *vz, uint32_t *id, int32_t *next, GridC g)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= *count) return;
+    const int32_t c = p.cell[k];
+    if (c < 0) return;
+    const int64_t o = live_index[k];
+    const int i = c / g.nr, j = c - i * g.nr;
+    R[o] = ((double)j + (double)p.dr[k]) * g.dr;
+    z[o] = ((double)i + (double)p.dz[k]) * g.dz;
+    vr[o] = (double)p.vr[k];
+    vt[o] = (double)p.vt[k];
+    vz[o] = (double)p.vz[k];
+    id[o] = p.id[k];
+    next[o] = p.next[k];
+}
+
+// ---------------------------------------------------------------------------
+// Wave-collective deposit of four node values around lower-left node `key`.
+// Lanes are grouped by key (segmented by ballot); each group's sums (wave
+// scan, total in lane 63) are added to the block's LDS window in the
+// working precision, or, for a node outside the window, straight to the
+// global 64-bit fixed-point accumulator.  The window is converted to fixed
+// point once per touched node when the block flushes it, so the global
+// sums are exact and independent of block order.  Called by all 64 lanes.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void deposit4(bool valid, int key, T v0, T v1, T v2, T v3, T *win, int base,
+                                         long long *acc, int nr1, double scale, unsigned long long *sstat)
+{
+    uint64_t todo = ballot(valid);
+    const int lane = lane_id();
+    while (todo) {
+        const int lead = __ffsll((unsigned long long)todo) - 1;
+        const int k = __builtin_amdgcn_readlane(key, lead);
+        const bool m = valid && key == k;
+        const uint64_t mm = ballot(m);
+        const T s0 = wave_total(m ? v0 : (T)0);
+        const T s1 = wave_total(m ? v1 : (T)0);
+        const T s2 = wave_total(m ? v2 : (T)0);
+        const T s3 = wave_total(m ? v3 : (T)0);
+        if (lane == 63) {
+            const int nodes[4] = {k, k + 1, k + nr1, k + nr1 + 1};
+            const T sums[4] = {s0, s1, s2, s3};
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                if (sums[c] == (T)0) continue;
+                const int o = nodes[c] - base;
+                if (o >= 0 && o < Win<T>::N) {
+                    atomicAdd(&win[o], sums[c]);
+                } else {
+                    atomic_add_i64(&acc[nodes[c]], to_fixed((double)sums[c], scale));
+                    atomicAdd(&sstat[ST_WINOUT], 1ull);
+                }
+            }
+        }
+        todo &= ~mm;
+    }
+}
+
+__device__ __forceinline__ void count_wave(bool c, unsigned long long *sstat, int slot)
+{
+    const uint64_t m = ballot(c);
+    if (m && lane_id() == __ffsll((unsigned long long)m) - 1) atomicAdd(&sstat[slot], (unsigned long long)__popcll(m));
+}
+
+// ---------------------------------------------------------------------------
+// Collision of one candidate (FP64 inside).  Velocity in/out in the local
+// frame at the particle's position.  Returns the process index or -1.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ int collide(const MccC &mc, int s, uint32_t id, int32_t step, T &vr, T &vt, T &vz, int32_t &next,
+                       bool &over, bool &born, double ve[3], double vi[3], int32_t nb[2])
+{
+    const U4 b0 = philox10(U4{id, (uint32_t)step, 1u, 0u}, mc.seed, (uint32_t)s);
+    next = next_candidate(step, b0.x, mc.lq[s]);
+    double v[3] = {(double)vr, (double)vt, (double)vz};
+    int ev = -1;
+    if (s == 0) {
+        const double v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+        const double speed = sqrt(v2);
+        const double eps = 0.5 * mc.me * v2 / mc.qe;
+        double sel, sex, siz;
+        sigma_electron(mc, eps, sel, sex, siz);
+        const double nel = mc.ngas * sel * speed, nex = mc.ngas * sex * speed, niz = mc.ngas * siz * speed;
+        over = nel + nex + niz > mc.numax[0];
+        const double Rv = unit(b0.y) * mc.numax[0];
+        double d[3];
+        isotropic(b0.z, b0.w, d);
+        double e1 = -1.0;
+        if (Rv < nel) {
+            const double cchi = speed > 0.0 ? (v[0] * d[0] + v[1] * d[1] + v[2] * d[2]) / speed : 1.0;
+            e1 = eps * (1.0 - 2.0 * mc.me / mc.mi * (1.0 - cchi));
+            ev = 0;
+        } else if (Rv < nel + nex) {
+            e1 = eps - mc.xs[3];
+            ev = 1;
+        } else if (Rv < nel + nex + niz) {
+            const U4 b2 = philox10(U4{id, (uint32_t)step, 2u, 0u}, mc.seed, 0u);
+            const U4 b3 = philox10(U4{id, (uint32_t)step, 3u, 0u}, mc.seed, 0u);
+            const double erem = eps - mc.xs[5];
+            const double esec = unit(b2.x) * erem;
+            e1 = erem - esec;
+            double d2[3];
+            isotropic(b2.y, b2.z, d2);
+            const double s2 = sqrt(2.0 * esec * mc.qe / mc.me);
+            double g0, g1, g2, g3;
+            normal_pair(b3.x, b3.y, g0, g1);
+            normal_pair(b3.z, b3.w, g2, g3);
+            ve[0] = s2 * d2[0];
+            ve[1] = s2 * d2[1];
+            ve[2] = s2 * d2[2];
+            vi[0] = mc.vg * g0;
+            vi[1] = mc.vg * g1;
+            vi[2] = mc.vg * g2;
+            nb[0] = next_candidate(step, b2.w, mc.lq[0]);
+            nb[1] = next_candidate(step, b3.w, mc.lq[1]);
+            born = true;
+            ev = 2;
+        }
+        if (ev >= 0) {
+            const double s1 = sqrt(2.0 * e1 * mc.qe / mc.me);
+            vr = (T)(s1 * d[0]);
+            vt = (T)(s1 * d[1]);
+            vz = (T)(s1 * d[2]);
+        }
+    } else {
+        const U4 b2 = philox10(U4{id, (uint32_t)step, 2u, 0u}, mc.seed, 1u);
+        double g0, g1, g2, g3;
+        normal_pair(b2.x, b2.y, g0, g1);
+        normal_pair(b2.z, b2.w, g2, g3);
+        const double vn[3] = {mc.vg * g0, mc.vg * g1, mc.vg * g2};
+        const double gv[3] = {v[0] - vn[0], v[1] - vn[1], v[2] - vn[2]};
+        const double gm = sqrt(gv[0] * gv[0] + gv[1] * gv[1] + gv[2] * gv[2]);
+        const double ecm = 0.25 * mc.mi * gm * gm / mc.qe;
+        double sel, scx;
+        sigma_ion(mc, ecm, sel, scx);
+        const double nel = mc.ngas * sel * gm, ncx = mc.ngas * scx * gm;
+        over = nel + ncx > mc.numax[1];
+        const double Rv = unit(b0.y) * mc.numax[1];
+        if (Rv < nel) {
+            double d[3];
+            isotropic(b0.z, b0.w, d);
+            vr = (T)(0.5 * (v[0] + vn[0]) + 0.5 * gm * d[0]);
+            vt = (T)(0.5 * (v[1] + vn[1]) + 0.5 * gm * d[1]);
+            vz = (T)(0.5 * (v[2] + vn[2]) + 0.5 * gm * d[2]);
+            ev = 0;
+        } else if (Rv < nel + ncx) {
+            vr = (T)vn[0];
+            vt = (T)vn[1];
+            vz = (T)vn[2];
+            ev = 1;
+        }
+    }
+    return ev;
+}
+
+// ---------------------------------------------------------------------------
+// The particle pass.  PUSH: gather + Boris + move + J deposit + absorption,
+// and the step's collision candidates (next == step) go to a queue; DEPQ:
+// charge deposit at the (new) positions.  Fused: both in one streaming
+// pass.  The collisions themselves run in k_collide over the queue, so the
+// rarely taken FP64 collision code does not weigh on this kernel's
+// registers.
+// ---------------------------------------------------------------------------
+template <typename T, bool PUSH, bool DEPQ>
+__global__ __launch_bounds__(BLOCK) void k_pass(PassArgs<T> a)
+{
+    using F4 = typename Field4<T>::type;
+    constexpr int WIN = Win<T>::N;
+    __shared__ T winJ[PUSH ? WIN : 1];
+    __shared__ T winQ[DEPQ ? WIN : 1];
+    __shared__ unsigned long long sstat[ST_NSTAT];
+    __shared__ int s_base;
+    constexpr int CAND_LDS = PUSH ? 512 : 1;
+    __shared__ int32_t s_cand[CAND_LDS];
+    __shared__ int s_ncand, s_qbase;
+
+    const int tid = threadIdx.x;
+    const int64_t n = *a.count;
+    const int64_t c0 = (int64_t)blockIdx.x * CHUNK;
+    if (c0 >= n) return;
+    const int64_t c1 = min(c0 + (int64_t)CHUNK, n);
+    const GridC g = a.g;
+    const int s = a.sc.s;
+    if (tid == 0) s_ncand = 0;
+
+    if (tid == 0) {
+        int cell = -1;
+        const int64_t mid = (c0 + c1) / 2;
+        for (int t = 0; t < 64 && cell < 0; ++t) {
+            const int64_t q = mid + t < c1 ? mid + t : c0 + t;
+            if (q < c1) cell = a.p.cell[q];
+        }
+        int base = 0;
+        if (cell >= 0) {
+            int i, j;
+            split_cell(g, cell, i, j);
+            const int rows = WIN / g.nr1;   // node rows the window holds
+            if (rows >= 3) {
+                base = (i - (rows - 1) / 2) * g.nr1;
+            } else {
+                base = i * g.nr1 + j + g.nr1 / 2 + 1 - WIN / 2;
+            }
+        }
+        base = min(base, g.nodes - WIN);
+        s_base = max(base, 0);
+    }
+    for (int k = tid; k < WIN; k += BLOCK) {
+        if (PUSH) winJ[k] = (T)0;
+        if (DEPQ) winQ[k] = (T)0;
+    }
+    if (tid < ST_NSTAT) sstat[tid] = 0;
+    __syncthreads();
+    const int base = s_base;
+
+    for (int64_t p0 = c0; p0 < c1; p0 += BLOCK) {
+        const int64_t p = p0 + tid;
+        const bool act = p < c1;
+        int32_t cell = act ? a.p.cell[p] : -1;
+        const bool live0 = cell >= 0;
+        int i = 0, j = 0;
+        T dr = 0, dz = 0, vr = 0, vt = 0, vz = 0;
+        int32_t next = -1;
+        if (live0) {
+            split_cell(g, cell, i, j);
+            dr = a.p.dr[p];
+            dz = a.p.dz[p];
+            if (PUSH) {
+                vr = a.p.vr[p];
+                vt = a.p.vt[p];
+                vz = a.p.vz[p];
+                next = a.p.next[p];
+            }
+        }
+        bool live = live0;
+        if constexpr (PUSH) {
+            int absorbed = 0;
+            T w00 = 0, w01 = 0, w10 = 0, w11 = 0, jv = 0;
+            int key = 0;
+            if (live0) {
+                const T fj = (T)j;
+                const T wr1 = quot(dr * ((T)2 * fj + dr), (T)2 * fj + (T)1);
+                const T wz1 = dz;
+                w00 = ((T)1 - wz1) * ((T)1 - wr1);
+                w01 = ((T)1 - wz1) * wr1;
+                w10 = wz1 * ((T)1 - wr1);
+                w11 = wz1 * wr1;
+                key = i * g.nr1 + j;
+                const F4 f00 = a.ef[key], f01 = a.ef[key + 1], f10 = a.ef[key + g.nr1], f11 = a.ef[key + g.nr1 + 1];
+                const T er = w00 * f00.x + w01 * f01.x + w10 * f10.x + w11 * f11.x;
+                const T ez = w00 * f00.y + w01 * f01.y + w10 * f10.y + w11 * f11.y;
+                const T et = w00 * f00.z + w01 * f01.z + w10 * f10.z + w11 * f11.z;
+                const T h = (T)a.sc.h;
+                T ur = vr + h * er, ut = vt + h * et, uz = vz + h * ez;
+                if (a.sc.has_b) {
+                    const T t0 = (T)a.sc.bt[0], t1 = (T)a.sc.bt[1], t2 = (T)a.sc.bt[2];
+                    const T s0 = (T)a.sc.bs[0], s1 = (T)a.sc.bs[1], s2 = (T)a.sc.bs[2];
+                    const T pr = ur + (ut * t2 - uz * t1), pt = ut + (uz * t0 - ur * t2), pz = uz + (ur * t1 - ut * t0);
+                    ur += pt * s2 - pz * s1;
+                    ut += pz * s0 - pr * s2;
+                    uz += pr * s1 - pt * s0;
+                }
+                ur += h * er;
+                ut += h * et;
+                uz += h * ez;
+                jv = (T)0.5 * (vt + ut) * (T)a.sc.inv_vref;
+                // Cartesian move in the particle's plane, in cell units
+                const T ar = dr + ur * (T)a.sc.dtr;
+                const T X = fj + ar;
+                const T Y = ut * (T)a.sc.dtr;
+                const T hyp = sqrt(X * X + Y * Y);
+                const T rel = X > (T)0 ? ar + quot(Y * Y, X + hyp) : hyp - fj;   // R' - j
+                T c = (T)1, sn = (T)0;
+                if (hyp > (T)0) {
+                    c = quot(X, hyp);
+                    sn = quot(Y, hyp);
+                }
+                const T vrn = c * ur + sn * ut;
+                const T vtn = -sn * ur + c * ut;
+                const T fr = floor(rel);
+                int jn = j + (int)fr;
+                T drn = rel - fr;
+                if (drn >= (T)1) {
+                    drn -= (T)1;
+                    jn += 1;
+                }
+                const T bz = dz + uz * (T)a.sc.dtz;
+                const T fz = floor(bz);
+                int in = i + (int)fz;
+                T dzn = bz - fz;
+                if (dzn >= (T)1) {
+                    dzn -= (T)1;
+                    in += 1;
+                }
+                if (!(hyp == hyp) || !(bz == bz) || in < 0) {
+                    absorbed = 1;   // below the bottom wall (or a non-finite state)
+                } else if (in >= g.ip) {
+                    absorbed = 1;
+                    if (g.window && uz > (T)0) {
+                        // crossing of z = zp within the step (FP64)
+                        const double frac = ((double)g.ip - ((double)i + (double)dz)) / ((double)uz * a.sc.dtz);
+                        const double xs = (double)j + (double)dr + (double)ur * a.sc.dtr * frac;
+                        const double ys = (double)ut * a.sc.dtr * frac;
+                        const double Rs = sqrt(xs * xs + ys * ys);
+                        if (Rs < (double)g.nr) {
+                            int js = (int)floor(Rs);
+                            js = min(js, g.nr - 1);
+                            const double w1 = (Rs * Rs - (double)js * js) / (2.0 * js + 1.0);
+                            const int nd = g.ip * g.nr1 + js;
+                            atomicAdd(&a.accS[nd], 1.0 - w1);
+                            atomicAdd(&a.accS[nd + 1], w1);
+                            absorbed = 2;
+                        }
+                    }
+                } else if (jn >= g.nr || jn < 0) {
+                    absorbed = 1;
+                }
+                live = absorbed == 0;
+                cell = live ? in * g.nr + jn : -1;
+                dr = drn;
+                dz = dzn;
+                vr = vrn;
+                vt = vtn;
+                vz = uz;
+            }
+            deposit4<T>(live0, key, jv * w00, jv * w01, jv * w10, jv * w11, winJ, base, a.accJ, g.nr1,
+                        a.sc.jscale, sstat);
+            count_wave(absorbed != 0, sstat, ST_ABS0 + s);
+            // this step's collision candidates -> block-local list (LDS), one
+            // global reservation per block at the end; a full list spills
+            // straight to the queue
+            const bool cand = live && next == a.step;
+            const uint64_t cm = ballot(cand);
+            if (cm) {
+                const int lead = __ffsll((unsigned long long)cm) - 1;
+                int slot0 = 0;
+                if (lane_id() == lead) slot0 = atomicAdd(&s_ncand, __popcll(cm));
+                slot0 = __builtin_amdgcn_readlane(slot0, lead);
+                if (cand) {
+                    const int slot = slot0 + __builtin_amdgcn_mbcnt_hi((uint32_t)(cm >> 32),
+                                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)cm, 0u));
+                    if (slot < CAND_LDS) {
+                        s_cand[slot] = (int32_t)p;
+                    } else {
+                        const int gs = atomicAdd(a.q.count, 1);
+                        if (gs < a.q.cap)
+                            a.q.idx[gs] = (int32_t)p;
+                        else
+                            atomicOr(a.err, (int)ERR_QUEUE_OVERFLOW);
+                    }
+                }
+            }
+        }
+        if constexpr (DEPQ) {
+            T w00 = 0, w01 = 0, w10 = 0, w11 = 0;
+            int key = 0;
+            if (live) {
+                int ii, jj;
+                split_cell(g, cell, ii, jj);
+                const T fj = (T)jj;
+                const T wr1 = quot(dr * ((T)2 * fj + dr), (T)2 * fj + (T)1);
+                w00 = ((T)1 - dz) * ((T)1 - wr1);
+                w01 = ((T)1 - dz) * wr1;
+                w10 = dz * ((T)1 - wr1);
+                w11 = dz * wr1;
+                key = ii * g.nr1 + jj;
+            }
+            deposit4<T>(live, key, w00, w01, w10, w11, winQ, base, a.accQ, g.nr1, a.sc.qscale, sstat);
+        }
+        if constexpr (PUSH) {
+            if (live0) {
+                a.p.cell[p] = cell;
+                if (live) {
+                    a.p.dr[p] = dr;
+                    a.p.dz[p] = dz;
+                    a.p.vr[p] = vr;
+                    a.p.vt[p] = vt;
+                    a.p.vz[p] = vz;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if constexpr (PUSH) {
+        const int nc = min(s_ncand, CAND_LDS);
+        if (tid == 0) s_qbase = nc ? atomicAdd(a.q.count, nc) : 0;
+        __syncthreads();
+        for (int k = tid; k < nc; k += BLOCK) {
+            const int gs = s_qbase + k;
+            if (gs < a.q.cap)
+                a.q.idx[gs] = s_cand[k];
+            else
+                atomicOr(a.err, (int)ERR_QUEUE_OVERFLOW);
+        }
+    }
+    for (int k = tid; k < WIN; k += BLOCK) {
+        if (PUSH) {
+            const T v = winJ[k];
+            if (v != (T)0) atomic_add_i64(&a.accJ[base + k], to_fixed((double)v, a.sc.jscale));
+        }
+        if (DEPQ) {
+            const T v = winQ[k];
+            if (v != (T)0) atomic_add_i64(&a.accQ[base + k], to_fixed((double)v, a.sc.qscale));
+        }
+    }
+    if (tid < ST_NSTAT && sstat[tid]) atomicAdd(&a.stats[tid], sstat[tid]);
+}
+
+// ---------------------------------------------------------------------------
+// Collisions of the queued candidates of step `step` (velocity at x^{n+1}
+// after the push); births recorded for the ionizations.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_collide(PassArgs<T> a)
+{
+    __shared__ unsigned long long sstat[ST_NSTAT];
+    const int s = a.sc.s;
+    const int nq = min(*a.q.count, a.q.cap);
+    if ((int64_t)blockIdx.x * blockDim.x >= nq) return;
+    if (threadIdx.x < ST_NSTAT) sstat[threadIdx.x] = 0;
+    __syncthreads();
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool act = t < nq;
+    int64_t p = act ? a.q.idx[t] : 0;
+    bool over = false, born = false;
+    int ev = -1;
+    double ve[3], vi[3];
+    int32_t nb[2];
+    T vr = 0, vt = 0, vz = 0;
+    int32_t next = 0;
+    if (act) {
+        vr = a.p.vr[p];
+        vt = a.p.vt[p];
+        vz = a.p.vz[p];
+        ev = collide<T>(a.mc, s, a.p.id[p], a.step, vr, vt, vz, next, over, born, ve, vi, nb);
+        a.p.vr[p] = vr;
+        a.p.vt[p] = vt;
+        a.p.vz[p] = vz;
+        a.p.next[p] = next;
+    }
+    count_wave(act, sstat, ST_CAND0 + s);
+    count_wave(ev == 0, sstat, (s == 0 ? ST_EV00 : ST_EV10));
+    count_wave(ev == 1, sstat, (s == 0 ? ST_EV01 : ST_EV11));
+    count_wave(ev == 2, sstat, ST_EV02);
+    count_wave(over, sstat, ST_OVER0 + s);
+    const uint64_t bm = ballot(born);
+    if (bm) {
+        const int lead = __ffsll((unsigned long long)bm) - 1;
+        int slot0 = 0;
+        if (lane_id() == lead) slot0 = atomicAdd(a.b.count, __popcll(bm));
+        slot0 = __builtin_amdgcn_readlane(slot0, lead);
+        if (born) {
+            const int slot = slot0 + __builtin_amdgcn_mbcnt_hi((uint32_t)(bm >> 32),
+                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)bm, 0u));
+            if (slot < a.b.cap) {
+                a.b.parent[slot] = a.p.id[p];
+                a.b.cell[slot] = a.p.cell[p];
+                a.b.dr[slot] = a.p.dr[p];
+                a.b.dz[slot] = a.p.dz[p];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    a.b.ve[3 * slot + c] = (T)ve[c];
+                    a.b.vi[3 * slot + c] = (T)vi[c];
+                }
+                a.b.next[2 * slot] = nb[0];
+                a.b.next[2 * slot + 1] = nb[1];
+            } else {
+                atomicOr(a.err, (int)ERR_BIRTH_OVERFLOW);
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < ST_NSTAT && sstat[threadIdx.x]) atomicAdd(&a.stats[threadIdx.x], sstat[threadIdx.x]);
+}
+
+__global__ void k_reset_count(int32_t *c) { *c = 0; }
+
+// ---------------------------------------------------------------------------
+// Births: rank by parent id (ids then follow parent-id order, as in a
+// sequential sort), append to both species, deposit their charge.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_births(Births<T> b, Parts<T> pe, Parts<T> pi, const int64_t *count,
+                                                const int64_t *next_id, int64_t cap_e, int64_t cap_i,
+                                                long long *accQe, long long *accQi, int deposit, double qscale,
+                                                GridC g, int32_t *err)
+{
+    __shared__ uint32_t keys[1024];
+    const int B = min(*b.count, b.cap);
+    if ((int64_t)blockIdx.x * blockDim.x >= B) return;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t mine = t < B ? b.parent[t] : 0xFFFFFFFFu;
+    int rank = 0;
+    for (int t0 = 0; t0 < B; t0 += 1024) {
+        __syncthreads();
+        for (int k = threadIdx.x; k < 1024; k += blockDim.x) keys[k] = t0 + k < B ? b.parent[t0 + k] : 0xFFFFFFFFu;
+        __syncthreads();
+        const int lim = min(1024, B - t0);
+        for (int k = 0; k < lim; ++k) rank += keys[k] < mine;
+    }
+    if (t >= B) return;
+    const int64_t ne = count[0], ni = count[1];
+    if (ne + B > cap_e || ni + B > cap_i) {
+        atomicOr(err, (int)ERR_CAPACITY);
+        return;
+    }
+    const int64_t oe = ne + rank, oi = ni + rank;
+    const int32_t c = b.cell[t];
+    const T dr = b.dr[t], dz = b.dz[t];
+    pe.cell[oe] = c;
+    pe.dr[oe] = dr;
+    pe.dz[oe] = dz;
+    pe.vr[oe] = b.ve[3 * t];
+    pe.vt[oe] = b.ve[3 * t + 1];
+    pe.vz[oe] = b.ve[3 * t + 2];
+    pe.id[oe] = (uint32_t)(next_id[0] + rank);
+    pe.next[oe] = b.next[2 * t];
+    pi.cell[oi] = c;
+    pi.dr[oi] = dr;
+    pi.dz[oi] = dz;
+    pi.vr[oi] = b.vi[3 * t];
+    pi.vt[oi] = b.vi[3 * t + 1];
+    pi.vz[oi] = b.vi[3 * t + 2];
+    pi.id[oi] = (uint32_t)(next_id[1] + rank);
+    pi.next[oi] = b.next[2 * t + 1];
+    if (deposit) {
+        const int ii = c / g.nr, jj = c - ii * g.nr;
+        const T fj = (T)jj;
+        const T wr1 = dr * ((T)2 * fj + dr) / ((T)2 * fj + (T)1);
+        const T w[4] = {((T)1 - dz) * ((T)1 - wr1), ((T)1 - dz) * wr1, dz * ((T)1 - wr1), dz * wr1};
+        const int k0 = ii * g.nr1 + jj;
+        const int nd[4] = {k0, k0 + 1, k0 + g.nr1, k0 + g.nr1 + 1};
+        for (int q = 0; q < 4; ++q) {
+            const long long f = to_fixed((double)w[q], qscale);
+            atomic_add_i64(&accQe[nd[q]], f);
+            atomic_add_i64(&accQi[nd[q]], f);
+        }
+    }
+}
+
+__global__ void k_births_commit(int32_t *bcount, int32_t cap, int64_t *count, int64_t *next_id,
+                                int64_t cap_e, int64_t cap_i, unsigned long long *stats)
+{
+    const int B = min(*bcount, cap);
+    if (B > 0 && count[0] + B <= cap_e && count[1] + B <= cap_i) {
+        count[0] += B;
+        count[1] += B;
+        next_id[0] += B;
+        next_id[1] += B;
+        stats[ST_BIRTHS] += (unsigned long long)B;
+    }
+    *bcount = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Counting sort by cell (absorbed particles dropped)
+// ---------------------------------------------------------------------------
+__global__ void k_sort_hist(const int32_t *cell, const int64_t *count, int32_t *hist, int ncells)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool act = p < *count;
+    const int32_t c = act ? cell[p] : -1;
+    const bool live = c >= 0 && c < ncells;
+    uint64_t todo = ballot(live);
+    while (todo) {
+        const int lead = __ffsll((unsigned long long)todo) - 1;
+        const int k = __builtin_amdgcn_readlane(c, lead);
+        const uint64_t mm = ballot(live && c == k);
+        if (lane_id() == lead) atomicAdd(&hist[k], (int)__popcll(mm));
+        todo &= ~mm;
+    }
+}
+
+// single block: exclusive scan of hist[0..ncells) into cursor, hist reset,
+// count_old <- count, count <- live total
+__global__ __launch_bounds__(1024) void k_sort_scan(int32_t *hist, int32_t *cursor, int ncells, int64_t *count,
+                                                    int64_t *count_old)
+{
+    __shared__ int64_t part[1024];
+    const int t = threadIdx.x;
+    const int per = (ncells + 1023) / 1024;
+    const int lo = min(t * per, ncells), hi = min(lo + per, ncells);
+    int64_t sum = 0;
+    for (int k = lo; k < hi; ++k) sum += hist[k];
+    part[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int64_t v = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int64_t run = part[t] - sum;
+    for (int k = lo; k < hi; ++k) {
+        const int h = hist[k];
+        cursor[k] = (int32_t)run;
+        run += h;
+        hist[k] = 0;
+    }
+    if (t == 1023) {
+        *count_old = *count;
+        *count = part[1023];
+    }
+}
+
+template <typename T>
+__global__ void k_sort_scatter(Parts<T> src, Parts<T> dst, const int64_t *count_old, int32_t *cursor, int ncells)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool act = p < *count_old;
+    const int32_t c = act ? src.cell[p] : -1;
+    const bool live = c >= 0 && c < ncells;
+    uint64_t todo = ballot(live);
+    int64_t pos = -1;
+    while (todo) {
+        const int lead = __ffsll((unsigned long long)todo) - 1;
+        const int k = __builtin_amdgcn_readlane(c, lead);
+        const uint64_t mm = ballot(live && c == k);
+        int b0 = 0;
+        if (lane_id() == lead) b0 = atomicAdd(&cursor[k], (int)__popcll(mm));
+        b0 = __builtin_amdgcn_readlane(b0, lead);
+        if (live && c == k)
+            pos = b0 + __builtin_amdgcn_mbcnt_hi((uint32_t)(mm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mm, 0u));
+        todo &= ~mm;
+    }
+    if (live) {
+        dst.cell[pos] = c;
+        dst.dr[pos] = src.dr[p];
+        dst.dz[pos] = src.dz[p];
+        dst.vr[pos] = src.vr[p];
+        dst.vt[pos] = src.vt[p];
+        dst.vz[pos] = src.vz[p];
+        dst.id[pos] = src.id[p];
+        dst.next[pos] = src.next[p];
+    }
+}
+
+// live-index prefix for the getters: index[k] = number of live slots < k
+__global__ __launch_bounds__(1024) void k_live_index(const int32_t *cell, const int64_t *count, int64_t *index,
+                                                     int64_t *nlive)
+{
+    __shared__ int64_t part[1024];
+    const int64_t n = *count;
+    const int t = threadIdx.x;
+    const int64_t per = (n + 1023) / 1024;
+    const int64_t lo = min((int64_t)t * per, n), hi = min(lo + per, n);
+    int64_t sum = 0;
+    for (int64_t k = lo; k < hi; ++k) sum += cell[k] >= 0;
+    part[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int64_t v = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int64_t run = part[t] - sum;
+    for (int64_t k = lo; k < hi; ++k) {
+        index[k] = run;
+        run += cell[k] >= 0;
+    }
+    if (t == 1023) *nlive = part[1023];
+}
+
+// number of live slots (cell >= 0) among the first *count
+__global__ __launch_bounds__(256) void k_count_live(const int32_t *cell, const int64_t *count, unsigned long long *out)
+{
+    __shared__ unsigned long long red[256];
+    const int64_t n = *count;
+    unsigned long long c = 0;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+        c += cell[k] >= 0;
+    red[threadIdx.x] = c;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && red[0]) atomicAdd(out, red[0]);
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+void launch_count_live(const int32_t *cell, const int64_t *count, unsigned long long *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_count_live, dim3(1024), dim3(256), 0, st, cell, count, out);
+}
+
+template <typename T>
+void launch_load(const Parts<T> &p, int64_t n, uint32_t seed, int s, double rmax, double zp, double vth, double lq,
+                 const GridC &g, hipStream_t st)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_load<T>, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, n, seed, s, rmax, zp, vth, lq, g);
+}
+
+template <typename T>
+void launch_place(const Parts<T> &p, int64_t n, const double *R, const double *z, const double *vr,
+                  const double *vt, const double *vz, const uint32_t *id, const int32_t *next, const GridC &g,
+                  hipStream_t st)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_place<T>, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, n, R, z, vr, vt, vz, id, next, g);
+}
+
+template <typename T>
+void launch_unplace(const Parts<T> &p, const int64_t *count, int64_t cap, const int64_t *index, double *R, double *z,
+                    double *vr, double *vt, double *vz, uint32_t *id, int32_t *next, const GridC &g, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_unplace<T>, dim3(blocks_for(cap, 256)), dim3(256), 0, st, p, count, index, R, z, vr, vt, vz,
+                       id, next, g);
+}
+
+void launch_live_index(const int32_t *cell, const int64_t *count, int64_t *index, int64_t *nlive, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_live_index, dim3(1), dim3(1024), 0, st, cell, count, index, nlive);
+}
+
+template <typename T>
+void launch_pass(const PassArgs<T> &a, int64_t cap, bool push, bool depq, hipStream_t st)
+{
+    const dim3 grid(blocks_for(cap, CHUNK)), blk(BLOCK);
+    if (push) hipLaunchKernelGGL(k_reset_count, dim3(1), dim3(1), 0, st, a.q.count);
+    if (push && depq)
+        hipLaunchKernelGGL((k_pass<T, true, true>), grid, blk, 0, st, a);
+    else if (push)
+        hipLaunchKernelGGL((k_pass<T, true, false>), grid, blk, 0, st, a);
+    else if (depq)
+        hipLaunchKernelGGL((k_pass<T, false, true>), grid, blk, 0, st, a);
+}
+
+template <typename T> void launch_collide(const PassArgs<T> &a, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_collide<T>, dim3(blocks_for(a.q.cap, 256)), dim3(256), 0, st, a);
+}
+
+template <typename T>
+void launch_births(const Births<T> &b, const Parts<T> &pe, const Parts<T> &pi, int64_t *count, int64_t *next_id,
+                   int64_t cap_e, int64_t cap_i, long long *accQe, long long *accQi, bool deposit, double qscale,
+                   const GridC &g, int32_t *err, unsigned long long *stats, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_births<T>, dim3(blocks_for(b.cap, 256)), dim3(256), 0, st, b, pe, pi, count, next_id, cap_e,
+                       cap_i, accQe, accQi, deposit ? 1 : 0, qscale, g, err);
+    hipLaunchKernelGGL(k_births_commit, dim3(1), dim3(1), 0, st, b.count, b.cap, count, next_id, cap_e, cap_i, stats);
+}
+
+template <typename T>
+void launch_sort(const Parts<T> &src, const Parts<T> &dst, int64_t *count, int64_t *count_old, int32_t *hist,
+                 int32_t *cursor, int ncells, int64_t cap, hipStream_t st)
+{
+    const unsigned nb = blocks_for(cap, 256);
+    hipLaunchKernelGGL(k_sort_hist, dim3(nb), dim3(256), 0, st, src.cell, count, hist, ncells);
+    hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, st, hist, cursor, ncells, count, count_old);
+    hipLaunchKernelGGL(k_sort_scatter<T>, dim3(nb), dim3(256), 0, st, src, dst, count_old, cursor, ncells);
+}
+
+#define PIC_INSTANTIATE(T)                                                                                          \
+    template void launch_load<T>(const Parts<T> &, int64_t, uint32_t, int, double, double, double, double,          \
+                                 const GridC &, hipStream_t);                                                       \
+    template void launch_place<T>(const Parts<T> &, int64_t, const double *, const double *, const double *,        \
+                                  const double *, const double *, const uint32_t *, const int32_t *, const GridC &, \
+                                  hipStream_t);                                                                     \
+    template void launch_unplace<T>(const Parts<T> &, const int64_t *, int64_t, const int64_t *, double *,          \
+                                    double *, double *, double *, double *, uint32_t *, int32_t *, const GridC &,   \
+                                    hipStream_t);                                                                   \
+    template void launch_pass<T>(const PassArgs<T> &, int64_t, bool, bool, hipStream_t);                            \
+    template void launch_collide<T>(const PassArgs<T> &, hipStream_t);                                              \
+    template void launch_births<T>(const Births<T> &, const Parts<T> &, const Parts<T> &, int64_t *, int64_t *,     \
+                                   int64_t, int64_t, long long *, long long *, bool, double, const GridC &,         \
+                                   int32_t *, unsigned long long *, hipStream_t);                                   \
+    template void launch_sort<T>(const Parts<T> &, const Parts<T> &, int64_t *, int64_t *, int32_t *, int32_t *,    \
+                                 int, int64_t, hipStream_t);
+
+PIC_INSTANTIATE(float)
+PIC_INSTANTIATE(double)
+
+}  // namespace pic

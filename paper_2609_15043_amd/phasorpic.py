@@ -1,0 +1,322 @@
+"""ctypes binding of libphasorpic (include/phasorpic.h): argument marshalling
+only.  Every step of the method runs in the library's HIP kernels; this
+module fails loudly when the library is missing.  PyTorch provides the
+device workspace and the stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+from . import workloads as W
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libphasorpic.so")
+
+PIC_OK, PIC_EINVAL, PIC_ENOMEM, PIC_EDEVICE, PIC_ENOTCONV, PIC_EPHASE, PIC_ESTATE = 0, -1, -2, -3, -4, -5, -6
+PIC_FP64, PIC_MIXED = 0, 1
+(PIC_GRID_PHI, PIC_GRID_CHARGE, PIC_GRID_CURRENT, PIC_GRID_ER, PIC_GRID_EZ, PIC_GRID_ETHETA,
+ PIC_GRID_SURFACE, PIC_GRID_JC, PIC_GRID_JS) = range(9)
+
+_D, _I32, _I64, _U32 = ctypes.c_double, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+_PD, _PI32, _PU32 = ctypes.POINTER(_D), ctypes.POINTER(_I32), ctypes.POINTER(_U32)
+
+
+class PicConfig(ctypes.Structure):
+    _fields_ = [
+        ("nr", _I32), ("nz", _I32), ("ip", _I32), ("window", _I32),
+        ("rmax", _D), ("zmax", _D), ("dt", _D), ("freq", _D),
+        ("precision", _I32), ("seed", _U32),
+        ("q", _D * 2), ("m", _D * 2), ("w", _D * 2), ("temp_ev", _D * 2),
+        ("np_init", _I64 * 2), ("capacity", _I64 * 2), ("bfield", _D * 3),
+        ("ngas", _D), ("tgas_ev", _D), ("qe", _D), ("eps0", _D),
+        ("xs_kind", _I32), ("nscan", _I32), ("xs", _D * 13),
+        ("nturns", _I32), ("fuse", _I32),
+        ("eps_cell", _PD), ("node_tag", _PI32), ("ec", _PD), ("es_sto", _PD),
+        ("turn_vc", _PD), ("turn_vs", _PD),
+        ("mg_rtol", _D), ("mg_max_cycles", _I32), ("sort_every", _I32), ("load", _I32),
+        ("birth_capacity", _I32),
+    ]
+
+
+class PicSolveInfo(ctypes.Structure):
+    _fields_ = [("cycles", _I32), ("converged", _I32), ("rel_residual", _D)]
+
+
+class PicStats(ctypes.Structure):
+    _fields_ = [
+        ("slots", _I64 * 2), ("live", _I64 * 2), ("next_id", _I64 * 2), ("candidates", _I64 * 2),
+        ("events", (_I64 * 3) * 2), ("births", _I64), ("absorbed", _I64 * 2), ("over_numax", _I64 * 2),
+        ("window_out", _I64), ("samples", _I64), ("nrf", _I32), ("phase_closed", _I32),
+        ("numax", _D * 2), ("pnull", _D * 2), ("pind_sum", _D),
+        ("qc", _D * 16), ("qs", _D * 16), ("wk", _D * 16), ("qk", _D * 16),
+        ("pass_ms", _D), ("pass_count", _I64), ("poisson_ms", _D), ("poisson_count", _I64),
+        ("sort_ms", _D), ("sort_count", _I64), ("mg_cycles", _I64), ("mg_rel", _D),
+    ]
+
+
+class PicPeriodReport(ctypes.Structure):
+    _fields_ = [("accepted", _I32), ("samples", _I32), ("p_ind", _D), ("p_cap", _D), ("p_cap_ph", _D),
+                ("qc", _D * 16), ("qs", _D * 16), ("icap_re", _D * 16), ("icap_im", _D * 16)]
+
+
+class PicError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"phasorpic status {status}: {msg}")
+        self.status = status
+
+
+_LIB = None
+
+# exported C symbols, in header order
+SYMBOLS = ["pic_workspace_bytes", "pic_init", "pic_gather_push", "mcc_collide", "pic_deposit",
+           "poisson_solve_rz", "harmonic_accumulate", "circuit_period_update", "pic_sync",
+           "pic_clear_error", "pic_get_particles", "pic_set_particles", "pic_set_step", "pic_set_phi",
+           "pic_get_grid", "pic_timing", "pic_get_stats", "pic_destroy", "pic_last_error"]
+
+
+def lib():
+    """Load libphasorpic.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} missing: build it with paper_2609_15043_amd/build.py "
+                               "(or __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.c_void_p
+        L.pic_workspace_bytes.argtypes = [ctypes.POINTER(PicConfig), ctypes.POINTER(ctypes.c_size_t)]
+        L.pic_init.argtypes = [ctypes.POINTER(PicConfig), P, ctypes.c_size_t, P, ctypes.POINTER(P)]
+        for name in ("pic_gather_push", "mcc_collide", "pic_deposit", "harmonic_accumulate", "pic_set_step"):
+            getattr(L, name).argtypes = [P, _I64]
+        L.poisson_solve_rz.argtypes = [P, _I64, _D, _I32, ctypes.POINTER(PicSolveInfo)]
+        L.circuit_period_update.argtypes = [P, _PD, _PD, _PD, _PD, ctypes.POINTER(PicPeriodReport), _PD, _PD]
+        L.pic_sync.argtypes = [P]
+        L.pic_clear_error.argtypes = [P]
+        L.pic_get_particles.argtypes = [P, _I32, _I64, _PD, _PD, _PD, _PD, _PD, _PU32, _PI32,
+                                        ctypes.POINTER(_I64)]
+        L.pic_set_particles.argtypes = [P, _I32, _I64, _PD, _PD, _PD, _PD, _PD, _PU32, _PI32]
+        L.pic_set_phi.argtypes = [P, _PD]
+        L.pic_get_grid.argtypes = [P, _I32, _PD]
+        L.pic_get_stats.argtypes = [P, ctypes.POINTER(PicStats)]
+        L.pic_timing.argtypes = [P, _I32]
+        L.pic_destroy.argtypes = [P]
+        L.pic_destroy.restype = None
+        L.pic_last_error.argtypes = [P]
+        L.pic_last_error.restype = ctypes.c_char_p
+        for name in SYMBOLS:
+            if name not in ("pic_destroy", "pic_last_error"):
+                getattr(L, name).restype = _I32
+        _LIB = L
+    return _LIB
+
+
+def _ptr(a, t):
+    return a.ctypes.data_as(ctypes.POINTER(t)) if a is not None else None
+
+
+# ---------------------------------------------------------------------------
+# Configuration from a workload description
+# ---------------------------------------------------------------------------
+def config_from_workload(wl, precision="mixed", fuse=True, load=True, mg_rtol=None, mg_max_cycles=30,
+                         sort_every=16, birth_capacity=65536, nscan=200_000):
+    """(PicConfig, keep-alive list).  precision: 'fp64' or 'mixed'."""
+    keep = []
+    c = PicConfig()
+    c.nr, c.nz, c.ip, c.window = wl.nr, wl.nz, wl.ip, 1 if wl.window else 0
+    c.rmax, c.zmax, c.dt, c.freq = wl.rmax, wl.zmax, wl.dt, wl.freq
+    c.precision = PIC_MIXED if precision == "mixed" else PIC_FP64
+    c.seed = wl.seed
+    for s in range(2):
+        c.q[s], c.m[s], c.w[s], c.temp_ev[s] = wl.charge[s], wl.mass[s], wl.weight[s], wl.temp_ev[s]
+        c.np_init[s] = wl.np_init[s]
+        c.capacity[s] = wl.capacity[s]
+    for k in range(3):
+        c.bfield[k] = wl.bfield[k]
+    c.ngas, c.tgas_ev, c.qe, c.eps0 = wl.ngas, wl.tgas_ev, W.QE, W.EPS0
+    x = wl.xs
+    c.xs_kind, c.nscan = x.kind, nscan
+    for k, v in enumerate((x.el_a, x.el_b, x.exc_a, x.exc_th, x.iz_a, x.iz_th, x.iel_a, x.iel_p, x.icx_a,
+                           x.icx_p, x.e_cap_ev, x.i_gcap, x.nu_margin)):
+        c.xs[k] = v
+    eps = np.ascontiguousarray(wl.eps_cell, dtype=np.float64)
+    tag = np.ascontiguousarray(wl.node_tag, dtype=np.int32)
+    ec = np.ascontiguousarray(wl.ec, dtype=np.float64)
+    es = np.ascontiguousarray(wl.es_sto, dtype=np.float64)
+    vc = np.ascontiguousarray(wl.turn_vc, dtype=np.float64)
+    vs = np.ascontiguousarray(wl.turn_vs, dtype=np.float64)
+    keep += [eps, tag, ec, es, vc, vs]
+    c.nturns, c.fuse = wl.nturns, 1 if fuse else 0
+    c.eps_cell, c.node_tag, c.ec, c.es_sto = _ptr(eps, _D), _ptr(tag, _I32), _ptr(ec, _D), _ptr(es, _D)
+    c.turn_vc, c.turn_vs = _ptr(vc, _D), _ptr(vs, _D)
+    if mg_rtol is None:
+        mg_rtol = 1e-13 if precision == "fp64" else 1e-9
+    c.mg_rtol, c.mg_max_cycles, c.sort_every, c.load = mg_rtol, mg_max_cycles, sort_every, 1 if load else 0
+    c.birth_capacity = birth_capacity
+    return c, keep
+
+
+# ---------------------------------------------------------------------------
+# The entry points, same names as the C ABI
+# ---------------------------------------------------------------------------
+class Context:
+    """A pic_ctx together with the torch workspace it lives in."""
+
+    def __init__(self, handle, workspace, keep, cfg):
+        self.handle = handle
+        self.workspace = workspace
+        self.keep = keep
+        self.cfg = cfg
+        self.nodes = (cfg.nz + 1) * (cfg.nr + 1)
+        self.shape = (cfg.nz + 1, cfg.nr + 1)
+
+    def check(self, st):
+        if st != PIC_OK:
+            raise PicError(st, lib().pic_last_error(self.handle).decode())
+        return st
+
+    def __del__(self):
+        try:
+            if self.handle:
+                lib().pic_destroy(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+
+
+def pic_workspace_bytes(cfg):
+    n = ctypes.c_size_t()
+    st = lib().pic_workspace_bytes(ctypes.byref(cfg), ctypes.byref(n))
+    if st:
+        raise PicError(st, "pic_workspace_bytes")
+    return n.value
+
+
+def pic_init(cfg, keep=(), device="cuda", stream=None):
+    import torch
+    nbytes = pic_workspace_bytes(cfg)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    if stream is None:
+        stream = torch.cuda.current_stream(ws.device).cuda_stream
+    h = ctypes.c_void_p()
+    st = lib().pic_init(ctypes.byref(cfg), ctypes.c_void_p(ws.data_ptr()), nbytes, ctypes.c_void_p(stream),
+                        ctypes.byref(h))
+    if st:
+        raise PicError(st, "pic_init failed (see configuration)")
+    return Context(h, ws, list(keep), cfg)
+
+
+def pic_gather_push(ctx, n):
+    return ctx.check(lib().pic_gather_push(ctx.handle, n))
+
+
+def mcc_collide(ctx, n):
+    return ctx.check(lib().mcc_collide(ctx.handle, n))
+
+
+def pic_deposit(ctx, n1):
+    return ctx.check(lib().pic_deposit(ctx.handle, n1))
+
+
+def poisson_solve_rz(ctx, n, rtol=0.0, max_cycles=0, info=False):
+    if not info:
+        return ctx.check(lib().poisson_solve_rz(ctx.handle, n, rtol, max_cycles, None))
+    inf = PicSolveInfo()
+    st = lib().poisson_solve_rz(ctx.handle, n, rtol, max_cycles, ctypes.byref(inf))
+    if st not in (PIC_OK, PIC_ENOTCONV):
+        ctx.check(st)
+    return dict(status=st, cycles=inf.cycles, converged=inf.converged, rel_residual=inf.rel_residual)
+
+
+def harmonic_accumulate(ctx, n):
+    return ctx.check(lib().harmonic_accumulate(ctx.handle, n))
+
+
+def circuit_period_update(ctx, new_vc=None, new_vs=None, new_ec=None, new_es_sto=None, want_j=False):
+    """Returns (status, report dict, jc, js)."""
+    rep = PicPeriodReport()
+    arrs = [None if a is None else np.ascontiguousarray(a, dtype=np.float64) for a in
+            (new_vc, new_vs, new_ec, new_es_sto)]
+    jc = np.zeros(ctx.shape) if want_j else None
+    js = np.zeros(ctx.shape) if want_j else None
+    st = lib().circuit_period_update(ctx.handle, *[_ptr(a, _D) for a in arrs], ctypes.byref(rep), _ptr(jc, _D),
+                                     _ptr(js, _D))
+    K = ctx.cfg.nturns
+    out = dict(accepted=rep.accepted, samples=rep.samples, p_ind=rep.p_ind, p_cap=rep.p_cap, p_cap_ph=rep.p_cap_ph,
+               qc=np.array(rep.qc[:K]), qs=np.array(rep.qs[:K]),
+               icap=np.array(rep.icap_re[:K]) + 1j * np.array(rep.icap_im[:K]))
+    return st, out, jc, js
+
+
+def pic_sync(ctx):
+    return ctx.check(lib().pic_sync(ctx.handle))
+
+
+def pic_clear_error(ctx):
+    return ctx.check(lib().pic_clear_error(ctx.handle))
+
+
+def pic_set_step(ctx, n):
+    return ctx.check(lib().pic_set_step(ctx.handle, n))
+
+
+def pic_set_phi(ctx, phi):
+    a = np.ascontiguousarray(phi, dtype=np.float64).reshape(-1)
+    assert a.size == ctx.nodes
+    return ctx.check(lib().pic_set_phi(ctx.handle, _ptr(a, _D)))
+
+
+def pic_get_grid(ctx, which):
+    out = np.zeros(ctx.nodes)
+    ctx.check(lib().pic_get_grid(ctx.handle, which, _ptr(out, _D)))
+    return out.reshape(ctx.shape)
+
+
+def pic_timing(ctx, enable=True):
+    return ctx.check(lib().pic_timing(ctx.handle, 1 if enable else 0))
+
+
+def pic_get_stats(ctx):
+    s = PicStats()
+    ctx.check(lib().pic_get_stats(ctx.handle, ctypes.byref(s)))
+    return s
+
+
+def pic_get_particles(ctx, s):
+    """Dict of live particles (R, z, vr, vt, vz, id, next), sorted by id."""
+    st = pic_get_stats(ctx)
+    cap = int(st.slots[s])
+    R, z, vr, vt, vz = (np.zeros(cap) for _ in range(5))
+    ids = np.zeros(cap, np.uint32)
+    nxt = np.zeros(cap, np.int32)
+    cnt = _I64()
+    ctx.check(lib().pic_get_particles(ctx.handle, s, cap, _ptr(R, _D), _ptr(z, _D), _ptr(vr, _D), _ptr(vt, _D),
+                                      _ptr(vz, _D), _ptr(ids, _U32), _ptr(nxt, _I32), ctypes.byref(cnt)))
+    n = cnt.value
+    o = np.argsort(ids[:n], kind="stable")
+    return dict(id=ids[:n][o], R=R[:n][o], z=z[:n][o], vr=vr[:n][o], vt=vt[:n][o], vz=vz[:n][o], next=nxt[:n][o])
+
+
+def pic_set_particles(ctx, s, d):
+    n = len(d["R"])
+    a = {k: np.ascontiguousarray(d[k], dtype=np.float64) for k in ("R", "z", "vr", "vt", "vz")}
+    ids = np.ascontiguousarray(d["id"], dtype=np.uint32)
+    nxt = np.ascontiguousarray(d["next"], dtype=np.int32)
+    return ctx.check(lib().pic_set_particles(ctx.handle, s, n, _ptr(a["R"], _D), _ptr(a["z"], _D),
+                                             _ptr(a["vr"], _D), _ptr(a["vt"], _D), _ptr(a["vz"], _D),
+                                             _ptr(ids, _U32), _ptr(nxt, _I32)))
+
+
+def step(ctx, n):
+    """One whole PIC step n in the library's order (without the period update)."""
+    pic_gather_push(ctx, n)
+    harmonic_accumulate(ctx, n)
+    mcc_collide(ctx, n)
+    pic_deposit(ctx, n + 1)
+    poisson_solve_rz(ctx, n + 1)
+
+
+def nrf(wl):
+    return int(round(1.0 / (wl.freq * wl.dt)))
