@@ -36,6 +36,7 @@ struct Carver {
 
 template <typename T> void carve_parts(Carver &c, Parts<T> &p, int64_t cap)
 {
+    cap = (cap + PAD - 1) / PAD * PAD;   // the pass reads and writes whole blocks of particles
     p.cell = c.take<int32_t>(cap);
     p.dr = c.take<T>(cap);
     p.dz = c.take<T>(cap);
@@ -678,7 +679,7 @@ static void vcycle(pic_ctx &c)
             for (int col = 0; col < nc; ++col) launch_mg_smooth(c.lv.L[l], col, c.mgs, c.stream);
         launch_mg_restrict(c.lv.L[l], c.lv.L[l + 1], c.mgs, c.stream);
     }
-    launch_mg_bottom(c.lv, c.lb, c.lb == 0 ? 2 : 1, c.lb == 0 ? 2 : 1, 0, c.mgs, c.stream);
+    launch_mg_bottom(c.lv, c.lb, c.lb == 0 ? 2 : 1, c.lb == 0 ? 2 : 1, c.mgs, c.stream);
     for (int l = c.lb - 1; l >= 0; --l) {
         launch_mg_prolong(c.lv.L[l], c.lv.L[l + 1], c.mgs, c.stream);
         const int nc = c.lv.L[l].nine ? 4 : 2;
@@ -719,13 +720,17 @@ static pic_status solve(pic_ctx &c, int64_t n, double rtol, int max_cycles, pic_
     launch_pcg_begin(L0, v, c.d_tag, c.d_vc, c.d_vs, std::cos(th), std::sin(th), c.mgs, c.phi_prev, extrap, c.stream);
     c.have_prev = true;
     c.last_solve = n;
-    launch_pcg_resid(L0, v, c.mgs, c.mgpartial, rtol, c.stream);
+    const int np = pcg_blocks(L0.nodes);
+    budget = std::min(budget, MAX_CG);
+    launch_pcg_resid(L0, v, c.mgpartial, c.stream);
+    launch_pcg_check(c.mgs, c.mgpartial, np, rtol, true, c.stream);
     for (int k = 0; k < budget; ++k) {
         vcycle(c);
         launch_pcg_rz(L0, v, c.mgs, c.mgpartial, c.stream);
-        launch_pcg_p(L0, v, c.mgs, c.stream);
+        launch_pcg_p(L0, v, c.mgs, c.mgpartial, c.stream);
         launch_pcg_matvec(L0, v, c.mgs, c.mgpartial, c.stream);
-        launch_pcg_update(L0, v, c.mgs, c.mgpartial, rtol, c.stream);
+        launch_pcg_update(L0, v, c.mgs, c.mgpartial, c.stream);
+        launch_pcg_check(c.mgs, c.mgpartial, np, rtol, false, c.stream);
     }
     if (c.cfg.nturns > 0)
         launch_face_charge(c.phi, c.fp, c.fq, c.fk, c.fc, c.nfaces, c.Qk, c.cfg.nturns, c.stream);

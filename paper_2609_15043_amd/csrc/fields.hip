@@ -260,9 +260,10 @@ __global__ void k_mg_prolong(MGLevel F, MGLevel C, const MGState *st)
     op_prolong(F, C, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
 }
 
-// Levels lb .. nl-1 as one V-cycle in a single workgroup.
-__global__ __launch_bounds__(1024) void k_mg_bottom(MGLevels lv, int lb, int nu1, int nu2, int nbottom,
-                                                    const MGState *st)
+// Levels lb .. nl-1 as one V-cycle in a single workgroup (level lb's
+// right-hand side comes from the multi-block restriction), with an exact
+// dense solve on the coarsest level.
+__global__ __launch_bounds__(1024) void k_mg_bottom(MGLevels lv, int lb, int nu1, int nu2, const MGState *st)
 {
     if (st->done) return;
     const int t = threadIdx.x, S = blockDim.x;
@@ -278,12 +279,11 @@ __global__ __launch_bounds__(1024) void k_mg_bottom(MGLevels lv, int lb, int nu1
         __syncthreads();
     }
     {
-        // exact solve on the coarsest level: phi = A^-1 rhs (dense, precomputed)
-        const MGLevel &L = lv.L[nl - 1];
-        for (int r = t; r < L.nodes; r += S) {
+        const MGLevel &Lc = lv.L[nl - 1];
+        for (int r = t; r < Lc.nodes; r += S) {
             double acc = 0.0;
-            for (int k = 0; k < L.nodes; ++k) acc += lv.coarse_inv[(size_t)r * L.nodes + k] * L.rhs[k];
-            L.phi[r] = acc;
+            for (int k = 0; k < Lc.nodes; ++k) acc += lv.coarse_inv[(size_t)r * Lc.nodes + k] * Lc.rhs[k];
+            Lc.phi[r] = acc;
         }
         __syncthreads();
     }
@@ -301,48 +301,43 @@ __global__ __launch_bounds__(1024) void k_mg_bottom(MGLevels lv, int lb, int nu1
 
 // ---------------------------------------------------------------------------
 // Conjugate gradient on the free nodes of level 0, preconditioned by one
-// V-cycle.  Scalars (r.z, alpha, beta, norms) stay on the device; every
-// kernel returns at once after convergence, so the host can enqueue a
-// fixed budget of iterations without synchronising.  Reductions go through
-// per-block partials summed in block order by the last block.
+// V-cycle.  Scalars (r.z, alpha, beta, norms) stay on the device.  Each
+// reduction writes per-block partials that the NEXT kernel sums (stream
+// order makes them visible without device-scope fences), every block the
+// same partials in the same order, so all blocks agree bit for bit.  After
+// convergence every kernel returns at once, so the host can enqueue a
+// budget of iterations without synchronising.
 // ---------------------------------------------------------------------------
-template <int NV>
-__device__ __forceinline__ bool block_reduce_last(double (&v)[NV], double *partial, MGState *st, bool is_max)
+__device__ __forceinline__ void block_partial(double v, double *out, bool is_max)
 {
-    __shared__ double red[NV][256];
-    __shared__ bool last;
-    auto op = [is_max](double x, double y) { return is_max ? fmax(x, y) : x + y; };
-    for (int q = 0; q < NV; ++q) red[q][threadIdx.x] = v[q];
+    __shared__ double red[256];
+    red[threadIdx.x] = v;
     __syncthreads();
     for (int off = 128; off > 0; off >>= 1) {
         if (threadIdx.x < off)
-            for (int q = 0; q < NV; ++q) red[q][threadIdx.x] = op(red[q][threadIdx.x], red[q][threadIdx.x + off]);
+            red[threadIdx.x] = is_max ? fmax(red[threadIdx.x], red[threadIdx.x + off]) : red[threadIdx.x] + red[threadIdx.x + off];
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        for (int q = 0; q < NV; ++q) partial[NV * blockIdx.x + q] = red[q][0];
-        __threadfence();
-        last = atomicAdd(&st->ticket, 1u) == gridDim.x - 1;
-    }
-    __syncthreads();
-    if (!last) return false;
-    __threadfence();
-    // the last block: strided sums of the partials, then a fixed tree
-    for (int q = 0; q < NV; ++q) {
-        double acc = 0.0;
-        for (unsigned b = threadIdx.x; b < gridDim.x; b += 256) acc = op(acc, partial[NV * b + q]);
-        red[q][threadIdx.x] = acc;
-    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
+// sum (or max) of the first np partials, same value in every thread
+__device__ __forceinline__ double fold_partials(const double *part, int np, int stride, bool is_max)
+{
+    __shared__ double red[256];
+    __shared__ double result;
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < np; b += blockDim.x) acc = is_max ? fmax(acc, part[b * stride]) : acc + part[b * stride];
+    red[threadIdx.x] = acc;
     __syncthreads();
     for (int off = 128; off > 0; off >>= 1) {
         if (threadIdx.x < off)
-            for (int q = 0; q < NV; ++q) red[q][threadIdx.x] = op(red[q][threadIdx.x], red[q][threadIdx.x + off]);
+            red[threadIdx.x] = is_max ? fmax(red[threadIdx.x], red[threadIdx.x + off]) : red[threadIdx.x] + red[threadIdx.x + off];
         __syncthreads();
     }
-    if (threadIdx.x != 0) return false;
-    for (int q = 0; q < NV; ++q) v[q] = red[q][0];
-    st->ticket = 0;
-    return true;
+    if (threadIdx.x == 0) result = red[0];
+    __syncthreads();
+    return result;
 }
 
 // Dirichlet values (turn k nodes: phi_k(t_n)); free nodes start from the
@@ -354,10 +349,9 @@ __global__ void k_pcg_begin(MGLevel L, PCGVec v, const int32_t *tag, const doubl
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n == 0) {
         st->done = 0;
-        st->cycles = 0;
+        st->cycles = -1;
         st->ticket = 0;
-        st->rz = 0.0;
-        st->beta = 0.0;
+        st->rz[0] = 0.0;
     }
     if (n >= L.nodes) return;
     const int k = tag[n];
@@ -370,10 +364,11 @@ __global__ void k_pcg_begin(MGLevel L, PCGVec v, const int32_t *tag, const doubl
     }
 }
 
-// r = b - A x on free nodes (0 on Dirichlet), z = 0, norms
-__global__ __launch_bounds__(256) void k_pcg_resid(MGLevel L, PCGVec v, MGState *st, double *partial, double rtol)
+// r = b - A x on free nodes (0 on Dirichlet), z = p = 0; partials of
+// max|r| and of the equation scale max(|b|, |cc x|)
+__global__ __launch_bounds__(256) void k_pcg_resid(MGLevel L, PCGVec v, double *partial)
 {
-    double m[2] = {0.0, 0.0};
+    double m0 = 0.0, m1 = 0.0;
     for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < L.nodes; n += gridDim.x * blockDim.x) {
         v.z[n] = 0.0;
         v.p[n] = 0.0;
@@ -384,43 +379,54 @@ __global__ __launch_bounds__(256) void k_pcg_resid(MGLevel L, PCGVec v, MGState 
         const int i = n / L.nr1, j = n - i * L.nr1;
         const double r = v.b[n] - apply_op(L, v.x, n, i, j);
         v.r[n] = r;
-        m[0] = fmax(m[0], fabs(r));
-        m[1] = fmax(m[1], fmax(fabs(v.b[n]), fabs(L.cc[n] * v.x[n])));
+        m0 = fmax(m0, fabs(r));
+        m1 = fmax(m1, fmax(fabs(v.b[n]), fabs(L.cc[n] * v.x[n])));
     }
-    if (block_reduce_last<2>(m, partial, st, true)) {
-        st->scale = m[1] > 0.0 ? m[1] : 1.0;
-        st->rel = m[0] / st->scale;
-        if (m[0] == 0.0 || st->rel <= rtol) st->done = 1;
-    }
+    block_partial(m0, partial + 2 * blockIdx.x, true);
+    block_partial(m1, partial + 2 * blockIdx.x + 1, true);
 }
 
-// rz_new = r.z ; beta = rz_new / rz_old (0 on the first iteration)
-__global__ __launch_bounds__(256) void k_pcg_rz(MGLevel L, PCGVec v, MGState *st, double *partial)
+// One block: convergence test on the residual partials (k_pcg_resid at the
+// start of a solve, k_pcg_update afterwards); counts the iteration.
+__global__ __launch_bounds__(256) void k_pcg_check(MGState *st, const double *partial, int np, double rtol, int first)
 {
     if (st->done) return;
-    double s[1] = {0.0};
-    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < L.nodes; n += gridDim.x * blockDim.x)
-        s[0] += v.r[n] * v.z[n];
-    if (block_reduce_last<1>(s, partial, st, false)) {
-        st->beta = st->cycles == 0 || st->rz == 0.0 ? 0.0 : s[0] / st->rz;
-        st->rz = s[0];
-    }
+    const double R = fold_partials(partial, np, 2, true);
+    double scale = st->scale;
+    if (first) scale = fold_partials(partial + 1, np, 2, true);
+    if (threadIdx.x != 0) return;
+    if (first) st->scale = scale = scale > 0.0 ? scale : 1.0;
+    st->cycles += 1;
+    st->rel = R / scale;
+    if (R == 0.0 || st->rel <= rtol) st->done = 1;
 }
 
-// p = z + beta p
-__global__ void k_pcg_p(MGLevel L, PCGVec v, const MGState *st)
+// partials of r.z
+__global__ __launch_bounds__(256) void k_pcg_rz(MGLevel L, PCGVec v, const MGState *st, double *partial)
 {
     if (st->done) return;
-    const double beta = st->beta;
+    double s = 0.0;
+    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < L.nodes; n += gridDim.x * blockDim.x) s += v.r[n] * v.z[n];
+    block_partial(s, partial + 2 * blockIdx.x, false);
+}
+
+// rz_k = sum of partials; p = z + (rz_k / rz_{k-1}) p (beta = 0 first)
+__global__ __launch_bounds__(256) void k_pcg_p(MGLevel L, PCGVec v, MGState *st, const double *partial, int np)
+{
+    if (st->done) return;
+    const int it = st->cycles;
+    const double rz = fold_partials(partial, np, 2, false);
+    const double beta = it == 0 || st->rz[it] == 0.0 ? 0.0 : rz / st->rz[it];
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->rz[it + 1] = rz;
     for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < L.nodes; n += gridDim.x * blockDim.x)
         v.p[n] = v.z[n] + beta * v.p[n];
 }
 
-// Ap = A p on free nodes; alpha = rz / (p.Ap)
-__global__ __launch_bounds__(256) void k_pcg_matvec(MGLevel L, PCGVec v, MGState *st, double *partial)
+// Ap = A p on free nodes; partials of p.Ap
+__global__ __launch_bounds__(256) void k_pcg_matvec(MGLevel L, PCGVec v, const MGState *st, double *partial)
 {
     if (st->done) return;
-    double s[1] = {0.0};
+    double s = 0.0;
     for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < L.nodes; n += gridDim.x * blockDim.x) {
         double ap = 0.0;
         if (!L.dir[n]) {
@@ -428,30 +434,28 @@ __global__ __launch_bounds__(256) void k_pcg_matvec(MGLevel L, PCGVec v, MGState
             ap = apply_op(L, v.p, n, i, j);
         }
         v.Ap[n] = ap;
-        s[0] += v.p[n] * ap;
+        s += v.p[n] * ap;
     }
-    if (block_reduce_last<1>(s, partial, st, false)) st->alpha = s[0] != 0.0 ? st->rz / s[0] : 0.0;
+    block_partial(s, partial + 2 * blockIdx.x, false);
 }
 
-// x += alpha p, r -= alpha Ap, z = 0; convergence check
-__global__ __launch_bounds__(256) void k_pcg_update(MGLevel L, PCGVec v, MGState *st, double *partial, double rtol)
+// alpha = rz / p.Ap; x += alpha p, r -= alpha Ap, z = 0; partials of max|r|
+__global__ __launch_bounds__(256) void k_pcg_update(MGLevel L, PCGVec v, const MGState *st, double *partial, int np)
 {
     if (st->done) return;
-    const double alpha = st->alpha;
-    double m[1] = {0.0};
+    const double pap = fold_partials(partial, np, 2, false);
+    const double alpha = pap != 0.0 ? st->rz[st->cycles + 1] / pap : 0.0;
+    __syncthreads();
+    double m = 0.0;
     for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < L.nodes; n += gridDim.x * blockDim.x) {
         v.z[n] = 0.0;
         if (L.dir[n]) continue;
         v.x[n] += alpha * v.p[n];
         const double r = v.r[n] - alpha * v.Ap[n];
         v.r[n] = r;
-        m[0] = fmax(m[0], fabs(r));
+        m = fmax(m, fabs(r));
     }
-    if (block_reduce_last<1>(m, partial, st, true)) {
-        st->cycles += 1;
-        st->rel = m[0] / st->scale;
-        if (m[0] == 0.0 || st->rel <= rtol) st->done = 1;
-    }
+    block_partial(m, partial + 2 * blockIdx.x, true);
 }
 
 // Q_k = sum over faces (turn-k node p, outside node q) of c (phi_p - phi_q)
@@ -515,35 +519,47 @@ void launch_mg_prolong(const MGLevel &F, const MGLevel &C, const MGState *st, hi
 {
     hipLaunchKernelGGL(k_mg_prolong, dim3(mg_grid(F.nodes)), dim3(256), 0, s, F, C, st);
 }
-void launch_mg_bottom(const MGLevels &lv, int lb, int nu1, int nu2, int nbottom, const MGState *st, hipStream_t s)
+void launch_mg_bottom(const MGLevels &lv, int lb, int nu1, int nu2, const MGState *st, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_mg_bottom, dim3(1), dim3(1024), 0, s, lv, lb, nu1, nu2, nbottom, st);
+    hipLaunchKernelGGL(k_mg_bottom, dim3(1), dim3(1024), 0, s, lv, lb, nu1, nu2, st);
 }
+size_t mg_bottom_lds(const MGLevels &lv, int lb)
+{
+    size_t nodes = 0;
+    for (int l = lb; l < lv.n; ++l) nodes += lv.L[l].nodes;
+    return 2 * nodes * sizeof(double);
+}
+int pcg_blocks(int nodes) { return (int)red_grid(nodes); }
 void launch_pcg_begin(const MGLevel &L, const PCGVec &v, const int32_t *tag, const double *vc, const double *vs,
                       double cs, double sn, MGState *st, double *prev, bool extrap, hipStream_t s)
 {
     hipLaunchKernelGGL(k_pcg_begin, dim3(nblk(L.nodes, 256)), dim3(256), 0, s, L, v, tag, vc, vs, cs, sn, st, prev,
                        extrap ? 1 : 0);
 }
-void launch_pcg_resid(const MGLevel &L, const PCGVec &v, MGState *st, double *partial, double rtol, hipStream_t s)
+void launch_pcg_resid(const MGLevel &L, const PCGVec &v, double *partial, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_pcg_resid, dim3(red_grid(L.nodes)), dim3(256), 0, s, L, v, st, partial, rtol);
+    hipLaunchKernelGGL(k_pcg_resid, dim3(red_grid(L.nodes)), dim3(256), 0, s, L, v, partial);
 }
-void launch_pcg_rz(const MGLevel &L, const PCGVec &v, MGState *st, double *partial, hipStream_t s)
+void launch_pcg_check(MGState *st, const double *partial, int np, double rtol, bool first, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pcg_check, dim3(1), dim3(256), 0, s, st, partial, np, rtol, first ? 1 : 0);
+}
+void launch_pcg_rz(const MGLevel &L, const PCGVec &v, const MGState *st, double *partial, hipStream_t s)
 {
     hipLaunchKernelGGL(k_pcg_rz, dim3(red_grid(L.nodes)), dim3(256), 0, s, L, v, st, partial);
 }
-void launch_pcg_p(const MGLevel &L, const PCGVec &v, const MGState *st, hipStream_t s)
+void launch_pcg_p(const MGLevel &L, const PCGVec &v, MGState *st, const double *partial, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_pcg_p, dim3(mg_grid(L.nodes)), dim3(256), 0, s, L, v, st);
+    hipLaunchKernelGGL(k_pcg_p, dim3(red_grid(L.nodes)), dim3(256), 0, s, L, v, st, partial, (int)red_grid(L.nodes));
 }
-void launch_pcg_matvec(const MGLevel &L, const PCGVec &v, MGState *st, double *partial, hipStream_t s)
+void launch_pcg_matvec(const MGLevel &L, const PCGVec &v, const MGState *st, double *partial, hipStream_t s)
 {
     hipLaunchKernelGGL(k_pcg_matvec, dim3(red_grid(L.nodes)), dim3(256), 0, s, L, v, st, partial);
 }
-void launch_pcg_update(const MGLevel &L, const PCGVec &v, MGState *st, double *partial, double rtol, hipStream_t s)
+void launch_pcg_update(const MGLevel &L, const PCGVec &v, const MGState *st, double *partial, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_pcg_update, dim3(red_grid(L.nodes)), dim3(256), 0, s, L, v, st, partial, rtol);
+    hipLaunchKernelGGL(k_pcg_update, dim3(red_grid(L.nodes)), dim3(256), 0, s, L, v, st, partial,
+                       (int)red_grid(L.nodes));
 }
 void launch_face_charge(const double *phi, const int32_t *fp, const int32_t *fq, const int32_t *fk, const double *fc,
                         int nfaces, double *Qk, int nturns, hipStream_t s)

@@ -10,13 +10,15 @@ namespace pic {
 
 // LDS deposit window (nodes) of one particle block: whole node rows around
 // the block's middle particle, so particles that drifted a few cells since
-// the last sort still land in LDS.  FP32 window values: 4096 nodes; FP64: 2048.
+// the last sort still land in LDS.  FP32 window values: 2048 nodes; FP64: 1024.
 template <typename T> struct Win {
-    static constexpr int N = sizeof(T) == 4 ? 4096 : 2048;
+    static constexpr int N = sizeof(T) == 4 ? 2048 : 1024;
 };
 constexpr int BLOCK = 256;
-constexpr int PPT = 16;                 // particles per thread per pass block
-constexpr int CHUNK = BLOCK * PPT;      // particles per pass block
+constexpr int RUN = 4;                  // consecutive particles per lane per vector load
+constexpr int RUNS = 4;                 // runs per wave per block
+constexpr int CHUNK = BLOCK * RUN * RUNS;   // particles per pass block (4096)
+constexpr int PAD = CHUNK;              // particle capacities are padded to this multiple
 
 // Counter slots (int64) in the device statistics block.
 enum StatSlot {
@@ -127,6 +129,7 @@ struct MGLevels {
 };
 
 // Device-resident state of one preconditioned-CG solve.
+constexpr int MAX_CG = 64;
 struct MGState {
     int32_t done;
     int32_t cycles;          // CG iterations (one V-cycle each)
@@ -134,7 +137,7 @@ struct MGState {
     int32_t pad;
     double rel;              // max |r| / scale
     double scale;            // max(|b|, |diag x|) at the start of the solve
-    double rz, alpha, beta;
+    double rz[MAX_CG + 1];   // r.z of each iteration
 };
 
 constexpr int MAX_TURNS = 16;

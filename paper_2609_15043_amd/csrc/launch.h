@@ -49,14 +49,17 @@ int pcg_partial_size(int nodes);
 void launch_mg_smooth(const MGLevel &L, int color, const MGState *st, hipStream_t s);
 void launch_mg_restrict(const MGLevel &F, const MGLevel &C, const MGState *st, hipStream_t s);
 void launch_mg_prolong(const MGLevel &F, const MGLevel &C, const MGState *st, hipStream_t s);
-void launch_mg_bottom(const MGLevels &lv, int lb, int nu1, int nu2, int nbottom, const MGState *st, hipStream_t s);
+void launch_mg_bottom(const MGLevels &lv, int lb, int nu1, int nu2, const MGState *st, hipStream_t s);
+size_t mg_bottom_lds(const MGLevels &lv, int lb);
+int pcg_blocks(int nodes);
 void launch_pcg_begin(const MGLevel &L, const PCGVec &v, const int32_t *tag, const double *vc, const double *vs,
                       double cs, double sn, MGState *st, double *prev, bool extrap, hipStream_t s);
-void launch_pcg_resid(const MGLevel &L, const PCGVec &v, MGState *st, double *partial, double rtol, hipStream_t s);
-void launch_pcg_rz(const MGLevel &L, const PCGVec &v, MGState *st, double *partial, hipStream_t s);
-void launch_pcg_p(const MGLevel &L, const PCGVec &v, const MGState *st, hipStream_t s);
-void launch_pcg_matvec(const MGLevel &L, const PCGVec &v, MGState *st, double *partial, hipStream_t s);
-void launch_pcg_update(const MGLevel &L, const PCGVec &v, MGState *st, double *partial, double rtol, hipStream_t s);
+void launch_pcg_resid(const MGLevel &L, const PCGVec &v, double *partial, hipStream_t s);
+void launch_pcg_check(MGState *st, const double *partial, int np, double rtol, bool first, hipStream_t s);
+void launch_pcg_rz(const MGLevel &L, const PCGVec &v, const MGState *st, double *partial, hipStream_t s);
+void launch_pcg_p(const MGLevel &L, const PCGVec &v, MGState *st, const double *partial, hipStream_t s);
+void launch_pcg_matvec(const MGLevel &L, const PCGVec &v, const MGState *st, double *partial, hipStream_t s);
+void launch_pcg_update(const MGLevel &L, const PCGVec &v, const MGState *st, double *partial, hipStream_t s);
 void launch_face_charge(const double *phi, const int32_t *fp, const int32_t *fq, const int32_t *fk, const double *fc,
                         int nfaces, double *Qk, int nturns, hipStream_t s);
 

@@ -309,12 +309,78 @@ __device__ int collide(const MccC &mc, int s, uint32_t id, int32_t step, T &vr, 
 }
 
 // ---------------------------------------------------------------------------
-// The particle pass.  PUSH: gather + Boris + move + J deposit + absorption,
-// and the step's collision candidates (next == step) go to a queue; DEPQ:
-// charge deposit at the (new) positions.  Fused: both in one streaming
-// pass.  The collisions themselves run in k_collide over the queue, so the
-// rarely taken FP64 collision code does not weigh on this kernel's
-// registers.
+// 16-byte vector access to four consecutive particles of one lane.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void ld4(const float *p, float (&o)[4])
+{
+    const float4 v = *reinterpret_cast<const float4 *>(p);
+    o[0] = v.x, o[1] = v.y, o[2] = v.z, o[3] = v.w;
+}
+__device__ __forceinline__ void ld4(const double *p, double (&o)[4])
+{
+    const double2 u = *reinterpret_cast<const double2 *>(p), v = *reinterpret_cast<const double2 *>(p + 2);
+    o[0] = u.x, o[1] = u.y, o[2] = v.x, o[3] = v.y;
+}
+__device__ __forceinline__ void ld4(const int32_t *p, int32_t (&o)[4])
+{
+    const int4 v = *reinterpret_cast<const int4 *>(p);
+    o[0] = v.x, o[1] = v.y, o[2] = v.z, o[3] = v.w;
+}
+__device__ __forceinline__ void st4(float *p, const float (&o)[4])
+{
+    *reinterpret_cast<float4 *>(p) = make_float4(o[0], o[1], o[2], o[3]);
+}
+__device__ __forceinline__ void st4(double *p, const double (&o)[4])
+{
+    *reinterpret_cast<double2 *>(p) = make_double2(o[0], o[1]);
+    *reinterpret_cast<double2 *>(p + 2) = make_double2(o[2], o[3]);
+}
+__device__ __forceinline__ void st4(int32_t *p, const int32_t (&o)[4])
+{
+    *reinterpret_cast<int4 *>(p) = make_int4(o[0], o[1], o[2], o[3]);
+}
+
+// Four node values of one particle straight into the window (or the global
+// accumulator outside it): the per-lane path for a particle whose cell
+// differs from its run's key.
+template <typename T>
+__device__ __forceinline__ void deposit_lane(int key, T v0, T v1, T v2, T v3, T *win, int base, long long *acc,
+                                             int nr1, double scale, unsigned long long *sstat)
+{
+    const int nodes[4] = {key, key + 1, key + nr1, key + nr1 + 1};
+    const T vals[4] = {v0, v1, v2, v3};
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int o = nodes[c] - base;
+        if (o >= 0 && o < Win<T>::N) {
+            atomicAdd(&win[o], vals[c]);
+        } else {
+            atomic_add_i64(&acc[nodes[c]], to_fixed((double)vals[c], scale));
+            atomicAdd(&sstat[ST_WINOUT], 1ull);
+        }
+    }
+}
+
+// R^2-linear radial and linear axial weights of the four cell nodes
+template <typename T>
+__device__ __forceinline__ void node_weights(int j, T dr, T dz, T &w00, T &w01, T &w10, T &w11)
+{
+    const T fj = (T)j;
+    const T wr1 = quot(dr * ((T)2 * fj + dr), (T)2 * fj + (T)1);
+    w00 = ((T)1 - dz) * ((T)1 - wr1);
+    w01 = ((T)1 - dz) * wr1;
+    w10 = dz * ((T)1 - wr1);
+    w11 = dz * wr1;
+}
+
+// ---------------------------------------------------------------------------
+// The particle pass.  Each lane takes runs of four consecutive particles
+// (16-byte vector loads; a wave reads 1 KiB contiguous per instruction).
+// PUSH: gather + Boris + move + J deposit + absorption, and this step's
+// collision candidates (next == step) go to a queue; DEPQ: charge deposit
+// at the (new) positions.  Fused: both in one streaming pass.  Deposits
+// accumulate in registers over the run (particles of one cell), then one
+// wave reduction per run; the collisions run in k_collide over the queue.
 // ---------------------------------------------------------------------------
 template <typename T, bool PUSH, bool DEPQ>
 __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs<T> a)
@@ -330,6 +396,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs<T> a)
     __shared__ int s_ncand, s_qbase;
 
     const int tid = threadIdx.x;
+    const int lane = lane_id();
     const int64_t n = *a.count;
     const int64_t c0 = (int64_t)blockIdx.x * CHUNK;
     if (c0 >= n) return;
@@ -367,45 +434,43 @@ __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs<T> a)
     __syncthreads();
     const int base = s_base;
 
-    for (int64_t p0 = c0; p0 < c1; p0 += BLOCK) {
-        const int64_t p = p0 + tid;
-        const bool act = p < c1;
-        int32_t cell = act ? a.p.cell[p] : -1;
-        const bool live0 = cell >= 0;
-        int i = 0, j = 0;
-        T dr = 0, dz = 0, vr = 0, vt = 0, vz = 0;
-        int32_t next = -1;
-        if (live0) {
-            split_cell(g, cell, i, j);
-            dr = a.p.dr[p];
-            dz = a.p.dz[p];
-            if (PUSH) {
-                vr = a.p.vr[p];
-                vt = a.p.vt[p];
-                vz = a.p.vz[p];
-                next = a.p.next[p];
-            }
+    const int64_t wbase = c0 + (int64_t)(tid >> 6) * (RUN * RUNS * 64);
+    for (int r = 0; r < RUNS; ++r) {
+        const int64_t q0 = wbase + (int64_t)r * (RUN * 64) + RUN * lane;
+        int32_t cell[RUN], nxt[RUN];
+        T dr[RUN], dz[RUN], vr[RUN], vt[RUN], vz[RUN];
+        ld4(a.p.cell + q0, cell);
+        ld4(a.p.dr + q0, dr);
+        ld4(a.p.dz + q0, dz);
+        if (PUSH) {
+            ld4(a.p.vr + q0, vr);
+            ld4(a.p.vt + q0, vt);
+            ld4(a.p.vz + q0, vz);
+            ld4(a.p.next + q0, nxt);
         }
-        bool live = live0;
-        if constexpr (PUSH) {
-            int absorbed = 0;
-            T w00 = 0, w01 = 0, w10 = 0, w11 = 0, jv = 0;
-            int key = 0;
-            if (live0) {
-                const T fj = (T)j;
-                const T wr1 = quot(dr * ((T)2 * fj + dr), (T)2 * fj + (T)1);
-                const T wz1 = dz;
-                w00 = ((T)1 - wz1) * ((T)1 - wr1);
-                w01 = ((T)1 - wz1) * wr1;
-                w10 = wz1 * ((T)1 - wr1);
-                w11 = wz1 * wr1;
-                key = i * g.nr1 + j;
+        bool live[RUN];
+#pragma unroll
+        for (int k = 0; k < RUN; ++k) live[k] = q0 + k < c1 && cell[k] >= 0;
+
+        // lane's run sums around its key nodes (old cell for J, new for Q)
+        int keyJ = -1, keyQ = -1;
+        T aJ[4] = {0, 0, 0, 0}, aQ[4] = {0, 0, 0, 0};
+        int absorbed_n = 0;
+        uint32_t cand_bits = 0;
+#pragma unroll
+        for (int k = 0; k < RUN; ++k) {
+            if (PUSH && live[k]) {
+                int i, j;
+                split_cell(g, cell[k], i, j);
+                T w00, w01, w10, w11;
+                node_weights<T>(j, dr[k], dz[k], w00, w01, w10, w11);
+                const int key = i * g.nr1 + j;
                 const F4 f00 = a.ef[key], f01 = a.ef[key + 1], f10 = a.ef[key + g.nr1], f11 = a.ef[key + g.nr1 + 1];
                 const T er = w00 * f00.x + w01 * f01.x + w10 * f10.x + w11 * f11.x;
                 const T ez = w00 * f00.y + w01 * f01.y + w10 * f10.y + w11 * f11.y;
                 const T et = w00 * f00.z + w01 * f01.z + w10 * f10.z + w11 * f11.z;
                 const T h = (T)a.sc.h;
-                T ur = vr + h * er, ut = vt + h * et, uz = vz + h * ez;
+                T ur = vr[k] + h * er, ut = vt[k] + h * et, uz = vz[k] + h * ez;
                 if (a.sc.has_b) {
                     const T t0 = (T)a.sc.bt[0], t1 = (T)a.sc.bt[1], t2 = (T)a.sc.bt[2];
                     const T s0 = (T)a.sc.bs[0], s1 = (T)a.sc.bs[1], s2 = (T)a.sc.bs[2];
@@ -417,9 +482,21 @@ __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs<T> a)
                 ur += h * er;
                 ut += h * et;
                 uz += h * ez;
-                jv = (T)0.5 * (vt + ut) * (T)a.sc.inv_vref;
+                // azimuthal current at x^n with the time-centred v_theta
+                const T jv = (T)0.5 * (vt[k] + ut) * (T)a.sc.inv_vref;
+                if (keyJ < 0) keyJ = key;
+                if (key == keyJ) {
+                    aJ[0] += jv * w00;
+                    aJ[1] += jv * w01;
+                    aJ[2] += jv * w10;
+                    aJ[3] += jv * w11;
+                } else {
+                    deposit_lane<T>(key, jv * w00, jv * w01, jv * w10, jv * w11, winJ, base, a.accJ, g.nr1,
+                                    a.sc.jscale, sstat);
+                }
                 // Cartesian move in the particle's plane, in cell units
-                const T ar = dr + ur * (T)a.sc.dtr;
+                const T fj = (T)j;
+                const T ar = dr[k] + ur * (T)a.sc.dtr;
                 const T X = fj + ar;
                 const T Y = ut * (T)a.sc.dtr;
                 const T hyp = sqrt(X * X + Y * Y);
@@ -438,7 +515,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs<T> a)
                     drn -= (T)1;
                     jn += 1;
                 }
-                const T bz = dz + uz * (T)a.sc.dtz;
+                const T bz = dz[k] + uz * (T)a.sc.dtz;
                 const T fz = floor(bz);
                 int in = i + (int)fz;
                 T dzn = bz - fz;
@@ -446,14 +523,15 @@ __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs<T> a)
                     dzn -= (T)1;
                     in += 1;
                 }
+                int absorbed = 0;
                 if (!(hyp == hyp) || !(bz == bz) || in < 0) {
                     absorbed = 1;   // below the bottom wall (or a non-finite state)
                 } else if (in >= g.ip) {
                     absorbed = 1;
                     if (g.window && uz > (T)0) {
                         // crossing of z = zp within the step (FP64)
-                        const double frac = ((double)g.ip - ((double)i + (double)dz)) / ((double)uz * a.sc.dtz);
-                        const double xs = (double)j + (double)dr + (double)ur * a.sc.dtr * frac;
+                        const double frac = ((double)g.ip - ((double)i + (double)dz[k])) / ((double)uz * a.sc.dtz);
+                        const double xs = (double)j + (double)dr[k] + (double)ur * a.sc.dtr * frac;
                         const double ys = (double)ut * a.sc.dtr * frac;
                         const double Rs = sqrt(xs * xs + ys * ys);
                         if (Rs < (double)g.nr) {
@@ -469,69 +547,84 @@ __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs<T> a)
                 } else if (jn >= g.nr || jn < 0) {
                     absorbed = 1;
                 }
-                live = absorbed == 0;
-                cell = live ? in * g.nr + jn : -1;
-                dr = drn;
-                dz = dzn;
-                vr = vrn;
-                vt = vtn;
-                vz = uz;
+                absorbed_n += absorbed != 0;
+                live[k] = absorbed == 0;
+                cell[k] = live[k] ? in * g.nr + jn : -1;
+                dr[k] = drn;
+                dz[k] = dzn;
+                vr[k] = vrn;
+                vt[k] = vtn;
+                vz[k] = uz;
+                if (live[k] && nxt[k] == a.step) cand_bits |= 1u << k;
             }
-            deposit4<T>(live0, key, jv * w00, jv * w01, jv * w10, jv * w11, winJ, base, a.accJ, g.nr1,
-                        a.sc.jscale, sstat);
-            count_wave(absorbed != 0, sstat, ST_ABS0 + s);
-            // this step's collision candidates -> block-local list (LDS), one
-            // global reservation per block at the end; a full list spills
-            // straight to the queue
-            const bool cand = live && next == a.step;
-            const uint64_t cm = ballot(cand);
-            if (cm) {
-                const int lead = __ffsll((unsigned long long)cm) - 1;
-                int slot0 = 0;
-                if (lane_id() == lead) slot0 = atomicAdd(&s_ncand, __popcll(cm));
-                slot0 = __builtin_amdgcn_readlane(slot0, lead);
-                if (cand) {
-                    const int slot = slot0 + __builtin_amdgcn_mbcnt_hi((uint32_t)(cm >> 32),
-                                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)cm, 0u));
-                    if (slot < CAND_LDS) {
-                        s_cand[slot] = (int32_t)p;
-                    } else {
-                        const int gs = atomicAdd(a.q.count, 1);
-                        if (gs < a.q.cap)
-                            a.q.idx[gs] = (int32_t)p;
-                        else
-                            atomicOr(a.err, (int)ERR_QUEUE_OVERFLOW);
-                    }
+            if (DEPQ && live[k]) {
+                int i, j;
+                split_cell(g, cell[k], i, j);
+                T w00, w01, w10, w11;
+                node_weights<T>(j, dr[k], dz[k], w00, w01, w10, w11);
+                const int key = i * g.nr1 + j;
+                if (keyQ < 0) keyQ = key;
+                if (key == keyQ) {
+                    aQ[0] += w00;
+                    aQ[1] += w01;
+                    aQ[2] += w10;
+                    aQ[3] += w11;
+                } else {
+                    deposit_lane<T>(key, w00, w01, w10, w11, winQ, base, a.accQ, g.nr1, a.sc.qscale, sstat);
                 }
             }
-        }
-        if constexpr (DEPQ) {
-            T w00 = 0, w01 = 0, w10 = 0, w11 = 0;
-            int key = 0;
-            if (live) {
-                int ii, jj;
-                split_cell(g, cell, ii, jj);
-                const T fj = (T)jj;
-                const T wr1 = quot(dr * ((T)2 * fj + dr), (T)2 * fj + (T)1);
-                w00 = ((T)1 - dz) * ((T)1 - wr1);
-                w01 = ((T)1 - dz) * wr1;
-                w10 = dz * ((T)1 - wr1);
-                w11 = dz * wr1;
-                key = ii * g.nr1 + jj;
-            }
-            deposit4<T>(live, key, w00, w01, w10, w11, winQ, base, a.accQ, g.nr1, a.sc.qscale, sstat);
         }
         if constexpr (PUSH) {
-            if (live0) {
-                a.p.cell[p] = cell;
-                if (live) {
-                    a.p.dr[p] = dr;
-                    a.p.dz[p] = dz;
-                    a.p.vr[p] = vr;
-                    a.p.vt[p] = vt;
-                    a.p.vz[p] = vz;
-                }
+            deposit4<T>(keyJ >= 0, keyJ, aJ[0], aJ[1], aJ[2], aJ[3], winJ, base, a.accJ, g.nr1, a.sc.jscale, sstat);
+            {
+                const uint64_t m = ballot(absorbed_n > 0);
+                (void)m;
+                // absorbed count: sum over the wave
+                int tot = absorbed_n;
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off);
+                if (lane == 0 && tot) atomicAdd(&sstat[ST_ABS0 + s], (unsigned long long)tot);
             }
+            // this step's collision candidates -> block-local list (LDS), one
+            // global reservation per block at the end
+            const int nc = __popc(cand_bits);
+            int pre = nc;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const int v = __shfl_up(pre, off);
+                if (lane >= off) pre += v;
+            }
+            const int wtot = __shfl(pre, 63);
+            int slot0 = 0;
+            if (wtot) {
+                if (lane == 63) slot0 = atomicAdd(&s_ncand, wtot);
+                slot0 = __shfl(slot0, 63);
+            }
+            int slot = slot0 + pre - nc;
+#pragma unroll
+            for (int k = 0; k < RUN; ++k) {
+                if (!(cand_bits >> k & 1u)) continue;
+                if (slot < CAND_LDS) {
+                    s_cand[slot] = (int32_t)(q0 + k);
+                } else {
+                    const int gs = atomicAdd(a.q.count, 1);
+                    if (gs < a.q.cap)
+                        a.q.idx[gs] = (int32_t)(q0 + k);
+                    else
+                        atomicOr(a.err, (int)ERR_QUEUE_OVERFLOW);
+                }
+                ++slot;
+            }
+        }
+        if constexpr (DEPQ)
+            deposit4<T>(keyQ >= 0, keyQ, aQ[0], aQ[1], aQ[2], aQ[3], winQ, base, a.accQ, g.nr1, a.sc.qscale, sstat);
+        if constexpr (PUSH) {
+            st4(a.p.cell + q0, cell);
+            st4(a.p.dr + q0, dr);
+            st4(a.p.dz + q0, dz);
+            st4(a.p.vr + q0, vr);
+            st4(a.p.vt + q0, vt);
+            st4(a.p.vz + q0, vz);
         }
     }
     __syncthreads();
