@@ -134,8 +134,8 @@ typedef struct pic_stats {
     double wk[16];           /* open-period trapezoid sums of V dQ (first 16 turns) */
     double qk[16];           /* Q_k of the last Poisson solve (C) */
     /* HIP-event timing since pic_timing(ctx, 1) (milliseconds, launches) */
-    double pass_ms;          /* particle pass of both species (pic_gather_push's main launches) */
-    int64_t pass_count;
+    double pass_ms;          /* particle pass, summed over launches (one launch per species and step) */
+    int64_t pass_count;      /* launches timed */
     double poisson_ms;       /* whole poisson_solve_rz */
     int64_t poisson_count;
     double sort_ms;          /* cell sorts of both species */

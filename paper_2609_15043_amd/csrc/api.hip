@@ -643,10 +643,12 @@ template <typename T> static void stage(pic_ctx &c, int64_t n)
 
 template <typename T> static void run_pass(pic_ctx &c, int64_t n, bool push, bool depq)
 {
-    const bool timed = push;
-    if (timed) timer_start(c, c.t_pass);
-    for (int s = 0; s < 2; ++s) launch_pass<T>(pass_args<T>(c, s, n), c.cfg.capacity[s], push, depq, c.stream);
-    if (timed) timer_stop(c, c.t_pass);
+    const bool timed = push;   // one timer pair per species launch
+    for (int s = 0; s < 2; ++s) {
+        if (timed) timer_start(c, c.t_pass);
+        launch_pass<T>(pass_args<T>(c, s, n), c.cfg.capacity[s], push, depq, c.stream);
+        if (timed) timer_stop(c, c.t_pass);
+    }
 }
 
 template <typename T> static void run_collide(pic_ctx &c, int64_t n)
