@@ -163,7 +163,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the particle "
-              "decomposition across GPUs is described in DESIGN.md but not built.", file=sys.stderr)
+              "decomposition across GPUs is a design, not built.", file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():

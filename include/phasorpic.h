@@ -52,6 +52,9 @@ enum {
 };
 
 enum { PIC_FP64 = 0, PIC_MIXED = 1 };
+enum { PIC_FIELD_FULL = 0, PIC_FIELD_MQS = 1 };   /* inductive operator with / without displacement term */
+enum { PIC_RRF_GIVEN = 0, PIC_RRF_SKIN = 1 };     /* turn RF resistance: given / round-wire skin model */
+#define PIC_MAX_TURNS 16
 
 /* grids readable with pic_get_grid (all FP64 node arrays) */
 enum {
@@ -63,7 +66,12 @@ enum {
     PIC_GRID_ETHETA = 5,   /* staged E_theta(t_n) (V/m) */
     PIC_GRID_SURFACE = 6,  /* accumulated window surface charge (C) */
     PIC_GRID_JC = 7,       /* running sum of I^n cos(theta_n) of the open period */
-    PIC_GRID_JS = 8        /* running sum of I^n sin(theta_n) of the open period */
+    PIC_GRID_JS = 8,       /* running sum of I^n sin(theta_n) of the open period */
+    PIC_GRID_EC = 9,       /* E_c of the applied azimuthal field (V/m) */
+    PIC_GRID_ES = 10,      /* stored sine array E_s^sto = -E_s of the applied field (V/m) */
+    PIC_GRID_EC_PLASMA = 11,  /* plasma-only E_c^p of the last circuit update */
+    PIC_GRID_ES_PLASMA = 12,  /* plasma-only E_s^sto,p of the last circuit update */
+    PIC_GRID_UNIT = 16     /* + k: unit-current field U_k of turn k+1 (V/m per A) */
 };
 
 typedef struct pic_config {
@@ -101,11 +109,35 @@ typedef struct pic_config {
     const double *turn_vc;   /* nturns: V_c,k of the turn potentials (V) */
     const double *turn_vs;   /* nturns: V_s,k */
     /* Poisson multigrid and scheduling */
-    double mg_rtol;          /* residual tolerance relative to the equation's scale */
+    double mg_rtol;          /* residual tolerance relative to the equation's scale: the largest
+                                over free nodes of max(|b_n|, sum_m |A_nm x_m|) for the start
+                                value x (Dirichlet values included) */
     int32_t mg_max_cycles;   /* V-cycles per solve at most */
     int32_t sort_every;      /* steps between cell sorts of the particle arrays (>= 1) */
     int32_t load;            /* 1: load the initial uniform Maxwellian plasma */
     int32_t birth_capacity;  /* ionization events buffered per step */
+    /* field-circuit coupling (Secs. 2.2 and 2.4).  circuit == 0 keeps the
+     * prescribed ec / es_sto / turn_vc / turn_vs; circuit == 1 derives them
+     * from the unit-current fields and the network, and updates them at
+     * every closed period.  Turn k's nodes (tag k) are its source region
+     * Omega_k for the inductive solve and its Dirichlet conductor for the
+     * Poisson solve. */
+    int32_t circuit;
+    int32_t field_mode;      /* PIC_FIELD_FULL or PIC_FIELD_MQS */
+    double mu0;              /* vacuum permeability used by the inductive operator */
+    const double *turn_sign; /* s_k (+1 or -1), nturns; NULL = +1 */
+    double r_g, r_m, l_m, c_m;   /* generator R, series matching R, L, C (c_m <= 0: no capacitor) */
+    const double *c_stray;   /* out-of-domain shunt capacitance per node (F), nturns; NULL = 0 */
+    int32_t rrf_mode;        /* PIC_RRF_GIVEN (r_rf) or PIC_RRF_SKIN (Eq. skin) */
+    const double *r_rf;      /* nturns (ohm), rrf_mode == PIC_RRF_GIVEN */
+    double rho20, alpha_cu, temp_c;   /* copper resistivity at 20 C, its coefficient, temperature (C) */
+    double vg_amp, vg_phase; /* Thevenin peak amplitude (V) and phase (rad) */
+    int32_t vg_from_target;  /* 1: start from the amplitude that puts p_target into the vacuum network */
+    int32_t controller;      /* 1: closed-loop power control (Eqs. pfilter, ptrend, pcontrol) */
+    double p_target, gamma, n_trend, eps_p, alpha_v, f_step, v_min, v_max;
+    double alpha;            /* state relaxation, 0 < alpha <= 1 (Eq. relaxation) */
+    double helm_rtol;        /* inductive solves: residual tolerance relative to the equation's scale */
+    int32_t helm_max_cycles; /* ... and their iteration limit */
 } pic_config;
 
 typedef struct pic_solve_info {
@@ -140,6 +172,8 @@ typedef struct pic_stats {
     int64_t poisson_count;
     double sort_ms;          /* cell sorts of both species */
     int64_t sort_count;
+    double circuit_ms;       /* circuit_period_update's device work */
+    int64_t circuit_count;
     int64_t mg_cycles;       /* V-cycles of the last solve */
     double mg_rel;           /* its final relative residual */
 } pic_stats;
@@ -203,7 +237,11 @@ pic_status poisson_solve_rz(pic_ctx *ctx, int64_t n, double rtol, int32_t max_cy
  * pic_gather_push(n); calling it twice for one step is PIC_ESTATE. */
 pic_status harmonic_accumulate(pic_ctx *ctx, int64_t n);
 
-/* Closed-period report (Eqs. fourier, icap, pind, pcap, pcap_phasor). */
+/* Closed-period report (Eqs. fourier, icap, pind, pcap, pcap_phasor) and,
+ * with cfg->circuit, the circuit update (Eqs. vpind, pport, pbalance,
+ * power_imbalance, pcontrol, blockmatrix, relaxation, kclres, kvlres).
+ * Phasors are peak values under Re[x exp(+i w t)]; x = (I_f, I_1..I_N,
+ * V_1..V_N). */
 typedef struct pic_period_report {
     int32_t accepted;        /* 0: sample count != N_RF, nothing changed */
     int32_t samples;
@@ -212,18 +250,56 @@ typedef struct pic_period_report {
     double p_cap_ph;         /* W, phasor cross-check */
     double qc[16], qs[16];   /* charge harmonics Q_c,k, Q_s,k */
     double icap_re[16], icap_im[16];  /* I_cap,k = w Q_s,k + i w Q_c,k */
+    /* circuit update (cfg->circuit != 0) */
+    double p_port;           /* 1/2 Re(V_1 conj(I_f)) of the completed period's state */
+    double p_cu;             /* copper loss of that state */
+    double eps_bal;          /* |P_port - (P_ind + P_cap + P_Cu)| / |P_port| */
+    double kcl, kvl;         /* max residuals of the new state, / |I_f| and / |V_g| */
+    double vg_old, vg_amp;   /* Thevenin amplitude before / after the controller */
+    double pf, pc;           /* filtered and trend-extrapolated power (controller on) */
+    double vp_re[16], vp_im[16];      /* plasma reaction voltages V_p,k */
+    double xt_re[33], xt_im[33];      /* target network solution */
+    double x_re[33], x_im[33];        /* relaxed state applied in the next period */
+    int32_t helm_cycles[2];  /* CG iterations of the two plasma-only inductive solves */
+    double helm_rel[2];      /* and their final relative residuals */
 } pic_period_report;
 
-/* Closes the RF period: synchronises, requires exactly N_RF samples
- * (otherwise PIC_EPHASE and the accumulators are kept), finalises the
- * harmonics and powers into *report, copies J_c, J_s (x 2/N_RF) into the
- * caller's host arrays jc, js when non-NULL, optionally installs the next
- * period's turn voltages (new_vc, new_vs, nturns each; NULL keeps them) and
- * azimuthal field (new_ec, new_es_sto node arrays; NULL keeps them), and
- * resets the accumulators. */
+/* Inductive-port data of a coupled context (pic_get_circuit). */
+typedef struct pic_circuit_info {
+    int32_t nturns;
+    double omega;
+    double zvac_im[16 * 16];  /* Im Z_vac,kl (row-major, stride 16); Re Z_vac = 0 */
+    double eps_rec;           /* reciprocity error of Z_vac (Eq. reciprocity) */
+    double r_rf[16];          /* turn RF resistances */
+    double zs_re, zs_im;      /* source + matching branch impedance */
+    double g[16];             /* shape-function value s_k / A_k of each turn (1/m^2) */
+    double area[16];          /* A_k = N_k dz dR */
+    double vg_amp, vg_phase;  /* current Thevenin amplitude and phase */
+    double x_re[33], x_im[33];  /* applied state */
+} pic_circuit_info;
+
+/* Closes the RF period: synchronises and requires phase closure and
+ * exactly N_RF samples (otherwise PIC_EPHASE: the update is rejected, the
+ * circuit state and fields stay as they are, and the accumulators restart
+ * empty).  Finalises the harmonics and powers into *report (nullable) and
+ * copies J_c, J_s (x 2/N_RF) into the caller's host arrays jc, js when
+ * non-NULL.  Without cfg->circuit it then optionally installs the next
+ * period's turn voltages (new_vc, new_vs, nturns each) and azimuthal field
+ * (new_ec, new_es_sto node arrays); NULL keeps them.  With cfg->circuit the
+ * new_* arguments must be NULL and the update of Sec. 2.4 runs on the
+ * device: two plasma-only inductive solves K E_c^p = J_s / V_node,
+ * K E_s^sto,p = J_c / V_node (Eq. helmholtz_two_real), V_p,k (Eq. vpind),
+ * I_cap,k (Eq. icap), the power controller, the (2N+1) complex network
+ * solve with partial pivoting, the relaxation, the residuals, and the next
+ * period's turn potentials and field (Eq. compose).  PIC_ENOTCONV if an
+ * inductive solve misses helm_rtol.  The accumulators are reset. */
 pic_status circuit_period_update(pic_ctx *ctx, const double *new_vc, const double *new_vs,
                                  const double *new_ec, const double *new_es_sto,
                                  pic_period_report *report, double *jc, double *js);
+
+/* Copy the inductive-port data and the applied circuit state of a coupled
+ * context (synchronising); PIC_EINVAL without cfg->circuit. */
+pic_status pic_get_circuit(pic_ctx *ctx, pic_circuit_info *info);
 
 /* Synchronise the stream and report any sticky device-side error. */
 pic_status pic_sync(pic_ctx *ctx);

@@ -17,8 +17,8 @@
  *     the caller passes the node values already rebuilt.
  *   - The particle modules themselves are inherited by the paper from earlier
  *     PIC/MCC work and not written out there (Sec. 2.1, first paragraph);
- *     the readings used here are the textbook ones listed in the design doc:
- *     volume (R^2-linear) radial weights, leapfrog/Boris kick, Cartesian
+ *     the readings used here are the textbook ones: volume (R^2-linear)
+ *     radial weights, leapfrog/Boris kick, Cartesian
  *     move + rotation back to (r, theta), null-collision MCC with Philox
  *     counters keyed by (particle id, step).
  */

@@ -5,8 +5,8 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 two meet only in ``paper_2609_15043_amd.workloads`` (input descriptions).
 
 Per step n (ordering of the paper's workflow, Sec. 2.5 and its algorithm
-figure; the particle modules are inherited by the paper and read as in
-DESIGN.md):
+figure; the particle modules are inherited by the paper and read in their
+textbook forms):
 
 1. E_r, E_z at nodes from phi^n by central differences (E_R = 0 on the axis,
    Eq. axis_electrostatic_bc); E_theta(t_n) = E_c cos th - E_s^sto sin th
@@ -440,6 +440,18 @@ class OraclePIC:
         shape = (wl.nz + 1, wl.nr + 1)
         self.shape = shape
         self.poisson = Poisson(wl.nr, wl.nz, wl.dr, wl.dz, wl.eps_cell, wl.node_tag, W.EPS0)
+        # applied turn potentials and azimuthal field: prescribed, or from the
+        # field-circuit coupling (oracle/circuit.py)
+        self.fc = None
+        self.last_report = None
+        if wl.circuit is not None:
+            from .circuit import FieldCircuit
+            self.fc = FieldCircuit(wl.nr, wl.nz, wl.dr, wl.dz, wl.node_tag, wl.eps_cell, wl.freq, W.EPS0,
+                                   wl.circuit)
+            self.vc, self.vs, self.ec, self.es = self.fc.turn_vc, self.fc.turn_vs, self.fc.Ec, self.fc.Es
+        else:
+            self.vc, self.vs = np.asarray(wl.turn_vc, np.float64), np.asarray(wl.turn_vs, np.float64)
+            self.ec, self.es = np.asarray(wl.ec, np.float64), np.asarray(wl.es_sto, np.float64)
         self.surf = np.zeros(shape)
         self.parts = [load_species(wl, s, self.lq[s]) if load else Particles(0) for s in range(2)]
         self.next_id = [wl.np_init[0], wl.np_init[1]]
@@ -454,11 +466,11 @@ class OraclePIC:
     # -- fields -----------------------------------------------------------
     def turn_phi(self, n):
         th = theta(n, self.nrf)
-        return self.wl.turn_vc * math.cos(th) + self.wl.turn_vs * math.sin(th)
+        return self.vc * math.cos(th) + self.vs * math.sin(th)
 
     def etheta(self, n):
         th = theta(n, self.nrf)
-        return self.wl.ec * math.cos(th) - self.wl.es_sto * math.sin(th)
+        return self.ec * math.cos(th) - self.es * math.sin(th)
 
     # -- particle operations ------------------------------------------------
     def gather_push(self, n):
@@ -529,6 +541,22 @@ class OraclePIC:
     def harmonic(self, n):
         self.harm.add(n, self.I, self.etheta(n), self.Qk, self.turn_phi(n))
 
+    def period_update(self):
+        """Close the RF period: finalise the harmonics and, when coupled,
+        update the circuit and the next period's turn potentials and field.
+        Returns the report (None and restart of the accumulators when the
+        sample count is not N_RF)."""
+        r = self.harm.finalize(self.vc, self.vs)
+        self.reset_harmonics()
+        if r is None:
+            return None
+        if self.fc is not None:
+            rep = self.fc.update(r)
+            self.vc, self.vs, self.ec, self.es = self.fc.turn_vc, self.fc.turn_vs, self.fc.Ec, self.fc.Es
+            r = {**r, **rep}
+        self.last_report = r
+        return r
+
     # -- one whole step -----------------------------------------------------------
     def step(self):
         n = self.n
@@ -536,6 +564,8 @@ class OraclePIC:
         self.harmonic(n)
         self.mcc(n)
         self.Q = self.deposit()
+        if self.fc is not None and (n + 1) % self.nrf == 0:
+            self.period_update()
         self.solve(n + 1)
         self.n = n + 1
         for P in self.parts:

@@ -4,7 +4,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["api.hip", "particles.hip", "fields.hip"]
+SOURCES = ["api.hip", "particles.hip", "fields.hip", "circuit.hip"]
 LIB = os.path.join(HERE, "libphasorpic.so")
 
 
@@ -19,7 +19,7 @@ def build(verbose=False, arch="gfx950"):
     csrc = os.path.join(HERE, "csrc")
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={arch}", "-O3", "-std=c++17", "-fPIC", "-shared",
-           # packed FP32 instructions stay off (traps)
+           # no packed FP32 (v_pk_*_f32) instructions in the generated code
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            # every atomic in these kernels is already issued by one lane per
            # wave after an explicit wave reduction; the compiler's own

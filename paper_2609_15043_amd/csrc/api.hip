@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -134,6 +135,22 @@ struct pic_ctx {
     double *fc = nullptr, *Qk = nullptr;
     int nfaces = 0;
 
+    // field-circuit coupling
+    MGLevels hlv{};               // inductive-operator hierarchy (level work arrays shared with lv)
+    MGState *hgs = nullptr;
+    int32_t *htag = nullptr;      // inductive Dirichlet structure as a tag array: 0 fixed at 0, -1 free
+    double *U = nullptr;          // unit-current fields, nturns * nodes
+    double *Ep = nullptr;         // plasma-only E_c^p and E_s^sto,p (2 * nodes)
+    double *hb = nullptr;         // right-hand side of an inductive solve
+    CircuitDev *cd = nullptr;     // device circuit state (also the period finalisation)
+    CircuitDev cdh{};             // host copy after the last update
+    int32_t *plist = nullptr, *pturn = nullptr;   // turn nodes in node order, their turn index
+    double *gval = nullptr;       // s_k / A_k
+    int nlist = 0;
+    std::vector<double> area;
+    int helm_cycles[2]{};
+    double helm_rel[2]{};
+
     // HIP-event timing: ring of (start, stop) pairs per timed region
     struct Timer {
         static constexpr int RING = 64;
@@ -143,7 +160,7 @@ struct pic_ctx {
         int64_t count = 0;
     };
     bool timing = false;
-    Timer t_pass, t_poisson, t_sort;
+    Timer t_pass, t_poisson, t_sort, t_circuit;
 
     // constants
     SpeciesC sc[2]{};
@@ -514,6 +531,35 @@ static void layout(pic_ctx &c, Carver &cv)
     c.fk = cv.take<int32_t>(fmax);
     c.fc = cv.take<double>(fmax);
     c.Qk = cv.take<double>(MAX_TURNS);
+    c.cd = cv.take<CircuitDev>(1);
+    c.gval = cv.take<double>(MAX_TURNS);
+    c.plist = cv.take<int32_t>(nturn_nodes + 1);
+    c.pturn = cv.take<int32_t>(nturn_nodes + 1);
+    if (f.circuit) {
+        c.hgs = cv.take<MGState>(1);
+        c.htag = cv.take<int32_t>(nodes);
+        c.U = cv.take<double>((size_t)f.nturns * nodes);
+        c.Ep = cv.take<double>(2 * (size_t)nodes);
+        c.hb = cv.take<double>(nodes);
+        c.hlv.n = nl;
+        for (int l = 0; l < nl; ++l) {
+            const MGLevel &P = c.lv.L[l];
+            MGLevel &L = c.hlv.L[l];
+            L = P;   // same geometry and work arrays, own operator
+            if (l == 0) {
+                L.cw = cv.take<double>(L.nodes);
+                L.ce = cv.take<double>(L.nodes);
+                L.cs = cv.take<double>(L.nodes);
+                L.cn = cv.take<double>(L.nodes);
+                L.cc = cv.take<double>(L.nodes);
+            } else {
+                L.a = cv.take<double>(9 * (size_t)L.nodes);
+            }
+            L.dir = cv.take<uint8_t>(L.nodes);
+        }
+        const MGLevel &Lc = c.hlv.L[nl - 1];
+        c.hlv.coarse_inv = cv.take<double>((size_t)Lc.nodes * Lc.nodes);
+    }
 }
 
 static pic_status check_config(const pic_config *f, pic_ctx *c)
@@ -531,7 +577,21 @@ static pic_status check_config(const pic_config *f, pic_ctx *c)
         if (!(f->m[s] > 0)) return fail(c, PIC_EINVAL, "mass must be positive");
     }
     if (f->nturns < 0 || f->nturns > MAX_TURNS) return fail(c, PIC_EINVAL, "nturns outside 0..%d", MAX_TURNS);
-    if (f->nturns > 0 && (!f->turn_vc || !f->turn_vs)) return fail(c, PIC_EINVAL, "turn voltages missing");
+    if (f->nturns > 0 && !f->circuit && (!f->turn_vc || !f->turn_vs))
+        return fail(c, PIC_EINVAL, "turn voltages missing");
+    if (f->circuit) {
+        if (f->nturns < 1) return fail(c, PIC_EINVAL, "circuit coupling needs at least one turn");
+        if (!(f->alpha > 0.0 && f->alpha <= 1.0)) return fail(c, PIC_EINVAL, "relaxation alpha outside (0, 1]");
+        if (!(f->mu0 > 0.0) || !(f->eps0 > 0.0)) return fail(c, PIC_EINVAL, "mu0, eps0 must be positive");
+        if (f->field_mode != PIC_FIELD_FULL && f->field_mode != PIC_FIELD_MQS) return fail(c, PIC_EINVAL, "bad field_mode");
+        if (f->rrf_mode == PIC_RRF_GIVEN && !f->r_rf) return fail(c, PIC_EINVAL, "r_rf missing");
+        if (f->rrf_mode != PIC_RRF_GIVEN && f->rrf_mode != PIC_RRF_SKIN) return fail(c, PIC_EINVAL, "bad rrf_mode");
+        if (!(f->helm_rtol > 0.0) || f->helm_max_cycles < 1 || f->helm_max_cycles > MAX_CG)
+            return fail(c, PIC_EINVAL, "helm_rtol > 0 and helm_max_cycles in 1..%d required", MAX_CG);
+        if (f->controller && !(f->p_target > 0.0 && f->v_min > 0.0 && f->v_max >= f->v_min && f->f_step >= 0.0))
+            return fail(c, PIC_EINVAL, "controller settings invalid");
+        if (f->vg_from_target && !(f->p_target > 0.0)) return fail(c, PIC_EINVAL, "p_target must be positive");
+    }
     if (!f->eps_cell || !f->node_tag) return fail(c, PIC_EINVAL, "eps_cell and node_tag are required");
     if (f->sort_every < 1) return fail(c, PIC_EINVAL, "sort_every must be >= 1");
     if (f->birth_capacity < 0) return fail(c, PIC_EINVAL, "birth_capacity < 0");
@@ -552,8 +612,8 @@ static pic_status prepare_host(pic_ctx &c, const pic_config *f)
     c.vc.assign(MAX_TURNS, 0.0);
     c.vs.assign(MAX_TURNS, 0.0);
     for (int k = 0; k < f->nturns; ++k) {
-        c.vc[k] = f->turn_vc[k];
-        c.vs[k] = f->turn_vs[k];
+        c.vc[k] = f->turn_vc ? f->turn_vc[k] : 0.0;
+        c.vs[k] = f->turn_vs ? f->turn_vs[k] : 0.0;
     }
     for (int n = 0; n < nodes; ++n)
         if (c.tag[n] > f->nturns || c.tag[n] < -1) return fail(&c, PIC_EINVAL, "node tag %d invalid", c.tag[n]);
@@ -672,23 +732,35 @@ static void finalize_charge(pic_ctx &c)
 
 // V-cycle on the correction: two red-black sweeps on the 5-point fine
 // level, one four-colour sweep on the Galerkin levels, exact coarsest solve.
-static void vcycle(pic_ctx &c)
+static void vcycle(pic_ctx &c, const MGLevels &lv, const MGState *st)
 {
     for (int l = 0; l < c.lb; ++l) {
-        const int nc = c.lv.L[l].nine ? 4 : 2;
+        const int nc = lv.L[l].nine ? 4 : 2;
         const int nu = l == 0 ? 2 : 1;
         for (int k = 0; k < nu; ++k)
-            for (int col = 0; col < nc; ++col) launch_mg_smooth(c.lv.L[l], col, c.mgs, c.stream);
-        launch_mg_restrict(c.lv.L[l], c.lv.L[l + 1], c.mgs, c.stream);
+            for (int col = 0; col < nc; ++col) launch_mg_smooth(lv.L[l], col, st, c.stream);
+        launch_mg_restrict(lv.L[l], lv.L[l + 1], st, c.stream);
     }
-    launch_mg_bottom(c.lv, c.lb, c.lb == 0 ? 2 : 1, c.lb == 0 ? 2 : 1, c.mgs, c.stream);
+    launch_mg_bottom(lv, c.lb, c.lb == 0 ? 2 : 1, c.lb == 0 ? 2 : 1, st, c.stream);
     for (int l = c.lb - 1; l >= 0; --l) {
-        launch_mg_prolong(c.lv.L[l], c.lv.L[l + 1], c.mgs, c.stream);
-        const int nc = c.lv.L[l].nine ? 4 : 2;
+        launch_mg_prolong(lv.L[l], lv.L[l + 1], st, c.stream);
+        const int nc = lv.L[l].nine ? 4 : 2;
         const int nu = l == 0 ? 2 : 1;
         for (int k = 0; k < nu; ++k)
-            for (int col = nc - 1; col >= 0; --col) launch_mg_smooth(c.lv.L[l], col, c.mgs, c.stream);
+            for (int col = nc - 1; col >= 0; --col) launch_mg_smooth(lv.L[l], col, st, c.stream);
     }
+}
+
+// one preconditioned-CG iteration (no-ops once st->done)
+static void pcg_iteration(pic_ctx &c, const MGLevels &lv, MGState *st, const PCGVec &v, double rtol)
+{
+    const MGLevel &L0 = lv.L[0];
+    vcycle(c, lv, st);
+    launch_pcg_rz(L0, v, st, c.mgpartial, c.stream);
+    launch_pcg_p(L0, v, st, c.mgpartial, c.stream);
+    launch_pcg_matvec(L0, v, st, c.mgpartial, c.stream);
+    launch_pcg_update(L0, v, st, c.mgpartial, c.stream);
+    launch_pcg_check(st, c.mgpartial, pcg_blocks(L0.nodes), rtol, false, c.stream);
 }
 
 // Preconditioned CG on the free nodes (x = phi, b = node charge), one
@@ -726,14 +798,7 @@ static pic_status solve(pic_ctx &c, int64_t n, double rtol, int max_cycles, pic_
     budget = std::min(budget, MAX_CG);
     launch_pcg_resid(L0, v, c.mgpartial, c.stream);
     launch_pcg_check(c.mgs, c.mgpartial, np, rtol, true, c.stream);
-    for (int k = 0; k < budget; ++k) {
-        vcycle(c);
-        launch_pcg_rz(L0, v, c.mgs, c.mgpartial, c.stream);
-        launch_pcg_p(L0, v, c.mgs, c.mgpartial, c.stream);
-        launch_pcg_matvec(L0, v, c.mgs, c.mgpartial, c.stream);
-        launch_pcg_update(L0, v, c.mgs, c.mgpartial, c.stream);
-        launch_pcg_check(c.mgs, c.mgpartial, np, rtol, false, c.stream);
-    }
+    for (int k = 0; k < budget; ++k) pcg_iteration(c, c.lv, c.mgs, v, rtol);
     if (c.cfg.nturns > 0)
         launch_face_charge(c.phi, c.fp, c.fq, c.fk, c.fc, c.nfaces, c.Qk, c.cfg.nturns, c.stream);
     timer_stop(c, c.t_poisson);
@@ -751,6 +816,258 @@ static pic_status solve(pic_ctx &c, int64_t n, double rtol, int max_cycles, pic_
         if (!s.done) return fail(&c, PIC_ENOTCONV, "multigrid-CG: rel residual %.3e after %d iterations", s.rel,
                                  s.cycles);
     }
+    return PIC_OK;
+}
+
+// Multigrid hierarchy of a level-0 five-point operator (co) with Dirichlet
+// mask dir: level-0 coefficients, Galerkin coarse levels and the dense
+// inverse of the coarsest level, all copied into lv's device arrays.
+static pic_status build_levels(pic_ctx &c, MGLevels &lv, const Coeffs &co, const std::vector<uint8_t> &dir)
+{
+    const pic_config &f = c.cfg;
+    const int nodes = c.g.nodes;
+    MGLevel &L0 = lv.L[0];
+    const size_t nb = (size_t)nodes * sizeof(double);
+    HIPCHK(&c, cpy(c.stream, (void *)L0.cw, co.cw.data(), nb, hipMemcpyHostToDevice));
+    HIPCHK(&c, cpy(c.stream, (void *)L0.ce, co.ce.data(), nb, hipMemcpyHostToDevice));
+    HIPCHK(&c, cpy(c.stream, (void *)L0.cs, co.cs.data(), nb, hipMemcpyHostToDevice));
+    HIPCHK(&c, cpy(c.stream, (void *)L0.cn, co.cn.data(), nb, hipMemcpyHostToDevice));
+    HIPCHK(&c, cpy(c.stream, (void *)L0.cc, co.cc.data(), nb, hipMemcpyHostToDevice));
+    HIPCHK(&c, cpy(c.stream, (void *)L0.dir, dir.data(), nodes, hipMemcpyHostToDevice));
+    Stencil9 S;
+    S.nr = f.nr;
+    S.nz = f.nz;
+    S.dir = dir;
+    S.a.assign(9 * (size_t)nodes, 0.0);
+    for (int n = 0; n < nodes; ++n) {
+        S.a[(size_t)4 * nodes + n] = co.cc[n];
+        S.a[(size_t)3 * nodes + n] = -co.cw[n];
+        S.a[(size_t)5 * nodes + n] = -co.ce[n];
+        S.a[(size_t)1 * nodes + n] = -co.cs[n];
+        S.a[(size_t)7 * nodes + n] = -co.cn[n];
+    }
+    for (int l = 1; l < lv.n; ++l) {
+        S = galerkin(S);
+        MGLevel &L = lv.L[l];
+        HIPCHK(&c, cpy(c.stream, (void *)L.a, S.a.data(), S.a.size() * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHK(&c, cpy(c.stream, (void *)L.dir, S.dir.data(), S.dir.size(), hipMemcpyHostToDevice));
+        HIPCHK(&c, mset(c.stream, L.phi, 0, (size_t)L.nodes * sizeof(double)));
+        HIPCHK(&c, mset(c.stream, L.rhs, 0, (size_t)L.nodes * sizeof(double)));
+    }
+    // dense inverse of the coarsest level (Gauss-Jordan, partial pivoting); rows and
+    // columns of its Dirichlet nodes are zero so their correction stays 0
+    {
+        const int m = (S.nz + 1) * (S.nr + 1), nr1 = S.nr + 1;
+        std::vector<double> A((size_t)m * m, 0.0), Inv((size_t)m * m, 0.0);
+        for (int n = 0; n < m; ++n) {
+            const int i = n / nr1, j = n - i * nr1;
+            for (int k = 0; k < 9; ++k) {
+                const int di = k / 3 - 1, dj = k % 3 - 1;
+                if (i + di < 0 || i + di > S.nz || j + dj < 0 || j + dj > S.nr) continue;
+                A[(size_t)n * m + (n + di * nr1 + dj)] = S.a[(size_t)k * m + n];
+            }
+            Inv[(size_t)n * m + n] = 1.0;
+        }
+        for (int col = 0; col < m; ++col) {
+            int piv = col;
+            for (int r = col + 1; r < m; ++r)
+                if (std::fabs(A[(size_t)r * m + col]) > std::fabs(A[(size_t)piv * m + col])) piv = r;
+            if (A[(size_t)piv * m + col] == 0.0) return fail(&c, PIC_EINVAL, "singular coarsest multigrid level");
+            if (piv != col)
+                for (int k = 0; k < m; ++k) {
+                    std::swap(A[(size_t)piv * m + k], A[(size_t)col * m + k]);
+                    std::swap(Inv[(size_t)piv * m + k], Inv[(size_t)col * m + k]);
+                }
+            const double d = A[(size_t)col * m + col];
+            for (int k = 0; k < m; ++k) {
+                A[(size_t)col * m + k] /= d;
+                Inv[(size_t)col * m + k] /= d;
+            }
+            for (int r = 0; r < m; ++r) {
+                if (r == col) continue;
+                const double f2 = A[(size_t)r * m + col];
+                if (f2 == 0.0) continue;
+                for (int k = 0; k < m; ++k) {
+                    A[(size_t)r * m + k] -= f2 * A[(size_t)col * m + k];
+                    Inv[(size_t)r * m + k] -= f2 * Inv[(size_t)col * m + k];
+                }
+            }
+        }
+        for (int n = 0; n < m; ++n)
+            if (S.dir[n])
+                for (int k = 0; k < m; ++k) Inv[(size_t)n * m + k] = Inv[(size_t)k * m + n] = 0.0;
+        HIPCHK(&c, cpy(c.stream, (void *)lv.coarse_inv, Inv.data(), Inv.size() * sizeof(double),
+                       hipMemcpyHostToDevice));
+    }
+    return PIC_OK;
+}
+
+// K u = src for one inductive field x (free nodes), b = -mu0 w R src in
+// hb: CG on the R-weighted symmetric operator with multigrid preconditioning,
+// in chunks of iterations with a convergence check between chunks.
+static pic_status helm_solve(pic_ctx &c, double *x, int *cycles, double *rel)
+{
+    const MGLevel &L0 = c.hlv.L[0];
+    const PCGVec v{x, c.hb, c.pr, c.pz, c.pp, c.pAp};
+    const double rtol = c.cfg.helm_rtol;
+    const int maxc = std::min(c.cfg.helm_max_cycles, MAX_CG);
+    launch_pcg_begin(L0, v, c.htag, nullptr, nullptr, 0.0, 0.0, c.hgs, nullptr, false, c.stream);
+    launch_pcg_resid(L0, v, c.mgpartial, c.stream);
+    launch_pcg_check(c.hgs, c.mgpartial, pcg_blocks(L0.nodes), rtol, true, c.stream);
+    MGState s{};
+    int run = 0;
+    for (;;) {
+        HIPCHK(&c, cpy(c.stream, &s, c.hgs, sizeof s, hipMemcpyDeviceToHost));
+        if (s.done || run >= maxc) break;
+        const int chunk = std::min(run == 0 ? 4 : 8, maxc - run);
+        for (int k = 0; k < chunk; ++k) pcg_iteration(c, c.hlv, c.hgs, v, rtol);
+        run += chunk;
+    }
+    if (cycles) *cycles = s.cycles;
+    if (rel) *rel = s.rel;
+    if (!s.done)
+        return fail(&c, PIC_ENOTCONV, "inductive solve: rel residual %.3e after %d iterations", s.rel, s.cycles);
+    return PIC_OK;
+}
+
+// Five-point inductive operator in R-weighted symmetric form (see
+// circuit.hip): Dirichlet on the axis, the outer boundary and metal
+// (tag 0); turn nodes are free source nodes.
+static void helm_operator(const pic_ctx &c, Coeffs &co, std::vector<uint8_t> &dir)
+{
+    const pic_config &f = c.cfg;
+    const int nr = f.nr, nz = f.nz, nr1 = nr + 1, nodes = (nz + 1) * nr1;
+    const double dr = c.g.dr, dz = c.g.dz, w = TWO_PI * f.freq;
+    co.cw.assign(nodes, 0.0);
+    co.ce.assign(nodes, 0.0);
+    co.cs.assign(nodes, 0.0);
+    co.cn.assign(nodes, 0.0);
+    co.cc.assign(nodes, 1.0);
+    dir.assign(nodes, 1);
+    for (int i = 1; i < nz; ++i)
+        for (int j = 1; j < nr; ++j) {
+            const int n = i * nr1 + j;
+            if (c.tag[n] == 0) continue;
+            dir[n] = 0;
+            double k2 = 0.0;
+            if (f.field_mode == PIC_FIELD_FULL) {
+                // node permittivity: mean of the four cells touching the node
+                const double e = 0.25 * (c.eps_cell[(size_t)(i - 1) * nr + j - 1] + c.eps_cell[(size_t)(i - 1) * nr + j] +
+                                         c.eps_cell[(size_t)i * nr + j - 1] + c.eps_cell[(size_t)i * nr + j]);
+                k2 = f.mu0 * f.eps0 * e * w * w;
+            }
+            const double R = j * dr;
+            co.cc[n] = R * (2.0 / (dz * dz) + 2.0 / (dr * dr) + 1.0 / (R * R) - k2);
+            co.cs[n] = co.cn[n] = R / (dz * dz);
+            co.ce[n] = (R + 0.5 * dr) / (dr * dr);
+            co.cw[n] = (R - 0.5 * dr) / (dr * dr);
+        }
+}
+
+// Initialisation of the coupling (Sec. 2.2 and the workflow's
+// initialisation): shape functions, unit fields, Z_vac, network constants,
+// the first applied state, its turn potentials and azimuthal field.
+static pic_status circuit_init(pic_ctx &c)
+{
+    const pic_config &f = c.cfg;
+    const int N = f.nturns, nodes = c.g.nodes, nr1 = f.nr + 1;
+    const double w = TWO_PI * f.freq, dr = c.g.dr, dz = c.g.dz;
+    CircuitDev &h = c.cdh;
+    std::memset(&h, 0, sizeof h);
+    h.N = N;
+    h.nrf = c.nrf;
+    h.omega = w;
+    h.freq = f.freq;
+    // turn node list, shape functions g_k = s_k / A_k (Eq. shape)
+    std::vector<int32_t> list, lturn;
+    std::vector<int> count(N, 0);
+    std::vector<double> rsum(N, 0.0);
+    for (int n = 0; n < nodes; ++n)
+        if (c.tag[n] >= 1) {
+            list.push_back(n);
+            lturn.push_back(c.tag[n] - 1);
+            count[c.tag[n] - 1] += 1;
+            rsum[c.tag[n] - 1] += (n % nr1) * dr;
+        }
+    c.nlist = (int)list.size();
+    std::vector<double> g(MAX_TURNS, 0.0);
+    c.area.assign(N, 0.0);
+    for (int k = 0; k < N; ++k) {
+        if (count[k] == 0) return fail(&c, PIC_EINVAL, "turn %d has no nodes", k + 1);
+        const double s = f.turn_sign ? f.turn_sign[k] : 1.0;
+        if (s != 1.0 && s != -1.0) return fail(&c, PIC_EINVAL, "turn_sign[%d] must be +1 or -1", k);
+        c.area[k] = count[k] * dz * dr;
+        g[k] = s / c.area[k];
+        double norm = 0.0;
+        for (int e = 0; e < c.nlist; ++e)
+            if (lturn[e] == k) norm += g[k] * dz * dr;
+        if (std::fabs(norm - s) > 1e-12) return fail(&c, PIC_EINVAL, "turn %d: shape normalisation fails", k + 1);
+    }
+    if (c.nlist) {
+        HIPCHK(&c, cpy(c.stream, c.plist, list.data(), list.size() * 4, hipMemcpyHostToDevice));
+        HIPCHK(&c, cpy(c.stream, c.pturn, lturn.data(), lturn.size() * 4, hipMemcpyHostToDevice));
+    }
+    HIPCHK(&c, cpy(c.stream, c.gval, g.data(), MAX_TURNS * 8, hipMemcpyHostToDevice));
+    if (!f.circuit) {
+        HIPCHK(&c, cpy(c.stream, c.cd, &h, sizeof h, hipMemcpyHostToDevice));
+        return PIC_OK;
+    }
+    // network constants (Eqs. zsource, skin, zturn_field)
+    h.alpha = f.alpha;
+    h.zs_re = f.r_g + f.r_m;
+    h.zs_im = w * f.l_m - (f.c_m > 0.0 ? 1.0 / (w * f.c_m) : 0.0);
+    const double rho = f.rho20 * (1.0 + f.alpha_cu * (f.temp_c - 20.0));
+    const double delta = std::sqrt(2.0 * rho / (w * f.mu0));
+    for (int k = 0; k < N; ++k) {
+        if (f.rrf_mode == PIC_RRF_SKIN) {
+            const double rw = std::sqrt(c.area[k] / M_PI), rmean = rsum[k] / count[k];
+            const double inner = std::max(rw - delta, 0.0);
+            h.rrf[k] = rho * TWO_PI * rmean / (M_PI * (rw * rw - inner * inner));
+        } else {
+            h.rrf[k] = f.r_rf[k];
+        }
+        h.cstray[k] = f.c_stray ? f.c_stray[k] : 0.0;
+    }
+    h.controller = f.controller;
+    h.vg_from_target = f.vg_from_target;
+    h.p_target = f.p_target;
+    h.gamma = f.gamma;
+    h.n_trend = f.n_trend;
+    h.eps_p = f.eps_p;
+    h.alpha_v = f.alpha_v;
+    h.f_step = f.f_step;
+    h.v_min = f.v_min;
+    h.v_max = f.v_max;
+    h.vg_amp = f.vg_amp;
+    h.vg_phase = f.vg_phase;
+    HIPCHK(&c, cpy(c.stream, c.cd, &h, sizeof h, hipMemcpyHostToDevice));
+    // inductive operator hierarchy
+    Coeffs co;
+    std::vector<uint8_t> dir;
+    helm_operator(c, co, dir);
+    pic_status st = build_levels(c, c.hlv, co, dir);
+    if (st) return st;
+    std::vector<int32_t> htag(nodes);
+    for (int n = 0; n < nodes; ++n) htag[n] = dir[n] ? 0 : -1;
+    HIPCHK(&c, cpy(c.stream, c.htag, htag.data(), nodes * 4, hipMemcpyHostToDevice));
+    HIPCHK(&c, mset(c.stream, c.U, 0, (size_t)N * nodes * 8));
+    HIPCHK(&c, mset(c.stream, c.Ep, 0, 2 * (size_t)nodes * 8));
+    HIPCHK(&c, mset(c.stream, c.hgs, 0, sizeof(MGState)));
+    // unit-current fields K U_k = g_k (Eq. unitfield)
+    const double mw = f.mu0 * w;
+    for (int k = 0; k < N; ++k) {
+        launch_unit_rhs(c.d_tag, k, g[k], c.hlv.L[0].dir, mw, c.hb, c.g, c.stream);
+        st = helm_solve(c, c.U + (size_t)k * nodes, nullptr, nullptr);
+        if (st) return st;
+    }
+    // Z_vac (Eq. zvac), first state, turn potentials and field
+    launch_project(c.U, N, nodes, c.plist, c.pturn, c.nlist, c.gval, N,
+                   reinterpret_cast<double *>(reinterpret_cast<char *>(c.cd) + offsetof(CircuitDev, mvac)), MAX_TURNS,
+                   c.g, c.stream);
+    launch_circuit(c.cd, c.harm, c.d_vc, c.d_vs, 0, c.stream);
+    launch_compose(c.Ep, c.Ep + nodes, c.U, nodes, c.cd, c.d_ec, c.d_es, nodes, c.stream);
+    HIPCHK(&c, cpy(c.stream, &h, c.cd, sizeof h, hipMemcpyDeviceToHost));
+    if (h.singular) return fail(&c, PIC_EINVAL, "singular circuit network");
     return PIC_OK;
 }
 
@@ -815,83 +1132,17 @@ template <typename T> static pic_status init_impl(pic_ctx &c)
                 HIPCHK(&c, cpy(c.stream, c.fc, hc.data(), hc.size() * 8, hipMemcpyHostToDevice));
             }
         }
-        MGLevel &L0 = c.lv.L[0];
-        const size_t nb = (size_t)nodes * sizeof(double);
-        HIPCHK(&c, cpy(c.stream, (void *)L0.cw, co.cw.data(), nb, hipMemcpyHostToDevice));
-        HIPCHK(&c, cpy(c.stream, (void *)L0.ce, co.ce.data(), nb, hipMemcpyHostToDevice));
-        HIPCHK(&c, cpy(c.stream, (void *)L0.cs, co.cs.data(), nb, hipMemcpyHostToDevice));
-        HIPCHK(&c, cpy(c.stream, (void *)L0.cn, co.cn.data(), nb, hipMemcpyHostToDevice));
-        HIPCHK(&c, cpy(c.stream, (void *)L0.cc, co.cc.data(), nb, hipMemcpyHostToDevice));
-        HIPCHK(&c, cpy(c.stream, (void *)L0.dir, dir.data(), nodes, hipMemcpyHostToDevice));
-        Stencil9 S;
-        S.nr = f.nr;
-        S.nz = f.nz;
-        S.dir = dir;
-        S.a.assign(9 * (size_t)nodes, 0.0);
-        for (int n = 0; n < nodes; ++n) {
-            S.a[(size_t)4 * nodes + n] = co.cc[n];
-            S.a[(size_t)3 * nodes + n] = -co.cw[n];
-            S.a[(size_t)5 * nodes + n] = -co.ce[n];
-            S.a[(size_t)1 * nodes + n] = -co.cs[n];
-            S.a[(size_t)7 * nodes + n] = -co.cn[n];
-        }
-        for (int l = 1; l < c.lv.n; ++l) {
-            S = galerkin(S);
-            MGLevel &L = c.lv.L[l];
-            HIPCHK(&c, cpy(c.stream, (void *)L.a, S.a.data(), S.a.size() * sizeof(double), hipMemcpyHostToDevice));
-            HIPCHK(&c, cpy(c.stream, (void *)L.dir, S.dir.data(), S.dir.size(), hipMemcpyHostToDevice));
-            HIPCHK(&c, mset(c.stream, L.phi, 0, (size_t)L.nodes * sizeof(double)));
-            HIPCHK(&c, mset(c.stream, L.rhs, 0, (size_t)L.nodes * sizeof(double)));
-        }
-        for (double *v : {c.pr, c.pz, c.pp, c.pAp, c.phi_prev}) HIPCHK(&c, mset(c.stream, v, 0, nb));
-        // dense inverse of the coarsest level (Gauss-Jordan, partial pivoting); rows and
-        // columns of its Dirichlet nodes are zero so their correction stays 0
-        {
-            const int m = (S.nz + 1) * (S.nr + 1), nr1 = S.nr + 1;
-            std::vector<double> A((size_t)m * m, 0.0), Inv((size_t)m * m, 0.0);
-            for (int n = 0; n < m; ++n) {
-                const int i = n / nr1, j = n - i * nr1;
-                for (int k = 0; k < 9; ++k) {
-                    const int di = k / 3 - 1, dj = k % 3 - 1;
-                    if (i + di < 0 || i + di > S.nz || j + dj < 0 || j + dj > S.nr) continue;
-                    A[(size_t)n * m + (n + di * nr1 + dj)] = S.a[(size_t)k * m + n];
-                }
-                Inv[(size_t)n * m + n] = 1.0;
-            }
-            for (int col = 0; col < m; ++col) {
-                int piv = col;
-                for (int r = col + 1; r < m; ++r)
-                    if (std::fabs(A[(size_t)r * m + col]) > std::fabs(A[(size_t)piv * m + col])) piv = r;
-                if (A[(size_t)piv * m + col] == 0.0) return fail(&c, PIC_EINVAL, "singular coarsest multigrid level");
-                if (piv != col)
-                    for (int k = 0; k < m; ++k) {
-                        std::swap(A[(size_t)piv * m + k], A[(size_t)col * m + k]);
-                        std::swap(Inv[(size_t)piv * m + k], Inv[(size_t)col * m + k]);
-                    }
-                const double d = A[(size_t)col * m + col];
-                for (int k = 0; k < m; ++k) {
-                    A[(size_t)col * m + k] /= d;
-                    Inv[(size_t)col * m + k] /= d;
-                }
-                for (int r = 0; r < m; ++r) {
-                    if (r == col) continue;
-                    const double f2 = A[(size_t)r * m + col];
-                    if (f2 == 0.0) continue;
-                    for (int k = 0; k < m; ++k) {
-                        A[(size_t)r * m + k] -= f2 * A[(size_t)col * m + k];
-                        Inv[(size_t)r * m + k] -= f2 * Inv[(size_t)col * m + k];
-                    }
-                }
-            }
-            for (int n = 0; n < m; ++n)
-                if (S.dir[n])
-                    for (int k = 0; k < m; ++k) Inv[(size_t)n * m + k] = Inv[(size_t)k * m + n] = 0.0;
-            HIPCHK(&c, cpy(c.stream, (void *)c.lv.coarse_inv, Inv.data(), Inv.size() * sizeof(double),
-                           hipMemcpyHostToDevice));
-        }
+        pic_status bs = build_levels(c, c.lv, co, dir);
+        if (bs) return bs;
+        for (double *v : {c.pr, c.pz, c.pp, c.pAp, c.phi_prev})
+            HIPCHK(&c, mset(c.stream, v, 0, (size_t)nodes * sizeof(double)));
     }
     c.lb = 0;
     while (c.lb < c.lv.n - 1 && c.lv.L[c.lb].nodes > 2200) ++c.lb;
+    {
+        pic_status cs = circuit_init(c);
+        if (cs) return cs;
+    }
 
     // fixed-point scales
     const double cells = (double)f.nr * f.ip;
@@ -1081,42 +1332,101 @@ extern "C" pic_status harmonic_accumulate(pic_ctx *c, int64_t n)
     return hipGetLastError() == hipSuccess ? PIC_OK : fail(c, PIC_EDEVICE, "kernel launch failed");
 }
 
+static pic_status reset_period(pic_ctx *c)
+{
+    const int nodes = c->g.nodes;
+    HIPCHK(c, mset(c->stream, c->Jc, 0, nodes * 8));
+    HIPCHK(c, mset(c->stream, c->Jcc, 0, nodes * 8));
+    HIPCHK(c, mset(c->stream, c->Js, 0, nodes * 8));
+    HIPCHK(c, mset(c->stream, c->Jsc, 0, nodes * 8));
+    HIPCHK(c, mset(c->stream, c->harm, 0, sizeof(HarmState)));
+    return PIC_OK;
+}
+
 extern "C" pic_status circuit_period_update(pic_ctx *c, const double *new_vc, const double *new_vs,
                                             const double *new_ec, const double *new_es, pic_period_report *rep,
                                             double *jc, double *js)
 {
     if (!c) return PIC_EINVAL;
+    const bool coupled = c->cfg.circuit != 0;
+    if (coupled && (new_vc || new_vs || new_ec || new_es))
+        return fail(c, PIC_EINVAL, "a coupled context derives turn potentials and field itself");
     pic_status st = sticky(c);
     if (st) return st;
-    HarmState h;
-    HIPCHK(c, cpy(c->stream, &h, c->harm, sizeof h, hipMemcpyDeviceToHost));
-    const int N = c->nrf, K = c->cfg.nturns;
+    int32_t samples = 0;
+    HIPCHK(c, cpy(c->stream, &samples, reinterpret_cast<char *>(c->harm) + offsetof(HarmState, samples), 4,
+                  hipMemcpyDeviceToHost));
+    const int N = c->nrf, K = c->cfg.nturns, nodes = c->g.nodes;
     if (rep) {
         std::memset(rep, 0, sizeof *rep);
-        rep->samples = h.samples;
+        rep->samples = samples;
     }
-    if (!c->closed) return fail(c, PIC_EPHASE, "phase closure |f dt N_RF - 1| >= 1e-10: period update rejected");
-    if (h.samples != N) return fail(c, PIC_EPHASE, "%d samples in the period, N_RF = %d: update rejected", h.samples, N);
-    const double w = TWO_PI * c->cfg.freq;
+    if (!c->closed || samples != N) {
+        st = reset_period(c);
+        if (st) return st;
+        if (!c->closed) return fail(c, PIC_EPHASE, "phase closure |f dt N_RF - 1| >= 1e-10: period update rejected");
+        return fail(c, PIC_EPHASE, "%d samples in the period, N_RF = %d: update rejected", samples, N);
+    }
+    timer_start(*c, c->t_circuit);
+    if (coupled) {
+        // plasma-only fields from the current harmonics (Eq. helmholtz_two_real)
+        const double mw = c->cfg.mu0 * TWO_PI * c->cfg.freq;
+        const uint8_t *hdir = c->hlv.L[0].dir;
+        launch_helm_rhs(c->Js, c->Jsc, 2.0 / N, hdir, mw, c->hb, c->g, c->stream);
+        st = helm_solve(*c, c->Ep, &c->helm_cycles[0], &c->helm_rel[0]);
+        if (st) return st;
+        launch_helm_rhs(c->Jc, c->Jcc, 2.0 / N, hdir, mw, c->hb, c->g, c->stream);
+        st = helm_solve(*c, c->Ep + nodes, &c->helm_cycles[1], &c->helm_rel[1]);
+        if (st) return st;
+        launch_project(c->Ep, 2, nodes, c->plist, c->pturn, c->nlist, c->gval, K,
+                       reinterpret_cast<double *>(reinterpret_cast<char *>(c->cd) + offsetof(CircuitDev, proj)), 2,
+                       c->g, c->stream);
+        launch_circuit(c->cd, c->harm, c->d_vc, c->d_vs, 1, c->stream);
+        launch_compose(c->Ep, c->Ep + nodes, c->U, nodes, c->cd, c->d_ec, c->d_es, nodes, c->stream);
+    } else {
+        launch_circuit(c->cd, c->harm, c->d_vc, c->d_vs, 2, c->stream);
+    }
+    timer_stop(*c, c->t_circuit);
+    CircuitDev &h = c->cdh;
+    HIPCHK(c, cpy(c->stream, &h, c->cd, sizeof h, hipMemcpyDeviceToHost));
+    if (coupled && h.singular) return fail(c, PIC_EDEVICE, "singular circuit network");
     if (rep) {
         rep->accepted = 1;
-        rep->p_ind = (h.pind + h.pind_c) / N;
-        double wsum = 0.0, pph = 0.0;
+        rep->p_ind = h.p_ind;
+        rep->p_cap = h.p_cap;
+        rep->p_cap_ph = h.p_cap_ph;
         for (int k = 0; k < K; ++k) {
-            const double Wk = (h.w[k] + h.w_c[k]) + 0.5 * (h.v_first[k] + h.v_prev[k]) * (h.q_first[k] - h.q_prev[k]);
-            wsum += Wk;
-            const double qc = 2.0 / N * (h.qc[k] + h.qc_c[k]), qs = 2.0 / N * (h.qs[k] + h.qs_c[k]);
-            rep->qc[k] = qc;
-            rep->qs[k] = qs;
-            rep->icap_re[k] = w * qs;
-            rep->icap_im[k] = w * qc;
-            // 1/2 Re( V conj(I) ), V = Vc - i Vs
-            pph += 0.5 * (c->vc[k] * rep->icap_re[k] - c->vs[k] * rep->icap_im[k]);
+            rep->qc[k] = h.qc[k];
+            rep->qs[k] = h.qs[k];
+            rep->icap_re[k] = h.icap_re[k];
+            rep->icap_im[k] = h.icap_im[k];
         }
-        rep->p_cap = c->cfg.freq * wsum;
-        rep->p_cap_ph = pph;
+        if (coupled) {
+            rep->p_port = h.p_port;
+            rep->p_cu = h.p_cu;
+            rep->eps_bal = h.eps_bal;
+            rep->kcl = h.kcl;
+            rep->kvl = h.kvl;
+            rep->vg_old = h.vg_old;
+            rep->vg_amp = h.vg_amp;
+            rep->pf = h.pf;
+            rep->pc = h.pc;
+            for (int k = 0; k < K; ++k) {
+                rep->vp_re[k] = h.vp_re[k];
+                rep->vp_im[k] = h.vp_im[k];
+            }
+            for (int r = 0; r < 2 * K + 1; ++r) {
+                rep->xt_re[r] = h.xt_re[r];
+                rep->xt_im[r] = h.xt_im[r];
+                rep->x_re[r] = h.x_re[r];
+                rep->x_im[r] = h.x_im[r];
+            }
+            for (int q = 0; q < 2; ++q) {
+                rep->helm_cycles[q] = c->helm_cycles[q];
+                rep->helm_rel[q] = c->helm_rel[q];
+            }
+        }
     }
-    const int nodes = c->g.nodes;
     if (jc || js) {
         std::vector<double> a(nodes), b(nodes);
         if (jc) {
@@ -1130,25 +1440,53 @@ extern "C" pic_status circuit_period_update(pic_ctx *c, const double *new_vc, co
             for (int n = 0; n < nodes; ++n) js[n] = 2.0 / N * (a[n] + b[n]);
         }
     }
-    if (new_vc)
-        for (int k = 0; k < K; ++k) c->vc[k] = new_vc[k];
-    if (new_vs)
-        for (int k = 0; k < K; ++k) c->vs[k] = new_vs[k];
-    HIPCHK(c, cpy(c->stream, c->d_vc, c->vc.data(), MAX_TURNS * 8, hipMemcpyHostToDevice));
-    HIPCHK(c, cpy(c->stream, c->d_vs, c->vs.data(), MAX_TURNS * 8, hipMemcpyHostToDevice));
-    if (new_ec) {
-        c->ec.assign(new_ec, new_ec + nodes);
-        HIPCHK(c, cpy(c->stream, c->d_ec, new_ec, nodes * 8, hipMemcpyHostToDevice));
+    if (!coupled) {
+        if (new_vc)
+            for (int k = 0; k < K; ++k) c->vc[k] = new_vc[k];
+        if (new_vs)
+            for (int k = 0; k < K; ++k) c->vs[k] = new_vs[k];
+        HIPCHK(c, cpy(c->stream, c->d_vc, c->vc.data(), MAX_TURNS * 8, hipMemcpyHostToDevice));
+        HIPCHK(c, cpy(c->stream, c->d_vs, c->vs.data(), MAX_TURNS * 8, hipMemcpyHostToDevice));
+        if (new_ec) {
+            c->ec.assign(new_ec, new_ec + nodes);
+            HIPCHK(c, cpy(c->stream, c->d_ec, new_ec, nodes * 8, hipMemcpyHostToDevice));
+        }
+        if (new_es) {
+            c->es.assign(new_es, new_es + nodes);
+            HIPCHK(c, cpy(c->stream, c->d_es, new_es, nodes * 8, hipMemcpyHostToDevice));
+        }
     }
-    if (new_es) {
-        c->es.assign(new_es, new_es + nodes);
-        HIPCHK(c, cpy(c->stream, c->d_es, new_es, nodes * 8, hipMemcpyHostToDevice));
+    return reset_period(c);
+}
+
+extern "C" pic_status pic_get_circuit(pic_ctx *c, pic_circuit_info *o)
+{
+    if (!c || !o) return PIC_EINVAL;
+    if (!c->cfg.circuit) return fail(c, PIC_EINVAL, "context without circuit coupling");
+    HIPCHK(c, cpy(c->stream, &c->cdh, c->cd, sizeof(CircuitDev), hipMemcpyDeviceToHost));
+    const CircuitDev &h = c->cdh;
+    std::memset(o, 0, sizeof *o);
+    const int K = c->cfg.nturns;
+    o->nturns = K;
+    o->omega = h.omega;
+    for (int k = 0; k < K; ++k)
+        for (int l = 0; l < K; ++l) o->zvac_im[k * 16 + l] = -h.mvac[k * MAX_TURNS + l];
+    o->eps_rec = h.eps_rec;
+    std::vector<double> g(MAX_TURNS);
+    HIPCHK(c, cpy(c->stream, g.data(), c->gval, MAX_TURNS * 8, hipMemcpyDeviceToHost));
+    for (int k = 0; k < K; ++k) {
+        o->r_rf[k] = h.rrf[k];
+        o->g[k] = g[k];
+        o->area[k] = c->area[k];
     }
-    HIPCHK(c, mset(c->stream, c->Jc, 0, nodes * 8));
-    HIPCHK(c, mset(c->stream, c->Jcc, 0, nodes * 8));
-    HIPCHK(c, mset(c->stream, c->Js, 0, nodes * 8));
-    HIPCHK(c, mset(c->stream, c->Jsc, 0, nodes * 8));
-    HIPCHK(c, mset(c->stream, c->harm, 0, sizeof(HarmState)));
+    o->zs_re = h.zs_re;
+    o->zs_im = h.zs_im;
+    o->vg_amp = h.vg_amp;
+    o->vg_phase = h.vg_phase;
+    for (int r = 0; r < 2 * K + 1; ++r) {
+        o->x_re[r] = h.x_re[r];
+        o->x_im[r] = h.x_im[r];
+    }
     return PIC_OK;
 }
 
@@ -1355,7 +1693,21 @@ extern "C" pic_status pic_get_grid(pic_ctx *c, int32_t which, double *out)
         for (int n = 0; n < nodes; ++n) out[n] = a[n] + b[n];
         break;
     }
-    default: return fail(c, PIC_EINVAL, "unknown grid %d", which);
+    case PIC_GRID_EC: HIPCHK(c, cpy(c->stream, out, c->d_ec, nodes * 8, hipMemcpyDeviceToHost)); break;
+    case PIC_GRID_ES: HIPCHK(c, cpy(c->stream, out, c->d_es, nodes * 8, hipMemcpyDeviceToHost)); break;
+    case PIC_GRID_EC_PLASMA:
+    case PIC_GRID_ES_PLASMA:
+        if (!c->cfg.circuit) return fail(c, PIC_EINVAL, "context without circuit coupling");
+        HIPCHK(c, cpy(c->stream, out, c->Ep + (which == PIC_GRID_ES_PLASMA ? nodes : 0), nodes * 8,
+                      hipMemcpyDeviceToHost));
+        break;
+    default:
+        if (which >= PIC_GRID_UNIT && which < PIC_GRID_UNIT + c->cfg.nturns && c->cfg.circuit) {
+            HIPCHK(c, cpy(c->stream, out, c->U + (size_t)(which - PIC_GRID_UNIT) * nodes, nodes * 8,
+                          hipMemcpyDeviceToHost));
+            break;
+        }
+        return fail(c, PIC_EINVAL, "unknown grid %d", which);
     }
     return PIC_OK;
 }
@@ -1364,7 +1716,7 @@ extern "C" pic_status pic_timing(pic_ctx *c, int32_t enable)
 {
     if (!c) return PIC_EINVAL;
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    for (auto *t : {&c->t_pass, &c->t_poisson, &c->t_sort}) {
+    for (auto *t : {&c->t_pass, &c->t_poisson, &c->t_sort, &c->t_circuit}) {
         timer_drain(*t);
         t->ms = 0.0;
         t->count = 0;
@@ -1378,13 +1730,15 @@ extern "C" pic_status pic_get_stats(pic_ctx *c, pic_stats *o)
     if (!c || !o) return PIC_EINVAL;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     std::memset(o, 0, sizeof *o);
-    for (auto *t : {&c->t_pass, &c->t_poisson, &c->t_sort}) timer_drain(*t);
+    for (auto *t : {&c->t_pass, &c->t_poisson, &c->t_sort, &c->t_circuit}) timer_drain(*t);
     o->pass_ms = c->t_pass.ms;
     o->pass_count = c->t_pass.count;
     o->poisson_ms = c->t_poisson.ms;
     o->poisson_count = c->t_poisson.count;
     o->sort_ms = c->t_sort.ms;
     o->sort_count = c->t_sort.count;
+    o->circuit_ms = c->t_circuit.ms;
+    o->circuit_count = c->t_circuit.count;
     {
         MGState ms;
         HIPCHK(c, cpy(c->stream, &ms, c->mgs, sizeof ms, hipMemcpyDeviceToHost));
@@ -1439,7 +1793,7 @@ extern "C" void pic_destroy(pic_ctx *c)
 {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
-    for (auto *t : {&c->t_pass, &c->t_poisson, &c->t_sort})
+    for (auto *t : {&c->t_pass, &c->t_poisson, &c->t_sort, &c->t_circuit})
         for (auto &e : t->ev)
             for (auto &x : e)
                 if (x) (void)hipEventDestroy(x);

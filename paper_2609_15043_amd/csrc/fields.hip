@@ -341,8 +341,8 @@ __device__ __forceinline__ double fold_partials(const double *part, int np, int 
 }
 
 // Dirichlet values (turn k nodes: phi_k(t_n)); free nodes start from the
-// linear extrapolation 2 phi^n - phi^{n-1} when `extrap` (prev keeps phi^n);
-// state reset.
+// linear extrapolation 2 phi^n - phi^{n-1} when `extrap` (prev, when given,
+// keeps phi^n); state reset.
 __global__ void k_pcg_begin(MGLevel L, PCGVec v, const int32_t *tag, const double *vc, const double *vs, double cs,
                             double sn, MGState *st, double *prev, int extrap)
 {
@@ -357,15 +357,27 @@ __global__ void k_pcg_begin(MGLevel L, PCGVec v, const int32_t *tag, const doubl
     const int k = tag[n];
     if (k >= 1) {
         v.x[n] = vc[k - 1] * cs + vs[k - 1] * sn;
-    } else if (k < 0) {
+    } else if (k < 0 && prev) {
         const double cur = v.x[n];
         if (extrap) v.x[n] = 2.0 * cur - prev[n];
         prev[n] = cur;
     }
 }
 
+// sum of |terms| of (A x)_n on the 5-point level: the size of the equation,
+// including the drive from Dirichlet neighbours
+__device__ __forceinline__ double apply_abs(const MGLevel &L, const double *x, int n, int i, int j)
+{
+    double a = fabs(L.cc[n] * x[n]);
+    if (j > 0) a += fabs(L.cw[n] * x[n - 1]);
+    if (j < L.nr) a += fabs(L.ce[n] * x[n + 1]);
+    if (i > 0) a += fabs(L.cs[n] * x[n - L.nr1]);
+    if (i < L.nz) a += fabs(L.cn[n] * x[n + L.nr1]);
+    return a;
+}
+
 // r = b - A x on free nodes (0 on Dirichlet), z = p = 0; partials of
-// max|r| and of the equation scale max(|b|, |cc x|)
+// max|r| and of the equation scale max(|b|, sum |A_nm x_m|)
 __global__ __launch_bounds__(256) void k_pcg_resid(MGLevel L, PCGVec v, double *partial)
 {
     double m0 = 0.0, m1 = 0.0;
@@ -380,7 +392,7 @@ __global__ __launch_bounds__(256) void k_pcg_resid(MGLevel L, PCGVec v, double *
         const double r = v.b[n] - apply_op(L, v.x, n, i, j);
         v.r[n] = r;
         m0 = fmax(m0, fabs(r));
-        m1 = fmax(m1, fmax(fabs(v.b[n]), fabs(L.cc[n] * v.x[n])));
+        m1 = fmax(m1, fmax(fabs(v.b[n]), apply_abs(L, v.x, n, i, j)));
     }
     block_partial(m0, partial + 2 * blockIdx.x, true);
     block_partial(m1, partial + 2 * blockIdx.x + 1, true);

@@ -151,4 +151,27 @@ struct HarmState {
     double v_first[MAX_TURNS], q_first[MAX_TURNS], v_prev[MAX_TURNS], q_prev[MAX_TURNS];
 };
 
+// Field-circuit coupling (device-resident; one update per closed period).
+// Turn currents and voltages are peak phasors under Re[x exp(+i w t)]; the
+// network unknowns are x = (I_f, I_1..I_N, V_1..V_N).
+constexpr int MAX_X = 2 * MAX_TURNS + 1;
+struct CircuitDev {
+    int32_t N, nrf, controller, vg_from_target;
+    int32_t have_pf, pad;
+    double omega, freq, alpha;
+    double zs_re, zs_im;                    // source + matching branch impedance
+    double rrf[MAX_TURNS], cstray[MAX_TURNS];
+    double mvac[MAX_TURNS * MAX_TURNS];     // sum g_k U_l dV; Z_vac = -i mvac
+    double p_target, gamma, n_trend, eps_p, alpha_v, f_step, v_min, v_max;
+    double vg_amp, vg_phase, pf_prev;
+    double x_re[MAX_X], x_im[MAX_X];        // applied state
+    double proj[2 * MAX_TURNS];             // sum g_k E_c^p dV, sum g_k E_s^sto,p dV
+    // results of the last update
+    double xt_re[MAX_X], xt_im[MAX_X];      // target state
+    double vp_re[MAX_TURNS], vp_im[MAX_TURNS];
+    double qc[MAX_TURNS], qs[MAX_TURNS], icap_re[MAX_TURNS], icap_im[MAX_TURNS], wk[MAX_TURNS];
+    double p_port, p_cu, p_ind, p_cap, p_cap_ph, eps_bal, kcl, kvl, eps_rec, pf, pc, vg_old;
+    int32_t samples, singular;
+};
+
 }  // namespace pic

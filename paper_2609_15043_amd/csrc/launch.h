@@ -60,6 +60,15 @@ void launch_pcg_rz(const MGLevel &L, const PCGVec &v, const MGState *st, double 
 void launch_pcg_p(const MGLevel &L, const PCGVec &v, MGState *st, const double *partial, hipStream_t s);
 void launch_pcg_matvec(const MGLevel &L, const PCGVec &v, const MGState *st, double *partial, hipStream_t s);
 void launch_pcg_update(const MGLevel &L, const PCGVec &v, const MGState *st, double *partial, hipStream_t s);
+void launch_helm_rhs(const double *acc, const double *comp, double scale, const uint8_t *dir, double mw, double *b,
+                     const GridC &g, hipStream_t s);
+void launch_unit_rhs(const int32_t *tag, int turn, double gval, const uint8_t *dir, double mw, double *b,
+                     const GridC &g, hipStream_t s);
+void launch_project(const double *fields, int nf, int64_t stride, const int32_t *list, const int32_t *lturn, int nlist,
+                    const double *gval, int nturns, double *out, int ostride, const GridC &g, hipStream_t s);
+void launch_circuit(CircuitDev *cd, const HarmState *h, double *vc, double *vs, int mode, hipStream_t s);
+void launch_compose(const double *ecp, const double *esp, const double *U, int64_t stride, const CircuitDev *cd,
+                    double *ec, double *es, int nodes, hipStream_t s);
 void launch_face_charge(const double *phi, const int32_t *fp, const int32_t *fq, const int32_t *fk, const double *fc,
                         int nfaces, double *Qk, int nturns, hipStream_t s);
 

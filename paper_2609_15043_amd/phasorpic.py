@@ -18,8 +18,12 @@ LIB_PATH = os.path.join(_HERE, "libphasorpic.so")
 
 PIC_OK, PIC_EINVAL, PIC_ENOMEM, PIC_EDEVICE, PIC_ENOTCONV, PIC_EPHASE, PIC_ESTATE = 0, -1, -2, -3, -4, -5, -6
 PIC_FP64, PIC_MIXED = 0, 1
+PIC_FIELD_FULL, PIC_FIELD_MQS = 0, 1
+PIC_RRF_GIVEN, PIC_RRF_SKIN = 0, 1
 (PIC_GRID_PHI, PIC_GRID_CHARGE, PIC_GRID_CURRENT, PIC_GRID_ER, PIC_GRID_EZ, PIC_GRID_ETHETA,
- PIC_GRID_SURFACE, PIC_GRID_JC, PIC_GRID_JS) = range(9)
+ PIC_GRID_SURFACE, PIC_GRID_JC, PIC_GRID_JS, PIC_GRID_EC, PIC_GRID_ES, PIC_GRID_EC_PLASMA,
+ PIC_GRID_ES_PLASMA) = range(13)
+PIC_GRID_UNIT = 16
 
 _D, _I32, _I64, _U32 = ctypes.c_double, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
 _PD, _PI32, _PU32 = ctypes.POINTER(_D), ctypes.POINTER(_I32), ctypes.POINTER(_U32)
@@ -39,6 +43,12 @@ class PicConfig(ctypes.Structure):
         ("turn_vc", _PD), ("turn_vs", _PD),
         ("mg_rtol", _D), ("mg_max_cycles", _I32), ("sort_every", _I32), ("load", _I32),
         ("birth_capacity", _I32),
+        ("circuit", _I32), ("field_mode", _I32), ("mu0", _D), ("turn_sign", _PD),
+        ("r_g", _D), ("r_m", _D), ("l_m", _D), ("c_m", _D), ("c_stray", _PD),
+        ("rrf_mode", _I32), ("r_rf", _PD), ("rho20", _D), ("alpha_cu", _D), ("temp_c", _D),
+        ("vg_amp", _D), ("vg_phase", _D), ("vg_from_target", _I32), ("controller", _I32),
+        ("p_target", _D), ("gamma", _D), ("n_trend", _D), ("eps_p", _D), ("alpha_v", _D), ("f_step", _D),
+        ("v_min", _D), ("v_max", _D), ("alpha", _D), ("helm_rtol", _D), ("helm_max_cycles", _I32),
     ]
 
 
@@ -54,13 +64,24 @@ class PicStats(ctypes.Structure):
         ("numax", _D * 2), ("pnull", _D * 2), ("pind_sum", _D),
         ("qc", _D * 16), ("qs", _D * 16), ("wk", _D * 16), ("qk", _D * 16),
         ("pass_ms", _D), ("pass_count", _I64), ("poisson_ms", _D), ("poisson_count", _I64),
-        ("sort_ms", _D), ("sort_count", _I64), ("mg_cycles", _I64), ("mg_rel", _D),
+        ("sort_ms", _D), ("sort_count", _I64), ("circuit_ms", _D), ("circuit_count", _I64),
+        ("mg_cycles", _I64), ("mg_rel", _D),
     ]
 
 
 class PicPeriodReport(ctypes.Structure):
     _fields_ = [("accepted", _I32), ("samples", _I32), ("p_ind", _D), ("p_cap", _D), ("p_cap_ph", _D),
-                ("qc", _D * 16), ("qs", _D * 16), ("icap_re", _D * 16), ("icap_im", _D * 16)]
+                ("qc", _D * 16), ("qs", _D * 16), ("icap_re", _D * 16), ("icap_im", _D * 16),
+                ("p_port", _D), ("p_cu", _D), ("eps_bal", _D), ("kcl", _D), ("kvl", _D),
+                ("vg_old", _D), ("vg_amp", _D), ("pf", _D), ("pc", _D),
+                ("vp_re", _D * 16), ("vp_im", _D * 16), ("xt_re", _D * 33), ("xt_im", _D * 33),
+                ("x_re", _D * 33), ("x_im", _D * 33), ("helm_cycles", _I32 * 2), ("helm_rel", _D * 2)]
+
+
+class PicCircuitInfo(ctypes.Structure):
+    _fields_ = [("nturns", _I32), ("omega", _D), ("zvac_im", _D * 256), ("eps_rec", _D), ("r_rf", _D * 16),
+                ("zs_re", _D), ("zs_im", _D), ("g", _D * 16), ("area", _D * 16), ("vg_amp", _D),
+                ("vg_phase", _D), ("x_re", _D * 33), ("x_im", _D * 33)]
 
 
 class PicError(RuntimeError):
@@ -73,7 +94,7 @@ _LIB = None
 
 # exported C symbols, in header order
 SYMBOLS = ["pic_workspace_bytes", "pic_init", "pic_gather_push", "mcc_collide", "pic_deposit",
-           "poisson_solve_rz", "harmonic_accumulate", "circuit_period_update", "pic_sync",
+           "poisson_solve_rz", "harmonic_accumulate", "circuit_period_update", "pic_get_circuit", "pic_sync",
            "pic_clear_error", "pic_get_particles", "pic_set_particles", "pic_set_step", "pic_set_phi",
            "pic_get_grid", "pic_timing", "pic_get_stats", "pic_destroy", "pic_last_error"]
 
@@ -93,6 +114,7 @@ def lib():
             getattr(L, name).argtypes = [P, _I64]
         L.poisson_solve_rz.argtypes = [P, _I64, _D, _I32, ctypes.POINTER(PicSolveInfo)]
         L.circuit_period_update.argtypes = [P, _PD, _PD, _PD, _PD, ctypes.POINTER(PicPeriodReport), _PD, _PD]
+        L.pic_get_circuit.argtypes = [P, ctypes.POINTER(PicCircuitInfo)]
         L.pic_sync.argtypes = [P]
         L.pic_clear_error.argtypes = [P]
         L.pic_get_particles.argtypes = [P, _I32, _I64, _PD, _PD, _PD, _PD, _PD, _PU32, _PI32,
@@ -121,8 +143,10 @@ def _ptr(a, t):
 # Configuration from a workload description
 # ---------------------------------------------------------------------------
 def config_from_workload(wl, precision="mixed", fuse=True, load=True, mg_rtol=None, mg_max_cycles=30,
-                         sort_every=16, birth_capacity=65536, nscan=200_000):
-    """(PicConfig, keep-alive list).  precision: 'fp64' or 'mixed'."""
+                         sort_every=16, birth_capacity=65536, nscan=200_000, helm_rtol=1e-12,
+                         helm_max_cycles=60):
+    """(PicConfig, keep-alive list).  precision: 'fp64' or 'mixed'.  A
+    workload with a ``circuit`` couples its turns to the external network."""
     keep = []
     c = PicConfig()
     c.nr, c.nz, c.ip, c.window = wl.nr, wl.nz, wl.ip, 1 if wl.window else 0
@@ -155,6 +179,23 @@ def config_from_workload(wl, precision="mixed", fuse=True, load=True, mg_rtol=No
         mg_rtol = 1e-13 if precision == "fp64" else 1e-9
     c.mg_rtol, c.mg_max_cycles, c.sort_every, c.load = mg_rtol, mg_max_cycles, sort_every, 1 if load else 0
     c.birth_capacity = birth_capacity
+    cp = wl.circuit
+    if cp is not None:
+        N = wl.nturns
+        sign = np.ascontiguousarray(np.ones(N) if cp.turn_sign is None else cp.turn_sign, dtype=np.float64)
+        cst = np.ascontiguousarray(np.zeros(N) if cp.c_stray is None else cp.c_stray, dtype=np.float64)
+        rrf = np.ascontiguousarray(np.zeros(N) if cp.r_rf is None else cp.r_rf, dtype=np.float64)
+        keep += [sign, cst, rrf]
+        c.circuit, c.field_mode, c.mu0 = 1, cp.field_mode, cp.mu0
+        c.turn_sign, c.c_stray, c.r_rf = _ptr(sign, _D), _ptr(cst, _D), _ptr(rrf, _D)
+        c.r_g, c.r_m, c.l_m, c.c_m = cp.r_g, cp.r_m, cp.l_m, cp.c_m
+        c.rrf_mode, c.rho20, c.alpha_cu, c.temp_c = cp.rrf_mode, cp.rho20, cp.alpha_cu, cp.temp_c
+        c.vg_amp, c.vg_phase, c.vg_from_target = cp.vg_amp, cp.vg_phase, 1 if cp.vg_from_target else 0
+        c.controller = 1 if cp.controller else 0
+        c.p_target, c.gamma, c.n_trend, c.eps_p = cp.p_target, cp.gamma, cp.n_trend, cp.eps_p
+        c.alpha_v, c.f_step, c.v_min, c.v_max = cp.alpha_v, cp.f_step, cp.v_min, cp.v_max
+        c.alpha = cp.alpha
+        c.helm_rtol, c.helm_max_cycles = helm_rtol, helm_max_cycles
     return c, keep
 
 
@@ -247,7 +288,28 @@ def circuit_period_update(ctx, new_vc=None, new_vs=None, new_ec=None, new_es_sto
     out = dict(accepted=rep.accepted, samples=rep.samples, p_ind=rep.p_ind, p_cap=rep.p_cap, p_cap_ph=rep.p_cap_ph,
                qc=np.array(rep.qc[:K]), qs=np.array(rep.qs[:K]),
                icap=np.array(rep.icap_re[:K]) + 1j * np.array(rep.icap_im[:K]))
+    if ctx.cfg.circuit:
+        M = 2 * K + 1
+        out.update(p_port=rep.p_port, p_cu=rep.p_cu, eps_bal=rep.eps_bal, kcl=rep.kcl, kvl=rep.kvl,
+                   vg_old=rep.vg_old, vg_amp=rep.vg_amp, pf=rep.pf, pc=rep.pc,
+                   vp=np.array(rep.vp_re[:K]) + 1j * np.array(rep.vp_im[:K]),
+                   x_target=np.array(rep.xt_re[:M]) + 1j * np.array(rep.xt_im[:M]),
+                   x=np.array(rep.x_re[:M]) + 1j * np.array(rep.x_im[:M]),
+                   helm_cycles=tuple(rep.helm_cycles), helm_rel=tuple(rep.helm_rel))
     return st, out, jc, js
+
+
+def pic_get_circuit(ctx):
+    """Dict with Z_vac (complex K x K), eps_rec, R_rf, Z_source, g, A, V_g and the applied state x."""
+    info = PicCircuitInfo()
+    ctx.check(lib().pic_get_circuit(ctx.handle, ctypes.byref(info)))
+    K = info.nturns
+    zim = np.array(info.zvac_im).reshape(16, 16)[:K, :K]
+    M = 2 * K + 1
+    return dict(omega=info.omega, zvac=1j * zim, eps_rec=info.eps_rec, r_rf=np.array(info.r_rf[:K]),
+                zs=complex(info.zs_re, info.zs_im), g=np.array(info.g[:K]), area=np.array(info.area[:K]),
+                vg_amp=info.vg_amp, vg_phase=info.vg_phase,
+                x=np.array(info.x_re[:M]) + 1j * np.array(info.x_im[:M]))
 
 
 def pic_sync(ctx):

@@ -20,6 +20,10 @@ synthetic stand-ins for the GEC cell, whose coil geometry is not tabulated):
   particles, argon 20 mTorr, dt = 1/(2000 f).
 * ``large``  : same geometry on 256 x 512 cells, 3.2e7 + 3.2e7 particles,
   argon 50 mTorr.
+
+The coil cells couple their turns to the external network by default
+(``CircuitParams``); ``circuit=False`` prescribes the turns' free-space
+field and fixed potentials instead.
 """
 from __future__ import annotations
 
@@ -76,6 +80,44 @@ class CrossSections:
     nu_margin: float = 1.01
 
 
+FIELD_FULL, FIELD_MQS = 0, 1      # inductive operator with / without the displacement term
+RRF_GIVEN, RRF_SKIN = 0, 1        # turn RF resistance: given values / round-wire skin model
+
+
+@dataclasses.dataclass
+class CircuitParams:
+    """External network, conductor and power-controller settings of the
+    field-circuit coupling (the paper's circuit symbols; values for the
+    synthetic cells: 50 ohm generator behind a 200 pF series capacitor, no
+    stray capacitance, copper turns, controller towards 60 W)."""
+    mu0: float = MU0
+    field_mode: int = FIELD_FULL
+    turn_sign: tuple = None           # s_k, default +1 for every turn
+    r_g: float = 50.0                 # generator resistance (ohm)
+    r_m: float = 0.0                  # matching branch R, L, C (C <= 0: no capacitor)
+    l_m: float = 0.0
+    c_m: float = 200e-12
+    c_stray: tuple = None             # out-of-domain shunt capacitance per node (F), default 0
+    rrf_mode: int = RRF_SKIN
+    r_rf: tuple = None                # per-turn resistance when rrf_mode == RRF_GIVEN (ohm)
+    rho20: float = 1.68e-8            # copper resistivity at 20 C (ohm m)
+    alpha_cu: float = 3.93e-3         # its temperature coefficient (1/K)
+    temp_c: float = 20.0
+    vg_amp: float = 100.0             # Thevenin peak amplitude (V) ...
+    vg_phase: float = 0.0             # ... and phase (rad)
+    vg_from_target: bool = True       # start from the amplitude that puts p_target into the vacuum network
+    controller: bool = True
+    p_target: float = 60.0            # W
+    gamma: float = 0.3                # filter weight of the newest cycle
+    n_trend: float = 1.0              # trend extrapolation in cycles
+    eps_p: float = 1e-3               # floor of the controlled power (W)
+    alpha_v: float = 0.5              # voltage relaxation towards the desired value
+    f_step: float = 0.1               # symmetric per-cycle step limit
+    v_min: float = 1.0
+    v_max: float = 5000.0
+    alpha: float = 0.3                # state relaxation of the circuit update
+
+
 @dataclasses.dataclass
 class Workload:
     name: str
@@ -99,6 +141,7 @@ class Workload:
     es_sto: np.ndarray            # (nz+1, nr+1) stored sine array = -E_s (V/m)
     turn_vc: np.ndarray           # (N,) V_c,k of the turn potentials (V)
     turn_vs: np.ndarray           # (N,) V_s,k
+    circuit: CircuitParams = None     # None: prescribed E_theta and turn potentials
     bfield: tuple = (0.0, 0.0, 0.0)   # uniform (B_r, B_theta, B_z), tests only
     xs: CrossSections = dataclasses.field(default_factory=CrossSections)
     capacity_factor: float = 1.25
@@ -191,10 +234,14 @@ def small(seed=0, n_per_species=100_000, nsteps=200) -> Workload:
 
 
 def _coil_cell(nr, nz, n_per_species, pressure_mtorr, name, seed, nsteps, coil_current=5.0,
-               v_feed=300.0):
+               v_feed=300.0, circuit=True):
     """Chamber R = 0.15 m, z = 0.2 m: plasma z < 0.15 m, quartz window
     0.15 m .. 0.15 m + 13 * 0.78125 mm, 5 planar turns in the vacuum
-    compartment above, grounded side wall, bottom and lid."""
+    compartment above, grounded side wall, bottom and lid.
+
+    circuit=True couples the coil to the external network (CircuitParams
+    defaults); circuit=False prescribes the free-space field of the five
+    turns at coil_current and fixed turn potentials from v_feed instead."""
     rmax, zmax, freq = 0.15, 0.2, 13.56e6
     dr, dz = rmax / nr, zmax / nz
     ip = int(round(0.15 / dz))
@@ -232,15 +279,15 @@ def _coil_cell(nr, nz, n_per_species, pressure_mtorr, name, seed, nsteps, coil_c
         freq=freq, nsteps=nsteps, pressure_pa=pressure_mtorr * 1e-3 * TORR, tgas_k=300.0,
         n0=1e16, np_init=(n_per_species, n_per_species), temp_ev=(3.0, 0.026), seed=seed,
         eps_cell=eps, node_tag=tag, ec=ec, es_sto=es,
-        turn_vc=vfeed, turn_vs=np.zeros(5))
+        turn_vc=vfeed, turn_vs=np.zeros(5), circuit=CircuitParams() if circuit else None)
 
 
-def cell(seed=0, n_per_species=2_000_000, nsteps=20_000) -> Workload:
-    return _coil_cell(128, 256, n_per_species, 20.0, "cell", seed, nsteps)
+def cell(seed=0, n_per_species=2_000_000, nsteps=20_000, circuit=True) -> Workload:
+    return _coil_cell(128, 256, n_per_species, 20.0, "cell", seed, nsteps, circuit=circuit)
 
 
-def large(seed=0, n_per_species=32_000_000, nsteps=4_000) -> Workload:
-    return _coil_cell(256, 512, n_per_species, 50.0, "large", seed, nsteps)
+def large(seed=0, n_per_species=32_000_000, nsteps=4_000, circuit=True) -> Workload:
+    return _coil_cell(256, 512, n_per_species, 50.0, "large", seed, nsteps, circuit=circuit)
 
 
 def by_name(name, **kw) -> Workload:

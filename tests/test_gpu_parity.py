@@ -97,7 +97,7 @@ def _step_case(wlname, prec, fuse, n0):
     if wlname == "small":
         wl = W.small(n_per_species=60_000)
     else:
-        wl = W.cell(n_per_species=120_000)
+        wl = W.cell(n_per_species=120_000, circuit=False)
     say(f"[gpu] one step {wlname} {prec} fuse={fuse} n0={n0}")
     ora = O.OraclePIC(wl)
     cfg, keep = pp.config_from_workload(wl, precision=prec, fuse=fuse, load=False)
@@ -174,7 +174,7 @@ def test_closed_period_report(prec):
     import paper_2609_15043_amd.phasorpic as pp
     from paper_2609_15043_amd import workloads as W
     from oracle import pic as O
-    wl = W.cell(n_per_species=60_000)
+    wl = W.cell(n_per_species=60_000, circuit=False)
     wl.freq = 1.0 / (16 * wl.dt)
     say(f"[gpu] closed period N_RF=16 cell 60k/species {prec}")
     cfg, keep = pp.config_from_workload(wl, precision=prec, load=True)
