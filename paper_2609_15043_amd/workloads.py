@@ -292,3 +292,27 @@ def large(seed=0, n_per_species=32_000_000, nsteps=4_000, circuit=True) -> Workl
 
 def by_name(name, **kw) -> Workload:
     return {"small": small, "cell": cell, "large": large}[name](**kw)
+
+
+# ---------------------------------------------------------------------------
+# Surrogate network: sizes and seeded initial parameters
+# ---------------------------------------------------------------------------
+MLP_PAD = 32          # inputs and outputs padded to 32 columns
+MLP_HIDDEN = 256      # three hidden layers
+MLP_IN, MLP_OUT = 29, 20
+
+
+def mlp_init_params(seed=0, hidden=MLP_HIDDEN, n_in=MLP_IN, n_out=MLP_OUT):
+    """Flat FP32 parameter vector [W1 (H x 32), b1, W2 (H x H), b2, W3, b3,
+    W4 (32 x H), b4 (32)]: He-normal weights (std sqrt(2 / fan_in)) over the
+    real inputs / outputs, zero biases and zero padding."""
+    rng = np.random.default_rng(seed)
+    H, P = hidden, MLP_PAD
+    W1 = np.zeros((H, P))
+    W1[:, :n_in] = rng.normal(0.0, math.sqrt(2.0 / n_in), (H, n_in))
+    W2 = rng.normal(0.0, math.sqrt(2.0 / H), (H, H))
+    W3 = rng.normal(0.0, math.sqrt(2.0 / H), (H, H))
+    W4 = np.zeros((P, H))
+    W4[:n_out] = rng.normal(0.0, math.sqrt(2.0 / H), (n_out, H))
+    parts = [W1, np.zeros(H), W2, np.zeros(H), W3, np.zeros(H), W4, np.zeros(P)]
+    return np.concatenate([a.reshape(-1) for a in parts]).astype(np.float32)
