@@ -342,6 +342,51 @@ void pic_destroy(pic_ctx *ctx);
 
 const char *pic_last_error(const pic_ctx *ctx);
 
+/* ------------------------------------------------------------------------
+ * Surrogate network of the coil-plasma response (the learned predictor of
+ * the circuit update): n_in (<= 32) standardised inputs -> three GELU
+ * hidden layers of width `hidden` -> n_out (<= 32) standardised outputs.
+ * BF16 weights and activations on the matrix cores with FP32
+ * accumulation; FP32 master weights trained by Adam on mean-squared
+ * error.  Inputs and outputs are padded to 32 columns internally.
+ * Flat FP32 parameter vector (padded):
+ *   W1 [hidden x 32], b1 [hidden], W2 [hidden x hidden], b2, W3, b3,
+ *   W4 [32 x hidden], b4 [32]   (W row-major, rows = outputs).
+ * ------------------------------------------------------------------------ */
+typedef struct mlp_ctx mlp_ctx;
+
+typedef struct mlp_config {
+    int32_t n_in, n_out;      /* 1..32 */
+    int32_t hidden;           /* multiple of 64 */
+    int32_t max_batch;        /* rows per call at most */
+    double lr, beta1, beta2, eps;   /* Adam */
+    /* standardisation x_std = (x - mean) / std, y = y_std * std + mean (host
+     * arrays of n_in / n_out, read by mlp_init; NULL = 0 / 1) */
+    const float *in_mean, *in_std, *out_mean, *out_std;
+} mlp_config;
+
+pic_status mlp_workspace_bytes(const mlp_config *cfg, size_t *bytes);
+/* workspace: device memory of mlp_workspace_bytes; parameters start at 0
+ * (load them with mlp_set_params). */
+pic_status mlp_init(const mlp_config *cfg, void *workspace, size_t workspace_bytes, void *stream,
+                    mlp_ctx **out);
+pic_status mlp_param_count(const mlp_ctx *ctx, int64_t *n);
+/* Host FP32 parameter vector in, Adam moments and step count reset. */
+pic_status mlp_set_params(mlp_ctx *ctx, const float *host);
+pic_status mlp_get_params(mlp_ctx *ctx, float *host);
+/* y[batch x n_out] (device, FP32) = network(x[batch x n_in]) (device, FP32). */
+pic_status mlp_forward(mlp_ctx *ctx, const float *x, int32_t batch, float *y);
+/* One training step on a batch (device arrays x[batch x n_in], t[batch x
+ * n_out]): forward, mean-squared error over batch x n_out standardised
+ * targets, backward (7 products), Adam.  loss (host, nullable): the batch
+ * loss before the update; giving it synchronises. */
+pic_status mlp_train_step(mlp_ctx *ctx, const float *x, const float *t, int32_t batch, float *loss);
+/* Gradient of the last training step (host FP32, parameter layout). */
+pic_status mlp_get_grads(mlp_ctx *ctx, float *host);
+pic_status mlp_sync(mlp_ctx *ctx);
+void mlp_destroy(mlp_ctx *ctx);
+const char *mlp_last_error(const mlp_ctx *ctx);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,604 @@
+// Surrogate network of the coil-plasma response: three GELU hidden layers
+// of width H between 32-column (padded) inputs and outputs.  BF16 weights
+// and activations on the matrix cores (v_mfma_f32_16x16x16_bf16, FP32
+// accumulation), FP32 master weights, Adam (Kingma & Ba) in FP32.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/phasorpic.h"
+
+namespace {
+
+constexpr int PAD = 32;        // padded input / output width
+constexpr int TM = 64, TN = 64, TK = 32, KP = 40;   // GEMM tile and LDS row pitch (bf16 elements)
+constexpr int SPLITK = 16;     // K splits of the weight-gradient products
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// FP32 -> BF16, round to nearest, ties to even (finite inputs)
+__device__ __forceinline__ uint16_t f2bf(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad(float z)
+{
+    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
+}
+
+template <typename T> __device__ __forceinline__ uint16_t to_bf(T v);
+template <> __device__ __forceinline__ uint16_t to_bf<uint16_t>(uint16_t v) { return v; }
+template <> __device__ __forceinline__ uint16_t to_bf<float>(float v) { return f2bf(v); }
+
+enum Epi { EPI_GELU = 0, EPI_LINEAR = 1, EPI_DGELU = 2, EPI_STORE = 3 };
+
+// C = A B with A(m, k) = A[m sam + k sak], B(k, n) = B[k sbk + n sbn]; both
+// operands are rounded to BF16 when staged (FP32 sources) and multiplied
+// on the matrix cores with FP32 accumulation.
+struct GemmArgs {
+    int M, N, K;
+    const void *A;
+    int64_t sam, sak;
+    const void *B;
+    int64_t sbk, sbn;
+    const float *bias;     // EPI_GELU, EPI_LINEAR
+    float *C;              // FP32 result (or K-split partials for EPI_STORE)
+    int64_t ldc;
+    uint16_t *Abf;         // EPI_GELU: BF16 activation
+    int64_t ldabf;
+    const float *Zin;      // EPI_DGELU: pre-activation
+    int64_t ldz;
+    int ksplit;            // EPI_STORE: number of K splits (grid.z); partial z at C + z * M * ldc
+};
+
+template <typename TA, typename TB, int EPI> __global__ __launch_bounds__(256) void k_gemm(GemmArgs g)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t As[TM * KP];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[TN * KP];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    int kb = 0, ke = g.K;
+    if (EPI == EPI_STORE && g.ksplit > 1) {
+        const int per = (g.K + g.ksplit - 1) / g.ksplit;
+        kb = blockIdx.z * per;
+        ke = min(g.K, kb + per);
+    }
+    const TA *A = static_cast<const TA *>(g.A);
+    const TB *B = static_cast<const TB *>(g.B);
+    floatx4 acc[2][2];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const bool a_mfast = g.sam == 1, b_nfast = g.sbn == 1;
+    for (int k0 = kb; k0 < ke; k0 += TK) {
+        for (int e = t; e < TM * TK; e += 256) {
+            const int mm = a_mfast ? e % TM : e / TK, kk = a_mfast ? e / TM : e % TK;
+            const int m = m0 + mm, k = k0 + kk;
+            As[mm * KP + kk] = (m < g.M && k < ke) ? to_bf<TA>(A[(int64_t)m * g.sam + (int64_t)k * g.sak]) : 0;
+        }
+        for (int e = t; e < TN * TK; e += 256) {
+            const int nn = b_nfast ? e % TN : e / TK, kk = b_nfast ? e / TN : e % TK;
+            const int n = n0 + nn, k = k0 + kk;
+            Bs[nn * KP + kk] = (n < g.N && k < ke) ? to_bf<TB>(B[(int64_t)k * g.sbk + (int64_t)n * g.sbn]) : 0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < TK; kk += 16) {
+            bf16x4 a[2], b[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                a[i] = *reinterpret_cast<const bf16x4 *>(&As[(wm + 16 * i + (lane & 15)) * KP + kk + 4 * (lane >> 4)]);
+                b[i] = *reinterpret_cast<const bf16x4 *>(&Bs[(wn + 16 * i + (lane & 15)) * KP + kk + 4 * (lane >> 4)]);
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    // D of a 16x16 block: lane l holds rows 4 (l / 16) + r, column l % 16
+    float *C = g.C;
+    if (EPI == EPI_STORE && g.ksplit > 1) C += (int64_t)blockIdx.z * g.M * g.ldc;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
+                const int col = n0 + wn + 16 * j + (lane & 15);
+                if (row >= g.M || col >= g.N) continue;
+                const float v = acc[i][j][r];
+                if (EPI == EPI_GELU) {
+                    const float z = v + g.bias[col];
+                    C[(int64_t)row * g.ldc + col] = z;
+                    g.Abf[(int64_t)row * g.ldabf + col] = f2bf(gelu(z));
+                } else if (EPI == EPI_LINEAR) {
+                    C[(int64_t)row * g.ldc + col] = v + g.bias[col];
+                } else if (EPI == EPI_DGELU) {
+                    C[(int64_t)row * g.ldc + col] = v * gelu_grad(g.Zin[(int64_t)row * g.ldz + col]);
+                } else {
+                    C[(int64_t)row * g.ldc + col] = v;
+                }
+            }
+}
+
+// sum of the K-split partials in split order
+__global__ void k_splitk_sum(const float *part, int splits, int64_t count, float *out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    float s = 0.f;
+    for (int z = 0; z < splits; ++z) s += part[(int64_t)z * count + i];
+    out[i] = s;
+}
+
+// standardised, padded BF16 input rows
+__global__ void k_input(const float *x, int B, int n_in, const float *mean, const float *stdv, uint16_t *X)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= B * PAD) return;
+    const int b = e / PAD, i = e % PAD;
+    X[e] = i < n_in ? f2bf((x[(int64_t)b * n_in + i] - mean[i]) / stdv[i]) : (uint16_t)0;
+}
+
+// de-standardised outputs
+__global__ void k_output(const float *Y, int B, int n_out, const float *mean, const float *stdv, float *y)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= B * n_out) return;
+    const int b = e / n_out, o = e % n_out;
+    y[e] = Y[(int64_t)b * PAD + o] * stdv[o] + mean[o];
+}
+
+// mean-squared error on standardised targets: dY = 2 (Y - T) / (B n_out) on
+// the real columns (0 on the padding), per-block partial sums of (Y - T)^2
+__global__ __launch_bounds__(256) void k_loss(const float *Y, const float *t, int B, int n_out, const float *mean,
+                                              const float *stdv, float *dY, float *partial)
+{
+    __shared__ float red[256];
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    float sq = 0.f;
+    if (e < B * PAD) {
+        const int b = e / PAD, o = e % PAD;
+        float d = 0.f;
+        if (o < n_out) d = Y[e] - (t[(int64_t)b * n_out + o] - mean[o]) / stdv[o];
+        dY[e] = 2.0f * d / (float)(B * n_out);
+        sq = d * d;
+    }
+    red[threadIdx.x] = sq;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_fold(const float *partial, int np, float scale, float *out)
+{
+    __shared__ float red[256];
+    float s = 0.f;
+    for (int i = threadIdx.x; i < np; i += 256) s += partial[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0] * scale;
+}
+
+// bias gradient: column sums of the BF16-rounded output gradient, in two
+// passes (row chunks, then chunks in order)
+constexpr int COLSUM_CHUNKS = 32;
+__global__ __launch_bounds__(256) void k_colsum(const float *G, int B, int N, int64_t ld, float *partial)
+{
+    __shared__ float red[4][64];
+    const int c = blockIdx.x * 64 + (threadIdx.x & 63), grp = threadIdx.x >> 6;
+    const int per = (B + COLSUM_CHUNKS - 1) / COLSUM_CHUNKS;
+    const int r0 = blockIdx.y * per, r1 = min(B, r0 + per);
+    float s = 0.f;
+    if (c < N)
+        for (int r = r0 + grp; r < r1; r += 4) s += bf2f(f2bf(G[(int64_t)r * ld + c]));
+    red[grp][threadIdx.x & 63] = s;
+    __syncthreads();
+    if (grp == 0 && c < N)
+        partial[(int64_t)blockIdx.y * N + c] = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) +
+                                               red[3][threadIdx.x];
+}
+
+__global__ void k_colsum_fold(const float *partial, int N, float *out)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= N) return;
+    float s = 0.f;
+    for (int z = 0; z < COLSUM_CHUNKS; ++z) s += partial[(int64_t)z * N + c];
+    out[c] = s;
+}
+
+// Adam on the FP32 master parameters; refreshes the BF16 copy
+__global__ void k_adam(float *p, const float *gr, float *m, float *v, uint16_t *pbf, int64_t n, float lr, float b1,
+                       float b2, float eps, float bc1, float bc2)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float g = gr[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * g;
+    const float vi = b2 * v[i] + (1.0f - b2) * g * g;
+    m[i] = mi;
+    v[i] = vi;
+    const float x = p[i] - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+    p[i] = x;
+    pbf[i] = f2bf(x);
+}
+
+__global__ void k_to_bf16(const float *p, uint16_t *q, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) q[i] = f2bf(p[i]);
+}
+
+inline unsigned nb(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+struct Carver {
+    uint8_t *base;
+    size_t off = 0;
+    template <typename U> U *take(size_t count)
+    {
+        off = (off + 255) & ~size_t(255);
+        U *p = base ? reinterpret_cast<U *>(base + off) : nullptr;
+        off += count * sizeof(U);
+        return p;
+    }
+};
+
+}  // namespace
+
+struct mlp_ctx {
+    mlp_config cfg{};
+    hipStream_t stream = nullptr;
+    std::string err;
+    int H = 0, maxB = 0;
+    int64_t P = 0;
+    // parameter layout offsets (floats)
+    int64_t oW[4]{}, ob[4]{};
+    float *p = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr;
+    uint16_t *pbf = nullptr;
+    float *norm = nullptr;   // in_mean[32], in_std[32], out_mean[32], out_std[32]
+    uint16_t *X = nullptr, *A[3]{};
+    float *Z[3]{}, *Y = nullptr, *dY = nullptr, *D[2]{}, *part = nullptr, *colpart = nullptr, *lpart = nullptr,
+          *loss = nullptr;
+    int64_t step = 0;
+};
+
+namespace {
+
+pic_status mfail(mlp_ctx *c, pic_status s, const char *fmt, ...)
+{
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return s;
+}
+
+#define MCHK(ctx, expr)                                                                                \
+    do {                                                                                               \
+        hipError_t e_ = (expr);                                                                        \
+        if (e_ != hipSuccess) return mfail(ctx, PIC_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));  \
+    } while (0)
+
+void mlp_layout(mlp_ctx &c, Carver &cv)
+{
+    const int H = c.H, B = c.maxB;
+    int64_t o = 0;
+    const int64_t wsz[4] = {(int64_t)H * PAD, (int64_t)H * H, (int64_t)H * H, (int64_t)PAD * H};
+    const int64_t bsz[4] = {H, H, H, PAD};
+    for (int l = 0; l < 4; ++l) {
+        c.oW[l] = o;
+        o += wsz[l];
+        c.ob[l] = o;
+        o += bsz[l];
+    }
+    c.P = o;
+    c.p = cv.take<float>(c.P);
+    c.grad = cv.take<float>(c.P);
+    c.m = cv.take<float>(c.P);
+    c.v = cv.take<float>(c.P);
+    c.pbf = cv.take<uint16_t>(c.P);
+    c.norm = cv.take<float>(4 * PAD);
+    c.X = cv.take<uint16_t>((size_t)B * PAD);
+    for (int l = 0; l < 3; ++l) {
+        c.A[l] = cv.take<uint16_t>((size_t)B * H);
+        c.Z[l] = cv.take<float>((size_t)B * H);
+    }
+    c.Y = cv.take<float>((size_t)B * PAD);
+    c.dY = cv.take<float>((size_t)B * PAD);
+    c.D[0] = cv.take<float>((size_t)B * H);
+    c.D[1] = cv.take<float>((size_t)B * H);
+    c.part = cv.take<float>((size_t)SPLITK * H * H);
+    c.colpart = cv.take<float>((size_t)COLSUM_CHUNKS * H);
+    c.lpart = cv.take<float>(nb((int64_t)B * PAD, 256));
+    c.loss = cv.take<float>(1);
+}
+
+template <typename TA, typename TB, int EPI> void gemm(mlp_ctx &c, GemmArgs g)
+{
+    dim3 grid(nb(g.N, TN), nb(g.M, TM), EPI == EPI_STORE ? g.ksplit : 1);
+    hipLaunchKernelGGL((k_gemm<TA, TB, EPI>), grid, dim3(256), 0, c.stream, g);
+}
+
+// weight gradient dW[M x N] = sum_b G[b, m] Act[b, n] (K = batch), split-K
+template <typename TB> void weight_grad(mlp_ctx &c, const float *G, int ldg, const TB *Act, int lda, int M, int N,
+                                        int B, float *out)
+{
+    GemmArgs g{};
+    g.M = M;
+    g.N = N;
+    g.K = B;
+    g.A = G;
+    g.sam = 1;
+    g.sak = ldg;
+    g.B = Act;
+    g.sbk = lda;
+    g.sbn = 1;
+    g.C = c.part;
+    g.ldc = N;
+    g.ksplit = std::max(1, std::min(SPLITK, (B + TK - 1) / TK));
+    gemm<float, TB, EPI_STORE>(c, g);
+    const int64_t cnt = (int64_t)M * N;
+    hipLaunchKernelGGL(k_splitk_sum, dim3(nb(cnt, 256)), dim3(256), 0, c.stream, c.part, g.ksplit, cnt, out);
+}
+
+void bias_grad(mlp_ctx &c, const float *G, int ld, int B, int N, float *out)
+{
+    hipLaunchKernelGGL(k_colsum, dim3(nb(N, 64), COLSUM_CHUNKS), dim3(256), 0, c.stream, G, B, N, (int64_t)ld,
+                       c.colpart);
+    hipLaunchKernelGGL(k_colsum_fold, dim3(nb(N, 256)), dim3(256), 0, c.stream, c.colpart, N, out);
+}
+
+void forward(mlp_ctx &c, int B)
+{
+    const int H = c.H;
+    const uint16_t *in = c.X;
+    int K = PAD;
+    for (int l = 0; l < 3; ++l) {
+        GemmArgs g{};
+        g.M = B;
+        g.N = H;
+        g.K = K;
+        g.A = in;
+        g.sam = K;
+        g.sak = 1;
+        g.B = c.pbf + c.oW[l];
+        g.sbk = 1;
+        g.sbn = K;
+        g.bias = c.p + c.ob[l];
+        g.C = c.Z[l];
+        g.ldc = H;
+        g.Abf = c.A[l];
+        g.ldabf = H;
+        gemm<uint16_t, uint16_t, EPI_GELU>(c, g);
+        in = c.A[l];
+        K = H;
+    }
+    GemmArgs g{};
+    g.M = B;
+    g.N = PAD;
+    g.K = H;
+    g.A = c.A[2];
+    g.sam = H;
+    g.sak = 1;
+    g.B = c.pbf + c.oW[3];
+    g.sbk = 1;
+    g.sbn = H;
+    g.bias = c.p + c.ob[3];
+    g.C = c.Y;
+    g.ldc = PAD;
+    gemm<uint16_t, uint16_t, EPI_LINEAR>(c, g);
+}
+
+void backward(mlp_ctx &c, int B)
+{
+    const int H = c.H;
+    float *gr = c.grad;
+    // output layer
+    weight_grad<uint16_t>(c, c.dY, PAD, c.A[2], H, PAD, H, B, gr + c.oW[3]);
+    bias_grad(c, c.dY, PAD, B, PAD, gr + c.ob[3]);
+    // dZ3 = (dY W4) * GELU'(Z3)
+    const float *G = c.dY;
+    int ldG = PAD, Kin = PAD;
+    int buf = 0;
+    for (int l = 2; l >= 0; --l) {
+        GemmArgs g{};
+        g.M = B;
+        g.N = H;
+        g.K = Kin;
+        g.A = G;
+        g.sam = ldG;
+        g.sak = 1;
+        g.B = c.pbf + c.oW[l + 1];
+        g.sbk = H;   // W_{l+1} rows = outputs (Kin), columns = H inputs
+        g.sbn = 1;
+        g.C = c.D[buf];
+        g.ldc = H;
+        g.Zin = c.Z[l];
+        g.ldz = H;
+        gemm<float, uint16_t, EPI_DGELU>(c, g);
+        // dW_l = dZ_l^T A_{l-1}, db_l
+        if (l > 0)
+            weight_grad<uint16_t>(c, c.D[buf], H, c.A[l - 1], H, H, H, B, gr + c.oW[l]);
+        else
+            weight_grad<uint16_t>(c, c.D[buf], H, c.X, PAD, H, PAD, B, gr + c.oW[0]);
+        bias_grad(c, c.D[buf], H, B, H, gr + c.ob[l]);
+        G = c.D[buf];
+        ldG = H;
+        Kin = H;
+        buf ^= 1;
+    }
+}
+
+}  // namespace
+
+extern "C" pic_status mlp_workspace_bytes(const mlp_config *cfg, size_t *bytes)
+{
+    if (!cfg || !bytes) return PIC_EINVAL;
+    if (cfg->n_in < 1 || cfg->n_in > PAD || cfg->n_out < 1 || cfg->n_out > PAD || cfg->hidden < 64 ||
+        cfg->hidden % 64 != 0 || cfg->max_batch < 1)
+        return PIC_EINVAL;
+    mlp_ctx c;
+    c.H = cfg->hidden;
+    c.maxB = cfg->max_batch;
+    Carver cv{nullptr};
+    mlp_layout(c, cv);
+    *bytes = cv.off + 256;
+    return PIC_OK;
+}
+
+extern "C" pic_status mlp_init(const mlp_config *cfg, void *workspace, size_t bytes, void *stream, mlp_ctx **out)
+{
+    if (!out) return PIC_EINVAL;
+    *out = nullptr;
+    size_t need = 0;
+    pic_status st = mlp_workspace_bytes(cfg, &need);
+    if (st) return st;
+    if (!workspace || bytes < need) return PIC_ENOMEM;
+    mlp_ctx *c = new mlp_ctx();
+    c->cfg = *cfg;
+    c->H = cfg->hidden;
+    c->maxB = cfg->max_batch;
+    c->stream = reinterpret_cast<hipStream_t>(stream);
+    Carver cv{reinterpret_cast<uint8_t *>(workspace)};
+    mlp_layout(*c, cv);
+    std::vector<float> nrm(4 * PAD, 0.0f);
+    for (int i = 0; i < PAD; ++i) nrm[PAD + i] = nrm[3 * PAD + i] = 1.0f;
+    for (int i = 0; i < cfg->n_in; ++i) {
+        if (cfg->in_mean) nrm[i] = cfg->in_mean[i];
+        if (cfg->in_std) nrm[PAD + i] = cfg->in_std[i];
+    }
+    for (int i = 0; i < cfg->n_out; ++i) {
+        if (cfg->out_mean) nrm[2 * PAD + i] = cfg->out_mean[i];
+        if (cfg->out_std) nrm[3 * PAD + i] = cfg->out_std[i];
+    }
+    hipError_t e = hipMemcpyAsync(c->norm, nrm.data(), nrm.size() * 4, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->p, 0, c->P * 4, c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->pbf, 0, c->P * 2, c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->m, 0, c->P * 4, c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->v, 0, c->P * 4, c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->grad, 0, c->P * 4, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        delete c;
+        return PIC_EDEVICE;
+    }
+    *out = c;
+    return PIC_OK;
+}
+
+extern "C" pic_status mlp_param_count(const mlp_ctx *c, int64_t *n)
+{
+    if (!c || !n) return PIC_EINVAL;
+    *n = c->P;
+    return PIC_OK;
+}
+
+extern "C" pic_status mlp_set_params(mlp_ctx *c, const float *host)
+{
+    if (!c || !host) return PIC_EINVAL;
+    MCHK(c, hipMemcpyAsync(c->p, host, c->P * 4, hipMemcpyHostToDevice, c->stream));
+    hipLaunchKernelGGL(k_to_bf16, dim3(nb(c->P, 256)), dim3(256), 0, c->stream, c->p, c->pbf, c->P);
+    MCHK(c, hipMemsetAsync(c->m, 0, c->P * 4, c->stream));
+    MCHK(c, hipMemsetAsync(c->v, 0, c->P * 4, c->stream));
+    c->step = 0;
+    MCHK(c, hipStreamSynchronize(c->stream));
+    return PIC_OK;
+}
+
+extern "C" pic_status mlp_get_params(mlp_ctx *c, float *host)
+{
+    if (!c || !host) return PIC_EINVAL;
+    MCHK(c, hipMemcpyAsync(host, c->p, c->P * 4, hipMemcpyDeviceToHost, c->stream));
+    MCHK(c, hipStreamSynchronize(c->stream));
+    return PIC_OK;
+}
+
+extern "C" pic_status mlp_get_grads(mlp_ctx *c, float *host)
+{
+    if (!c || !host) return PIC_EINVAL;
+    MCHK(c, hipMemcpyAsync(host, c->grad, c->P * 4, hipMemcpyDeviceToHost, c->stream));
+    MCHK(c, hipStreamSynchronize(c->stream));
+    return PIC_OK;
+}
+
+extern "C" pic_status mlp_forward(mlp_ctx *c, const float *x, int32_t batch, float *y)
+{
+    if (!c || !x || !y) return PIC_EINVAL;
+    if (batch < 1 || batch > c->maxB) return mfail(c, PIC_EINVAL, "batch %d outside 1..%d", batch, c->maxB);
+    const mlp_config &f = c->cfg;
+    hipLaunchKernelGGL(k_input, dim3(nb((int64_t)batch * PAD, 256)), dim3(256), 0, c->stream, x, batch, f.n_in, c->norm,
+                       c->norm + PAD, c->X);
+    forward(*c, batch);
+    hipLaunchKernelGGL(k_output, dim3(nb((int64_t)batch * f.n_out, 256)), dim3(256), 0, c->stream, c->Y, batch,
+                       f.n_out, c->norm + 2 * PAD, c->norm + 3 * PAD, y);
+    return hipGetLastError() == hipSuccess ? PIC_OK : mfail(c, PIC_EDEVICE, "kernel launch failed");
+}
+
+extern "C" pic_status mlp_train_step(mlp_ctx *c, const float *x, const float *t, int32_t batch, float *loss)
+{
+    if (!c || !x || !t) return PIC_EINVAL;
+    if (batch < 1 || batch > c->maxB) return mfail(c, PIC_EINVAL, "batch %d outside 1..%d", batch, c->maxB);
+    const mlp_config &f = c->cfg;
+    hipLaunchKernelGGL(k_input, dim3(nb((int64_t)batch * PAD, 256)), dim3(256), 0, c->stream, x, batch, f.n_in, c->norm,
+                       c->norm + PAD, c->X);
+    forward(*c, batch);
+    const unsigned nl = nb((int64_t)batch * PAD, 256);
+    hipLaunchKernelGGL(k_loss, dim3(nl), dim3(256), 0, c->stream, c->Y, t, batch, f.n_out, c->norm + 2 * PAD,
+                       c->norm + 3 * PAD, c->dY, c->lpart);
+    hipLaunchKernelGGL(k_fold, dim3(1), dim3(256), 0, c->stream, c->lpart, (int)nl, 1.0f / (float)(batch * f.n_out),
+                       c->loss);
+    backward(*c, batch);
+    c->step += 1;
+    const double bc1 = 1.0 - std::pow(f.beta1, (double)c->step), bc2 = 1.0 - std::pow(f.beta2, (double)c->step);
+    hipLaunchKernelGGL(k_adam, dim3(nb(c->P, 256)), dim3(256), 0, c->stream, c->p, c->grad, c->m, c->v, c->pbf, c->P,
+                       (float)f.lr, (float)f.beta1, (float)f.beta2, (float)f.eps, (float)bc1, (float)bc2);
+    if (hipGetLastError() != hipSuccess) return mfail(c, PIC_EDEVICE, "kernel launch failed");
+    if (loss) {
+        MCHK(c, hipMemcpyAsync(loss, c->loss, 4, hipMemcpyDeviceToHost, c->stream));
+        MCHK(c, hipStreamSynchronize(c->stream));
+    }
+    return PIC_OK;
+}
+
+extern "C" pic_status mlp_sync(mlp_ctx *c)
+{
+    if (!c) return PIC_EINVAL;
+    MCHK(c, hipStreamSynchronize(c->stream));
+    return PIC_OK;
+}
+
+extern "C" void mlp_destroy(mlp_ctx *c)
+{
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    delete c;
+}
+
+extern "C" const char *mlp_last_error(const mlp_ctx *c) { return c ? c->err.c_str() : "null context"; }

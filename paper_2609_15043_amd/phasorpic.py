@@ -382,3 +382,126 @@ def step(ctx, n):
 
 def nrf(wl):
     return int(round(1.0 / (wl.freq * wl.dt)))
+
+
+# ---------------------------------------------------------------------------
+# Surrogate network (mlp_* calls)
+# ---------------------------------------------------------------------------
+class MlpConfig(ctypes.Structure):
+    _fields_ = [("n_in", _I32), ("n_out", _I32), ("hidden", _I32), ("max_batch", _I32),
+                ("lr", _D), ("beta1", _D), ("beta2", _D), ("eps", _D),
+                ("in_mean", ctypes.POINTER(ctypes.c_float)), ("in_std", ctypes.POINTER(ctypes.c_float)),
+                ("out_mean", ctypes.POINTER(ctypes.c_float)), ("out_std", ctypes.POINTER(ctypes.c_float))]
+
+
+MLP_SYMBOLS = ["mlp_workspace_bytes", "mlp_init", "mlp_param_count", "mlp_set_params", "mlp_get_params",
+               "mlp_forward", "mlp_train_step", "mlp_get_grads", "mlp_sync", "mlp_destroy", "mlp_last_error"]
+SYMBOLS += MLP_SYMBOLS
+
+_MLP_BOUND = False
+_PF = ctypes.POINTER(ctypes.c_float)
+
+
+def _mlp_lib():
+    global _MLP_BOUND
+    L = lib()
+    if not _MLP_BOUND:
+        P = ctypes.c_void_p
+        L.mlp_workspace_bytes.argtypes = [ctypes.POINTER(MlpConfig), ctypes.POINTER(ctypes.c_size_t)]
+        L.mlp_init.argtypes = [ctypes.POINTER(MlpConfig), P, ctypes.c_size_t, P, ctypes.POINTER(P)]
+        L.mlp_param_count.argtypes = [P, ctypes.POINTER(_I64)]
+        L.mlp_set_params.argtypes = [P, _PF]
+        L.mlp_get_params.argtypes = [P, _PF]
+        L.mlp_get_grads.argtypes = [P, _PF]
+        L.mlp_forward.argtypes = [P, P, _I32, P]
+        L.mlp_train_step.argtypes = [P, P, P, _I32, _PF]
+        L.mlp_sync.argtypes = [P]
+        L.mlp_destroy.argtypes = [P]
+        L.mlp_destroy.restype = None
+        L.mlp_last_error.argtypes = [P]
+        L.mlp_last_error.restype = ctypes.c_char_p
+        for name in MLP_SYMBOLS:
+            if name not in ("mlp_destroy", "mlp_last_error"):
+                getattr(L, name).restype = _I32
+        _MLP_BOUND = True
+    return L
+
+
+class Mlp:
+    """An mlp_ctx with its torch workspace.  x, t, y are torch FP32 device
+    tensors; parameters move as numpy FP32 vectors."""
+
+    def __init__(self, n_in=W.MLP_IN, n_out=W.MLP_OUT, hidden=W.MLP_HIDDEN, max_batch=4096, lr=1e-3,
+                 beta1=0.9, beta2=0.999, eps=1e-8, norm=None, device="cuda"):
+        import torch
+        L = _mlp_lib()
+        c = MlpConfig()
+        c.n_in, c.n_out, c.hidden, c.max_batch = n_in, n_out, hidden, max_batch
+        c.lr, c.beta1, c.beta2, c.eps = lr, beta1, beta2, eps
+        self._keep = []
+        if norm is not None:
+            arrs = [np.ascontiguousarray(a, dtype=np.float32) for a in norm]
+            self._keep += arrs
+            c.in_mean, c.in_std, c.out_mean, c.out_std = (a.ctypes.data_as(_PF) for a in arrs)
+        n = ctypes.c_size_t()
+        st = L.mlp_workspace_bytes(ctypes.byref(c), ctypes.byref(n))
+        if st:
+            raise PicError(st, "mlp_workspace_bytes: bad configuration")
+        self.ws = torch.empty(n.value, dtype=torch.uint8, device=device)
+        stream = torch.cuda.current_stream(self.ws.device).cuda_stream
+        h = ctypes.c_void_p()
+        st = L.mlp_init(ctypes.byref(c), ctypes.c_void_p(self.ws.data_ptr()), n.value, ctypes.c_void_p(stream),
+                        ctypes.byref(h))
+        if st:
+            raise PicError(st, "mlp_init failed")
+        self.handle, self.cfg = h, c
+        cnt = _I64()
+        self.check(L.mlp_param_count(h, ctypes.byref(cnt)))
+        self.n_params = cnt.value
+
+    def check(self, st):
+        if st != PIC_OK:
+            raise PicError(st, _mlp_lib().mlp_last_error(self.handle).decode())
+        return st
+
+    def set_params(self, theta):
+        a = np.ascontiguousarray(theta, dtype=np.float32)
+        assert a.size == self.n_params
+        self.check(_mlp_lib().mlp_set_params(self.handle, a.ctypes.data_as(_PF)))
+
+    def get_params(self):
+        a = np.zeros(self.n_params, np.float32)
+        self.check(_mlp_lib().mlp_get_params(self.handle, a.ctypes.data_as(_PF)))
+        return a
+
+    def get_grads(self):
+        a = np.zeros(self.n_params, np.float32)
+        self.check(_mlp_lib().mlp_get_grads(self.handle, a.ctypes.data_as(_PF)))
+        return a
+
+    def forward(self, x, y=None):
+        import torch
+        x = x.contiguous()
+        if y is None:
+            y = torch.empty((x.shape[0], self.cfg.n_out), dtype=torch.float32, device=x.device)
+        self.check(_mlp_lib().mlp_forward(self.handle, ctypes.c_void_p(x.data_ptr()), x.shape[0],
+                                          ctypes.c_void_p(y.data_ptr())))
+        return y
+
+    def train_step(self, x, t, want_loss=True):
+        x, t = x.contiguous(), t.contiguous()
+        loss = ctypes.c_float()
+        self.check(_mlp_lib().mlp_train_step(self.handle, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(t.data_ptr()),
+                                             x.shape[0], ctypes.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def sync(self):
+        self.check(_mlp_lib().mlp_sync(self.handle))
+
+    def __del__(self):
+        try:
+            if self.handle:
+                _mlp_lib().mlp_destroy(self.handle)
+                self.handle = None
+        except Exception:
+            pass
