@@ -179,6 +179,7 @@ typedef struct pic_stats {
 } pic_stats;
 
 typedef struct pic_ctx pic_ctx;
+typedef struct mlp_ctx mlp_ctx;
 
 /* Bytes of device workspace pic_init needs for this configuration. */
 pic_status pic_workspace_bytes(const pic_config *cfg, size_t *bytes);
@@ -262,7 +263,31 @@ typedef struct pic_period_report {
     double x_re[33], x_im[33];        /* relaxed state applied in the next period */
     int32_t helm_cycles[2];  /* CG iterations of the two plasma-only inductive solves */
     double helm_rel[2];      /* and their final relative residuals */
+    double xp_re[33], xp_im[33];      /* state applied during the completed period */
+    double pressure;         /* gas pressure (Pa) */
+    /* plasma moments at the end of the period: <n_e>, <n_i> (m^-3, over the
+     * particle box), max n_e (m^-3, nodes), <eps_e>, <eps_i> (eV), electron
+     * centroid R, z (m), ionizations during the period */
+    double moments[8];
+    int32_t sur_used;        /* 1: the surrogate-assisted update was applied */
+    int32_t sur_iters;       /* its inner fixed-point iterations */
+    double sur_err;          /* scaled prediction error at the applied state */
 } pic_period_report;
+
+/* Surrogate-assisted circuit update (the learned predictor of the load
+ * responses).  With a network attached, circuit_period_update predicts
+ * yhat(x^n) = (V_p, I_cap) from the applied state, pressure and moments,
+ * and compares it with the measured y_n (V_p scaled by |V_g|, I_cap by
+ * |I_f|).  Above err_max the plain update runs; otherwise the state
+ * iterates x_{i+1} = relax(network(yhat(x_i) + y_n - yhat(x^n), V_g,i)),
+ * with the controller acting on each iterate's port power inside the
+ * period's step bounds, until the relative step is below tol or max_iter,
+ * and the converged state is applied. */
+typedef struct pic_surrogate_config {
+    double err_max;          /* e.g. 0.02 */
+    double tol;              /* e.g. 1e-6 */
+    int32_t max_iter;        /* e.g. 50 */
+} pic_surrogate_config;
 
 /* Inductive-port data of a coupled context (pic_get_circuit). */
 typedef struct pic_circuit_info {
@@ -296,6 +321,17 @@ typedef struct pic_circuit_info {
 pic_status circuit_period_update(pic_ctx *ctx, const double *new_vc, const double *new_vs,
                                  const double *new_ec, const double *new_es_sto,
                                  pic_period_report *report, double *jc, double *js);
+
+/* Set the Thevenin source amplitude (V, > 0) and phase (rad) used by the
+ * next circuit update of a coupled context (the controller, when on, starts
+ * from this amplitude).  For scans of the operating point. */
+pic_status pic_set_source(pic_ctx *ctx, double vg_amp, double vg_phase);
+
+/* Attach (net != NULL) or detach (NULL) a surrogate network: n_in = 4 N + 9
+ * (turn current and voltage phasors, pressure, the eight moments), n_out =
+ * 4 N (V_p and I_cap phasors), N <= 5, same stream as the context.  The
+ * network stays owned by the caller and must outlive the attachment. */
+pic_status pic_attach_surrogate(pic_ctx *ctx, mlp_ctx *net, const pic_surrogate_config *cfg);
 
 /* Copy the inductive-port data and the applied circuit state of a coupled
  * context (synchronising); PIC_EINVAL without cfg->circuit. */
@@ -353,8 +389,6 @@ const char *pic_last_error(const pic_ctx *ctx);
  *   W1 [hidden x 32], b1 [hidden], W2 [hidden x hidden], b2, W3, b3,
  *   W4 [32 x hidden], b4 [32]   (W row-major, rows = outputs).
  * ------------------------------------------------------------------------ */
-typedef struct mlp_ctx mlp_ctx;
-
 typedef struct mlp_config {
     int32_t n_in, n_out;      /* 1..32 */
     int32_t hidden;           /* multiple of 64 */

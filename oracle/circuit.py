@@ -358,10 +358,15 @@ class FieldCircuit:
         self.Es_p = self.helm.solve(Jc / self.vnode)
         return self.Ec_p, self.Es_p
 
-    def update(self, h):
-        """Closed-period update from finalised harmonics h (the dict of
-        Harmonics.finalize).  Returns the period report."""
-        N, w = self.N, self.omega
+    def set_source(self, amp, phase=0.0):
+        self.vg_amp = amp
+        self.p.vg_phase = phase
+        self.vg = amp * complex(math.cos(phase), math.sin(phase))
+
+    def _measure(self, h):
+        """Loads and powers of the completed period (plain and surrogate
+        updates share them)."""
+        N = self.N
         x_n = self.x
         self.plasma_fields(h["Jc"], h["Js"])
         vp = v_p_ind(self.g, self.Ec_p, self.Es_p, self.wts)
@@ -370,7 +375,85 @@ class FieldCircuit:
         pcu = 0.5 * float(np.sum(self.rrf * np.abs(x_n[1:1 + N]) ** 2))
         pbal = h["P_ind"] + h["P_cap"] + pcu
         eps_bal = abs(pp - pbal) / abs(pp) if pp != 0 else float("inf")
+        return x_n, vp, icap, pp, pcu, eps_bal
+
+    def _report(self, h, x_n, vp, icap, pp, pcu, eps_bal, xt, vg_old, pf, pc, loads=None):
+        N, w = self.N, self.omega
+        li, lv = (icap, vp) if loads is None else loads
+        rI, rV = network_residuals(self.x, self.vg, self.Zs, self.Zturn, self.cstray, w, li, lv)
+        iscale = abs(self.x[0]) if abs(self.x[0]) > 0 else 1.0
+        self.Ec, self.Es = compose(self.Ec_p, self.Es_p, self.U, self.x[1:1 + N])
+        return dict(p_port=pp, p_ind=h["P_ind"], p_cap=h["P_cap"], p_cap_ph=h["P_cap_ph"], p_cu=pcu,
+                    eps_bal=eps_bal, vp=vp, icap=icap, x_prev=x_n, x_target=xt, x=self.x.copy(),
+                    vg=self.vg, vg_old=vg_old, pf=pf, pc=pc,
+                    kcl=float(np.max(np.abs(rI))) / iscale, kvl=float(np.max(np.abs(rV))) / abs(self.vg))
+
+    def features(self, x, pressure, moments):
+        """Surrogate input: (I_k re, im), (V_k re, im), pressure, moments."""
+        N = self.N
+        f = []
+        for k in range(N):
+            f += [x[1 + k].real, x[1 + k].imag]
+        for k in range(N):
+            f += [x[1 + N + k].real, x[1 + N + k].imag]
+        return np.array(f + [pressure] + list(moments))
+
+    def update_surrogate(self, h, pressure, moments, predict, err_max=0.02, tol=1e-6, max_iter=50):
+        """Surrogate-assisted closed-period update: predict the load
+        responses yhat(x^n); beyond err_max (V_p scaled by |V_g|, I_cap by
+        |I_f|) fall back to the plain update; else iterate the relaxed
+        network solve with loads yhat(x_i) + (y_n - yhat(x^n)) and a
+        controller step on each iterate's port power, within the period's
+        step bounds, and apply the converged state."""
+        N = self.N
+        x_n, vp, icap, pp, pcu, eps_bal = self._measure(h)
         vg_old = self.vg_amp
+        y = np.concatenate([np.ravel(np.column_stack([vp.real, vp.imag])),
+                            np.ravel(np.column_stack([icap.real, icap.imag]))])
+        yh = np.asarray(predict(self.features(x_n, pressure, moments)), dtype=np.float64)
+        sc = np.concatenate([np.full(2 * N, 1.0 / abs(self.vg_amp)), np.full(2 * N, 1.0 / max(abs(x_n[0]), 1e-300))])
+        err = math.sqrt(np.sum(((yh - y) * sc) ** 2) / np.sum((y * sc) ** 2))
+        corr = y - yh
+        if not err <= err_max:
+            rep = self._plain(h, x_n, vp, icap, pp, pcu, eps_bal, vg_old)
+            rep.update(sur_used=0, sur_iters=0, sur_err=err)
+            return rep
+        xi, vgi = x_n.copy(), self.vg_amp
+        it = 0
+        ph = complex(math.cos(self.p.vg_phase), math.sin(self.p.vg_phase))
+        loads = None
+        for it in range(1, max_iter + 1):
+            l = np.asarray(predict(self.features(xi, pressure, moments)), dtype=np.float64) + corr
+            lv = l[0:2 * N:2] + 1j * l[1:2 * N:2]
+            li = l[2 * N::2] + 1j * l[2 * N + 1::2]
+            loads = (li, lv)
+            if self.ctrl is not None:
+                c = self.ctrl
+                pc = max(p_port(xi, N), c.eps_p)
+                vn = vgi + c.alpha_v * (vgi * math.sqrt(c.p_target / pc) - vgi)
+                vn = min(max(vn, (1 - c.f_step) * vg_old), (1 + c.f_step) * vg_old)
+                vgi = min(max(vn, c.v_min), c.v_max)
+            xt = np.linalg.solve(self.A, network_rhs(vgi * ph, li, lv))
+            a = self.p.alpha
+            new = (1 - a) * xi + a * xt
+            step = np.linalg.norm(new - xi) / np.linalg.norm(new)
+            xi = new
+            if not np.isfinite(step) or np.linalg.norm(xi) ** 2 > 1e6 * np.linalg.norm(x_n) ** 2:
+                # the predicted load map does not contract here: plain update
+                rep = self._plain(h, x_n, vp, icap, pp, pcu, eps_bal, vg_old)
+                rep.update(sur_used=0, sur_iters=it, sur_err=err)
+                return rep
+            if step < tol:
+                break
+        self.x = xi
+        self.vg_amp, self.vg = vgi, vgi * ph
+        if self.ctrl is not None:
+            self.ctrl.pf_prev = p_port(self.x, N)
+        rep = self._report(h, x_n, vp, icap, pp, pcu, eps_bal, xt, vg_old, None, None, loads)
+        rep.update(sur_used=1, sur_iters=it, sur_err=err)
+        return rep
+
+    def _plain(self, h, x_n, vp, icap, pp, pcu, eps_bal, vg_old):
         pf = pc = None
         if self.ctrl is not None:
             self.vg_amp, pf, pc = self.ctrl.step(vg_old, pp)
@@ -378,10 +461,10 @@ class FieldCircuit:
         xt = np.linalg.solve(self.A, network_rhs(self.vg, icap, vp))
         a = self.p.alpha
         self.x = (1 - a) * x_n + a * xt
-        rI, rV = network_residuals(self.x, self.vg, self.Zs, self.Zturn, self.cstray, w, icap, vp)
-        iscale = abs(self.x[0]) if abs(self.x[0]) > 0 else 1.0
-        self.Ec, self.Es = compose(self.Ec_p, self.Es_p, self.U, self.x[1:1 + N])
-        return dict(p_port=pp, p_ind=h["P_ind"], p_cap=h["P_cap"], p_cap_ph=h["P_cap_ph"], p_cu=pcu,
-                    eps_bal=eps_bal, vp=vp, icap=icap, x_prev=x_n, x_target=xt, x=self.x.copy(),
-                    vg=self.vg, vg_old=vg_old, pf=pf, pc=pc,
-                    kcl=float(np.max(np.abs(rI))) / iscale, kvl=float(np.max(np.abs(rV))) / abs(self.vg))
+        return self._report(h, x_n, vp, icap, pp, pcu, eps_bal, xt, vg_old, pf, pc)
+
+    def update(self, h):
+        """Closed-period update from finalised harmonics h (the dict of
+        Harmonics.finalize).  Returns the period report."""
+        x_n, vp, icap, pp, pcu, eps_bal = self._measure(h)
+        return self._plain(h, x_n, vp, icap, pp, pcu, eps_bal, self.vg_amp)

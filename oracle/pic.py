@@ -444,6 +444,10 @@ class OraclePIC:
         # field-circuit coupling (oracle/circuit.py)
         self.fc = None
         self.last_report = None
+        self.surrogate = None          # callable features -> predicted (V_p, I_cap) vector, or None
+        self.sur_cfg = dict(err_max=0.02, tol=1e-6, max_iter=50)
+        self.births_total = 0
+        self.births_prev = 0
         if wl.circuit is not None:
             from .circuit import FieldCircuit
             self.fc = FieldCircuit(wl.nr, wl.nz, wl.dr, wl.dz, wl.node_tag, wl.eps_cell, wl.freq, W.EPS0,
@@ -520,6 +524,7 @@ class OraclePIC:
             self.next_id[0] += nb
             self.next_id[1] += nb
         self.last_births = (bp, ide if nb else np.zeros(0), idi if nb else np.zeros(0))
+        self.births_total += nb
 
     def deposit(self):
         Q = np.zeros(self.shape)
@@ -541,17 +546,56 @@ class OraclePIC:
     def harmonic(self, n):
         self.harm.add(n, self.I, self.etheta(n), self.Qk, self.turn_phi(n))
 
+    def moments(self):
+        """Plasma moments of the current particles: <n_e>, <n_i> over the
+        particle box (m^-3), the largest electron node density (m^-3, node
+        weights over the node control volume), <eps_e>, <eps_i> (eV), the
+        electron centroid R, z (m) and the ionizations since the last call."""
+        from .circuit import node_volume
+        wl = self.wl
+        vol = math.pi * wl.rmax ** 2 * wl.zp
+        out = []
+        for s in range(2):
+            P = self.parts[s]
+            a = P.alive.astype(bool)
+            out.append((a.sum(), P, a))
+        (ne, Pe, ae), (ni, Pi, ai) = out
+        we, wi = self.sp[0].w, self.sp[1].w
+        Wn = np.zeros(self.shape)
+        lib().ora_deposit(ctypes.byref(self.grid), Pe.n, _p(Pe.R, _D), _p(Pe.z, _D), _p(Pe.alive, _I32), we,
+                          _p(Wn, _D))
+        nmax = float(np.max(Wn / node_volume(wl.nr, wl.nz, wl.dr, wl.dz)))
+        me, mi = self.sp[0].m, self.sp[1].m
+
+        def energy(P, a, m):
+            v2 = P.vr[a] ** 2 + P.vt[a] ** 2 + P.vz[a] ** 2
+            return float(np.mean(0.5 * m * v2 / self.W.QE)) if a.any() else 0.0
+
+        ion = self.births_total - self.births_prev
+        self.births_prev = self.births_total
+        return np.array([ne * we / vol, ni * wi / vol, nmax, energy(Pe, ae, me), energy(Pi, ai, mi),
+                         float(np.mean(Pe.R[ae])) if ne else 0.0, float(np.mean(Pe.z[ae])) if ne else 0.0,
+                         float(ion)])
+
     def period_update(self):
         """Close the RF period: finalise the harmonics and, when coupled,
-        update the circuit and the next period's turn potentials and field.
-        Returns the report (None and restart of the accumulators when the
-        sample count is not N_RF)."""
+        update the circuit (plainly, or surrogate-assisted when a predictor
+        is set) and the next period's turn potentials and field.  Returns
+        the report (None and restart of the accumulators when the sample
+        count is not N_RF)."""
         r = self.harm.finalize(self.vc, self.vs)
         self.reset_harmonics()
         if r is None:
             return None
         if self.fc is not None:
-            rep = self.fc.update(r)
+            mom = self.moments()
+            pressure = self.wl.pressure_pa
+            if self.surrogate is not None:
+                rep = self.fc.update_surrogate(r, pressure, mom, self.surrogate, **self.sur_cfg)
+            else:
+                rep = self.fc.update(r)
+            rep["moments"] = mom
+            rep["pressure"] = pressure
             self.vc, self.vs, self.ec, self.es = self.fc.turn_vc, self.fc.turn_vs, self.fc.Ec, self.fc.Es
             r = {**r, **rep}
         self.last_report = r

@@ -150,6 +150,10 @@ struct pic_ctx {
     std::vector<double> area;
     int helm_cycles[2]{};
     double helm_rel[2]{};
+    // surrogate network (owned by the caller) and its device buffers
+    mlp_ctx *net = nullptr;
+    float *feat = nullptr, *pred = nullptr;
+    double *mompart = nullptr;
 
     // HIP-event timing: ring of (start, stop) pairs per timed region
     struct Timer {
@@ -535,6 +539,9 @@ static void layout(pic_ctx &c, Carver &cv)
     c.gval = cv.take<double>(MAX_TURNS);
     c.plist = cv.take<int32_t>(nturn_nodes + 1);
     c.pturn = cv.take<int32_t>(nturn_nodes + 1);
+    c.feat = cv.take<float>(32);
+    c.pred = cv.take<float>(32);
+    c.mompart = cv.take<double>((size_t)moments_blocks() * MOM_SUMS);
     if (f.circuit) {
         c.hgs = cv.take<MGState>(1);
         c.htag = cv.take<int32_t>(nodes);
@@ -1040,6 +1047,7 @@ static pic_status circuit_init(pic_ctx &c)
     h.v_max = f.v_max;
     h.vg_amp = f.vg_amp;
     h.vg_phase = f.vg_phase;
+    h.pressure = f.ngas * f.tgas_ev * f.qe;
     HIPCHK(&c, cpy(c.stream, c.cd, &h, sizeof h, hipMemcpyHostToDevice));
     // inductive operator hierarchy
     Coeffs co;
@@ -1332,6 +1340,74 @@ extern "C" pic_status harmonic_accumulate(pic_ctx *c, int64_t n)
     return hipGetLastError() == hipSuccess ? PIC_OK : fail(c, PIC_EDEVICE, "kernel launch failed");
 }
 
+// Surrogate-assisted update (see pic_attach_surrogate): measurement, the
+// prediction at the applied state, then the inner fixed point with one
+// network prediction per iterate.
+static pic_status surrogate_update(pic_ctx &c)
+{
+    launch_circuit(c.cd, c.harm, c.d_vc, c.d_vs, 3, c.stream);
+    launch_features(c.cd, c.feat, false, c.stream);
+    pic_status st = mlp_forward(c.net, c.feat, 1, c.pred);
+    if (st) return fail(&c, st, "surrogate forward: %s", mlp_last_error(c.net));
+    launch_surrogate(c.cd, c.pred, c.d_vc, c.d_vs, 0, c.stream);
+    const int maxit = c.cdh.sur_max_iter;
+    int32_t done = 0;
+    for (int it = 0; it < maxit; ++it) {
+        if (it % 5 == 0) {
+            HIPCHK(&c, cpy(c.stream, &done, reinterpret_cast<char *>(c.cd) + offsetof(CircuitDev, sur_done), 4,
+                           hipMemcpyDeviceToHost));
+            if (done) break;
+        }
+        launch_features(c.cd, c.feat, true, c.stream);
+        st = mlp_forward(c.net, c.feat, 1, c.pred);
+        if (st) return fail(&c, st, "surrogate forward: %s", mlp_last_error(c.net));
+        launch_surrogate(c.cd, c.pred, c.d_vc, c.d_vs, 1, c.stream);
+    }
+    launch_surrogate(c.cd, c.pred, c.d_vc, c.d_vs, 2, c.stream);
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_set_source(pic_ctx *c, double vg_amp, double vg_phase)
+{
+    if (!c) return PIC_EINVAL;
+    if (!c->cfg.circuit) return fail(c, PIC_EINVAL, "context without circuit coupling");
+    if (!(vg_amp > 0.0)) return fail(c, PIC_EINVAL, "vg_amp must be positive");
+    char *d = reinterpret_cast<char *>(c->cd);
+    HIPCHK(c, cpy(c->stream, d + offsetof(CircuitDev, vg_amp), &vg_amp, 8, hipMemcpyHostToDevice));
+    HIPCHK(c, cpy(c->stream, d + offsetof(CircuitDev, vg_phase), &vg_phase, 8, hipMemcpyHostToDevice));
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_attach_surrogate(pic_ctx *c, mlp_ctx *net, const pic_surrogate_config *sc)
+{
+    if (!c) return PIC_EINVAL;
+    if (!net) {
+        c->net = nullptr;
+        return PIC_OK;
+    }
+    if (!c->cfg.circuit) return fail(c, PIC_EINVAL, "surrogate needs a coupled context");
+    if (!sc || !(sc->err_max > 0.0) || !(sc->tol > 0.0) || sc->max_iter < 1)
+        return fail(c, PIC_EINVAL, "surrogate settings invalid");
+    const int N = c->cfg.nturns;
+    if (N > SUR_MAX_TURNS) return fail(c, PIC_EINVAL, "surrogate supports at most %d turns", SUR_MAX_TURNS);
+    int n_in = 0, n_out = 0;
+    void *nst = nullptr;
+    mlp_shape(net, &n_in, &n_out, &nst);
+    if (n_in != 4 * N + 9 || n_out != 4 * N)
+        return fail(c, PIC_EINVAL, "surrogate network has %d -> %d, needs %d -> %d", n_in, n_out, 4 * N + 9, 4 * N);
+    if (nst != (void *)c->stream) return fail(c, PIC_EINVAL, "surrogate network must use the context's stream");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->cdh.sur_err_max = sc->err_max;
+    c->cdh.sur_tol = sc->tol;
+    c->cdh.sur_max_iter = sc->max_iter;
+    char *d = reinterpret_cast<char *>(c->cd);
+    HIPCHK(c, cpy(c->stream, d + offsetof(CircuitDev, sur_max_iter), &c->cdh.sur_max_iter, 4, hipMemcpyHostToDevice));
+    HIPCHK(c, cpy(c->stream, d + offsetof(CircuitDev, sur_err_max), &c->cdh.sur_err_max, 8, hipMemcpyHostToDevice));
+    HIPCHK(c, cpy(c->stream, d + offsetof(CircuitDev, sur_tol), &c->cdh.sur_tol, 8, hipMemcpyHostToDevice));
+    c->net = net;
+    return PIC_OK;
+}
+
 static pic_status reset_period(pic_ctx *c)
 {
     const int nodes = c->g.nodes;
@@ -1381,8 +1457,35 @@ extern "C" pic_status circuit_period_update(pic_ctx *c, const double *new_vc, co
         launch_project(c->Ep, 2, nodes, c->plist, c->pturn, c->nlist, c->gval, K,
                        reinterpret_cast<double *>(reinterpret_cast<char *>(c->cd) + offsetof(CircuitDev, proj)), 2,
                        c->g, c->stream);
-        launch_circuit(c->cd, c->harm, c->d_vc, c->d_vs, 1, c->stream);
+        // plasma moments of the completed period (surrogate features, report)
+        {
+            const pic_config &f = c->cfg;
+            if (c->mixed)
+                launch_moments<float>(c->pf[0][c->cur[0]], c->pf[1][c->cur[1]], c->ctl, c->accQ, c->qscale, f.w[0],
+                                      f.w[1], f.m[0], f.m[1], f.qe, c->mompart, moments_blocks(), c->cd, c->stats,
+                                      c->g, c->stream);
+            else
+                launch_moments<double>(c->pd[0][c->cur[0]], c->pd[1][c->cur[1]], c->ctl, c->accQ, c->qscale, f.w[0],
+                                       f.w[1], f.m[0], f.m[1], f.qe, c->mompart, moments_blocks(), c->cd, c->stats,
+                                       c->g, c->stream);
+        }
+        // the state applied during the completed period, for the report
+        HIPCHK(c, cpy(c->stream, c->cdh.x_re, reinterpret_cast<char *>(c->cd) + offsetof(CircuitDev, x_re),
+                      sizeof(c->cdh.x_re) + sizeof(c->cdh.x_im), hipMemcpyDeviceToHost));
+        double xp[2 * MAX_X];
+        std::memcpy(xp, c->cdh.x_re, sizeof xp);
+        if (c->net) {
+            st = surrogate_update(*c);
+            if (st) return st;
+        } else {
+            launch_circuit(c->cd, c->harm, c->d_vc, c->d_vs, 1, c->stream);
+        }
         launch_compose(c->Ep, c->Ep + nodes, c->U, nodes, c->cd, c->d_ec, c->d_es, nodes, c->stream);
+        if (rep)
+            for (int r = 0; r < 2 * K + 1; ++r) {
+                rep->xp_re[r] = xp[r];
+                rep->xp_im[r] = xp[MAX_X + r];
+            }
     } else {
         launch_circuit(c->cd, c->harm, c->d_vc, c->d_vs, 2, c->stream);
     }
@@ -1425,6 +1528,11 @@ extern "C" pic_status circuit_period_update(pic_ctx *c, const double *new_vc, co
                 rep->helm_cycles[q] = c->helm_cycles[q];
                 rep->helm_rel[q] = c->helm_rel[q];
             }
+            rep->pressure = h.pressure;
+            for (int q = 0; q < 8; ++q) rep->moments[q] = h.moments[q];
+            rep->sur_used = c->net ? h.sur_used : 0;
+            rep->sur_iters = c->net ? h.sur_iters : 0;
+            rep->sur_err = c->net ? h.sur_err : 0.0;
         }
     }
     if (jc || js) {

@@ -73,7 +73,8 @@ __global__ void k_project(const double *fields, int nf, int64_t stride, const in
 // mode 1: finalise the period's harmonics and powers, controller, target
 //         network solve, relaxation, residuals;
 // mode 2: finalise the period's harmonics and powers only (prescribed
-//         turn potentials and field).
+//         turn potentials and field);
+// mode 3: finalise and measure only (the surrogate stages follow).
 // New turn potentials V_c = Re V_k, V_s = -Im V_k go to vc / vs.
 // ---------------------------------------------------------------------------
 struct Cx {
@@ -122,164 +123,253 @@ __device__ Cx net_entry(const CircuitDev &c, int r, int col)
     return v;
 }
 
-__global__ __launch_bounds__(64) void k_circuit(CircuitDev *cdp, const HarmState *h, double *vc, double *vs,
-                                                int mode)
+// Shared memory of one network solve.
+struct NetSmem {
+    double Are[MAX_X][MAX_X], Aim[MAX_X][MAX_X];
+    double bre[MAX_X], bim[MAX_X];
+    int piv;
+};
+
+// The whole workgroup solves A x = b (Eq. blockmatrix) for source V_g and
+// loads (icap, vp) by Gaussian elimination with partial pivoting (largest
+// |re| + |im|); thread 0 writes x.  Returns false (every thread) when
+// singular.
+__device__ bool network_solve(const CircuitDev &c, Cx vg, const double *icap_re, const double *icap_im,
+                              const double *vp_re, const double *vp_im, double *x_re, double *x_im, NetSmem &S)
 {
-    __shared__ double Are[MAX_X][MAX_X], Aim[MAX_X][MAX_X];
-    __shared__ double bre[MAX_X], bim[MAX_X];
-    __shared__ int piv;
-    const int t = threadIdx.x;
-    CircuitDev &c = *cdp;
-    const int N = c.N, M = 2 * N + 1;
-
-    if (t == 0 && mode != 0) {
-        // period finalisation (Eqs. fourier, icap, pind, pcap, pcap_phasor)
-        const double two_n = 2.0 / c.nrf;
-        double wsum = 0.0, pph = 0.0;
-        for (int k = 0; k < N; ++k) {
-            const double qc = two_n * (h->qc[k] + h->qc_c[k]), qs = two_n * (h->qs[k] + h->qs_c[k]);
-            c.qc[k] = qc;
-            c.qs[k] = qs;
-            c.icap_re[k] = c.omega * qs;
-            c.icap_im[k] = c.omega * qc;
-            const double Wk = (h->w[k] + h->w_c[k]) + 0.5 * (h->v_first[k] + h->v_prev[k]) * (h->q_first[k] - h->q_prev[k]);
-            c.wk[k] = Wk;
-            wsum += Wk;
-            // 1/2 Re(V conj(I_cap)) with V = V_c - i V_s
-            pph += 0.5 * (vc[k] * c.icap_re[k] - vs[k] * c.icap_im[k]);
-        }
-        c.samples = h->samples;
-        c.p_ind = (h->pind + h->pind_c) / c.nrf;
-        c.p_cap = c.freq * wsum;
-        c.p_cap_ph = pph;
-    }
-    if (mode == 2) return;
-
-    if (t == 0 && mode == 1) {
-        // loads of the completed period (Eq. vpind) and its powers (Eqs. pport, pbalance)
-        for (int k = 0; k < N; ++k) {
-            c.vp_re[k] = -c.proj[2 * k];
-            c.vp_im[k] = -c.proj[2 * k + 1];
-        }
-        c.p_port = 0.5 * (c.x_re[1 + N] * c.x_re[0] + c.x_im[1 + N] * c.x_im[0]);
-        double pcu = 0.0;
-        for (int k = 0; k < N; ++k) pcu += 0.5 * c.rrf[k] * (c.x_re[1 + k] * c.x_re[1 + k] + c.x_im[1 + k] * c.x_im[1 + k]);
-        c.p_cu = pcu;
-        const double bal = c.p_ind + c.p_cap + pcu;
-        c.eps_bal = c.p_port != 0.0 ? fabs(c.p_port - bal) / fabs(c.p_port) : INFINITY;
-        c.vg_old = c.vg_amp;
-        if (c.controller) {   // Eqs. pfilter, ptrend, pcontrol, limiter, bounds
-            const double prev = c.have_pf ? c.pf_prev : c.p_port;
-            const double pf = c.gamma * c.p_port + (1.0 - c.gamma) * prev;
-            const double pc = fmax(pf + c.n_trend * (pf - prev), c.eps_p);
-            const double vold = c.vg_amp;
-            double vn = vold + c.alpha_v * (vold * sqrt(c.p_target / pc) - vold);
-            vn = fmin(fmax(vn, (1.0 - c.f_step) * vold), (1.0 + c.f_step) * vold);
-            vn = fmin(fmax(vn, c.v_min), c.v_max);
-            c.vg_amp = vn;
-            c.pf_prev = pf;
-            c.have_pf = 1;
-            c.pf = pf;
-            c.pc = pc;
-        }
-    }
-    __syncthreads();
-
-    // assemble the network and its right-hand side
-    const Cx vg1{cos(c.vg_phase), sin(c.vg_phase)};
+    const int t = threadIdx.x, N = c.N, M = 2 * N + 1;
     for (int e = t; e < M * M; e += blockDim.x) {
         const int r = e / M, col = e - r * M;
         const Cx v = net_entry(c, r, col);
-        Are[r][col] = v.re;
-        Aim[r][col] = v.im;
+        S.Are[r][col] = v.re;
+        S.Aim[r][col] = v.im;
     }
     for (int r = t; r < M; r += blockDim.x) {
         Cx v{0.0, 0.0};
-        if (r == 0) {
-            // init with the target-power start solves for V_g = 1 first
-            const double a = (mode == 0 && c.vg_from_target) ? 1.0 : c.vg_amp;
-            v = {a * vg1.re, a * vg1.im};
-        } else if (mode == 1 && r <= N) {
-            v = {c.icap_re[r - 1], c.icap_im[r - 1]};
-        } else if (mode == 1) {
-            v = {c.vp_re[r - 1 - N], c.vp_im[r - 1 - N]};
-        }
-        bre[r] = v.re;
-        bim[r] = v.im;
+        if (r == 0)
+            v = vg;
+        else if (r <= N)
+            v = {icap_re[r - 1], icap_im[r - 1]};
+        else
+            v = {vp_re[r - 1 - N], vp_im[r - 1 - N]};
+        S.bre[r] = v.re;
+        S.bim[r] = v.im;
     }
     __syncthreads();
-
-    // Gaussian elimination with partial pivoting (largest |re| + |im|)
     for (int col = 0; col < M; ++col) {
         if (t == 0) {
             int p = col;
-            double best = cabs1({Are[col][col], Aim[col][col]});
+            double best = cabs1({S.Are[col][col], S.Aim[col][col]});
             for (int r = col + 1; r < M; ++r) {
-                const double m = cabs1({Are[r][col], Aim[r][col]});
+                const double m = cabs1({S.Are[r][col], S.Aim[r][col]});
                 if (m > best) {
                     best = m;
                     p = r;
                 }
             }
-            piv = best > 0.0 ? p : -1;
-            if (best == 0.0) c.singular = 1;
+            S.piv = best > 0.0 ? p : -1;
         }
         __syncthreads();
-        const int p = piv;
-        if (p < 0) return;
+        const int p = S.piv;
+        if (p < 0) return false;
         if (p != col) {
             for (int k = t; k < M; k += blockDim.x) {
-                double x = Are[p][k];
-                Are[p][k] = Are[col][k];
-                Are[col][k] = x;
-                x = Aim[p][k];
-                Aim[p][k] = Aim[col][k];
-                Aim[col][k] = x;
+                double x = S.Are[p][k];
+                S.Are[p][k] = S.Are[col][k];
+                S.Are[col][k] = x;
+                x = S.Aim[p][k];
+                S.Aim[p][k] = S.Aim[col][k];
+                S.Aim[col][k] = x;
             }
             if (t == 0) {
-                double x = bre[p];
-                bre[p] = bre[col];
-                bre[col] = x;
-                x = bim[p];
-                bim[p] = bim[col];
-                bim[col] = x;
+                double x = S.bre[p];
+                S.bre[p] = S.bre[col];
+                S.bre[col] = x;
+                x = S.bim[p];
+                S.bim[p] = S.bim[col];
+                S.bim[col] = x;
             }
         }
         __syncthreads();
-        // multipliers of the rows below, then the row updates
-        const Cx d{Are[col][col], Aim[col][col]};
+        const Cx d{S.Are[col][col], S.Aim[col][col]};
         for (int r = col + 1 + t; r < M; r += blockDim.x) {
-            const Cx f = cdiv({Are[r][col], Aim[r][col]}, d);
+            const Cx f = cdiv({S.Are[r][col], S.Aim[r][col]}, d);
             for (int k = col + 1; k < M; ++k) {
-                const Cx u = csub({Are[r][k], Aim[r][k]}, cmul(f, {Are[col][k], Aim[col][k]}));
-                Are[r][k] = u.re;
-                Aim[r][k] = u.im;
+                const Cx u = csub({S.Are[r][k], S.Aim[r][k]}, cmul(f, {S.Are[col][k], S.Aim[col][k]}));
+                S.Are[r][k] = u.re;
+                S.Aim[r][k] = u.im;
             }
-            const Cx u = csub({bre[r], bim[r]}, cmul(f, {bre[col], bim[col]}));
-            bre[r] = u.re;
-            bim[r] = u.im;
-            Are[r][col] = 0.0;
-            Aim[r][col] = 0.0;
+            const Cx u = csub({S.bre[r], S.bim[r]}, cmul(f, {S.bre[col], S.bim[col]}));
+            S.bre[r] = u.re;
+            S.bim[r] = u.im;
+            S.Are[r][col] = 0.0;
+            S.Aim[r][col] = 0.0;
         }
         __syncthreads();
     }
-    if (t != 0) return;
-    Cx x[MAX_X];
-    for (int r = M - 1; r >= 0; --r) {
-        Cx s{bre[r], bim[r]};
-        for (int k = r + 1; k < M; ++k) s = csub(s, cmul({Are[r][k], Aim[r][k]}, x[k]));
-        x[r] = cdiv(s, {Are[r][r], Aim[r][r]});
-    }
-    if (mode == 0) {
-        if (c.vg_from_target) {
-            // linear network: x(V_g) = V_g x(1); P_port scales with V_g^2
-            const double p1 = 0.5 * (x[1 + N].re * x[0].re + x[1 + N].im * x[0].im);
-            c.vg_amp = sqrt(c.p_target / p1);
-            for (int r = 0; r < M; ++r) x[r] = {c.vg_amp * x[r].re, c.vg_amp * x[r].im};
+    if (t == 0) {
+        Cx x[MAX_X];
+        for (int r = M - 1; r >= 0; --r) {
+            Cx s{S.bre[r], S.bim[r]};
+            for (int k = r + 1; k < M; ++k) s = csub(s, cmul({S.Are[r][k], S.Aim[r][k]}, x[k]));
+            x[r] = cdiv(s, {S.Are[r][r], S.Aim[r][r]});
         }
         for (int r = 0; r < M; ++r) {
-            c.x_re[r] = c.xt_re[r] = x[r].re;
-            c.x_im[r] = c.xt_im[r] = x[r].im;
+            x_re[r] = x[r].re;
+            x_im[r] = x[r].im;
+        }
+    }
+    __syncthreads();
+    return true;
+}
+
+// max residuals of state x against source vg and loads (Eqs. kclres, kvlres)
+__device__ void network_residuals(CircuitDev &c, Cx vg, const double *icap_re, const double *icap_im,
+                                  const double *vp_re, const double *vp_im)
+{
+    const int N = c.N, M = 2 * N + 1;
+    double rk = 0.0, rv = 0.0;
+    for (int r = 0; r < M; ++r) {
+        Cx s{0.0, 0.0};
+        if (r == 0)
+            s = vg;
+        else if (r <= N)
+            s = {icap_re[r - 1], icap_im[r - 1]};
+        else
+            s = {vp_re[r - 1 - N], vp_im[r - 1 - N]};
+        for (int k = 0; k < M; ++k) s = csub(s, cmul(net_entry(c, r, k), {c.x_re[k], c.x_im[k]}));
+        const double m = sqrt(s.re * s.re + s.im * s.im);
+        if (r >= 1 && r <= N)
+            rk = fmax(rk, m);
+        else
+            rv = fmax(rv, m);
+    }
+    const double is = sqrt(c.x_re[0] * c.x_re[0] + c.x_im[0] * c.x_im[0]);
+    c.kcl = rk / (is > 0.0 ? is : 1.0);
+    c.kvl = rv / sqrt(vg.re * vg.re + vg.im * vg.im);
+}
+
+// period finalisation (Eqs. fourier, icap, pind, pcap, pcap_phasor), thread 0
+__device__ void finalize_period(CircuitDev &c, const HarmState *h, const double *vc, const double *vs)
+{
+    const int N = c.N;
+    const double two_n = 2.0 / c.nrf;
+    double wsum = 0.0, pph = 0.0;
+    for (int k = 0; k < N; ++k) {
+        const double qc = two_n * (h->qc[k] + h->qc_c[k]), qs = two_n * (h->qs[k] + h->qs_c[k]);
+        c.qc[k] = qc;
+        c.qs[k] = qs;
+        c.icap_re[k] = c.omega * qs;
+        c.icap_im[k] = c.omega * qc;
+        const double Wk = (h->w[k] + h->w_c[k]) + 0.5 * (h->v_first[k] + h->v_prev[k]) * (h->q_first[k] - h->q_prev[k]);
+        c.wk[k] = Wk;
+        wsum += Wk;
+        // 1/2 Re(V conj(I_cap)) with V = V_c - i V_s
+        pph += 0.5 * (vc[k] * c.icap_re[k] - vs[k] * c.icap_im[k]);
+    }
+    c.samples = h->samples;
+    c.p_ind = (h->pind + h->pind_c) / c.nrf;
+    c.p_cap = c.freq * wsum;
+    c.p_cap_ph = pph;
+}
+
+// loads of the completed period (Eq. vpind) and its powers (Eqs. pport,
+// pbalance, power_imbalance), thread 0
+__device__ void measure_period(CircuitDev &c)
+{
+    const int N = c.N;
+    for (int k = 0; k < N; ++k) {
+        c.vp_re[k] = -c.proj[2 * k];
+        c.vp_im[k] = -c.proj[2 * k + 1];
+    }
+    c.p_port = 0.5 * (c.x_re[1 + N] * c.x_re[0] + c.x_im[1 + N] * c.x_im[0]);
+    double pcu = 0.0;
+    for (int k = 0; k < N; ++k) pcu += 0.5 * c.rrf[k] * (c.x_re[1 + k] * c.x_re[1 + k] + c.x_im[1 + k] * c.x_im[1 + k]);
+    c.p_cu = pcu;
+    const double bal = c.p_ind + c.p_cap + pcu;
+    c.eps_bal = c.p_port != 0.0 ? fabs(c.p_port - bal) / fabs(c.p_port) : INFINITY;
+    c.vg_old = c.vg_amp;
+}
+
+// filtered, trend-extrapolated power controller (Eqs. pfilter, ptrend,
+// pcontrol, limiter, bounds), thread 0
+__device__ void controller_step(CircuitDev &c)
+{
+    if (!c.controller) return;
+    const double prev = c.have_pf ? c.pf_prev : c.p_port;
+    const double pf = c.gamma * c.p_port + (1.0 - c.gamma) * prev;
+    const double pc = fmax(pf + c.n_trend * (pf - prev), c.eps_p);
+    const double vold = c.vg_amp;
+    double vn = vold + c.alpha_v * (vold * sqrt(c.p_target / pc) - vold);
+    vn = fmin(fmax(vn, (1.0 - c.f_step) * vold), (1.0 + c.f_step) * vold);
+    vn = fmin(fmax(vn, c.v_min), c.v_max);
+    c.vg_amp = vn;
+    c.pf_prev = pf;
+    c.have_pf = 1;
+    c.pf = pf;
+    c.pc = pc;
+}
+
+__device__ __forceinline__ Cx vg_phasor(const CircuitDev &c, double amp)
+{
+    return {amp * cos(c.vg_phase), amp * sin(c.vg_phase)};
+}
+
+// relaxation (Eq. relaxation) of the applied state towards the target, then
+// the residuals against the loads used; thread 0
+__device__ void relax_and_check(CircuitDev &c, const double *icap_re, const double *icap_im, const double *vp_re,
+                                const double *vp_im)
+{
+    const int M = 2 * c.N + 1;
+    for (int r = 0; r < M; ++r) {
+        c.x_re[r] = (1.0 - c.alpha) * c.x_re[r] + c.alpha * c.xt_re[r];
+        c.x_im[r] = (1.0 - c.alpha) * c.x_im[r] + c.alpha * c.xt_im[r];
+    }
+    network_residuals(c, vg_phasor(c, c.vg_amp), icap_re, icap_im, vp_re, vp_im);
+}
+
+__device__ void write_turn_potentials(const CircuitDev &c, double *vc, double *vs)
+{
+    for (int k = 0; k < c.N; ++k) {
+        vc[k] = c.x_re[1 + c.N + k];
+        vs[k] = -c.x_im[1 + c.N + k];
+    }
+}
+
+__global__ __launch_bounds__(64) void k_circuit(CircuitDev *cdp, const HarmState *h, double *vc, double *vs,
+                                                int mode)
+{
+    __shared__ NetSmem S;
+    const int t = threadIdx.x;
+    CircuitDev &c = *cdp;
+    const int N = c.N, M = 2 * N + 1;
+    if (t == 0 && mode != 0) finalize_period(c, h, vc, vs);
+    if (mode == 2) return;
+    if (t == 0 && (mode == 1 || mode == 3)) measure_period(c);
+    if (mode == 3) return;
+    if (t == 0 && mode == 1) controller_step(c);
+    __syncthreads();
+    if (mode == 0) {
+        // first state: zero load responses; with the target-power start the
+        // network is solved for V_g = 1 and scaled (it is linear in V_g)
+        __shared__ double zero[MAX_TURNS];
+        if (t < MAX_TURNS) zero[t] = 0.0;
+        __syncthreads();
+        const double a = c.vg_from_target ? 1.0 : c.vg_amp;
+        if (!network_solve(c, vg_phasor(c, a), zero, zero, zero, zero, c.xt_re, c.xt_im, S)) {
+            if (t == 0) c.singular = 1;
+            return;
+        }
+        if (t != 0) return;
+        double scale = 1.0;
+        if (c.vg_from_target) {
+            const double p1 = 0.5 * (c.xt_re[1 + N] * c.xt_re[0] + c.xt_im[1 + N] * c.xt_im[0]);
+            c.vg_amp = sqrt(c.p_target / p1);
+            scale = c.vg_amp;
+        }
+        for (int r = 0; r < M; ++r) {
+            c.x_re[r] = c.xt_re[r] = scale * c.xt_re[r];
+            c.x_im[r] = c.xt_im[r] = scale * c.xt_im[r];
         }
         double num = 0.0, den = 0.0;   // Eq. reciprocity
         for (int k = 0; k < N; ++k)
@@ -288,33 +378,193 @@ __global__ __launch_bounds__(64) void k_circuit(CircuitDev *cdp, const HarmState
                 den = fmax(den, fabs(c.mvac[k * MAX_TURNS + l]));
             }
         c.eps_rec = den > 0.0 ? num / den : 0.0;
-    } else {
-        // relaxation (Eq. relaxation)
-        for (int r = 0; r < M; ++r) {
-            c.xt_re[r] = x[r].re;
-            c.xt_im[r] = x[r].im;
-            c.x_re[r] = (1.0 - c.alpha) * c.x_re[r] + c.alpha * x[r].re;
-            c.x_im[r] = (1.0 - c.alpha) * c.x_im[r] + c.alpha * x[r].im;
-        }
-        // residuals of the new state against this period's loads (Eqs. kclres, kvlres)
-        double rk = 0.0, rv = 0.0;
-        for (int r = 0; r < M; ++r) {
-            Cx s{0.0, 0.0};
-            if (r == 0) s = {c.vg_amp * vg1.re, c.vg_amp * vg1.im};
-            else if (r <= N) s = {c.icap_re[r - 1], c.icap_im[r - 1]};
-            else s = {c.vp_re[r - 1 - N], c.vp_im[r - 1 - N]};
-            for (int k = 0; k < M; ++k) s = csub(s, cmul(net_entry(c, r, k), {c.x_re[k], c.x_im[k]}));
-            const double m = sqrt(s.re * s.re + s.im * s.im);
-            if (r >= 1 && r <= N) rk = fmax(rk, m);
-            else rv = fmax(rv, m);
-        }
-        const double is = sqrt(c.x_re[0] * c.x_re[0] + c.x_im[0] * c.x_im[0]);
-        c.kcl = rk / (is > 0.0 ? is : 1.0);
-        c.kvl = rv / c.vg_amp;
+        write_turn_potentials(c, vc, vs);
+        return;
     }
+    // mode 1: target network solve with this period's loads, relaxation
+    if (!network_solve(c, vg_phasor(c, c.vg_amp), c.icap_re, c.icap_im, c.vp_re, c.vp_im, c.xt_re, c.xt_im, S)) {
+        if (t == 0) c.singular = 1;
+        return;
+    }
+    if (t != 0) return;
+    relax_and_check(c, c.icap_re, c.icap_im, c.vp_re, c.vp_im);
+    write_turn_potentials(c, vc, vs);
+}
+
+// ---------------------------------------------------------------------------
+// Surrogate-assisted update.  y = (V_p, I_cap) measured over the completed
+// period; yhat(x) the network's prediction for circuit state x.
+// stage 0: prediction at x^n -> correction y - yhat(x^n) and its scaled
+//          error (V_p by |V_g|, I_cap by |I_f|); above err_max the plain
+//          update runs here instead (controller, target solve, relaxation);
+//          else the inner iteration starts at x^n.
+// stage 1: one inner step: loads yhat(x_i) + correction, controller on the
+//          iterate's port power (limited to the period's step bounds),
+//          target solve, relaxation; converged when the step is below
+//          tol |x|.
+// stage 2: the converged iterate becomes the applied state; an iterate
+//          that ran away from the period's state (|x_i|^2 > 1e6 |x^n|^2
+//          or non-finite) is discarded for the plain update.
+// ---------------------------------------------------------------------------
+__device__ void features(const CircuitDev &c, const double *xr, const double *xi, float *f)
+{
+    const int N = c.N;
     for (int k = 0; k < N; ++k) {
-        vc[k] = c.x_re[1 + N + k];
-        vs[k] = -c.x_im[1 + N + k];
+        f[2 * k] = (float)xr[1 + k];
+        f[2 * k + 1] = (float)xi[1 + k];
+        f[2 * N + 2 * k] = (float)xr[1 + N + k];
+        f[2 * N + 2 * k + 1] = (float)xi[1 + N + k];
+    }
+    f[4 * N] = (float)c.pressure;
+    for (int m = 0; m < 8; ++m) f[4 * N + 1 + m] = (float)c.moments[m];
+}
+
+__global__ void k_features(const CircuitDev *cd, float *f, int iterate)
+{
+    if (threadIdx.x != 0) return;
+    const CircuitDev &c = *cd;
+    if (iterate && c.sur_done) return;
+    features(c, iterate ? c.xi_re : c.x_re, iterate ? c.xi_im : c.x_im, f);
+}
+
+__global__ __launch_bounds__(64) void k_surrogate(CircuitDev *cdp, const float *pred, double *vc, double *vs, int stage)
+{
+    __shared__ NetSmem S;
+    __shared__ double lre[MAX_TURNS], lim[MAX_TURNS], vre[MAX_TURNS], vim[MAX_TURNS];
+    __shared__ int mode;   // 0 plain fallback, 1 inner step, -1 nothing
+    const int t = threadIdx.x;
+    CircuitDev &c = *cdp;
+    const int N = c.N, M = 2 * N + 1;
+    if (t == 0) {
+        mode = -1;
+        if (stage == 0) {
+            const double sv = sqrt(c.vg_amp * c.vg_amp), si = sqrt(c.x_re[0] * c.x_re[0] + c.x_im[0] * c.x_im[0]);
+            double num = 0.0, den = 0.0;
+            for (int k = 0; k < N; ++k) {
+                const double y[4] = {c.vp_re[k], c.vp_im[k], c.icap_re[k], c.icap_im[k]};
+                const double yh[4] = {pred[2 * k], pred[2 * k + 1], pred[2 * N + 2 * k], pred[2 * N + 2 * k + 1]};
+                for (int q = 0; q < 4; ++q) {
+                    const double sc = q < 2 ? 1.0 / (sv > 0.0 ? sv : 1.0) : 1.0 / (si > 0.0 ? si : 1.0);
+                    num += (yh[q] - y[q]) * (yh[q] - y[q]) * sc * sc;
+                    den += y[q] * y[q] * sc * sc;
+                }
+                c.sur_corr[2 * k] = c.vp_re[k] - yh[0];
+                c.sur_corr[2 * k + 1] = c.vp_im[k] - yh[1];
+                c.sur_corr[2 * N + 2 * k] = c.icap_re[k] - yh[2];
+                c.sur_corr[2 * N + 2 * k + 1] = c.icap_im[k] - yh[3];
+            }
+            c.sur_err = den > 0.0 ? sqrt(num / den) : INFINITY;
+            c.sur_iters = 0;
+            c.sur_step = 0.0;
+            if (!(c.sur_err <= c.sur_err_max)) {
+                c.sur_used = 0;
+                c.sur_done = 1;
+                controller_step(c);
+                mode = 0;
+            } else {
+                c.sur_used = 1;
+                c.sur_done = 0;
+                for (int r = 0; r < M; ++r) {
+                    c.xi_re[r] = c.x_re[r];
+                    c.xi_im[r] = c.x_im[r];
+                }
+                c.vg_iter = c.vg_amp;
+            }
+        } else if (stage == 1 && !c.sur_done) {
+            mode = 1;
+            for (int k = 0; k < N; ++k) {
+                vre[k] = pred[2 * k] + c.sur_corr[2 * k];
+                vim[k] = pred[2 * k + 1] + c.sur_corr[2 * k + 1];
+                lre[k] = pred[2 * N + 2 * k] + c.sur_corr[2 * N + 2 * k];
+                lim[k] = pred[2 * N + 2 * k + 1] + c.sur_corr[2 * N + 2 * k + 1];
+            }
+            if (c.controller) {
+                // port power of the iterate; the amplitude stays within the
+                // period's controller bounds
+                const double pp = 0.5 * (c.xi_re[1 + N] * c.xi_re[0] + c.xi_im[1 + N] * c.xi_im[0]);
+                const double pc = fmax(pp, c.eps_p), v = c.vg_iter;
+                double vn = v + c.alpha_v * (v * sqrt(c.p_target / pc) - v);
+                vn = fmin(fmax(vn, (1.0 - c.f_step) * c.vg_old), (1.0 + c.f_step) * c.vg_old);
+                c.vg_iter = fmin(fmax(vn, c.v_min), c.v_max);
+            }
+        }
+    }
+    __syncthreads();
+    if (mode == 0) {
+        // plain update with the measured loads
+        if (!network_solve(c, vg_phasor(c, c.vg_amp), c.icap_re, c.icap_im, c.vp_re, c.vp_im, c.xt_re, c.xt_im, S)) {
+            if (t == 0) c.singular = 1;
+            return;
+        }
+        if (t != 0) return;
+        relax_and_check(c, c.icap_re, c.icap_im, c.vp_re, c.vp_im);
+        write_turn_potentials(c, vc, vs);
+        return;
+    }
+    if (mode == 1) {
+        if (!network_solve(c, vg_phasor(c, c.vg_iter), lre, lim, vre, vim, c.xt_re, c.xt_im, S)) {
+            if (t == 0) {
+                c.singular = 1;
+                c.sur_done = 1;
+            }
+            return;
+        }
+        if (t != 0) return;
+        double dn = 0.0, xn = 0.0;
+        for (int r = 0; r < M; ++r) {
+            const double nr = (1.0 - c.alpha) * c.xi_re[r] + c.alpha * c.xt_re[r];
+            const double ni = (1.0 - c.alpha) * c.xi_im[r] + c.alpha * c.xt_im[r];
+            dn += (nr - c.xi_re[r]) * (nr - c.xi_re[r]) + (ni - c.xi_im[r]) * (ni - c.xi_im[r]);
+            xn += nr * nr + ni * ni;
+            c.xi_re[r] = nr;
+            c.xi_im[r] = ni;
+        }
+        c.sur_iters += 1;
+        c.sur_step = sqrt(dn / (xn > 0.0 ? xn : 1.0));
+        // an iterate far outside the period's state means the predicted load
+        // map does not contract here: the plain update runs instead
+        double x0 = 0.0;
+        for (int r = 0; r < M; ++r) x0 += c.x_re[r] * c.x_re[r] + c.x_im[r] * c.x_im[r];
+        if (!(c.sur_step < 1e300) || xn > 1e6 * x0) {
+            c.sur_used = 2;
+            c.sur_done = 1;
+        }
+        if (c.sur_step < c.sur_tol || c.sur_iters >= c.sur_max_iter) c.sur_done = 1;
+        return;
+    }
+    if (stage == 2 && c.sur_used == 2) {
+        // diverged inner iteration: plain update with the measured loads
+        if (t == 0) controller_step(c);
+        __syncthreads();
+        if (!network_solve(c, vg_phasor(c, c.vg_amp), c.icap_re, c.icap_im, c.vp_re, c.vp_im, c.xt_re, c.xt_im, S)) {
+            if (t == 0) c.singular = 1;
+            return;
+        }
+        if (t != 0) return;
+        relax_and_check(c, c.icap_re, c.icap_im, c.vp_re, c.vp_im);
+        write_turn_potentials(c, vc, vs);
+        c.sur_used = 0;
+        return;
+    }
+    if (stage == 2 && t == 0 && c.sur_used == 1) {
+        for (int r = 0; r < M; ++r) {
+            c.x_re[r] = c.xi_re[r];
+            c.x_im[r] = c.xi_im[r];
+        }
+        c.vg_amp = c.vg_iter;
+        // the filter restarts from the port power of the new state
+        c.pf_prev = 0.5 * (c.x_re[1 + N] * c.x_re[0] + c.x_im[1 + N] * c.x_im[0]);
+        c.have_pf = 1;
+        // residuals against the loads the iterate converged with
+        double vre2[MAX_TURNS], vim2[MAX_TURNS], lre2[MAX_TURNS], lim2[MAX_TURNS];
+        for (int k = 0; k < N; ++k) {
+            vre2[k] = pred[2 * k] + c.sur_corr[2 * k];
+            vim2[k] = pred[2 * k + 1] + c.sur_corr[2 * k + 1];
+            lre2[k] = pred[2 * N + 2 * k] + c.sur_corr[2 * N + 2 * k];
+            lim2[k] = pred[2 * N + 2 * k + 1] + c.sur_corr[2 * N + 2 * k + 1];
+        }
+        network_residuals(c, vg_phasor(c, c.vg_amp), lre2, lim2, vre2, vim2);
+        write_turn_potentials(c, vc, vs);
     }
 }
 
@@ -360,6 +610,14 @@ void launch_project(const double *fields, int nf, int64_t stride, const int32_t 
 void launch_circuit(CircuitDev *cd, const HarmState *h, double *vc, double *vs, int mode, hipStream_t s)
 {
     hipLaunchKernelGGL(k_circuit, dim3(1), dim3(64), 0, s, cd, h, vc, vs, mode);
+}
+void launch_features(const CircuitDev *cd, float *f, bool iterate, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_features, dim3(1), dim3(64), 0, s, cd, f, iterate ? 1 : 0);
+}
+void launch_surrogate(CircuitDev *cd, const float *pred, double *vc, double *vs, int stage, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_surrogate, dim3(1), dim3(64), 0, s, cd, pred, vc, vs, stage);
 }
 void launch_compose(const double *ecp, const double *esp, const double *U, int64_t stride, const CircuitDev *cd,
                     double *ec, double *es, int nodes, hipStream_t s)

@@ -172,6 +172,24 @@ struct CircuitDev {
     double qc[MAX_TURNS], qs[MAX_TURNS], icap_re[MAX_TURNS], icap_im[MAX_TURNS], wk[MAX_TURNS];
     double p_port, p_cu, p_ind, p_cap, p_cap_ph, eps_bal, kcl, kvl, eps_rec, pf, pc, vg_old;
     int32_t samples, singular;
+    // surrogate-assisted update: plasma moments of the completed period,
+    // the correction y_n - yhat(x^n), the inner fixed-point iterate
+    double pressure;
+    double moments[8];          // <n_e>, <n_i>, max n_e, <eps_e>, <eps_i> (eV), R_e, z_e (m), ionizations
+    double births_prev;
+    int32_t sur_max_iter, sur_iters, sur_used, sur_done;
+    double sur_err_max, sur_tol, sur_err;
+    double sur_corr[4 * MAX_TURNS];         // (V_p re, im) x N then (I_cap re, im) x N
+    double xi_re[MAX_X], xi_im[MAX_X];      // inner iterate
+    double vg_iter, sur_step;
 };
+
+// features of the surrogate network: (I_k re, im), (V_k re, im), pressure,
+// the eight moments; outputs: (V_p,k re, im), (I_cap,k re, im)
+constexpr int SUR_MAX_TURNS = 5;
+
+// per-block sums of the plasma moments (electrons: count, energy, R, z;
+// ions: count, energy)
+constexpr int MOM_SUMS = 6;
 
 }  // namespace pic

@@ -4,6 +4,7 @@
 #include <stdint.h>
 
 #include "kernels.h"
+#include "../../include/phasorpic.h"
 
 namespace pic {
 
@@ -67,8 +68,16 @@ void launch_unit_rhs(const int32_t *tag, int turn, double gval, const uint8_t *d
 void launch_project(const double *fields, int nf, int64_t stride, const int32_t *list, const int32_t *lturn, int nlist,
                     const double *gval, int nturns, double *out, int ostride, const GridC &g, hipStream_t s);
 void launch_circuit(CircuitDev *cd, const HarmState *h, double *vc, double *vs, int mode, hipStream_t s);
+void launch_features(const CircuitDev *cd, float *f, bool iterate, hipStream_t s);
+void launch_surrogate(CircuitDev *cd, const float *pred, double *vc, double *vs, int stage, hipStream_t s);
+template <typename T>
+void launch_moments(const Parts<T> &pe, const Parts<T> &pi, const int64_t *count, const long long *accQe,
+                    double qscale, double we, double wi, double me, double mi, double qe, double *partial,
+                    int np, CircuitDev *cd, const unsigned long long *stats, const GridC &g, hipStream_t st);
+int moments_blocks();
 void launch_compose(const double *ecp, const double *esp, const double *U, int64_t stride, const CircuitDev *cd,
                     double *ec, double *es, int nodes, hipStream_t s);
+void mlp_shape(const mlp_ctx *c, int *n_in, int *n_out, void **stream);
 void launch_face_charge(const double *phi, const int32_t *fp, const int32_t *fq, const int32_t *fk, const double *fc,
                         int nfaces, double *Qk, int nturns, hipStream_t s);
 

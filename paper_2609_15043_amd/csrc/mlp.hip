@@ -602,3 +602,13 @@ extern "C" void mlp_destroy(mlp_ctx *c)
 }
 
 extern "C" const char *mlp_last_error(const mlp_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+namespace pic {
+// input / output widths and stream of a network (for the circuit update)
+void mlp_shape(const mlp_ctx *c, int *n_in, int *n_out, void **stream)
+{
+    *n_in = c->cfg.n_in;
+    *n_out = c->cfg.n_out;
+    *stream = c->stream;
+}
+}  // namespace pic

@@ -1025,3 +1025,114 @@ PIC_INSTANTIATE(float)
 PIC_INSTANTIATE(double)
 
 }  // namespace pic
+
+namespace pic {
+
+// ---------------------------------------------------------------------------
+// Plasma moments of the current particle state (once per closed period):
+// per-block FP64 sums over live electrons (count, kinetic energy, R, z) and
+// ions (count, kinetic energy), then one workgroup folds them in block
+// order, adds the electron node-density maximum from this step's charge
+// accumulator and the period's ionizations.
+// ---------------------------------------------------------------------------
+constexpr int MOM_BLOCKS = 512;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_moments(Parts<T> pe, Parts<T> pi, const int64_t *count, double me, double mi,
+                                                 double inv_qe, GridC g, double *partial)
+{
+    __shared__ double red[MOM_SUMS][256];
+    double s[MOM_SUMS] = {0, 0, 0, 0, 0, 0};
+    for (int sp = 0; sp < 2; ++sp) {
+        const Parts<T> &p = sp ? pi : pe;
+        const int64_t n = count[sp];
+        const double hm = 0.5 * (sp ? mi : me) * inv_qe;
+        for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+            const int c = p.cell[k];
+            if (c < 0) continue;
+            const double vr = p.vr[k], vt = p.vt[k], vz = p.vz[k];
+            const double e = hm * (vr * vr + vt * vt + vz * vz);
+            if (sp == 0) {
+                int i, j;
+                split_cell(g, c, i, j);
+                s[0] += 1.0;
+                s[1] += e;
+                s[2] += (j + (double)p.dr[k]) * g.dr;
+                s[3] += (i + (double)p.dz[k]) * g.dz;
+            } else {
+                s[4] += 1.0;
+                s[5] += e;
+            }
+        }
+    }
+    for (int q = 0; q < MOM_SUMS; ++q) red[q][threadIdx.x] = s[q];
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off)
+            for (int q = 0; q < MOM_SUMS; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x < MOM_SUMS) partial[blockIdx.x * MOM_SUMS + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(256) void k_moments_fold(const double *partial, int np, const long long *accQe,
+                                                      double qscale, double we, double wi, CircuitDev *cd,
+                                                      const unsigned long long *stats, GridC g)
+{
+    __shared__ double red[256];
+    __shared__ double sums[MOM_SUMS];
+    if (threadIdx.x < MOM_SUMS) {
+        double a = 0.0;
+        for (int b = 0; b < np; ++b) a += partial[b * MOM_SUMS + threadIdx.x];
+        sums[threadIdx.x] = a;
+    }
+    // electron node density maximum: |accQ_e| / qscale * w_e / V_node
+    double m = 0.0;
+    for (int n = threadIdx.x; n < g.nodes; n += blockDim.x) {
+        const int i = n / g.nr1, j = n - i * g.nr1;
+        const double R = j * g.dr;
+        const double lo = fmax(R - 0.5 * g.dr, 0.0), hi = fmin(R + 0.5 * g.dr, g.nr * g.dr);
+        const double zl = fmax((i - 0.5) * g.dz, 0.0), zh = fmin((i + 0.5) * g.dz, g.nz * g.dz);
+        const double vol = 3.141592653589793 * (hi * hi - lo * lo) * (zh - zl);
+        m = fmax(m, fabs((double)accQe[n]) / qscale * we / vol);
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    CircuitDev &c = *cd;
+    const double vol = 3.141592653589793 * (g.nr * g.dr) * (g.nr * g.dr) * (g.ip * g.dz);
+    const double ne = sums[0], ni = sums[4];
+    c.moments[0] = ne * we / vol;
+    c.moments[1] = ni * wi / vol;
+    c.moments[2] = red[0];
+    c.moments[3] = ne > 0 ? sums[1] / ne : 0.0;
+    c.moments[4] = ni > 0 ? sums[5] / ni : 0.0;
+    c.moments[5] = ne > 0 ? sums[2] / ne : 0.0;
+    c.moments[6] = ne > 0 ? sums[3] / ne : 0.0;
+    const double births = (double)stats[ST_BIRTHS];
+    c.moments[7] = births - c.births_prev;
+    c.births_prev = births;
+}
+
+int moments_blocks() { return MOM_BLOCKS; }
+
+template <typename T>
+void launch_moments(const Parts<T> &pe, const Parts<T> &pi, const int64_t *count, const long long *accQe,
+                    double qscale, double we, double wi, double me, double mi, double qe, double *partial, int np,
+                    CircuitDev *cd, const unsigned long long *stats, const GridC &g, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_moments<T>, dim3(np), dim3(256), 0, st, pe, pi, count, me, mi, 1.0 / qe, g, partial);
+    hipLaunchKernelGGL(k_moments_fold, dim3(1), dim3(256), 0, st, partial, np, accQe, qscale, we, wi, cd, stats, g);
+}
+template void launch_moments<float>(const Parts<float> &, const Parts<float> &, const int64_t *, const long long *,
+                                    double, double, double, double, double, double, double *, int, CircuitDev *,
+                                    const unsigned long long *, const GridC &, hipStream_t);
+template void launch_moments<double>(const Parts<double> &, const Parts<double> &, const int64_t *,
+                                     const long long *, double, double, double, double, double, double, double *, int,
+                                     CircuitDev *, const unsigned long long *, const GridC &, hipStream_t);
+
+}  // namespace pic

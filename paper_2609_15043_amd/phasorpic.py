@@ -75,7 +75,13 @@ class PicPeriodReport(ctypes.Structure):
                 ("p_port", _D), ("p_cu", _D), ("eps_bal", _D), ("kcl", _D), ("kvl", _D),
                 ("vg_old", _D), ("vg_amp", _D), ("pf", _D), ("pc", _D),
                 ("vp_re", _D * 16), ("vp_im", _D * 16), ("xt_re", _D * 33), ("xt_im", _D * 33),
-                ("x_re", _D * 33), ("x_im", _D * 33), ("helm_cycles", _I32 * 2), ("helm_rel", _D * 2)]
+                ("x_re", _D * 33), ("x_im", _D * 33), ("helm_cycles", _I32 * 2), ("helm_rel", _D * 2),
+                ("xp_re", _D * 33), ("xp_im", _D * 33), ("pressure", _D), ("moments", _D * 8),
+                ("sur_used", _I32), ("sur_iters", _I32), ("sur_err", _D)]
+
+
+class PicSurrogateConfig(ctypes.Structure):
+    _fields_ = [("err_max", _D), ("tol", _D), ("max_iter", _I32)]
 
 
 class PicCircuitInfo(ctypes.Structure):
@@ -94,7 +100,9 @@ _LIB = None
 
 # exported C symbols, in header order
 SYMBOLS = ["pic_workspace_bytes", "pic_init", "pic_gather_push", "mcc_collide", "pic_deposit",
-           "poisson_solve_rz", "harmonic_accumulate", "circuit_period_update", "pic_get_circuit", "pic_sync",
+           "poisson_solve_rz", "harmonic_accumulate", "circuit_period_update", "pic_set_source",
+           "pic_attach_surrogate",
+           "pic_get_circuit", "pic_sync",
            "pic_clear_error", "pic_get_particles", "pic_set_particles", "pic_set_step", "pic_set_phi",
            "pic_get_grid", "pic_timing", "pic_get_stats", "pic_destroy", "pic_last_error"]
 
@@ -115,6 +123,8 @@ def lib():
         L.poisson_solve_rz.argtypes = [P, _I64, _D, _I32, ctypes.POINTER(PicSolveInfo)]
         L.circuit_period_update.argtypes = [P, _PD, _PD, _PD, _PD, ctypes.POINTER(PicPeriodReport), _PD, _PD]
         L.pic_get_circuit.argtypes = [P, ctypes.POINTER(PicCircuitInfo)]
+        L.pic_attach_surrogate.argtypes = [P, P, ctypes.POINTER(PicSurrogateConfig)]
+        L.pic_set_source.argtypes = [P, _D, _D]
         L.pic_sync.argtypes = [P]
         L.pic_clear_error.argtypes = [P]
         L.pic_get_particles.argtypes = [P, _I32, _I64, _PD, _PD, _PD, _PD, _PD, _PU32, _PI32,
@@ -295,8 +305,44 @@ def circuit_period_update(ctx, new_vc=None, new_vs=None, new_ec=None, new_es_sto
                    vp=np.array(rep.vp_re[:K]) + 1j * np.array(rep.vp_im[:K]),
                    x_target=np.array(rep.xt_re[:M]) + 1j * np.array(rep.xt_im[:M]),
                    x=np.array(rep.x_re[:M]) + 1j * np.array(rep.x_im[:M]),
-                   helm_cycles=tuple(rep.helm_cycles), helm_rel=tuple(rep.helm_rel))
+                   helm_cycles=tuple(rep.helm_cycles), helm_rel=tuple(rep.helm_rel),
+                   x_prev=np.array(rep.xp_re[:M]) + 1j * np.array(rep.xp_im[:M]), pressure=rep.pressure,
+                   moments=np.array(rep.moments[:]), sur_used=rep.sur_used, sur_iters=rep.sur_iters,
+                   sur_err=rep.sur_err)
     return st, out, jc, js
+
+
+def pic_set_source(ctx, vg_amp, vg_phase=0.0):
+    return ctx.check(lib().pic_set_source(ctx.handle, vg_amp, vg_phase))
+
+
+def pic_attach_surrogate(ctx, net, err_max=0.02, tol=1e-6, max_iter=50):
+    """Attach an Mlp (or None to detach) to a coupled context."""
+    sc = PicSurrogateConfig(err_max, tol, max_iter)
+    ctx.check(lib().pic_attach_surrogate(ctx.handle, net.handle if net is not None else None, ctypes.byref(sc)))
+    ctx.keep.append(net)
+
+
+def surrogate_features(rep, N):
+    """Network input of a period report: (I_k re, im), (V_k re, im) of the
+    state applied during the period, pressure, the eight moments."""
+    x = rep["x_prev"]
+    f = []
+    for k in range(N):
+        f += [x[1 + k].real, x[1 + k].imag]
+    for k in range(N):
+        f += [x[1 + N + k].real, x[1 + N + k].imag]
+    return np.array(f + [rep["pressure"]] + list(rep["moments"]))
+
+
+def surrogate_targets(rep, N):
+    """Network output of a period report: (V_p,k re, im), (I_cap,k re, im)."""
+    f = []
+    for k in range(N):
+        f += [rep["vp"][k].real, rep["vp"][k].imag]
+    for k in range(N):
+        f += [rep["icap"][k].real, rep["icap"][k].imag]
+    return np.array(f)
 
 
 def pic_get_circuit(ctx):
