@@ -67,6 +67,9 @@ struct HostLevel {
     std::vector<uint8_t> dir;  // nodes
 };
 
+// largest level solved by its dense inverse (nodes)
+constexpr int BOTTOM_NODES = 2200;
+
 int64_t ceil_log2(double x)
 {
     int64_t k = 0;
@@ -486,9 +489,21 @@ static void layout(pic_ctx &c, Carver &cv)
     c.Jsc = cv.take<double>(nodes);
     c.hpartial = cv.take<double>(harmonic_blocks(nodes));
     c.harm = cv.take<HarmState>(1);
-    // multigrid: level 0 holds the CG correction (z) and residual (r)
-    const int nl = mg_levels(f.nr, f.nz);
+    // multigrid: level 0 holds the CG correction (z) and residual (r); the
+    // hierarchy stops at the first level of at most BOTTOM_NODES nodes, which
+    // is solved exactly with a dense inverse
+    int nl = mg_levels(f.nr, f.nz);
+    {
+        int nr_ = f.nr, nz_ = f.nz, l = 0;
+        while (l < nl - 1 && (nz_ + 1) * (nr_ + 1) > BOTTOM_NODES) {
+            nr_ /= 2;
+            nz_ /= 2;
+            ++l;
+        }
+        nl = l + 1;
+    }
     c.lv.n = nl;
+    c.lb = nl - 1;
     c.pr = cv.take<double>(nodes);
     c.pz = cv.take<double>(nodes);
     c.pp = cv.take<double>(nodes);
@@ -640,6 +655,16 @@ static pic_status prepare_host(pic_ctx &c, const pic_config *f)
     c.g.dz = f->zmax / f->nz;
     c.g.inv_nr = 1.0f / (float)f->nr;
     if ((int64_t)f->nr * f->nz >= (1 << 22)) return fail(&c, PIC_EINVAL, "grid too large (nr nz >= 2^22)");
+    {
+        int nr_ = f->nr, nz_ = f->nz, nl = mg_levels(f->nr, f->nz);
+        for (int l = 0; l < nl - 1 && (nz_ + 1) * (nr_ + 1) > BOTTOM_NODES; ++l) {
+            nr_ /= 2;
+            nz_ /= 2;
+        }
+        if ((nz_ + 1) * (nr_ + 1) > 4 * BOTTOM_NODES)
+            return fail(&c, PIC_EINVAL, "grid %d x %d does not coarsen to a small bottom level (use even, ideally "
+                                        "power-of-two cell counts)", f->nr, f->nz);
+    }
     null_constants(*f, c.numax, c.pnull, c.lq);
     const double nf = 1.0 / (f->freq * f->dt);
     c.nrf = (int)std::lround(nf);
@@ -738,7 +763,8 @@ static void finalize_charge(pic_ctx &c)
 }
 
 // V-cycle on the correction: two red-black sweeps on the 5-point fine
-// level, one four-colour sweep on the Galerkin levels, exact coarsest solve.
+// level, one four-colour sweep on the Galerkin levels, exact solve on the
+// bottom level (dense inverse, one multi-block product).
 static void vcycle(pic_ctx &c, const MGLevels &lv, const MGState *st)
 {
     for (int l = 0; l < c.lb; ++l) {
@@ -748,7 +774,7 @@ static void vcycle(pic_ctx &c, const MGLevels &lv, const MGState *st)
             for (int col = 0; col < nc; ++col) launch_mg_smooth(lv.L[l], col, st, c.stream);
         launch_mg_restrict(lv.L[l], lv.L[l + 1], st, c.stream);
     }
-    launch_mg_bottom(lv, c.lb, c.lb == 0 ? 2 : 1, c.lb == 0 ? 2 : 1, st, c.stream);
+    launch_dense_solve(lv.coarse_inv, lv.L[c.lb], st, c.stream);
     for (int l = c.lb - 1; l >= 0; --l) {
         launch_mg_prolong(lv.L[l], lv.L[l + 1], st, c.stream);
         const int nc = lv.L[l].nine ? 4 : 2;
@@ -861,50 +887,30 @@ static pic_status build_levels(pic_ctx &c, MGLevels &lv, const Coeffs &co, const
         HIPCHK(&c, mset(c.stream, L.phi, 0, (size_t)L.nodes * sizeof(double)));
         HIPCHK(&c, mset(c.stream, L.rhs, 0, (size_t)L.nodes * sizeof(double)));
     }
-    // dense inverse of the coarsest level (Gauss-Jordan, partial pivoting); rows and
-    // columns of its Dirichlet nodes are zero so their correction stays 0
+    // dense inverse of the bottom level, computed on the device by
+    // Gauss-Jordan elimination (no pivoting: the free block is symmetric
+    // positive definite and Dirichlet rows are identity rows)
     {
         const int m = (S.nz + 1) * (S.nr + 1), nr1 = S.nr + 1;
-        std::vector<double> A((size_t)m * m, 0.0), Inv((size_t)m * m, 0.0);
+        std::vector<double> A((size_t)m * m, 0.0);
         for (int n = 0; n < m; ++n) {
             const int i = n / nr1, j = n - i * nr1;
+            if (S.dir[n]) {
+                A[(size_t)n * m + n] = 1.0;
+                continue;
+            }
             for (int k = 0; k < 9; ++k) {
                 const int di = k / 3 - 1, dj = k % 3 - 1;
                 if (i + di < 0 || i + di > S.nz || j + dj < 0 || j + dj > S.nr) continue;
-                A[(size_t)n * m + (n + di * nr1 + dj)] = S.a[(size_t)k * m + n];
+                const int q = n + di * nr1 + dj;
+                if (S.dir[q]) continue;
+                A[(size_t)n * m + q] = S.a[(size_t)k * m + n];
             }
-            Inv[(size_t)n * m + n] = 1.0;
+            if (!(A[(size_t)n * m + n] > 0.0)) return fail(&c, PIC_EINVAL, "bottom multigrid level not definite");
         }
-        for (int col = 0; col < m; ++col) {
-            int piv = col;
-            for (int r = col + 1; r < m; ++r)
-                if (std::fabs(A[(size_t)r * m + col]) > std::fabs(A[(size_t)piv * m + col])) piv = r;
-            if (A[(size_t)piv * m + col] == 0.0) return fail(&c, PIC_EINVAL, "singular coarsest multigrid level");
-            if (piv != col)
-                for (int k = 0; k < m; ++k) {
-                    std::swap(A[(size_t)piv * m + k], A[(size_t)col * m + k]);
-                    std::swap(Inv[(size_t)piv * m + k], Inv[(size_t)col * m + k]);
-                }
-            const double d = A[(size_t)col * m + col];
-            for (int k = 0; k < m; ++k) {
-                A[(size_t)col * m + k] /= d;
-                Inv[(size_t)col * m + k] /= d;
-            }
-            for (int r = 0; r < m; ++r) {
-                if (r == col) continue;
-                const double f2 = A[(size_t)r * m + col];
-                if (f2 == 0.0) continue;
-                for (int k = 0; k < m; ++k) {
-                    A[(size_t)r * m + k] -= f2 * A[(size_t)col * m + k];
-                    Inv[(size_t)r * m + k] -= f2 * Inv[(size_t)col * m + k];
-                }
-            }
-        }
-        for (int n = 0; n < m; ++n)
-            if (S.dir[n])
-                for (int k = 0; k < m; ++k) Inv[(size_t)n * m + k] = Inv[(size_t)k * m + n] = 0.0;
-        HIPCHK(&c, cpy(c.stream, (void *)lv.coarse_inv, Inv.data(), Inv.size() * sizeof(double),
-                       hipMemcpyHostToDevice));
+        HIPCHK(&c, cpy(c.stream, (void *)lv.coarse_inv, A.data(), A.size() * sizeof(double), hipMemcpyHostToDevice));
+        launch_gauss_jordan(const_cast<double *>(lv.coarse_inv), m, c.pp, c.pAp, c.stream);
+        HIPCHK(&c, hipStreamSynchronize(c.stream));
     }
     return PIC_OK;
 }
@@ -1145,8 +1151,6 @@ template <typename T> static pic_status init_impl(pic_ctx &c)
         for (double *v : {c.pr, c.pz, c.pp, c.pAp, c.phi_prev})
             HIPCHK(&c, mset(c.stream, v, 0, (size_t)nodes * sizeof(double)));
     }
-    c.lb = 0;
-    while (c.lb < c.lv.n - 1 && c.lv.L[c.lb].nodes > 2200) ++c.lb;
     {
         pic_status cs = circuit_init(c);
         if (cs) return cs;

@@ -260,43 +260,40 @@ __global__ void k_mg_prolong(MGLevel F, MGLevel C, const MGState *st)
     op_prolong(F, C, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
 }
 
-// Levels lb .. nl-1 as one V-cycle in a single workgroup (level lb's
-// right-hand side comes from the multi-block restriction), with an exact
-// dense solve on the coarsest level.
-__global__ __launch_bounds__(1024) void k_mg_bottom(MGLevels lv, int lb, int nu1, int nu2, const MGState *st)
+// Exact solve on the bottom level: phi = Inv rhs, one wave per row.
+__global__ __launch_bounds__(256) void k_dense_solve(const double *inv, MGLevel L, const MGState *st)
 {
     if (st->done) return;
-    const int t = threadIdx.x, S = blockDim.x;
-    const int nl = lv.n;
-    for (int l = lb; l < nl - 1; ++l) {
-        const int nc = lv.L[l].nine ? 4 : 2;
-        for (int k = 0; k < nu1; ++k)
-            for (int c = 0; c < nc; ++c) {
-                op_smooth(lv.L[l], c, t, S);
-                __syncthreads();
-            }
-        op_restrict(lv.L[l], lv.L[l + 1], t, S);
-        __syncthreads();
-    }
-    {
-        const MGLevel &Lc = lv.L[nl - 1];
-        for (int r = t; r < Lc.nodes; r += S) {
-            double acc = 0.0;
-            for (int k = 0; k < Lc.nodes; ++k) acc += lv.coarse_inv[(size_t)r * Lc.nodes + k] * Lc.rhs[k];
-            Lc.phi[r] = acc;
-        }
-        __syncthreads();
-    }
-    for (int l = nl - 2; l >= lb; --l) {
-        op_prolong(lv.L[l], lv.L[l + 1], t, S);
-        __syncthreads();
-        const int nc = lv.L[l].nine ? 4 : 2;
-        for (int k = 0; k < nu2; ++k)
-            for (int c = nc - 1; c >= 0; --c) {
-                op_smooth(lv.L[l], c, t, S);
-                __syncthreads();
-            }
-    }
+    const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= L.nodes) return;
+    const int lane = threadIdx.x & 63;
+    const double *row = inv + (size_t)r * L.nodes;
+    double s = 0.0;
+    for (int k = lane; k < L.nodes; k += 64) s += row[k] * L.rhs[k];
+    s = wave_total(s);
+    if (lane == 63) L.phi[r] = s;
+}
+
+// In-place Gauss-Jordan inversion, one pivot per kernel pair: save the
+// scaled pivot row and the pivot column, then update every entry.
+__global__ void k_gj_save(const double *A, int n, int k, double *rowk, double *colk)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const double p = A[(size_t)k * n + k];
+    rowk[t] = t == k ? 1.0 / p : A[(size_t)k * n + t] / p;
+    colk[t] = A[(size_t)t * n + k];
+}
+
+__global__ void k_gj_update(double *A, int n, int k, const double *rowk, const double *colk)
+{
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (size_t)n * n) return;
+    const int i = (int)(e / n), j = (int)(e - (size_t)i * n);
+    if (i == k)
+        A[e] = rowk[j];
+    else
+        A[e] = (j == k ? 0.0 : A[e]) - colk[i] * rowk[j];
 }
 
 // ---------------------------------------------------------------------------
@@ -470,13 +467,27 @@ __global__ __launch_bounds__(256) void k_pcg_update(MGLevel L, PCGVec v, const M
     block_partial(m, partial + 2 * blockIdx.x, true);
 }
 
-// Q_k = sum over faces (turn-k node p, outside node q) of c (phi_p - phi_q)
-__global__ void k_face_charge(const double *phi, const int32_t *fp, const int32_t *fq, const int32_t *fk,
-                              const double *fc, int nfaces, double *Qk, int nturns)
+// Q_k = sum over faces (turn-k node p, outside node q) of c (phi_p - phi_q);
+// one workgroup, per-thread partial sums per turn, tree reduction in a
+// fixed order (the face list is sorted by turn-node index on the host)
+__global__ __launch_bounds__(256) void k_face_charge(const double *phi, const int32_t *fp, const int32_t *fq,
+                                                     const int32_t *fk, const double *fc, int nfaces, double *Qk,
+                                                     int nturns)
 {
-    if (threadIdx.x != 0) return;
-    for (int k = 0; k < nturns; ++k) Qk[k] = 0.0;
-    for (int f = 0; f < nfaces; ++f) Qk[fk[f]] += fc[f] * (phi[fp[f]] - phi[fq[f]]);
+    __shared__ double red[256];
+    for (int k = 0; k < nturns; ++k) {
+        double s = 0.0;
+        for (int f = threadIdx.x; f < nfaces; f += 256)
+            if (fk[f] == k) s += fc[f] * (phi[fp[f]] - phi[fq[f]]);
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int off = 128; off > 0; off >>= 1) {
+            if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) Qk[k] = red[0];
+        __syncthreads();
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -531,15 +542,16 @@ void launch_mg_prolong(const MGLevel &F, const MGLevel &C, const MGState *st, hi
 {
     hipLaunchKernelGGL(k_mg_prolong, dim3(mg_grid(F.nodes)), dim3(256), 0, s, F, C, st);
 }
-void launch_mg_bottom(const MGLevels &lv, int lb, int nu1, int nu2, const MGState *st, hipStream_t s)
+void launch_dense_solve(const double *inv, const MGLevel &L, const MGState *st, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_mg_bottom, dim3(1), dim3(1024), 0, s, lv, lb, nu1, nu2, st);
+    hipLaunchKernelGGL(k_dense_solve, dim3(nblk(L.nodes, 4)), dim3(256), 0, s, inv, L, st);
 }
-size_t mg_bottom_lds(const MGLevels &lv, int lb)
+void launch_gauss_jordan(double *A, int n, double *rowk, double *colk, hipStream_t s)
 {
-    size_t nodes = 0;
-    for (int l = lb; l < lv.n; ++l) nodes += lv.L[l].nodes;
-    return 2 * nodes * sizeof(double);
+    for (int k = 0; k < n; ++k) {
+        hipLaunchKernelGGL(k_gj_save, dim3(nblk(n, 256)), dim3(256), 0, s, A, n, k, rowk, colk);
+        hipLaunchKernelGGL(k_gj_update, dim3(nblk((int64_t)n * n, 256)), dim3(256), 0, s, A, n, k, rowk, colk);
+    }
 }
 int pcg_blocks(int nodes) { return (int)red_grid(nodes); }
 void launch_pcg_begin(const MGLevel &L, const PCGVec &v, const int32_t *tag, const double *vc, const double *vs,
@@ -576,7 +588,7 @@ void launch_pcg_update(const MGLevel &L, const PCGVec &v, const MGState *st, dou
 void launch_face_charge(const double *phi, const int32_t *fp, const int32_t *fq, const int32_t *fk, const double *fc,
                         int nfaces, double *Qk, int nturns, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_face_charge, dim3(1), dim3(64), 0, s, phi, fp, fq, fk, fc, nfaces, Qk, nturns);
+    hipLaunchKernelGGL(k_face_charge, dim3(1), dim3(256), 0, s, phi, fp, fq, fk, fc, nfaces, Qk, nturns);
 }
 
 }  // namespace pic

@@ -11,10 +11,20 @@ namespace pic {
 // LDS deposit window (nodes) of one particle block: whole node rows around
 // the block's middle particle, so particles that drifted a few cells since
 // the last sort still land in LDS.  FP32 window values: 2048 nodes; FP64: 1024.
+#ifndef PIC_WIN_NODES_F32
+#define PIC_WIN_NODES_F32 2048
+#endif
+#ifndef PIC_WIN_NODES_F64
+#define PIC_WIN_NODES_F64 1024
+#endif
 template <typename T> struct Win {
-    static constexpr int N = sizeof(T) == 4 ? 2048 : 1024;
+    static constexpr int N = sizeof(T) == 4 ? PIC_WIN_NODES_F32 : PIC_WIN_NODES_F64;
 };
 constexpr int BLOCK = 256;
+#ifndef PIC_DEPOSIT_GROUPS
+#define PIC_DEPOSIT_GROUPS 2
+#endif
+constexpr int DEPOSIT_GROUPS = PIC_DEPOSIT_GROUPS;   // wave reductions per run deposit before lanes add their own
 constexpr int RUN = 4;                  // consecutive particles per lane per vector load
 constexpr int RUNS = 4;                 // runs per wave per block
 constexpr int CHUNK = BLOCK * RUN * RUNS;   // particles per pass block (4096)
@@ -125,7 +135,7 @@ constexpr int MAX_LEVELS = 14;
 struct MGLevels {
     int n;
     MGLevel L[MAX_LEVELS];
-    const double *coarse_inv;   // dense inverse of the coarsest operator (free rows / columns)
+    const double *coarse_inv;   // dense inverse of the bottom operator (Dirichlet rows identity)
 };
 
 // Device-resident state of one preconditioned-CG solve.

@@ -50,8 +50,8 @@ int pcg_partial_size(int nodes);
 void launch_mg_smooth(const MGLevel &L, int color, const MGState *st, hipStream_t s);
 void launch_mg_restrict(const MGLevel &F, const MGLevel &C, const MGState *st, hipStream_t s);
 void launch_mg_prolong(const MGLevel &F, const MGLevel &C, const MGState *st, hipStream_t s);
-void launch_mg_bottom(const MGLevels &lv, int lb, int nu1, int nu2, const MGState *st, hipStream_t s);
-size_t mg_bottom_lds(const MGLevels &lv, int lb);
+void launch_dense_solve(const double *inv, const MGLevel &L, const MGState *st, hipStream_t s);
+void launch_gauss_jordan(double *A, int n, double *rowk, double *colk, hipStream_t s);
 int pcg_blocks(int nodes);
 void launch_pcg_begin(const MGLevel &L, const PCGVec &v, const int32_t *tag, const double *vc, const double *vs,
                       double cs, double sn, MGState *st, double *prev, bool extrap, hipStream_t s);

@@ -178,12 +178,18 @@ __global__ void k_unplace(Parts<T> p, const int64_t *count, const int64_t *live_
 // sums are exact and independent of block order.  Called by all 64 lanes.
 // ---------------------------------------------------------------------------
 template <typename T>
+__device__ __forceinline__ void deposit_lane(int key, T v0, T v1, T v2, T v3, T *win, int base, long long *acc,
+                                             int nr1, double scale, int &nout);
+
+template <typename T>
 __device__ __forceinline__ void deposit4(bool valid, int key, T v0, T v1, T v2, T v3, T *win, int base,
-                                         long long *acc, int nr1, double scale, unsigned long long *sstat)
+                                         long long *acc, int nr1, double scale, int &nout)
 {
     uint64_t todo = ballot(valid);
     const int lane = lane_id();
-    while (todo) {
+    // at most DEPOSIT_GROUPS wave reductions; lanes of further keys (a wave
+    // whose particles drifted apart since the sort) add their own sums
+    for (int it = 0; todo && it < DEPOSIT_GROUPS; ++it) {
         const int lead = __ffsll((unsigned long long)todo) - 1;
         const int k = __builtin_amdgcn_readlane(key, lead);
         const bool m = valid && key == k;
@@ -203,12 +209,13 @@ __device__ __forceinline__ void deposit4(bool valid, int key, T v0, T v1, T v2, 
                     atomicAdd(&win[o], sums[c]);
                 } else {
                     atomic_add_i64(&acc[nodes[c]], to_fixed((double)sums[c], scale));
-                    atomicAdd(&sstat[ST_WINOUT], 1ull);
+                    ++nout;
                 }
             }
         }
         todo &= ~mm;
     }
+    if (todo >> lane & 1ull) deposit_lane<T>(key, v0, v1, v2, v3, win, base, acc, nr1, scale, nout);
 }
 
 __device__ __forceinline__ void count_wave(bool c, unsigned long long *sstat, int slot)
@@ -345,7 +352,7 @@ __device__ __forceinline__ void st4(int32_t *p, const int32_t (&o)[4])
 // differs from its run's key.
 template <typename T>
 __device__ __forceinline__ void deposit_lane(int key, T v0, T v1, T v2, T v3, T *win, int base, long long *acc,
-                                             int nr1, double scale, unsigned long long *sstat)
+                                             int nr1, double scale, int &nout)
 {
     const int nodes[4] = {key, key + 1, key + nr1, key + nr1 + 1};
     const T vals[4] = {v0, v1, v2, v3};
@@ -356,7 +363,7 @@ __device__ __forceinline__ void deposit_lane(int key, T v0, T v1, T v2, T v3, T 
             atomicAdd(&win[o], vals[c]);
         } else {
             atomic_add_i64(&acc[nodes[c]], to_fixed((double)vals[c], scale));
-            atomicAdd(&sstat[ST_WINOUT], 1ull);
+            ++nout;
         }
     }
 }
@@ -398,8 +405,12 @@ __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs<T> a)
     const int tid = threadIdx.x;
     const int lane = lane_id();
     const int64_t n = *a.count;
-    const int64_t c0 = (int64_t)blockIdx.x * CHUNK;
-    if (c0 >= n) return;
+    // chunks in reverse order: the tail of the arrays (births appended since
+    // the last sort, in no cell order) is the slowest to deposit, so its
+    // blocks start first and overlap the streaming of the sorted bulk
+    const int64_t nchunks = (n + CHUNK - 1) / CHUNK;
+    if ((int64_t)blockIdx.x >= nchunks) return;
+    const int64_t c0 = (nchunks - 1 - (int64_t)blockIdx.x) * CHUNK;
     const int64_t c1 = min(c0 + (int64_t)CHUNK, n);
     const GridC g = a.g;
     const int s = a.sc.s;
@@ -433,6 +444,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs<T> a)
     if (tid < ST_NSTAT) sstat[tid] = 0;
     __syncthreads();
     const int base = s_base;
+    int nout = 0;   // this lane's deposits outside the window
 
     const int64_t wbase = c0 + (int64_t)(tid >> 6) * (RUN * RUNS * 64);
     for (int r = 0; r < RUNS; ++r) {
@@ -492,7 +504,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs<T> a)
                     aJ[3] += jv * w11;
                 } else {
                     deposit_lane<T>(key, jv * w00, jv * w01, jv * w10, jv * w11, winJ, base, a.accJ, g.nr1,
-                                    a.sc.jscale, sstat);
+                                    a.sc.jscale, nout);
                 }
                 // Cartesian move in the particle's plane, in cell units
                 const T fj = (T)j;
@@ -570,12 +582,12 @@ __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs<T> a)
                     aQ[2] += w10;
                     aQ[3] += w11;
                 } else {
-                    deposit_lane<T>(key, w00, w01, w10, w11, winQ, base, a.accQ, g.nr1, a.sc.qscale, sstat);
+                    deposit_lane<T>(key, w00, w01, w10, w11, winQ, base, a.accQ, g.nr1, a.sc.qscale, nout);
                 }
             }
         }
         if constexpr (PUSH) {
-            deposit4<T>(keyJ >= 0, keyJ, aJ[0], aJ[1], aJ[2], aJ[3], winJ, base, a.accJ, g.nr1, a.sc.jscale, sstat);
+            deposit4<T>(keyJ >= 0, keyJ, aJ[0], aJ[1], aJ[2], aJ[3], winJ, base, a.accJ, g.nr1, a.sc.jscale, nout);
             {
                 const uint64_t m = ballot(absorbed_n > 0);
                 (void)m;
@@ -617,7 +629,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs<T> a)
             }
         }
         if constexpr (DEPQ)
-            deposit4<T>(keyQ >= 0, keyQ, aQ[0], aQ[1], aQ[2], aQ[3], winQ, base, a.accQ, g.nr1, a.sc.qscale, sstat);
+            deposit4<T>(keyQ >= 0, keyQ, aQ[0], aQ[1], aQ[2], aQ[3], winQ, base, a.accQ, g.nr1, a.sc.qscale, nout);
         if constexpr (PUSH) {
             st4(a.p.cell + q0, cell);
             st4(a.p.dr + q0, dr);
@@ -626,6 +638,12 @@ __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs<T> a)
             st4(a.p.vt + q0, vt);
             st4(a.p.vz + q0, vz);
         }
+    }
+    {
+        int tot = nout;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off);
+        if (lane == 0 && tot) atomicAdd(&sstat[ST_WINOUT], (unsigned long long)tot);
     }
     __syncthreads();
     if constexpr (PUSH) {
