@@ -105,6 +105,7 @@ struct pic_ctx {
     unsigned long long *stats = nullptr;
     int32_t *errw = nullptr;
     int32_t *hist = nullptr, *cursor = nullptr;
+    int64_t *scanpart = nullptr;   // block totals of the sort's scan
     int64_t *live_index = nullptr;
     double *stage = nullptr;     // 5 doubles + id + next per staged particle
     int64_t stage_cap = 0;
@@ -129,7 +130,7 @@ struct pic_ctx {
     bool have_prev = false;
     int64_t last_solve = -2;
     // adaptive iteration budget: each solve's state lands in pinned host
-    // memory asynchronously; the next solve budgets the recent count + 2
+    // memory asynchronously; the next solve budgets the recent count + 1
     MGState *mg_host = nullptr;   // pinned ring
     int mg_ring = 0;
     int mg_budget = 8;
@@ -467,6 +468,7 @@ static void layout(pic_ctx &c, Carver &cv)
     c.errw = cv.take<int32_t>(1);
     c.hist = cv.take<int32_t>(ncells + 1);
     c.cursor = cv.take<int32_t>(ncells + 1);
+    c.scanpart = cv.take<int64_t>(sort_scan_blocks(ncells) + 1);
     const int64_t capmax = std::max(f.capacity[0], f.capacity[1]);
     c.live_index = cv.take<int64_t>(capmax);
     c.stage_cap = std::min<int64_t>(capmax, 1 << 20);
@@ -720,8 +722,8 @@ template <typename T> static void sort_species(pic_ctx &c, int s)
 {
     const int from = c.cur[s], to = 1 - from;
     timer_start(c, c.t_sort);
-    launch_sort<T>(parts<T>(c, s, from), parts<T>(c, s, to), c.ctl + s, c.ctl + 2 + s, c.hist, c.cursor, c.g.ncells,
-                   c.cfg.capacity[s], c.stream);
+    launch_sort<T>(parts<T>(c, s, from), parts<T>(c, s, to), c.ctl + s, c.ctl + 2 + s, c.hist, c.cursor, c.scanpart,
+                   c.g.ncells, c.cfg.capacity[s], c.stream);
     timer_stop(c, c.t_sort);
     c.cur[s] = to;
 }
@@ -765,13 +767,19 @@ static void finalize_charge(pic_ctx &c)
 // V-cycle on the correction: two red-black sweeps on the 5-point fine
 // level, one four-colour sweep on the Galerkin levels, exact solve on the
 // bottom level (dense inverse, one multi-block product).
+#ifndef PIC_TILE_SMOOTH
+#define PIC_TILE_SMOOTH 1
+#endif
 static void vcycle(pic_ctx &c, const MGLevels &lv, const MGState *st)
 {
     for (int l = 0; l < c.lb; ++l) {
         const int nc = lv.L[l].nine ? 4 : 2;
         const int nu = l == 0 ? 2 : 1;
-        for (int k = 0; k < nu; ++k)
-            for (int col = 0; col < nc; ++col) launch_mg_smooth(lv.L[l], col, st, c.stream);
+        if (PIC_TILE_SMOOTH)
+            launch_mg_smooth_tile(lv.L[l], nu, false, st, c.stream);
+        else
+            for (int k = 0; k < nu; ++k)
+                for (int col = 0; col < nc; ++col) launch_mg_smooth(lv.L[l], col, st, c.stream);
         launch_mg_restrict(lv.L[l], lv.L[l + 1], st, c.stream);
     }
     launch_dense_solve(lv.coarse_inv, lv.L[c.lb], st, c.stream);
@@ -779,8 +787,11 @@ static void vcycle(pic_ctx &c, const MGLevels &lv, const MGState *st)
         launch_mg_prolong(lv.L[l], lv.L[l + 1], st, c.stream);
         const int nc = lv.L[l].nine ? 4 : 2;
         const int nu = l == 0 ? 2 : 1;
-        for (int k = 0; k < nu; ++k)
-            for (int col = nc - 1; col >= 0; --col) launch_mg_smooth(lv.L[l], col, st, c.stream);
+        if (PIC_TILE_SMOOTH)
+            launch_mg_smooth_tile(lv.L[l], nu, true, st, c.stream);
+        else
+            for (int k = 0; k < nu; ++k)
+                for (int col = nc - 1; col >= 0; --col) launch_mg_smooth(lv.L[l], col, st, c.stream);
     }
 }
 
@@ -818,7 +829,7 @@ static pic_status solve(pic_ctx &c, int64_t n, double rtol, int max_cycles, pic_
         if (short_run) {
             c.mg_budget = std::min(max_cycles, c.mg_budget + 4);
         } else if (seen > 0) {
-            c.mg_budget = std::min(max_cycles, seen + 2);
+            c.mg_budget = std::min(max_cycles, seen + 1);
         }
         budget = std::max(2, std::min(max_cycles, c.mg_budget));
     }

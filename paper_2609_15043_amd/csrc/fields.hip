@@ -242,6 +242,83 @@ __device__ __forceinline__ void op_prolong(const MGLevel &F, const MGLevel &C, i
     }
 }
 
+// Tile smoother: each workgroup stages a TZ x TR tile of the correction plus
+// a one-node halo in LDS and runs `sweeps` Gauss-Seidel sweeps (red-black on
+// the 5-point level, four colours on the Galerkin levels; colours in reverse
+// order when `reverse`) on its tile, the halo held at its values from the
+// start of the kernel: Gauss-Seidel inside a tile, Jacobi across tiles.
+// Reversing the colour order for the post-smoother keeps the V-cycle a
+// symmetric preconditioner.
+constexpr int TILE_Z = 16, TILE_R = 64, TILE_PER = TILE_Z * TILE_R / 256;
+__global__ __launch_bounds__(256) void k_mg_smooth_tile(MGLevel L, int sweeps, int reverse, const MGState *st)
+{
+    __shared__ double xs[(TILE_Z + 2) * (TILE_R + 2)];
+    if (st->done) return;
+    constexpr int W = TILE_R + 2;
+    const int tiles_r = (L.nr1 + TILE_R - 1) / TILE_R;
+    const int i0 = (blockIdx.x / tiles_r) * TILE_Z, j0 = (blockIdx.x % tiles_r) * TILE_R;
+    for (int e = threadIdx.x; e < (TILE_Z + 2) * W; e += 256) {
+        const int i = i0 - 1 + e / W, j = j0 - 1 + e % W;
+        xs[e] = (i >= 0 && i <= L.nz && j >= 0 && j <= L.nr) ? L.phi[i * L.nr1 + j] : 0.0;
+    }
+    // owned nodes: coefficients and right-hand side in registers
+    const int nc = L.nine ? 4 : 2;
+    double coef[TILE_PER][9], rhs[TILE_PER];
+    int own[TILE_PER], col[TILE_PER];
+#pragma unroll
+    for (int q = 0; q < TILE_PER; ++q) {
+        const int e = threadIdx.x + 256 * q;
+        const int i = i0 + e / TILE_R, j = j0 + e % TILE_R;
+        own[q] = -1;
+        col[q] = -1;
+        rhs[q] = 0.0;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) coef[q][k] = 0.0;
+        if (i > L.nz || j > L.nr) continue;
+        const int n = i * L.nr1 + j;
+        if (L.dir[n]) continue;
+        own[q] = n;
+        col[q] = L.nine ? ((i & 1) << 1) | (j & 1) : ((i + j) & 1);
+        rhs[q] = L.rhs[n];
+        if (L.nine) {
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                const int di = k / 3 - 1, dj = k % 3 - 1;
+                const bool in = i + di >= 0 && i + di <= L.nz && j + dj >= 0 && j + dj <= L.nr;
+                coef[q][k] = in ? L.a[(size_t)k * L.nodes + n] : 0.0;
+            }
+        } else {
+            coef[q][4] = L.cc[n];
+            coef[q][3] = j > 0 ? -L.cw[n] : 0.0;
+            coef[q][5] = j < L.nr ? -L.ce[n] : 0.0;
+            coef[q][1] = i > 0 ? -L.cs[n] : 0.0;
+            coef[q][7] = i < L.nz ? -L.cn[n] : 0.0;
+        }
+    }
+    __syncthreads();
+    for (int sw = 0; sw < sweeps; ++sw)
+        for (int cc = 0; cc < nc; ++cc) {
+            const int c = reverse ? nc - 1 - cc : cc;
+#pragma unroll
+            for (int q = 0; q < TILE_PER; ++q) {
+                if (col[q] != c) continue;
+                const int e = threadIdx.x + 256 * q;
+                const int li = e / TILE_R + 1, lj = e % TILE_R + 1;
+                double ax = 0.0;
+#pragma unroll
+                for (int k = 0; k < 9; ++k) ax += coef[q][k] * xs[(li + k / 3 - 1) * W + lj + k % 3 - 1];
+                xs[li * W + lj] += (rhs[q] - ax) / coef[q][4];
+            }
+            __syncthreads();
+        }
+#pragma unroll
+    for (int q = 0; q < TILE_PER; ++q) {
+        if (own[q] < 0) continue;
+        const int e = threadIdx.x + 256 * q;
+        L.phi[own[q]] = xs[(e / TILE_R + 1) * W + e % TILE_R + 1];
+    }
+}
+
 __global__ void k_mg_smooth(MGLevel L, int color, const MGState *st)
 {
     if (st->done) return;
@@ -533,6 +610,11 @@ int pcg_partial_size(int nodes) { return 2 * (int)red_grid(nodes); }
 void launch_mg_smooth(const MGLevel &L, int color, const MGState *st, hipStream_t s)
 {
     hipLaunchKernelGGL(k_mg_smooth, dim3(mg_grid(L.nodes)), dim3(256), 0, s, L, color, st);
+}
+void launch_mg_smooth_tile(const MGLevel &L, int sweeps, bool reverse, const MGState *st, hipStream_t s)
+{
+    const int tiles = ((L.nz + 1 + TILE_Z - 1) / TILE_Z) * ((L.nr1 + TILE_R - 1) / TILE_R);
+    hipLaunchKernelGGL(k_mg_smooth_tile, dim3(tiles), dim3(256), 0, s, L, sweeps, reverse ? 1 : 0, st);
 }
 void launch_mg_restrict(const MGLevel &F, const MGLevel &C, const MGState *st, hipStream_t s)
 {

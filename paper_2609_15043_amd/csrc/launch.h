@@ -29,7 +29,8 @@ void launch_births(const Births<T> &b, const Parts<T> &pe, const Parts<T> &pi, i
                    const GridC &g, int32_t *err, unsigned long long *stats, hipStream_t st);
 template <typename T>
 void launch_sort(const Parts<T> &src, const Parts<T> &dst, int64_t *count, int64_t *count_old, int32_t *hist,
-                 int32_t *cursor, int ncells, int64_t cap, hipStream_t st);
+                 int32_t *cursor, int64_t *scanpart, int ncells, int64_t cap, hipStream_t st);
+int sort_scan_blocks(int ncells);
 
 template <typename T>
 void launch_stage(const double *phi, const double *ec, const double *es, double cs, double sn,
@@ -48,6 +49,7 @@ struct PCGVec {
 };
 int pcg_partial_size(int nodes);
 void launch_mg_smooth(const MGLevel &L, int color, const MGState *st, hipStream_t s);
+void launch_mg_smooth_tile(const MGLevel &L, int sweeps, bool reverse, const MGState *st, hipStream_t s);
 void launch_mg_restrict(const MGLevel &F, const MGLevel &C, const MGState *st, hipStream_t s);
 void launch_mg_prolong(const MGLevel &F, const MGLevel &C, const MGState *st, hipStream_t s);
 void launch_dense_solve(const double *inv, const MGLevel &L, const MGState *st, hipStream_t s);

@@ -389,8 +389,13 @@ __device__ __forceinline__ void node_weights(int j, T dr, T dz, T &w00, T &w01, 
 // accumulate in registers over the run (particles of one cell), then one
 // wave reduction per run; the collisions run in k_collide over the queue.
 // ---------------------------------------------------------------------------
+#ifdef PIC_PASS_WAVES_PER_EU
+#define PIC_PASS_OCCUPANCY __attribute__((amdgpu_waves_per_eu(PIC_PASS_WAVES_PER_EU, 8)))
+#else
+#define PIC_PASS_OCCUPANCY
+#endif
 template <typename T, bool PUSH, bool DEPQ>
-__global__ __launch_bounds__(BLOCK) void k_pass(PassArgs<T> a)
+__global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassArgs<T> a)
 {
     using F4 = typename Field4<T>::type;
     constexpr int WIN = Win<T>::N;
@@ -818,85 +823,184 @@ __global__ void k_births_commit(int32_t *bcount, int32_t cap, int64_t *count, in
 }
 
 // ---------------------------------------------------------------------------
-// Counting sort by cell (absorbed particles dropped)
+// Counting sort by cell (absorbed particles dropped).  The arrays are
+// nearly sorted (particles move a fraction of a cell per step), so each
+// block of SORT_PER particles counts its cells in an LDS window of
+// SORT_WIN cells around its first particle and touches the global
+// histogram / cursors once per window cell it uses; particles outside the
+// window (births appended since the last sort) go to global atomics.
 // ---------------------------------------------------------------------------
-__global__ void k_sort_hist(const int32_t *cell, const int64_t *count, int32_t *hist, int ncells)
+constexpr int SORT_PER = 1024;
+constexpr int SORT_WIN = 4096;
+constexpr int SCAN_BLOCK = 1024;
+
+__device__ __forceinline__ int sort_window_lo(const int32_t *cell, int64_t p0, int64_t n, int ncells)
 {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool act = p < *count;
-    const int32_t c = act ? cell[p] : -1;
-    const bool live = c >= 0 && c < ncells;
-    uint64_t todo = ballot(live);
-    while (todo) {
-        const int lead = __ffsll((unsigned long long)todo) - 1;
-        const int k = __builtin_amdgcn_readlane(c, lead);
-        const uint64_t mm = ballot(live && c == k);
-        if (lane_id() == lead) atomicAdd(&hist[k], (int)__popcll(mm));
-        todo &= ~mm;
+    int c = -1;
+    for (int k = 0; k < 64 && c < 0 && p0 + k < n; ++k) {
+        const int v = cell[p0 + k];
+        if (v >= 0 && v < ncells) c = v;
+    }
+    return c < 0 ? 0 : max(0, c - SORT_WIN / 4);
+}
+
+__global__ __launch_bounds__(256) void k_sort_hist(const int32_t *cell, const int64_t *count, int32_t *hist, int ncells)
+{
+    __shared__ int bins[SORT_WIN];
+    __shared__ int s_lo;
+    const int64_t n = *count;
+    const int64_t p0 = (int64_t)blockIdx.x * SORT_PER;
+    if (p0 >= n) return;
+    if (threadIdx.x == 0) s_lo = sort_window_lo(cell, p0, n, ncells);
+    for (int k = threadIdx.x; k < SORT_WIN; k += blockDim.x) bins[k] = 0;
+    __syncthreads();
+    const int lo = s_lo;
+    for (int q = 0; q < SORT_PER / 256; ++q) {
+        const int64_t p = p0 + q * 256 + threadIdx.x;
+        const int32_t c = p < n ? cell[p] : -1;
+        const bool live = c >= 0 && c < ncells;
+        uint64_t todo = ballot(live);
+        while (todo) {
+            const int lead = __ffsll((unsigned long long)todo) - 1;
+            const int k = __builtin_amdgcn_readlane(c, lead);
+            const uint64_t mm = ballot(live && c == k);
+            if (lane_id() == lead) {
+                const int b = k - lo;
+                if (b >= 0 && b < SORT_WIN)
+                    atomicAdd(&bins[b], (int)__popcll(mm));
+                else
+                    atomicAdd(&hist[k], (int)__popcll(mm));
+            }
+            todo &= ~mm;
+        }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < SORT_WIN; k += blockDim.x)
+        if (bins[k]) atomicAdd(&hist[lo + k], bins[k]);
+}
+
+// exclusive scan of hist in blocks of SCAN_BLOCK cells (block totals to part)
+__global__ __launch_bounds__(1024) void k_scan_blocks(const int32_t *hist, int ncells, int32_t *cursor, int64_t *part)
+{
+    __shared__ int64_t v[SCAN_BLOCK];
+    const int i = blockIdx.x * SCAN_BLOCK + threadIdx.x;
+    const int64_t h = i < ncells ? hist[i] : 0;
+    v[threadIdx.x] = h;
+    __syncthreads();
+    for (int off = 1; off < SCAN_BLOCK; off <<= 1) {
+        const int64_t a = threadIdx.x >= off ? v[threadIdx.x - off] : 0;
+        __syncthreads();
+        v[threadIdx.x] += a;
+        __syncthreads();
+    }
+    if (i < ncells) cursor[i] = (int32_t)(v[threadIdx.x] - h);
+    if (threadIdx.x == SCAN_BLOCK - 1) part[blockIdx.x] = v[threadIdx.x];
+}
+
+// single block: exclusive scan of the block totals; count_old <- count,
+// count <- live total
+__global__ __launch_bounds__(1024) void k_scan_top(int64_t *part, int nblocks, int64_t *count, int64_t *count_old)
+{
+    __shared__ int64_t v[1024];
+    __shared__ int64_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    for (int b0 = 0; b0 < nblocks; b0 += 1024) {
+        __syncthreads();
+        const int b = b0 + threadIdx.x;
+        const int64_t h = b < nblocks ? part[b] : 0;
+        v[threadIdx.x] = h;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            const int64_t a = threadIdx.x >= off ? v[threadIdx.x - off] : 0;
+            __syncthreads();
+            v[threadIdx.x] += a;
+            __syncthreads();
+        }
+        if (b < nblocks) part[b] = carry + v[threadIdx.x] - h;
+        __syncthreads();
+        if (threadIdx.x == 1023) carry += v[1023];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        *count_old = *count;
+        *count = carry;
     }
 }
 
-// single block: exclusive scan of hist[0..ncells) into cursor, hist reset,
-// count_old <- count, count <- live total
-__global__ __launch_bounds__(1024) void k_sort_scan(int32_t *hist, int32_t *cursor, int ncells, int64_t *count,
-                                                    int64_t *count_old)
+// cursor += block offset; histogram cleared for the next sort
+__global__ void k_scan_add(int32_t *cursor, int32_t *hist, int ncells, const int64_t *part)
 {
-    __shared__ int64_t part[1024];
-    const int t = threadIdx.x;
-    const int per = (ncells + 1023) / 1024;
-    const int lo = min(t * per, ncells), hi = min(lo + per, ncells);
-    int64_t sum = 0;
-    for (int k = lo; k < hi; ++k) sum += hist[k];
-    part[t] = sum;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const int64_t v = t >= off ? part[t - off] : 0;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
-    }
-    int64_t run = part[t] - sum;
-    for (int k = lo; k < hi; ++k) {
-        const int h = hist[k];
-        cursor[k] = (int32_t)run;
-        run += h;
-        hist[k] = 0;
-    }
-    if (t == 1023) {
-        *count_old = *count;
-        *count = part[1023];
-    }
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ncells) return;
+    cursor[i] += (int32_t)part[i / SCAN_BLOCK];
+    hist[i] = 0;
 }
 
 template <typename T>
-__global__ void k_sort_scatter(Parts<T> src, Parts<T> dst, const int64_t *count_old, int32_t *cursor, int ncells)
+__global__ __launch_bounds__(256) void k_sort_scatter(Parts<T> src, Parts<T> dst, const int64_t *count_old,
+                                                      int32_t *cursor, int ncells)
 {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool act = p < *count_old;
-    const int32_t c = act ? src.cell[p] : -1;
-    const bool live = c >= 0 && c < ncells;
-    uint64_t todo = ballot(live);
-    int64_t pos = -1;
-    while (todo) {
-        const int lead = __ffsll((unsigned long long)todo) - 1;
-        const int k = __builtin_amdgcn_readlane(c, lead);
-        const uint64_t mm = ballot(live && c == k);
-        int b0 = 0;
-        if (lane_id() == lead) b0 = atomicAdd(&cursor[k], (int)__popcll(mm));
-        b0 = __builtin_amdgcn_readlane(b0, lead);
-        if (live && c == k)
-            pos = b0 + __builtin_amdgcn_mbcnt_hi((uint32_t)(mm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mm, 0u));
-        todo &= ~mm;
+    __shared__ int bins[SORT_WIN];
+    __shared__ int s_lo;
+    constexpr int Q = SORT_PER / 256;
+    const int64_t n = *count_old;
+    const int64_t p0 = (int64_t)blockIdx.x * SORT_PER;
+    if (p0 >= n) return;
+    if (threadIdx.x == 0) s_lo = sort_window_lo(src.cell, p0, n, ncells);
+    for (int k = threadIdx.x; k < SORT_WIN; k += blockDim.x) bins[k] = 0;
+    __syncthreads();
+    const int lo = s_lo;
+    int32_t c[Q];
+    int64_t pos[Q];
+    bool inwin[Q];
+    // 1. offsets inside the block (window cells) or global positions (others)
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int64_t p = p0 + q * 256 + threadIdx.x;
+        c[q] = p < n ? src.cell[p] : -1;
+        const bool live = c[q] >= 0 && c[q] < ncells;
+        pos[q] = -1;
+        inwin[q] = live && c[q] - lo >= 0 && c[q] - lo < SORT_WIN;
+        uint64_t todo = ballot(live);
+        while (todo) {
+            const int lead = __ffsll((unsigned long long)todo) - 1;
+            const int k = __builtin_amdgcn_readlane(c[q], lead);
+            const uint64_t mm = ballot(live && c[q] == k);
+            int b0 = 0;
+            if (lane_id() == lead) {
+                const int b = k - lo;
+                if (b >= 0 && b < SORT_WIN)
+                    b0 = atomicAdd(&bins[b], (int)__popcll(mm));
+                else
+                    b0 = atomicAdd(&cursor[k], (int)__popcll(mm));
+            }
+            b0 = __builtin_amdgcn_readlane(b0, lead);
+            if (live && c[q] == k)
+                pos[q] = b0 + __builtin_amdgcn_mbcnt_hi((uint32_t)(mm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mm, 0u));
+            todo &= ~mm;
+        }
     }
-    if (live) {
-        dst.cell[pos] = c;
-        dst.dr[pos] = src.dr[p];
-        dst.dz[pos] = src.dz[p];
-        dst.vr[pos] = src.vr[p];
-        dst.vt[pos] = src.vt[p];
-        dst.vz[pos] = src.vz[p];
-        dst.id[pos] = src.id[p];
-        dst.next[pos] = src.next[p];
+    __syncthreads();
+    // 2. one global reservation per window cell the block uses
+    for (int k = threadIdx.x; k < SORT_WIN; k += blockDim.x) {
+        const int cnt = bins[k];
+        if (cnt) bins[k] = atomicAdd(&cursor[lo + k], cnt);
+    }
+    __syncthreads();
+    // 3. move
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        if (pos[q] < 0) continue;
+        const int64_t p = p0 + q * 256 + threadIdx.x;
+        const int64_t o = inwin[q] ? bins[c[q] - lo] + pos[q] : pos[q];
+        dst.cell[o] = c[q];
+        dst.dr[o] = src.dr[p];
+        dst.dz[o] = src.dz[p];
+        dst.vr[o] = src.vr[p];
+        dst.vt[o] = src.vt[p];
+        dst.vz[o] = src.vz[p];
+        dst.id[o] = src.id[p];
+        dst.next[o] = src.next[p];
     }
 }
 
@@ -1014,13 +1118,16 @@ void launch_births(const Births<T> &b, const Parts<T> &pe, const Parts<T> &pi, i
 
 template <typename T>
 void launch_sort(const Parts<T> &src, const Parts<T> &dst, int64_t *count, int64_t *count_old, int32_t *hist,
-                 int32_t *cursor, int ncells, int64_t cap, hipStream_t st)
+                 int32_t *cursor, int64_t *scanpart, int ncells, int64_t cap, hipStream_t st)
 {
-    const unsigned nb = blocks_for(cap, 256);
+    const unsigned nb = blocks_for(cap, SORT_PER), ns = blocks_for(ncells, SCAN_BLOCK);
     hipLaunchKernelGGL(k_sort_hist, dim3(nb), dim3(256), 0, st, src.cell, count, hist, ncells);
-    hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, st, hist, cursor, ncells, count, count_old);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(ns), dim3(SCAN_BLOCK), 0, st, hist, ncells, cursor, scanpart);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, scanpart, (int)ns, count, count_old);
+    hipLaunchKernelGGL(k_scan_add, dim3(blocks_for(ncells, 256)), dim3(256), 0, st, cursor, hist, ncells, scanpart);
     hipLaunchKernelGGL(k_sort_scatter<T>, dim3(nb), dim3(256), 0, st, src, dst, count_old, cursor, ncells);
 }
+int sort_scan_blocks(int ncells) { return (int)blocks_for(ncells, SCAN_BLOCK); }
 
 #define PIC_INSTANTIATE(T)                                                                                          \
     template void launch_load<T>(const Parts<T> &, int64_t, uint32_t, int, double, double, double, double,          \
@@ -1037,7 +1144,7 @@ void launch_sort(const Parts<T> &src, const Parts<T> &dst, int64_t *count, int64
                                    int64_t, int64_t, long long *, long long *, bool, double, const GridC &,         \
                                    int32_t *, unsigned long long *, hipStream_t);                                   \
     template void launch_sort<T>(const Parts<T> &, const Parts<T> &, int64_t *, int64_t *, int32_t *, int32_t *,    \
-                                 int, int64_t, hipStream_t);
+                                 int64_t *, int, int64_t, hipStream_t);
 
 PIC_INSTANTIATE(float)
 PIC_INSTANTIATE(double)
