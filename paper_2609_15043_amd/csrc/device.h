@@ -92,6 +92,24 @@ __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ long long to_fixed(double v, double scale) { return __double2ll_rn(v * scale); }
 
+// round(v * scale) for a power-of-two scale, fast path of the particle
+// deposits: for |x| < 2^51, x + 1.5 * 2^52 rounds x to an integer (half to
+// even, as the conversion above) and leaves it in the low significand bits,
+// so the integer is the difference of the two bit patterns.  Larger values
+// take the library conversion.  The FP32 overload is exact in the same way
+// (the product of an FP32 value and a power of two is exact in FP64).
+__device__ __forceinline__ long long to_fixed_fast(double v, double scale)
+{
+    constexpr double magic = 6755399441055744.0;   // 1.5 * 2^52
+    const double x = v * scale;
+    if (!(fabs(x) < 0x1p51)) return __double2ll_rn(x);
+    return __double_as_longlong(x + magic) - __double_as_longlong(magic);
+}
+__device__ __forceinline__ long long to_fixed_fast(float v, float scale)
+{
+    return to_fixed_fast((double)v, (double)scale);
+}
+
 __device__ __forceinline__ void atomic_add_i64(long long *p, long long v)
 {
     atomicAdd(reinterpret_cast<unsigned long long *>(p), static_cast<unsigned long long>(v));

@@ -8,23 +8,26 @@
 
 namespace pic {
 
-// LDS deposit window (nodes) of one particle block: whole node rows around
-// the block's middle particle, so particles that drifted a few cells since
-// the last sort still land in LDS.  FP32 window values: 2048 nodes; FP64: 1024.
-#ifndef PIC_WIN_NODES_F32
-#define PIC_WIN_NODES_F32 2048
-#endif
-#ifndef PIC_WIN_NODES_F64
-#define PIC_WIN_NODES_F64 1024
+// LDS deposit window of one particle block (node slots, 64-bit fixed point
+// in either precision): whole node rows around the block's particles, so
+// particles that drifted a few cells since the last sort still land in LDS.
+// 2304 slots: eight padded rows of a 256-cell radial grid, and four blocks
+// of the fused pass per CU.
+#ifndef PIC_WIN_NODES
+#define PIC_WIN_NODES 2304
 #endif
 template <typename T> struct Win {
-    static constexpr int N = sizeof(T) == 4 ? PIC_WIN_NODES_F32 : PIC_WIN_NODES_F64;
+    static constexpr int N = PIC_WIN_NODES;
 };
 constexpr int BLOCK = 256;
 #ifndef PIC_DEPOSIT_GROUPS
-#define PIC_DEPOSIT_GROUPS 2
+#define PIC_DEPOSIT_GROUPS 4
 #endif
 constexpr int DEPOSIT_GROUPS = PIC_DEPOSIT_GROUPS;   // wave reductions per run deposit before lanes add their own
+#ifndef PIC_DEPOSIT_MIN_LANES
+#define PIC_DEPOSIT_MIN_LANES 16
+#endif
+constexpr int DEPOSIT_MIN_LANES = PIC_DEPOSIT_MIN_LANES;   // smallest group worth a wave reduction
 constexpr int RUN = 4;                  // consecutive particles per lane per vector load
 constexpr int RUNS = 4;                 // runs per wave per block
 constexpr int CHUNK = BLOCK * RUN * RUNS;   // particles per pass block (4096)

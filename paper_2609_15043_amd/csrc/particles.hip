@@ -169,53 +169,102 @@ __global__ void k_unplace(Parts<T> p, const int64_t *count, const int64_t *live_
 }
 
 // ---------------------------------------------------------------------------
-// Wave-collective deposit of four node values around lower-left node `key`.
-// Lanes are grouped by key (segmented by ballot); each group's sums (wave
-// scan, total in lane 63) are added to the block's LDS window in the
-// working precision, or, for a node outside the window, straight to the
-// global 64-bit fixed-point accumulator.  The window is converted to fixed
-// point once per touched node when the block flushes it, so the global
-// sums are exact and independent of block order.  Called by all 64 lanes.
+// LDS window of node values of one pass block.  Row mode: `rows` whole node
+// rows from row ib, stored with a padded row stride ws = 8 (mod 64).  With
+// the grid's own stride nr + 1 a node row sits one bank after the row below
+// it, so the nodes around a few neighbouring cells all fall in a handful of
+// banks and the adds of a wave whose particles spread over those cells
+// queue there; with the padded stride adjacent rows are 8 banks apart.
+// Linear mode (a row too long for three to fit): nodes [base, base + N).
+// ---------------------------------------------------------------------------
+struct WinMap {
+    int ib, rows, ws, base;   // rows == 0: linear mode
+};
+
+__device__ __forceinline__ int win_stride(int nr1) { return nr1 + ((8 - nr1) & 63); }
+
+// window slot of node (r, c), or -1 outside the window
+template <int N> __device__ __forceinline__ int win_off(const WinMap &w, int r, int c, int nr1)
+{
+    if (w.rows) {
+        const int d = r - w.ib;
+        return (unsigned)d < (unsigned)w.rows ? d * w.ws + c : -1;
+    }
+    const int o = r * nr1 + c - w.base;
+    return (unsigned)o < (unsigned)N ? o : -1;
+}
+
+// One node value, in the accumulator's 64-bit fixed point, to the window
+// (an integer LDS add: exact, independent of order, and on this hardware
+// an order of magnitude faster than a floating-point LDS add) or, outside
+// the window, to the global accumulator.
+template <typename T>
+__device__ __forceinline__ void deposit_node(const WinMap &w, int r, int c, T v, long long *win, long long *acc,
+                                             int nr1, T scale, int &nout)
+{
+    const long long f = to_fixed_fast(v, scale);
+    const int o = win_off<Win<T>::N>(w, r, c, nr1);
+    if (o >= 0) {
+        atomicAdd(reinterpret_cast<unsigned long long *>(&win[o]), static_cast<unsigned long long>(f));
+    } else {
+        atomic_add_i64(&acc[r * nr1 + c], f);
+        ++nout;
+    }
+}
+
+// Four node values of one particle in cell (i, j) straight into the window
+// (or the global accumulator outside it): the per-lane path.
+template <typename T>
+__device__ __forceinline__ void deposit_lane(int i, int j, T v0, T v1, T v2, T v3, long long *win, const WinMap &w,
+                                             long long *acc, int nr1, T scale, int &nout)
+{
+    deposit_node<T>(w, i, j, v0, win, acc, nr1, scale, nout);
+    deposit_node<T>(w, i, j + 1, v1, win, acc, nr1, scale, nout);
+    deposit_node<T>(w, i + 1, j, v2, win, acc, nr1, scale, nout);
+    deposit_node<T>(w, i + 1, j + 1, v3, win, acc, nr1, scale, nout);
+}
+
+// ---------------------------------------------------------------------------
+// Wave-collective deposit of four node values around the lower-left node
+// (i, j) of each lane's run.  Lanes are grouped by cell (segmented by
+// ballot); each group's sums (wave scan, total in lane 63) are added to the
+// block's LDS window in the working precision, or, for a node outside the
+// window, straight to the global 64-bit fixed-point accumulator.  The
+// window is converted to fixed point once per touched node when the block
+// flushes it, so the global sums are exact and independent of block order.
+// Called by all 64 lanes.
 // ---------------------------------------------------------------------------
 template <typename T>
-__device__ __forceinline__ void deposit_lane(int key, T v0, T v1, T v2, T v3, T *win, int base, long long *acc,
-                                             int nr1, double scale, int &nout);
-
-template <typename T>
-__device__ __forceinline__ void deposit4(bool valid, int key, T v0, T v1, T v2, T v3, T *win, int base,
-                                         long long *acc, int nr1, double scale, int &nout)
+__device__ __forceinline__ void deposit4(bool valid, int i, int j, T v0, T v1, T v2, T v3, long long *win,
+                                         const WinMap &w, long long *acc, int nr1, T scale, int &nout)
 {
+    const int key = i * nr1 + j;
     uint64_t todo = ballot(valid);
     const int lane = lane_id();
-    // at most DEPOSIT_GROUPS wave reductions; lanes of further keys (a wave
-    // whose particles drifted apart since the sort) add their own sums
+    // wave reductions for groups of at least DEPOSIT_MIN_LANES lanes (at most
+    // DEPOSIT_GROUPS of them); the lanes of smaller groups (a wave whose
+    // particles drifted apart since the sort) add their own values, an
+    // integer LDS add being cheaper than a reduction for a few lanes
     for (int it = 0; todo && it < DEPOSIT_GROUPS; ++it) {
         const int lead = __ffsll((unsigned long long)todo) - 1;
         const int k = __builtin_amdgcn_readlane(key, lead);
         const bool m = valid && key == k;
         const uint64_t mm = ballot(m);
+        if (__popcll(mm) < DEPOSIT_MIN_LANES) break;
+        const int ki = __builtin_amdgcn_readlane(i, lead), kj = __builtin_amdgcn_readlane(j, lead);
         const T s0 = wave_total(m ? v0 : (T)0);
         const T s1 = wave_total(m ? v1 : (T)0);
         const T s2 = wave_total(m ? v2 : (T)0);
         const T s3 = wave_total(m ? v3 : (T)0);
         if (lane == 63) {
-            const int nodes[4] = {k, k + 1, k + nr1, k + nr1 + 1};
-            const T sums[4] = {s0, s1, s2, s3};
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                if (sums[c] == (T)0) continue;
-                const int o = nodes[c] - base;
-                if (o >= 0 && o < Win<T>::N) {
-                    atomicAdd(&win[o], sums[c]);
-                } else {
-                    atomic_add_i64(&acc[nodes[c]], to_fixed((double)sums[c], scale));
-                    ++nout;
-                }
-            }
+            if (s0 != (T)0) deposit_node<T>(w, ki, kj, s0, win, acc, nr1, scale, nout);
+            if (s1 != (T)0) deposit_node<T>(w, ki, kj + 1, s1, win, acc, nr1, scale, nout);
+            if (s2 != (T)0) deposit_node<T>(w, ki + 1, kj, s2, win, acc, nr1, scale, nout);
+            if (s3 != (T)0) deposit_node<T>(w, ki + 1, kj + 1, s3, win, acc, nr1, scale, nout);
         }
         todo &= ~mm;
     }
-    if (todo >> lane & 1ull) deposit_lane<T>(key, v0, v1, v2, v3, win, base, acc, nr1, scale, nout);
+    if (todo >> lane & 1ull) deposit_lane<T>(i, j, v0, v1, v2, v3, win, w, acc, nr1, scale, nout);
 }
 
 __device__ __forceinline__ void count_wave(bool c, unsigned long long *sstat, int slot)
@@ -347,27 +396,6 @@ __device__ __forceinline__ void st4(int32_t *p, const int32_t (&o)[4])
     *reinterpret_cast<int4 *>(p) = make_int4(o[0], o[1], o[2], o[3]);
 }
 
-// Four node values of one particle straight into the window (or the global
-// accumulator outside it): the per-lane path for a particle whose cell
-// differs from its run's key.
-template <typename T>
-__device__ __forceinline__ void deposit_lane(int key, T v0, T v1, T v2, T v3, T *win, int base, long long *acc,
-                                             int nr1, double scale, int &nout)
-{
-    const int nodes[4] = {key, key + 1, key + nr1, key + nr1 + 1};
-    const T vals[4] = {v0, v1, v2, v3};
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        const int o = nodes[c] - base;
-        if (o >= 0 && o < Win<T>::N) {
-            atomicAdd(&win[o], vals[c]);
-        } else {
-            atomic_add_i64(&acc[nodes[c]], to_fixed((double)vals[c], scale));
-            ++nout;
-        }
-    }
-}
-
 // R^2-linear radial and linear axial weights of the four cell nodes
 template <typename T>
 __device__ __forceinline__ void node_weights(int j, T dr, T dz, T &w00, T &w01, T &w10, T &w11)
@@ -389,20 +417,24 @@ __device__ __forceinline__ void node_weights(int j, T dr, T dz, T &w00, T &w01, 
 // accumulate in registers over the run (particles of one cell), then one
 // wave reduction per run; the collisions run in k_collide over the queue.
 // ---------------------------------------------------------------------------
-#ifdef PIC_PASS_WAVES_PER_EU
-#define PIC_PASS_OCCUPANCY __attribute__((amdgpu_waves_per_eu(PIC_PASS_WAVES_PER_EU, 8)))
-#else
-#define PIC_PASS_OCCUPANCY
+// FP32 pass: at least PIC_PASS_WAVES_PER_EU waves per SIMD (the register
+// budget is held to fit them); FP64 runs at what its registers allow
+#ifndef PIC_PASS_WAVES_PER_EU
+#define PIC_PASS_WAVES_PER_EU 4
 #endif
+template <typename T> struct PassOcc {
+    static constexpr int min_waves = sizeof(T) == 4 ? PIC_PASS_WAVES_PER_EU : 1;
+};
+#define PIC_PASS_OCCUPANCY __attribute__((amdgpu_waves_per_eu(PassOcc<T>::min_waves, 8)))
 template <typename T, bool PUSH, bool DEPQ>
 __global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassArgs<T> a)
 {
     using F4 = typename Field4<T>::type;
     constexpr int WIN = Win<T>::N;
-    __shared__ T winJ[PUSH ? WIN : 1];
-    __shared__ T winQ[DEPQ ? WIN : 1];
+    __shared__ long long winJ[PUSH ? WIN : 1];   // fixed point, the accumulators' scales
+    __shared__ long long winQ[DEPQ ? WIN : 1];
     __shared__ unsigned long long sstat[ST_NSTAT];
-    __shared__ int s_base;
+    __shared__ WinMap s_w;
     constexpr int CAND_LDS = PUSH ? 512 : 1;
     __shared__ int32_t s_cand[CAND_LDS];
     __shared__ int s_ncand, s_qbase;
@@ -421,34 +453,43 @@ __global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassArgs<T> a
     const int s = a.sc.s;
     if (tid == 0) s_ncand = 0;
 
-    if (tid == 0) {
-        int cell = -1;
-        const int64_t mid = (c0 + c1) / 2;
-        for (int t = 0; t < 64 && cell < 0; ++t) {
-            const int64_t q = mid + t < c1 ? mid + t : c0 + t;
-            if (q < c1) cell = a.p.cell[q];
+    if (tid < 64) {
+        // window centre: mean row of 64 particles sampled across the chunk
+        // (one hot particle far from the rest cannot shift it by much)
+        const int64_t q = c0 + (int64_t)tid * (CHUNK / 64);
+        const int cl = q < c1 ? a.p.cell[q] : -1;
+        int ci = 0, cj = 0;
+        if (cl >= 0) split_cell(g, cl, ci, cj);
+        const float sr = wave_total(cl >= 0 ? (float)ci : 0.f);
+        const float sc = wave_total(cl >= 0 ? (float)cj : 0.f);
+        const float sn = wave_total(cl >= 0 ? 1.f : 0.f);
+        if (tid == 63) {
+        const int i = sn > 0.f ? (int)(sr / sn) : 0;
+        const int j = sn > 0.f ? (int)(sc / sn) : 0;
+        WinMap w;
+        w.ws = win_stride(g.nr1);
+        const int nrows = g.nodes / g.nr1;   // node rows of the grid
+        w.rows = min(WIN / w.ws, nrows);
+        if (w.rows >= min(3, nrows)) {
+            w.ib = max(0, min(i - (w.rows - 1) / 2, nrows - w.rows));
+            w.base = 0;
+        } else {
+            w.rows = 0;
+            w.ib = 0;
+            const int base = i * g.nr1 + j + g.nr1 / 2 + 1 - WIN / 2;
+            w.base = max(min(base, g.nodes - WIN), 0);
         }
-        int base = 0;
-        if (cell >= 0) {
-            int i, j;
-            split_cell(g, cell, i, j);
-            const int rows = WIN / g.nr1;   // node rows the window holds
-            if (rows >= 3) {
-                base = (i - (rows - 1) / 2) * g.nr1;
-            } else {
-                base = i * g.nr1 + j + g.nr1 / 2 + 1 - WIN / 2;
-            }
+        s_w = w;
         }
-        base = min(base, g.nodes - WIN);
-        s_base = max(base, 0);
     }
     for (int k = tid; k < WIN; k += BLOCK) {
-        if (PUSH) winJ[k] = (T)0;
-        if (DEPQ) winQ[k] = (T)0;
+        if (PUSH) winJ[k] = 0;
+        if (DEPQ) winQ[k] = 0;
     }
     if (tid < ST_NSTAT) sstat[tid] = 0;
     __syncthreads();
-    const int base = s_base;
+    const WinMap w = s_w;
+    const T jscale = (T)a.sc.jscale, qscale = (T)a.sc.qscale;   // powers of two
     int nout = 0;   // this lane's deposits outside the window
 
     const int64_t wbase = c0 + (int64_t)(tid >> 6) * (RUN * RUNS * 64);
@@ -470,7 +511,7 @@ __global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassArgs<T> a
         for (int k = 0; k < RUN; ++k) live[k] = q0 + k < c1 && cell[k] >= 0;
 
         // lane's run sums around its key nodes (old cell for J, new for Q)
-        int keyJ = -1, keyQ = -1;
+        int iJ = -1, jJ = 0, iQ = -1, jQ = 0;   // each run's first cell (row, column)
         T aJ[4] = {0, 0, 0, 0}, aQ[4] = {0, 0, 0, 0};
         int absorbed_n = 0;
         uint32_t cand_bits = 0;
@@ -501,15 +542,15 @@ __global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassArgs<T> a
                 uz += h * ez;
                 // azimuthal current at x^n with the time-centred v_theta
                 const T jv = (T)0.5 * (vt[k] + ut) * (T)a.sc.inv_vref;
-                if (keyJ < 0) keyJ = key;
-                if (key == keyJ) {
+                if (iJ < 0) iJ = i, jJ = j;
+                if (i == iJ && j == jJ) {
                     aJ[0] += jv * w00;
                     aJ[1] += jv * w01;
                     aJ[2] += jv * w10;
                     aJ[3] += jv * w11;
                 } else {
-                    deposit_lane<T>(key, jv * w00, jv * w01, jv * w10, jv * w11, winJ, base, a.accJ, g.nr1,
-                                    a.sc.jscale, nout);
+                    deposit_lane<T>(i, j, jv * w00, jv * w01, jv * w10, jv * w11, winJ, w, a.accJ, g.nr1,
+                                    jscale, nout);
                 }
                 // Cartesian move in the particle's plane, in cell units
                 const T fj = (T)j;
@@ -579,20 +620,19 @@ __global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassArgs<T> a
                 split_cell(g, cell[k], i, j);
                 T w00, w01, w10, w11;
                 node_weights<T>(j, dr[k], dz[k], w00, w01, w10, w11);
-                const int key = i * g.nr1 + j;
-                if (keyQ < 0) keyQ = key;
-                if (key == keyQ) {
+                if (iQ < 0) iQ = i, jQ = j;
+                if (i == iQ && j == jQ) {
                     aQ[0] += w00;
                     aQ[1] += w01;
                     aQ[2] += w10;
                     aQ[3] += w11;
                 } else {
-                    deposit_lane<T>(key, w00, w01, w10, w11, winQ, base, a.accQ, g.nr1, a.sc.qscale, nout);
+                    deposit_lane<T>(i, j, w00, w01, w10, w11, winQ, w, a.accQ, g.nr1, qscale, nout);
                 }
             }
         }
         if constexpr (PUSH) {
-            deposit4<T>(keyJ >= 0, keyJ, aJ[0], aJ[1], aJ[2], aJ[3], winJ, base, a.accJ, g.nr1, a.sc.jscale, nout);
+            deposit4<T>(iJ >= 0, iJ, jJ, aJ[0], aJ[1], aJ[2], aJ[3], winJ, w, a.accJ, g.nr1, jscale, nout);
             {
                 const uint64_t m = ballot(absorbed_n > 0);
                 (void)m;
@@ -634,7 +674,7 @@ __global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassArgs<T> a
             }
         }
         if constexpr (DEPQ)
-            deposit4<T>(keyQ >= 0, keyQ, aQ[0], aQ[1], aQ[2], aQ[3], winQ, base, a.accQ, g.nr1, a.sc.qscale, nout);
+            deposit4<T>(iQ >= 0, iQ, jQ, aQ[0], aQ[1], aQ[2], aQ[3], winQ, w, a.accQ, g.nr1, qscale, nout);
         if constexpr (PUSH) {
             st4(a.p.cell + q0, cell);
             st4(a.p.dr + q0, dr);
@@ -663,14 +703,21 @@ __global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassArgs<T> a
                 atomicOr(a.err, (int)ERR_QUEUE_OVERFLOW);
         }
     }
-    for (int k = tid; k < WIN; k += BLOCK) {
-        if (PUSH) {
-            const T v = winJ[k];
-            if (v != (T)0) atomic_add_i64(&a.accJ[base + k], to_fixed((double)v, a.sc.jscale));
-        }
-        if (DEPQ) {
-            const T v = winQ[k];
-            if (v != (T)0) atomic_add_i64(&a.accQ[base + k], to_fixed((double)v, a.sc.qscale));
+    // flush: row mode walks the rows (the padding is skipped), linear mode
+    // the slots
+    const int nrow = w.rows ? w.rows : 1, ncol = w.rows ? g.nr1 : WIN;
+    for (int r = 0; r < nrow; ++r) {
+        for (int c = tid; c < ncol; c += BLOCK) {
+            const int k = r * w.ws + c;   // ws is unused (0 rows) in linear mode
+            const int node = w.rows ? (w.ib + r) * g.nr1 + c : w.base + c;
+            if (PUSH) {
+                const long long v = winJ[w.rows ? k : c];
+                if (v) atomic_add_i64(&a.accJ[node], v);
+            }
+            if (DEPQ) {
+                const long long v = winQ[w.rows ? k : c];
+                if (v) atomic_add_i64(&a.accQ[node], v);
+            }
         }
     }
     if (tid < ST_NSTAT && sstat[tid]) atomicAdd(&a.stats[tid], sstat[tid]);
