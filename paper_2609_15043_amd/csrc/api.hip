@@ -126,6 +126,7 @@ struct pic_ctx {
     MGState *mgs = nullptr;
     double *mgpartial = nullptr;
     double *pr = nullptr, *pz = nullptr, *pp = nullptr, *pAp = nullptr;   // CG vectors
+    double *pp2 = nullptr;   // second search-direction buffer (alternates with pp)
     double *phi_prev = nullptr;   // phi of the previous solve (initial-guess extrapolation)
     bool have_prev = false;
     int64_t last_solve = -2;
@@ -510,6 +511,7 @@ static void layout(pic_ctx &c, Carver &cv)
     c.pz = cv.take<double>(nodes);
     c.pp = cv.take<double>(nodes);
     c.pAp = cv.take<double>(nodes);
+    c.pp2 = cv.take<double>(nodes);
     int nr = f.nr, nz = f.nz;
     for (int l = 0; l < nl; ++l) {
         MGLevel &L = c.lv.L[l];
@@ -520,6 +522,7 @@ static void layout(pic_ctx &c, Carver &cv)
         L.nine = l > 0;
         L.phi = l == 0 ? c.pz : cv.take<double>(L.nodes);
         L.rhs = l == 0 ? c.pr : cv.take<double>(L.nodes);
+        L.res = l < nl - 1 ? cv.take<double>(L.nodes) : nullptr;
         if (l == 0) {
             L.cw = cv.take<double>(L.nodes);
             L.ce = cv.take<double>(L.nodes);
@@ -541,7 +544,7 @@ static void layout(pic_ctx &c, Carver &cv)
         c.lv.coarse_inv = cv.take<double>((size_t)Lc.nodes * Lc.nodes);
     }
     c.mgs = cv.take<MGState>(1);
-    c.mgpartial = cv.take<double>(pcg_partial_size(nodes));
+    c.mgpartial = cv.take<double>(pcg_partial_size(c.lv.L[0]));
     // face list upper bound: 4 faces per turn node
     int nturn_nodes = 0;
     if (!c.tag.empty())
@@ -764,46 +767,53 @@ static void finalize_charge(pic_ctx &c)
                       f.q[0] * f.w[0], f.q[1] * f.w[1], c.Q, c.g.nodes, c.stream);
 }
 
-// V-cycle on the correction: two red-black sweeps on the 5-point fine
-// level, one four-colour sweep on the Galerkin levels, exact solve on the
-// bottom level (dense inverse, one multi-block product).
-#ifndef PIC_TILE_SMOOTH
-#define PIC_TILE_SMOOTH 1
+// V-cycle on the correction (level 0: right-hand side = the CG residual r,
+// correction = z): two red-black sweeps on the 5-point fine level, one
+// four-colour sweep on the Galerkin levels, exact solve on the bottom level
+// (dense inverse, one multi-block product).  The pre-smoothers start from
+// zero, the coarse ones with the right-hand side restricted from the finer
+// level's residual; the post-smoothers add the prolonged coarse correction
+// as they load their tiles, the level-0 one leaving the partials of r.z.
+#ifndef PIC_MG_NU0
+#define PIC_MG_NU0 2
+#endif
+#ifndef PIC_MG_NU
+#define PIC_MG_NU 1
 #endif
 static void vcycle(pic_ctx &c, const MGLevels &lv, const MGState *st)
 {
-    for (int l = 0; l < c.lb; ++l) {
-        const int nc = lv.L[l].nine ? 4 : 2;
-        const int nu = l == 0 ? 2 : 1;
-        if (PIC_TILE_SMOOTH)
-            launch_mg_smooth_tile(lv.L[l], nu, false, st, c.stream);
-        else
-            for (int k = 0; k < nu; ++k)
-                for (int col = 0; col < nc; ++col) launch_mg_smooth(lv.L[l], col, st, c.stream);
-        launch_mg_restrict(lv.L[l], lv.L[l + 1], st, c.stream);
+    const int lb = c.lb;
+    for (int l = 0; l < lb; ++l) {
+        const int nu = l == 0 ? PIC_MG_NU0 : PIC_MG_NU;
+        launch_mg_smooth_tile(lv.L[l], l > 0 ? &lv.L[l - 1] : nullptr, nullptr, nu, SM_ZERO | (l > 0 ? SM_RHS : 0),
+                              st, nullptr, c.stream);
+        launch_mg_resid(lv.L[l], st, c.stream);
     }
-    launch_dense_solve(lv.coarse_inv, lv.L[c.lb], st, c.stream);
-    for (int l = c.lb - 1; l >= 0; --l) {
-        launch_mg_prolong(lv.L[l], lv.L[l + 1], st, c.stream);
-        const int nc = lv.L[l].nine ? 4 : 2;
-        const int nu = l == 0 ? 2 : 1;
-        if (PIC_TILE_SMOOTH)
-            launch_mg_smooth_tile(lv.L[l], nu, true, st, c.stream);
-        else
-            for (int k = 0; k < nu; ++k)
-                for (int col = nc - 1; col >= 0; --col) launch_mg_smooth(lv.L[l], col, st, c.stream);
+    if (lb > 0) launch_mg_restrict_res(lv.L[lb - 1], lv.L[lb], st, c.stream);
+    launch_dense_solve(lv.coarse_inv, lv.L[lb], st, c.stream);
+    for (int l = lb - 1; l >= 0; --l) {
+        const int nu = l == 0 ? PIC_MG_NU0 : PIC_MG_NU;
+        launch_mg_smooth_tile(lv.L[l], nullptr, &lv.L[l + 1], nu, SM_REVERSE | SM_PROLONG | (l == 0 ? SM_RZ : 0), st,
+                              c.mgpartial, c.stream);
     }
 }
 
-// one preconditioned-CG iteration (no-ops once st->done)
-static void pcg_iteration(pic_ctx &c, const MGLevels &lv, MGState *st, const PCGVec &v, double rtol)
+// preconditioned-CG iteration k of a solve (no-ops once st->done); the
+// search direction alternates between two buffers (the p update and the
+// product A p are one kernel)
+static void pcg_iteration(pic_ctx &c, const MGLevels &lv, MGState *st, const PCGVec &v, double rtol, int k)
 {
     const MGLevel &L0 = lv.L[0];
     vcycle(c, lv, st);
-    launch_pcg_rz(L0, v, st, c.mgpartial, c.stream);
-    launch_pcg_p(L0, v, st, c.mgpartial, c.stream);
-    launch_pcg_matvec(L0, v, st, c.mgpartial, c.stream);
-    launch_pcg_update(L0, v, st, c.mgpartial, c.stream);
+    int nrz = smooth_blocks(L0);
+    if (c.lb == 0) {
+        launch_pcg_rz(L0, v, st, c.mgpartial, c.stream);
+        nrz = pcg_blocks(L0.nodes);
+    }
+    const double *pold = (k & 1) ? c.pp2 : c.pp;
+    double *pnew = (k & 1) ? c.pp : c.pp2;
+    launch_pcg_pmatvec(L0, v, pold, pnew, st, c.mgpartial, nrz, c.stream);
+    launch_pcg_update(L0, v, pnew, st, c.mgpartial, c.stream);
     launch_pcg_check(st, c.mgpartial, pcg_blocks(L0.nodes), rtol, false, c.stream);
 }
 
@@ -842,7 +852,7 @@ static pic_status solve(pic_ctx &c, int64_t n, double rtol, int max_cycles, pic_
     budget = std::min(budget, MAX_CG);
     launch_pcg_resid(L0, v, c.mgpartial, c.stream);
     launch_pcg_check(c.mgs, c.mgpartial, np, rtol, true, c.stream);
-    for (int k = 0; k < budget; ++k) pcg_iteration(c, c.lv, c.mgs, v, rtol);
+    for (int k = 0; k < budget; ++k) pcg_iteration(c, c.lv, c.mgs, v, rtol, k);
     if (c.cfg.nturns > 0)
         launch_face_charge(c.phi, c.fp, c.fq, c.fk, c.fc, c.nfaces, c.Qk, c.cfg.nturns, c.stream);
     timer_stop(c, c.t_poisson);
@@ -944,7 +954,7 @@ static pic_status helm_solve(pic_ctx &c, double *x, int *cycles, double *rel)
         HIPCHK(&c, cpy(c.stream, &s, c.hgs, sizeof s, hipMemcpyDeviceToHost));
         if (s.done || run >= maxc) break;
         const int chunk = std::min(run == 0 ? 4 : 8, maxc - run);
-        for (int k = 0; k < chunk; ++k) pcg_iteration(c, c.hlv, c.hgs, v, rtol);
+        for (int k = 0; k < chunk; ++k) pcg_iteration(c, c.hlv, c.hgs, v, rtol, run + k);
         run += chunk;
     }
     if (cycles) *cycles = s.cycles;

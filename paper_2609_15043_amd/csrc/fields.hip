@@ -170,87 +170,61 @@ __device__ __forceinline__ double apply_op(const MGLevel &L, const double *x, in
     return a;
 }
 
-__device__ __forceinline__ double resid(const MGLevel &L, int n, int i, int j)
+// Full-weighting restriction of the finer level's residual to coarse node
+// (I, J): weights 1, 1/2, 1/4 on the 3 x 3 fine nodes around (2I, 2J), the
+// transpose of the bilinear prolongation below.
+__device__ __forceinline__ double restrict_res(const MGLevel &F, int I, int J)
 {
-    if (L.dir[n]) return 0.0;
-    return L.rhs[n] - apply_op(L, L.phi, n, i, j);
-}
-
-__device__ __forceinline__ int colour_of(const MGLevel &L, int i, int j)
-{
-    return L.nine ? ((i & 1) << 1) | (j & 1) : ((i + j) & 1);
-}
-
-__device__ __forceinline__ void op_smooth(const MGLevel &L, int color, int t0, int st)
-{
-    for (int n = t0; n < L.nodes; n += st) {
-        const int i = n / L.nr1, j = n - i * L.nr1;
-        if (colour_of(L, i, j) != color || L.dir[n]) continue;
-        double diag;
-        if (!L.nine) {
-            diag = L.cc[n];
-        } else {
-            diag = L.a[(size_t)4 * L.nodes + n];
+    double s = 0.0;
+#pragma unroll
+    for (int di = -1; di <= 1; ++di) {
+        const int i = 2 * I + di;
+        if (i < 0 || i > F.nz) continue;
+        const double wi = di == 0 ? 1.0 : 0.5;
+#pragma unroll
+        for (int dj = -1; dj <= 1; ++dj) {
+            const int j = 2 * J + dj;
+            if (j < 0 || j > F.nr) continue;
+            const double wj = dj == 0 ? 1.0 : 0.5;
+            s += wi * wj * F.res[i * F.nr1 + j];
         }
-        // x_n <- x_n + (rhs - A x)_n / diag
-        L.phi[n] += (L.rhs[n] - apply_op(L, L.phi, n, i, j)) / diag;
     }
+    return s;
 }
 
-__device__ __forceinline__ void op_restrict(const MGLevel &F, const MGLevel &C, int t0, int st)
+// Bilinear prolongation of the coarse correction to fine node (i, j)
+__device__ __forceinline__ double prolong_at(const MGLevel &C, int i, int j)
 {
-    for (int n = t0; n < C.nodes; n += st) {
-        const int I = n / C.nr1, J = n - I * C.nr1;
-        C.phi[n] = 0.0;
-        if (C.dir[n]) {
-            C.rhs[n] = 0.0;
-            continue;
-        }
-        double s = 0.0;
-        for (int di = -1; di <= 1; ++di) {
-            const int i = 2 * I + di;
-            if (i < 0 || i > F.nz) continue;
-            const double wi = di == 0 ? 1.0 : 0.5;
-            for (int dj = -1; dj <= 1; ++dj) {
-                const int j = 2 * J + dj;
-                if (j < 0 || j > F.nr) continue;
-                const double wj = dj == 0 ? 1.0 : 0.5;
-                s += wi * wj * resid(F, i * F.nr1 + j, i, j);
-            }
-        }
-        C.rhs[n] = s;
-    }
+    const int I = i >> 1, J = j >> 1;
+    const int c = I * C.nr1 + J;
+    if (!(i & 1) && !(j & 1)) return C.phi[c];
+    if (!(i & 1)) return 0.5 * (C.phi[c] + C.phi[c + 1]);
+    if (!(j & 1)) return 0.5 * (C.phi[c] + C.phi[c + C.nr1]);
+    return 0.25 * (C.phi[c] + C.phi[c + 1] + C.phi[c + C.nr1] + C.phi[c + C.nr1 + 1]);
 }
 
-__device__ __forceinline__ void op_prolong(const MGLevel &F, const MGLevel &C, int t0, int st)
-{
-    for (int n = t0; n < F.nodes; n += st) {
-        if (F.dir[n]) continue;
-        const int i = n / F.nr1, j = n - i * F.nr1;
-        const int I = i >> 1, J = j >> 1;
-        const int c = I * C.nr1 + J;
-        double v;
-        if (!(i & 1) && !(j & 1))
-            v = C.phi[c];
-        else if (!(i & 1))
-            v = 0.5 * (C.phi[c] + C.phi[c + 1]);
-        else if (!(j & 1))
-            v = 0.5 * (C.phi[c] + C.phi[c + C.nr1]);
-        else
-            v = 0.25 * (C.phi[c] + C.phi[c + 1] + C.phi[c + C.nr1] + C.phi[c + C.nr1 + 1]);
-        F.phi[n] += v;
-    }
-}
+// block partial sums of the CG kernels (defined with them below)
+__device__ __forceinline__ void block_partial(double v, double *out, bool is_max);
 
 // Tile smoother: each workgroup stages a TZ x TR tile of the correction plus
 // a one-node halo in LDS and runs `sweeps` Gauss-Seidel sweeps (red-black on
 // the 5-point level, four colours on the Galerkin levels; colours in reverse
-// order when `reverse`) on its tile, the halo held at its values from the
+// order when SM_REVERSE) on its tile, the halo held at its values from the
 // start of the kernel: Gauss-Seidel inside a tile, Jacobi across tiles.
 // Reversing the colour order for the post-smoother keeps the V-cycle a
-// symmetric preconditioner.
+// symmetric preconditioner.  The modes fold the V-cycle's transfers into
+// the smoothers:
+//   SM_ZERO     the correction starts from zero (pre-smoother; Dirichlet
+//               nodes are written 0);
+//   SM_RHS      the right-hand side is the full-weighting restriction of
+//               the finer level's residual, stored in L.rhs;
+//   SM_PROLONG  the coarser level's correction is prolonged and added to
+//               the tile (and halo) as it is loaded (post-smoother);
+//   SM_RZ       per-block partial of rhs . x over the tile (the CG r.z of
+//               the level-0 post-smoother) to partial[2 * block].
 constexpr int TILE_Z = 16, TILE_R = 64, TILE_PER = TILE_Z * TILE_R / 256;
-__global__ __launch_bounds__(256) void k_mg_smooth_tile(MGLevel L, int sweeps, int reverse, const MGState *st)
+__global__ __launch_bounds__(256) void k_mg_smooth_tile(MGLevel L, MGLevel F, MGLevel C, int sweeps, int mode,
+                                                        const MGState *st, double *partial)
 {
     __shared__ double xs[(TILE_Z + 2) * (TILE_R + 2)];
     if (st->done) return;
@@ -259,7 +233,13 @@ __global__ __launch_bounds__(256) void k_mg_smooth_tile(MGLevel L, int sweeps, i
     const int i0 = (blockIdx.x / tiles_r) * TILE_Z, j0 = (blockIdx.x % tiles_r) * TILE_R;
     for (int e = threadIdx.x; e < (TILE_Z + 2) * W; e += 256) {
         const int i = i0 - 1 + e / W, j = j0 - 1 + e % W;
-        xs[e] = (i >= 0 && i <= L.nz && j >= 0 && j <= L.nr) ? L.phi[i * L.nr1 + j] : 0.0;
+        double v = 0.0;
+        if (i >= 0 && i <= L.nz && j >= 0 && j <= L.nr) {
+            const int n = i * L.nr1 + j;
+            if (!(mode & SM_ZERO)) v = L.phi[n];
+            if ((mode & SM_PROLONG) && !L.dir[n]) v += prolong_at(C, i, j);
+        }
+        xs[e] = v;
     }
     // owned nodes: coefficients and right-hand side in registers
     const int nc = L.nine ? 4 : 2;
@@ -276,10 +256,19 @@ __global__ __launch_bounds__(256) void k_mg_smooth_tile(MGLevel L, int sweeps, i
         for (int k = 0; k < 9; ++k) coef[q][k] = 0.0;
         if (i > L.nz || j > L.nr) continue;
         const int n = i * L.nr1 + j;
-        if (L.dir[n]) continue;
+        if (L.dir[n]) {
+            if (mode & SM_ZERO) L.phi[n] = 0.0;
+            if (mode & SM_RHS) L.rhs[n] = 0.0;
+            continue;
+        }
         own[q] = n;
         col[q] = L.nine ? ((i & 1) << 1) | (j & 1) : ((i + j) & 1);
-        rhs[q] = L.rhs[n];
+        if (mode & SM_RHS) {
+            rhs[q] = restrict_res(F, i, j);
+            L.rhs[n] = rhs[q];
+        } else {
+            rhs[q] = L.rhs[n];
+        }
         if (L.nine) {
 #pragma unroll
             for (int k = 0; k < 9; ++k) {
@@ -298,7 +287,7 @@ __global__ __launch_bounds__(256) void k_mg_smooth_tile(MGLevel L, int sweeps, i
     __syncthreads();
     for (int sw = 0; sw < sweeps; ++sw)
         for (int cc = 0; cc < nc; ++cc) {
-            const int c = reverse ? nc - 1 - cc : cc;
+            const int c = (mode & SM_REVERSE) ? nc - 1 - cc : cc;
 #pragma unroll
             for (int q = 0; q < TILE_PER; ++q) {
                 if (col[q] != c) continue;
@@ -311,30 +300,41 @@ __global__ __launch_bounds__(256) void k_mg_smooth_tile(MGLevel L, int sweeps, i
             }
             __syncthreads();
         }
+    double rz = 0.0;
 #pragma unroll
     for (int q = 0; q < TILE_PER; ++q) {
         if (own[q] < 0) continue;
         const int e = threadIdx.x + 256 * q;
-        L.phi[own[q]] = xs[(e / TILE_R + 1) * W + e % TILE_R + 1];
+        const double x = xs[(e / TILE_R + 1) * W + e % TILE_R + 1];
+        L.phi[own[q]] = x;
+        rz += rhs[q] * x;
+    }
+    if (mode & SM_RZ) block_partial(rz, partial + 2 * blockIdx.x, false);
+}
+
+// residual of a level after its pre-smoother: res = rhs - A phi on free
+// nodes, 0 on Dirichlet nodes
+__global__ __launch_bounds__(256) void k_mg_resid(MGLevel L, const MGState *st)
+{
+    if (st->done) return;
+    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < L.nodes; n += gridDim.x * blockDim.x) {
+        if (L.dir[n]) {
+            L.res[n] = 0.0;
+            continue;
+        }
+        const int i = n / L.nr1, j = n - i * L.nr1;
+        L.res[n] = L.rhs[n] - apply_op(L, L.phi, n, i, j);
     }
 }
 
-__global__ void k_mg_smooth(MGLevel L, int color, const MGState *st)
+// right-hand side of the bottom level: restriction of the finer residual
+__global__ __launch_bounds__(256) void k_mg_restrict_res(MGLevel F, MGLevel C, const MGState *st)
 {
     if (st->done) return;
-    op_smooth(L, color, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
-}
-
-__global__ void k_mg_restrict(MGLevel F, MGLevel C, const MGState *st)
-{
-    if (st->done) return;
-    op_restrict(F, C, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
-}
-
-__global__ void k_mg_prolong(MGLevel F, MGLevel C, const MGState *st)
-{
-    if (st->done) return;
-    op_prolong(F, C, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < C.nodes; n += gridDim.x * blockDim.x) {
+        const int I = n / C.nr1, J = n - I * C.nr1;
+        C.rhs[n] = C.dir[n] ? 0.0 : restrict_res(F, I, J);
+    }
 }
 
 // Exact solve on the bottom level: phi = Inv rhs, one wave per row.
@@ -487,7 +487,7 @@ __global__ __launch_bounds__(256) void k_pcg_check(MGState *st, const double *pa
     if (R == 0.0 || st->rel <= rtol) st->done = 1;
 }
 
-// partials of r.z
+// partials of r.z when the V-cycle is the dense solve alone (no smoother)
 __global__ __launch_bounds__(256) void k_pcg_rz(MGLevel L, PCGVec v, const MGState *st, double *partial)
 {
     if (st->done) return;
@@ -496,47 +496,51 @@ __global__ __launch_bounds__(256) void k_pcg_rz(MGLevel L, PCGVec v, const MGSta
     block_partial(s, partial + 2 * blockIdx.x, false);
 }
 
-// rz_k = sum of partials; p = z + (rz_k / rz_{k-1}) p (beta = 0 first)
-__global__ __launch_bounds__(256) void k_pcg_p(MGLevel L, PCGVec v, MGState *st, const double *partial, int np)
+// rz_k = sum of the r.z partials (from the level-0 post-smoother, even
+// slots); p' = z + (rz_k / rz_{k-1}) p (beta = 0 first) into the other p
+// buffer; Ap' = A p' on free nodes, with p' at the neighbours formed on
+// the fly from z and p; partials of p'.Ap' to the odd slots.
+__global__ __launch_bounds__(256) void k_pcg_pmatvec(MGLevel L, PCGVec v, const double *pold, double *pnew,
+                                                     MGState *st, double *partial, int nrz)
 {
     if (st->done) return;
     const int it = st->cycles;
-    const double rz = fold_partials(partial, np, 2, false);
+    const double rz = fold_partials(partial, nrz, 2, false);
     const double beta = it == 0 || st->rz[it] == 0.0 ? 0.0 : rz / st->rz[it];
     if (blockIdx.x == 0 && threadIdx.x == 0) st->rz[it + 1] = rz;
-    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < L.nodes; n += gridDim.x * blockDim.x)
-        v.p[n] = v.z[n] + beta * v.p[n];
-}
-
-// Ap = A p on free nodes; partials of p.Ap
-__global__ __launch_bounds__(256) void k_pcg_matvec(MGLevel L, PCGVec v, const MGState *st, double *partial)
-{
-    if (st->done) return;
     double s = 0.0;
+    const double *z = v.z;
     for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < L.nodes; n += gridDim.x * blockDim.x) {
+        const double pn = z[n] + beta * pold[n];
+        pnew[n] = pn;
         double ap = 0.0;
         if (!L.dir[n]) {
             const int i = n / L.nr1, j = n - i * L.nr1;
-            ap = apply_op(L, v.p, n, i, j);
+            ap = L.cc[n] * pn;
+            if (j > 0) ap -= L.cw[n] * (z[n - 1] + beta * pold[n - 1]);
+            if (j < L.nr) ap -= L.ce[n] * (z[n + 1] + beta * pold[n + 1]);
+            if (i > 0) ap -= L.cs[n] * (z[n - L.nr1] + beta * pold[n - L.nr1]);
+            if (i < L.nz) ap -= L.cn[n] * (z[n + L.nr1] + beta * pold[n + L.nr1]);
         }
         v.Ap[n] = ap;
-        s += v.p[n] * ap;
+        s += pn * ap;
     }
-    block_partial(s, partial + 2 * blockIdx.x, false);
+    block_partial(s, partial + 2 * blockIdx.x + 1, false);
 }
 
-// alpha = rz / p.Ap; x += alpha p, r -= alpha Ap, z = 0; partials of max|r|
-__global__ __launch_bounds__(256) void k_pcg_update(MGLevel L, PCGVec v, const MGState *st, double *partial, int np)
+// alpha = rz / p.Ap (odd-slot partials); x += alpha p, r -= alpha Ap;
+// partials of max|r| to the even slots
+__global__ __launch_bounds__(256) void k_pcg_update(MGLevel L, PCGVec v, const double *p, const MGState *st,
+                                                    double *partial, int np)
 {
     if (st->done) return;
-    const double pap = fold_partials(partial, np, 2, false);
+    const double pap = fold_partials(partial + 1, np, 2, false);
     const double alpha = pap != 0.0 ? st->rz[st->cycles + 1] / pap : 0.0;
     __syncthreads();
     double m = 0.0;
     for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < L.nodes; n += gridDim.x * blockDim.x) {
-        v.z[n] = 0.0;
         if (L.dir[n]) continue;
-        v.x[n] += alpha * v.p[n];
+        v.x[n] += alpha * p[n];
         const double r = v.r[n] - alpha * v.Ap[n];
         v.r[n] = r;
         m = fmax(m, fabs(r));
@@ -605,24 +609,31 @@ int harmonic_blocks(int nodes) { return (int)nblk(nodes, 256); }
 
 static unsigned mg_grid(int work) { return nblk(work, 256) < 2048 ? nblk(work, 256) : 2048; }
 static unsigned red_grid(int work) { return nblk(work, 256) < 1024 ? nblk(work, 256) : 1024; }
-int pcg_partial_size(int nodes) { return 2 * (int)red_grid(nodes); }
 
-void launch_mg_smooth(const MGLevel &L, int color, const MGState *st, hipStream_t s)
+static int smooth_tiles(const MGLevel &L)
 {
-    hipLaunchKernelGGL(k_mg_smooth, dim3(mg_grid(L.nodes)), dim3(256), 0, s, L, color, st);
+    return ((L.nz + 1 + TILE_Z - 1) / TILE_Z) * ((L.nr1 + TILE_R - 1) / TILE_R);
 }
-void launch_mg_smooth_tile(const MGLevel &L, int sweeps, bool reverse, const MGState *st, hipStream_t s)
+int smooth_blocks(const MGLevel &L) { return smooth_tiles(L); }
+int pcg_partial_size(const MGLevel &L0)
 {
-    const int tiles = ((L.nz + 1 + TILE_Z - 1) / TILE_Z) * ((L.nr1 + TILE_R - 1) / TILE_R);
-    hipLaunchKernelGGL(k_mg_smooth_tile, dim3(tiles), dim3(256), 0, s, L, sweeps, reverse ? 1 : 0, st);
+    const int t = smooth_tiles(L0), r = (int)red_grid(L0.nodes);
+    return 2 * (t > r ? t : r);
 }
-void launch_mg_restrict(const MGLevel &F, const MGLevel &C, const MGState *st, hipStream_t s)
+void launch_mg_smooth_tile(const MGLevel &L, const MGLevel *F, const MGLevel *C, int sweeps, int mode,
+                           const MGState *st, double *partial, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_mg_restrict, dim3(mg_grid(C.nodes)), dim3(256), 0, s, F, C, st);
+    const MGLevel none{};
+    hipLaunchKernelGGL(k_mg_smooth_tile, dim3(smooth_tiles(L)), dim3(256), 0, s, L, F ? *F : none, C ? *C : none,
+                       sweeps, mode, st, partial);
 }
-void launch_mg_prolong(const MGLevel &F, const MGLevel &C, const MGState *st, hipStream_t s)
+void launch_mg_resid(const MGLevel &L, const MGState *st, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_mg_prolong, dim3(mg_grid(F.nodes)), dim3(256), 0, s, F, C, st);
+    hipLaunchKernelGGL(k_mg_resid, dim3(mg_grid(L.nodes)), dim3(256), 0, s, L, st);
+}
+void launch_mg_restrict_res(const MGLevel &F, const MGLevel &C, const MGState *st, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_mg_restrict_res, dim3(mg_grid(C.nodes)), dim3(256), 0, s, F, C, st);
 }
 void launch_dense_solve(const double *inv, const MGLevel &L, const MGState *st, hipStream_t s)
 {
@@ -654,17 +665,15 @@ void launch_pcg_rz(const MGLevel &L, const PCGVec &v, const MGState *st, double 
 {
     hipLaunchKernelGGL(k_pcg_rz, dim3(red_grid(L.nodes)), dim3(256), 0, s, L, v, st, partial);
 }
-void launch_pcg_p(const MGLevel &L, const PCGVec &v, MGState *st, const double *partial, hipStream_t s)
+void launch_pcg_pmatvec(const MGLevel &L, const PCGVec &v, const double *pold, double *pnew, MGState *st,
+                        double *partial, int nrz, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_pcg_p, dim3(red_grid(L.nodes)), dim3(256), 0, s, L, v, st, partial, (int)red_grid(L.nodes));
+    hipLaunchKernelGGL(k_pcg_pmatvec, dim3(red_grid(L.nodes)), dim3(256), 0, s, L, v, pold, pnew, st, partial, nrz);
 }
-void launch_pcg_matvec(const MGLevel &L, const PCGVec &v, const MGState *st, double *partial, hipStream_t s)
+void launch_pcg_update(const MGLevel &L, const PCGVec &v, const double *p, const MGState *st, double *partial,
+                       hipStream_t s)
 {
-    hipLaunchKernelGGL(k_pcg_matvec, dim3(red_grid(L.nodes)), dim3(256), 0, s, L, v, st, partial);
-}
-void launch_pcg_update(const MGLevel &L, const PCGVec &v, const MGState *st, double *partial, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_pcg_update, dim3(red_grid(L.nodes)), dim3(256), 0, s, L, v, st, partial,
+    hipLaunchKernelGGL(k_pcg_update, dim3(red_grid(L.nodes)), dim3(256), 0, s, L, v, p, st, partial,
                        (int)red_grid(L.nodes));
 }
 void launch_face_charge(const double *phi, const int32_t *fp, const int32_t *fq, const int32_t *fk, const double *fc,

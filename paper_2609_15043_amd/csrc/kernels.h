@@ -129,6 +129,7 @@ struct MGLevel {
     int nr, nz, nr1, nodes;
     int nine;
     double *phi, *rhs;       // correction and its right-hand side
+    double *res;             // residual after the pre-smoother (levels above the bottom)
     const double *cw, *ce, *cs, *cn, *cc;
     const double *a;         // 9 * nodes (nine == 1)
     const uint8_t *dir;      // 1: Dirichlet (correction fixed at 0)

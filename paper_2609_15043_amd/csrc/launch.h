@@ -47,11 +47,14 @@ int harmonic_blocks(int nodes);
 struct PCGVec {
     double *x, *b, *r, *z, *p, *Ap;
 };
-int pcg_partial_size(int nodes);
-void launch_mg_smooth(const MGLevel &L, int color, const MGState *st, hipStream_t s);
-void launch_mg_smooth_tile(const MGLevel &L, int sweeps, bool reverse, const MGState *st, hipStream_t s);
-void launch_mg_restrict(const MGLevel &F, const MGLevel &C, const MGState *st, hipStream_t s);
-void launch_mg_prolong(const MGLevel &F, const MGLevel &C, const MGState *st, hipStream_t s);
+int pcg_partial_size(const MGLevel &L0);
+// tile smoother modes (combinable)
+constexpr int SM_REVERSE = 1, SM_ZERO = 2, SM_RHS = 4, SM_PROLONG = 8, SM_RZ = 16;
+int smooth_blocks(const MGLevel &L);
+void launch_mg_smooth_tile(const MGLevel &L, const MGLevel *F, const MGLevel *C, int sweeps, int mode,
+                           const MGState *st, double *partial, hipStream_t s);
+void launch_mg_resid(const MGLevel &L, const MGState *st, hipStream_t s);
+void launch_mg_restrict_res(const MGLevel &F, const MGLevel &C, const MGState *st, hipStream_t s);
 void launch_dense_solve(const double *inv, const MGLevel &L, const MGState *st, hipStream_t s);
 void launch_gauss_jordan(double *A, int n, double *rowk, double *colk, hipStream_t s);
 int pcg_blocks(int nodes);
@@ -60,9 +63,10 @@ void launch_pcg_begin(const MGLevel &L, const PCGVec &v, const int32_t *tag, con
 void launch_pcg_resid(const MGLevel &L, const PCGVec &v, double *partial, hipStream_t s);
 void launch_pcg_check(MGState *st, const double *partial, int np, double rtol, bool first, hipStream_t s);
 void launch_pcg_rz(const MGLevel &L, const PCGVec &v, const MGState *st, double *partial, hipStream_t s);
-void launch_pcg_p(const MGLevel &L, const PCGVec &v, MGState *st, const double *partial, hipStream_t s);
-void launch_pcg_matvec(const MGLevel &L, const PCGVec &v, const MGState *st, double *partial, hipStream_t s);
-void launch_pcg_update(const MGLevel &L, const PCGVec &v, const MGState *st, double *partial, hipStream_t s);
+void launch_pcg_pmatvec(const MGLevel &L, const PCGVec &v, const double *pold, double *pnew, MGState *st,
+                        double *partial, int nrz, hipStream_t s);
+void launch_pcg_update(const MGLevel &L, const PCGVec &v, const double *p, const MGState *st, double *partial,
+                       hipStream_t s);
 void launch_helm_rhs(const double *acc, const double *comp, double scale, const uint8_t *dir, double mw, double *b,
                      const GridC &g, hipStream_t s);
 void launch_unit_rhs(const int32_t *tag, int turn, double gval, const uint8_t *dir, double mw, double *b,
