@@ -51,6 +51,7 @@ template <typename T> void carve_parts(Carver &c, Parts<T> &p, int64_t cap)
 template <typename T> void carve_births(Carver &c, Births<T> &b, int cap)
 {
     b.parent = c.take<uint32_t>(cap);
+    b.sorted = c.take<uint32_t>(cap);
     b.cell = c.take<int32_t>(cap);
     b.dr = c.take<T>(cap);
     b.dz = c.take<T>(cap);

@@ -222,10 +222,15 @@ __device__ __forceinline__ void block_partial(double v, double *out, bool is_max
 //               the tile (and halo) as it is loaded (post-smoother);
 //   SM_RZ       per-block partial of rhs . x over the tile (the CG r.z of
 //               the level-0 post-smoother) to partial[2 * block].
-constexpr int TILE_Z = 16, TILE_R = 64, TILE_PER = TILE_Z * TILE_R / 256;
+// Tiles: 16 x 64 nodes (4 per thread) on the 5-point level, 8 x 32 (one
+// per thread, four times the workgroups) on the smaller Galerkin levels.
+constexpr int TILE_Z = 16, TILE_R = 64;       // level 0
+constexpr int TILE_ZC = 8, TILE_RC = 32;      // Galerkin levels
+template <int TILE_Z, int TILE_R>
 __global__ __launch_bounds__(256) void k_mg_smooth_tile(MGLevel L, MGLevel F, MGLevel C, int sweeps, int mode,
                                                         const MGState *st, double *partial)
 {
+    constexpr int TILE_PER = TILE_Z * TILE_R / 256;
     __shared__ double xs[(TILE_Z + 2) * (TILE_R + 2)];
     if (st->done) return;
     constexpr int W = TILE_R + 2;
@@ -612,6 +617,7 @@ static unsigned red_grid(int work) { return nblk(work, 256) < 1024 ? nblk(work, 
 
 static int smooth_tiles(const MGLevel &L)
 {
+    if (L.nine) return ((L.nz + 1 + TILE_ZC - 1) / TILE_ZC) * ((L.nr1 + TILE_RC - 1) / TILE_RC);
     return ((L.nz + 1 + TILE_Z - 1) / TILE_Z) * ((L.nr1 + TILE_R - 1) / TILE_R);
 }
 int smooth_blocks(const MGLevel &L) { return smooth_tiles(L); }
@@ -624,8 +630,12 @@ void launch_mg_smooth_tile(const MGLevel &L, const MGLevel *F, const MGLevel *C,
                            const MGState *st, double *partial, hipStream_t s)
 {
     const MGLevel none{};
-    hipLaunchKernelGGL(k_mg_smooth_tile, dim3(smooth_tiles(L)), dim3(256), 0, s, L, F ? *F : none, C ? *C : none,
-                       sweeps, mode, st, partial);
+    if (L.nine)
+        hipLaunchKernelGGL((k_mg_smooth_tile<TILE_ZC, TILE_RC>), dim3(smooth_tiles(L)), dim3(256), 0, s, L,
+                           F ? *F : none, C ? *C : none, sweeps, mode, st, partial);
+    else
+        hipLaunchKernelGGL((k_mg_smooth_tile<TILE_Z, TILE_R>), dim3(smooth_tiles(L)), dim3(256), 0, s, L,
+                           F ? *F : none, C ? *C : none, sweeps, mode, st, partial);
 }
 void launch_mg_resid(const MGLevel &L, const MGState *st, hipStream_t s)
 {
