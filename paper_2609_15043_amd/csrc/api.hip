@@ -128,8 +128,8 @@ struct pic_ctx {
     double *mgpartial = nullptr;
     double *pr = nullptr, *pz = nullptr, *pp = nullptr, *pAp = nullptr;   // CG vectors
     double *pp2 = nullptr;   // second search-direction buffer (alternates with pp)
-    double *phi_prev = nullptr;   // phi of the previous solve (initial-guess extrapolation)
-    bool have_prev = false;
+    double *phi_prev = nullptr;   // phi of the two previous solves (initial-guess extrapolation)
+    int run = 0;                  // consecutive solves of the running sequence before this one
     int64_t last_solve = -2;
     // adaptive iteration budget: each solve's state lands in pinned host
     // memory asynchronously; the next solve budgets the recent count + 1
@@ -539,7 +539,7 @@ static void layout(pic_ctx &c, Carver &cv)
         nr /= 2;
         nz /= 2;
     }
-    c.phi_prev = cv.take<double>(nodes);
+    c.phi_prev = cv.take<double>(2 * (size_t)nodes);
     {
         const MGLevel &Lc = c.lv.L[nl - 1];
         c.lv.coarse_inv = cv.take<double>((size_t)Lc.nodes * Lc.nodes);
@@ -845,9 +845,11 @@ static pic_status solve(pic_ctx &c, int64_t n, double rtol, int max_cycles, pic_
         budget = std::max(2, std::min(max_cycles, c.mg_budget));
     }
     // extrapolate only across consecutive steps of a running sequence
-    const bool extrap = c.have_prev && n == c.last_solve + 1 && !full && !info;
-    launch_pcg_begin(L0, v, c.d_tag, c.d_vc, c.d_vs, std::cos(th), std::sin(th), c.mgs, c.phi_prev, extrap, c.stream);
-    c.have_prev = true;
+    // extrapolate only across consecutive steps of a running sequence: linear
+    // once two previous solutions are stored, quadratic once three are
+    c.run = (n == c.last_solve + 1 && !full && !info) ? c.run + 1 : 0;
+    const int order = c.run >= 3 ? 2 : c.run >= 2 ? 1 : 0;
+    launch_pcg_begin(L0, v, c.d_tag, c.d_vc, c.d_vs, std::cos(th), std::sin(th), c.mgs, c.phi_prev, order, c.stream);
     c.last_solve = n;
     const int np = pcg_blocks(L0.nodes);
     budget = std::min(budget, MAX_CG);
@@ -946,7 +948,7 @@ static pic_status helm_solve(pic_ctx &c, double *x, int *cycles, double *rel)
     const PCGVec v{x, c.hb, c.pr, c.pz, c.pp, c.pAp};
     const double rtol = c.cfg.helm_rtol;
     const int maxc = std::min(c.cfg.helm_max_cycles, MAX_CG);
-    launch_pcg_begin(L0, v, c.htag, nullptr, nullptr, 0.0, 0.0, c.hgs, nullptr, false, c.stream);
+    launch_pcg_begin(L0, v, c.htag, nullptr, nullptr, 0.0, 0.0, c.hgs, nullptr, 0, c.stream);
     launch_pcg_resid(L0, v, c.mgpartial, c.stream);
     launch_pcg_check(c.hgs, c.mgpartial, pcg_blocks(L0.nodes), rtol, true, c.stream);
     MGState s{};
@@ -1170,7 +1172,7 @@ template <typename T> static pic_status init_impl(pic_ctx &c)
         }
         pic_status bs = build_levels(c, c.lv, co, dir);
         if (bs) return bs;
-        for (double *v : {c.pr, c.pz, c.pp, c.pAp, c.phi_prev})
+        for (double *v : {c.pr, c.pz, c.pp, c.pp2, c.pAp, c.phi_prev, c.phi_prev + nodes})
             HIPCHK(&c, mset(c.stream, v, 0, (size_t)nodes * sizeof(double)));
     }
     {
@@ -1782,7 +1784,7 @@ extern "C" pic_status pic_set_step(pic_ctx *c, int64_t n)
 extern "C" pic_status pic_set_phi(pic_ctx *c, const double *phi)
 {
     if (!c || !phi) return PIC_EINVAL;
-    c->have_prev = false;
+    c->run = 0;
     HIPCHK(c, hipMemcpyAsync(c->phi, phi, c->g.nodes * 8, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return PIC_OK;

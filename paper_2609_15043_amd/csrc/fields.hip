@@ -420,10 +420,12 @@ __device__ __forceinline__ double fold_partials(const double *part, int np, int 
 }
 
 // Dirichlet values (turn k nodes: phi_k(t_n)); free nodes start from the
-// linear extrapolation 2 phi^n - phi^{n-1} when `extrap` (prev, when given,
-// keeps phi^n); state reset.
+// solution extrapolated in time from the stored previous solutions (prev:
+// two arrays, phi^{n-1} then phi^{n-2}): order 1 gives 2 phi^n - phi^{n-1},
+// order 2 gives 3 phi^n - 3 phi^{n-1} + phi^{n-2}; the stored solutions then
+// shift by one; state reset.
 __global__ void k_pcg_begin(MGLevel L, PCGVec v, const int32_t *tag, const double *vc, const double *vs, double cs,
-                            double sn, MGState *st, double *prev, int extrap)
+                            double sn, MGState *st, double *prev, int order)
 {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n == 0) {
@@ -437,8 +439,13 @@ __global__ void k_pcg_begin(MGLevel L, PCGVec v, const int32_t *tag, const doubl
     if (k >= 1) {
         v.x[n] = vc[k - 1] * cs + vs[k - 1] * sn;
     } else if (k < 0 && prev) {
-        const double cur = v.x[n];
-        if (extrap) v.x[n] = 2.0 * cur - prev[n];
+        double *prev2 = prev + L.nodes;
+        const double cur = v.x[n], p1 = prev[n];
+        if (order == 2)
+            v.x[n] = 3.0 * cur - 3.0 * p1 + prev2[n];
+        else if (order == 1)
+            v.x[n] = 2.0 * cur - p1;
+        prev2[n] = p1;
         prev[n] = cur;
     }
 }
@@ -658,10 +665,10 @@ void launch_gauss_jordan(double *A, int n, double *rowk, double *colk, hipStream
 }
 int pcg_blocks(int nodes) { return (int)red_grid(nodes); }
 void launch_pcg_begin(const MGLevel &L, const PCGVec &v, const int32_t *tag, const double *vc, const double *vs,
-                      double cs, double sn, MGState *st, double *prev, bool extrap, hipStream_t s)
+                      double cs, double sn, MGState *st, double *prev, int order, hipStream_t s)
 {
     hipLaunchKernelGGL(k_pcg_begin, dim3(nblk(L.nodes, 256)), dim3(256), 0, s, L, v, tag, vc, vs, cs, sn, st, prev,
-                       extrap ? 1 : 0);
+                       order);
 }
 void launch_pcg_resid(const MGLevel &L, const PCGVec &v, double *partial, hipStream_t s)
 {

@@ -29,7 +29,10 @@ constexpr int DEPOSIT_GROUPS = PIC_DEPOSIT_GROUPS;   // wave reductions per run 
 #endif
 constexpr int DEPOSIT_MIN_LANES = PIC_DEPOSIT_MIN_LANES;   // smallest group worth a wave reduction
 constexpr int RUN = 4;                  // consecutive particles per lane per vector load
-constexpr int RUNS = 4;                 // runs per wave per block
+#ifndef PIC_PASS_RUNS
+#define PIC_PASS_RUNS 4
+#endif
+constexpr int RUNS = PIC_PASS_RUNS;     // runs per wave per block
 constexpr int CHUNK = BLOCK * RUN * RUNS;   // particles per pass block (4096)
 constexpr int PAD = CHUNK;              // particle capacities are padded to this multiple
 

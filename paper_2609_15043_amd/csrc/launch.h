@@ -59,7 +59,7 @@ void launch_dense_solve(const double *inv, const MGLevel &L, const MGState *st, 
 void launch_gauss_jordan(double *A, int n, double *rowk, double *colk, hipStream_t s);
 int pcg_blocks(int nodes);
 void launch_pcg_begin(const MGLevel &L, const PCGVec &v, const int32_t *tag, const double *vc, const double *vs,
-                      double cs, double sn, MGState *st, double *prev, bool extrap, hipStream_t s);
+                      double cs, double sn, MGState *st, double *prev, int order, hipStream_t s);
 void launch_pcg_resid(const MGLevel &L, const PCGVec &v, double *partial, hipStream_t s);
 void launch_pcg_check(MGState *st, const double *partial, int np, double rtol, bool first, hipStream_t s);
 void launch_pcg_rz(const MGLevel &L, const PCGVec &v, const MGState *st, double *partial, hipStream_t s);
