@@ -138,6 +138,8 @@ typedef struct pic_config {
     double alpha;            /* state relaxation, 0 < alpha <= 1 (Eq. relaxation) */
     double helm_rtol;        /* inductive solves: residual tolerance relative to the equation's scale */
     int32_t helm_max_cycles; /* ... and their iteration limit */
+    int32_t sort_every_ion;  /* steps between cell sorts of the ion arrays (ions move a small fraction of a
+                                cell per step); 0: sort_every */
 } pic_config;
 
 typedef struct pic_solve_info {
@@ -204,7 +206,8 @@ pic_status pic_init(const pic_config *cfg, void *workspace, size_t workspace_byt
  * that leave the box (window crossings leave their charge on row ip).
  * With cfg->fuse the same pass also runs the collisions and the charge
  * deposit of the new positions.  Requires n == last step + 1 (first n = 0);
- * sorts the arrays by cell first when n % sort_every == 0. */
+ * sorts the electron arrays by cell first when n % sort_every == 0, the ion
+ * arrays when n % sort_every_ion == 0 (sort_every when 0). */
 pic_status pic_gather_push(pic_ctx *ctx, int64_t n);
 
 /* Null-collision MCC of step n on v^{n+1/2} at x^{n+1}: particles whose

@@ -622,6 +622,7 @@ static pic_status check_config(const pic_config *f, pic_ctx *c)
     }
     if (!f->eps_cell || !f->node_tag) return fail(c, PIC_EINVAL, "eps_cell and node_tag are required");
     if (f->sort_every < 1) return fail(c, PIC_EINVAL, "sort_every must be >= 1");
+    if (f->sort_every_ion < 0) return fail(c, PIC_EINVAL, "sort_every_ion must be >= 0");
     if (f->birth_capacity < 0) return fail(c, PIC_EINVAL, "birth_capacity < 0");
     return PIC_OK;
 }
@@ -1296,18 +1297,16 @@ extern "C" pic_status pic_gather_push(pic_ctx *c, int64_t n)
                                            (long long)c->last_push);
     if (n > 2147483000ll) return fail(c, PIC_EINVAL, "step index too large");
     const bool fuse = c->cfg.fuse != 0;
+    const int every_ion = c->cfg.sort_every_ion > 0 ? c->cfg.sort_every_ion : c->cfg.sort_every;
+    const bool sort_e = n > 0 && n % c->cfg.sort_every == 0, sort_i = n > 0 && n % every_ion == 0;
     if (c->mixed) {
-        if (n % c->cfg.sort_every == 0 && n > 0) {
-            sort_species<float>(*c, 0);
-            sort_species<float>(*c, 1);
-        }
+        if (sort_e) sort_species<float>(*c, 0);
+        if (sort_i) sort_species<float>(*c, 1);
         stage<float>(*c, n);
         run_pass<float>(*c, n, true, fuse);
     } else {
-        if (n % c->cfg.sort_every == 0 && n > 0) {
-            sort_species<double>(*c, 0);
-            sort_species<double>(*c, 1);
-        }
+        if (sort_e) sort_species<double>(*c, 0);
+        if (sort_i) sort_species<double>(*c, 1);
         stage<double>(*c, n);
         run_pass<double>(*c, n, true, fuse);
     }

@@ -923,6 +923,14 @@ __global__ void k_births_commit(int32_t *bcount, int32_t cap, int64_t *count, in
 // ---------------------------------------------------------------------------
 constexpr int SORT_PER = 1024;
 constexpr int SORT_WIN = 4096;
+#ifndef PIC_SORT_GROUPS
+#define PIC_SORT_GROUPS 4
+#endif
+#ifndef PIC_SORT_MIN_LANES
+#define PIC_SORT_MIN_LANES 8
+#endif
+constexpr int SORT_GROUPS = PIC_SORT_GROUPS;        // wave-aggregated cells per wave before own adds
+constexpr int SORT_MIN_LANES = PIC_SORT_MIN_LANES;  // smallest group worth a wave aggregation
 constexpr int SCAN_BLOCK = 1024;
 
 __device__ __forceinline__ int sort_window_lo(const int32_t *cell, int64_t p0, int64_t n, int ncells)
@@ -951,10 +959,11 @@ __global__ __launch_bounds__(256) void k_sort_hist(const int32_t *cell, const in
         const int32_t c = p < n ? cell[p] : -1;
         const bool live = c >= 0 && c < ncells;
         uint64_t todo = ballot(live);
-        while (todo) {
+        for (int it = 0; todo && it < SORT_GROUPS; ++it) {
             const int lead = __ffsll((unsigned long long)todo) - 1;
             const int k = __builtin_amdgcn_readlane(c, lead);
             const uint64_t mm = ballot(live && c == k);
+            if (__popcll(mm) < SORT_MIN_LANES) break;
             if (lane_id() == lead) {
                 const int b = k - lo;
                 if (b >= 0 && b < SORT_WIN)
@@ -963,6 +972,14 @@ __global__ __launch_bounds__(256) void k_sort_hist(const int32_t *cell, const in
                     atomicAdd(&hist[k], (int)__popcll(mm));
             }
             todo &= ~mm;
+        }
+        if (todo >> lane_id() & 1ull) {
+            // small groups (particles spread over many cells): own adds
+            const int b = c - lo;
+            if (b >= 0 && b < SORT_WIN)
+                atomicAdd(&bins[b], 1);
+            else
+                atomicAdd(&hist[c], 1);
         }
     }
     __syncthreads();
@@ -1053,10 +1070,11 @@ __global__ __launch_bounds__(256) void k_sort_scatter(Parts<T> src, Parts<T> dst
         pos[q] = -1;
         inwin[q] = live && c[q] - lo >= 0 && c[q] - lo < SORT_WIN;
         uint64_t todo = ballot(live);
-        while (todo) {
+        for (int it = 0; todo && it < SORT_GROUPS; ++it) {
             const int lead = __ffsll((unsigned long long)todo) - 1;
             const int k = __builtin_amdgcn_readlane(c[q], lead);
             const uint64_t mm = ballot(live && c[q] == k);
+            if (__popcll(mm) < SORT_MIN_LANES) break;
             int b0 = 0;
             if (lane_id() == lead) {
                 const int b = k - lo;
@@ -1069,6 +1087,12 @@ __global__ __launch_bounds__(256) void k_sort_scatter(Parts<T> src, Parts<T> dst
             if (live && c[q] == k)
                 pos[q] = b0 + __builtin_amdgcn_mbcnt_hi((uint32_t)(mm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mm, 0u));
             todo &= ~mm;
+        }
+        if (todo >> lane_id() & 1ull) {
+            // small groups: own reservation (offset in the window cell's
+            // block-local count, or a global position outside the window)
+            const int b = c[q] - lo;
+            pos[q] = (b >= 0 && b < SORT_WIN) ? atomicAdd(&bins[b], 1) : atomicAdd(&cursor[c[q]], 1);
         }
     }
     __syncthreads();

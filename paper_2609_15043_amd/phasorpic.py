@@ -49,6 +49,7 @@ class PicConfig(ctypes.Structure):
         ("vg_amp", _D), ("vg_phase", _D), ("vg_from_target", _I32), ("controller", _I32),
         ("p_target", _D), ("gamma", _D), ("n_trend", _D), ("eps_p", _D), ("alpha_v", _D), ("f_step", _D),
         ("v_min", _D), ("v_max", _D), ("alpha", _D), ("helm_rtol", _D), ("helm_max_cycles", _I32),
+        ("sort_every_ion", _I32),
     ]
 
 
@@ -153,7 +154,7 @@ def _ptr(a, t):
 # Configuration from a workload description
 # ---------------------------------------------------------------------------
 def config_from_workload(wl, precision="mixed", fuse=True, load=True, mg_rtol=None, mg_max_cycles=30,
-                         sort_every=16, birth_capacity=65536, nscan=200_000, helm_rtol=1e-12,
+                         sort_every=16, sort_every_ion=0, birth_capacity=65536, nscan=200_000, helm_rtol=1e-12,
                          helm_max_cycles=60):
     """(PicConfig, keep-alive list).  precision: 'fp64' or 'mixed'.  A
     workload with a ``circuit`` couples its turns to the external network."""
@@ -188,6 +189,7 @@ def config_from_workload(wl, precision="mixed", fuse=True, load=True, mg_rtol=No
     if mg_rtol is None:
         mg_rtol = 1e-13 if precision == "fp64" else 1e-9
     c.mg_rtol, c.mg_max_cycles, c.sort_every, c.load = mg_rtol, mg_max_cycles, sort_every, 1 if load else 0
+    c.sort_every_ion = sort_every_ion
     c.birth_capacity = birth_capacity
     cp = wl.circuit
     if cp is not None:
