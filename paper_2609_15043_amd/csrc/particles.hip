@@ -234,6 +234,19 @@ __device__ __forceinline__ void deposit_lane(int i, int j, T v0, T v1, T v2, T v
 // flushes it, so the global sums are exact and independent of block order.
 // Called by all 64 lanes.
 // ---------------------------------------------------------------------------
+// lane 63's value in every lane (a wave total after wave_total)
+__device__ __forceinline__ float lane63(float v)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+__device__ __forceinline__ double lane63(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), 63);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(uint32_t)lo);
+}
+
 template <typename T>
 __device__ __forceinline__ void deposit4(bool valid, int i, int j, T v0, T v1, T v2, T v3, long long *win,
                                          const WinMap &w, long long *acc, int nr1, T scale, int &nout)
@@ -252,15 +265,14 @@ __device__ __forceinline__ void deposit4(bool valid, int i, int j, T v0, T v1, T
         const uint64_t mm = ballot(m);
         if (__popcll(mm) < DEPOSIT_MIN_LANES) break;
         const int ki = __builtin_amdgcn_readlane(i, lead), kj = __builtin_amdgcn_readlane(j, lead);
-        const T s0 = wave_total(m ? v0 : (T)0);
-        const T s1 = wave_total(m ? v1 : (T)0);
-        const T s2 = wave_total(m ? v2 : (T)0);
-        const T s3 = wave_total(m ? v3 : (T)0);
-        if (lane == 63) {
-            if (s0 != (T)0) deposit_node<T>(w, ki, kj, s0, win, acc, nr1, scale, nout);
-            if (s1 != (T)0) deposit_node<T>(w, ki, kj + 1, s1, win, acc, nr1, scale, nout);
-            if (s2 != (T)0) deposit_node<T>(w, ki + 1, kj, s2, win, acc, nr1, scale, nout);
-            if (s3 != (T)0) deposit_node<T>(w, ki + 1, kj + 1, s3, win, acc, nr1, scale, nout);
+        const T s0 = lane63(wave_total(m ? v0 : (T)0));
+        const T s1 = lane63(wave_total(m ? v1 : (T)0));
+        const T s2 = lane63(wave_total(m ? v2 : (T)0));
+        const T s3 = lane63(wave_total(m ? v3 : (T)0));
+        // the four node sums are added by lanes 0..3 at once
+        if (lane < 4) {
+            const T v = lane == 0 ? s0 : lane == 1 ? s1 : lane == 2 ? s2 : s3;
+            if (v != (T)0) deposit_node<T>(w, ki + (lane >> 1), kj + (lane & 1), v, win, acc, nr1, scale, nout);
         }
         todo &= ~mm;
     }
@@ -417,13 +429,13 @@ __device__ __forceinline__ void node_weights(int j, T dr, T dz, T &w00, T &w01, 
 // accumulate in registers over the run (particles of one cell), then one
 // wave reduction per run; the collisions run in k_collide over the queue.
 // ---------------------------------------------------------------------------
-// FP32 pass: at least PIC_PASS_WAVES_PER_EU waves per SIMD (the register
-// budget is held to fit them); FP64 runs at what its registers allow
+// At least PIC_PASS_WAVES_PER_EU waves per SIMD for the FP32 pass and 3 for
+// the FP64 one (the register budget is held to fit them)
 #ifndef PIC_PASS_WAVES_PER_EU
 #define PIC_PASS_WAVES_PER_EU 4
 #endif
 template <typename T> struct PassOcc {
-    static constexpr int min_waves = sizeof(T) == 4 ? PIC_PASS_WAVES_PER_EU : 1;
+    static constexpr int min_waves = sizeof(T) == 4 ? PIC_PASS_WAVES_PER_EU : 3;
 };
 #define PIC_PASS_OCCUPANCY __attribute__((amdgpu_waves_per_eu(PassOcc<T>::min_waves, 8)))
 template <typename T, bool PUSH, bool DEPQ>
@@ -750,9 +762,11 @@ __global__ __launch_bounds__(256) void k_collide(PassArgs<T> a)
         vt = a.p.vt[p];
         vz = a.p.vz[p];
         ev = collide<T>(a.mc, s, a.p.id[p], a.step, vr, vt, vz, next, over, born, ve, vi, nb);
-        a.p.vr[p] = vr;
-        a.p.vt[p] = vt;
-        a.p.vz[p] = vz;
+        if (ev >= 0) {   // a null collision leaves the velocity as it is
+            a.p.vr[p] = vr;
+            a.p.vt[p] = vt;
+            a.p.vz[p] = vz;
+        }
         a.p.next[p] = next;
     }
     count_wave(act, sstat, ST_CAND0 + s);
