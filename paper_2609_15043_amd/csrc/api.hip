@@ -542,7 +542,7 @@ static void layout(pic_ctx &c, Carver &cv)
     c.phi_prev = cv.take<double>(2 * (size_t)nodes);
     {
         const MGLevel &Lc = c.lv.L[nl - 1];
-        c.lv.coarse_inv = cv.take<double>((size_t)Lc.nodes * Lc.nodes);
+        c.lv.coarse_inv = cv.take<double>((size_t)Lc.nodes * dense_ld(Lc.nodes));
     }
     c.mgs = cv.take<MGState>(1);
     c.mgpartial = cv.take<double>(pcg_partial_size(c.lv.L[0]));
@@ -586,7 +586,7 @@ static void layout(pic_ctx &c, Carver &cv)
             L.dir = cv.take<uint8_t>(L.nodes);
         }
         const MGLevel &Lc = c.hlv.L[nl - 1];
-        c.hlv.coarse_inv = cv.take<double>((size_t)Lc.nodes * Lc.nodes);
+        c.hlv.coarse_inv = cv.take<double>((size_t)Lc.nodes * dense_ld(Lc.nodes));
     }
 }
 
@@ -933,7 +933,9 @@ static pic_status build_levels(pic_ctx &c, MGLevels &lv, const Coeffs &co, const
             }
             if (!(A[(size_t)n * m + n] > 0.0)) return fail(&c, PIC_EINVAL, "bottom multigrid level not definite");
         }
-        HIPCHK(&c, cpy(c.stream, (void *)lv.coarse_inv, A.data(), A.size() * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHK(&c, hipMemcpy2DAsync((void *)lv.coarse_inv, (size_t)dense_ld(m) * sizeof(double), A.data(),
+                                    (size_t)m * sizeof(double), (size_t)m * sizeof(double), m, hipMemcpyHostToDevice,
+                                    c.stream));
         launch_gauss_jordan(const_cast<double *>(lv.coarse_inv), m, c.pp, c.pAp, c.stream);
         HIPCHK(&c, hipStreamSynchronize(c.stream));
     }

@@ -222,11 +222,10 @@ __device__ __forceinline__ void block_partial(double v, double *out, bool is_max
 //               the tile (and halo) as it is loaded (post-smoother);
 //   SM_RZ       per-block partial of rhs . x over the tile (the CG r.z of
 //               the level-0 post-smoother) to partial[2 * block].
-// Tiles: 16 x 64 nodes (4 per thread) on the 5-point level, 8 x 32 (one
-// per thread, four times the workgroups) on the smaller Galerkin levels.
-constexpr int TILE_Z = 16, TILE_R = 64;       // level 0
-constexpr int TILE_ZC = 8, TILE_RC = 32;      // Galerkin levels
-template <int TILE_Z, int TILE_R>
+// Tiles of 8 x 32 nodes, one per thread: every level is latency-bound, and
+// small tiles give it the most workgroups (16 x 64 tiles on level 0 took
+// 13 us per sweep pair against 7 us, at the same CG iteration counts).
+constexpr int TILE_Z = 8, TILE_R = 32;
 __global__ __launch_bounds__(256) void k_mg_smooth_tile(MGLevel L, MGLevel F, MGLevel C, int sweeps, int mode,
                                                         const MGState *st, double *partial)
 {
@@ -342,40 +341,50 @@ __global__ __launch_bounds__(256) void k_mg_restrict_res(MGLevel F, MGLevel C, c
     }
 }
 
-// Exact solve on the bottom level: phi = Inv rhs, one wave per row.
-__global__ __launch_bounds__(256) void k_dense_solve(const double *inv, MGLevel L, const MGState *st)
+// Exact solve on the bottom level: phi = Inv rhs, one wave per row, the row
+// streamed in 16-byte loads (rows are padded to an even length, ld doubles)
+// into two independent partial sums.
+__global__ __launch_bounds__(256) void k_dense_solve(const double *inv, int ld, MGLevel L, const MGState *st)
 {
     if (st->done) return;
     const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (r >= L.nodes) return;
     const int lane = threadIdx.x & 63;
-    const double *row = inv + (size_t)r * L.nodes;
-    double s = 0.0;
-    for (int k = lane; k < L.nodes; k += 64) s += row[k] * L.rhs[k];
-    s = wave_total(s);
+    const double2 *row = reinterpret_cast<const double2 *>(inv + (size_t)r * ld);
+    const int n2 = L.nodes >> 1;
+    double s0 = 0.0, s1 = 0.0;
+    for (int k = lane; k < n2; k += 64) {
+        const double2 a = row[k];
+        s0 += a.x * L.rhs[2 * k];
+        s1 += a.y * L.rhs[2 * k + 1];
+    }
+    if ((L.nodes & 1) && lane == 0) s0 += inv[(size_t)r * ld + L.nodes - 1] * L.rhs[L.nodes - 1];
+    const double s = wave_total(s0 + s1);
     if (lane == 63) L.phi[r] = s;
 }
 
-// In-place Gauss-Jordan inversion, one pivot per kernel pair: save the
-// scaled pivot row and the pivot column, then update every entry.
-__global__ void k_gj_save(const double *A, int n, int k, double *rowk, double *colk)
+// In-place Gauss-Jordan inversion (row stride ld), one pivot per kernel
+// pair: save the scaled pivot row and the pivot column, then update every
+// entry.
+__global__ void k_gj_save(const double *A, int n, int ld, int k, double *rowk, double *colk)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
-    const double p = A[(size_t)k * n + k];
-    rowk[t] = t == k ? 1.0 / p : A[(size_t)k * n + t] / p;
-    colk[t] = A[(size_t)t * n + k];
+    const double p = A[(size_t)k * ld + k];
+    rowk[t] = t == k ? 1.0 / p : A[(size_t)k * ld + t] / p;
+    colk[t] = A[(size_t)t * ld + k];
 }
 
-__global__ void k_gj_update(double *A, int n, int k, const double *rowk, const double *colk)
+__global__ void k_gj_update(double *A, int n, int ld, int k, const double *rowk, const double *colk)
 {
     const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (size_t)n * n) return;
     const int i = (int)(e / n), j = (int)(e - (size_t)i * n);
+    double &a = A[(size_t)i * ld + j];
     if (i == k)
-        A[e] = rowk[j];
+        a = rowk[j];
     else
-        A[e] = (j == k ? 0.0 : A[e]) - colk[i] * rowk[j];
+        a = (j == k ? 0.0 : a) - colk[i] * rowk[j];
 }
 
 // ---------------------------------------------------------------------------
@@ -624,7 +633,6 @@ static unsigned red_grid(int work) { return nblk(work, 256) < 1024 ? nblk(work, 
 
 static int smooth_tiles(const MGLevel &L)
 {
-    if (L.nine) return ((L.nz + 1 + TILE_ZC - 1) / TILE_ZC) * ((L.nr1 + TILE_RC - 1) / TILE_RC);
     return ((L.nz + 1 + TILE_Z - 1) / TILE_Z) * ((L.nr1 + TILE_R - 1) / TILE_R);
 }
 int smooth_blocks(const MGLevel &L) { return smooth_tiles(L); }
@@ -637,12 +645,8 @@ void launch_mg_smooth_tile(const MGLevel &L, const MGLevel *F, const MGLevel *C,
                            const MGState *st, double *partial, hipStream_t s)
 {
     const MGLevel none{};
-    if (L.nine)
-        hipLaunchKernelGGL((k_mg_smooth_tile<TILE_ZC, TILE_RC>), dim3(smooth_tiles(L)), dim3(256), 0, s, L,
-                           F ? *F : none, C ? *C : none, sweeps, mode, st, partial);
-    else
-        hipLaunchKernelGGL((k_mg_smooth_tile<TILE_Z, TILE_R>), dim3(smooth_tiles(L)), dim3(256), 0, s, L,
-                           F ? *F : none, C ? *C : none, sweeps, mode, st, partial);
+    hipLaunchKernelGGL(k_mg_smooth_tile, dim3(smooth_tiles(L)), dim3(256), 0, s, L, F ? *F : none, C ? *C : none,
+                       sweeps, mode, st, partial);
 }
 void launch_mg_resid(const MGLevel &L, const MGState *st, hipStream_t s)
 {
@@ -652,15 +656,17 @@ void launch_mg_restrict_res(const MGLevel &F, const MGLevel &C, const MGState *s
 {
     hipLaunchKernelGGL(k_mg_restrict_res, dim3(mg_grid(C.nodes)), dim3(256), 0, s, F, C, st);
 }
+int dense_ld(int n) { return n + (n & 1); }
 void launch_dense_solve(const double *inv, const MGLevel &L, const MGState *st, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_dense_solve, dim3(nblk(L.nodes, 4)), dim3(256), 0, s, inv, L, st);
+    hipLaunchKernelGGL(k_dense_solve, dim3(nblk(L.nodes, 4)), dim3(256), 0, s, inv, dense_ld(L.nodes), L, st);
 }
 void launch_gauss_jordan(double *A, int n, double *rowk, double *colk, hipStream_t s)
 {
+    const int ld = dense_ld(n);
     for (int k = 0; k < n; ++k) {
-        hipLaunchKernelGGL(k_gj_save, dim3(nblk(n, 256)), dim3(256), 0, s, A, n, k, rowk, colk);
-        hipLaunchKernelGGL(k_gj_update, dim3(nblk((int64_t)n * n, 256)), dim3(256), 0, s, A, n, k, rowk, colk);
+        hipLaunchKernelGGL(k_gj_save, dim3(nblk(n, 256)), dim3(256), 0, s, A, n, ld, k, rowk, colk);
+        hipLaunchKernelGGL(k_gj_update, dim3(nblk((int64_t)n * n, 256)), dim3(256), 0, s, A, n, ld, k, rowk, colk);
     }
 }
 int pcg_blocks(int nodes) { return (int)red_grid(nodes); }

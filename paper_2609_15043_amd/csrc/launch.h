@@ -56,6 +56,9 @@ void launch_mg_smooth_tile(const MGLevel &L, const MGLevel *F, const MGLevel *C,
 void launch_mg_resid(const MGLevel &L, const MGState *st, hipStream_t s);
 void launch_mg_restrict_res(const MGLevel &F, const MGLevel &C, const MGState *st, hipStream_t s);
 void launch_dense_solve(const double *inv, const MGLevel &L, const MGState *st, hipStream_t s);
+// dense inverse of the bottom level: n rows of stride dense_ld(n) (even, so
+// that rows start 16-byte aligned)
+int dense_ld(int n);
 void launch_gauss_jordan(double *A, int n, double *rowk, double *colk, hipStream_t s);
 int pcg_blocks(int nodes);
 void launch_pcg_begin(const MGLevel &L, const PCGVec &v, const int32_t *tag, const double *vc, const double *vs,
