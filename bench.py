@@ -217,6 +217,12 @@ def main():
                           "HIP events on the library stream over the timed steps",
                 "launch_ms": r["pass_launch_ms"], "launches": r["pass_count"],
                 "bytes_per_launch": launch_bytes, "bytes_per_particle_step": bpp}
+    # whole step: the same algorithmic particle bytes over the step's wall
+    # time (multigrid, sort, collisions and births included)
+    step_bytes = bpp * r["mean_live"]
+    step_gbs = step_bytes / (r["ms_per_step"] * 1e-3) / 1e9
+    step_hbm = {"achieved": step_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": step_gbs / HBM_PEAK_GBS,
+                "bytes_per_step": step_bytes}
     cpu = None
     if not args.no_cpu_baseline:
         print(f"[bench] cpu baseline: oracle on 1/{args.cpu_scale} of {wl.name}, {args.cpu_steps} steps",
@@ -229,7 +235,7 @@ def main():
         "config": {"workload": describe(wl, prec), "particles": r["mean_live"], "grid": [wl.nr, wl.nz],
                    "parallelism": "1 GPU", "sort_every": SORT_EVERY, "sort_every_ion": SORT_EVERY_ION,
                    "fused": not args.split},
-        "roofline": roofline, "cpu_baseline": cpu,
+        "roofline": roofline, "step_hbm": step_hbm, "cpu_baseline": cpu,
         "breakdown_ms": {"pass": r["pass_ms"], "poisson": r["poisson_ms"], "sort_per_species": r["sort_ms"],
                          "window_fallback_atomics": r["window_out"],
                          "species_sorts_per_step": r["sort_count"] / max(1, r["steps"]),
