@@ -1,7 +1,7 @@
 """Throughput of the RZ PIC/MCC step on one MI355X.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload large|cell|small]
-                [--precision mixed|fp64] [--fp64-steps K64] [--no-cpu-baseline]
+                [--precision mixed|fp64] [--fp64-steps K64] [--no-cpu-baseline] [--no-stationary]
 
 A step is one pass of the whole per-step cycle through the C ABI:
 pic_gather_push (stage + sort every 16 steps + fused gather/push/MCC/deposit
@@ -134,6 +134,101 @@ def measured_traffic(name, prec, particles_per_launch):
     return per_particle * particles_per_launch
 
 
+def stationary_circuit(plain_periods=100, sur_periods=40):
+    """Wall-seconds to the stationary circuit state: the plain FP64 GPU run
+    against the surrogate-assisted FP32-mixed run.  A stand-in for the
+    plasma-loaded cell (hundreds of RF periods of 2000 steps): the coil cell
+    without plasma at 13.56 MHz, 16 steps per RF period, controller driving
+    the port power to its target.  The network is trained first on the
+    method's own (state, response) pairs from periods at scanned source
+    settings (their cost is reported, not counted in either run).
+    Stationary: the applied state moves by < 1 % over a period and the port
+    power is within 1 % of the target."""
+    import numpy as np
+    import torch
+    import paper_2609_15043_amd.phasorpic as pp
+    from paper_2609_15043_amd import workloads as W
+    wl = W.cell(n_per_species=1000)
+    wl.dt = 1.0 / (16 * wl.freq)
+    nrf, N = 16, wl.nturns
+
+    def periods_of(ctx, periods, source=None):
+        reps, times = [], []
+        n = 0
+        t0 = time.perf_counter()
+        for p in range(periods):
+            if source is not None:
+                pp.pic_set_source(ctx, *source(p))
+            for _ in range(nrf):
+                pp.pic_gather_push(ctx, n)
+                pp.harmonic_accumulate(ctx, n)
+                pp.mcc_collide(ctx, n)
+                pp.pic_deposit(ctx, n + 1)
+                if (n + 1) % nrf == 0:
+                    st, rep, _, _ = pp.circuit_period_update(ctx)   # synchronises
+                    if st != 0:
+                        raise RuntimeError(f"period update status {st}")
+                    reps.append(rep)
+                    times.append(time.perf_counter() - t0)
+                pp.poisson_solve_rz(ctx, n + 1)
+                n += 1
+        return reps, times
+
+    def stationary(reps, tol=0.01):
+        for i in range(1, len(reps)):
+            x0, x1 = reps[i - 1]["x"], reps[i]["x"]
+            if (np.linalg.norm(x1 - x0) / np.linalg.norm(x0) < tol
+                    and abs(reps[i]["p_port"] - wl.circuit.p_target) / wl.circuit.p_target < tol):
+                return i
+        return None
+
+    # training pairs from the method itself, scanning the source
+    t0 = time.perf_counter()
+    cfg, keep = pp.config_from_workload(wl, precision="fp64", load=False)
+    ctx = pp.pic_init(cfg, keep)
+    rng = np.random.default_rng(21)
+    scan = [(float(rng.uniform(1500.0, 6000.0)), float(rng.uniform(-0.5, 0.5))) for _ in range(240)]
+    reps, _ = periods_of(ctx, 240, source=lambda p: scan[p])
+    del ctx
+    X = np.array([pp.surrogate_features(r, N) for r in reps])
+    Y = np.array([pp.surrogate_targets(r, N) for r in reps])
+    sx, sy = X.std(0), Y.std(0)
+    norm = (X.mean(0), np.where(sx > 0, sx, 1.0), Y.mean(0), np.where(sy > 0, sy, 1.0))
+    net = pp.Mlp(norm=norm, lr=1e-3, max_batch=256)
+    net.set_params(W.mlp_init_params(seed=22))
+    xd = torch.from_numpy(X.astype(np.float32)).cuda()
+    yd = torch.from_numpy(Y.astype(np.float32)).cuda()
+    for it in range(1500):
+        loss = net.train_step(xd, yd, want_loss=(it == 1499))
+    net.sync()
+    t_train = time.perf_counter() - t0
+    runs = {}
+    for mode, prec, periods in (("plain", "fp64", plain_periods), ("surrogate", "mixed", sur_periods)):
+        cfg, keep = pp.config_from_workload(wl, precision=prec, load=False)
+        ctx = pp.pic_init(cfg, keep)
+        if mode == "surrogate":
+            pp.pic_attach_surrogate(ctx, net, err_max=0.02, tol=1e-6, max_iter=50)
+        reps, times = periods_of(ctx, periods)
+        i = stationary(reps)
+        runs[mode] = dict(reps=reps, times=times, i=i, used=sum(r["sur_used"] for r in reps))
+        del ctx
+    x_ref = runs["plain"]["reps"][-1]["x"]
+    dev = float(np.linalg.norm(runs["surrogate"]["reps"][-1]["x"] - x_ref) / np.linalg.norm(x_ref))
+
+    def leg(m, prec):
+        r = runs[m]
+        i = r["i"]
+        return {"precision": prec, "periods": None if i is None else i + 1,
+                "wall_s": None if i is None else r["times"][i], "surrogate_periods": r["used"]}
+
+    return {"workload": f"{wl.name} coil cell without plasma, {wl.nr}x{wl.nz} cells, 13.56 MHz, 16 steps per RF "
+                        f"period, port power target {wl.circuit.p_target:g} W",
+            "criterion": "state change < 1 % per period and port power within 1 % of the target",
+            "plain": leg("plain", "fp64"), "surrogate_assisted": leg("surrogate", "mixed"),
+            "final_state_deviation": dev,
+            "training": {"pairs": len(X), "adam_steps": 1500, "final_loss": float(loss), "wall_s": t_train}}
+
+
 def cpu_baseline(name, scale, nsteps):
     """The oracle as it stands, on a bounded sample: same grid and physics,
     1/scale of the particles, nsteps whole steps (init not timed)."""
@@ -160,6 +255,7 @@ def main():
     ap.add_argument("--precision", default="mixed")
     ap.add_argument("--fp64-steps", type=int, default=400)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-stationary", action="store_true", help="skip the wall-seconds-to-stationary leg")
     ap.add_argument("--cpu-scale", type=int, default=4)
     ap.add_argument("--cpu-steps", type=int, default=15)
     ap.add_argument("--split", action="store_true", help="unfused pass (parity-isolation mode)")
@@ -223,6 +319,13 @@ def main():
     step_gbs = step_bytes / (r["ms_per_step"] * 1e-3) / 1e9
     step_hbm = {"achieved": step_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": step_gbs / HBM_PEAK_GBS,
                 "bytes_per_step": step_bytes}
+    stat = None
+    if not args.no_stationary:
+        print("[bench] wall-s to stationary circuit: plain FP64 vs surrogate-assisted mixed", file=sys.stderr,
+              flush=True)
+        stat = stationary_circuit()
+        print(f"[bench] stationary: plain {stat['plain']}, surrogate {stat['surrogate_assisted']}, "
+              f"final deviation {stat['final_state_deviation']:.2e}", file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu_baseline:
         print(f"[bench] cpu baseline: oracle on 1/{args.cpu_scale} of {wl.name}, {args.cpu_steps} steps",
@@ -235,7 +338,7 @@ def main():
         "config": {"workload": describe(wl, prec), "particles": r["mean_live"], "grid": [wl.nr, wl.nz],
                    "parallelism": "1 GPU", "sort_every": SORT_EVERY, "sort_every_ion": SORT_EVERY_ION,
                    "fused": not args.split},
-        "roofline": roofline, "step_hbm": step_hbm, "cpu_baseline": cpu,
+        "roofline": roofline, "step_hbm": step_hbm, "stationary_circuit": stat, "cpu_baseline": cpu,
         "breakdown_ms": {"pass": r["pass_ms"], "poisson": r["poisson_ms"], "sort_per_species": r["sort_ms"],
                          "window_fallback_atomics": r["window_out"],
                          "species_sorts_per_step": r["sort_count"] / max(1, r["steps"]),
