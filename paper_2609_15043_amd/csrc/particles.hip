@@ -505,19 +505,25 @@ __global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassArgs<T> a
     int nout = 0;   // this lane's deposits outside the window
 
     const int64_t wbase = c0 + (int64_t)(tid >> 6) * (RUN * RUNS * 64);
+    int32_t cell[RUN], nxt[RUN];
+    T dr[RUN], dz[RUN], vr[RUN], vt[RUN], vz[RUN];
+    // a run's particles; the next run's loads are issued right after this
+    // run's stores (its registers are free then), so that their latency
+    // overlaps this run's deposit reductions
+    auto load_run = [&](int64_t q) {
+        ld4(a.p.cell + q, cell);
+        ld4(a.p.dr + q, dr);
+        ld4(a.p.dz + q, dz);
+        if (PUSH) {
+            ld4(a.p.vr + q, vr);
+            ld4(a.p.vt + q, vt);
+            ld4(a.p.vz + q, vz);
+            ld4(a.p.next + q, nxt);
+        }
+    };
+    load_run(wbase + RUN * lane);
     for (int r = 0; r < RUNS; ++r) {
         const int64_t q0 = wbase + (int64_t)r * (RUN * 64) + RUN * lane;
-        int32_t cell[RUN], nxt[RUN];
-        T dr[RUN], dz[RUN], vr[RUN], vt[RUN], vz[RUN];
-        ld4(a.p.cell + q0, cell);
-        ld4(a.p.dr + q0, dr);
-        ld4(a.p.dz + q0, dz);
-        if (PUSH) {
-            ld4(a.p.vr + q0, vr);
-            ld4(a.p.vt + q0, vt);
-            ld4(a.p.vz + q0, vz);
-            ld4(a.p.next + q0, nxt);
-        }
         bool live[RUN];
 #pragma unroll
         for (int k = 0; k < RUN; ++k) live[k] = q0 + k < c1 && cell[k] >= 0;
@@ -644,16 +650,12 @@ __global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassArgs<T> a
             }
         }
         if constexpr (PUSH) {
-            deposit4<T>(iJ >= 0, iJ, jJ, aJ[0], aJ[1], aJ[2], aJ[3], winJ, w, a.accJ, g.nr1, jscale, nout);
-            {
-                const uint64_t m = ballot(absorbed_n > 0);
-                (void)m;
-                // absorbed count: sum over the wave
-                int tot = absorbed_n;
-#pragma unroll
-                for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off);
-                if (lane == 0 && tot) atomicAdd(&sstat[ST_ABS0 + s], (unsigned long long)tot);
-            }
+            st4(a.p.cell + q0, cell);
+            st4(a.p.dr + q0, dr);
+            st4(a.p.dz + q0, dz);
+            st4(a.p.vr + q0, vr);
+            st4(a.p.vt + q0, vt);
+            st4(a.p.vz + q0, vz);
             // this step's collision candidates -> block-local list (LDS), one
             // global reservation per block at the end
             const int nc = __popc(cand_bits);
@@ -685,16 +687,17 @@ __global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassArgs<T> a
                 ++slot;
             }
         }
+        if (r + 1 < RUNS) load_run(q0 + RUN * 64);
+        if constexpr (PUSH) {
+            deposit4<T>(iJ >= 0, iJ, jJ, aJ[0], aJ[1], aJ[2], aJ[3], winJ, w, a.accJ, g.nr1, jscale, nout);
+            // absorbed count: sum over the wave
+            int tot = absorbed_n;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off);
+            if (lane == 0 && tot) atomicAdd(&sstat[ST_ABS0 + s], (unsigned long long)tot);
+        }
         if constexpr (DEPQ)
             deposit4<T>(iQ >= 0, iQ, jQ, aQ[0], aQ[1], aQ[2], aQ[3], winQ, w, a.accQ, g.nr1, qscale, nout);
-        if constexpr (PUSH) {
-            st4(a.p.cell + q0, cell);
-            st4(a.p.dr + q0, dr);
-            st4(a.p.dz + q0, dz);
-            st4(a.p.vr + q0, vr);
-            st4(a.p.vt + q0, vt);
-            st4(a.p.vz + q0, vz);
-        }
     }
     {
         int tot = nout;
