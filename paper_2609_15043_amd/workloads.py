@@ -218,8 +218,9 @@ def loop_field(nr, nz, rmax, zmax, a, z_loop, current, freq):
     return np.zeros_like(A), -w * A
 
 
-def small(seed=0, n_per_species=100_000, nsteps=200) -> Workload:
-    nr, nz, rmax, zmax = 32, 64, 0.1, 0.1
+def small(seed=0, n_per_species=100_000, nsteps=200, nr=32, nz=64) -> Workload:
+    """The smallest instance (32 x 64 cells; other grid sizes for edge cases)."""
+    rmax, zmax = 0.1, 0.1
     ec, es = loop_field(nr, nz, rmax, zmax, a=0.06, z_loop=0.11, current=10.0, freq=13.56e6)
     tag = np.full((nz + 1, nr + 1), -1, np.int32)
     tag[0, :] = 0

@@ -96,6 +96,10 @@ def _step_case(wlname, prec, fuse, n0):
     from oracle import pic as O
     if wlname == "small":
         wl = W.small(n_per_species=60_000)
+    elif wlname == "ragged":
+        # 40 x 70 cells: a two-level hierarchy with an odd bottom level
+        # (21 x 36 nodes), partial smoother tiles, an odd particle count
+        wl = W.small(n_per_species=50_001, nr=40, nz=70)
     else:
         wl = W.cell(n_per_species=120_000, circuit=False)
     say(f"[gpu] one step {wlname} {prec} fuse={fuse} n0={n0}")
