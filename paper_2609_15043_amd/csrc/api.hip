@@ -785,18 +785,31 @@ static void finalize_charge(pic_ctx &c)
 static void vcycle(pic_ctx &c, const MGLevels &lv, const MGState *st)
 {
     const int lb = c.lb;
+    // Each level above the bottom keeps two corrections: the pre-smoothed one
+    // (read as the post-smoother's start and halo) and the post-smoothed one,
+    // so no smoother launch reads what a neighbouring tile of the same launch
+    // writes.  Level 0: pre-smoothed in the A p buffer (idle during the
+    // V-cycle), post-smoothed into z (= L[0].phi, Dirichlet entries 0 since
+    // the start of the solve).  Levels l >= 1: pre-smoothed in phi,
+    // post-smoothed into res, free once restricted (Dirichlet entries 0).
+    MGLevel pre[MAX_LEVELS], post[MAX_LEVELS];
+    for (int l = 0; l <= lb; ++l) {
+        pre[l] = post[l] = lv.L[l];
+        if (l == 0 && lb > 0) pre[0].phi = c.pAp;
+        if (l > 0 && l < lb) post[l].phi = lv.L[l].res;
+    }
     for (int l = 0; l < lb; ++l) {
         const int nu = l == 0 ? PIC_MG_NU0 : PIC_MG_NU;
-        launch_mg_smooth_tile(lv.L[l], l > 0 ? &lv.L[l - 1] : nullptr, nullptr, nu, SM_ZERO | (l > 0 ? SM_RHS : 0),
-                              st, nullptr, c.stream);
-        launch_mg_resid(lv.L[l], st, c.stream);
+        launch_mg_smooth_tile(pre[l], l > 0 ? &pre[l - 1] : nullptr, nullptr, nu, SM_ZERO | (l > 0 ? SM_RHS : 0), st,
+                              nullptr, pre[l].phi, c.stream);
+        launch_mg_resid(pre[l], st, c.stream);
     }
-    if (lb > 0) launch_mg_restrict_res(lv.L[lb - 1], lv.L[lb], st, c.stream);
+    if (lb > 0) launch_mg_restrict_res(pre[lb - 1], pre[lb], st, c.stream);
     launch_dense_solve(lv.coarse_inv, lv.L[lb], st, c.stream);
     for (int l = lb - 1; l >= 0; --l) {
         const int nu = l == 0 ? PIC_MG_NU0 : PIC_MG_NU;
-        launch_mg_smooth_tile(lv.L[l], nullptr, &lv.L[l + 1], nu, SM_REVERSE | SM_PROLONG | (l == 0 ? SM_RZ : 0), st,
-                              c.mgpartial, c.stream);
+        launch_mg_smooth_tile(pre[l], nullptr, &post[l + 1], nu, SM_REVERSE | SM_PROLONG | (l == 0 ? SM_RZ : 0), st,
+                              c.mgpartial, post[l].phi, c.stream);
     }
 }
 

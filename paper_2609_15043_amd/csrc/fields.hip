@@ -211,11 +211,14 @@ __device__ __forceinline__ void block_partial(double v, double *out, bool is_max
 // the 5-point level, four colours on the Galerkin levels; colours in reverse
 // order when SM_REVERSE) on its tile, the halo held at its values from the
 // start of the kernel: Gauss-Seidel inside a tile, Jacobi across tiles.
-// Reversing the colour order for the post-smoother keeps the V-cycle a
-// symmetric preconditioner.  The modes fold the V-cycle's transfers into
-// the smoothers:
-//   SM_ZERO     the correction starts from zero (pre-smoother; Dirichlet
-//               nodes are written 0);
+// The result goes to `out`, which must not be L.phi unless SM_ZERO is set:
+// a tile that finished early would otherwise change the halo its
+// neighbours load, and the V-cycle would depend on the order in which
+// workgroups run.  Reversing the colour order for the post-smoother keeps
+// the V-cycle a symmetric preconditioner.  The modes fold the V-cycle's
+// transfers into the smoothers:
+//   SM_ZERO     the correction starts from zero (pre-smoother; L.phi is not
+//               read, Dirichlet nodes of out are written 0);
 //   SM_RHS      the right-hand side is the full-weighting restriction of
 //               the finer level's residual, stored in L.rhs;
 //   SM_PROLONG  the coarser level's correction is prolonged and added to
@@ -227,7 +230,7 @@ __device__ __forceinline__ void block_partial(double v, double *out, bool is_max
 // 13 us per sweep pair against 7 us, at the same CG iteration counts).
 constexpr int TILE_Z = 8, TILE_R = 32;
 __global__ __launch_bounds__(256) void k_mg_smooth_tile(MGLevel L, MGLevel F, MGLevel C, int sweeps, int mode,
-                                                        const MGState *st, double *partial)
+                                                        const MGState *st, double *partial, double *out)
 {
     constexpr int TILE_PER = TILE_Z * TILE_R / 256;
     __shared__ double xs[(TILE_Z + 2) * (TILE_R + 2)];
@@ -261,7 +264,7 @@ __global__ __launch_bounds__(256) void k_mg_smooth_tile(MGLevel L, MGLevel F, MG
         if (i > L.nz || j > L.nr) continue;
         const int n = i * L.nr1 + j;
         if (L.dir[n]) {
-            if (mode & SM_ZERO) L.phi[n] = 0.0;
+            if (mode & SM_ZERO) out[n] = 0.0;
             if (mode & SM_RHS) L.rhs[n] = 0.0;
             continue;
         }
@@ -310,7 +313,7 @@ __global__ __launch_bounds__(256) void k_mg_smooth_tile(MGLevel L, MGLevel F, MG
         if (own[q] < 0) continue;
         const int e = threadIdx.x + 256 * q;
         const double x = xs[(e / TILE_R + 1) * W + e % TILE_R + 1];
-        L.phi[own[q]] = x;
+        out[own[q]] = x;
         rz += rhs[q] * x;
     }
     if (mode & SM_RZ) block_partial(rz, partial + 2 * blockIdx.x, false);
@@ -642,11 +645,11 @@ int pcg_partial_size(const MGLevel &L0)
     return 2 * (t > r ? t : r);
 }
 void launch_mg_smooth_tile(const MGLevel &L, const MGLevel *F, const MGLevel *C, int sweeps, int mode,
-                           const MGState *st, double *partial, hipStream_t s)
+                           const MGState *st, double *partial, double *out, hipStream_t s)
 {
     const MGLevel none{};
     hipLaunchKernelGGL(k_mg_smooth_tile, dim3(smooth_tiles(L)), dim3(256), 0, s, L, F ? *F : none, C ? *C : none,
-                       sweeps, mode, st, partial);
+                       sweeps, mode, st, partial, out);
 }
 void launch_mg_resid(const MGLevel &L, const MGState *st, hipStream_t s)
 {

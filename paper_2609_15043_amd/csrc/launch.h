@@ -48,11 +48,12 @@ struct PCGVec {
     double *x, *b, *r, *z, *p, *Ap;
 };
 int pcg_partial_size(const MGLevel &L0);
-// tile smoother modes (combinable)
+// tile smoother modes (combinable); the smoothed correction is written to
+// out, which may be L.phi only with SM_ZERO (otherwise the halo is read there)
 constexpr int SM_REVERSE = 1, SM_ZERO = 2, SM_RHS = 4, SM_PROLONG = 8, SM_RZ = 16;
 int smooth_blocks(const MGLevel &L);
 void launch_mg_smooth_tile(const MGLevel &L, const MGLevel *F, const MGLevel *C, int sweeps, int mode,
-                           const MGState *st, double *partial, hipStream_t s);
+                           const MGState *st, double *partial, double *out, hipStream_t s);
 void launch_mg_resid(const MGLevel &L, const MGState *st, hipStream_t s);
 void launch_mg_restrict_res(const MGLevel &F, const MGLevel &C, const MGState *st, hipStream_t s);
 void launch_dense_solve(const double *inv, const MGLevel &L, const MGState *st, hipStream_t s);
