@@ -136,7 +136,7 @@ def measured_traffic(name, prec, particles_per_launch):
 
 def stationary_circuit(plain_periods=100, sur_periods=40):
     """Wall-seconds to the stationary circuit state: the plain FP64 GPU run
-    against the surrogate-assisted FP32-mixed run.  A stand-in for the
+    against the surrogate-assisted run (FP64 as well).  A stand-in for the
     plasma-loaded cell (hundreds of RF periods of 2000 steps): the coil cell
     without plasma at 13.56 MHz, 16 steps per RF period, controller driving
     the port power to its target.  The network is trained first on the
@@ -203,7 +203,9 @@ def stationary_circuit(plain_periods=100, sur_periods=40):
     net.sync()
     t_train = time.perf_counter() - t0
     runs = {}
-    for mode, prec, periods in (("plain", "fp64", plain_periods), ("surrogate", "mixed", sur_periods)):
+    # both runs FP64 (the surrogate-assisted run differs only in the period
+    # update; the FP32 pass kernels then time the large workload alone)
+    for mode, prec, periods in (("plain", "fp64", plain_periods), ("surrogate", "fp64", sur_periods)):
         cfg, keep = pp.config_from_workload(wl, precision=prec, load=False)
         ctx = pp.pic_init(cfg, keep)
         if mode == "surrogate":
@@ -224,7 +226,7 @@ def stationary_circuit(plain_periods=100, sur_periods=40):
     return {"workload": f"{wl.name} coil cell without plasma, {wl.nr}x{wl.nz} cells, 13.56 MHz, 16 steps per RF "
                         f"period, port power target {wl.circuit.p_target:g} W",
             "criterion": "state change < 1 % per period and port power within 1 % of the target",
-            "plain": leg("plain", "fp64"), "surrogate_assisted": leg("surrogate", "mixed"),
+            "plain": leg("plain", "fp64"), "surrogate_assisted": leg("surrogate", "fp64"),
             "final_state_deviation": dev,
             "training": {"pairs": len(X), "adam_steps": 1500, "final_loss": float(loss), "wall_s": t_train}}
 
@@ -321,7 +323,7 @@ def main():
                 "bytes_per_step": step_bytes}
     stat = None
     if not args.no_stationary:
-        print("[bench] wall-s to stationary circuit: plain FP64 vs surrogate-assisted mixed", file=sys.stderr,
+        print("[bench] wall-s to stationary circuit: plain FP64 vs surrogate-assisted FP64", file=sys.stderr,
               flush=True)
         stat = stationary_circuit()
         print(f"[bench] stationary: plain {stat['plain']}, surrogate {stat['surrogate_assisted']}, "
