@@ -1,7 +1,7 @@
 """Throughput of the RZ PIC/MCC step on one MI355X.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload large|cell|small]
-                [--precision mixed|fp64] [--fp64-steps K64] [--no-cpu-baseline] [--no-stationary]
+                [--precision mixed|fp64] [--fp64-steps K64] [--no-cpu-baseline] [--no-stationary] [--no-mlp]
 
 A step is one pass of the whole per-step cycle through the C ABI:
 pic_gather_push (stage + sort every 16 steps + fused gather/push/MCC/deposit
@@ -17,11 +17,14 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "particle-steps/s and % HBM peak (FP32-mixed vs FP64); wall-s to stationary circuit"
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0   # dense BF16 MFMA peak of MI355X
 # algorithmic bytes per particle-step of the particle pass: read cell, two
 # offsets, three velocity components and the next-candidate step; write
 # cell, offsets and velocity (the id and next step are touched only at
@@ -134,17 +137,40 @@ def measured_traffic(name, prec, particles_per_launch):
     return per_particle * particles_per_launch
 
 
-def stationary_circuit(plain_periods=100, sur_periods=40):
+def stationary_index(reps, p_target, tol=0.01, window=10):
+    """First period i from which, for `window` periods, the port power stays
+    within tol of the target and the applied state within tol of its value
+    at i (None if no such period): stationarity held over a window, so that
+    one period that happens to pass the test does not count."""
+    for i in range(len(reps) - window + 1):
+        xi = reps[i]["x"]
+        ni = float(np.linalg.norm(xi))
+        if all(abs(reps[j]["p_port"] - p_target) / p_target <= tol
+               and float(np.linalg.norm(reps[j]["x"] - xi)) <= tol * ni for j in range(i, i + window)):
+            return i
+    return None
+
+
+def feature_scale(A):
+    """Standard deviation of each column of A, 1 where the column is constant
+    to rounding: a scale of ~1e-16 would turn a one-ulp difference from the
+    mean into an input of order one."""
+    mu, sd = A.mean(0), A.std(0)
+    return np.where(sd > 1e-9 * np.maximum(np.abs(mu), 1.0), sd, 1.0)
+
+
+def stationary_circuit(targets=(60.0, 100.0), plain_periods=100, sur_periods=40, adam_steps=5000):
     """Wall-seconds to the stationary circuit state: the plain FP64 GPU run
-    against the surrogate-assisted run (FP64 as well).  A stand-in for the
-    plasma-loaded cell (hundreds of RF periods of 2000 steps): the coil cell
-    without plasma at 13.56 MHz, 16 steps per RF period, controller driving
-    the port power to its target.  The network is trained first on the
-    method's own (state, response) pairs from periods at scanned source
-    settings (their cost is reported, not counted in either run).
-    Stationary: the applied state moves by < 1 % over a period and the port
-    power is within 1 % of the target."""
-    import numpy as np
+    against the surrogate-assisted run (FP64 as well: without plasma the two
+    precisions run the same FP64 field and circuit arithmetic), at each port
+    power target.  A stand-in for the plasma-loaded cell (hundreds of RF
+    periods of 2000 steps): the coil cell without plasma at 13.56 MHz, 16
+    steps per RF period, controller driving the port power to its target.
+    The network is trained first on the method's own (state, response) pairs
+    from 240 periods at scanned source settings: amplitudes 2000-5600 V,
+    which span about 20-150 W of port power on this cell, and phases within
+    0.5 rad (their cost is reported, not counted in either run).
+    Stationary: see stationary_index."""
     import torch
     import paper_2609_15043_amd.phasorpic as pp
     from paper_2609_15043_amd import workloads as W
@@ -174,61 +200,103 @@ def stationary_circuit(plain_periods=100, sur_periods=40):
                 n += 1
         return reps, times
 
-    def stationary(reps, tol=0.01):
-        for i in range(1, len(reps)):
-            x0, x1 = reps[i - 1]["x"], reps[i]["x"]
-            if (np.linalg.norm(x1 - x0) / np.linalg.norm(x0) < tol
-                    and abs(reps[i]["p_port"] - wl.circuit.p_target) / wl.circuit.p_target < tol):
-                return i
-        return None
-
     # training pairs from the method itself, scanning the source
     t0 = time.perf_counter()
     cfg, keep = pp.config_from_workload(wl, precision="fp64", load=False)
     ctx = pp.pic_init(cfg, keep)
     rng = np.random.default_rng(21)
-    scan = [(float(rng.uniform(1500.0, 6000.0)), float(rng.uniform(-0.5, 0.5))) for _ in range(240)]
+    scan = [(float(rng.uniform(2000.0, 5600.0)), float(rng.uniform(-0.5, 0.5))) for _ in range(240)]
     reps, _ = periods_of(ctx, 240, source=lambda p: scan[p])
     del ctx
     X = np.array([pp.surrogate_features(r, N) for r in reps])
     Y = np.array([pp.surrogate_targets(r, N) for r in reps])
-    sx, sy = X.std(0), Y.std(0)
-    norm = (X.mean(0), np.where(sx > 0, sx, 1.0), Y.mean(0), np.where(sy > 0, sy, 1.0))
+    norm = (X.mean(0), feature_scale(X), Y.mean(0), feature_scale(Y))
     net = pp.Mlp(norm=norm, lr=1e-3, max_batch=256)
     net.set_params(W.mlp_init_params(seed=22))
     xd = torch.from_numpy(X.astype(np.float32)).cuda()
     yd = torch.from_numpy(Y.astype(np.float32)).cuda()
-    for it in range(1500):
-        loss = net.train_step(xd, yd, want_loss=(it == 1499))
+    for it in range(adam_steps):
+        loss = net.train_step(xd, yd, want_loss=(it == adam_steps - 1))
     net.sync()
     t_train = time.perf_counter() - t0
-    runs = {}
-    # both runs FP64 (the surrogate-assisted run differs only in the period
-    # update; the FP32 pass kernels then time the large workload alone)
-    for mode, prec, periods in (("plain", "fp64", plain_periods), ("surrogate", "fp64", sur_periods)):
-        cfg, keep = pp.config_from_workload(wl, precision=prec, load=False)
-        ctx = pp.pic_init(cfg, keep)
-        if mode == "surrogate":
-            pp.pic_attach_surrogate(ctx, net, err_max=0.02, tol=1e-6, max_iter=50)
-        reps, times = periods_of(ctx, periods)
-        i = stationary(reps)
-        runs[mode] = dict(reps=reps, times=times, i=i, used=sum(r["sur_used"] for r in reps))
-        del ctx
-    x_ref = runs["plain"]["reps"][-1]["x"]
-    dev = float(np.linalg.norm(runs["surrogate"]["reps"][-1]["x"] - x_ref) / np.linalg.norm(x_ref))
-
-    def leg(m, prec):
-        r = runs[m]
+    def leg(r, prec):
         i = r["i"]
         return {"precision": prec, "periods": None if i is None else i + 1,
                 "wall_s": None if i is None else r["times"][i], "surrogate_periods": r["used"]}
 
+    out = []
+    for target in targets:
+        wl.circuit.p_target = target
+        runs = {}
+        # both runs FP64; the surrogate-assisted run differs only in the period update
+        for mode, periods in (("plain", plain_periods), ("surrogate", sur_periods)):
+            cfg, keep = pp.config_from_workload(wl, precision="fp64", load=False)
+            ctx = pp.pic_init(cfg, keep)
+            if mode == "surrogate":
+                pp.pic_attach_surrogate(ctx, net, err_max=0.02, tol=1e-6, max_iter=50)
+            reps, times = periods_of(ctx, periods)
+            runs[mode] = dict(reps=reps, times=times, i=stationary_index(reps, target),
+                              used=sum(r["sur_used"] for r in reps))
+            del ctx
+        x_ref = runs["plain"]["reps"][-1]["x"]
+        dev = float(np.linalg.norm(runs["surrogate"]["reps"][-1]["x"] - x_ref) / np.linalg.norm(x_ref))
+        final = {k: runs["plain"]["reps"][-1][k] for k in ("p_port", "p_cu", "p_ind", "p_cap", "eps_bal")}
+        out.append({"p_target_w": target, "plain_final_powers_w": final, "plain": leg(runs["plain"], "fp64"),
+                    "surrogate_assisted": leg(runs["surrogate"], "fp64"), "final_state_deviation": dev})
     return {"workload": f"{wl.name} coil cell without plasma, {wl.nr}x{wl.nz} cells, 13.56 MHz, 16 steps per RF "
-                        f"period, port power target {wl.circuit.p_target:g} W",
-            "criterion": "state change < 1 % per period and port power within 1 % of the target",
-            "plain": leg("plain", "fp64"), "surrogate_assisted": leg("surrogate", "fp64"),
-            "final_state_deviation": dev,
-            "training": {"pairs": len(X), "adam_steps": 1500, "final_loss": float(loss), "wall_s": t_train}}
+                        f"period, port power targets " + ", ".join(f"{t:g}" for t in targets) + " W",
+            "criterion": "first period from which, for 10 periods, the port power stays within 1 % of the target "
+                         "and the applied state within 1 % of its value at that period",
+            "runs": out,
+            "training": {"pairs": len(X), "adam_steps": adam_steps, "final_loss": float(loss), "wall_s": t_train}}
+
+
+def surrogate_mlp(batch=4096, steps=200, warmup=20):
+    """The surrogate network's kernels at their training configuration: MLP
+    29-256-256-256-20 (GELU; BF16 operands, FP32 accumulation on MFMA),
+    batch 4096, Adam lr 1e-3.  Forward alone, then whole training steps
+    (forward, MSE backward, Adam), timed with HIP events on the stream the
+    network runs on (torch's current stream, fixed at its creation).
+    FLOPs are those of the unpadded layer shapes: forward 2 B sum(in x out);
+    a training step adds the weight gradients (as many) and the activation
+    gradients of every layer but the first."""
+    import torch
+    import paper_2609_15043_amd.phasorpic as pp
+    from paper_2609_15043_amd import workloads as W
+    dims = [W.MLP_IN, W.MLP_HIDDEN, W.MLP_HIDDEN, W.MLP_HIDDEN, W.MLP_OUT]
+    macs = [a * b for a, b in zip(dims[:-1], dims[1:])]
+    fwd_flop = 2.0 * batch * sum(macs)
+    train_flop = 2.0 * fwd_flop + 2.0 * batch * sum(macs[1:])
+    net = pp.Mlp(max_batch=batch, lr=1e-3)
+    net.set_params(W.mlp_init_params(seed=22))
+    g = torch.Generator().manual_seed(23)
+    x = torch.randn(batch, W.MLP_IN, generator=g).cuda()
+    t = torch.randn(batch, W.MLP_OUT, generator=g).cuda()
+    y = torch.empty(batch, W.MLP_OUT, device="cuda")
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    fwd_ms = timed(lambda: net.forward(x, y))
+    train_ms = timed(lambda: net.train_step(x, t, want_loss=False))
+    net.sync()
+    tf = train_flop / (train_ms * 1e-3) / 1e12
+    return {"model": "MLP 29-256-256-256-20, GELU, BF16 MFMA with FP32 accumulation, Adam lr 1e-3",
+            "batch": batch, "steps": steps,
+            "forward": {"ms": fwd_ms, "gflop": fwd_flop / 1e9, "tflops": fwd_flop / (fwd_ms * 1e-3) / 1e12},
+            "train_step": {"ms": train_ms, "gflop": train_flop / 1e9, "tflops": tf},
+            "roofline": {"bound": "mfma", "achieved": tf, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": tf / BF16_PEAK_TFLOPS, "kernel": "whole training step (11 products + GELU, "
+                                                               "loss and Adam kernels)"}}
 
 
 def cpu_baseline(name, scale, nsteps):
@@ -258,6 +326,7 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=400)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stationary", action="store_true", help="skip the wall-seconds-to-stationary leg")
+    ap.add_argument("--no-mlp", action="store_true", help="skip the surrogate network's kernel timing")
     ap.add_argument("--cpu-scale", type=int, default=4)
     ap.add_argument("--cpu-steps", type=int, default=15)
     ap.add_argument("--split", action="store_true", help="unfused pass (parity-isolation mode)")
@@ -321,13 +390,21 @@ def main():
     step_gbs = step_bytes / (r["ms_per_step"] * 1e-3) / 1e9
     step_hbm = {"achieved": step_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": step_gbs / HBM_PEAK_GBS,
                 "bytes_per_step": step_bytes}
+    mlp = None
+    if not args.no_mlp:
+        mlp = surrogate_mlp()
+        print(f"[bench] surrogate MLP, batch {mlp['batch']}: forward {mlp['forward']['ms']:.3f} ms "
+              f"({mlp['forward']['tflops']:.1f} TFLOP/s), training step {mlp['train_step']['ms']:.3f} ms "
+              f"({mlp['train_step']['tflops']:.1f} TFLOP/s)", file=sys.stderr, flush=True)
     stat = None
     if not args.no_stationary:
         print("[bench] wall-s to stationary circuit: plain FP64 vs surrogate-assisted FP64", file=sys.stderr,
               flush=True)
         stat = stationary_circuit()
-        print(f"[bench] stationary: plain {stat['plain']}, surrogate {stat['surrogate_assisted']}, "
-              f"final deviation {stat['final_state_deviation']:.2e}", file=sys.stderr, flush=True)
+        for run in stat["runs"]:
+            print(f"[bench] stationary at {run['p_target_w']:g} W: plain {run['plain']}, surrogate "
+                  f"{run['surrogate_assisted']}, final deviation {run['final_state_deviation']:.2e}",
+                  file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu_baseline:
         print(f"[bench] cpu baseline: oracle on 1/{args.cpu_scale} of {wl.name}, {args.cpu_steps} steps",
@@ -340,7 +417,8 @@ def main():
         "config": {"workload": describe(wl, prec), "particles": r["mean_live"], "grid": [wl.nr, wl.nz],
                    "parallelism": "1 GPU", "sort_every": SORT_EVERY, "sort_every_ion": SORT_EVERY_ION,
                    "fused": not args.split},
-        "roofline": roofline, "step_hbm": step_hbm, "stationary_circuit": stat, "cpu_baseline": cpu,
+        "roofline": roofline, "step_hbm": step_hbm, "stationary_circuit": stat, "surrogate_mlp": mlp,
+        "cpu_baseline": cpu,
         "breakdown_ms": {"pass": r["pass_ms"], "poisson": r["poisson_ms"], "sort_per_species": r["sort_ms"],
                          "window_fallback_atomics": r["window_out"],
                          "species_sorts_per_step": r["sort_count"] / max(1, r["steps"]),

@@ -404,7 +404,11 @@ class FieldCircuit:
         |I_f|) fall back to the plain update; else iterate the relaxed
         network solve with loads yhat(x_i) + (y_n - yhat(x^n)) and a
         controller step on each iterate's port power, within the period's
-        step bounds, and apply the converged state."""
+        step bounds, and apply the converged state.  When max_iter iterates
+        pass without meeting tol, the state and amplitude applied are the
+        means of the iterates of the second half: the network's BF16
+        activations make the predicted loads a step function of the state,
+        so the iterates circle the fixed point instead of settling on it."""
         N = self.N
         x_n, vp, icap, pp, pcu, eps_bal = self._measure(h)
         vg_old = self.vg_amp
@@ -422,6 +426,7 @@ class FieldCircuit:
         it = 0
         ph = complex(math.cos(self.p.vg_phase), math.sin(self.p.vg_phase))
         loads = None
+        acc, vacc, navg = np.zeros_like(xi), 0.0, 0
         for it in range(1, max_iter + 1):
             l = np.asarray(predict(self.features(xi, pressure, moments)), dtype=np.float64) + corr
             lv = l[0:2 * N:2] + 1j * l[1:2 * N:2]
@@ -445,6 +450,13 @@ class FieldCircuit:
                 return rep
             if step < tol:
                 break
+            if it > max_iter // 2:
+                acc += xi
+                vacc += vgi
+                navg += 1
+        else:
+            if navg:
+                xi, vgi = acc / navg, vacc / navg
         self.x = xi
         self.vg_amp, self.vg = vgi, vgi * ph
         if self.ctrl is not None:

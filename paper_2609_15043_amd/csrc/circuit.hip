@@ -467,8 +467,12 @@ __global__ __launch_bounds__(64) void k_surrogate(CircuitDev *cdp, const float *
                 for (int r = 0; r < M; ++r) {
                     c.xi_re[r] = c.x_re[r];
                     c.xi_im[r] = c.x_im[r];
+                    c.xa_re[r] = 0.0;
+                    c.xa_im[r] = 0.0;
                 }
                 c.vg_iter = c.vg_amp;
+                c.vg_acc = 0.0;
+                c.sur_navg = 0;
             }
         } else if (stage == 1 && !c.sur_done) {
             mode = 1;
@@ -530,6 +534,17 @@ __global__ __launch_bounds__(64) void k_surrogate(CircuitDev *cdp, const float *
             c.sur_done = 1;
         }
         if (c.sur_step < c.sur_tol || c.sur_iters >= c.sur_max_iter) c.sur_done = 1;
+        // BF16 activations make the predicted loads a step function of the
+        // state: iterates that circle the fixed point instead of settling
+        // on it are averaged over the second half
+        if (c.sur_used == 1 && !(c.sur_step < c.sur_tol) && c.sur_iters > c.sur_max_iter / 2) {
+            for (int r = 0; r < M; ++r) {
+                c.xa_re[r] += c.xi_re[r];
+                c.xa_im[r] += c.xi_im[r];
+            }
+            c.vg_acc += c.vg_iter;
+            c.sur_navg += 1;
+        }
         return;
     }
     if (stage == 2 && c.sur_used == 2) {
@@ -547,11 +562,15 @@ __global__ __launch_bounds__(64) void k_surrogate(CircuitDev *cdp, const float *
         return;
     }
     if (stage == 2 && t == 0 && c.sur_used == 1) {
+        // the last iterate when it met the tolerance, else the mean of the
+        // second half's iterates
+        const bool mean = !(c.sur_step < c.sur_tol) && c.sur_navg > 0;
+        const double na = mean ? (double)c.sur_navg : 1.0;
         for (int r = 0; r < M; ++r) {
-            c.x_re[r] = c.xi_re[r];
-            c.x_im[r] = c.xi_im[r];
+            c.x_re[r] = mean ? c.xa_re[r] / na : c.xi_re[r];
+            c.x_im[r] = mean ? c.xa_im[r] / na : c.xi_im[r];
         }
-        c.vg_amp = c.vg_iter;
+        c.vg_amp = mean ? c.vg_acc / na : c.vg_iter;
         // the filter restarts from the port power of the new state
         c.pf_prev = 0.5 * (c.x_re[1 + N] * c.x_re[0] + c.x_im[1 + N] * c.x_im[0]);
         c.have_pf = 1;

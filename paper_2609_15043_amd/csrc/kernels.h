@@ -200,6 +200,11 @@ struct CircuitDev {
     double sur_corr[4 * MAX_TURNS];         // (V_p re, im) x N then (I_cap re, im) x N
     double xi_re[MAX_X], xi_im[MAX_X];      // inner iterate
     double vg_iter, sur_step;
+    // sums of the second half's iterates (applied as their mean when the
+    // inner iteration ends without meeting its tolerance)
+    double xa_re[MAX_X], xa_im[MAX_X];
+    double vg_acc;
+    int32_t sur_navg, pad2;
 };
 
 // features of the surrogate network: (I_k re, im), (V_k re, im), pressure,
