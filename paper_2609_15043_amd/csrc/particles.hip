@@ -533,6 +533,7 @@ __global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassArgs<T> a
         T aJ[4] = {0, 0, 0, 0}, aQ[4] = {0, 0, 0, 0};
         int absorbed_n = 0;
         uint32_t cand_bits = 0;
+        bool moved = false;   // a particle of the run changed cell (or was absorbed)
 #pragma unroll
         for (int k = 0; k < RUN; ++k) {
             if (PUSH && live[k]) {
@@ -625,7 +626,9 @@ __global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassArgs<T> a
                 }
                 absorbed_n += absorbed != 0;
                 live[k] = absorbed == 0;
-                cell[k] = live[k] ? in * g.nr + jn : -1;
+                const int32_t cn = live[k] ? in * g.nr + jn : -1;
+                moved |= cn != cell[k];
+                cell[k] = cn;
                 dr[k] = drn;
                 dz[k] = dzn;
                 vr[k] = vrn;
@@ -650,7 +653,9 @@ __global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassArgs<T> a
             }
         }
         if constexpr (PUSH) {
-            st4(a.p.cell + q0, cell);
+            // the cell array is written only where it changed: ions cross a
+            // cell edge every ~1e4 steps, electrons every ~20
+            if (moved) st4(a.p.cell + q0, cell);
             st4(a.p.dr + q0, dr);
             st4(a.p.dz + q0, dz);
             st4(a.p.vr + q0, vr);
