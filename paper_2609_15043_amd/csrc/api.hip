@@ -463,6 +463,7 @@ static void layout(pic_ctx &c, Carver &cv)
         const int64_t qc = std::min<int64_t>(f.capacity[s], (int64_t)(4.0 * expect + 16.0 * std::sqrt(expect + 1.0)) + 4096);
         c.cq[s].cap = (int32_t)qc;
         c.cq[s].idx = cv.take<int32_t>(qc);
+        c.cq[s].vel = cv.take<uint8_t>(3 * (size_t)qc * (c.mixed ? sizeof(float) : sizeof(double)));
         c.cq[s].count = cv.take<int32_t>(1);
     }
     c.ctl = cv.take<int64_t>(8);

@@ -104,6 +104,7 @@ template <typename T> struct Births {
 // into its particle arrays), filled by the streaming pass.
 struct CandQueue {
     int32_t *idx;
+    void *vel;         // the candidates' v_r, v_theta, v_z after the push (3 x cap, particle precision)
     int32_t *count;
     int32_t cap;
 };

@@ -684,9 +684,13 @@ __global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassArgs<T> a
                     s_cand[slot] = (int32_t)(q0 + k);
                 } else {
                     const int gs = atomicAdd(a.q.count, 1);
-                    if (gs < a.q.cap)
+                    if (gs < a.q.cap) {
+                        T *qv = static_cast<T *>(a.q.vel);
                         a.q.idx[gs] = (int32_t)(q0 + k);
-                    else
+                        qv[gs] = vr[k];
+                        qv[a.q.cap + gs] = vt[k];
+                        qv[2 * a.q.cap + gs] = vz[k];
+                    } else
                         atomicOr(a.err, (int)ERR_QUEUE_OVERFLOW);
                 }
                 ++slot;
@@ -715,11 +719,19 @@ __global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassArgs<T> a
         const int nc = min(s_ncand, CAND_LDS);
         if (tid == 0) s_qbase = nc ? atomicAdd(a.q.count, nc) : 0;
         __syncthreads();
+        // queue records: index and the velocity after the push (written by
+        // this block above, read back from L2), so that the collisions read
+        // them contiguously instead of from scattered particle slots
+        T *qv = static_cast<T *>(a.q.vel);
         for (int k = tid; k < nc; k += BLOCK) {
             const int gs = s_qbase + k;
-            if (gs < a.q.cap)
-                a.q.idx[gs] = s_cand[k];
-            else
+            if (gs < a.q.cap) {
+                const int32_t p = s_cand[k];
+                a.q.idx[gs] = p;
+                qv[gs] = a.p.vr[p];
+                qv[a.q.cap + gs] = a.p.vt[p];
+                qv[2 * a.q.cap + gs] = a.p.vz[p];
+            } else
                 atomicOr(a.err, (int)ERR_QUEUE_OVERFLOW);
         }
     }
@@ -766,9 +778,10 @@ __global__ __launch_bounds__(256) void k_collide(PassArgs<T> a)
     T vr = 0, vt = 0, vz = 0;
     int32_t next = 0;
     if (act) {
-        vr = a.p.vr[p];
-        vt = a.p.vt[p];
-        vz = a.p.vz[p];
+        const T *qv = static_cast<const T *>(a.q.vel);
+        vr = qv[t];
+        vt = qv[a.q.cap + t];
+        vz = qv[2 * a.q.cap + t];
         ev = collide<T>(a.mc, s, a.p.id[p], a.step, vr, vt, vz, next, over, born, ve, vi, nb);
         if (ev >= 0) {   // a null collision leaves the velocity as it is
             a.p.vr[p] = vr;
