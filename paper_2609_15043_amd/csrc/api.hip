@@ -51,7 +51,7 @@ template <typename T> void carve_parts(Carver &c, Parts<T> &p, int64_t cap)
 template <typename T> void carve_births(Carver &c, Births<T> &b, int cap)
 {
     b.parent = c.take<uint32_t>(cap);
-    b.sorted = c.take<uint32_t>(cap);
+    b.rank = c.take<int32_t>(cap);
     b.cell = c.take<int32_t>(cap);
     b.dr = c.take<T>(cap);
     b.dz = c.take<T>(cap);
@@ -1137,6 +1137,7 @@ template <typename T> static pic_status init_impl(pic_ctx &c)
     HIPCHK(&c, hipMemsetAsync(c.errw, 0, sizeof(int32_t), st));
     HIPCHK(&c, hipMemsetAsync(c.hist, 0, (c.g.ncells + 1) * sizeof(int32_t), st));
     HIPCHK(&c, hipMemsetAsync(births<T>(c).count, 0, sizeof(int32_t), st));
+    HIPCHK(&c, hipMemsetAsync(births<T>(c).rank, 0, (size_t)births<T>(c).cap * sizeof(int32_t), st));
     for (int s2 = 0; s2 < 2; ++s2) HIPCHK(&c, hipMemsetAsync(c.cq[s2].count, 0, sizeof(int32_t), st));
     HIPCHK(&c, hipMemsetAsync(c.accS, 0, 2 * (size_t)nodes * sizeof(double), st));
     HIPCHK(&c, hipMemsetAsync(c.phi, 0, nodes * sizeof(double), st));

@@ -90,7 +90,7 @@ struct MccC {
 // Birth records (structure of arrays), one per ionization event.
 template <typename T> struct Births {
     uint32_t *parent;
-    uint32_t *sorted;  // parent ids sorted within chunks of BIRTH_CHUNK (ranking scratch)
+    int32_t *rank;     // ranks being counted (number of smaller parent ids); zero between steps
     int32_t *cell;
     T *dr, *dz;
     T *ve;             // 3 per record

@@ -831,36 +831,40 @@ __global__ void k_reset_count(int32_t *c) { *c = 0; }
 // Births: rank by parent id (ids then follow parent-id order, as in a
 // sequential sort), append to both species, deposit their charge.  A parent
 // ionizes at most once per step, so the ids are distinct and a birth's rank
-// is the number of smaller parent ids: each chunk of BIRTH_CHUNK records is
-// sorted in LDS (bitonic), then every record counts the smaller ids of each
-// sorted chunk by binary search.
+// is the number of smaller parent ids, counted against all of them: the ids
+// are cut into BIRTH_SLICES slices, each workgroup stages one slice in LDS
+// and adds its counts for 256 records to the rank array (every lane reads
+// the same LDS words, four ids at a time).
 // ---------------------------------------------------------------------------
-constexpr int BIRTH_CHUNK = 1024;
+constexpr int BIRTH_SLICES = 16;
+constexpr int BIRTH_STAGE = 4096;   // ids staged at a time (a longer slice loops)
 
-__global__ __launch_bounds__(256) void k_birth_sort(const uint32_t *parent, const int32_t *bcount, int cap,
-                                                    uint32_t *sorted)
+__global__ __launch_bounds__(256) void k_birth_rank(const uint32_t *parent, const int32_t *bcount, int cap,
+                                                    int32_t *rank)
 {
-    __shared__ uint32_t k[BIRTH_CHUNK];
+    __shared__ __attribute__((aligned(16))) uint32_t ids[BIRTH_STAGE];
     const int B = min(*bcount, cap);
-    const int c0 = blockIdx.x * BIRTH_CHUNK;
-    if (c0 >= B) return;
-    for (int e = threadIdx.x; e < BIRTH_CHUNK; e += 256) k[e] = c0 + e < B ? parent[c0 + e] : 0xFFFFFFFFu;
-    __syncthreads();
-    for (int size = 2; size <= BIRTH_CHUNK; size <<= 1)
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int e = threadIdx.x; e < BIRTH_CHUNK; e += 256) {
-                const int o = e ^ stride;
-                if (o > e) {
-                    const uint32_t a = k[e], b = k[o];
-                    if ((a > b) == ((e & size) == 0)) {
-                        k[e] = b;
-                        k[o] = a;
-                    }
-                }
-            }
-            __syncthreads();
+    if ((int)blockIdx.x * 256 >= B) return;
+    const int len = (B + BIRTH_SLICES - 1) / BIRTH_SLICES;
+    const int k0 = (int)blockIdx.y * len, k1 = min(B, k0 + len);
+    if (k0 >= k1) return;
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    const uint32_t mine = t < B ? parent[t] : 0u;
+    int cnt = 0;
+    for (int c0 = k0; c0 < k1; c0 += BIRTH_STAGE) {
+        const int n = min(BIRTH_STAGE, k1 - c0);
+        __syncthreads();
+        for (int e = threadIdx.x; e < n; e += 256) ids[e] = parent[c0 + e];
+        __syncthreads();
+        const uint4 *v4 = reinterpret_cast<const uint4 *>(ids);
+        const int n4 = n >> 2;
+        for (int e = 0; e < n4; ++e) {
+            const uint4 v = v4[e];
+            cnt += (int)(v.x < mine) + (int)(v.y < mine) + (int)(v.z < mine) + (int)(v.w < mine);
         }
-    for (int e = threadIdx.x; e < BIRTH_CHUNK && c0 + e < B; e += 256) sorted[c0 + e] = k[e];
+        for (int e = n4 << 2; e < n; ++e) cnt += (int)(ids[e] < mine);
+    }
+    if (t < B && cnt) atomicAdd(&rank[t], cnt);
 }
 
 template <typename T>
@@ -869,32 +873,11 @@ __global__ __launch_bounds__(256) void k_births(Births<T> b, Parts<T> pe, Parts<
                                                 long long *accQe, long long *accQi, int deposit, double qscale,
                                                 GridC g, int32_t *err)
 {
-    constexpr int STAGE = 8192;   // sorted ids staged in LDS up to this count
-    __shared__ uint32_t srt[STAGE];
     const int B = min(*b.count, b.cap);
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if ((int64_t)blockIdx.x * blockDim.x >= B) return;
-    const bool staged = B <= STAGE;
-    if (staged) {
-        for (int e = threadIdx.x; e < B; e += blockDim.x) srt[e] = b.sorted[e];
-        __syncthreads();
-    }
     if (t >= B) return;
-    const uint32_t *keys = staged ? srt : b.sorted;
-    const uint32_t mine = b.parent[t];
-    int rank = 0;
-    for (int c0 = 0; c0 < B; c0 += BIRTH_CHUNK) {
-        // smaller ids in sorted chunk [c0, c0 + len): lower bound of `mine`
-        int lo = 0, hi = min(BIRTH_CHUNK, B - c0);
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (keys[c0 + mid] < mine)
-                lo = mid + 1;
-            else
-                hi = mid;
-        }
-        rank += lo;
-    }
+    const int rank = b.rank[t];
+    b.rank[t] = 0;   // zero again for the next step
     const int64_t ne = count[0], ni = count[1];
     if (ne + B > cap_e || ni + B > cap_i) {
         atomicOr(err, (int)ERR_CAPACITY);
@@ -1261,8 +1244,8 @@ void launch_births(const Births<T> &b, const Parts<T> &pe, const Parts<T> &pi, i
                    int64_t cap_e, int64_t cap_i, long long *accQe, long long *accQi, bool deposit, double qscale,
                    const GridC &g, int32_t *err, unsigned long long *stats, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_birth_sort, dim3(blocks_for(b.cap, BIRTH_CHUNK)), dim3(256), 0, st, b.parent, b.count, b.cap,
-                       b.sorted);
+    hipLaunchKernelGGL(k_birth_rank, dim3(blocks_for(b.cap, 256), BIRTH_SLICES), dim3(256), 0, st, b.parent, b.count,
+                       b.cap, b.rank);
     hipLaunchKernelGGL(k_births<T>, dim3(blocks_for(b.cap, 256)), dim3(256), 0, st, b, pe, pi, count, next_id, cap_e,
                        cap_i, accQe, accQi, deposit ? 1 : 0, qscale, g, err);
     hipLaunchKernelGGL(k_births_commit, dim3(1), dim3(1), 0, st, b.count, b.cap, count, next_id, cap_e, cap_i, stats);
