@@ -937,10 +937,13 @@ __global__ void k_births_commit(int32_t *bcount, int32_t cap, int64_t *count, in
 // block of SORT_PER particles counts its cells in an LDS window of
 // SORT_WIN cells around its first particle and touches the global
 // histogram / cursors once per window cell it uses; particles outside the
-// window (births appended since the last sort) go to global atomics.
+// window (births appended since the last sort) go to global atomics.  The
+// window, [c - 512, c + 1536) around the block's first cell c, holds the
+// block's cells and a move of one row (256 cells at 256 radial cells) either
+// way.
 // ---------------------------------------------------------------------------
 constexpr int SORT_PER = 1024;
-constexpr int SORT_WIN = 4096;
+constexpr int SORT_WIN = 2048;
 #ifndef PIC_SORT_GROUPS
 #define PIC_SORT_GROUPS 4
 #endif
@@ -1062,28 +1065,52 @@ __global__ void k_scan_add(int32_t *cursor, int32_t *hist, int ncells, const int
     hist[i] = 0;
 }
 
+// Scatter of one block of SORT_PER particles.  The in-window particles are
+// staged in LDS in destination order (block-local scan of the window cells'
+// counts), so that consecutive lanes write consecutive slots of each cell's
+// reserved range and the stores fill whole lines: written in source order,
+// electrons that changed cell since the last sort left short runs in several
+// cells per store, and the scatter wrote 2.3x the bytes it moved.
 template <typename T>
 __global__ __launch_bounds__(256) void k_sort_scatter(Parts<T> src, Parts<T> dst, const int64_t *count_old,
                                                       int32_t *cursor, int ncells)
 {
     __shared__ int bins[SORT_WIN];
-    __shared__ int s_lo;
+    __shared__ int s_lo, s_wt[BLOCK / 64];
+    __shared__ int32_t sg_cell[SORT_PER], sg_next[SORT_PER];
+    __shared__ uint32_t sg_id[SORT_PER];
+    __shared__ T sg_dr[SORT_PER], sg_dz[SORT_PER], sg_vr[SORT_PER], sg_vt[SORT_PER], sg_vz[SORT_PER];
     constexpr int Q = SORT_PER / 256;
+    constexpr int BPT = SORT_WIN / 256;   // window cells per thread in the scan
     const int64_t n = *count_old;
     const int64_t p0 = (int64_t)blockIdx.x * SORT_PER;
     if (p0 >= n) return;
-    if (threadIdx.x == 0) s_lo = sort_window_lo(src.cell, p0, n, ncells);
-    for (int k = threadIdx.x; k < SORT_WIN; k += blockDim.x) bins[k] = 0;
+    const int tid = threadIdx.x, lane = lane_id();
+    if (tid == 0) s_lo = sort_window_lo(src.cell, p0, n, ncells);
+    for (int k = tid; k < SORT_WIN; k += blockDim.x) bins[k] = 0;
+    int32_t c[Q], nx[Q];
+    uint32_t id[Q];
+    T dr[Q], dz[Q], vr[Q], vt[Q], vz[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int64_t p = p0 + q * 256 + tid;
+        const bool in = p < n;
+        c[q] = in ? src.cell[p] : -1;
+        dr[q] = in ? src.dr[p] : (T)0;
+        dz[q] = in ? src.dz[p] : (T)0;
+        vr[q] = in ? src.vr[p] : (T)0;
+        vt[q] = in ? src.vt[p] : (T)0;
+        vz[q] = in ? src.vz[p] : (T)0;
+        id[q] = in ? src.id[p] : 0u;
+        nx[q] = in ? src.next[p] : 0;
+    }
     __syncthreads();
     const int lo = s_lo;
-    int32_t c[Q];
-    int64_t pos[Q];
+    int pos[Q];
     bool inwin[Q];
     // 1. offsets inside the block (window cells) or global positions (others)
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        const int64_t p = p0 + q * 256 + threadIdx.x;
-        c[q] = p < n ? src.cell[p] : -1;
         const bool live = c[q] >= 0 && c[q] < ncells;
         pos[q] = -1;
         inwin[q] = live && c[q] - lo >= 0 && c[q] - lo < SORT_WIN;
@@ -1094,7 +1121,7 @@ __global__ __launch_bounds__(256) void k_sort_scatter(Parts<T> src, Parts<T> dst
             const uint64_t mm = ballot(live && c[q] == k);
             if (__popcll(mm) < SORT_MIN_LANES) break;
             int b0 = 0;
-            if (lane_id() == lead) {
+            if (lane == lead) {
                 const int b = k - lo;
                 if (b >= 0 && b < SORT_WIN)
                     b0 = atomicAdd(&bins[b], (int)__popcll(mm));
@@ -1106,7 +1133,7 @@ __global__ __launch_bounds__(256) void k_sort_scatter(Parts<T> src, Parts<T> dst
                 pos[q] = b0 + __builtin_amdgcn_mbcnt_hi((uint32_t)(mm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mm, 0u));
             todo &= ~mm;
         }
-        if (todo >> lane_id() & 1ull) {
+        if (todo >> lane & 1ull) {
             // small groups: own reservation (offset in the window cell's
             // block-local count, or a global position outside the window)
             const int b = c[q] - lo;
@@ -1114,26 +1141,79 @@ __global__ __launch_bounds__(256) void k_sort_scatter(Parts<T> src, Parts<T> dst
         }
     }
     __syncthreads();
-    // 2. one global reservation per window cell the block uses
-    for (int k = threadIdx.x; k < SORT_WIN; k += blockDim.x) {
-        const int cnt = bins[k];
-        if (cnt) bins[k] = atomicAdd(&cursor[lo + k], cnt);
+    // 2. block-local exclusive scan of the window counts: bins = start
+    int cnt[BPT], start[BPT];
+    int sum = 0;
+#pragma unroll
+    for (int i = 0; i < BPT; ++i) {
+        cnt[i] = bins[tid * BPT + i];
+        start[i] = sum;
+        sum += cnt[i];
+    }
+    int pre = sum;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int v = __shfl_up(pre, off);
+        if (lane >= off) pre += v;
+    }
+    if (lane == 63) s_wt[tid >> 6] = pre;
+    __syncthreads();
+    int excl = pre - sum;
+    for (int w = 0; w < (tid >> 6); ++w) excl += s_wt[w];
+    int nin = 0;
+    for (int w = 0; w < BLOCK / 64; ++w) nin += s_wt[w];
+#pragma unroll
+    for (int i = 0; i < BPT; ++i) {
+        start[i] += excl;
+        bins[tid * BPT + i] = start[i];
     }
     __syncthreads();
-    // 3. move
+    // 3. stage the in-window particles in destination order; the others go
+    // to their global positions now
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         if (pos[q] < 0) continue;
-        const int64_t p = p0 + q * 256 + threadIdx.x;
-        const int64_t o = inwin[q] ? bins[c[q] - lo] + pos[q] : pos[q];
-        dst.cell[o] = c[q];
-        dst.dr[o] = src.dr[p];
-        dst.dz[o] = src.dz[p];
-        dst.vr[o] = src.vr[p];
-        dst.vt[o] = src.vt[p];
-        dst.vz[o] = src.vz[p];
-        dst.id[o] = src.id[p];
-        dst.next[o] = src.next[p];
+        if (inwin[q]) {
+            const int L = bins[c[q] - lo] + pos[q];
+            sg_cell[L] = c[q];
+            sg_dr[L] = dr[q];
+            sg_dz[L] = dz[q];
+            sg_vr[L] = vr[q];
+            sg_vt[L] = vt[q];
+            sg_vz[L] = vz[q];
+            sg_id[L] = id[q];
+            sg_next[L] = nx[q];
+        } else {
+            const int64_t o = pos[q];
+            dst.cell[o] = c[q];
+            dst.dr[o] = dr[q];
+            dst.dz[o] = dz[q];
+            dst.vr[o] = vr[q];
+            dst.vt[o] = vt[q];
+            dst.vz[o] = vz[q];
+            dst.id[o] = id[q];
+            dst.next[o] = nx[q];
+        }
+    }
+    __syncthreads();
+    // 4. one global reservation per window cell the block uses: bins = the
+    // cell's global base minus its local start
+#pragma unroll
+    for (int i = 0; i < BPT; ++i)
+        if (cnt[i]) bins[tid * BPT + i] = atomicAdd(&cursor[lo + tid * BPT + i], cnt[i]) - start[i];
+    __syncthreads();
+    // 5. move in destination order
+    for (int k = tid; k < nin; k += BLOCK) {
+        const int32_t cc = sg_cell[k];
+        const int64_t o = (int64_t)bins[cc - lo] + k;
+        dst.cell[o] = cc;
+        dst.dr[o] = sg_dr[k];
+        dst.dz[o] = sg_dz[k];
+        dst.vr[o] = sg_vr[k];
+        dst.vt[o] = sg_vt[k];
+        dst.vz[o] = sg_vz[k];
+        dst.id[o] = sg_id[k];
+        dst.next[o] = sg_next[k];
     }
 }
 
