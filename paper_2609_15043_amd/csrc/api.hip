@@ -69,7 +69,10 @@ struct HostLevel {
 };
 
 // largest level solved by its dense inverse (nodes)
-constexpr int BOTTOM_NODES = 2200;
+#ifndef PIC_BOTTOM_NODES
+#define PIC_BOTTOM_NODES 2200
+#endif
+constexpr int BOTTOM_NODES = PIC_BOTTOM_NODES;
 
 int64_t ceil_log2(double x)
 {
