@@ -67,18 +67,15 @@ __device__ __forceinline__ void neumaier(double &sum, double &comp, double x)
 }
 
 // ---------------------------------------------------------------------------
-// Per-step period accumulation (compensated FP64).  The last block to
-// finish reduces the inductive-power partials in block order and updates
+// Per-step period accumulation (compensated FP64).  A second one-block
+// kernel reduces the inductive-power partials in block order and updates
 // the turn sums, so the result does not depend on block scheduling.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_harmonic(const long long *accJ, double cj0, double cj1, const double *ec,
                                                   const double *es, double cs, double sn, double *I, double *Jc,
-                                                  double *Jcc, double *Js, double *Jsc, double *partial,
-                                                  HarmState *h, const double *Qk, const double *vc,
-                                                  const double *vs, int nturns, int nodes)
+                                                  double *Jcc, double *Js, double *Jsc, double *partial, int nodes)
 {
     __shared__ double red[256];
-    __shared__ bool last;
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     double pw = 0.0;
     if (n < nodes) {
@@ -101,18 +98,17 @@ __global__ __launch_bounds__(256) void k_harmonic(const long long *accJ, double 
         if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        partial[blockIdx.x] = red[0];
-        __threadfence();
-        const unsigned t = atomicAdd(&h->ticket, 1u);
-        last = t == gridDim.x - 1;
-    }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_harmonic_fold(const double *partial, int nparts, double cs, double sn,
+                                                       HarmState *h, const double *Qk, const double *vc,
+                                                       const double *vs, int nturns)
+{
+    __shared__ double red[256];
     {
         double acc = 0.0;
-        for (unsigned b = threadIdx.x; b < gridDim.x; b += 256) acc += partial[b];
+        for (int b = threadIdx.x; b < nparts; b += 256) acc += partial[b];
         red[threadIdx.x] = acc;
     }
     __syncthreads();
@@ -137,7 +133,6 @@ __global__ __launch_bounds__(256) void k_harmonic(const long long *accJ, double 
         h->q_prev[k] = q;
     }
     h->samples += 1;
-    h->ticket = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -625,8 +620,10 @@ void launch_harmonic(const long long *accJ, double cj0, double cj1, const double
                      HarmState *h, const double *Qk, const double *vc, const double *vs, int nturns, int nodes,
                      hipStream_t st)
 {
-    hipLaunchKernelGGL(k_harmonic, dim3(nblk(nodes, 256)), dim3(256), 0, st, accJ, cj0, cj1, ec, es, cs, sn, I, Jc,
-                       Jcc, Js, Jsc, partial, h, Qk, vc, vs, nturns, nodes);
+    const int nb = (int)nblk(nodes, 256);
+    hipLaunchKernelGGL(k_harmonic, dim3(nb), dim3(256), 0, st, accJ, cj0, cj1, ec, es, cs, sn, I, Jc, Jcc, Js, Jsc,
+                       partial, nodes);
+    hipLaunchKernelGGL(k_harmonic_fold, dim3(1), dim3(256), 0, st, partial, nb, cs, sn, h, Qk, vc, vs, nturns);
 }
 
 int harmonic_blocks(int nodes) { return (int)nblk(nodes, 256); }

@@ -162,8 +162,7 @@ struct MGState {
 constexpr int MAX_TURNS = 16;
 // Open-period accumulators (compensated sums: value + correction).
 struct HarmState {
-    uint32_t ticket;
-    int32_t samples;
+    int32_t samples, pad;
     double pind, pind_c;
     double qc[MAX_TURNS], qc_c[MAX_TURNS], qs[MAX_TURNS], qs_c[MAX_TURNS];
     double w[MAX_TURNS], w_c[MAX_TURNS];
