@@ -763,7 +763,7 @@ template <typename T> static void run_births(pic_ctx &c, bool deposit)
 {
     launch_births<T>(births<T>(c), parts<T>(c, 0, c.cur[0]), parts<T>(c, 1, c.cur[1]), c.ctl, c.ctl + 4,
                      c.cfg.capacity[0], c.cfg.capacity[1], c.accQ, c.accQ + c.g.nodes, deposit, c.qscale, c.g,
-                     c.errw, c.stats, c.stream);
+                     c.errw, c.stats, c.cq[0].count, c.cq[1].count, c.stream);
 }
 
 static void finalize_charge(pic_ctx &c)

@@ -825,8 +825,6 @@ __global__ __launch_bounds__(256) void k_collide(PassArgs<T> a)
     if (threadIdx.x < ST_NSTAT && sstat[threadIdx.x]) atomicAdd(&a.stats[threadIdx.x], sstat[threadIdx.x]);
 }
 
-__global__ void k_reset_count(int32_t *c) { *c = 0; }
-
 // ---------------------------------------------------------------------------
 // Births: rank by parent id (ids then follow parent-id order, as in a
 // sequential sort), append to both species, deposit their charge.  A parent
@@ -917,8 +915,10 @@ __global__ __launch_bounds__(256) void k_births(Births<T> b, Parts<T> pe, Parts<
     }
 }
 
+// Commit of the step's births, and the collision queues emptied for the
+// next pass (every push pass is followed by the collisions and this commit).
 __global__ void k_births_commit(int32_t *bcount, int32_t cap, int64_t *count, int64_t *next_id,
-                                int64_t cap_e, int64_t cap_i, unsigned long long *stats)
+                                int64_t cap_e, int64_t cap_i, unsigned long long *stats, int32_t *q0, int32_t *q1)
 {
     const int B = min(*bcount, cap);
     if (B > 0 && count[0] + B <= cap_e && count[1] + B <= cap_i) {
@@ -929,6 +929,8 @@ __global__ void k_births_commit(int32_t *bcount, int32_t cap, int64_t *count, in
         stats[ST_BIRTHS] += (unsigned long long)B;
     }
     *bcount = 0;
+    *q0 = 0;
+    *q1 = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1305,7 +1307,6 @@ template <typename T>
 void launch_pass(const PassArgs<T> &a, int64_t cap, bool push, bool depq, hipStream_t st)
 {
     const dim3 grid(blocks_for(cap, CHUNK)), blk(BLOCK);
-    if (push) hipLaunchKernelGGL(k_reset_count, dim3(1), dim3(1), 0, st, a.q.count);
     if (push && depq)
         hipLaunchKernelGGL((k_pass<T, true, true>), grid, blk, 0, st, a);
     else if (push)
@@ -1322,13 +1323,14 @@ template <typename T> void launch_collide(const PassArgs<T> &a, hipStream_t st)
 template <typename T>
 void launch_births(const Births<T> &b, const Parts<T> &pe, const Parts<T> &pi, int64_t *count, int64_t *next_id,
                    int64_t cap_e, int64_t cap_i, long long *accQe, long long *accQi, bool deposit, double qscale,
-                   const GridC &g, int32_t *err, unsigned long long *stats, hipStream_t st)
+                   const GridC &g, int32_t *err, unsigned long long *stats, int32_t *q0, int32_t *q1, hipStream_t st)
 {
     hipLaunchKernelGGL(k_birth_rank, dim3(blocks_for(b.cap, 256), BIRTH_SLICES), dim3(256), 0, st, b.parent, b.count,
                        b.cap, b.rank);
     hipLaunchKernelGGL(k_births<T>, dim3(blocks_for(b.cap, 256)), dim3(256), 0, st, b, pe, pi, count, next_id, cap_e,
                        cap_i, accQe, accQi, deposit ? 1 : 0, qscale, g, err);
-    hipLaunchKernelGGL(k_births_commit, dim3(1), dim3(1), 0, st, b.count, b.cap, count, next_id, cap_e, cap_i, stats);
+    hipLaunchKernelGGL(k_births_commit, dim3(1), dim3(1), 0, st, b.count, b.cap, count, next_id, cap_e, cap_i, stats,
+                       q0, q1);
 }
 
 template <typename T>
@@ -1357,7 +1359,7 @@ int sort_scan_blocks(int ncells) { return (int)blocks_for(ncells, SCAN_BLOCK); }
     template void launch_collide<T>(const PassArgs<T> &, hipStream_t);                                              \
     template void launch_births<T>(const Births<T> &, const Parts<T> &, const Parts<T> &, int64_t *, int64_t *,     \
                                    int64_t, int64_t, long long *, long long *, bool, double, const GridC &,         \
-                                   int32_t *, unsigned long long *, hipStream_t);                                   \
+                                   int32_t *, unsigned long long *, int32_t *, int32_t *, hipStream_t);             \
     template void launch_sort<T>(const Parts<T> &, const Parts<T> &, int64_t *, int64_t *, int32_t *, int32_t *,    \
                                  int64_t *, int, int64_t, hipStream_t);
 
