@@ -136,6 +136,46 @@ template <typename TA, typename TB, int EPI> __global__ __launch_bounds__(256) v
             }
 }
 
+// Products with a few rows (inference inside the surrogate-assisted period
+// update, batch 1): the tile kernel would stream K in eight dependent slices
+// for one useful row.  One workgroup per row stages the BF16 activations in
+// LDS as floats; each thread takes one output column and reads its weight
+// row (contiguous, W[n][k]) in 16-byte loads.  Products of BF16 values are
+// exact in FP32 and accumulate in FP32, as on the matrix cores (in another
+// order).  Same epilogues as k_gemm (GELU, linear).
+constexpr int GEMV_MAX_K = 1024;
+constexpr int GEMV_MAX_M = 8;
+template <int EPI> __global__ __launch_bounds__(256) void k_gemv(GemmArgs g)
+{
+    __shared__ float a[GEMV_MAX_K];
+    const int m = blockIdx.y;
+    const uint16_t *A = static_cast<const uint16_t *>(g.A);
+    for (int k = threadIdx.x; k < g.K; k += blockDim.x) a[k] = bf2f(A[(int64_t)m * g.sam + k]);
+    __syncthreads();
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= g.N) return;
+    const uint16_t *w = static_cast<const uint16_t *>(g.B) + (int64_t)n * g.sbn;
+    float acc = 0.f;
+    int k = 0;
+    for (; k + 8 <= g.K; k += 8) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(w + k);
+        const uint32_t q[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            acc += bf2f((uint16_t)(q[e] & 0xFFFFu)) * a[k + 2 * e];
+            acc += bf2f((uint16_t)(q[e] >> 16)) * a[k + 2 * e + 1];
+        }
+    }
+    for (; k < g.K; ++k) acc += bf2f(w[k]) * a[k];
+    if (EPI == EPI_GELU) {
+        const float z = acc + g.bias[n];
+        g.C[(int64_t)m * g.ldc + n] = z;
+        g.Abf[(int64_t)m * g.ldabf + n] = f2bf(gelu(z));
+    } else {
+        g.C[(int64_t)m * g.ldc + n] = acc + g.bias[n];
+    }
+}
+
 // sum of the K-split partials in split order
 __global__ void k_splitk_sum(const float *part, int splits, int64_t count, float *out)
 {
@@ -342,6 +382,15 @@ void mlp_layout(mlp_ctx &c, Carver &cv)
 
 template <typename TA, typename TB, int EPI> void gemm(mlp_ctx &c, GemmArgs g)
 {
+    // a few rows of a forward product (BF16 operands, weight rows contiguous
+    // and 16-byte aligned): one workgroup per row
+    if constexpr ((EPI == EPI_GELU || EPI == EPI_LINEAR) && sizeof(TA) == 2 && sizeof(TB) == 2) {
+        if (g.M <= GEMV_MAX_M && g.K <= GEMV_MAX_K && g.sak == 1 && g.sbk == 1 && g.sbn % 8 == 0 &&
+            reinterpret_cast<uintptr_t>(g.B) % 16 == 0) {
+            hipLaunchKernelGGL((k_gemv<EPI>), dim3(nb(g.N, 256), g.M), dim3(256), 0, c.stream, g);
+            return;
+        }
+    }
     dim3 grid(nb(g.N, TN), nb(g.M, TM), EPI == EPI_STORE ? g.ksplit : 1);
     hipLaunchKernelGGL((k_gemm<TA, TB, EPI>), grid, dim3(256), 0, c.stream, g);
 }

@@ -43,7 +43,7 @@ def _norm(x, t):
     return (x.mean(0), x.std(0), t.mean(0), t.std(0))
 
 
-@pytest.mark.parametrize("B", [4096, 37, 1])
+@pytest.mark.parametrize("B", [4096, 37, 5, 1])
 def test_forward_matches_oracle(B):
     _need_gpu()
     import torch
