@@ -334,8 +334,8 @@ def main():
                     help="also run one plain device copy of this many MiB (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the particle "
-              "decomposition across GPUs is a design, not built.", file=sys.stderr)
+        print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}); the particle decomposition "
+              "across GPUs is designed but not implemented.", file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():
