@@ -63,6 +63,38 @@ struct GemmArgs {
     int ksplit;            // EPI_STORE: number of K splits (grid.z); partial z at C + z * M * ldc
 };
 
+// Store of a wave's 32 x 32 accumulators (2 x 2 MFMA blocks) at (r0, c0)
+// with the fused epilogue.  D of a 16x16 block: lane l holds rows
+// 4 (l / 16) + r, column l % 16.
+template <int EPI> __device__ __forceinline__ void gemm_epilogue(const GemmArgs &g, const floatx4 (&acc)[2][2], int r0,
+                                                                 int c0, int lane)
+{
+    float *C = g.C;
+    if (EPI == EPI_STORE && g.ksplit > 1) C += (int64_t)blockIdx.z * g.M * g.ldc;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = r0 + 16 * i + 4 * (lane >> 4) + r;
+                const int col = c0 + 16 * j + (lane & 15);
+                if (row >= g.M || col >= g.N) continue;
+                const float v = acc[i][j][r];
+                if (EPI == EPI_GELU) {
+                    const float z = v + g.bias[col];
+                    C[(int64_t)row * g.ldc + col] = z;
+                    g.Abf[(int64_t)row * g.ldabf + col] = f2bf(gelu(z));
+                } else if (EPI == EPI_LINEAR) {
+                    C[(int64_t)row * g.ldc + col] = v + g.bias[col];
+                } else if (EPI == EPI_DGELU) {
+                    C[(int64_t)row * g.ldc + col] = v * gelu_grad(g.Zin[(int64_t)row * g.ldz + col]);
+                } else {
+                    C[(int64_t)row * g.ldc + col] = v;
+                }
+            }
+}
+
 template <typename TA, typename TB, int EPI> __global__ __launch_bounds__(256) void k_gemm(GemmArgs g)
 {
     __shared__ __attribute__((aligned(16))) uint16_t As[TM * KP];
@@ -109,31 +141,108 @@ template <typename TA, typename TB, int EPI> __global__ __launch_bounds__(256) v
         }
         __syncthreads();
     }
-    // D of a 16x16 block: lane l holds rows 4 (l / 16) + r, column l % 16
-    float *C = g.C;
-    if (EPI == EPI_STORE && g.ksplit > 1) C += (int64_t)blockIdx.z * g.M * g.ldc;
+    gemm_epilogue<EPI>(g, acc, m0 + wm, n0 + wn, lane);
+}
+
+// Tile kernel with vector staging, for operands contiguous along K (A: the
+// activations or the FP32 gradient; B: the weights, contiguous along K in
+// the forward products and along N in the activation gradients).  Each
+// thread moves 16-byte vectors (8 BF16 values; FP32 sources are rounded to
+// BF16 as in k_gemm), the K slice is VTK wide, and the next slice's loads
+// are issued before the current slice's products, so a hidden layer takes
+// two dependent memory round trips instead of eight.  Same products and
+// epilogues as k_gemm.
+constexpr int VTK = 128, VKP = VTK + 8;
+template <typename TA> __device__ __forceinline__ uint4 load8_bf(const TA *p);
+template <> __device__ __forceinline__ uint4 load8_bf<uint16_t>(const uint16_t *p)
+{
+    return *reinterpret_cast<const uint4 *>(p);
+}
+template <> __device__ __forceinline__ uint4 load8_bf<float>(const float *p)
+{
+    const float4 a = *reinterpret_cast<const float4 *>(p), b = *reinterpret_cast<const float4 *>(p + 4);
+    uint4 r;
+    r.x = (uint32_t)f2bf(a.x) | ((uint32_t)f2bf(a.y) << 16);
+    r.y = (uint32_t)f2bf(a.z) | ((uint32_t)f2bf(a.w) << 16);
+    r.z = (uint32_t)f2bf(b.x) | ((uint32_t)f2bf(b.y) << 16);
+    r.w = (uint32_t)f2bf(b.z) | ((uint32_t)f2bf(b.w) << 16);
+    return r;
+}
+
+template <typename TA, int EPI, bool BK> __global__ __launch_bounds__(256) void k_gemm_v(GemmArgs g)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t As[TM * VKP];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[TN * VKP];
+    constexpr int NV = TM * VTK / 8 / 256;   // vectors per thread and operand
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    const TA *A = static_cast<const TA *>(g.A);
+    const uint16_t *B = static_cast<const uint16_t *>(g.B);
+    const uint4 zero{0u, 0u, 0u, 0u};
+    uint4 ra[NV], rb[NV];
+    auto load = [&](int k0) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+        for (int v = 0; v < NV; ++v) {
+            const int e = t + 256 * v;
+            const int r = e / (VTK / 8), k8 = (e % (VTK / 8)) * 8;
+            const int m = m0 + r, k = k0 + k8;
+            ra[v] = (m < g.M && k < g.K) ? load8_bf<TA>(A + (int64_t)m * g.sam + k) : zero;
+            if (BK) {
+                const int n = n0 + r;
+                rb[v] = (n < g.N && k < g.K) ? load8_bf<uint16_t>(B + (int64_t)n * g.sbn + k) : zero;
+            } else {
+                const int kk = e / (TN / 8), n8 = (e % (TN / 8)) * 8;
+                const int n = n0 + n8, kb = k0 + kk;
+                rb[v] = (n < g.N && kb < g.K) ? load8_bf<uint16_t>(B + (int64_t)kb * g.sbk + n) : zero;
+            }
+        }
+    };
+    auto store = [&]() {
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int v = 0; v < NV; ++v) {
+            const int e = t + 256 * v;
+            const int r = e / (VTK / 8), k8 = (e % (VTK / 8)) * 8;
+            *reinterpret_cast<uint4 *>(&As[r * VKP + k8]) = ra[v];
+            if (BK) {
+                *reinterpret_cast<uint4 *>(&Bs[r * VKP + k8]) = rb[v];
+            } else {
+                const int kk = e / (TN / 8), n8 = (e % (TN / 8)) * 8;
+                const uint32_t w[4] = {rb[v].x, rb[v].y, rb[v].z, rb[v].w};
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
-                const int col = n0 + wn + 16 * j + (lane & 15);
-                if (row >= g.M || col >= g.N) continue;
-                const float v = acc[i][j][r];
-                if (EPI == EPI_GELU) {
-                    const float z = v + g.bias[col];
-                    C[(int64_t)row * g.ldc + col] = z;
-                    g.Abf[(int64_t)row * g.ldabf + col] = f2bf(gelu(z));
-                } else if (EPI == EPI_LINEAR) {
-                    C[(int64_t)row * g.ldc + col] = v + g.bias[col];
-                } else if (EPI == EPI_DGELU) {
-                    C[(int64_t)row * g.ldc + col] = v * gelu_grad(g.Zin[(int64_t)row * g.ldz + col]);
-                } else {
-                    C[(int64_t)row * g.ldc + col] = v;
+                for (int q = 0; q < 4; ++q) {
+                    Bs[(n8 + 2 * q) * VKP + kk] = (uint16_t)(w[q] & 0xFFFFu);
+                    Bs[(n8 + 2 * q + 1) * VKP + kk] = (uint16_t)(w[q] >> 16);
                 }
             }
+        }
+    };
+    floatx4 acc[2][2];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    load(0);
+    for (int k0 = 0; k0 < g.K; k0 += VTK) {
+        store();
+        __syncthreads();
+        if (k0 + VTK < g.K) load(k0 + VTK);
+        const int kend = g.K - k0;   // K blocks past the end hold zeros only
+#pragma unroll
+        for (int kk = 0; kk < VTK; kk += 16) {
+            if (kk >= kend) break;
+            bf16x4 a[2], b[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                a[i] = *reinterpret_cast<const bf16x4 *>(&As[(wm + 16 * i + (lane & 15)) * VKP + kk + 4 * (lane >> 4)]);
+                b[i] = *reinterpret_cast<const bf16x4 *>(&Bs[(wn + 16 * i + (lane & 15)) * VKP + kk + 4 * (lane >> 4)]);
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    gemm_epilogue<EPI>(g, acc, m0 + wm, n0 + wn, lane);
 }
 
 // Products with a few rows (inference inside the surrogate-assisted period
@@ -388,6 +497,21 @@ template <typename TA, typename TB, int EPI> void gemm(mlp_ctx &c, GemmArgs g)
         if (g.M <= GEMV_MAX_M && g.K <= GEMV_MAX_K && g.sak == 1 && g.sbk == 1 && g.sbn % 8 == 0 &&
             reinterpret_cast<uintptr_t>(g.B) % 16 == 0) {
             hipLaunchKernelGGL((k_gemv<EPI>), dim3(nb(g.N, 256), g.M), dim3(256), 0, c.stream, g);
+            return;
+        }
+    }
+    // operands contiguous along K (B along K or N), 16-byte aligned rows
+    if constexpr (EPI != EPI_STORE && sizeof(TB) == 2) {
+        const bool a_ok = g.sak == 1 && g.K % 8 == 0 && (g.sam * (int64_t)sizeof(TA)) % 16 == 0 &&
+                          reinterpret_cast<uintptr_t>(g.A) % 16 == 0;
+        const bool b_ok = reinterpret_cast<uintptr_t>(g.B) % 16 == 0;
+        const dim3 grid(nb(g.N, TN), nb(g.M, TM));
+        if (a_ok && b_ok && g.sbk == 1 && (g.sbn * 2) % 16 == 0) {
+            hipLaunchKernelGGL((k_gemm_v<TA, EPI, true>), grid, dim3(256), 0, c.stream, g);
+            return;
+        }
+        if (a_ok && b_ok && g.sbn == 1 && g.N % 8 == 0 && (g.sbk * 2) % 16 == 0) {
+            hipLaunchKernelGGL((k_gemm_v<TA, EPI, false>), grid, dim3(256), 0, c.stream, g);
             return;
         }
     }
