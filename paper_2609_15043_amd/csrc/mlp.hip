@@ -169,7 +169,7 @@ template <> __device__ __forceinline__ uint4 load8_bf<float>(const float *p)
     return r;
 }
 
-template <typename TA, int EPI, bool BK> __global__ __launch_bounds__(256) void k_gemm_v(GemmArgs g)
+template <typename TA, int EPI, bool AK, bool BK> __global__ __launch_bounds__(256) void k_gemm_v(GemmArgs g)
 {
     __shared__ __attribute__((aligned(16))) uint16_t As[TM * VKP];
     __shared__ __attribute__((aligned(16))) uint16_t Bs[TN * VKP];
@@ -180,21 +180,35 @@ template <typename TA, int EPI, bool BK> __global__ __launch_bounds__(256) void 
     const TA *A = static_cast<const TA *>(g.A);
     const uint16_t *B = static_cast<const uint16_t *>(g.B);
     const uint4 zero{0u, 0u, 0u, 0u};
+    // K range: the whole of K, or this block's split of it
+    int kb = 0, ke = g.K;
+    if (EPI == EPI_STORE && g.ksplit > 1) {
+        const int per = (g.K + g.ksplit - 1) / g.ksplit;
+        kb = blockIdx.z * per;
+        ke = min(g.K, kb + per);
+    }
     uint4 ra[NV], rb[NV];
     auto load = [&](int k0) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             const int e = t + 256 * v;
-            const int r = e / (VTK / 8), k8 = (e % (VTK / 8)) * 8;
-            const int m = m0 + r, k = k0 + k8;
-            ra[v] = (m < g.M && k < g.K) ? load8_bf<TA>(A + (int64_t)m * g.sam + k) : zero;
+            if (AK) {
+                const int r = e / (VTK / 8), k8 = (e % (VTK / 8)) * 8;
+                const int m = m0 + r, k = k0 + k8;
+                ra[v] = (m < g.M && k < ke) ? load8_bf<TA>(A + (int64_t)m * g.sam + k) : zero;
+            } else {
+                const int kk = e / (TM / 8), m8 = (e % (TM / 8)) * 8;
+                const int m = m0 + m8, k = k0 + kk;
+                ra[v] = (m < g.M && k < ke) ? load8_bf<TA>(A + (int64_t)k * g.sak + m) : zero;
+            }
             if (BK) {
-                const int n = n0 + r;
-                rb[v] = (n < g.N && k < g.K) ? load8_bf<uint16_t>(B + (int64_t)n * g.sbn + k) : zero;
+                const int r = e / (VTK / 8), k8 = (e % (VTK / 8)) * 8;
+                const int n = n0 + r, k = k0 + k8;
+                rb[v] = (n < g.N && k < ke) ? load8_bf<uint16_t>(B + (int64_t)n * g.sbn + k) : zero;
             } else {
                 const int kk = e / (TN / 8), n8 = (e % (TN / 8)) * 8;
-                const int n = n0 + n8, kb = k0 + kk;
-                rb[v] = (n < g.N && kb < g.K) ? load8_bf<uint16_t>(B + (int64_t)kb * g.sbk + n) : zero;
+                const int n = n0 + n8, k = k0 + kk;
+                rb[v] = (n < g.N && k < ke) ? load8_bf<uint16_t>(B + (int64_t)k * g.sbk + n) : zero;
             }
         }
     };
@@ -203,7 +217,17 @@ template <typename TA, int EPI, bool BK> __global__ __launch_bounds__(256) void 
         for (int v = 0; v < NV; ++v) {
             const int e = t + 256 * v;
             const int r = e / (VTK / 8), k8 = (e % (VTK / 8)) * 8;
-            *reinterpret_cast<uint4 *>(&As[r * VKP + k8]) = ra[v];
+            if (AK) {
+                *reinterpret_cast<uint4 *>(&As[r * VKP + k8]) = ra[v];
+            } else {
+                const int kk = e / (TM / 8), m8 = (e % (TM / 8)) * 8;
+                const uint32_t w[4] = {ra[v].x, ra[v].y, ra[v].z, ra[v].w};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    As[(m8 + 2 * q) * VKP + kk] = (uint16_t)(w[q] & 0xFFFFu);
+                    As[(m8 + 2 * q + 1) * VKP + kk] = (uint16_t)(w[q] >> 16);
+                }
+            }
             if (BK) {
                 *reinterpret_cast<uint4 *>(&Bs[r * VKP + k8]) = rb[v];
             } else {
@@ -220,12 +244,12 @@ template <typename TA, int EPI, bool BK> __global__ __launch_bounds__(256) void 
     floatx4 acc[2][2];
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-    load(0);
-    for (int k0 = 0; k0 < g.K; k0 += VTK) {
+    load(kb);
+    for (int k0 = kb; k0 < ke; k0 += VTK) {
         store();
         __syncthreads();
-        if (k0 + VTK < g.K) load(k0 + VTK);
-        const int kend = g.K - k0;   // K blocks past the end hold zeros only
+        if (k0 + VTK < ke) load(k0 + VTK);
+        const int kend = ke - k0;   // K blocks past the end hold zeros only
 #pragma unroll
         for (int kk = 0; kk < VTK; kk += 16) {
             if (kk >= kend) break;
@@ -500,18 +524,25 @@ template <typename TA, typename TB, int EPI> void gemm(mlp_ctx &c, GemmArgs g)
             return;
         }
     }
-    // operands contiguous along K (B along K or N), 16-byte aligned rows
-    if constexpr (EPI != EPI_STORE && sizeof(TB) == 2) {
-        const bool a_ok = g.sak == 1 && g.K % 8 == 0 && (g.sam * (int64_t)sizeof(TA)) % 16 == 0 &&
-                          reinterpret_cast<uintptr_t>(g.A) % 16 == 0;
-        const bool b_ok = reinterpret_cast<uintptr_t>(g.B) % 16 == 0;
-        const dim3 grid(nb(g.N, TN), nb(g.M, TM));
-        if (a_ok && b_ok && g.sbk == 1 && (g.sbn * 2) % 16 == 0) {
-            hipLaunchKernelGGL((k_gemm_v<TA, EPI, true>), grid, dim3(256), 0, c.stream, g);
+    // vector staging: each operand contiguous along K or along its other
+    // dimension (multiple of 8), rows 16-byte aligned
+    if constexpr (sizeof(TB) == 2) {
+        const bool al = reinterpret_cast<uintptr_t>(g.A) % 16 == 0 && reinterpret_cast<uintptr_t>(g.B) % 16 == 0;
+        const bool ak = g.sak == 1 && g.K % 8 == 0 && (g.sam * (int64_t)sizeof(TA)) % 16 == 0;
+        const bool am = g.sam == 1 && g.M % 8 == 0 && (g.sak * (int64_t)sizeof(TA)) % 16 == 0;
+        const bool bk = g.sbk == 1 && g.K % 8 == 0 && (g.sbn * 2) % 16 == 0;
+        const bool bn = g.sbn == 1 && g.N % 8 == 0 && (g.sbk * 2) % 16 == 0;
+        const dim3 grid(nb(g.N, TN), nb(g.M, TM), EPI == EPI_STORE ? g.ksplit : 1);
+        if (al && ak && bk) {
+            hipLaunchKernelGGL((k_gemm_v<TA, EPI, true, true>), grid, dim3(256), 0, c.stream, g);
             return;
         }
-        if (a_ok && b_ok && g.sbn == 1 && g.N % 8 == 0 && (g.sbk * 2) % 16 == 0) {
-            hipLaunchKernelGGL((k_gemm_v<TA, EPI, false>), grid, dim3(256), 0, c.stream, g);
+        if (al && ak && bn) {
+            hipLaunchKernelGGL((k_gemm_v<TA, EPI, true, false>), grid, dim3(256), 0, c.stream, g);
+            return;
+        }
+        if (al && am && bn) {
+            hipLaunchKernelGGL((k_gemm_v<TA, EPI, false, false>), grid, dim3(256), 0, c.stream, g);
             return;
         }
     }
