@@ -465,6 +465,27 @@ __global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassArgs<T> a
     const int s = a.sc.s;
     if (tid == 0) s_ncand = 0;
 
+    const int64_t wbase = c0 + (int64_t)(tid >> 6) * (RUN * RUNS * 64);
+    int32_t cell[RUN], nxt[RUN];
+    T dr[RUN], dz[RUN], vr[RUN], vt[RUN], vz[RUN];
+    // a run's particles; the next run's loads are issued right after this
+    // run's stores (its registers are free then), so that their latency
+    // overlaps this run's deposit reductions
+    auto load_run = [&](int64_t q) {
+        ld4(a.p.cell + q, cell);
+        ld4(a.p.dr + q, dr);
+        ld4(a.p.dz + q, dz);
+        if (PUSH) {
+            ld4(a.p.vr + q, vr);
+            ld4(a.p.vt + q, vt);
+            ld4(a.p.vz + q, vz);
+            ld4(a.p.next + q, nxt);
+        }
+    };
+    // the first run's loads do not depend on the window: issued first, their
+    // latency overlaps the window set-up below
+    load_run(wbase + RUN * lane);
+
     if (tid < 64) {
         // window centre: mean row of 64 particles sampled across the chunk
         // (one hot particle far from the rest cannot shift it by much)
@@ -504,24 +525,6 @@ __global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassArgs<T> a
     const T jscale = (T)a.sc.jscale, qscale = (T)a.sc.qscale;   // powers of two
     int nout = 0;   // this lane's deposits outside the window
 
-    const int64_t wbase = c0 + (int64_t)(tid >> 6) * (RUN * RUNS * 64);
-    int32_t cell[RUN], nxt[RUN];
-    T dr[RUN], dz[RUN], vr[RUN], vt[RUN], vz[RUN];
-    // a run's particles; the next run's loads are issued right after this
-    // run's stores (its registers are free then), so that their latency
-    // overlaps this run's deposit reductions
-    auto load_run = [&](int64_t q) {
-        ld4(a.p.cell + q, cell);
-        ld4(a.p.dr + q, dr);
-        ld4(a.p.dz + q, dz);
-        if (PUSH) {
-            ld4(a.p.vr + q, vr);
-            ld4(a.p.vt + q, vt);
-            ld4(a.p.vz + q, vz);
-            ld4(a.p.next + q, nxt);
-        }
-    };
-    load_run(wbase + RUN * lane);
     for (int r = 0; r < RUNS; ++r) {
         const int64_t q0 = wbase + (int64_t)r * (RUN * 64) + RUN * lane;
         bool live[RUN];
