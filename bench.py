@@ -372,7 +372,9 @@ def main():
         other = {"precision": p2, "value": r2["rate"], "unit": "particle-steps/s",
                  "ms_per_step": r2["ms_per_step"], "steps": r2["steps"],
                  "pass_ms": r2["pass_ms"], "pass_hbm_frac": bpp2 * r2["mean_live"] / (r2["pass_ms"] * 1e-3) / 1e9
-                 / HBM_PEAK_GBS}
+                 / HBM_PEAK_GBS,
+                 # counter-measured HBM bytes of one pass launch (committed summary), or None
+                 "pass_traffic": measured_traffic(wl.name, p2, r2["mean_live"] / 2.0)}
     bpp = BYTES_PER_PARTICLE_STEP[prec]
     # one launch moves one species: half of the live particles on average
     launch_bytes = bpp * r["mean_live"] / 2
