@@ -285,7 +285,10 @@ typedef struct pic_period_report {
  * iterates x_{i+1} = relax(network(yhat(x_i) + y_n - yhat(x^n), V_g,i)),
  * with the controller acting on each iterate's port power inside the
  * period's step bounds, until the relative step is below tol or max_iter,
- * and the converged state is applied. */
+ * and the converged state is applied.  When max_iter iterates pass without
+ * meeting tol, the state and source amplitude applied are the means of the
+ * iterates of the second half (the BF16 activations make the predictions a
+ * step function of the state, so the iterates circle the fixed point). */
 typedef struct pic_surrogate_config {
     double err_max;          /* e.g. 0.02 */
     double tol;              /* e.g. 1e-6 */
