@@ -4,11 +4,13 @@ python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload large|cell|small
                 [--precision mixed|fp64] [--fp64-steps K64] [--no-cpu-baseline] [--no-stationary] [--no-mlp]
 
 A step is one pass of the whole per-step cycle through the C ABI:
-pic_gather_push (stage + sort every 16 steps + fused gather/push/MCC/deposit
-pass), harmonic_accumulate, mcc_collide (births), pic_deposit (node
+pic_gather_push (stage + sort by cell, electrons every 16 steps and ions
+every 32 + fused gather/push/MCC/deposit pass), harmonic_accumulate, mcc_collide (births), pic_deposit (node
 charge), circuit_period_update at every closed RF period, and
 poisson_solve_rz (FP64 multigrid + turn charges).  Inputs are resident in
-HBM before the timed region starts.  Prints one JSON line.
+HBM before the timed region starts.  By default two RF periods (4000 steps,
+two circuit updates) of the large workload in each precision.  Prints one
+JSON line.
 """
 import argparse
 import json
@@ -319,11 +321,11 @@ def cpu_baseline(name, scale, nsteps):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--steps", type=int, default=4000)   # two RF periods of the large workload
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="large")
     ap.add_argument("--precision", default="mixed")
-    ap.add_argument("--fp64-steps", type=int, default=400)
+    ap.add_argument("--fp64-steps", type=int, default=4000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stationary", action="store_true", help="skip the wall-seconds-to-stationary leg")
     ap.add_argument("--no-mlp", action="store_true", help="skip the surrogate network's kernel timing")

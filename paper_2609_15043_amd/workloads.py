@@ -144,7 +144,7 @@ class Workload:
     circuit: CircuitParams = None     # None: prescribed E_theta and turn potentials
     bfield: tuple = (0.0, 0.0, 0.0)   # uniform (B_r, B_theta, B_z), tests only
     xs: CrossSections = dataclasses.field(default_factory=CrossSections)
-    capacity_factor: float = 1.25
+    capacity_factor: float = 1.5
 
     # derived, descriptive only
     @property
