@@ -126,6 +126,13 @@ template <typename T> struct PassArgs {
     int32_t step;
 };
 
+// Both species' arguments of the streaming pass, launched as one grid whose
+// first nb0 blocks take the electrons' chunks.
+template <typename T> struct PassPair {
+    PassArgs<T> a[2];
+    int32_t nb0;
+};
+
 // One multigrid level (device arrays).  Level 0 is the 5-point finite-
 // volume operator (A x)_p = cc x_p - cw x_W - ce x_E - cs x_S - cn x_N; the
 // coarser levels are Galerkin products P^T A P with 9-point stencils

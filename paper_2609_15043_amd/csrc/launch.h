@@ -21,7 +21,8 @@ void launch_unplace(const Parts<T> &p, const int64_t *count, int64_t cap, const 
 void launch_count_live(const int32_t *cell, const int64_t *count, unsigned long long *out, hipStream_t st);
 void launch_live_index(const int32_t *cell, const int64_t *count, int64_t *index, int64_t *nlive, hipStream_t st);
 template <typename T>
-void launch_pass(const PassArgs<T> &a, int64_t cap, bool push, bool depq, hipStream_t st);
+void launch_pass(const PassArgs<T> &e, const PassArgs<T> &i, int64_t cap_e, int64_t cap_i, bool push, bool depq,
+                 hipStream_t st);
 template <typename T> void launch_collide(const PassArgs<T> &a, hipStream_t st);
 template <typename T>
 void launch_births(const Births<T> &b, const Parts<T> &pe, const Parts<T> &pi, int64_t *count, int64_t *next_id,

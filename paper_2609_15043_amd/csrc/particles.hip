@@ -439,8 +439,14 @@ template <typename T> struct PassOcc {
 };
 #define PIC_PASS_OCCUPANCY __attribute__((amdgpu_waves_per_eu(PassOcc<T>::min_waves, 8)))
 template <typename T, bool PUSH, bool DEPQ>
-__global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassArgs<T> a)
+__global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassPair<T> pp)
 {
+    // one grid for both species: blocks [0, nb0) take the electrons' chunks,
+    // the rest the ions', so the ions' blocks fill the CUs as the electrons'
+    // drain instead of waiting for a second launch
+    const int sp = (int)blockIdx.x >= pp.nb0 ? 1 : 0;
+    const PassArgs<T> &a = pp.a[sp];
+    const int64_t bid = (int64_t)blockIdx.x - (sp ? pp.nb0 : 0);
     using F4 = typename Field4<T>::type;
     constexpr int WIN = Win<T>::N;
     __shared__ long long winJ[PUSH ? WIN : 1];   // fixed point, the accumulators' scales
@@ -458,8 +464,8 @@ __global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassArgs<T> a
     // the last sort, in no cell order) is the slowest to deposit, so its
     // blocks start first and overlap the streaming of the sorted bulk
     const int64_t nchunks = (n + CHUNK - 1) / CHUNK;
-    if ((int64_t)blockIdx.x >= nchunks) return;
-    const int64_t c0 = (nchunks - 1 - (int64_t)blockIdx.x) * CHUNK;
+    if (bid >= nchunks) return;
+    const int64_t c0 = (nchunks - 1 - bid) * CHUNK;
     const int64_t c1 = min(c0 + (int64_t)CHUNK, n);
     const GridC g = a.g;
     const int s = a.sc.s;
@@ -1307,15 +1313,20 @@ void launch_live_index(const int32_t *cell, const int64_t *count, int64_t *index
 }
 
 template <typename T>
-void launch_pass(const PassArgs<T> &a, int64_t cap, bool push, bool depq, hipStream_t st)
+void launch_pass(const PassArgs<T> &e, const PassArgs<T> &i, int64_t cap_e, int64_t cap_i, bool push, bool depq,
+                 hipStream_t st)
 {
-    const dim3 grid(blocks_for(cap, CHUNK)), blk(BLOCK);
+    PassPair<T> pp;
+    pp.a[0] = e;
+    pp.a[1] = i;
+    pp.nb0 = blocks_for(cap_e, CHUNK);
+    const dim3 grid(pp.nb0 + blocks_for(cap_i, CHUNK)), blk(BLOCK);
     if (push && depq)
-        hipLaunchKernelGGL((k_pass<T, true, true>), grid, blk, 0, st, a);
+        hipLaunchKernelGGL((k_pass<T, true, true>), grid, blk, 0, st, pp);
     else if (push)
-        hipLaunchKernelGGL((k_pass<T, true, false>), grid, blk, 0, st, a);
+        hipLaunchKernelGGL((k_pass<T, true, false>), grid, blk, 0, st, pp);
     else if (depq)
-        hipLaunchKernelGGL((k_pass<T, false, true>), grid, blk, 0, st, a);
+        hipLaunchKernelGGL((k_pass<T, false, true>), grid, blk, 0, st, pp);
 }
 
 template <typename T> void launch_collide(const PassArgs<T> &a, hipStream_t st)
@@ -1358,7 +1369,8 @@ int sort_scan_blocks(int ncells) { return (int)blocks_for(ncells, SCAN_BLOCK); }
     template void launch_unplace<T>(const Parts<T> &, const int64_t *, int64_t, const int64_t *, double *,          \
                                     double *, double *, double *, double *, uint32_t *, int32_t *, const GridC &,   \
                                     hipStream_t);                                                                   \
-    template void launch_pass<T>(const PassArgs<T> &, int64_t, bool, bool, hipStream_t);                            \
+    template void launch_pass<T>(const PassArgs<T> &, const PassArgs<T> &, int64_t, int64_t, bool, bool,          \
+                                 hipStream_t);                                                                      \
     template void launch_collide<T>(const PassArgs<T> &, hipStream_t);                                              \
     template void launch_births<T>(const Births<T> &, const Parts<T> &, const Parts<T> &, int64_t *, int64_t *,     \
                                    int64_t, int64_t, long long *, long long *, bool, double, const GridC &,         \
