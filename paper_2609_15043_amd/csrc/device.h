@@ -102,8 +102,14 @@ __device__ __forceinline__ long long to_fixed_fast(double v, double scale)
 {
     constexpr double magic = 6755399441055744.0;   // 1.5 * 2^52
     const double x = v * scale;
-    if (!(fabs(x) < 0x1p51)) return __double2ll_rn(x);
-    return __double_as_longlong(x + magic) - __double_as_longlong(magic);
+    const bool big = !(fabs(x) < 0x1p51);
+    long long f = __double_as_longlong(x + magic) - __double_as_longlong(magic);
+    // the library conversion behind a wave-uniform branch: short divergent
+    // blocks are issued with the lanes masked off rather than skipped, and
+    // this one would cost every conversion six more instructions
+    if (__builtin_expect(__ballot(big) != 0, 0))
+        if (big) f = __double2ll_rn(x);
+    return f;
 }
 __device__ __forceinline__ long long to_fixed_fast(float v, float scale)
 {
