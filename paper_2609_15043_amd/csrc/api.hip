@@ -1225,6 +1225,16 @@ template <typename T> static pic_status init_impl(pic_ctx &c)
         sc.qscale = c.qscale;
         sc.vref = std::sqrt(std::max(f.temp_ev[s], 1e-3) * f.qe / f.m[s]);
         sc.inv_vref = 1.0 / sc.vref;
+        sc.hf = (float)sc.h;
+        sc.dtrf = (float)sc.dtr;
+        sc.dtzf = (float)sc.dtz;
+        sc.inv_vreff = (float)sc.inv_vref;
+        sc.jscalef = (float)sc.jscale;
+        sc.qscalef = (float)sc.qscale;
+        for (int k = 0; k < 3; ++k) {
+            sc.btf[k] = (float)sc.bt[k];
+            sc.bsf[k] = (float)sc.bs[k];
+        }
     }
     c.mc.seed = f.seed;
     c.mc.xs_kind = f.xs_kind;

@@ -83,6 +83,12 @@ __device__ __forceinline__ double wave_total(double v)
 __device__ __forceinline__ float quot(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 __device__ __forceinline__ double quot(double a, double b) { return a / b; }
 
+// square root: the hardware instruction in FP32 (about 1 ulp; the correctly
+// rounded form adds a dozen instructions of range scaling and refinement),
+// IEEE in FP64
+__device__ __forceinline__ float root(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double root(double x) { return sqrt(x); }
+
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
 // ---------------------------------------------------------------------------

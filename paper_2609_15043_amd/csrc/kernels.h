@@ -76,7 +76,15 @@ struct SpeciesC {
     double qscale;     // fixed-point scale of W
     double vref;
     double inv_vref;
+    // the same constants rounded to FP32, for the FP32 particle pass (read
+    // from the kernel arguments as they are, with no conversion per use)
+    float hf, dtrf, dtzf, inv_vreff, jscalef, qscalef, btf[3], bsf[3];
 };
+
+// a species constant in the pass's working precision
+template <typename T> __device__ __forceinline__ T sc_val(double d, float f);
+template <> __device__ __forceinline__ float sc_val<float>(double, float f) { return f; }
+template <> __device__ __forceinline__ double sc_val<double>(double d, float) { return d; }
 
 struct MccC {
     uint32_t seed;

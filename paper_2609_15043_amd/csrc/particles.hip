@@ -528,7 +528,7 @@ __global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassPair<T> p
     if (tid < ST_NSTAT) sstat[tid] = 0;
     __syncthreads();
     const WinMap w = s_w;
-    const T jscale = (T)a.sc.jscale, qscale = (T)a.sc.qscale;   // powers of two
+    const T jscale = sc_val<T>(a.sc.jscale, a.sc.jscalef), qscale = sc_val<T>(a.sc.qscale, a.sc.qscalef);   // powers of two
     int nout = 0;   // this lane's deposits outside the window
 
     for (int r = 0; r < RUNS; ++r) {
@@ -555,11 +555,13 @@ __global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassPair<T> p
                 const T er = w00 * f00.x + w01 * f01.x + w10 * f10.x + w11 * f11.x;
                 const T ez = w00 * f00.y + w01 * f01.y + w10 * f10.y + w11 * f11.y;
                 const T et = w00 * f00.z + w01 * f01.z + w10 * f10.z + w11 * f11.z;
-                const T h = (T)a.sc.h;
+                const T h = sc_val<T>(a.sc.h, a.sc.hf);
                 T ur = vr[k] + h * er, ut = vt[k] + h * et, uz = vz[k] + h * ez;
                 if (a.sc.has_b) {
-                    const T t0 = (T)a.sc.bt[0], t1 = (T)a.sc.bt[1], t2 = (T)a.sc.bt[2];
-                    const T s0 = (T)a.sc.bs[0], s1 = (T)a.sc.bs[1], s2 = (T)a.sc.bs[2];
+                    const T t0 = sc_val<T>(a.sc.bt[0], a.sc.btf[0]), t1 = sc_val<T>(a.sc.bt[1], a.sc.btf[1]),
+                            t2 = sc_val<T>(a.sc.bt[2], a.sc.btf[2]);
+                    const T s0 = sc_val<T>(a.sc.bs[0], a.sc.bsf[0]), s1 = sc_val<T>(a.sc.bs[1], a.sc.bsf[1]),
+                            s2 = sc_val<T>(a.sc.bs[2], a.sc.bsf[2]);
                     const T pr = ur + (ut * t2 - uz * t1), pt = ut + (uz * t0 - ur * t2), pz = uz + (ur * t1 - ut * t0);
                     ur += pt * s2 - pz * s1;
                     ut += pz * s0 - pr * s2;
@@ -569,7 +571,7 @@ __global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassPair<T> p
                 ut += h * et;
                 uz += h * ez;
                 // azimuthal current at x^n with the time-centred v_theta
-                const T jv = (T)0.5 * (vt[k] + ut) * (T)a.sc.inv_vref;
+                const T jv = (T)0.5 * (vt[k] + ut) * sc_val<T>(a.sc.inv_vref, a.sc.inv_vreff);
                 if (iJ < 0) iJ = i, jJ = j;
                 if (i == iJ && j == jJ) {
                     aJ[0] += jv * w00;
@@ -582,10 +584,10 @@ __global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassPair<T> p
                 }
                 // Cartesian move in the particle's plane, in cell units
                 const T fj = (T)j;
-                const T ar = dr[k] + ur * (T)a.sc.dtr;
+                const T ar = dr[k] + ur * sc_val<T>(a.sc.dtr, a.sc.dtrf);
                 const T X = fj + ar;
-                const T Y = ut * (T)a.sc.dtr;
-                const T hyp = sqrt(X * X + Y * Y);
+                const T Y = ut * sc_val<T>(a.sc.dtr, a.sc.dtrf);
+                const T hyp = root(X * X + Y * Y);
                 const T rel = X > (T)0 ? ar + quot(Y * Y, X + hyp) : hyp - fj;   // R' - j
                 T c = (T)1, sn = (T)0;
                 if (hyp > (T)0) {
@@ -601,7 +603,7 @@ __global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassPair<T> p
                     drn -= (T)1;
                     jn += 1;
                 }
-                const T bz = dz[k] + uz * (T)a.sc.dtz;
+                const T bz = dz[k] + uz * sc_val<T>(a.sc.dtz, a.sc.dtzf);
                 const T fz = floor(bz);
                 int in = i + (int)fz;
                 T dzn = bz - fz;
