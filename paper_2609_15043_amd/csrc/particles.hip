@@ -540,7 +540,7 @@ __global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassPair<T> p
         // lane's run sums around its key nodes (old cell for J, new for Q)
         int iJ = -1, jJ = 0, iQ = -1, jQ = 0;   // each run's first cell (row, column)
         T aJ[4] = {0, 0, 0, 0}, aQ[4] = {0, 0, 0, 0};
-        int absorbed_n = 0;
+        uint32_t abs_bits = 0;    // bit k: particle k of the run was absorbed
         uint32_t cand_bits = 0;
         bool moved = false;   // a particle of the run changed cell (or was absorbed)
 #pragma unroll
@@ -635,7 +635,7 @@ __global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassPair<T> p
                 } else if (jn >= g.nr || jn < 0) {
                     absorbed = 1;
                 }
-                absorbed_n += absorbed != 0;
+                if (absorbed) abs_bits |= 1u << k;
                 live[k] = absorbed == 0;
                 const int32_t cn = live[k] ? in * g.nr + jn : -1;
                 moved |= cn != cell[k];
@@ -674,20 +674,22 @@ __global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassPair<T> p
             st4(a.p.vz + q0, vz);
             // this step's collision candidates -> block-local list (LDS), one
             // global reservation per block at the end
-            const int nc = __popc(cand_bits);
-            int pre = nc;
+            // candidates of the lanes below this one and of the whole wave,
+            // from one ballot per run position (no shuffles)
+            int before = 0, wtot = 0;
 #pragma unroll
-            for (int off = 1; off < 64; off <<= 1) {
-                const int v = __shfl_up(pre, off);
-                if (lane >= off) pre += v;
+            for (int k = 0; k < RUN; ++k) {
+                const uint64_t bk = ballot(cand_bits >> k & 1u);
+                before += (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bk >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)bk, 0u));
+                wtot += (int)__popcll(bk);
             }
-            const int wtot = __shfl(pre, 63);
             int slot0 = 0;
             if (wtot) {
                 if (lane == 63) slot0 = atomicAdd(&s_ncand, wtot);
-                slot0 = __shfl(slot0, 63);
+                slot0 = __builtin_amdgcn_readlane(slot0, 63);
             }
-            int slot = slot0 + pre - nc;
+            int slot = slot0 + before;
 #pragma unroll
             for (int k = 0; k < RUN; ++k) {
                 if (!(cand_bits >> k & 1u)) continue;
@@ -710,10 +712,10 @@ __global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassPair<T> p
         if (r + 1 < RUNS) load_run(q0 + RUN * 64);
         if constexpr (PUSH) {
             deposit4<T>(iJ >= 0, iJ, jJ, aJ[0], aJ[1], aJ[2], aJ[3], winJ, w, a.accJ, g.nr1, jscale, nout);
-            // absorbed count: sum over the wave
-            int tot = absorbed_n;
+            // absorbed count of the wave, from one ballot per run position
+            int tot = 0;
 #pragma unroll
-            for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off);
+            for (int k = 0; k < RUN; ++k) tot += (int)__popcll(ballot(abs_bits >> k & 1u));
             if (lane == 0 && tot) atomicAdd(&sstat[ST_ABS0 + s], (unsigned long long)tot);
         }
         if constexpr (DEPQ)
