@@ -547,6 +547,7 @@ static void layout(pic_ctx &c, Carver &cv)
     {
         const MGLevel &Lc = c.lv.L[nl - 1];
         c.lv.coarse_inv = cv.take<double>((size_t)Lc.nodes * dense_ld(Lc.nodes));
+        c.lv.coarse_inv32 = cv.take<float>((size_t)Lc.nodes * dense_ld32(Lc.nodes));
     }
     c.mgs = cv.take<MGState>(1);
     c.mgpartial = cv.take<double>(pcg_partial_size(c.lv.L[0]));
@@ -591,6 +592,7 @@ static void layout(pic_ctx &c, Carver &cv)
         }
         const MGLevel &Lc = c.hlv.L[nl - 1];
         c.hlv.coarse_inv = cv.take<double>((size_t)Lc.nodes * dense_ld(Lc.nodes));
+        c.hlv.coarse_inv32 = cv.take<float>((size_t)Lc.nodes * dense_ld32(Lc.nodes));
     }
 }
 
@@ -808,7 +810,7 @@ static void vcycle(pic_ctx &c, const MGLevels &lv, const MGState *st)
         launch_mg_resid(pre[l], st, c.stream);
     }
     if (lb > 0) launch_mg_restrict_res(pre[lb - 1], pre[lb], st, c.stream);
-    launch_dense_solve(lv.coarse_inv, lv.L[lb], st, c.stream);
+    launch_dense_solve(lv.coarse_inv32, lv.L[lb], st, c.stream);
     for (int l = lb - 1; l >= 0; --l) {
         const int nu = l == 0 ? PIC_MG_NU0 : PIC_MG_NU;
         launch_mg_smooth_tile(pre[l], nullptr, &post[l + 1], nu, SM_REVERSE | SM_PROLONG | (l == 0 ? SM_RZ : 0), st,
@@ -953,6 +955,7 @@ static pic_status build_levels(pic_ctx &c, MGLevels &lv, const Coeffs &co, const
                                     (size_t)m * sizeof(double), (size_t)m * sizeof(double), m, hipMemcpyHostToDevice,
                                     c.stream));
         launch_gauss_jordan(const_cast<double *>(lv.coarse_inv), m, c.pp, c.pAp, c.stream);
+        launch_inverse_f32(lv.coarse_inv, m, const_cast<float *>(lv.coarse_inv32), c.stream);
         HIPCHK(&c, hipStreamSynchronize(c.stream));
     }
     return PIC_OK;

@@ -339,26 +339,41 @@ __global__ __launch_bounds__(256) void k_mg_restrict_res(MGLevel F, MGLevel C, c
     }
 }
 
-// Exact solve on the bottom level: phi = Inv rhs, one wave per row, the row
-// streamed in 16-byte loads (rows are padded to an even length, ld doubles)
-// into two independent partial sums.
-__global__ __launch_bounds__(256) void k_dense_solve(const double *inv, int ld, MGLevel L, const MGState *st)
+// Bottom solve of the preconditioner: phi = Inv rhs with the inverse held in
+// FP32 (symmetrised when rounded, so the preconditioner stays symmetric;
+// products and sums in FP64).  It is half the bytes of the FP64 inverse,
+// which every CG iteration streams; an approximate bottom solve changes
+// only how fast CG converges, not the tolerance it converges to.  One wave
+// per row, the row streamed in 16-byte loads (rows padded to a multiple of
+// four, ld floats) into two independent partial sums.
+__global__ __launch_bounds__(256) void k_dense_solve(const float *inv, int ld, MGLevel L, const MGState *st)
 {
     if (st->done) return;
     const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (r >= L.nodes) return;
     const int lane = threadIdx.x & 63;
-    const double2 *row = reinterpret_cast<const double2 *>(inv + (size_t)r * ld);
-    const int n2 = L.nodes >> 1;
+    const float4 *row = reinterpret_cast<const float4 *>(inv + (size_t)r * ld);
+    const int n4 = L.nodes >> 2;
     double s0 = 0.0, s1 = 0.0;
-    for (int k = lane; k < n2; k += 64) {
-        const double2 a = row[k];
-        s0 += a.x * L.rhs[2 * k];
-        s1 += a.y * L.rhs[2 * k + 1];
+    for (int k = lane; k < n4; k += 64) {
+        const float4 a = row[k];
+        s0 += (double)a.x * L.rhs[4 * k] + (double)a.z * L.rhs[4 * k + 2];
+        s1 += (double)a.y * L.rhs[4 * k + 1] + (double)a.w * L.rhs[4 * k + 3];
     }
-    if ((L.nodes & 1) && lane == 0) s0 += inv[(size_t)r * ld + L.nodes - 1] * L.rhs[L.nodes - 1];
+    for (int k = 4 * n4 + lane; k < L.nodes; k += 64) s0 += (double)inv[(size_t)r * ld + k] * L.rhs[k];
     const double s = wave_total(s0 + s1);
     if (lane == 63) L.phi[r] = s;
+}
+
+// FP32 copy of the FP64 inverse (row stride ld), symmetrised: out(r, c) =
+// (inv(r, c) + inv(c, r)) / 2 rounded once; the padding columns are 0.
+__global__ void k_inverse_f32(const double *inv, int n, int ld, float *out, int ld32)
+{
+    const int64_t total = (int64_t)n * ld32;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        const int r = (int)(t / ld32), c = (int)(t - (int64_t)r * ld32);
+        out[t] = c < n ? (float)(0.5 * (inv[(size_t)r * ld + c] + inv[(size_t)c * ld + r])) : 0.f;
+    }
 }
 
 // In-place Gauss-Jordan inversion (row stride ld), one pivot per kernel
@@ -657,9 +672,16 @@ void launch_mg_restrict_res(const MGLevel &F, const MGLevel &C, const MGState *s
     hipLaunchKernelGGL(k_mg_restrict_res, dim3(mg_grid(C.nodes)), dim3(256), 0, s, F, C, st);
 }
 int dense_ld(int n) { return n + (n & 1); }
-void launch_dense_solve(const double *inv, const MGLevel &L, const MGState *st, hipStream_t s)
+int dense_ld32(int n) { return (n + 3) & ~3; }
+void launch_dense_solve(const float *inv, const MGLevel &L, const MGState *st, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_dense_solve, dim3(nblk(L.nodes, 4)), dim3(256), 0, s, inv, dense_ld(L.nodes), L, st);
+    hipLaunchKernelGGL(k_dense_solve, dim3(nblk(L.nodes, 4)), dim3(256), 0, s, inv, dense_ld32(L.nodes), L, st);
+}
+void launch_inverse_f32(const double *inv, int n, float *out, hipStream_t s)
+{
+    const int64_t total = (int64_t)n * dense_ld32(n);
+    hipLaunchKernelGGL(k_inverse_f32, dim3(std::min<int64_t>(nblk(total, 256), 4096)), dim3(256), 0, s, inv, n,
+                       dense_ld(n), out, dense_ld32(n));
 }
 void launch_gauss_jordan(double *A, int n, double *rowk, double *colk, hipStream_t s)
 {

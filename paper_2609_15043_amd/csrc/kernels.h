@@ -160,6 +160,7 @@ struct MGLevels {
     int n;
     MGLevel L[MAX_LEVELS];
     const double *coarse_inv;   // dense inverse of the bottom operator (Dirichlet rows identity)
+    const float *coarse_inv32;  // the same, symmetrised and rounded to FP32 (rows of dense_ld32 floats)
 };
 
 // Device-resident state of one preconditioned-CG solve.

@@ -57,7 +57,9 @@ void launch_mg_smooth_tile(const MGLevel &L, const MGLevel *F, const MGLevel *C,
                            const MGState *st, double *partial, double *out, hipStream_t s);
 void launch_mg_resid(const MGLevel &L, const MGState *st, hipStream_t s);
 void launch_mg_restrict_res(const MGLevel &F, const MGLevel &C, const MGState *st, hipStream_t s);
-void launch_dense_solve(const double *inv, const MGLevel &L, const MGState *st, hipStream_t s);
+void launch_dense_solve(const float *inv, const MGLevel &L, const MGState *st, hipStream_t s);
+int dense_ld32(int n);
+void launch_inverse_f32(const double *inv, int n, float *out, hipStream_t s);
 // dense inverse of the bottom level: n rows of stride dense_ld(n) (even, so
 // that rows start 16-byte aligned)
 int dense_ld(int n);
