@@ -499,7 +499,7 @@ static void layout(pic_ctx &c, Carver &cv)
     c.harm = cv.take<HarmState>(1);
     // multigrid: level 0 holds the CG correction (z) and residual (r); the
     // hierarchy stops at the first level of at most BOTTOM_NODES nodes, which
-    // is solved exactly with a dense inverse
+    // is solved with a dense inverse (inverted in FP64, applied from an FP32 copy)
     int nl = mg_levels(f.nr, f.nz);
     {
         int nr_ = f.nr, nz_ = f.nz, l = 0;
@@ -776,7 +776,7 @@ static void finalize_charge(pic_ctx &c)
 
 // V-cycle on the correction (level 0: right-hand side = the CG residual r,
 // correction = z): two red-black sweeps on the 5-point fine level, one
-// four-colour sweep on the Galerkin levels, exact solve on the bottom level
+// four-colour sweep on the Galerkin levels, dense-inverse solve on the bottom level
 // (dense inverse, one multi-block product).  The pre-smoothers start from
 // zero, the coarse ones with the right-hand side restricted from the finer
 // level's residual; the post-smoothers add the prolonged coarse correction
