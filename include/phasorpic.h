@@ -52,6 +52,8 @@ enum {
 };
 
 enum { PIC_FP64 = 0, PIC_MIXED = 1 };
+/* poisson_solve_rz operators */
+enum { PIC_OP_POISSON = 0, PIC_OP_HELMHOLTZ_C = 1, PIC_OP_HELMHOLTZ_S = 2 };
 enum { PIC_FIELD_FULL = 0, PIC_FIELD_MQS = 1 };   /* inductive operator with / without displacement term */
 enum { PIC_RRF_GIVEN = 0, PIC_RRF_SKIN = 1 };     /* turn RF resistance: given / round-wire skin model */
 #define PIC_MAX_TURNS 16
@@ -64,7 +66,7 @@ enum {
     PIC_GRID_ER = 3,       /* staged E_r of the last pic_gather_push (V/m) */
     PIC_GRID_EZ = 4,       /* staged E_z (V/m) */
     PIC_GRID_ETHETA = 5,   /* staged E_theta(t_n) (V/m) */
-    PIC_GRID_SURFACE = 6,  /* accumulated window surface charge (C) */
+    PIC_GRID_SURFACE = 6,  /* window surface charge accumulated up to the last pic_deposit (C) */
     PIC_GRID_JC = 7,       /* running sum of I^n cos(theta_n) of the open period */
     PIC_GRID_JS = 8,       /* running sum of I^n sin(theta_n) of the open period */
     PIC_GRID_EC = 9,       /* E_c of the applied azimuthal field (V/m) */
@@ -140,6 +142,13 @@ typedef struct pic_config {
     int32_t helm_max_cycles; /* ... and their iteration limit */
     int32_t sort_every_ion;  /* steps between cell sorts of the ion arrays (ions move a small fraction of a
                                 cell per step); 0: sort_every */
+    /* manufactured boundaries (host arrays of nturns x nodes, copied by pic_init; NULL = 0), as in the
+     * paper's joint benchmark (Sec. 3.3): a grounded node n (tag 0) of the Poisson problem takes
+     * sum_k dir_basis[k * nodes + n] V_k(t_n), with V_k(t_n) the turn potentials of Eq. dirichlet,
+     * and the unit-current field U_k takes unit_bvals[k * nodes + n] on the Dirichlet nodes of the
+     * inductive operator (axis, outer boundary, metal) */
+    const double *dir_basis;
+    const double *unit_bvals;
 } pic_config;
 
 typedef struct pic_solve_info {
@@ -178,6 +187,9 @@ typedef struct pic_stats {
     int64_t circuit_count;
     int64_t mg_cycles;       /* V-cycles of the last solve */
     double mg_rel;           /* its final relative residual */
+    int64_t mg_unconverged;  /* Poisson solves since init that used up their iteration budget before
+                                rtol (the stepping path's budget adapts to the recent counts; a solve
+                                given an info record runs max_cycles and returns PIC_ENOTCONV instead) */
 } pic_stats;
 
 typedef struct pic_ctx pic_ctx;
@@ -222,16 +234,32 @@ pic_status mcc_collide(pic_ctx *ctx, int64_t n);
  * exact 64-bit fixed point, plus the accumulated window surface charge. */
 pic_status pic_deposit(pic_ctx *ctx, int64_t n1);
 
-/* FP64 geometric multigrid solve of the finite-volume RZ Poisson problem
+/* Field solves on the grid, FP64 multigrid-preconditioned CG.
+ *
+ * op = PIC_OP_POISSON: the finite-volume RZ Poisson problem
  * sum_f eps0 eps_f A_f (phi_p - phi_nb) / d_f = Q_p (Eqs. poisson with
  * chi = 0, epseff, areas; Neumann axis, Eq. axis_electrostatic_bc) with
  * Dirichlet 0 on grounded nodes and phi_k(t_n) = V_c,k cos th_n +
  * V_s,k sin th_n on turn k (Eq. dirichlet), warm-started from the last
- * phi.  Then the turn charges Q_k(t_n) from the operator's face fluxes
- * (Eq. facecharge).  rtol <= 0 / max_cycles <= 0 take the config values.
- * info (nullable): when given the call synchronises and fills it;
- * PIC_ENOTCONV if rtol was not met. */
-pic_status poisson_solve_rz(pic_ctx *ctx, int64_t n, double rtol, int32_t max_cycles,
+ * phi (extrapolated in time along a running sequence of steps).  Then the
+ * turn charges Q_k(t_n) from the operator's face fluxes (Eq. facecharge).
+ *
+ * op = PIC_OP_HELMHOLTZ_C / _S (coupled contexts only, else PIC_EINVAL):
+ * one of the two real plasma-only inductive solves of the period update
+ * (Sec. 2.2, Eq. helmholtz_two_real), K E_c^p = J_s / V and K E_s^sto,p =
+ * J_c / V, with the harmonics J_c, J_s = (2 / N_RF) sum_n I^n (cos, sin)
+ * th_n accumulated so far in the open period (after N_RF samples exactly
+ * the fields circuit_period_update computes); the result replaces
+ * PIC_GRID_EC_PLASMA / _ES_PLASMA.  n is ignored.
+ *
+ * rtol <= 0 / max_cycles <= 0 take the config values (mg_* for Poisson,
+ * helm_* for the inductive solves).  info (nullable): when given the call
+ * synchronises, fills it and returns PIC_ENOTCONV if rtol was not met;
+ * without it a Poisson solve runs an iteration budget adapted to the
+ * recent solves and a short solve is only counted (pic_stats.
+ * mg_unconverged), while the inductive solves always synchronise and
+ * return PIC_ENOTCONV when they miss rtol. */
+pic_status poisson_solve_rz(pic_ctx *ctx, int64_t n, int32_t op, double rtol, int32_t max_cycles,
                             pic_solve_info *info);
 
 /* Period accumulation of step n (Eqs. fourier, pind, pcap): J_c += I^n
@@ -275,6 +303,7 @@ typedef struct pic_period_report {
     int32_t sur_used;        /* 1: the surrogate-assisted update was applied */
     int32_t sur_iters;       /* its inner fixed-point iterations */
     double sur_err;          /* scaled prediction error at the applied state */
+    double sur_steps[64];    /* |x_{i+1} - x_i| / |x_{i+1}| of each inner iterate (first sur_iters) */
 } pic_period_report;
 
 /* Surrogate-assisted circuit update (the learned predictor of the load
@@ -292,7 +321,7 @@ typedef struct pic_period_report {
 typedef struct pic_surrogate_config {
     double err_max;          /* e.g. 0.02 */
     double tol;              /* e.g. 1e-6 */
-    int32_t max_iter;        /* e.g. 50 */
+    int32_t max_iter;        /* e.g. 50; at most 64 */
 } pic_surrogate_config;
 
 /* Inductive-port data of a coupled context (pic_get_circuit). */
@@ -309,24 +338,41 @@ typedef struct pic_circuit_info {
     double x_re[33], x_im[33];  /* applied state */
 } pic_circuit_info;
 
+/* What a caller may impose on one period update (all fields optional). */
+typedef struct pic_circuit_override {
+    /* context without circuit coupling: the next period's turn potentials
+     * (nturns each) and azimuthal field (node arrays); NULL keeps them */
+    const double *new_vc, *new_vs;
+    const double *new_ec, *new_es_sto;
+    /* coupled context: prescribed load responses (loads != 0) replace the
+     * measured plasma reaction voltages and capacitive currents of the
+     * closed period in the controller and the network solve (Eqs.
+     * blockmatrix, relaxation) -- a prescribed load or an external
+     * predictor; the powers of the report stay the measured ones, its
+     * V_p / I_cap are the prescribed values.  Not with a surrogate attached. */
+    int32_t loads;
+    double vp_re[16], vp_im[16];      /* V_p,k (V) */
+    double icap_re[16], icap_im[16];  /* I_cap,k (A) */
+} pic_circuit_override;
+
 /* Closes the RF period: synchronises and requires phase closure and
  * exactly N_RF samples (otherwise PIC_EPHASE: the update is rejected, the
  * circuit state and fields stay as they are, and the accumulators restart
  * empty).  Finalises the harmonics and powers into *report (nullable) and
  * copies J_c, J_s (x 2/N_RF) into the caller's host arrays jc, js when
- * non-NULL.  Without cfg->circuit it then optionally installs the next
- * period's turn voltages (new_vc, new_vs, nturns each) and azimuthal field
- * (new_ec, new_es_sto node arrays); NULL keeps them.  With cfg->circuit the
- * new_* arguments must be NULL and the update of Sec. 2.4 runs on the
- * device: two plasma-only inductive solves K E_c^p = J_s / V_node,
+ * non-NULL.  Without cfg->circuit it then installs what ovr (nullable)
+ * gives for the next period.  With cfg->circuit the update of Sec. 2.4 runs
+ * on the device: two plasma-only inductive solves K E_c^p = J_s / V_node,
  * K E_s^sto,p = J_c / V_node (Eq. helmholtz_two_real), V_p,k (Eq. vpind),
- * I_cap,k (Eq. icap), the power controller, the (2N+1) complex network
- * solve with partial pivoting, the relaxation, the residuals, and the next
- * period's turn potentials and field (Eq. compose).  PIC_ENOTCONV if an
- * inductive solve misses helm_rtol.  The accumulators are reset. */
-pic_status circuit_period_update(pic_ctx *ctx, const double *new_vc, const double *new_vs,
-                                 const double *new_ec, const double *new_es_sto,
-                                 pic_period_report *report, double *jc, double *js);
+ * I_cap,k (Eq. icap) -- or the loads ovr prescribes --, the power
+ * controller, the (2N+1) complex network solve with partial pivoting, the
+ * relaxation, the residuals, and the next period's turn potentials and
+ * field (Eq. compose).  PIC_EINVAL for an override that does not fit the
+ * context (turn data on a coupled one, loads on an uncoupled one or with a
+ * surrogate); PIC_ENOTCONV if an inductive solve misses helm_rtol.  The
+ * accumulators are reset. */
+pic_status circuit_period_update(pic_ctx *ctx, const pic_circuit_override *ovr, pic_period_report *report,
+                                 double *jc, double *js);
 
 /* Set the Thevenin source amplitude (V, > 0) and phase (rad) used by the
  * next circuit update of a coupled context (the controller, when on, starts
@@ -367,6 +413,25 @@ pic_status pic_set_step(pic_ctx *ctx, int64_t n);
 
 /* Replace phi (host node array); the next pic_gather_push stages from it. */
 pic_status pic_set_phi(pic_ctx *ctx, const double *phi);
+
+/* Restart (the restart check of the paper's appendix: a run stopped and
+ * resumed reproduces the uninterrupted one).  pic_checkpoint copies the
+ * whole time-dependent state at a step boundary -- both species' particle
+ * slots in storage order, counters, phi and the two previous solutions of
+ * the start-value extrapolation, the window charge, the turn charges, the
+ * open period's accumulators, the applied turn potentials and azimuthal
+ * field, the plasma-only fields and the circuit state -- into the caller's
+ * host buffer buf of cap bytes; with buf == NULL it only sets *bytes to
+ * the size needed.  PIC_ESTATE between the calls of a step, PIC_ENOMEM if
+ * cap is too small.  pic_restore loads such a buffer into a context made
+ * by pic_init with the same configuration (what pic_init derives from the
+ * configuration alone is not stored); PIC_EINVAL for a buffer from another
+ * configuration.  Then pic_gather_push continues with the step after the
+ * checkpoint.  The continuation is bit-identical to the uninterrupted run
+ * until the next cell sort (which orders the particles within a cell by
+ * atomics).  An attached surrogate stays attached. */
+pic_status pic_checkpoint(pic_ctx *ctx, void *buf, size_t cap, size_t *bytes);
+pic_status pic_restore(pic_ctx *ctx, const void *buf, size_t bytes);
 
 /* Copy one FP64 node grid (PIC_GRID_*) to host (synchronising). */
 pic_status pic_get_grid(pic_ctx *ctx, int32_t which, double *out);

@@ -133,16 +133,18 @@ def node_eps(eps_cell):
 
 
 def node_volume(nr, nz, dr, dz):
-    """Volume of each node's control volume, 2 pi int R dR dz over
-    [R_j - dR/2, R_j + dR/2] x [z_i - dz/2, z_i + dz/2] clipped to the
-    domain; equal to the integral of the R^2-linear / z-linear node weight,
-    so J = I_node / V_node is the current density seen by that weight."""
-    R = np.arange(nr + 1) * dr
-    lo = np.maximum(R - dr / 2, 0.0)
-    hi = np.minimum(R + dr / 2, nr * dr)
-    z = np.arange(nz + 1) * dz
-    h = np.minimum(z + dz / 2, nz * dz) - np.maximum(z - dz / 2, 0.0)
-    return np.outer(h, math.pi * (hi ** 2 - lo ** 2))
+    """Integral of each node's weight over the domain, 2 pi int W R dR dz:
+    the R^2-linear weight gives pi (R_{j+1}^2 - R_{j-1}^2) / 2 with the
+    neighbours clipped to the domain (pi dR^2 / 2 on the axis, pi (R_N^2 -
+    R_{N-1}^2) / 2 on the outer wall), the linear axial weight dz (dz / 2 on
+    the end rows).  J = I_node / V_node is then the current density, and
+    q w W / V_node the particle density, that the weight sees."""
+    j = np.arange(nr + 1)
+    hi = np.minimum(j + 1, nr) * dr
+    lo = np.maximum(j - 1, 0) * dr
+    h = np.full(nz + 1, dz)
+    h[0] = h[-1] = dz / 2
+    return np.outer(h, math.pi * (hi ** 2 - lo ** 2) / 2)
 
 
 # ---------------------------------------------------------------------------
@@ -427,6 +429,7 @@ class FieldCircuit:
         ph = complex(math.cos(self.p.vg_phase), math.sin(self.p.vg_phase))
         loads = None
         acc, vacc, navg = np.zeros_like(xi), 0.0, 0
+        steps = []
         for it in range(1, max_iter + 1):
             l = np.asarray(predict(self.features(xi, pressure, moments)), dtype=np.float64) + corr
             lv = l[0:2 * N:2] + 1j * l[1:2 * N:2]
@@ -442,6 +445,7 @@ class FieldCircuit:
             a = self.p.alpha
             new = (1 - a) * xi + a * xt
             step = np.linalg.norm(new - xi) / np.linalg.norm(new)
+            steps.append(step)
             xi = new
             if not np.isfinite(step) or np.linalg.norm(xi) ** 2 > 1e6 * np.linalg.norm(x_n) ** 2:
                 # the predicted load map does not contract here: plain update
@@ -462,7 +466,7 @@ class FieldCircuit:
         if self.ctrl is not None:
             self.ctrl.pf_prev = p_port(self.x, N)
         rep = self._report(h, x_n, vp, icap, pp, pcu, eps_bal, xt, vg_old, None, None, loads)
-        rep.update(sur_used=1, sur_iters=it, sur_err=err)
+        rep.update(sur_used=1, sur_iters=it, sur_err=err, sur_steps=np.array(steps))
         return rep
 
     def _plain(self, h, x_n, vp, icap, pp, pcu, eps_bal, vg_old):

@@ -117,9 +117,11 @@ struct pic_ctx {
     // grids
     void *ef = nullptr;
     long long *accJ = nullptr, *accQ = nullptr;
-    double *accS = nullptr;
+    double *accS = nullptr;       // window surface charge per species (weights, FP64, persistent)
+    long long *accW = nullptr;    // the step's window charge per species (fixed point, folded into accS)
     double *phi = nullptr, *Q = nullptr, *I = nullptr, *d_ec = nullptr, *d_es = nullptr;
     int32_t *d_tag = nullptr;
+    double *dbasis = nullptr;     // manufactured Dirichlet basis, nturns x nodes (or none)
     double *d_vc = nullptr, *d_vs = nullptr;
     double *Jc = nullptr, *Jcc = nullptr, *Js = nullptr, *Jsc = nullptr, *hpartial = nullptr;
     HarmState *harm = nullptr;
@@ -139,7 +141,7 @@ struct pic_ctx {
     MGState *mg_host = nullptr;   // pinned ring
     int mg_ring = 0;
     int mg_budget = 8;
-    int64_t mg_unconverged = 0;
+    bool mg_fresh = false;        // next solve runs max_cycles (the turn potentials just changed)
     int32_t *fp = nullptr, *fq = nullptr, *fk = nullptr;
     double *fc = nullptr, *Qk = nullptr;
     int nfaces = 0;
@@ -483,12 +485,14 @@ static void layout(pic_ctx &c, Carver &cv)
     c.accJ = cv.take<long long>(2 * (size_t)nodes);
     c.accQ = cv.take<long long>(2 * (size_t)nodes);
     c.accS = cv.take<double>(2 * (size_t)nodes);
+    c.accW = cv.take<long long>(2 * (size_t)nodes);
     c.phi = cv.take<double>(nodes);
     c.Q = cv.take<double>(nodes);
     c.I = cv.take<double>(nodes);
     c.d_ec = cv.take<double>(nodes);
     c.d_es = cv.take<double>(nodes);
     c.d_tag = cv.take<int32_t>(nodes);
+    if (f.dir_basis && f.nturns > 0) c.dbasis = cv.take<double>((size_t)f.nturns * nodes);
     c.d_vc = cv.take<double>(MAX_TURNS);
     c.d_vs = cv.take<double>(MAX_TURNS);
     c.Jc = cv.take<double>(nodes);
@@ -718,7 +722,7 @@ template <typename T> static PassArgs<T> pass_args(pic_ctx &c, int s, int64_t st
     a.ef = reinterpret_cast<const typename Field4<T>::type *>(c.ef);
     a.accJ = c.accJ + (size_t)s * c.g.nodes;
     a.accQ = c.accQ + (size_t)s * c.g.nodes;
-    a.accS = c.accS + (size_t)s * c.g.nodes;
+    a.accW = c.accW + (size_t)s * c.g.nodes;
     a.stats = c.stats;
     a.err = c.errw;
     a.g = c.g;
@@ -770,7 +774,7 @@ template <typename T> static void run_births(pic_ctx &c, bool deposit)
 static void finalize_charge(pic_ctx &c)
 {
     const pic_config &f = c.cfg;
-    launch_finalize_q(c.accQ, c.accS, f.q[0] * f.w[0] / c.qscale, f.q[1] * f.w[1] / c.qscale,
+    launch_finalize_q(c.accQ, c.accW, c.accS, 1.0 / c.qscale, f.q[0] * f.w[0] / c.qscale, f.q[1] * f.w[1] / c.qscale,
                       f.q[0] * f.w[0], f.q[1] * f.w[1], c.Q, c.g.nodes, c.stream);
 }
 
@@ -821,7 +825,8 @@ static void vcycle(pic_ctx &c, const MGLevels &lv, const MGState *st)
 // preconditioned-CG iteration k of a solve (no-ops once st->done); the
 // search direction alternates between two buffers (the p update and the
 // product A p are one kernel)
-static void pcg_iteration(pic_ctx &c, const MGLevels &lv, MGState *st, const PCGVec &v, double rtol, int k)
+static void pcg_iteration(pic_ctx &c, const MGLevels &lv, MGState *st, const PCGVec &v, double rtol, int k,
+                          unsigned long long *unconv = nullptr)
 {
     const MGLevel &L0 = lv.L[0];
     vcycle(c, lv, st);
@@ -834,7 +839,7 @@ static void pcg_iteration(pic_ctx &c, const MGLevels &lv, MGState *st, const PCG
     double *pnew = (k & 1) ? c.pp : c.pp2;
     launch_pcg_pmatvec(L0, v, pold, pnew, st, c.mgpartial, nrz, c.stream);
     launch_pcg_update(L0, v, pnew, st, c.mgpartial, c.stream);
-    launch_pcg_check(st, c.mgpartial, pcg_blocks(L0.nodes), rtol, false, c.stream);
+    launch_pcg_check(st, c.mgpartial, pcg_blocks(L0.nodes), rtol, false, c.stream, unconv);
 }
 
 // Preconditioned CG on the free nodes (x = phi, b = node charge), one
@@ -862,19 +867,29 @@ static pic_status solve(pic_ctx &c, int64_t n, double rtol, int max_cycles, pic_
             c.mg_budget = std::min(max_cycles, seen + 1);
         }
         budget = std::max(2, std::min(max_cycles, c.mg_budget));
+        // a circuit update moves the turn potentials by a whole period's
+        // correction and the time extrapolation of the start value no
+        // longer holds: that solve gets the full budget (iterations past
+        // convergence are no-ops)
+        if (c.mg_fresh) budget = max_cycles;
     }
+    c.mg_fresh = false;
     // extrapolate only across consecutive steps of a running sequence
     // extrapolate only across consecutive steps of a running sequence: linear
     // once two previous solutions are stored, quadratic once three are
     c.run = (n == c.last_solve + 1 && !full && !info) ? c.run + 1 : 0;
     const int order = c.run >= 3 ? 2 : c.run >= 2 ? 1 : 0;
-    launch_pcg_begin(L0, v, c.d_tag, c.d_vc, c.d_vs, std::cos(th), std::sin(th), c.mgs, c.phi_prev, order, c.stream);
+    launch_pcg_begin(L0, v, c.d_tag, c.d_vc, c.d_vs, std::cos(th), std::sin(th), c.mgs, c.phi_prev, order, c.stream,
+                     c.dbasis, c.cfg.nturns);
     c.last_solve = n;
     const int np = pcg_blocks(L0.nodes);
     budget = std::min(budget, MAX_CG);
     launch_pcg_resid(L0, v, c.mgpartial, c.stream);
     launch_pcg_check(c.mgs, c.mgpartial, np, rtol, true, c.stream);
-    for (int k = 0; k < budget; ++k) pcg_iteration(c, c.lv, c.mgs, v, rtol, k);
+    // the last iteration's check counts the solve if it ends short of rtol
+    // (pic_stats.mg_unconverged)
+    for (int k = 0; k < budget; ++k)
+        pcg_iteration(c, c.lv, c.mgs, v, rtol, k, k == budget - 1 ? c.stats + ST_MGUNCONV : nullptr);
     if (c.cfg.nturns > 0)
         launch_face_charge(c.phi, c.fp, c.fq, c.fk, c.fc, c.nfaces, c.Qk, c.cfg.nturns, c.stream);
     timer_stop(c, c.t_poisson);
@@ -964,12 +979,12 @@ static pic_status build_levels(pic_ctx &c, MGLevels &lv, const Coeffs &co, const
 // K u = src for one inductive field x (free nodes), b = -mu0 w R src in
 // hb: CG on the R-weighted symmetric operator with multigrid preconditioning,
 // in chunks of iterations with a convergence check between chunks.
-static pic_status helm_solve(pic_ctx &c, double *x, int *cycles, double *rel)
+static pic_status helm_solve(pic_ctx &c, double *x, int *cycles, double *rel, double rtol = 0.0, int maxc = 0)
 {
     const MGLevel &L0 = c.hlv.L[0];
     const PCGVec v{x, c.hb, c.pr, c.pz, c.pp, c.pAp};
-    const double rtol = c.cfg.helm_rtol;
-    const int maxc = std::min(c.cfg.helm_max_cycles, MAX_CG);
+    if (rtol <= 0.0) rtol = c.cfg.helm_rtol;
+    maxc = std::min(maxc > 0 ? maxc : c.cfg.helm_max_cycles, MAX_CG);
     launch_pcg_begin(L0, v, c.htag, nullptr, nullptr, 0.0, 0.0, c.hgs, nullptr, 0, c.stream);
     launch_pcg_resid(L0, v, c.mgpartial, c.stream);
     launch_pcg_check(c.hgs, c.mgpartial, pcg_blocks(L0.nodes), rtol, true, c.stream);
@@ -1111,6 +1126,15 @@ static pic_status circuit_init(pic_ctx &c)
     for (int n = 0; n < nodes; ++n) htag[n] = dir[n] ? 0 : -1;
     HIPCHK(&c, cpy(c.stream, c.htag, htag.data(), nodes * 4, hipMemcpyHostToDevice));
     HIPCHK(&c, mset(c.stream, c.U, 0, (size_t)N * nodes * 8));
+    // manufactured boundary values of the unit fields (the solves keep the
+    // Dirichlet entries of their start value)
+    if (f.unit_bvals) {
+        std::vector<double> ub((size_t)N * nodes, 0.0);
+        for (int k = 0; k < N; ++k)
+            for (int n = 0; n < nodes; ++n)
+                if (dir[n]) ub[(size_t)k * nodes + n] = f.unit_bvals[(size_t)k * nodes + n];
+        HIPCHK(&c, cpy(c.stream, c.U, ub.data(), ub.size() * 8, hipMemcpyHostToDevice));
+    }
     HIPCHK(&c, mset(c.stream, c.Ep, 0, 2 * (size_t)nodes * 8));
     HIPCHK(&c, mset(c.stream, c.hgs, 0, sizeof(MGState)));
     // unit-current fields K U_k = g_k (Eq. unitfield)
@@ -1145,6 +1169,7 @@ template <typename T> static pic_status init_impl(pic_ctx &c)
     HIPCHK(&c, hipMemsetAsync(births<T>(c).rank, 0, (size_t)births<T>(c).cap * sizeof(int32_t), st));
     for (int s2 = 0; s2 < 2; ++s2) HIPCHK(&c, hipMemsetAsync(c.cq[s2].count, 0, sizeof(int32_t), st));
     HIPCHK(&c, hipMemsetAsync(c.accS, 0, 2 * (size_t)nodes * sizeof(double), st));
+    HIPCHK(&c, hipMemsetAsync(c.accW, 0, 2 * (size_t)nodes * sizeof(long long), st));
     HIPCHK(&c, hipMemsetAsync(c.phi, 0, nodes * sizeof(double), st));
     HIPCHK(&c, hipMemsetAsync(c.I, 0, nodes * sizeof(double), st));
     HIPCHK(&c, hipMemsetAsync(c.Jc, 0, nodes * sizeof(double), st));
@@ -1157,6 +1182,9 @@ template <typename T> static pic_status init_impl(pic_ctx &c)
     HIPCHK(&c, hipMemcpyAsync(c.d_ec, c.ec.data(), nodes * sizeof(double), hipMemcpyHostToDevice, st));
     HIPCHK(&c, hipMemcpyAsync(c.d_es, c.es.data(), nodes * sizeof(double), hipMemcpyHostToDevice, st));
     HIPCHK(&c, hipMemcpyAsync(c.d_tag, c.tag.data(), nodes * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    if (c.dbasis)
+        HIPCHK(&c, hipMemcpyAsync(c.dbasis, f.dir_basis, (size_t)f.nturns * nodes * sizeof(double),
+                                  hipMemcpyHostToDevice, st));
     HIPCHK(&c, hipMemcpyAsync(c.d_vc, c.vc.data(), MAX_TURNS * sizeof(double), hipMemcpyHostToDevice, st));
     HIPCHK(&c, hipMemcpyAsync(c.d_vs, c.vs.data(), MAX_TURNS * sizeof(double), hipMemcpyHostToDevice, st));
 
@@ -1377,12 +1405,43 @@ extern "C" pic_status pic_deposit(pic_ctx *c, int64_t n1)
     return hipGetLastError() == hipSuccess ? PIC_OK : fail(c, PIC_EDEVICE, "kernel launch failed");
 }
 
-extern "C" pic_status poisson_solve_rz(pic_ctx *c, int64_t n, double rtol, int32_t max_cycles, pic_solve_info *info)
+// one plasma-only inductive field from the open period's harmonics:
+// which = 0: K E_c^p = J_s / V, which = 1: K E_s^sto,p = J_c / V
+static pic_status plasma_field(pic_ctx &c, int which, double rtol, int max_cycles, int *cycles, double *rel)
+{
+    const double mw = c.cfg.mu0 * TWO_PI * c.cfg.freq;
+    const uint8_t *hdir = c.hlv.L[0].dir;
+    if (which == 0)
+        launch_helm_rhs(c.Js, c.Jsc, 2.0 / c.nrf, hdir, mw, c.hb, c.g, c.stream);
+    else
+        launch_helm_rhs(c.Jc, c.Jcc, 2.0 / c.nrf, hdir, mw, c.hb, c.g, c.stream);
+    return helm_solve(c, c.Ep + (size_t)which * c.g.nodes, cycles, rel, rtol, max_cycles);
+}
+
+extern "C" pic_status poisson_solve_rz(pic_ctx *c, int64_t n, int32_t op, double rtol, int32_t max_cycles,
+                                       pic_solve_info *info)
 {
     if (!c) return PIC_EINVAL;
-    if (rtol <= 0) rtol = c->cfg.mg_rtol;
-    if (max_cycles <= 0) max_cycles = c->cfg.mg_max_cycles;
-    return solve(*c, n, rtol, max_cycles, info);
+    if (op == PIC_OP_POISSON) {
+        if (rtol <= 0) rtol = c->cfg.mg_rtol;
+        if (max_cycles <= 0) max_cycles = c->cfg.mg_max_cycles;
+        return solve(*c, n, rtol, max_cycles, info);
+    }
+    if (op != PIC_OP_HELMHOLTZ_C && op != PIC_OP_HELMHOLTZ_S) return fail(c, PIC_EINVAL, "unknown operator %d", op);
+    if (!c->cfg.circuit) return fail(c, PIC_EINVAL, "inductive solves need a coupled context");
+    pic_status st = sticky(c);
+    if (st) return st;
+    if (rtol <= 0) rtol = c->cfg.helm_rtol;
+    if (max_cycles <= 0) max_cycles = c->cfg.helm_max_cycles;
+    int cyc = 0;
+    double rel = 0.0;
+    st = plasma_field(*c, op == PIC_OP_HELMHOLTZ_C ? 0 : 1, rtol, std::min<int>(max_cycles, MAX_CG), &cyc, &rel);
+    if (info) {
+        info->cycles = cyc;
+        info->converged = st == PIC_OK;
+        info->rel_residual = rel;
+    }
+    return st;
 }
 
 extern "C" pic_status harmonic_accumulate(pic_ctx *c, int64_t n)
@@ -1445,8 +1504,8 @@ extern "C" pic_status pic_attach_surrogate(pic_ctx *c, mlp_ctx *net, const pic_s
         return PIC_OK;
     }
     if (!c->cfg.circuit) return fail(c, PIC_EINVAL, "surrogate needs a coupled context");
-    if (!sc || !(sc->err_max > 0.0) || !(sc->tol > 0.0) || sc->max_iter < 1)
-        return fail(c, PIC_EINVAL, "surrogate settings invalid");
+    if (!sc || !(sc->err_max > 0.0) || !(sc->tol > 0.0) || sc->max_iter < 1 || sc->max_iter > SUR_MAX_ITER)
+        return fail(c, PIC_EINVAL, "surrogate settings invalid (max_iter 1..%d)", SUR_MAX_ITER);
     const int N = c->cfg.nturns;
     if (N > SUR_MAX_TURNS) return fail(c, PIC_EINVAL, "surrogate supports at most %d turns", SUR_MAX_TURNS);
     int n_in = 0, n_out = 0;
@@ -1478,14 +1537,18 @@ static pic_status reset_period(pic_ctx *c)
     return PIC_OK;
 }
 
-extern "C" pic_status circuit_period_update(pic_ctx *c, const double *new_vc, const double *new_vs,
-                                            const double *new_ec, const double *new_es, pic_period_report *rep,
+extern "C" pic_status circuit_period_update(pic_ctx *c, const pic_circuit_override *ovr, pic_period_report *rep,
                                             double *jc, double *js)
 {
     if (!c) return PIC_EINVAL;
     const bool coupled = c->cfg.circuit != 0;
+    const double *new_vc = ovr ? ovr->new_vc : nullptr, *new_vs = ovr ? ovr->new_vs : nullptr;
+    const double *new_ec = ovr ? ovr->new_ec : nullptr, *new_es = ovr ? ovr->new_es_sto : nullptr;
+    const bool loads = ovr && ovr->loads;
     if (coupled && (new_vc || new_vs || new_ec || new_es))
         return fail(c, PIC_EINVAL, "a coupled context derives turn potentials and field itself");
+    if (loads && !coupled) return fail(c, PIC_EINVAL, "prescribed loads need a coupled context");
+    if (loads && c->net) return fail(c, PIC_EINVAL, "prescribed loads and an attached surrogate exclude each other");
     pic_status st = sticky(c);
     if (st) return st;
     int32_t samples = 0;
@@ -1505,14 +1568,10 @@ extern "C" pic_status circuit_period_update(pic_ctx *c, const double *new_vc, co
     timer_start(*c, c->t_circuit);
     if (coupled) {
         // plasma-only fields from the current harmonics (Eq. helmholtz_two_real)
-        const double mw = c->cfg.mu0 * TWO_PI * c->cfg.freq;
-        const uint8_t *hdir = c->hlv.L[0].dir;
-        launch_helm_rhs(c->Js, c->Jsc, 2.0 / N, hdir, mw, c->hb, c->g, c->stream);
-        st = helm_solve(*c, c->Ep, &c->helm_cycles[0], &c->helm_rel[0]);
-        if (st) return st;
-        launch_helm_rhs(c->Jc, c->Jcc, 2.0 / N, hdir, mw, c->hb, c->g, c->stream);
-        st = helm_solve(*c, c->Ep + nodes, &c->helm_cycles[1], &c->helm_rel[1]);
-        if (st) return st;
+        for (int q = 0; q < 2; ++q) {
+            st = plasma_field(*c, q, 0.0, 0, &c->helm_cycles[q], &c->helm_rel[q]);
+            if (st) return st;
+        }
         launch_project(c->Ep, 2, nodes, c->plist, c->pturn, c->nlist, c->gval, K,
                        reinterpret_cast<double *>(reinterpret_cast<char *>(c->cd) + offsetof(CircuitDev, proj)), 2,
                        c->g, c->stream);
@@ -1533,6 +1592,20 @@ extern "C" pic_status circuit_period_update(pic_ctx *c, const double *new_vc, co
                       sizeof(c->cdh.x_re) + sizeof(c->cdh.x_im), hipMemcpyDeviceToHost));
         double xp[2 * MAX_X];
         std::memcpy(xp, c->cdh.x_re, sizeof xp);
+        if (loads) {
+            // prescribed loads, taken by the update kernel in place of the measured ones
+            CircuitDev &h = c->cdh;
+            h.ovr_loads = 1;
+            for (int k = 0; k < MAX_TURNS; ++k) {
+                h.ovr_vp_re[k] = k < K ? ovr->vp_re[k] : 0.0;
+                h.ovr_vp_im[k] = k < K ? ovr->vp_im[k] : 0.0;
+                h.ovr_icap_re[k] = k < K ? ovr->icap_re[k] : 0.0;
+                h.ovr_icap_im[k] = k < K ? ovr->icap_im[k] : 0.0;
+            }
+            const size_t o0 = offsetof(CircuitDev, ovr_loads), o1 = offsetof(CircuitDev, ovr_icap_im) + sizeof h.ovr_icap_im;
+            HIPCHK(c, cpy(c->stream, reinterpret_cast<char *>(c->cd) + o0, reinterpret_cast<const char *>(&h) + o0,
+                          o1 - o0, hipMemcpyHostToDevice));
+        }
         if (c->net) {
             st = surrogate_update(*c);
             if (st) return st;
@@ -1592,6 +1665,8 @@ extern "C" pic_status circuit_period_update(pic_ctx *c, const double *new_vc, co
             rep->sur_used = c->net ? h.sur_used : 0;
             rep->sur_iters = c->net ? h.sur_iters : 0;
             rep->sur_err = c->net ? h.sur_err : 0.0;
+            if (c->net && h.sur_used)
+                for (int q = 0; q < std::min(h.sur_iters, SUR_MAX_ITER); ++q) rep->sur_steps[q] = h.sur_hist[q];
         }
     }
     if (jc || js) {
@@ -1623,7 +1698,183 @@ extern "C" pic_status circuit_period_update(pic_ctx *c, const double *new_vc, co
             HIPCHK(c, cpy(c->stream, c->d_es, new_es, nodes * 8, hipMemcpyHostToDevice));
         }
     }
+    // the turn potentials move by a whole period's correction: the next
+    // Poisson solve gets its full iteration budget
+    c->mg_fresh = true;
     return reset_period(c);
+}
+
+// ---------------------------------------------------------------------------
+// Checkpoint / restore of the whole time-dependent state at a step boundary
+// (the restart of the paper's Appendix A checks).  Everything pic_init
+// derives from the configuration alone (operators, multigrid hierarchies,
+// unit fields, Z_vac, null-collision constants) is rebuilt by pic_init of
+// the restoring context and not stored.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr uint64_t CKPT_MAGIC = 0x3143504349504850ull;   // "PHPICPC1"
+struct CkptHead {
+    uint64_t magic;
+    int32_t precision, nr, nz, nturns, circuit, nrf;
+    int64_t capacity[2], count[2];
+    int64_t last_push, last_harm, last_mcc, last_solve;
+    int32_t run, mg_budget;
+    double qscale, jscale;
+    uint64_t total;
+};
+struct Seg {
+    void *p;
+    size_t n;
+};
+}  // namespace
+
+// device arrays of the state, in storage order (count[s] particle slots)
+static std::vector<Seg> state_segments(pic_ctx &c, const int64_t count[2])
+{
+    std::vector<Seg> v;
+    const int nodes = c.g.nodes;
+    const size_t es = c.mixed ? sizeof(float) : sizeof(double);
+    for (int s = 0; s < 2; ++s) {
+        void *p[6];
+        int32_t *cell, *next;
+        uint32_t *id;
+        if (c.mixed) {
+            const Parts<float> &q = c.pf[s][c.cur[s]];
+            cell = q.cell, id = q.id, next = q.next;
+            p[0] = q.dr, p[1] = q.dz, p[2] = q.vr, p[3] = q.vt, p[4] = q.vz;
+        } else {
+            const Parts<double> &q = c.pd[s][c.cur[s]];
+            cell = q.cell, id = q.id, next = q.next;
+            p[0] = q.dr, p[1] = q.dz, p[2] = q.vr, p[3] = q.vt, p[4] = q.vz;
+        }
+        const size_t n = (size_t)count[s];
+        v.push_back({cell, n * 4});
+        for (int k = 0; k < 5; ++k) v.push_back({p[k], n * es});
+        v.push_back({id, n * 4});
+        v.push_back({next, n * 4});
+    }
+    const size_t nb = (size_t)nodes * sizeof(double);
+    v.push_back({c.ctl, 8 * sizeof(int64_t)});
+    v.push_back({c.stats, ST_NSTAT * sizeof(unsigned long long)});
+    v.push_back({c.phi, nb});
+    v.push_back({c.phi_prev, 2 * nb});
+    v.push_back({c.Q, nb});
+    v.push_back({c.I, nb});
+    v.push_back({c.accS, 2 * nb});
+    v.push_back({c.Qk, MAX_TURNS * sizeof(double)});
+    v.push_back({c.Jc, nb});
+    v.push_back({c.Jcc, nb});
+    v.push_back({c.Js, nb});
+    v.push_back({c.Jsc, nb});
+    v.push_back({c.harm, sizeof(HarmState)});
+    v.push_back({c.d_vc, MAX_TURNS * sizeof(double)});
+    v.push_back({c.d_vs, MAX_TURNS * sizeof(double)});
+    v.push_back({c.d_ec, nb});
+    v.push_back({c.d_es, nb});
+    if (c.cfg.circuit) {
+        v.push_back({c.Ep, 2 * nb});
+        v.push_back({c.cd, sizeof(CircuitDev)});
+    }
+    return v;
+}
+
+extern "C" pic_status pic_checkpoint(pic_ctx *c, void *buf, size_t cap, size_t *bytes)
+{
+    if (!c || !bytes) return PIC_EINVAL;
+    pic_status st = sticky(c);
+    if (st) return st;
+    if (c->last_push != c->last_solve - 1 || c->last_mcc != c->last_push)
+        return fail(c, PIC_ESTATE, "checkpoint between the calls of a step (last push %lld, solve %lld)",
+                    (long long)c->last_push, (long long)c->last_solve);
+    CkptHead h{};
+    h.magic = CKPT_MAGIC;
+    h.precision = c->cfg.precision;
+    h.nr = c->cfg.nr;
+    h.nz = c->cfg.nz;
+    h.nturns = c->cfg.nturns;
+    h.circuit = c->cfg.circuit;
+    h.nrf = c->nrf;
+    HIPCHK(c, cpy(c->stream, h.count, c->ctl, 2 * sizeof(int64_t), hipMemcpyDeviceToHost));
+    for (int s = 0; s < 2; ++s) h.capacity[s] = c->cfg.capacity[s];
+    h.last_push = c->last_push;
+    h.last_harm = c->last_harm;
+    h.last_mcc = c->last_mcc;
+    h.last_solve = c->last_solve;
+    h.run = c->run;
+    h.mg_budget = c->mg_budget;
+    h.qscale = c->qscale;
+    h.jscale = c->jscale;
+    const std::vector<Seg> segs = state_segments(*c, h.count);
+    size_t total = sizeof h;
+    for (const Seg &s : segs) total += s.n;
+    h.total = total;
+    *bytes = total;
+    if (!buf) return PIC_OK;
+    if (cap < total) return fail(c, PIC_ENOMEM, "checkpoint needs %zu bytes, buffer has %zu", total, cap);
+    char *o = static_cast<char *>(buf);
+    std::memcpy(o, &h, sizeof h);
+    o += sizeof h;
+    for (const Seg &s : segs) {
+        if (s.n) HIPCHK(c, hipMemcpyAsync(o, s.p, s.n, hipMemcpyDeviceToHost, c->stream));
+        o += s.n;
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return PIC_OK;
+}
+
+extern "C" pic_status pic_restore(pic_ctx *c, const void *buf, size_t bytes)
+{
+    if (!c || !buf) return PIC_EINVAL;
+    CkptHead h;
+    if (bytes < sizeof h) return fail(c, PIC_EINVAL, "checkpoint too short");
+    std::memcpy(&h, buf, sizeof h);
+    if (h.magic != CKPT_MAGIC) return fail(c, PIC_EINVAL, "not a checkpoint of this library");
+    if (h.total != bytes) return fail(c, PIC_EINVAL, "checkpoint of %llu bytes given %zu", (unsigned long long)h.total, bytes);
+    const pic_config &f = c->cfg;
+    if (h.precision != f.precision || h.nr != f.nr || h.nz != f.nz || h.nturns != f.nturns || h.circuit != f.circuit ||
+        h.nrf != c->nrf || h.qscale != c->qscale || h.jscale != c->jscale)
+        return fail(c, PIC_EINVAL, "checkpoint taken with another configuration");
+    for (int s = 0; s < 2; ++s)
+        if (h.count[s] > f.capacity[s]) return fail(c, PIC_ENOMEM, "checkpoint holds %lld slots of species %d, capacity %lld",
+                                                    (long long)h.count[s], s, (long long)f.capacity[s]);
+    pic_status st = sticky(c);
+    if (st) return st;
+    const std::vector<Seg> segs = state_segments(*c, h.count);
+    size_t total = sizeof h;
+    for (const Seg &s : segs) total += s.n;
+    if (total != bytes) return fail(c, PIC_EINVAL, "checkpoint layout does not match this context");
+    const char *in = static_cast<const char *>(buf) + sizeof h;
+    for (const Seg &s : segs) {
+        if (s.n) HIPCHK(c, hipMemcpyAsync(s.p, in, s.n, hipMemcpyHostToDevice, c->stream));
+        in += s.n;
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->last_push = h.last_push;
+    c->last_harm = h.last_harm;
+    c->last_mcc = h.last_mcc;
+    c->last_solve = h.last_solve;
+    c->run = h.run;
+    c->mg_budget = h.mg_budget;
+    c->mg_fresh = true;
+    // host mirrors of what the device arrays now hold
+    HIPCHK(c, cpy(c->stream, c->vc.data(), c->d_vc, MAX_TURNS * sizeof(double), hipMemcpyDeviceToHost));
+    HIPCHK(c, cpy(c->stream, c->vs.data(), c->d_vs, MAX_TURNS * sizeof(double), hipMemcpyDeviceToHost));
+    HIPCHK(c, cpy(c->stream, c->ec.data(), c->d_ec, (size_t)c->g.nodes * sizeof(double), hipMemcpyDeviceToHost));
+    HIPCHK(c, cpy(c->stream, c->es.data(), c->d_es, (size_t)c->g.nodes * sizeof(double), hipMemcpyDeviceToHost));
+    if (f.circuit) {
+        // the surrogate settings belong to the attachment, not the state
+        const int32_t mi = c->cdh.sur_max_iter;
+        const double em = c->cdh.sur_err_max, tl = c->cdh.sur_tol;
+        HIPCHK(c, cpy(c->stream, &c->cdh, c->cd, sizeof(CircuitDev), hipMemcpyDeviceToHost));
+        c->cdh.sur_max_iter = mi;
+        c->cdh.sur_err_max = em;
+        c->cdh.sur_tol = tl;
+        char *d = reinterpret_cast<char *>(c->cd);
+        HIPCHK(c, cpy(c->stream, d + offsetof(CircuitDev, sur_max_iter), &mi, 4, hipMemcpyHostToDevice));
+        HIPCHK(c, cpy(c->stream, d + offsetof(CircuitDev, sur_err_max), &em, 8, hipMemcpyHostToDevice));
+        HIPCHK(c, cpy(c->stream, d + offsetof(CircuitDev, sur_tol), &tl, 8, hipMemcpyHostToDevice));
+    }
+    return PIC_OK;
 }
 
 extern "C" pic_status pic_get_circuit(pic_ctx *c, pic_circuit_info *o)
@@ -1939,6 +2190,7 @@ extern "C" pic_status pic_get_stats(pic_ctx *c, pic_stats *o)
     o->events[1][1] = (int64_t)st[ST_EV11];
     o->births = (int64_t)st[ST_BIRTHS];
     o->window_out = (int64_t)st[ST_WINOUT];
+    o->mg_unconverged = (int64_t)st[ST_MGUNCONV];
     HarmState h;
     HIPCHK(c, cpy(c->stream, &h, c->harm, sizeof h, hipMemcpyDeviceToHost));
     o->samples = h.samples;

@@ -19,7 +19,7 @@ namespace pic {
 // ---------------------------------------------------------------------------
 
 // b = -mu0 w R_j (scale (acc + comp)) / V_node on free nodes; V_node is the
-// node's control volume clipped to the domain.
+// integral of the node's weight (node_volume).
 __global__ void k_helm_rhs(const double *acc, const double *comp, double scale, const uint8_t *dir, double mw,
                            double *b, GridC g)
 {
@@ -30,11 +30,7 @@ __global__ void k_helm_rhs(const double *acc, const double *comp, double scale, 
         return;
     }
     const int i = n / g.nr1, j = n - i * g.nr1;
-    const double R = j * g.dr;
-    const double lo = fmax(R - 0.5 * g.dr, 0.0), hi = fmin(R + 0.5 * g.dr, g.nr * g.dr);
-    const double zl = fmax((i - 0.5) * g.dz, 0.0), zh = fmin((i + 0.5) * g.dz, g.nz * g.dz);
-    const double vol = 3.141592653589793 * (hi * hi - lo * lo) * (zh - zl);
-    b[n] = -mw * R * (scale * (acc[n] + comp[n])) / vol;
+    b[n] = -mw * (j * g.dr) * (scale * (acc[n] + comp[n])) / node_volume(g, i, j);
 }
 
 // b = -mu0 w R_j g_k on the nodes of turn k (tag k + 1), 0 elsewhere
@@ -274,13 +270,23 @@ __device__ void finalize_period(CircuitDev &c, const HarmState *h, const double 
 }
 
 // loads of the completed period (Eq. vpind) and its powers (Eqs. pport,
-// pbalance, power_imbalance), thread 0
+// pbalance, power_imbalance), thread 0.  Prescribed loads (a circuit
+// override) replace the measured V_p and I_cap; the powers stay measured.
 __device__ void measure_period(CircuitDev &c)
 {
     const int N = c.N;
     for (int k = 0; k < N; ++k) {
         c.vp_re[k] = -c.proj[2 * k];
         c.vp_im[k] = -c.proj[2 * k + 1];
+    }
+    if (c.ovr_loads) {
+        for (int k = 0; k < N; ++k) {
+            c.vp_re[k] = c.ovr_vp_re[k];
+            c.vp_im[k] = c.ovr_vp_im[k];
+            c.icap_re[k] = c.ovr_icap_re[k];
+            c.icap_im[k] = c.ovr_icap_im[k];
+        }
+        c.ovr_loads = 0;
     }
     c.p_port = 0.5 * (c.x_re[1 + N] * c.x_re[0] + c.x_im[1 + N] * c.x_im[0]);
     double pcu = 0.0;
@@ -525,6 +531,7 @@ __global__ __launch_bounds__(64) void k_surrogate(CircuitDev *cdp, const float *
         }
         c.sur_iters += 1;
         c.sur_step = sqrt(dn / (xn > 0.0 ? xn : 1.0));
+        if (c.sur_iters <= SUR_MAX_ITER) c.sur_hist[c.sur_iters - 1] = c.sur_step;
         // an iterate far outside the period's state means the predicted load
         // map does not contract here: the plain update runs instead
         double x0 = 0.0;

@@ -47,13 +47,25 @@ __global__ void k_stage(const double *phi, const double *ec, const double *es, d
     }
 }
 
-// node charge = sum_s q_s w_s (accQ_s / 2^kQ + accS_s)
-__global__ void k_finalize_q(const long long *accQ, const double *accS, double cq0, double cq1, double cs0,
-                             double cs1, double *Q, int nodes)
+// node charge = sum_s q_s w_s (accQ_s / 2^kQ + accS_s), after the step's
+// window charge accW_s / 2^kQ (fixed point) has joined the persistent FP64
+// window sums accS_s (one add per node and step, in a fixed order)
+__global__ void k_finalize_q(const long long *accQ, long long *accW, double *accS, double inv_scale, double cq0,
+                             double cq1, double cs0, double cs1, double *Q, int nodes)
 {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= nodes) return;
-    Q[n] = (cq0 * (double)accQ[n] + cq1 * (double)accQ[nodes + n]) + (cs0 * accS[n] + cs1 * accS[nodes + n]);
+    const long long w0 = accW[n], w1 = accW[nodes + n];
+    double s0 = accS[n], s1 = accS[nodes + n];
+    if (w0 | w1) {
+        s0 += (double)w0 * inv_scale;
+        s1 += (double)w1 * inv_scale;
+        accS[n] = s0;
+        accS[nodes + n] = s1;
+        accW[n] = 0;
+        accW[nodes + n] = 0;
+    }
+    Q[n] = (cq0 * (double)accQ[n] + cq1 * (double)accQ[nodes + n]) + (cs0 * s0 + cs1 * s1);
 }
 
 __device__ __forceinline__ void neumaier(double &sum, double &comp, double x)
@@ -447,7 +459,7 @@ __device__ __forceinline__ double fold_partials(const double *part, int np, int 
 // order 2 gives 3 phi^n - 3 phi^{n-1} + phi^{n-2}; the stored solutions then
 // shift by one; state reset.
 __global__ void k_pcg_begin(MGLevel L, PCGVec v, const int32_t *tag, const double *vc, const double *vs, double cs,
-                            double sn, MGState *st, double *prev, int order)
+                            double sn, MGState *st, double *prev, int order, const double *basis, int nturns)
 {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n == 0) {
@@ -460,6 +472,11 @@ __global__ void k_pcg_begin(MGLevel L, PCGVec v, const int32_t *tag, const doubl
     const int k = tag[n];
     if (k >= 1) {
         v.x[n] = vc[k - 1] * cs + vs[k - 1] * sn;
+    } else if (k == 0 && basis) {
+        // manufactured boundary: linear in the turn potentials
+        double s = 0.0;
+        for (int q = 0; q < nturns; ++q) s += basis[(size_t)q * L.nodes + n] * (vc[q] * cs + vs[q] * sn);
+        v.x[n] = s;
     } else if (k < 0 && prev) {
         double *prev2 = prev + L.nodes;
         const double cur = v.x[n], p1 = prev[n];
@@ -508,7 +525,10 @@ __global__ __launch_bounds__(256) void k_pcg_resid(MGLevel L, PCGVec v, double *
 
 // One block: convergence test on the residual partials (k_pcg_resid at the
 // start of a solve, k_pcg_update afterwards); counts the iteration.
-__global__ __launch_bounds__(256) void k_pcg_check(MGState *st, const double *partial, int np, double rtol, int first)
+// unconv (nullable, given to the last check of a solve): counts the solve
+// when its iteration budget ran out before rtol was met
+__global__ __launch_bounds__(256) void k_pcg_check(MGState *st, const double *partial, int np, double rtol, int first,
+                                                   unsigned long long *unconv)
 {
     if (st->done) return;
     const double R = fold_partials(partial, np, 2, true);
@@ -519,6 +539,7 @@ __global__ __launch_bounds__(256) void k_pcg_check(MGState *st, const double *pa
     st->cycles += 1;
     st->rel = R / scale;
     if (R == 0.0 || st->rel <= rtol) st->done = 1;
+    else if (unconv) atomicAdd(unconv, 1ull);
 }
 
 // partials of r.z when the V-cycle is the dense solve alone (no smoother)
@@ -623,11 +644,11 @@ template void launch_stage<float>(const double *, const double *, const double *
 template void launch_stage<double>(const double *, const double *, const double *, double, double, double4 *,
                                    long long *, long long *, bool, const GridC &, hipStream_t);
 
-void launch_finalize_q(const long long *accQ, const double *accS, double cq0, double cq1, double cs0, double cs1,
-                       double *Q, int nodes, hipStream_t st)
+void launch_finalize_q(const long long *accQ, long long *accW, double *accS, double inv_scale, double cq0, double cq1,
+                       double cs0, double cs1, double *Q, int nodes, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_finalize_q, dim3(nblk(nodes, 256)), dim3(256), 0, st, accQ, accS, cq0, cq1, cs0, cs1, Q,
-                       nodes);
+    hipLaunchKernelGGL(k_finalize_q, dim3(nblk(nodes, 256)), dim3(256), 0, st, accQ, accW, accS, inv_scale, cq0, cq1,
+                       cs0, cs1, Q, nodes);
 }
 
 void launch_harmonic(const long long *accJ, double cj0, double cj1, const double *ec, const double *es, double cs,
@@ -693,18 +714,20 @@ void launch_gauss_jordan(double *A, int n, double *rowk, double *colk, hipStream
 }
 int pcg_blocks(int nodes) { return (int)red_grid(nodes); }
 void launch_pcg_begin(const MGLevel &L, const PCGVec &v, const int32_t *tag, const double *vc, const double *vs,
-                      double cs, double sn, MGState *st, double *prev, int order, hipStream_t s)
+                      double cs, double sn, MGState *st, double *prev, int order, hipStream_t s, const double *basis,
+                      int nturns)
 {
     hipLaunchKernelGGL(k_pcg_begin, dim3(nblk(L.nodes, 256)), dim3(256), 0, s, L, v, tag, vc, vs, cs, sn, st, prev,
-                       order);
+                       order, basis, nturns);
 }
 void launch_pcg_resid(const MGLevel &L, const PCGVec &v, double *partial, hipStream_t s)
 {
     hipLaunchKernelGGL(k_pcg_resid, dim3(red_grid(L.nodes)), dim3(256), 0, s, L, v, partial);
 }
-void launch_pcg_check(MGState *st, const double *partial, int np, double rtol, bool first, hipStream_t s)
+void launch_pcg_check(MGState *st, const double *partial, int np, double rtol, bool first, hipStream_t s,
+                      unsigned long long *unconv)
 {
-    hipLaunchKernelGGL(k_pcg_check, dim3(1), dim3(256), 0, s, st, partial, np, rtol, first ? 1 : 0);
+    hipLaunchKernelGGL(k_pcg_check, dim3(1), dim3(256), 0, s, st, partial, np, rtol, first ? 1 : 0, unconv);
 }
 void launch_pcg_rz(const MGLevel &L, const PCGVec &v, const MGState *st, double *partial, hipStream_t s)
 {

@@ -45,6 +45,7 @@ enum StatSlot {
     ST_ABS0, ST_ABS1,
     ST_OVER0, ST_OVER1,
     ST_WINOUT,
+    ST_MGUNCONV,                        // Poisson solves that ended before rtol
     ST_NSTAT
 };
 
@@ -56,6 +57,18 @@ struct GridC {
     double dr, dz;
     float inv_nr;      // 1 / nr, for the cell -> (i, j) split
 };
+
+// Integral of node (i, j)'s weight over the domain: pi (R_{j+1}^2 -
+// R_{j-1}^2) / 2 radially for the R^2-linear weight (neighbour radii clipped
+// to [0, R_max], so pi dR^2 / 2 on the axis), times dz axially (dz / 2 on
+// the end rows).  I / V and q w W / V are then the current and particle
+// densities the gather/deposit weight sees.
+__device__ __forceinline__ double node_volume(const GridC &g, int i, int j)
+{
+    const double hi = (double)min(j + 1, g.nr) * g.dr, lo = (double)max(j - 1, 0) * g.dr;
+    const double h = (i == 0 || i == g.nz) ? 0.5 * g.dz : g.dz;
+    return 1.5707963267948966 * (hi * hi - lo * lo) * h;
+}
 
 // cell -> (i, j) with i = floor(cell / nr): (cell + 1/2) / nr is at least
 // 1/(2 nr) from an integer and the FP32 product errs by < nz 2^-23, so the
@@ -124,7 +137,7 @@ template <typename T> struct PassArgs {
     const typename Field4<T>::type *ef;
     long long *accJ;                   // this species' current accumulator
     long long *accQ;                   // this species' charge accumulator
-    double *accS;                      // this species' window charge (weights, FP64)
+    long long *accW;                   // this species' window charge of the step (weights, fixed point)
     unsigned long long *stats;
     int32_t *err;
     GridC g;
@@ -176,6 +189,7 @@ struct MGState {
 };
 
 constexpr int MAX_TURNS = 16;
+constexpr int SUR_MAX_ITER = 64;        // inner iterations of the surrogate-assisted update at most
 // Open-period accumulators (compensated sums: value + correction).
 struct HarmState {
     int32_t samples, pad;
@@ -221,6 +235,10 @@ struct CircuitDev {
     double xa_re[MAX_X], xa_im[MAX_X];
     double vg_acc;
     int32_t sur_navg, pad2;
+    double sur_hist[SUR_MAX_ITER];          // relative step of each inner iterate
+    // prescribed load responses of the next update (circuit override)
+    int32_t ovr_loads, pad3;
+    double ovr_vp_re[MAX_TURNS], ovr_vp_im[MAX_TURNS], ovr_icap_re[MAX_TURNS], ovr_icap_im[MAX_TURNS];
 };
 
 // features of the surrogate network: (I_k re, im), (V_k re, im), pressure,

@@ -37,8 +37,8 @@ template <typename T>
 void launch_stage(const double *phi, const double *ec, const double *es, double cs, double sn,
                   typename Field4<T>::type *ef, long long *accJ, long long *accQ, bool clear_q, const GridC &g,
                   hipStream_t st);
-void launch_finalize_q(const long long *accQ, const double *accS, double cq0, double cq1, double cs0, double cs1,
-                       double *Q, int nodes, hipStream_t st);
+void launch_finalize_q(const long long *accQ, long long *accW, double *accS, double inv_scale, double cq0, double cq1,
+                       double cs0, double cs1, double *Q, int nodes, hipStream_t st);
 void launch_harmonic(const long long *accJ, double cj0, double cj1, const double *ec, const double *es, double cs,
                      double sn, double *I, double *Jc, double *Jcc, double *Js, double *Jsc, double *partial,
                      HarmState *h, const double *Qk, const double *vc, const double *vs, int nturns, int nodes,
@@ -66,9 +66,11 @@ int dense_ld(int n);
 void launch_gauss_jordan(double *A, int n, double *rowk, double *colk, hipStream_t s);
 int pcg_blocks(int nodes);
 void launch_pcg_begin(const MGLevel &L, const PCGVec &v, const int32_t *tag, const double *vc, const double *vs,
-                      double cs, double sn, MGState *st, double *prev, int order, hipStream_t s);
+                      double cs, double sn, MGState *st, double *prev, int order, hipStream_t s,
+                      const double *basis = nullptr, int nturns = 0);
 void launch_pcg_resid(const MGLevel &L, const PCGVec &v, double *partial, hipStream_t s);
-void launch_pcg_check(MGState *st, const double *partial, int np, double rtol, bool first, hipStream_t s);
+void launch_pcg_check(MGState *st, const double *partial, int np, double rtol, bool first, hipStream_t s,
+                      unsigned long long *unconv = nullptr);
 void launch_pcg_rz(const MGLevel &L, const PCGVec &v, const MGState *st, double *partial, hipStream_t s);
 void launch_pcg_pmatvec(const MGLevel &L, const PCGVec &v, const double *pold, double *pnew, MGState *st,
                         double *partial, int nrz, hipStream_t s);

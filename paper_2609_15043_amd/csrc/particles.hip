@@ -227,12 +227,15 @@ __device__ __forceinline__ void deposit_lane(int i, int j, T v0, T v1, T v2, T v
 // ---------------------------------------------------------------------------
 // Wave-collective deposit of four node values around the lower-left node
 // (i, j) of each lane's run.  Lanes are grouped by cell (segmented by
-// ballot); each group's sums (wave scan, total in lane 63) are added to the
-// block's LDS window in the working precision, or, for a node outside the
-// window, straight to the global 64-bit fixed-point accumulator.  The
-// window is converted to fixed point once per touched node when the block
-// flushes it, so the global sums are exact and independent of block order.
-// Called by all 64 lanes.
+// ballot); each group's four node sums (wave scan, total in lane 63) are
+// formed in the working precision and converted to 64-bit fixed point one
+// value at a time (deposit_node) as they are added to the block's LDS
+// window, or, for a node outside the window, to the global fixed-point
+// accumulator.  The integer adds are exact and independent of order, so a
+// node's total depends only on which particles share a wave: the in-wave
+// sums round in the working precision in the particle order the cell sort
+// leaves, and the sort orders the particles within a cell by atomics, so
+// two runs may differ in the last bits.  Called by all 64 lanes.
 // ---------------------------------------------------------------------------
 // lane 63's value in every lane (a wave total after wave_total)
 __device__ __forceinline__ float lane63(float v)
@@ -627,8 +630,10 @@ __global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassPair<T> p
                             js = min(js, g.nr - 1);
                             const double w1 = (Rs * Rs - (double)js * js) / (2.0 * js + 1.0);
                             const int nd = g.ip * g.nr1 + js;
-                            atomicAdd(&a.accS[nd], 1.0 - w1);
-                            atomicAdd(&a.accS[nd + 1], w1);
+                            // fixed point, like the node charge: integer adds
+                            // are exact and independent of order
+                            atomic_add_i64(&a.accW[nd], to_fixed(1.0 - w1, a.sc.qscale));
+                            atomic_add_i64(&a.accW[nd + 1], to_fixed(w1, a.sc.qscale));
                             absorbed = 2;
                         }
                     }
@@ -1451,11 +1456,7 @@ __global__ __launch_bounds__(256) void k_moments_fold(const double *partial, int
     double m = 0.0;
     for (int n = threadIdx.x; n < g.nodes; n += blockDim.x) {
         const int i = n / g.nr1, j = n - i * g.nr1;
-        const double R = j * g.dr;
-        const double lo = fmax(R - 0.5 * g.dr, 0.0), hi = fmin(R + 0.5 * g.dr, g.nr * g.dr);
-        const double zl = fmax((i - 0.5) * g.dz, 0.0), zh = fmin((i + 0.5) * g.dz, g.nz * g.dz);
-        const double vol = 3.141592653589793 * (hi * hi - lo * lo) * (zh - zl);
-        m = fmax(m, fabs((double)accQe[n]) / qscale * we / vol);
+        m = fmax(m, fabs((double)accQe[n]) / qscale * we / node_volume(g, i, j));
     }
     red[threadIdx.x] = m;
     __syncthreads();

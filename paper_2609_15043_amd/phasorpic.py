@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libphasorpic.so")
 
 PIC_OK, PIC_EINVAL, PIC_ENOMEM, PIC_EDEVICE, PIC_ENOTCONV, PIC_EPHASE, PIC_ESTATE = 0, -1, -2, -3, -4, -5, -6
 PIC_FP64, PIC_MIXED = 0, 1
+PIC_OP_POISSON, PIC_OP_HELMHOLTZ_C, PIC_OP_HELMHOLTZ_S = 0, 1, 2
 PIC_FIELD_FULL, PIC_FIELD_MQS = 0, 1
 PIC_RRF_GIVEN, PIC_RRF_SKIN = 0, 1
 (PIC_GRID_PHI, PIC_GRID_CHARGE, PIC_GRID_CURRENT, PIC_GRID_ER, PIC_GRID_EZ, PIC_GRID_ETHETA,
@@ -49,7 +50,7 @@ class PicConfig(ctypes.Structure):
         ("vg_amp", _D), ("vg_phase", _D), ("vg_from_target", _I32), ("controller", _I32),
         ("p_target", _D), ("gamma", _D), ("n_trend", _D), ("eps_p", _D), ("alpha_v", _D), ("f_step", _D),
         ("v_min", _D), ("v_max", _D), ("alpha", _D), ("helm_rtol", _D), ("helm_max_cycles", _I32),
-        ("sort_every_ion", _I32),
+        ("sort_every_ion", _I32), ("dir_basis", _PD), ("unit_bvals", _PD),
     ]
 
 
@@ -66,7 +67,7 @@ class PicStats(ctypes.Structure):
         ("qc", _D * 16), ("qs", _D * 16), ("wk", _D * 16), ("qk", _D * 16),
         ("pass_ms", _D), ("pass_count", _I64), ("poisson_ms", _D), ("poisson_count", _I64),
         ("sort_ms", _D), ("sort_count", _I64), ("circuit_ms", _D), ("circuit_count", _I64),
-        ("mg_cycles", _I64), ("mg_rel", _D),
+        ("mg_cycles", _I64), ("mg_rel", _D), ("mg_unconverged", _I64),
     ]
 
 
@@ -78,11 +79,16 @@ class PicPeriodReport(ctypes.Structure):
                 ("vp_re", _D * 16), ("vp_im", _D * 16), ("xt_re", _D * 33), ("xt_im", _D * 33),
                 ("x_re", _D * 33), ("x_im", _D * 33), ("helm_cycles", _I32 * 2), ("helm_rel", _D * 2),
                 ("xp_re", _D * 33), ("xp_im", _D * 33), ("pressure", _D), ("moments", _D * 8),
-                ("sur_used", _I32), ("sur_iters", _I32), ("sur_err", _D)]
+                ("sur_used", _I32), ("sur_iters", _I32), ("sur_err", _D), ("sur_steps", _D * 64)]
 
 
 class PicSurrogateConfig(ctypes.Structure):
     _fields_ = [("err_max", _D), ("tol", _D), ("max_iter", _I32)]
+
+
+class PicCircuitOverride(ctypes.Structure):
+    _fields_ = [("new_vc", _PD), ("new_vs", _PD), ("new_ec", _PD), ("new_es_sto", _PD), ("loads", _I32),
+                ("vp_re", _D * 16), ("vp_im", _D * 16), ("icap_re", _D * 16), ("icap_im", _D * 16)]
 
 
 class PicCircuitInfo(ctypes.Structure):
@@ -105,6 +111,7 @@ SYMBOLS = ["pic_workspace_bytes", "pic_init", "pic_gather_push", "mcc_collide", 
            "pic_attach_surrogate",
            "pic_get_circuit", "pic_sync",
            "pic_clear_error", "pic_get_particles", "pic_set_particles", "pic_set_step", "pic_set_phi",
+           "pic_checkpoint", "pic_restore",
            "pic_get_grid", "pic_timing", "pic_get_stats", "pic_destroy", "pic_last_error"]
 
 
@@ -121,8 +128,9 @@ def lib():
         L.pic_init.argtypes = [ctypes.POINTER(PicConfig), P, ctypes.c_size_t, P, ctypes.POINTER(P)]
         for name in ("pic_gather_push", "mcc_collide", "pic_deposit", "harmonic_accumulate", "pic_set_step"):
             getattr(L, name).argtypes = [P, _I64]
-        L.poisson_solve_rz.argtypes = [P, _I64, _D, _I32, ctypes.POINTER(PicSolveInfo)]
-        L.circuit_period_update.argtypes = [P, _PD, _PD, _PD, _PD, ctypes.POINTER(PicPeriodReport), _PD, _PD]
+        L.poisson_solve_rz.argtypes = [P, _I64, _I32, _D, _I32, ctypes.POINTER(PicSolveInfo)]
+        L.circuit_period_update.argtypes = [P, ctypes.POINTER(PicCircuitOverride), ctypes.POINTER(PicPeriodReport),
+                                            _PD, _PD]
         L.pic_get_circuit.argtypes = [P, ctypes.POINTER(PicCircuitInfo)]
         L.pic_attach_surrogate.argtypes = [P, P, ctypes.POINTER(PicSurrogateConfig)]
         L.pic_set_source.argtypes = [P, _D, _D]
@@ -132,6 +140,8 @@ def lib():
                                         ctypes.POINTER(_I64)]
         L.pic_set_particles.argtypes = [P, _I32, _I64, _PD, _PD, _PD, _PD, _PD, _PU32, _PI32]
         L.pic_set_phi.argtypes = [P, _PD]
+        L.pic_checkpoint.argtypes = [P, ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
+        L.pic_restore.argtypes = [P, ctypes.c_void_p, ctypes.c_size_t]
         L.pic_get_grid.argtypes = [P, _I32, _PD]
         L.pic_get_stats.argtypes = [P, ctypes.POINTER(PicStats)]
         L.pic_timing.argtypes = [P, _I32]
@@ -170,7 +180,7 @@ def config_from_workload(wl, precision="mixed", fuse=True, load=True, mg_rtol=No
         c.capacity[s] = wl.capacity[s]
     for k in range(3):
         c.bfield[k] = wl.bfield[k]
-    c.ngas, c.tgas_ev, c.qe, c.eps0 = wl.ngas, wl.tgas_ev, W.QE, W.EPS0
+    c.ngas, c.tgas_ev, c.qe, c.eps0 = wl.ngas, wl.tgas_ev, W.QE, wl.eps0
     x = wl.xs
     c.xs_kind, c.nscan = x.kind, nscan
     for k, v in enumerate((x.el_a, x.el_b, x.exc_a, x.exc_th, x.iz_a, x.iz_th, x.iel_a, x.iel_p, x.icx_a,
@@ -186,6 +196,13 @@ def config_from_workload(wl, precision="mixed", fuse=True, load=True, mg_rtol=No
     c.nturns, c.fuse = wl.nturns, 1 if fuse else 0
     c.eps_cell, c.node_tag, c.ec, c.es_sto = _ptr(eps, _D), _ptr(tag, _I32), _ptr(ec, _D), _ptr(es, _D)
     c.turn_vc, c.turn_vs = _ptr(vc, _D), _ptr(vs, _D)
+    for name in ("dir_basis", "unit_bvals"):
+        a = getattr(wl, name)
+        if a is not None:
+            a = np.ascontiguousarray(a, dtype=np.float64).reshape(-1)
+            assert a.size == wl.nturns * wl.nodes
+            keep.append(a)
+            setattr(c, name, _ptr(a, _D))
     if mg_rtol is None:
         mg_rtol = 1e-13 if precision == "fp64" else 1e-9
     c.mg_rtol, c.mg_max_cycles, c.sort_every, c.load = mg_rtol, mg_max_cycles, sort_every, 1 if load else 0
@@ -273,11 +290,11 @@ def pic_deposit(ctx, n1):
     return ctx.check(lib().pic_deposit(ctx.handle, n1))
 
 
-def poisson_solve_rz(ctx, n, rtol=0.0, max_cycles=0, info=False):
+def poisson_solve_rz(ctx, n, rtol=0.0, max_cycles=0, info=False, op=PIC_OP_POISSON):
     if not info:
-        return ctx.check(lib().poisson_solve_rz(ctx.handle, n, rtol, max_cycles, None))
+        return ctx.check(lib().poisson_solve_rz(ctx.handle, n, op, rtol, max_cycles, None))
     inf = PicSolveInfo()
-    st = lib().poisson_solve_rz(ctx.handle, n, rtol, max_cycles, ctypes.byref(inf))
+    st = lib().poisson_solve_rz(ctx.handle, n, op, rtol, max_cycles, ctypes.byref(inf))
     if st not in (PIC_OK, PIC_ENOTCONV):
         ctx.check(st)
     return dict(status=st, cycles=inf.cycles, converged=inf.converged, rel_residual=inf.rel_residual)
@@ -287,15 +304,28 @@ def harmonic_accumulate(ctx, n):
     return ctx.check(lib().harmonic_accumulate(ctx.handle, n))
 
 
-def circuit_period_update(ctx, new_vc=None, new_vs=None, new_ec=None, new_es_sto=None, want_j=False):
-    """Returns (status, report dict, jc, js)."""
+def circuit_period_update(ctx, new_vc=None, new_vs=None, new_ec=None, new_es_sto=None, want_j=False,
+                          loads=None):
+    """Returns (status, report dict, jc, js).  new_*: the next period's
+    turn potentials and field of an uncoupled context; loads = (V_p, I_cap)
+    complex arrays prescribed for a coupled context's update."""
     rep = PicPeriodReport()
     arrs = [None if a is None else np.ascontiguousarray(a, dtype=np.float64) for a in
             (new_vc, new_vs, new_ec, new_es_sto)]
     jc = np.zeros(ctx.shape) if want_j else None
     js = np.zeros(ctx.shape) if want_j else None
-    st = lib().circuit_period_update(ctx.handle, *[_ptr(a, _D) for a in arrs], ctypes.byref(rep), _ptr(jc, _D),
-                                     _ptr(js, _D))
+    ovr = None
+    if any(a is not None for a in arrs) or loads is not None:
+        ovr = PicCircuitOverride()
+        ovr.new_vc, ovr.new_vs, ovr.new_ec, ovr.new_es_sto = (_ptr(a, _D) for a in arrs)
+        if loads is not None:
+            vp, icap = (np.asarray(a, dtype=complex) for a in loads)
+            ovr.loads = 1
+            for k in range(len(vp)):
+                ovr.vp_re[k], ovr.vp_im[k] = vp[k].real, vp[k].imag
+                ovr.icap_re[k], ovr.icap_im[k] = icap[k].real, icap[k].imag
+    st = lib().circuit_period_update(ctx.handle, ctypes.byref(ovr) if ovr is not None else None, ctypes.byref(rep),
+                                     _ptr(jc, _D), _ptr(js, _D))
     K = ctx.cfg.nturns
     out = dict(accepted=rep.accepted, samples=rep.samples, p_ind=rep.p_ind, p_cap=rep.p_cap, p_cap_ph=rep.p_cap_ph,
                qc=np.array(rep.qc[:K]), qs=np.array(rep.qs[:K]),
@@ -310,7 +340,7 @@ def circuit_period_update(ctx, new_vc=None, new_vs=None, new_ec=None, new_es_sto
                    helm_cycles=tuple(rep.helm_cycles), helm_rel=tuple(rep.helm_rel),
                    x_prev=np.array(rep.xp_re[:M]) + 1j * np.array(rep.xp_im[:M]), pressure=rep.pressure,
                    moments=np.array(rep.moments[:]), sur_used=rep.sur_used, sur_iters=rep.sur_iters,
-                   sur_err=rep.sur_err)
+                   sur_err=rep.sur_err, sur_steps=np.array(rep.sur_steps[:min(rep.sur_iters, 64)]))
     return st, out, jc, js
 
 
@@ -376,6 +406,20 @@ def pic_set_phi(ctx, phi):
     a = np.ascontiguousarray(phi, dtype=np.float64).reshape(-1)
     assert a.size == ctx.nodes
     return ctx.check(lib().pic_set_phi(ctx.handle, _ptr(a, _D)))
+
+
+def pic_checkpoint(ctx):
+    """The context's state at a step boundary as a bytes object."""
+    n = ctypes.c_size_t()
+    ctx.check(lib().pic_checkpoint(ctx.handle, None, 0, ctypes.byref(n)))
+    buf = ctypes.create_string_buffer(n.value)
+    ctx.check(lib().pic_checkpoint(ctx.handle, buf, n.value, ctypes.byref(n)))
+    return buf.raw[:n.value]
+
+
+def pic_restore(ctx, data):
+    buf = ctypes.create_string_buffer(bytes(data), len(data))
+    return ctx.check(lib().pic_restore(ctx.handle, buf, len(data)))
 
 
 def pic_get_grid(ctx, which):

@@ -145,6 +145,11 @@ class Workload:
     bfield: tuple = (0.0, 0.0, 0.0)   # uniform (B_r, B_theta, B_z), tests only
     xs: CrossSections = dataclasses.field(default_factory=CrossSections)
     capacity_factor: float = 1.5
+    eps0: float = EPS0                # vacuum permittivity of the Poisson operator
+    # manufactured boundaries, (N, nz+1, nr+1) each: Dirichlet value of a
+    # grounded node per volt on turn k, and of the unit field U_k
+    dir_basis: np.ndarray = None
+    unit_bvals: np.ndarray = None
 
     # derived, descriptive only
     @property
@@ -186,7 +191,7 @@ class Workload:
     @property
     def weight(self):
         vol = math.pi * self.rmax ** 2 * self.zp
-        return tuple(self.n0 * vol / n for n in self.np_init)
+        return tuple(self.n0 * vol / n if n > 0 else 1.0 for n in self.np_init)
 
     @property
     def capacity(self):
@@ -283,12 +288,84 @@ def _coil_cell(nr, nz, n_per_species, pressure_mtorr, name, seed, nsteps, coil_c
         turn_vc=vfeed, turn_vs=np.zeros(5), circuit=CircuitParams() if circuit else None)
 
 
-def cell(seed=0, n_per_species=2_000_000, nsteps=20_000, circuit=True) -> Workload:
-    return _coil_cell(128, 256, n_per_species, 20.0, "cell", seed, nsteps, circuit=circuit)
+def cell(seed=0, n_per_species=2_000_000, nsteps=20_000, circuit=True, vg_start=None) -> Workload:
+    """vg_start: start the coupled source at this amplitude (V) instead of
+    the one that puts the power target into the vacuum network.  That one
+    (3.4 kV for 60 W: 26 A in every turn, |E_theta| up to 1.4 kV/m in the
+    plasma) is right for an empty cell, but a plasma loaded into the first
+    period's vacuum field absorbs kilowatts before the circuit sees it; a
+    plasma run starts low and lets the controller raise the amplitude."""
+    wl = _coil_cell(128, 256, n_per_species, 20.0, "cell", seed, nsteps, circuit=circuit)
+    if circuit and vg_start is not None:
+        wl.circuit = dataclasses.replace(wl.circuit, vg_from_target=False, vg_amp=float(vg_start))
+    return wl
 
 
 def large(seed=0, n_per_species=32_000_000, nsteps=4_000, circuit=True) -> Workload:
     return _coil_cell(256, 512, n_per_species, 50.0, "large", seed, nsteps, circuit=circuit)
+
+
+# The paper's joint inductive-capacitive benchmark (Sec. 3.3, its parameter
+# table): five nested cylindrical sheets in a grounded shield, no particles.
+T3_A = (8e-3, 20e-3, 32e-3, 48e-3, 64e-3)     # sheet radii (m)
+T3_B, T3_ELL = 0.08, 0.1                      # shield radius, source length (m)
+T3_EPS0, T3_MU0, T3_EPSR, T3_F = 8.8542e-12, 1.2566e-6, 9.0, 13.56e6
+
+
+def t3_unit_field(k, R):
+    """Radial unit-current coefficient of sheet k (the benchmark appendix's
+    closed form, Eq. t7unitfield): the manufactured axial boundary values
+    of the unit field U_k."""
+    a, w = T3_A[k], 2 * math.pi * T3_F
+    R = np.asarray(R, dtype=np.float64)
+    inside = (1 - a ** 2 / T3_B ** 2) * R
+    outside = a ** 2 * (1 / np.maximum(R, 1e-300) - R / T3_B ** 2)
+    return -w * T3_MU0 / (2 * T3_ELL) * np.where(R <= a, inside, outside)
+
+
+def t3_potential(V, R):
+    """Radial electrostatic potential of sheet potentials V (Eq.
+    t7potential): the manufactured axial boundary values."""
+    a6 = list(T3_A) + [T3_B]
+    Vx = list(np.asarray(V, dtype=np.float64)) + [0.0]
+    R = np.asarray(R, dtype=np.float64)
+    out = np.full(R.shape, Vx[0])
+    for k in range(5):
+        m = (R > a6[k]) & (R <= a6[k + 1])
+        out[m] = (Vx[k] * np.log(a6[k + 1] / R[m]) + Vx[k + 1] * np.log(R[m] / a6[k])) / np.log(a6[k + 1] / a6[k])
+    return out
+
+
+def test3(h=1e-3, samples=400) -> Workload:
+    """Five-node manufactured benchmark at grid spacing h: sheets a_k on the
+    radial node lines R = a_k over the interior node rows, (N_z, N_R) =
+    (l/h + 2, b/h + 1) nodes, eps_r = 9, the paper's truncated eps0 and mu0,
+    V_g = 100 V behind 50 ohm, 20 ohm per segment, MQS, no controller,
+    alpha = 1, `samples` steps per RF period; axial boundary rows carry the
+    closed-form potential (per volt on each sheet) and unit fields."""
+    nr = int(round(T3_B / h))
+    nz = int(round(T3_ELL / h)) + 1
+    tag = np.full((nz + 1, nr + 1), -1, np.int32)
+    tag[0, :] = tag[nz, :] = 0
+    tag[:, nr] = 0
+    for k, a in enumerate(T3_A):
+        tag[1:nz, int(round(a / h))] = k + 1
+    R = np.arange(nr + 1) * h
+    basis = np.zeros((5, nz + 1, nr + 1))
+    ub = np.zeros((5, nz + 1, nr + 1))
+    for k in range(5):
+        basis[k, 0, :] = basis[k, nz, :] = t3_potential(np.eye(5)[k], R)
+        ub[k, 0, :] = ub[k, nz, :] = t3_unit_field(k, R)
+    basis[:, :, nr] = 0.0
+    circ = CircuitParams(mu0=T3_MU0, field_mode=FIELD_MQS, rrf_mode=RRF_GIVEN, r_rf=(20.0,) * 5, r_g=50.0,
+                         r_m=0.0, l_m=0.0, c_m=0.0, vg_amp=100.0, vg_phase=0.0, vg_from_target=False,
+                         controller=False, alpha=1.0)
+    return Workload(
+        name="test3", nr=nr, nz=nz, rmax=nr * h, zmax=nz * h, zp=h, dt=1.0 / (samples * T3_F), freq=T3_F,
+        nsteps=30 * samples, pressure_pa=1e-3 * TORR, tgas_k=300.0, n0=0.0, np_init=(0, 0), temp_ev=(1.0, 0.026),
+        seed=0, eps_cell=np.full((nz, nr), T3_EPSR), node_tag=tag, ec=np.zeros((nz + 1, nr + 1)),
+        es_sto=np.zeros((nz + 1, nr + 1)), turn_vc=np.zeros(5), turn_vs=np.zeros(5), circuit=circ,
+        eps0=T3_EPS0, dir_basis=basis, unit_bvals=ub)
 
 
 def by_name(name, **kw) -> Workload:

@@ -13,9 +13,9 @@ charge, the window surface charge and phi^1.  Prescribed inductive field
 (the circuit update is tested on the coil cell).
 
 Tolerances as for the single-step cases: mixed 1e-5 normwise per array
-(1e-4 for Q and phi, whose sums cancel) and at most 1e-4 of the particles
-on the other side of an FP32 rounding decision; FP64 1e-12 (1e-11 for Q
-and phi) with every discrete outcome exact.
+(particles, I, Q, the window charge and phi) and at most 1e-4 of the
+particles on the other side of an FP32 rounding decision; FP64 1e-12 with
+every discrete outcome exact.
 """
 import sys
 
@@ -36,7 +36,7 @@ def _need_gpu():
         pytest.skip("no GPU")
 
 
-TOL = {"mixed": (1e-5, 1e-4), "fp64": (1e-12, 1e-11)}
+TOL = {"mixed": (1e-5, 1e-5), "fp64": (1e-12, 1e-12)}
 
 
 @pytest.mark.parametrize("prec", ["mixed", "fp64"])
@@ -82,11 +82,11 @@ def test_large_step_matches_oracle(prec):
         for k in range(2 if s else 3):
             assert abs(st.events[s][k] - ora.counts[s][k + 1]) <= slack, (s, k)
     res["Q"] = rel(pp.pic_get_grid(ctx, pp.PIC_GRID_CHARGE), ora.Q)
-    assert res["Q"] <= tg, res["Q"]
     res["surf"] = rel(pp.pic_get_grid(ctx, pp.PIC_GRID_SURFACE), ora.surf)
-    assert res["surf"] <= tg, res["surf"]
     res["phi"] = rel(pp.pic_get_grid(ctx, pp.PIC_GRID_PHI), ora.phi)
-    assert info["converged"], info
-    assert res["phi"] <= tg, res["phi"]
     say("    step: " + " ".join(f"{k}={v:.1e}" if isinstance(v, float) else f"{k}={v}" for k, v in res.items())
         + f" mg_cycles={info['cycles']} candidates {st.candidates[0]}/{st.candidates[1]}")
+    assert info["converged"], info
+    for k in ("Q", "surf", "phi"):
+        assert res[k] <= tg, (k, res[k])
+    assert st.mg_unconverged == 0

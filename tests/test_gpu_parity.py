@@ -83,11 +83,12 @@ def test_load_and_initial_field_match_oracle(prec):
     for s in range(2):
         _compare_particles(pp.pic_get_particles(ctx, s), ora.live(s), prec, f"load s={s}")
     Q = pp.pic_get_grid(ctx, pp.PIC_GRID_CHARGE)
-    assert rel(Q, ora.Q) <= TOL[prec] * 10, rel(Q, ora.Q)
+    eq = rel(Q, ora.Q)
     phi = pp.pic_get_grid(ctx, pp.PIC_GRID_PHI)
     e = rel(phi, ora.phi)
-    say(f"    phi0 rel err {e:.2e}")
-    assert e <= TOL[prec] * 10
+    say(f"    Q0 rel err {eq:.2e} phi0 rel err {e:.2e}")
+    assert eq <= TOL[prec]
+    assert e <= TOL[prec]
 
 
 def _step_case(wlname, prec, fuse, n0):
@@ -126,11 +127,11 @@ def _step_case(wlname, prec, fuse, n0):
     ora.step()
     res = {}
     tol = TOL[prec]
+    bars = {}
     for name, a, b in (("Er", ger, Er), ("Ez", gez, Ez), ("Et", get, Et)):
         res[name] = rel(a, b)
-        assert res[name] <= (tol if prec == "fp64" else 1e-6), (name, res[name])
+        bars[name] = tol if prec == "fp64" else 1e-6
     res["I"] = rel(gI, ora.I)
-    assert res["I"] <= tol, ("I", res["I"])
     for s in range(2):
         errs, mism = _compare_particles(pp.pic_get_particles(ctx, s), ora.live(s), prec, f"s={s}")
         res.update({f"{k}{s}": v for k, v in errs.items()})
@@ -140,18 +141,16 @@ def _step_case(wlname, prec, fuse, n0):
         for k in range(2 if s else 3):
             assert abs(st.events[s][k] - ora.counts[s][k + 1]) <= (0 if prec == "fp64" else 2)
     res["Q"] = rel(pp.pic_get_grid(ctx, pp.PIC_GRID_CHARGE), ora.Q)
-    assert res["Q"] <= tol * 10, ("Q", res["Q"])
     if wl.window:
         res["surf"] = rel(pp.pic_get_grid(ctx, pp.PIC_GRID_SURFACE), ora.surf)
-        assert res["surf"] <= tol, ("surf", res["surf"])
     phi = pp.pic_get_grid(ctx, pp.PIC_GRID_PHI)
     res["phi"] = rel(phi, ora.phi)
-    assert info["converged"], info
-    assert res["phi"] <= tol * 10, ("phi", res["phi"])
     if wl.nturns:
         res["Qk"] = rel(np.array(st.qk[:wl.nturns]), ora.Qk)
-        assert res["Qk"] <= tol * 100, ("Qk", res["Qk"])
     say("    " + " ".join(f"{k}={v:.1e}" for k, v in res.items()) + f" mg_cycles={info['cycles']}")
+    assert info["converged"], info
+    for k, v in res.items():
+        assert v <= bars.get(k, tol), (k, v)
     return res
 
 

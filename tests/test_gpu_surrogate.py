@@ -76,24 +76,33 @@ def test_moments_match_oracle():
     assert abs(g["pressure"] - wl.pressure_pa) <= 1e-12 * wl.pressure_pa
 
 
-def test_surrogate_update_matches_oracle():
-    """Two periods of the coil cell without plasma (13.56 MHz, 16 samples
-    per period) with a network whose output layer is scaled down (its
-    prediction barely depends on the state, so the predicted load map
-    contracts) and the fallback threshold lifted: the inner fixed point,
-    with its controller steps, runs and must agree with the oracle's."""
+@pytest.mark.parametrize("w4_scale", [1e-2, 1e-6])
+def test_surrogate_update_matches_oracle(w4_scale):
+    """Three periods of the coil cell without plasma (16 samples per period,
+    controller towards 60 W) with the surrogate attached and the fallback
+    threshold lifted, against the oracle running the same periods.  With
+    the output layer scaled by 1e-2 the prediction depends on the state (an
+    untrained network: the applied state of period 3 differs by about 1 %
+    from the 1e-6 case) and the inner fixed point, with its controller
+    steps, follows it; with 1e-6 it barely does and the iteration is a
+    constant-load relaxation.  Compared per period: whether the surrogate
+    was used, its inner iteration count, the scaled prediction error at the
+    applied state, the step of every inner iterate larger than 1e-3 (to
+    1e-3 relative: below that the iterates circle the fixed point, the BF16
+    activations making the prediction a step function of the state, and
+    FP32 and FP64 accumulation may round a value across a BF16 boundary),
+    the applied state and the source amplitude."""
     _need_gpu()
-    import torch
     import paper_2609_15043_amd.phasorpic as pp
     from paper_2609_15043_amd import workloads as W
     from oracle import mlp as M
     from oracle import pic as O
     wl = W.cell(n_per_species=1000)
     wl.dt = 1.0 / (16 * wl.freq)
-    say("[gpu] surrogate-assisted update vs oracle, vacuum coil cell fp64")
+    say(f"[gpu] surrogate-assisted update vs oracle, vacuum coil cell fp64, output layer x {w4_scale:g}")
     theta = W.mlp_init_params(seed=11).astype(np.float64)
     p = M.unpack(theta, 256)
-    p["W4"] *= 1e-6
+    p["W4"] *= w4_scale
     theta = M.pack(p, 256).astype(np.float32)
     ora = O.OraclePIC(wl, load=False)
     # inputs standardised by the size of the starting features
@@ -108,15 +117,35 @@ def test_surrogate_update_matches_oracle():
     onet = M.MLP(theta.astype(np.float64), 256, 29, 20, bf16_storage=True, norm=norm)
     ora.surrogate = lambda f: onet.predict(f[None, :])[0]
     ora.sur_cfg = dict(err_max=1e9, tol=1e-10, max_iter=40)
-    g = _run_periods(ctx, ora, 16, 2)[-1]
-    o = ora.last_report
-    say(f"    used {g['sur_used']}/{o['sur_used']} iters {g['sur_iters']}/{o['sur_iters']} "
-        f"err {g['sur_err']:.3e}/{o['sur_err']:.3e} x rel {rel(g['x'], o['x']):.1e} "
-        f"vg {g['vg_amp']:.6g}/{abs(o['vg']):.6g}")
-    assert g["sur_used"] == 1 and o["sur_used"] == 1
-    assert abs(g["sur_err"] - o["sur_err"]) <= 1e-3 * o["sur_err"]
-    assert rel(g["x"], o["x"]) <= 1e-3
-    assert abs(g["vg_amp"] - abs(o["vg"])) <= 1e-3 * abs(o["vg"])
+    reports = []
+    orig = ora.period_update
+
+    def keep_report():
+        r = orig()
+        reports.append(r)
+        return r
+    ora.period_update = keep_report
+    gs = _run_periods(ctx, ora, 16, 3)
+    moved = 0.0
+    fails = []
+    assert len(gs) == len(reports) == 3
+    for k, (g, o) in enumerate(zip(gs, reports)):
+        steps_g, steps_o = g["sur_steps"], o.get("sur_steps", np.zeros(0))
+        m = min(len(steps_g), len(steps_o))
+        big = steps_o[:m] > 1e-3
+        step_err = rel(steps_g[:m][big], steps_o[:m][big]) if big.any() else 0.0
+        xerr, vgerr = rel(g["x"], o["x"]), abs(g["vg_amp"] - abs(o["vg"])) / abs(o["vg"])
+        say(f"    period {k + 1}: used {g['sur_used']}/{o['sur_used']} iters {g['sur_iters']}/{o['sur_iters']} "
+            f"err {g['sur_err']:.3e}/{o['sur_err']:.3e} steps > 1e-3: {int(big.sum())} (rel {step_err:.1e}), "
+            f"first {np.array2string(steps_g[:3], precision=3)} x rel {xerr:.1e} vg rel {vgerr:.1e}")
+        checks = {"used": g["sur_used"] == 1 and o["sur_used"] == 1,
+                  "iters": abs(g["sur_iters"] - o["sur_iters"]) <= 1,
+                  "err": abs(g["sur_err"] - o["sur_err"]) <= 1e-3 * o["sur_err"],
+                  "steps": step_err <= 1e-3, "x": xerr <= 1e-3, "vg": vgerr <= 1e-3}
+        fails += [(k + 1, name) for name, ok in checks.items() if not ok]
+        moved = max(moved, rel(g["x"], g["x_prev"]))
+    say(f"    largest relative change of the applied state over a period {moved:.2e}")
+    assert not fails, fails
 
 
 def test_trained_surrogate_reaches_stationary_circuit_in_fewer_periods():

@@ -416,3 +416,179 @@ def test_mcc_ion_elastic_conserves_momentum_and_energy():
     e0 = (v0 ** 2).sum(1) + (vn ** 2).sum(1)
     e1 = (v1 ** 2).sum(1) + (vn1 ** 2).sum(1)
     np.testing.assert_allclose(e1[moved], e0[moved], rtol=1e-10)
+
+
+# ---------------------------------------------------------------------------
+# Analytic cross-section fits, hand-evaluated (the fits are the reading of
+# the unspecified "smooth analytic fits" for e-Ar and Ar+-Ar; their
+# coefficients are the workload's defaults: el 1e-19 m^2 / 10 eV, exc 1e-20
+# m^2 at 11.5 eV, iz 3e-20 m^2 at 15.76 eV, ion el 3e-19 m^2 ^0.2, cx 5e-19
+# m^2 ^0.1).  The numbers below were worked out by hand from those
+# coefficients, not by calling the fit.
+# ---------------------------------------------------------------------------
+def test_analytic_electron_cross_sections_at_hand_computed_points():
+    xs = W.CrossSections()
+    assert xs.kind == W.XS_ANALYTIC
+    s = pic.sigma_e(xs, 0.0)
+    assert s[0] == pytest.approx(1.0e-19, rel=1e-15) and s[1] == 0.0 and s[2] == 0.0
+    # elastic at 10 eV: 1e-19 / sqrt(2)
+    assert pic.sigma_e(xs, 10.0)[0] == pytest.approx(7.0710678118654752e-20, rel=1e-14)
+    # elastic at 30 eV: 1e-19 / 2
+    assert pic.sigma_e(xs, 30.0)[0] == pytest.approx(5.0e-20, rel=1e-14)
+    # thresholds: nothing at or below, the peak (= the coefficient) at twice
+    assert pic.sigma_e(xs, 11.5)[1] == 0.0
+    assert pic.sigma_e(xs, 11.4999)[1] == 0.0
+    assert pic.sigma_e(xs, 15.76)[2] == 0.0
+    assert pic.sigma_e(xs, 15.0)[2] == 0.0
+    assert pic.sigma_e(xs, 23.0)[1] == pytest.approx(1.0e-20, rel=1e-14)
+    assert pic.sigma_e(xs, 31.52)[2] == pytest.approx(3.0e-20, rel=1e-14)
+    # three times the threshold: 4 * 2 / 9 of the coefficient
+    assert pic.sigma_e(xs, 34.5)[1] == pytest.approx(8.888888888888889e-21, rel=1e-14)
+    assert pic.sigma_e(xs, 47.28)[2] == pytest.approx(2.6666666666666667e-20, rel=1e-14)
+    # just above threshold the fit rises linearly: 4 (x - 1) for x -> 1
+    assert pic.sigma_e(xs, 11.5 * 1.001)[1] == pytest.approx(1e-20 * 4 * 0.001 / 1.001 ** 2, rel=1e-9)
+    # the threshold shape never exceeds its coefficient
+    eps = np.linspace(0.0, 1000.0, 20001)
+    exc = np.array([pic.sigma_e(xs, e)[1] for e in eps])
+    assert exc.max() <= 1.0e-20 * (1 + 1e-15)
+
+
+def test_analytic_ion_cross_sections_at_hand_computed_points():
+    xs = W.CrossSections()
+    s0 = pic.sigma_i(xs, 0.0)
+    assert s0[0] == pytest.approx(3.0e-19, rel=1e-15)
+    assert s0[1] == pytest.approx(5.0e-19, rel=1e-15)
+    s1 = pic.sigma_i(xs, 1.0)
+    # 3e-19 * 2^-0.2 and 5e-19 * 2^-0.1
+    assert s1[0] == pytest.approx(2.6116517e-19, rel=1e-7)
+    assert s1[1] == pytest.approx(4.6651650e-19, rel=1e-7)
+    s3 = pic.sigma_i(xs, 3.0)
+    # 3e-19 * 4^-0.2 = 3e-19 * 2^-0.4; 5e-19 * 2^-0.2
+    assert s3[0] == pytest.approx(2.2736094e-19, rel=1e-7)
+    assert s3[1] == pytest.approx(4.3527528e-19, rel=1e-7)
+
+
+def test_null_frequency_bounds_the_analytic_fits():
+    """nu_max (analytic fits) is an upper bound of n_g sigma_T(v) v at every
+    energy of the scanned range, and within the 1 % margin of the largest
+    value found by an independent dense random search through the fits."""
+    wl = W.small()
+    nu, pn, lq = pic.null_setup(wl)
+    rng = np.random.default_rng(17)
+    eps = np.concatenate([rng.uniform(0.0, wl.xs.e_cap_ev, 200_000), np.linspace(0.0, 60.0, 60_001)])
+    v = np.sqrt(2 * eps * W.QE / W.ME)
+    sig = np.array([pic.sigma_e(wl.xs, e).sum() for e in eps])
+    nue = wl.ngas * sig * v
+    assert nue.max() <= nu[0]
+    assert nu[0] / nue.max() == pytest.approx(1.01, rel=2e-4)
+    g = np.concatenate([rng.uniform(0.0, wl.xs.i_gcap, 200_000), [wl.xs.i_gcap]])
+    ecm = 0.25 * W.M_AR * g * g / W.QE
+    sigi = np.array([pic.sigma_i(wl.xs, e).sum() for e in ecm])
+    nui = wl.ngas * sigi * g
+    assert nui.max() <= nu[1]
+    assert nu[1] / nui.max() == pytest.approx(1.01, rel=2e-4)
+    # P_null and log(1 - P_null) of that frequency
+    assert pn[0] == pytest.approx(-math.expm1(-nu[0] * wl.dt), rel=1e-14)
+    assert lq[1] == pytest.approx(-nu[1] * wl.dt, rel=1e-15)
+
+
+def _neutral_partner(n, seed, step, tgas_ev):
+    """The ion's neutral partner at a candidate: Box-Muller of Philox block
+    (id, step, 2, 0) keyed by (seed, 1), words (0, 1) and (2, 3)."""
+    ctr = np.zeros((n, 4), np.uint32)
+    ctr[:, 0] = np.arange(n)
+    ctr[:, 1] = step
+    ctr[:, 2] = 2
+    b = pic.philox(ctr, (seed, 1)).astype(np.float64)
+    u = (b + 0.5) / 2 ** 32
+    vg = math.sqrt(tgas_ev * W.QE / W.M_AR)
+    r01 = np.sqrt(-2 * np.log(u[:, 0]))
+    r23 = np.sqrt(-2 * np.log(u[:, 2]))
+    return vg * np.stack([r01 * np.cos(2 * np.pi * u[:, 1]), r01 * np.sin(2 * np.pi * u[:, 1]),
+                          r23 * np.cos(2 * np.pi * u[:, 3])], 1)
+
+
+def test_mcc_charge_exchange_fraction_and_outcome():
+    """Ar+-Ar with the elastic channel switched off (analytic fits): a
+    candidate charge-exchanges with probability nu_cx / nu_max, nu_cx =
+    n_g sigma_cx(eps_cm) |v_i - v_n|, and a charge-exchanged ion leaves
+    with the neutral partner's velocity exactly; the others keep theirs."""
+    wl = W.small()
+    xs = W.CrossSections(iel_a=1e-40)
+    wl2 = W.Workload(**{**wl.__dict__, "xs": xs})
+    nu, pn, lq = pic.null_setup(wl2)
+    n = 200_000
+    rng = np.random.default_rng(23)
+    v0 = rng.normal(0, 4e3, (n, 3))
+    P = _parts(np.full(n, 0.05), np.full(n, 0.05), v0[:, 0], v0[:, 1], v0[:, 2])
+    P.next[:] = 6
+    seed = 5
+    cnt, _ = pic.mcc_raw(1, seed, 6, pic.xs_struct(xs), _gas(wl2), nu[1], lq[1], lq[1], P)
+    assert cnt[0] == n
+    vn = _neutral_partner(n, seed, 6, wl2.tgas_ev)
+    v1 = np.stack([P.vr, P.vt, P.vz], 1)
+    # the partner is recomputed here with numpy's log/cos/sin, which may
+    # differ from the C library's by an ulp
+    cx = np.all(np.abs(v1 - vn) <= 1e-14 * np.abs(vn).max(axis=1)[:, None], axis=1)
+    kept = np.all(v1 == v0, axis=1)
+    assert np.all(cx | kept)
+    assert cx.sum() == cnt[2] and cnt[1] == 0
+    g = np.linalg.norm(v0 - vn, axis=1)
+    ecm = 0.25 * W.M_AR * g * g / W.QE
+    # sigma_cx hand-written from its fit: 5e-19 (1 + eps_cm)^-0.1
+    q = wl2.ngas * 5e-19 * (1 + ecm) ** -0.1 * g / nu[1]
+    mean = q.sum()
+    sd = math.sqrt(np.sum(q * (1 - q)))
+    assert abs(cx.sum() - mean) < 5 * sd, (cx.sum(), mean, sd)
+    # faster ions exchange more often (sigma g rises with g here)
+    fast = g > np.median(g)
+    assert cx[fast].mean() > cx[~fast].mean()
+
+
+def test_moments_of_placed_and_uniform_plasmas():
+    """The surrogate's plasma moments on inputs whose values are known:
+    particles placed on one node (mean densities N w / V_box, the node
+    density N w / V_node with the weight's own volume, energy 1/2 m v^2,
+    centroid the node), and a uniform Maxwellian load (flat: mean density
+    n0, largest node density n0 within its counting noise, <eps_e> 3/2 T_e,
+    centroid (2 R_max / 3, z_p / 2))."""
+    from oracle.pic import OraclePIC
+    wl = W.small(n_per_species=1000)
+    ora = OraclePIC(wl, load=False)
+    N = 5000
+    i0, j0 = 20, 7
+    R0, z0 = j0 * wl.dr, i0 * wl.dz
+    speed = 1.0e6
+    for s in range(2):
+        P = pic.Particles(N)
+        P.R[:], P.z[:] = R0, z0
+        P.vr[:], P.vt[:], P.vz[:] = 0.0, speed, 0.0
+        P.id[:] = np.arange(N)
+        ora.parts[s] = P
+    m = ora.moments()
+    vbox = math.pi * wl.rmax ** 2 * wl.zp
+    assert m[0] == pytest.approx(N * wl.weight[0] / vbox, rel=1e-13)
+    assert m[1] == pytest.approx(N * wl.weight[1] / vbox, rel=1e-13)
+    # interior node: 2 pi R_j dR dz
+    vnode = 2 * math.pi * R0 * wl.dr * wl.dz
+    assert m[2] == pytest.approx(N * wl.weight[0] / vnode, rel=1e-12)
+    assert m[3] == pytest.approx(0.5 * W.ME * speed ** 2 / W.QE, rel=1e-13)
+    assert m[4] == pytest.approx(0.5 * W.M_AR * speed ** 2 / W.QE, rel=1e-13)
+    assert m[5] == pytest.approx(R0, rel=1e-14) and m[6] == pytest.approx(z0, rel=1e-14)
+    assert m[7] == 0.0
+    # the same particles on the axis node: its weight integrates to pi dR^2 dz / 2
+    for s in range(2):
+        ora.parts[s].R[:] = 0.0
+    m = ora.moments()
+    assert m[2] == pytest.approx(N * wl.weight[0] / (math.pi * wl.dr ** 2 / 2 * wl.dz), rel=1e-12)
+    # uniform Maxwellian load
+    wl = W.small(n_per_species=2_000_000)
+    ora = OraclePIC(wl)
+    m = ora.moments()
+    assert m[0] == pytest.approx(wl.n0, rel=1e-12)
+    # per-node count ~ Poisson: the largest of ~2000 nodes lies a few sigma up
+    per_node_min = 2_000_000 * (math.pi * wl.dr ** 2 / 2 * wl.dz / 2) / vbox
+    assert wl.n0 <= m[2] <= wl.n0 * (1 + 6 / math.sqrt(per_node_min))
+    assert m[3] == pytest.approx(1.5 * wl.temp_ev[0], rel=5 * math.sqrt(2 / 3 / 2e6))
+    assert m[5] == pytest.approx(2 * wl.rmax / 3, rel=5 * math.sqrt(1 / 18) / math.sqrt(2e6) / (2 / 3))
+    assert m[6] == pytest.approx(wl.zp / 2, rel=5 * 0.2887 / math.sqrt(2e6) / 0.5)
