@@ -481,6 +481,20 @@ pic_status mlp_set_params(mlp_ctx *ctx, const float *host);
 pic_status mlp_get_params(mlp_ctx *ctx, float *host);
 /* y[batch x n_out] (device, FP32) = network(x[batch x n_in]) (device, FP32). */
 pic_status mlp_forward(mlp_ctx *ctx, const float *x, int32_t batch, float *y);
+/* mlp_forward for callers that cannot allocate device memory or let the
+ * library touch the context's workspace activations: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation.  Same
+ * result as mlp_forward (same kernels and arithmetic), but the input,
+ * hidden activations and output staging live in a static device array of
+ * the library (307,200 bytes per device, held until the process ends; its
+ * address is looked up once per device by mlp_init), so the call allocates
+ * nothing.  Limits: batch 1..64 and hidden <= 256, else PIC_EINVAL with
+ * nothing launched.  x, y as for mlp_forward (device FP32, caller-owned).
+ * Every call on a device shares that device's array: calls that overlap on
+ * one device (two streams, two threads) race and must be serialised by
+ * the caller; the array keeps the last call's contents and needs no
+ * clearing (every element read is written first in the same call). */
+pic_status mlp_forward_noalloc(mlp_ctx *ctx, const float *x, int32_t batch, float *y);
 /* One training step on a batch (device arrays x[batch x n_in], t[batch x
  * n_out]): forward, mean-squared error over batch x n_out standardised
  * targets, backward (7 products), Adam.  loss (host, nullable): the batch

@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -439,6 +440,41 @@ struct Carver {
     }
 };
 
+// Inference scratch of mlp_forward_noalloc: a file-scope device array, so
+// that entry point needs no device memory from anyone.  Layout (byte
+// offsets, each a multiple of 256): X [64 x 32] BF16, A_l [64 x 256] BF16 for
+// the three hidden layers, Z_l [64 x 256] FP32, Y [64 x 32] FP32.  Every
+// device the library runs on holds its own copy until the process ends.
+constexpr int NOALLOC_MAX_BATCH = 64, NOALLOC_MAX_HIDDEN = 256;
+constexpr size_t NA_X = 0, NA_A = NA_X + (size_t)NOALLOC_MAX_BATCH * PAD * 2,
+                 NA_Z = NA_A + 3 * (size_t)NOALLOC_MAX_BATCH * NOALLOC_MAX_HIDDEN * 2,
+                 NA_Y = NA_Z + 3 * (size_t)NOALLOC_MAX_BATCH * NOALLOC_MAX_HIDDEN * 4,
+                 NOALLOC_BYTES = NA_Y + (size_t)NOALLOC_MAX_BATCH * PAD * 4;
+static_assert(NA_A % 256 == 0 && NA_Z % 256 == 0 && NA_Y % 256 == 0, "scratch offsets must stay 256-aligned");
+
+__device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+// Device address of `scratch` on device dev (in host code the array's name
+// is a host-side stand-in, not a device address): looked up once per device
+// with that device current, then kept.
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void *scratch_dev[MAX_DEVICES] = {};
+
+hipError_t scratch_address(int dev, void **out)
+{
+    if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_dev[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        scratch_dev[dev] = p;
+    }
+    *out = scratch_dev[dev];
+    return hipSuccess;
+}
+
 }  // namespace
 
 struct mlp_ctx {
@@ -446,6 +482,7 @@ struct mlp_ctx {
     hipStream_t stream = nullptr;
     std::string err;
     int H = 0, maxB = 0;
+    void *scratch = nullptr;   // this device's static inference scratch (mlp_forward_noalloc)
     int64_t P = 0;
     // parameter layout offsets (floats)
     int64_t oW[4]{}, ob[4]{};
@@ -579,10 +616,18 @@ void bias_grad(mlp_ctx &c, const float *G, int ld, int B, int N, float *out)
     hipLaunchKernelGGL(k_colsum_fold, dim3(nb(N, 256)), dim3(256), 0, c.stream, c.colpart, N, out);
 }
 
-void forward(mlp_ctx &c, int B)
+// Activation buffers of one forward pass: padded BF16 input X [B x 32],
+// per hidden layer the pre-activation Z (FP32) and the BF16 activation A
+// [B x H], the FP32 output Y [B x 32].
+struct Acts {
+    uint16_t *X, *A[3];
+    float *Z[3], *Y;
+};
+
+void forward(mlp_ctx &c, int B, const Acts &a)
 {
     const int H = c.H;
-    const uint16_t *in = c.X;
+    const uint16_t *in = a.X;
     int K = PAD;
     for (int l = 0; l < 3; ++l) {
         GemmArgs g{};
@@ -596,29 +641,31 @@ void forward(mlp_ctx &c, int B)
         g.sbk = 1;
         g.sbn = K;
         g.bias = c.p + c.ob[l];
-        g.C = c.Z[l];
+        g.C = a.Z[l];
         g.ldc = H;
-        g.Abf = c.A[l];
+        g.Abf = a.A[l];
         g.ldabf = H;
         gemm<uint16_t, uint16_t, EPI_GELU>(c, g);
-        in = c.A[l];
+        in = a.A[l];
         K = H;
     }
     GemmArgs g{};
     g.M = B;
     g.N = PAD;
     g.K = H;
-    g.A = c.A[2];
+    g.A = a.A[2];
     g.sam = H;
     g.sak = 1;
     g.B = c.pbf + c.oW[3];
     g.sbk = 1;
     g.sbn = H;
     g.bias = c.p + c.ob[3];
-    g.C = c.Y;
+    g.C = a.Y;
     g.ldc = PAD;
     gemm<uint16_t, uint16_t, EPI_LINEAR>(c, g);
 }
+
+Acts ctx_acts(const mlp_ctx &c) { return Acts{c.X, {c.A[0], c.A[1], c.A[2]}, {c.Z[0], c.Z[1], c.Z[2]}, c.Y}; }
 
 void backward(mlp_ctx &c, int B)
 {
@@ -692,6 +739,16 @@ extern "C" pic_status mlp_init(const mlp_config *cfg, void *workspace, size_t by
     c->stream = reinterpret_cast<hipStream_t>(stream);
     Carver cv{reinterpret_cast<uint8_t *>(workspace)};
     mlp_layout(*c, cv);
+    // the static inference scratch of the current device (the stream's)
+    {
+        int dev = -1;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = scratch_address(dev, &c->scratch);
+        if (e != hipSuccess) {
+            delete c;
+            return PIC_EDEVICE;
+        }
+    }
     std::vector<float> nrm(4 * PAD, 0.0f);
     for (int i = 0; i < PAD; ++i) nrm[PAD + i] = nrm[3 * PAD + i] = 1.0f;
     for (int i = 0; i < cfg->n_in; ++i) {
@@ -759,8 +816,34 @@ extern "C" pic_status mlp_forward(mlp_ctx *c, const float *x, int32_t batch, flo
     const mlp_config &f = c->cfg;
     hipLaunchKernelGGL(k_input, dim3(nb((int64_t)batch * PAD, 256)), dim3(256), 0, c->stream, x, batch, f.n_in, c->norm,
                        c->norm + PAD, c->X);
-    forward(*c, batch);
+    forward(*c, batch, ctx_acts(*c));
     hipLaunchKernelGGL(k_output, dim3(nb((int64_t)batch * f.n_out, 256)), dim3(256), 0, c->stream, c->Y, batch,
+                       f.n_out, c->norm + 2 * PAD, c->norm + 3 * PAD, y);
+    return hipGetLastError() == hipSuccess ? PIC_OK : mfail(c, PIC_EDEVICE, "kernel launch failed");
+}
+
+extern "C" pic_status mlp_forward_noalloc(mlp_ctx *c, const float *x, int32_t batch, float *y)
+{
+    if (!c || !x || !y) return PIC_EINVAL;
+    if (batch < 1 || batch > NOALLOC_MAX_BATCH)
+        return mfail(c, PIC_EINVAL, "batch %d outside 1..%d (static inference scratch)", batch, NOALLOC_MAX_BATCH);
+    if (c->H > NOALLOC_MAX_HIDDEN)
+        return mfail(c, PIC_EINVAL, "hidden width %d above %d (static inference scratch)", c->H, NOALLOC_MAX_HIDDEN);
+    if (!c->scratch) return mfail(c, PIC_EDEVICE, "static inference scratch not available on this device");
+    uint8_t *s = reinterpret_cast<uint8_t *>(c->scratch);
+    const size_t la = (size_t)NOALLOC_MAX_BATCH * NOALLOC_MAX_HIDDEN;
+    Acts a{};
+    a.X = reinterpret_cast<uint16_t *>(s + NA_X);
+    for (int l = 0; l < 3; ++l) {
+        a.A[l] = reinterpret_cast<uint16_t *>(s + NA_A) + l * la;
+        a.Z[l] = reinterpret_cast<float *>(s + NA_Z) + l * la;
+    }
+    a.Y = reinterpret_cast<float *>(s + NA_Y);
+    const mlp_config &f = c->cfg;
+    hipLaunchKernelGGL(k_input, dim3(nb((int64_t)batch * PAD, 256)), dim3(256), 0, c->stream, x, batch, f.n_in, c->norm,
+                       c->norm + PAD, a.X);
+    forward(*c, batch, a);
+    hipLaunchKernelGGL(k_output, dim3(nb((int64_t)batch * f.n_out, 256)), dim3(256), 0, c->stream, a.Y, batch,
                        f.n_out, c->norm + 2 * PAD, c->norm + 3 * PAD, y);
     return hipGetLastError() == hipSuccess ? PIC_OK : mfail(c, PIC_EDEVICE, "kernel launch failed");
 }
@@ -772,7 +855,7 @@ extern "C" pic_status mlp_train_step(mlp_ctx *c, const float *x, const float *t,
     const mlp_config &f = c->cfg;
     hipLaunchKernelGGL(k_input, dim3(nb((int64_t)batch * PAD, 256)), dim3(256), 0, c->stream, x, batch, f.n_in, c->norm,
                        c->norm + PAD, c->X);
-    forward(*c, batch);
+    forward(*c, batch, ctx_acts(*c));
     const unsigned nl = nb((int64_t)batch * PAD, 256);
     hipLaunchKernelGGL(k_loss, dim3(nl), dim3(256), 0, c->stream, c->Y, t, batch, f.n_out, c->norm + 2 * PAD,
                        c->norm + 3 * PAD, c->dY, c->lpart);

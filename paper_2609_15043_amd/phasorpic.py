@@ -487,7 +487,8 @@ class MlpConfig(ctypes.Structure):
 
 
 MLP_SYMBOLS = ["mlp_workspace_bytes", "mlp_init", "mlp_param_count", "mlp_set_params", "mlp_get_params",
-               "mlp_forward", "mlp_train_step", "mlp_get_grads", "mlp_sync", "mlp_destroy", "mlp_last_error"]
+               "mlp_forward", "mlp_forward_noalloc", "mlp_train_step", "mlp_get_grads", "mlp_sync", "mlp_destroy",
+               "mlp_last_error"]
 SYMBOLS += MLP_SYMBOLS
 
 _MLP_BOUND = False
@@ -506,6 +507,7 @@ def _mlp_lib():
         L.mlp_get_params.argtypes = [P, _PF]
         L.mlp_get_grads.argtypes = [P, _PF]
         L.mlp_forward.argtypes = [P, P, _I32, P]
+        L.mlp_forward_noalloc.argtypes = [P, P, _I32, P]
         L.mlp_train_step.argtypes = [P, P, P, _I32, _PF]
         L.mlp_sync.argtypes = [P]
         L.mlp_destroy.argtypes = [P]
@@ -578,6 +580,17 @@ class Mlp:
             y = torch.empty((x.shape[0], self.cfg.n_out), dtype=torch.float32, device=x.device)
         self.check(_mlp_lib().mlp_forward(self.handle, ctypes.c_void_p(x.data_ptr()), x.shape[0],
                                           ctypes.c_void_p(y.data_ptr())))
+        return y
+
+    def forward_noalloc(self, x, y=None):
+        """mlp_forward_noalloc: the same network output, activations in the
+        library's static device scratch (batch <= 64)."""
+        import torch
+        x = x.contiguous()
+        if y is None:
+            y = torch.empty((x.shape[0], self.cfg.n_out), dtype=torch.float32, device=x.device)
+        self.check(_mlp_lib().mlp_forward_noalloc(self.handle, ctypes.c_void_p(x.data_ptr()), x.shape[0],
+                                                  ctypes.c_void_p(y.data_ptr())))
         return y
 
     def train_step(self, x, t, want_loss=True):
