@@ -73,6 +73,8 @@ enum {
     PIC_GRID_ES = 10,      /* stored sine array E_s^sto = -E_s of the applied field (V/m) */
     PIC_GRID_EC_PLASMA = 11,  /* plasma-only E_c^p of the last circuit update */
     PIC_GRID_ES_PLASMA = 12,  /* plasma-only E_s^sto,p of the last circuit update */
+    PIC_GRID_BR = 13,      /* staged RF B_r of the last pic_gather_push (T), cfg->rf_bfield only */
+    PIC_GRID_BZ = 14,      /* staged RF B_z (T) */
     PIC_GRID_UNIT = 16     /* + k: unit-current field U_k of turn k+1 (V/m per A) */
 };
 
@@ -149,6 +151,11 @@ typedef struct pic_config {
      * inductive operator (axis, outer boundary, metal) */
     const double *dir_basis;
     const double *unit_bvals;
+    /* 1: the RF magnetic field of the applied azimuthal field enters the Boris rotation (with bfield):
+     * by Faraday's law, with F = (E_c sin th_n + E_s^sto cos th_n) / w, B_r = dF/dz and
+     * B_z = -(1/R) d(R F)/dR at t_n, staged per node by central differences and gathered with the
+     * particle weights (the paper leaves the push's magnetic field unstated) */
+    int32_t rf_bfield;
 } pic_config;
 
 typedef struct pic_solve_info {

@@ -194,12 +194,15 @@ void ora_load(int64_t n, uint32_t seed, int sp, double rmax, double zlo, double 
  * particle region get alive = 0; absorbed[p] tells where: 1 wall, 2 window.
  * Inode accumulates q w vbar_theta W_node(x^n) (vbar = mean of the two half
  * step velocities in the frame at x^n); surf accumulates the charge left on
- * the window row.
+ * the window row.  Br, Bz (nullable): node values of the RF magnetic field
+ * at t_n, gathered with the same weights and added to the uniform field of
+ * the species block in the Boris rotation.
  */
 void ora_gather_push(const ora_grid *g, const ora_species *s, int64_t n,
                      double *R, double *z, double *vr, double *vt, double *vz,
                      int32_t *alive, int32_t *absorbed,
                      const double *Er, const double *Ez, const double *Et,
+                     const double *Br, const double *Bz,
                      double *Inode, double *surf)
 {
     const double qm = s->q / s->m;
@@ -222,12 +225,26 @@ void ora_gather_push(const ora_grid *g, const ora_species *s, int64_t n,
             e[1] += W[k] * Et[nd[k]];
             e[2] += W[k] * Ez[nd[k]];
         }
+        /* rotation vector t = (q/m) B dt / 2 and s = 2 t / (1 + t^2) */
+        double tp[3] = {tv[0], tv[1], tv[2]}, sp[3] = {sv[0], sv[1], sv[2]};
+        double tt = t2;
+        if (Br && Bz) {
+            double b[2] = {0, 0};
+            for (int k = 0; k < 4; ++k) {
+                b[0] += W[k] * Br[nd[k]];
+                b[1] += W[k] * Bz[nd[k]];
+            }
+            tp[0] = h * (s->b[0] + b[0]);
+            tp[2] = h * (s->b[2] + b[1]);
+            tt = tp[0] * tp[0] + tp[1] * tp[1] + tp[2] * tp[2];
+            for (int c = 0; c < 3; ++c) sp[c] = 2 * tp[c] / (1 + tt);
+        }
         /* half kick, rotation, half kick: (r, theta, z) right-handed */
         double v[3] = {vr[p] + h * e[0], vt[p] + h * e[1], vz[p] + h * e[2]};
-        if (t2 > 0) {
-            double c1[3] = {v[1] * tv[2] - v[2] * tv[1], v[2] * tv[0] - v[0] * tv[2], v[0] * tv[1] - v[1] * tv[0]};
+        if (tt > 0) {
+            double c1[3] = {v[1] * tp[2] - v[2] * tp[1], v[2] * tp[0] - v[0] * tp[2], v[0] * tp[1] - v[1] * tp[0]};
             double vp[3] = {v[0] + c1[0], v[1] + c1[1], v[2] + c1[2]};
-            double c2[3] = {vp[1] * sv[2] - vp[2] * sv[1], vp[2] * sv[0] - vp[0] * sv[2], vp[0] * sv[1] - vp[1] * sv[0]};
+            double c2[3] = {vp[1] * sp[2] - vp[2] * sp[1], vp[2] * sp[0] - vp[0] * sp[2], vp[0] * sp[1] - vp[1] * sp[0]};
             v[0] += c2[0]; v[1] += c2[1]; v[2] += c2[2];
         }
         v[0] += h * e[0];

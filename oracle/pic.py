@@ -73,7 +73,7 @@ class Gas(ctypes.Structure):
 
 
 def _p(a, t):
-    return a.ctypes.data_as(ctypes.POINTER(t))
+    return None if a is None else a.ctypes.data_as(ctypes.POINTER(t))
 
 
 _D = ctypes.c_double
@@ -93,7 +93,7 @@ def lib():
         L.ora_load.argtypes = [_I64, _U32, ctypes.c_int, _D, _D, _D, _D, _D] + \
             [ctypes.POINTER(_D)] * 5 + [ctypes.POINTER(_U32), ctypes.POINTER(_I32)]
         L.ora_gather_push.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Species), _I64] + \
-            [ctypes.POINTER(_D)] * 5 + [ctypes.POINTER(_I32)] * 2 + [ctypes.POINTER(_D)] * 5
+            [ctypes.POINTER(_D)] * 5 + [ctypes.POINTER(_I32)] * 2 + [ctypes.POINTER(_D)] * 7
         L.ora_deposit.argtypes = [ctypes.POINTER(Grid), _I64, ctypes.POINTER(_D), ctypes.POINTER(_D),
                                   ctypes.POINTER(_I32), _D, ctypes.POINTER(_D)]
         L.ora_sigma_e.argtypes = [ctypes.POINTER(XS), _D, ctypes.POINTER(_D)]
@@ -227,6 +227,31 @@ def n_rf(freq, dt):
     """N_RF = nint(1 / (f dt)) and whether the phase closes (Eqs. nrf, phaseclosure)."""
     N = int(round(1.0 / (freq * dt)))
     return N, abs(freq * dt * N - 1.0) < 1e-10
+
+
+def rf_bfield(ec, es_sto, dr, dz, omega, th):
+    """RF magnetic field (B_r, B_z) at phase th of the applied azimuthal
+    field E_theta(t) = E_c cos(wt) - E_s^sto sin(wt), from Faraday's law
+    dB/dt = -curl E (the paper leaves the push's magnetic field unstated;
+    this is the field that its own E_theta implies).  With the time
+    integral F = (E_c sin(wt) + E_s^sto cos(wt)) / w of E_theta (zero
+    mean), B = -curl(F theta_hat):
+        B_r = dF/dz,    B_z = -(1/R) d(R F)/dR.
+    Node values by central differences inside, one-sided at the domain
+    edges; on the axis (1/R) d(R F)/dR -> 2 dF/dR, with F = 0 there."""
+    F = (np.asarray(ec) * math.sin(th) + np.asarray(es_sto) * math.cos(th)) / omega
+    nz1, nr1 = F.shape
+    Br = np.zeros_like(F)
+    Bz = np.zeros_like(F)
+    Br[1:-1, :] = (F[2:, :] - F[:-2, :]) / (2 * dz)
+    Br[0, :] = (F[1, :] - F[0, :]) / dz
+    Br[-1, :] = (F[-1, :] - F[-2, :]) / dz
+    R = np.arange(nr1) * dr
+    RF = R[None, :] * F
+    Bz[:, 1:-1] = -(RF[:, 2:] - RF[:, :-2]) / (2 * dr) / R[None, 1:-1]
+    Bz[:, -1] = -(RF[:, -1] - RF[:, -2]) / dr / R[-1]
+    Bz[:, 0] = -2.0 * (F[:, 1] - F[:, 0]) / dr
+    return np.ascontiguousarray(Br), np.ascontiguousarray(Bz)
 
 
 def e_from_phi(phi, dr, dz):
@@ -481,6 +506,10 @@ class OraclePIC:
         Er, Ez = e_from_phi(self.phi, self.wl.dr, self.wl.dz)
         Et = self.etheta(n)
         Er, Ez, Et = (np.ascontiguousarray(a, dtype=np.float64) for a in (Er, Ez, Et))
+        Br = Bz = None
+        if self.wl.rf_bfield:
+            Br, Bz = rf_bfield(self.ec, self.es, self.wl.dr, self.wl.dz, 2 * math.pi * self.wl.freq,
+                               theta(n, self.nrf))
         self.I = np.zeros(self.shape)
         self.absorbed = []
         for s in range(2):
@@ -489,7 +518,7 @@ class OraclePIC:
             lib().ora_gather_push(ctypes.byref(self.grid), ctypes.byref(self.sp[s]), P.n,
                                   _p(P.R, _D), _p(P.z, _D), _p(P.vr, _D), _p(P.vt, _D), _p(P.vz, _D),
                                   _p(P.alive, _I32), _p(ab, _I32), _p(Er, _D), _p(Ez, _D), _p(Et, _D),
-                                  _p(self.I, _D), _p(self.surf, _D))
+                                  _p(Br, _D), _p(Bz, _D), _p(self.I, _D), _p(self.surf, _D))
             self.absorbed.append(ab)
 
     def mcc(self, n):
@@ -645,7 +674,7 @@ def gather_push_raw(grid, species, P, Er, Ez, Et):
     Er, Ez, Et = (np.ascontiguousarray(np.broadcast_to(a, shape), dtype=np.float64) for a in (Er, Ez, Et))
     lib().ora_gather_push(ctypes.byref(grid), ctypes.byref(species), P.n, _p(P.R, _D), _p(P.z, _D),
                           _p(P.vr, _D), _p(P.vt, _D), _p(P.vz, _D), _p(P.alive, _I32), _p(ab, _I32),
-                          _p(Er, _D), _p(Ez, _D), _p(Et, _D), _p(I, _D), _p(surf, _D))
+                          _p(Er, _D), _p(Ez, _D), _p(Et, _D), None, None, _p(I, _D), _p(surf, _D))
     return I, surf, ab
 
 

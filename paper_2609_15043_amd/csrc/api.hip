@@ -116,6 +116,7 @@ struct pic_ctx {
 
     // grids
     void *ef = nullptr;
+    void *eb = nullptr;           // staged RF magnetic field (B_r, B_z) per node, when the config asks for it
     long long *accJ = nullptr, *accQ = nullptr;
     double *accS = nullptr;       // window surface charge per species (weights, FP64, persistent)
     long long *accW = nullptr;    // the step's window charge per species (fixed point, folded into accS)
@@ -482,6 +483,7 @@ static void layout(pic_ctx &c, Carver &cv)
     c.stage_cap = std::min<int64_t>(capmax, 1 << 20);
     c.stage = cv.take<double>(6 * (size_t)c.stage_cap);
     c.ef = c.mixed ? (void *)cv.take<float4>(nodes) : (void *)cv.take<double4>(nodes);
+    if (f.rf_bfield) c.eb = c.mixed ? (void *)cv.take<float2>(nodes) : (void *)cv.take<double2>(nodes);
     c.accJ = cv.take<long long>(2 * (size_t)nodes);
     c.accQ = cv.take<long long>(2 * (size_t)nodes);
     c.accS = cv.take<double>(2 * (size_t)nodes);
@@ -720,6 +722,7 @@ template <typename T> static PassArgs<T> pass_args(pic_ctx &c, int s, int64_t st
     a.q = c.cq[s];
     a.count = c.ctl + s;
     a.ef = reinterpret_cast<const typename Field4<T>::type *>(c.ef);
+    a.eb = reinterpret_cast<const typename Field2<T>::type *>(c.eb);
     a.accJ = c.accJ + (size_t)s * c.g.nodes;
     a.accQ = c.accQ + (size_t)s * c.g.nodes;
     a.accW = c.accW + (size_t)s * c.g.nodes;
@@ -748,6 +751,9 @@ template <typename T> static void stage(pic_ctx &c, int64_t n)
     const double th = TWO_PI * (double)(n % c.nrf) / (double)c.nrf;
     launch_stage<T>(c.phi, c.d_ec, c.d_es, std::cos(th), std::sin(th),
                     reinterpret_cast<typename Field4<T>::type *>(c.ef), c.accJ, c.accQ, true, c.g, c.stream);
+    if (c.eb)
+        launch_stage_b<T>(c.d_ec, c.d_es, std::cos(th), std::sin(th), 1.0 / (TWO_PI * c.cfg.freq),
+                          reinterpret_cast<typename Field2<T>::type *>(c.eb), c.g, c.stream);
 }
 
 template <typename T> static void run_pass(pic_ctx &c, int64_t n, bool push, bool depq)
@@ -2072,6 +2078,13 @@ extern "C" pic_status pic_set_phi(pic_ctx *c, const double *phi)
     return PIC_OK;
 }
 
+template <typename T> static void bfield_component(pic_ctx *c, int comp, double *out)
+{
+    std::vector<typename Field2<T>::type> f(c->g.nodes);
+    (void)cpy(c->stream, f.data(), c->eb, f.size() * sizeof(f[0]), hipMemcpyDeviceToHost);
+    for (int n = 0; n < c->g.nodes; ++n) out[n] = comp == 0 ? (double)f[n].x : (double)f[n].y;
+}
+
 template <typename T> static void field_component(pic_ctx *c, int comp, double *out)
 {
     std::vector<typename Field4<T>::type> f(c->g.nodes);
@@ -2095,6 +2108,14 @@ extern "C" pic_status pic_get_grid(pic_ctx *c, int32_t which, double *out)
             field_component<float>(c, which - PIC_GRID_ER, out);
         else
             field_component<double>(c, which - PIC_GRID_ER, out);
+        break;
+    case PIC_GRID_BR:
+    case PIC_GRID_BZ:
+        if (!c->eb) return fail(c, PIC_EINVAL, "the configuration has no RF magnetic field");
+        if (c->mixed)
+            bfield_component<float>(c, which - PIC_GRID_BR, out);
+        else
+            bfield_component<double>(c, which - PIC_GRID_BR, out);
         break;
     case PIC_GRID_SURFACE: {
         std::vector<double> a(2 * (size_t)nodes);

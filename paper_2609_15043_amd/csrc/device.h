@@ -135,6 +135,14 @@ template <> struct Field4<float> {
 template <> struct Field4<double> {
     using type = double4;
 };
+// RF magnetic field of one node for the gather: (B_r, B_z).
+template <typename T> struct Field2;
+template <> struct Field2<float> {
+    using type = float2;
+};
+template <> struct Field2<double> {
+    using type = double2;
+};
 
 // Structure-of-arrays particle store of one species.
 template <typename T> struct Parts {

@@ -47,6 +47,41 @@ __global__ void k_stage(const double *phi, const double *ec, const double *es, d
     }
 }
 
+// RF magnetic field of the applied azimuthal field at phase th (Faraday's
+// law): with F = (E_c sin th + E_s^sto cos th) / w the zero-mean time
+// integral of E_theta(t) = E_c cos - E_s^sto sin, B = -curl(F theta_hat),
+// i.e. B_r = dF/dz and B_z = -(1/R) d(R F)/dR; central differences inside,
+// one-sided at the box edges, B_z = -2 dF/dR on the axis (F = 0 there).
+template <typename T>
+__global__ void k_stage_b(const double *ec, const double *es, double cs, double sn, double inv_w,
+                          typename Field2<T>::type *eb, GridC g)
+{
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= g.nodes) return;
+    const int i = n / g.nr1, j = n - i * g.nr1;
+    auto F = [&](int m) { return (ec[m] * sn + es[m] * cs) * inv_w; };
+    double br, bz;
+    if (i == 0)
+        br = (F(n + g.nr1) - F(n)) / g.dz;
+    else if (i == g.nz)
+        br = (F(n) - F(n - g.nr1)) / g.dz;
+    else
+        br = (F(n + g.nr1) - F(n - g.nr1)) / (2.0 * g.dz);
+    if (j == 0) {
+        bz = -2.0 * (F(n + 1) - F(n)) / g.dr;
+    } else {
+        const double R = j * g.dr;
+        if (j == g.nr)
+            bz = -(R * F(n) - (R - g.dr) * F(n - 1)) / g.dr / R;
+        else
+            bz = -((R + g.dr) * F(n + 1) - (R - g.dr) * F(n - 1)) / (2.0 * g.dr) / R;
+    }
+    typename Field2<T>::type b;
+    b.x = (T)br;
+    b.y = (T)bz;
+    eb[n] = b;
+}
+
 // node charge = sum_s q_s w_s (accQ_s / 2^kQ + accS_s), after the step's
 // window charge accW_s / 2^kQ (fixed point) has joined the persistent FP64
 // window sums accS_s (one add per node and step, in a fixed order)
@@ -639,6 +674,16 @@ void launch_stage(const double *phi, const double *ec, const double *es, double 
     hipLaunchKernelGGL(k_stage<T>, dim3(nblk(g.nodes, 256)), dim3(256), 0, st, phi, ec, es, cs, sn, ef, accJ, accQ,
                        clear_q ? 1 : 0, g);
 }
+template <typename T>
+void launch_stage_b(const double *ec, const double *es, double cs, double sn, double inv_w,
+                    typename Field2<T>::type *eb, const GridC &g, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_stage_b<T>, dim3(nblk(g.nodes, 256)), dim3(256), 0, st, ec, es, cs, sn, inv_w, eb, g);
+}
+template void launch_stage_b<float>(const double *, const double *, double, double, double, float2 *, const GridC &,
+                                    hipStream_t);
+template void launch_stage_b<double>(const double *, const double *, double, double, double, double2 *,
+                                     const GridC &, hipStream_t);
 template void launch_stage<float>(const double *, const double *, const double *, double, double, float4 *,
                                   long long *, long long *, bool, const GridC &, hipStream_t);
 template void launch_stage<double>(const double *, const double *, const double *, double, double, double4 *,

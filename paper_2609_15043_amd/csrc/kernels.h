@@ -135,6 +135,7 @@ template <typename T> struct PassArgs {
     CandQueue q;
     const int64_t *count;              // slots in use of this species
     const typename Field4<T>::type *ef;
+    const typename Field2<T>::type *eb;   // RF magnetic field per node, or none
     long long *accJ;                   // this species' current accumulator
     long long *accQ;                   // this species' charge accumulator
     long long *accW;                   // this species' window charge of the step (weights, fixed point)

@@ -34,6 +34,9 @@ void launch_sort(const Parts<T> &src, const Parts<T> &dst, int64_t *count, int64
 int sort_scan_blocks(int ncells);
 
 template <typename T>
+void launch_stage_b(const double *ec, const double *es, double cs, double sn, double inv_w,
+                    typename Field2<T>::type *eb, const GridC &g, hipStream_t st);
+template <typename T>
 void launch_stage(const double *phi, const double *ec, const double *es, double cs, double sn,
                   typename Field4<T>::type *ef, long long *accJ, long long *accQ, bool clear_q, const GridC &g,
                   hipStream_t st);

@@ -441,7 +441,9 @@ template <typename T> struct PassOcc {
     static constexpr int min_waves = sizeof(T) == 4 ? PIC_PASS_WAVES_PER_EU : 3;
 };
 #define PIC_PASS_OCCUPANCY __attribute__((amdgpu_waves_per_eu(PassOcc<T>::min_waves, 8)))
-template <typename T, bool PUSH, bool DEPQ>
+// RFB: the RF magnetic field staged per node (eb) joins the uniform field
+// in the Boris rotation, with the rotation vector formed per particle
+template <typename T, bool PUSH, bool DEPQ, bool RFB>
 __global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassPair<T> pp)
 {
     // one grid for both species: blocks [0, nb0) take the electrons' chunks,
@@ -560,7 +562,21 @@ __global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassPair<T> p
                 const T et = w00 * f00.z + w01 * f01.z + w10 * f10.z + w11 * f11.z;
                 const T h = sc_val<T>(a.sc.h, a.sc.hf);
                 T ur = vr[k] + h * er, ut = vt[k] + h * et, uz = vz[k] + h * ez;
-                if (a.sc.has_b) {
+                if constexpr (RFB) {
+                    using F2 = typename Field2<T>::type;
+                    const F2 b00 = a.eb[key], b01 = a.eb[key + 1], b10 = a.eb[key + g.nr1], b11 = a.eb[key + g.nr1 + 1];
+                    const T br = w00 * b00.x + w01 * b01.x + w10 * b10.x + w11 * b11.x;
+                    const T bz = w00 * b00.y + w01 * b01.y + w10 * b10.y + w11 * b11.y;
+                    // t = (q/m) (B_uniform + B_rf) dt / 2, s = 2 t / (1 + t^2)
+                    const T t0 = sc_val<T>(a.sc.bt[0], a.sc.btf[0]) + h * br, t1 = sc_val<T>(a.sc.bt[1], a.sc.btf[1]),
+                            t2 = sc_val<T>(a.sc.bt[2], a.sc.btf[2]) + h * bz;
+                    const T f = quot((T)2, (T)1 + (t0 * t0 + t1 * t1 + t2 * t2));
+                    const T s0 = f * t0, s1 = f * t1, s2 = f * t2;
+                    const T pr = ur + (ut * t2 - uz * t1), pt = ut + (uz * t0 - ur * t2), pz = uz + (ur * t1 - ut * t0);
+                    ur += pt * s2 - pz * s1;
+                    ut += pz * s0 - pr * s2;
+                    uz += pr * s1 - pt * s0;
+                } else if (a.sc.has_b) {
                     const T t0 = sc_val<T>(a.sc.bt[0], a.sc.btf[0]), t1 = sc_val<T>(a.sc.bt[1], a.sc.btf[1]),
                             t2 = sc_val<T>(a.sc.bt[2], a.sc.btf[2]);
                     const T s0 = sc_val<T>(a.sc.bs[0], a.sc.bsf[0]), s1 = sc_val<T>(a.sc.bs[1], a.sc.bsf[1]),
@@ -1330,12 +1346,17 @@ void launch_pass(const PassArgs<T> &e, const PassArgs<T> &i, int64_t cap_e, int6
     pp.a[1] = i;
     pp.nb0 = blocks_for(cap_e, CHUNK);
     const dim3 grid(pp.nb0 + blocks_for(cap_i, CHUNK)), blk(BLOCK);
-    if (push && depq)
-        hipLaunchKernelGGL((k_pass<T, true, true>), grid, blk, 0, st, pp);
+    const bool rfb = e.eb != nullptr;
+    if (push && depq && rfb)
+        hipLaunchKernelGGL((k_pass<T, true, true, true>), grid, blk, 0, st, pp);
+    else if (push && depq)
+        hipLaunchKernelGGL((k_pass<T, true, true, false>), grid, blk, 0, st, pp);
+    else if (push && rfb)
+        hipLaunchKernelGGL((k_pass<T, true, false, true>), grid, blk, 0, st, pp);
     else if (push)
-        hipLaunchKernelGGL((k_pass<T, true, false>), grid, blk, 0, st, pp);
+        hipLaunchKernelGGL((k_pass<T, true, false, false>), grid, blk, 0, st, pp);
     else if (depq)
-        hipLaunchKernelGGL((k_pass<T, false, true>), grid, blk, 0, st, pp);
+        hipLaunchKernelGGL((k_pass<T, false, true, false>), grid, blk, 0, st, pp);
 }
 
 template <typename T> void launch_collide(const PassArgs<T> &a, hipStream_t st)

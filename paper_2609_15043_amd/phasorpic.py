@@ -23,7 +23,7 @@ PIC_FIELD_FULL, PIC_FIELD_MQS = 0, 1
 PIC_RRF_GIVEN, PIC_RRF_SKIN = 0, 1
 (PIC_GRID_PHI, PIC_GRID_CHARGE, PIC_GRID_CURRENT, PIC_GRID_ER, PIC_GRID_EZ, PIC_GRID_ETHETA,
  PIC_GRID_SURFACE, PIC_GRID_JC, PIC_GRID_JS, PIC_GRID_EC, PIC_GRID_ES, PIC_GRID_EC_PLASMA,
- PIC_GRID_ES_PLASMA) = range(13)
+ PIC_GRID_ES_PLASMA, PIC_GRID_BR, PIC_GRID_BZ) = range(15)
 PIC_GRID_UNIT = 16
 
 _D, _I32, _I64, _U32 = ctypes.c_double, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
@@ -50,7 +50,7 @@ class PicConfig(ctypes.Structure):
         ("vg_amp", _D), ("vg_phase", _D), ("vg_from_target", _I32), ("controller", _I32),
         ("p_target", _D), ("gamma", _D), ("n_trend", _D), ("eps_p", _D), ("alpha_v", _D), ("f_step", _D),
         ("v_min", _D), ("v_max", _D), ("alpha", _D), ("helm_rtol", _D), ("helm_max_cycles", _I32),
-        ("sort_every_ion", _I32), ("dir_basis", _PD), ("unit_bvals", _PD),
+        ("sort_every_ion", _I32), ("dir_basis", _PD), ("unit_bvals", _PD), ("rf_bfield", _I32),
     ]
 
 
@@ -207,6 +207,7 @@ def config_from_workload(wl, precision="mixed", fuse=True, load=True, mg_rtol=No
         mg_rtol = 1e-13 if precision == "fp64" else 1e-9
     c.mg_rtol, c.mg_max_cycles, c.sort_every, c.load = mg_rtol, mg_max_cycles, sort_every, 1 if load else 0
     c.sort_every_ion = sort_every_ion
+    c.rf_bfield = 1 if wl.rf_bfield else 0
     c.birth_capacity = birth_capacity
     cp = wl.circuit
     if cp is not None:

@@ -143,6 +143,7 @@ class Workload:
     turn_vs: np.ndarray           # (N,) V_s,k
     circuit: CircuitParams = None     # None: prescribed E_theta and turn potentials
     bfield: tuple = (0.0, 0.0, 0.0)   # uniform (B_r, B_theta, B_z), tests only
+    rf_bfield: bool = False           # the RF magnetic field of the applied E_theta in the Boris rotation
     xs: CrossSections = dataclasses.field(default_factory=CrossSections)
     capacity_factor: float = 1.5
     eps0: float = EPS0                # vacuum permittivity of the Poisson operator
@@ -240,7 +241,7 @@ def small(seed=0, n_per_species=100_000, nsteps=200, nr=32, nz=64) -> Workload:
 
 
 def _coil_cell(nr, nz, n_per_species, pressure_mtorr, name, seed, nsteps, coil_current=5.0,
-               v_feed=300.0, circuit=True):
+               v_feed=300.0, circuit=True, n0=1e16):
     """Chamber R = 0.15 m, z = 0.2 m: plasma z < 0.15 m, quartz window
     0.15 m .. 0.15 m + 13 * 0.78125 mm, 5 planar turns in the vacuum
     compartment above, grounded side wall, bottom and lid.
@@ -283,19 +284,19 @@ def _coil_cell(nr, nz, n_per_species, pressure_mtorr, name, seed, nsteps, coil_c
     return Workload(
         name=name, nr=nr, nz=nz, rmax=rmax, zmax=zmax, zp=ip * dz, dt=1.0 / (2000 * freq),
         freq=freq, nsteps=nsteps, pressure_pa=pressure_mtorr * 1e-3 * TORR, tgas_k=300.0,
-        n0=1e16, np_init=(n_per_species, n_per_species), temp_ev=(3.0, 0.026), seed=seed,
+        n0=n0, np_init=(n_per_species, n_per_species), temp_ev=(3.0, 0.026), seed=seed,
         eps_cell=eps, node_tag=tag, ec=ec, es_sto=es,
         turn_vc=vfeed, turn_vs=np.zeros(5), circuit=CircuitParams() if circuit else None)
 
 
-def cell(seed=0, n_per_species=2_000_000, nsteps=20_000, circuit=True, vg_start=None) -> Workload:
+def cell(seed=0, n_per_species=2_000_000, nsteps=20_000, circuit=True, vg_start=None, n0=1e16) -> Workload:
     """vg_start: start the coupled source at this amplitude (V) instead of
     the one that puts the power target into the vacuum network.  That one
     (3.4 kV for 60 W: 26 A in every turn, |E_theta| up to 1.4 kV/m in the
     plasma) is right for an empty cell, but a plasma loaded into the first
     period's vacuum field absorbs kilowatts before the circuit sees it; a
     plasma run starts low and lets the controller raise the amplitude."""
-    wl = _coil_cell(128, 256, n_per_species, 20.0, "cell", seed, nsteps, circuit=circuit)
+    wl = _coil_cell(128, 256, n_per_species, 20.0, "cell", seed, nsteps, circuit=circuit, n0=n0)
     if circuit and vg_start is not None:
         wl.circuit = dataclasses.replace(wl.circuit, vg_from_target=False, vg_amp=float(vg_start))
     return wl
@@ -303,6 +304,28 @@ def cell(seed=0, n_per_species=2_000_000, nsteps=20_000, circuit=True, vg_start=
 
 def large(seed=0, n_per_species=32_000_000, nsteps=4_000, circuit=True) -> Workload:
     return _coil_cell(256, 512, n_per_species, 50.0, "large", seed, nsteps, circuit=circuit)
+
+
+def test1(r_series=0.1, v_source=1.0) -> Workload:
+    """The paper's single-solenoid benchmark (Sec. 3.1): one source line of
+    1000 nodes at R = a = 10 mm (node column 10, rows 121..1120) in a
+    grounded box of 120 x 1240 cells at h = 1 mm, MQS at 13.56 MHz with
+    mu0 = 4 pi 1e-7, driven by 1 V through 0.1 ohm (no other elements), no
+    particles."""
+    h, nr, nz = 1e-3, 120, 1240
+    tag = np.full((nz + 1, nr + 1), -1, np.int32)
+    tag[0, :] = tag[nz, :] = 0
+    tag[:, nr] = 0
+    tag[121:1121, 10] = 1
+    circ = CircuitParams(mu0=4e-7 * math.pi, field_mode=FIELD_MQS, rrf_mode=RRF_GIVEN, r_rf=(0.0,), r_g=r_series,
+                         r_m=0.0, l_m=0.0, c_m=0.0, vg_amp=v_source, vg_phase=0.0, vg_from_target=False,
+                         controller=False, alpha=1.0)
+    f = 13.56e6
+    return Workload(
+        name="test1", nr=nr, nz=nz, rmax=nr * h, zmax=nz * h, zp=h, dt=1.0 / (400 * f), freq=f, nsteps=0,
+        pressure_pa=1e-3 * TORR, tgas_k=300.0, n0=0.0, np_init=(0, 0), temp_ev=(1.0, 0.026), seed=0,
+        eps_cell=np.ones((nz, nr)), node_tag=tag, ec=np.zeros((nz + 1, nr + 1)), es_sto=np.zeros((nz + 1, nr + 1)),
+        turn_vc=np.zeros(1), turn_vs=np.zeros(1), circuit=circ)
 
 
 # The paper's joint inductive-capacitive benchmark (Sec. 3.3, its parameter

@@ -91,7 +91,7 @@ def test_load_and_initial_field_match_oracle(prec):
     assert e <= TOL[prec]
 
 
-def _step_case(wlname, prec, fuse, n0):
+def _step_case(wlname, prec, fuse, n0, rfb=False):
     import paper_2609_15043_amd.phasorpic as pp
     from paper_2609_15043_amd import workloads as W
     from oracle import pic as O
@@ -103,7 +103,8 @@ def _step_case(wlname, prec, fuse, n0):
         wl = W.small(n_per_species=50_001, nr=40, nz=70)
     else:
         wl = W.cell(n_per_species=120_000, circuit=False)
-    say(f"[gpu] one step {wlname} {prec} fuse={fuse} n0={n0}")
+    wl.rf_bfield = rfb
+    say(f"[gpu] one step {wlname} {prec} fuse={fuse} n0={n0}" + (" with the RF magnetic field" if rfb else ""))
     ora = O.OraclePIC(wl)
     cfg, keep = pp.config_from_workload(wl, precision=prec, fuse=fuse, load=False)
     ctx = pp.pic_init(cfg, keep)
@@ -121,6 +122,10 @@ def _step_case(wlname, prec, fuse, n0):
     gez = pp.pic_get_grid(ctx, pp.PIC_GRID_EZ)
     get = pp.pic_get_grid(ctx, pp.PIC_GRID_ETHETA)
     gI = pp.pic_get_grid(ctx, pp.PIC_GRID_CURRENT)
+    if rfb:
+        gbr = pp.pic_get_grid(ctx, pp.PIC_GRID_BR)
+        gbz = pp.pic_get_grid(ctx, pp.PIC_GRID_BZ)
+        obr, obz = O.rf_bfield(ora.ec, ora.es, wl.dr, wl.dz, 2 * math.pi * wl.freq, O.theta(n0, ora.nrf))
     pp.mcc_collide(ctx, n0)
     pp.pic_deposit(ctx, n0 + 1)
     info = pp.poisson_solve_rz(ctx, n0 + 1, info=True)
@@ -132,6 +137,9 @@ def _step_case(wlname, prec, fuse, n0):
         res[name] = rel(a, b)
         bars[name] = tol if prec == "fp64" else 1e-6
     res["I"] = rel(gI, ora.I)
+    if rfb:
+        res["Br"], res["Bz"] = rel(gbr, obr), rel(gbz, obz)
+        bars["Br"] = bars["Bz"] = tol if prec == "fp64" else 1e-6
     for s in range(2):
         errs, mism = _compare_particles(pp.pic_get_particles(ctx, s), ora.live(s), prec, f"s={s}")
         res.update({f"{k}{s}": v for k, v in errs.items()})
@@ -164,6 +172,16 @@ def test_single_step_small(prec, fuse):
 def test_single_step_coil_cell(prec):
     _need_gpu()
     _step_case("cell", prec, True, n0=1234)
+
+
+@pytest.mark.parametrize("wlname,prec", [("small", "fp64"), ("small", "mixed"), ("cell", "fp64"), ("cell", "mixed")])
+def test_single_step_with_rf_magnetic_field(wlname, prec):
+    """The RF magnetic field of the applied azimuthal field (Faraday's law)
+    in the Boris rotation: the staged B_r, B_z against the oracle's, and the
+    whole step, at the single-step tolerances.  The small cell's loop field
+    turns velocities by about 1e-3 rad per step, far above the bars."""
+    _need_gpu()
+    _step_case(wlname, prec, True, n0=411 if wlname == "small" else 1234, rfb=True)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])

@@ -275,12 +275,14 @@ def test_t3_coupled_periods_reproduce_table(t3):
     assert abs(h["P_cap"] - math.sin(th) / th * h["P_cap_ph"]) < 1e-10 * abs(h["P_cap_ph"])
     # alpha = 1: the applied state solves the assembled network exactly
     assert rep["kcl"] < 1e-13 and rep["kvl"] < 1e-13
-    # remaining periods from the recurrence, the sampled path is the same
-    # linear map (checked above), 30 completed periods in all
-    for _ in range(29):
+    # periods 2..29 from the recurrence, the sampled path being the same
+    # linear map (checked above); the 30th period sampled again, for the
+    # power defects of the final completed period
+    for _ in range(28):
         icap = 1j * w * Ch @ fc.x[6:]
         xt = np.linalg.solve(fc.A, C.network_rhs(fc.vg, icap, np.zeros(5)))
         fc.x = xt
+    h30, rep30 = t3.period()
     xf = fc.x
     assert np.max(np.abs(xf - T3_FIELD)) < 6e-9 * np.max(np.abs(T3_FIELD[6:])), np.abs(xf - T3_FIELD)
     assert abs(_scaled_err(xf, T3_CONT) - T3["state_err_cont"]) < 0.01 * T3["state_err_cont"]
@@ -296,6 +298,14 @@ def test_t3_coupled_periods_reproduce_table(t3):
     assert abs(Sg - rhs) / abs(Sg) < 1e-10
     assert abs(w / 2 * WM.real - T3["Q_L"]) < 2e-5
     assert abs(-w / 2 * WC.real - T3["Q_C"]) < 2e-5
+    # capacitive power and the two normalised power defects of the final
+    # completed period (Sec. 3.3 text): P_cap 1.34e-5 W, eta_cap 1.004e-6,
+    # eta_coil 4.51e-7
+    eta_cap = abs(h30["P_cap"]) / (abs(T3["Q_L"]) + abs(T3["Q_C"]))
+    eta_coil = abs(rep30["p_port"] - rep30["p_cu"]) / abs(rep30["p_port"])
+    assert abs(h30["P_cap"] - T3["P_cap_W"]) < 0.01 * T3["P_cap_W"]
+    assert abs(eta_cap - T3["eta_cap"]) < 0.01 * T3["eta_cap"]
+    assert abs(eta_coil - T3["eta_coil"]) < 0.01 * T3["eta_coil"]
 
 
 def _exact_loads(fc, Ch):

@@ -8,6 +8,7 @@ radial weights, the current deposit, or the collision laws.
 import math
 import os
 import subprocess
+import ctypes
 
 import numpy as np
 import pytest
@@ -592,3 +593,109 @@ def test_moments_of_placed_and_uniform_plasmas():
     assert m[3] == pytest.approx(1.5 * wl.temp_ev[0], rel=5 * math.sqrt(2 / 3 / 2e6))
     assert m[5] == pytest.approx(2 * wl.rmax / 3, rel=5 * math.sqrt(1 / 18) / math.sqrt(2e6) / (2 / 3))
     assert m[6] == pytest.approx(wl.zp / 2, rel=5 * 0.2887 / math.sqrt(2e6) / 0.5)
+
+
+# ---------------------------------------------------------------------------
+# RF magnetic field of the applied azimuthal field (Faraday's law)
+# ---------------------------------------------------------------------------
+def _loop_b(R, z, a, zl, current):
+    """Textbook closed form (complete elliptic integrals) of the magnetic
+    field of a circular loop of radius a at height zl carrying `current`:
+    B_z = mu0 I / (2 pi) / sqrt((a+R)^2 + s^2) [K + (a^2 - R^2 - s^2) / ((a-R)^2 + s^2) E],
+    B_r = mu0 I / (2 pi) s / (R sqrt((a+R)^2 + s^2)) [-K + (a^2 + R^2 + s^2) / ((a-R)^2 + s^2) E],
+    s = z - zl, parameter m = 4 a R / ((a+R)^2 + s^2)."""
+    from scipy import special
+    s = z - zl
+    q = (a + R) ** 2 + s ** 2
+    m = 4 * a * R / q
+    K, E = special.ellipk(m), special.ellipe(m)
+    d = (a - R) ** 2 + s ** 2
+    c = W.MU0 * current / (2 * math.pi)
+    bz = c / np.sqrt(q) * (K + (a * a - R * R - s * s) / d * E)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        br = np.where(R > 0, c * s / (R * np.sqrt(q)) * (-K + (a * a + R * R + s * s) / d * E), 0.0)
+    return br, bz
+
+
+def test_rf_bfield_of_a_current_loop_converges_to_biot_savart():
+    """The small cell's applied field is that of a loop carrying 10 A cos(wt)
+    (E_c = 0, stored sine array -w A_theta).  Its Faraday field at phase 0
+    must be the loop's static field at 10 A: compared at the interior nodes
+    up to z = 0.08 m, the error falls as h^2 (ratio 4 per halving, within
+    3.5..4.5); the field
+    at phase pi/2 vanishes, and the phase dependence is the cos/sin mix of
+    the two."""
+    errs = []
+    for nr, nz in ((32, 64), (64, 128), (128, 256)):
+        wl = W.small(nr=nr, nz=nz, n_per_species=10)
+        w = 2 * math.pi * wl.freq
+        br, bz = pic.rf_bfield(wl.ec, wl.es_sto, wl.dr, wl.dz, w, 0.0)
+        R = np.arange(nr + 1) * wl.dr
+        z = np.arange(nz + 1) * wl.dz
+        ZZ, RR = np.meshgrid(z, R, indexing="ij")
+        rbr, rbz = _loop_b(RR, ZZ, 0.06, 0.11, 10.0)
+        # interior nodes at least 3 cm from the loop (the asymptotic range)
+        inner = (slice(1, int(round(0.08 / wl.dz)) + 1), slice(1, -1))
+        scale = max(np.abs(rbr[inner]).max(), np.abs(rbz[inner]).max())
+        errs.append(max(np.abs(br - rbr)[inner].max(), np.abs(bz - rbz)[inner].max()) / scale)
+        b2r, b2z = pic.rf_bfield(wl.ec, wl.es_sto, wl.dr, wl.dz, w, math.pi / 2)
+        assert np.max(np.abs(b2r)) < 1e-12 * scale and np.max(np.abs(b2z)) < 1e-12 * scale
+        # the axis row: B_r = 0 (odd in R) and B_z from the limit 2 dF/dR
+        assert abs(bz[nz // 2, 0] - rbz[nz // 2, 0]) / scale < 4 * errs[-1] + 1e-3
+    assert errs[0] < 0.05
+    for a, b in zip(errs[:-1], errs[1:]):
+        assert 3.5 < a / b < 4.5, errs
+    # linear in (cos, sin) of the phase: a general E_c, E_s^sto pair
+    rng = np.random.default_rng(1)
+    ec, es = rng.normal(size=(2, 9, 7))
+    th = 0.7
+    b0 = pic.rf_bfield(ec, es, 0.01, 0.02, 3.0, 0.0)
+    b1 = pic.rf_bfield(ec, es, 0.01, 0.02, 3.0, math.pi / 2)
+    bt = pic.rf_bfield(ec, es, 0.01, 0.02, 3.0, th)
+    for k in range(2):
+        np.testing.assert_allclose(bt[k], math.cos(th) * b0[k] + math.sin(th) * b1[k], atol=1e-12)
+
+
+def test_push_in_rf_magnetic_field_conserves_speed():
+    """E = 0 and a non-uniform node B (B_r, B_z): the Boris rotation keeps
+    every particle's speed (to rounding) and turns its velocity; with
+    uniform node values it is the uniform-field rotation (the species
+    block's B) exactly."""
+    g = pic.make_grid(16, 32, 0.1, 0.2)
+    S = pic.make_species(-W.QE, W.ME, 1.0, 1e-10)
+    rng = np.random.default_rng(8)
+    n = 2000
+    R = rng.uniform(0.005, 0.095, n)
+    z = rng.uniform(0.01, 0.19, n)
+    v = rng.normal(0, 1e6, (n, 3))
+    shape = (33, 17)
+    zero = np.zeros(shape)
+    Br = rng.uniform(-2e-3, 2e-3, shape)
+    Bz = rng.uniform(-2e-3, 2e-3, shape)
+    P = _parts(R, z, v[:, 0], v[:, 1], v[:, 2])
+    ab = np.zeros(n, np.int32)
+    I, surf = np.zeros(shape), np.zeros(shape)
+    lib = pic.lib()
+    _p = pic._p
+    _D, _I32 = pic._D, pic._I32
+    lib.ora_gather_push(ctypes.byref(g), ctypes.byref(S), n, _p(P.R, _D), _p(P.z, _D), _p(P.vr, _D), _p(P.vt, _D),
+                        _p(P.vz, _D), _p(P.alive, _I32), _p(ab, _I32), _p(zero, _D), _p(zero, _D), _p(zero, _D),
+                        _p(Br, _D), _p(Bz, _D), _p(I, _D), _p(surf, _D))
+    s0 = np.linalg.norm(v, axis=1)
+    s1 = np.sqrt(P.vr ** 2 + P.vt ** 2 + P.vz ** 2)
+    live = ab == 0
+    np.testing.assert_allclose(s1[live], s0[live], rtol=1e-14)
+    # the velocity did turn (in the particle's new frame the components differ)
+    assert np.mean(np.abs(P.vz - v[:, 2])) > 1e-3 * np.mean(s0)
+    # uniform node B equals the species block's uniform field
+    B0 = (1.5e-3, 0.0, -0.7e-3)
+    P1 = _parts(R, z, v[:, 0], v[:, 1], v[:, 2])
+    P2 = _parts(R, z, v[:, 0], v[:, 1], v[:, 2])
+    pic.gather_push_raw(g, pic.make_species(-W.QE, W.ME, 1.0, 1e-10, b=B0), P1, zero, zero, zero)
+    ab2 = np.zeros(n, np.int32)
+    lib.ora_gather_push(ctypes.byref(g), ctypes.byref(S), n, _p(P2.R, _D), _p(P2.z, _D), _p(P2.vr, _D),
+                        _p(P2.vt, _D), _p(P2.vz, _D), _p(P2.alive, _I32), _p(ab2, _I32), _p(zero, _D), _p(zero, _D),
+                        _p(zero, _D), _p(np.full(shape, B0[0]), _D), _p(np.full(shape, B0[2]), _D),
+                        _p(np.zeros(shape), _D), _p(np.zeros(shape), _D))
+    for k in ("vr", "vt", "vz", "R", "z"):
+        np.testing.assert_allclose(getattr(P2, k), getattr(P1, k), rtol=2e-14, atol=1e-300)
