@@ -507,3 +507,161 @@ int64_t ora_mcc(int sp, uint32_t seed, uint32_t step, const ora_xs *x, const ora
     }
     return nb;
 }
+
+/* ---------------------------------------------------------------------- */
+/* Direct-implicit step (the paper's electrostatic scheme, Sec. 2.3, after */
+/* Langdon, Cohen & Friedman's direct implicit method; the paper inherits  */
+/* the particle update and does not write it out).  The D1 time filter is  */
+/* used: with a = (q/m) E_es,                                              */
+/*   v^{n+1/2} = v^{n-1/2} + (dt/2) (a^{n+1} + abar^{n-1})                 */
+/*               + dt (q/m) E_theta(t_n) theta_hat,                        */
+/*   abar^n    = (a^{n+1} + abar^{n-1}) / 2,  x^{n+1} = x^n + dt v^{n+1/2}.*/
+/* The predictor moves with everything but a^{n+1} (positions x~, whose    */
+/* charge and susceptibility the implicit field solve uses); the corrector */
+/* adds (dt^2/2) a^{n+1}(x~) to the position and (dt/2) a^{n+1}(x~) to the */
+/* velocity.  abar is a 3-vector in the particle's local (r, theta, z)     */
+/* frame and turns with the velocity when the move rotates that frame.     */
+/* No magnetic field in this mode.                                         */
+/* ---------------------------------------------------------------------- */
+static void window_charge(const ora_grid *g, double Rs, double qw, double *surf)
+{
+    int js = (int)floor(Rs / g->dr);
+    if (js > g->nr - 1) js = g->nr - 1;
+    const double r0 = js * g->dr, r1 = (js + 1) * g->dr;
+    const double w1 = (Rs * Rs - r0 * r0) / (r1 * r1 - r0 * r0);
+    surf[node(g, g->ip, js)] += qw * (1 - w1);
+    surf[node(g, g->ip, js + 1)] += qw * w1;
+}
+
+/* Predictor of step n: kick by (dt/2) abar and the inductive field, J_theta
+ * at x^n with the time-centred v_theta, Cartesian move to x~ with v and abar
+ * turned into the new frame, absorption and window charge as in the
+ * explicit push. */
+void ora_di_predict(const ora_grid *g, const ora_species *s, int64_t n,
+                    double *R, double *z, double *vr, double *vt, double *vz,
+                    double *ar, double *at, double *az,
+                    int32_t *alive, int32_t *absorbed, const double *Et,
+                    double *Inode, double *surf)
+{
+    const double h = 0.5 * s->q / s->m * s->dt;
+    const double qw = s->q * s->w;
+    for (int64_t p = 0; p < n; ++p) {
+        absorbed[p] = 0;
+        if (!alive[p]) continue;
+        int j, i;
+        double wr1, wz1;
+        weights(g, R[p], z[p], &j, &i, &wr1, &wz1);
+        const double W[4] = {(1 - wz1) * (1 - wr1), (1 - wz1) * wr1, wz1 * (1 - wr1), wz1 * wr1};
+        const int64_t nd[4] = {node(g, i, j), node(g, i, j + 1), node(g, i + 1, j), node(g, i + 1, j + 1)};
+        double et = 0;
+        for (int k = 0; k < 4; ++k) et += W[k] * Et[nd[k]];
+        const double u[3] = {vr[p] + 0.5 * s->dt * ar[p], vt[p] + 0.5 * s->dt * at[p] + 2 * h * et,
+                             vz[p] + 0.5 * s->dt * az[p]};
+        const double vbar = 0.5 * (vt[p] + u[1]);
+        for (int k = 0; k < 4; ++k) Inode[nd[k]] += qw * vbar * W[k];
+        const double X = R[p] + u[0] * s->dt, Y = u[1] * s->dt;
+        const double znew = z[p] + u[2] * s->dt;
+        const double Rnew = sqrt(X * X + Y * Y);
+        double c = 1.0, sn = 0.0;
+        if (Rnew > 0) { c = X / Rnew; sn = Y / Rnew; }
+        const double a0 = ar[p], a1 = at[p];
+        int out = 0;
+        if (znew < 0) {
+            out = 1;
+        } else if (znew >= g->zp) {
+            out = 1;
+            if (g->window) {
+                const double ts = (g->zp - z[p]) / u[2];
+                const double xs = R[p] + u[0] * ts, ys = u[1] * ts;
+                const double Rs = sqrt(xs * xs + ys * ys);
+                if (Rs < g->rmax) {
+                    window_charge(g, Rs, qw, surf);
+                    out = 2;
+                }
+            }
+        } else if (Rnew >= g->rmax) {
+            out = 1;
+        }
+        R[p] = Rnew;
+        z[p] = znew;
+        vr[p] = c * u[0] + sn * u[1];
+        vt[p] = -sn * u[0] + c * u[1];
+        vz[p] = u[2];
+        ar[p] = c * a0 + sn * a1;
+        at[p] = -sn * a0 + c * a1;
+        if (out) {
+            alive[p] = 0;
+            absorbed[p] = out;
+        }
+    }
+}
+
+/* Corrector of step n: a = (q/m) (E_r, E_z)^{n+1} gathered at x~; position
+ * += (dt^2/2) a (radially and axially: the frame does not turn), velocity
+ * += (dt/2) a, abar = (a + abar) / 2.  A corrected radius below zero passes
+ * through the axis: R -> -R with the radial and azimuthal components of v
+ * and abar reversed.  Absorption as in the push, the window crossing taken
+ * on the correction segment. */
+void ora_di_correct(const ora_grid *g, const ora_species *s, int64_t n,
+                    double *R, double *z, double *vr, double *vt, double *vz,
+                    double *ar, double *at, double *az,
+                    int32_t *alive, int32_t *absorbed, const double *Er, const double *Ez, double *surf)
+{
+    const double qm = s->q / s->m, dt = s->dt;
+    const double qw = s->q * s->w;
+    for (int64_t p = 0; p < n; ++p) {
+        absorbed[p] = 0;
+        if (!alive[p]) continue;
+        int j, i;
+        double wr1, wz1;
+        weights(g, R[p], z[p], &j, &i, &wr1, &wz1);
+        const double W[4] = {(1 - wz1) * (1 - wr1), (1 - wz1) * wr1, wz1 * (1 - wr1), wz1 * wr1};
+        const int64_t nd[4] = {node(g, i, j), node(g, i, j + 1), node(g, i + 1, j), node(g, i + 1, j + 1)};
+        double er = 0, ez = 0;
+        for (int k = 0; k < 4; ++k) {
+            er += W[k] * Er[nd[k]];
+            ez += W[k] * Ez[nd[k]];
+        }
+        const double a_r = qm * er, a_z = qm * ez;
+        const double z0 = z[p];
+        double Rn = R[p] + 0.5 * dt * dt * a_r;
+        const double zn = z0 + 0.5 * dt * dt * a_z;
+        double v0 = vr[p] + 0.5 * dt * a_r, v1 = vt[p], v2 = vz[p] + 0.5 * dt * a_z;
+        double b0 = 0.5 * (a_r + ar[p]), b1 = 0.5 * at[p], b2 = 0.5 * (a_z + az[p]);
+        if (Rn < 0) {
+            Rn = -Rn;
+            v0 = -v0;
+            v1 = -v1;
+            b0 = -b0;
+            b1 = -b1;
+        }
+        int out = 0;
+        if (zn < 0) {
+            out = 1;
+        } else if (zn >= g->zp) {
+            out = 1;
+            if (g->window) {
+                const double f = (g->zp - z0) / (zn - z0);
+                const double Rs = fabs(R[p] + f * 0.5 * dt * dt * a_r);
+                if (Rs < g->rmax) {
+                    window_charge(g, Rs, qw, surf);
+                    out = 2;
+                }
+            }
+        } else if (Rn >= g->rmax) {
+            out = 1;
+        }
+        R[p] = Rn;
+        z[p] = zn;
+        vr[p] = v0;
+        vt[p] = v1;
+        vz[p] = v2;
+        ar[p] = b0;
+        at[p] = b1;
+        az[p] = b2;
+        if (out) {
+            alive[p] = 0;
+            absorbed[p] = out;
+        }
+    }
+}

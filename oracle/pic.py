@@ -107,6 +107,10 @@ def lib():
                               ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_D),
                               ctypes.POINTER(_I32), ctypes.POINTER(_I64)]
         L.ora_mcc.restype = _I64
+        di = [ctypes.POINTER(Grid), ctypes.POINTER(Species), _I64] + [ctypes.POINTER(_D)] * 8 + \
+            [ctypes.POINTER(_I32)] * 2
+        L.ora_di_predict.argtypes = di + [ctypes.POINTER(_D)] * 3
+        L.ora_di_correct.argtypes = di + [ctypes.POINTER(_D)] * 3
         _LIB = L
     return _LIB
 
@@ -176,6 +180,11 @@ class Particles:
         self.id = np.zeros(n, np.uint32)
         self.alive = np.ones(n, np.int32)
         self.next = np.zeros(n, np.int32)
+        # filtered electrostatic acceleration of the direct-implicit update
+        # (local frame), zero unless that update runs
+        self.ar = np.zeros(n)
+        self.at = np.zeros(n)
+        self.az = np.zeros(n)
 
     @property
     def n(self):
@@ -190,17 +199,19 @@ class Particles:
         self.id = np.concatenate([self.id, ids.astype(np.uint32)])
         self.alive = np.concatenate([self.alive, np.ones(len(R), np.int32)])
         self.next = np.concatenate([self.next, nxt.astype(np.int32)])
+        for k in ("ar", "at", "az"):
+            setattr(self, k, np.concatenate([getattr(self, k), np.zeros(len(R))]))
 
     def compact(self):
         m = self.alive.astype(bool)
-        for k in ("R", "z", "vr", "vt", "vz", "id", "alive", "next"):
+        for k in ("R", "z", "vr", "vt", "vz", "id", "alive", "next", "ar", "at", "az"):
             setattr(self, k, getattr(self, k)[m].copy())
 
     def live(self):
         """Dict of the live particles, sorted by id."""
         m = self.alive.astype(bool)
         o = np.argsort(self.id[m], kind="stable")
-        return {k: getattr(self, k)[m][o] for k in ("id", "R", "z", "vr", "vt", "vz", "next")}
+        return {k: getattr(self, k)[m][o] for k in ("id", "R", "z", "vr", "vt", "vz", "next", "ar", "at", "az")}
 
 
 def load_species(wl, s, lq=None):
@@ -358,26 +369,61 @@ class Poisson:
             v[self.tag == k] = ph
         return v
 
-    def solve(self, Q, turn_phi, ground=None):
-        """phi on all nodes for node charge Q (C) and turn potentials."""
+    def solve(self, Q, turn_phi, ground=None, chi=None):
+        """phi on all nodes for node charge Q (C) and turn potentials.  chi
+        (node array, optional): the direct-implicit susceptibility; every
+        face conductance is multiplied by 1 + (chi_a + chi_b) / 2 (Eq.
+        epseff) and the system is assembled and factored for this call."""
         vD = self.dirichlet_values(turn_phi, ground)
         rhs = Q.reshape(-1)[self.free].copy()
-        np.add.at(rhs, self.dir_a, self.dir_c * vD[self.dir_b])
+        if chi is None:
+            lu, dc = self.lu, self.dir_c
+        else:
+            f = self.face_factor(chi)
+            lu, dc = self._factor(self.fc * f)
+        np.add.at(rhs, self.dir_a, dc * vD[self.dir_b])
         phi = vD.copy()
-        phi[self.free] = self.lu.solve(rhs)
+        phi[self.free] = lu.solve(rhs)
         return phi.reshape(self.nz + 1, self.nr + 1)
 
-    def turn_charges(self, phi, nturns):
+    def face_factor(self, chi):
+        """1 + (chi_a + chi_b) / 2 of every face (Eq. epseff)."""
+        c = np.asarray(chi, dtype=np.float64).reshape(-1)
+        return 1.0 + 0.5 * (c[self.fa] + c[self.fb])
+
+    def _factor(self, cond):
+        """Sparse LU of the free-node system with face conductances cond, and
+        the conductances of the free-to-Dirichlet couplings (in the order of
+        dir_a / dir_b)."""
+        free, idx = self.free, self.idx
+        m = int(free.sum())
+        fa, fb = self.fa, self.fb
+        diag = np.zeros(m)
+        rows, cols, vals, dcs = [], [], [], []
+        for a, b, c in zip(fa, fb, cond):
+            for p, q in ((a, b), (b, a)):
+                if free[p]:
+                    diag[idx[p]] += c
+                    if free[q]:
+                        rows.append(idx[p]); cols.append(idx[q]); vals.append(-c)
+                    else:
+                        dcs.append(c)
+        A = sp.coo_matrix((vals, (rows, cols)), shape=(m, m)).tocsc() + sp.diags(diag).tocsc()
+        return spla.splu(A.tocsc()), np.array(dcs)
+
+    def turn_charges(self, phi, nturns, chi=None):
         """Q_k = sum over faces between a turn-k node and a node outside the
-        turn of c_f (phi_k - phi_nb) (Eq. facecharge)."""
+        turn of c_f (phi_k - phi_nb) (Eq. facecharge), with the same face
+        coefficients as the solve (chi included when given)."""
         ph = phi.reshape(-1)
+        fc = self.fc if chi is None else self.fc * self.face_factor(chi)
         Qk = np.zeros(nturns)
         ta, tb = self.tag[self.fa], self.tag[self.fb]
         for k in range(1, nturns + 1):
             m1 = (ta == k) & (tb != k)
             m2 = (tb == k) & (ta != k)
-            Qk[k - 1] = np.sum(self.fc[m1] * (ph[self.fa[m1]] - ph[self.fb[m1]])) + \
-                np.sum(self.fc[m2] * (ph[self.fb[m2]] - ph[self.fa[m2]]))
+            Qk[k - 1] = np.sum(fc[m1] * (ph[self.fa[m1]] - ph[self.fb[m1]])) + \
+                np.sum(fc[m2] * (ph[self.fb[m2]] - ph[self.fa[m2]]))
         return Qk
 
 
@@ -482,6 +528,8 @@ class OraclePIC:
             self.vc, self.vs = np.asarray(wl.turn_vc, np.float64), np.asarray(wl.turn_vs, np.float64)
             self.ec, self.es = np.asarray(wl.ec, np.float64), np.asarray(wl.es_sto, np.float64)
         self.surf = np.zeros(shape)
+        self.implicit = bool(wl.implicit)
+        self.chi = np.zeros(shape)
         self.parts = [load_species(wl, s, self.lq[s]) if load else Particles(0) for s in range(2)]
         self.next_id = [wl.np_init[0], wl.np_init[1]]
         self.counts = np.zeros((2, 5), np.int64)
@@ -565,8 +613,52 @@ class OraclePIC:
         return Q + self.surf
 
     def solve(self, n1):
-        self.phi = self.poisson.solve(self.Q, self.turn_phi(n1))
-        self.Qk = self.poisson.turn_charges(self.phi, self.wl.nturns)
+        chi = self.chi if self.implicit else None
+        self.phi = self.poisson.solve(self.Q, self.turn_phi(n1), self._ground(), chi=chi)
+        self.Qk = self.poisson.turn_charges(self.phi, self.wl.nturns, chi=chi)
+
+    def _ground(self):
+        """Dirichlet values of the grounded nodes: 0, or the manufactured
+        boundary sum_k basis_k V_k(t) (the workload's dir_basis)."""
+        return None
+
+    # -- direct-implicit update (Sec. 2.3; D1 filter, see cpic.c) ------------
+    def susceptibility(self):
+        """chi at the nodes from the predicted particles: (dt^2 / 2) / eps0
+        sum_s (q_s^2 / m_s) n_s, n_s the node density of species s (weights
+        over the node volume), i.e. half the squared plasma frequency times
+        dt^2 (Eq. poisson's chi, here the D1 scheme's)."""
+        from .circuit import node_volume
+        wl = self.wl
+        acc = np.zeros(self.shape)
+        for s in range(2):
+            P = self.parts[s]
+            lib().ora_deposit(ctypes.byref(self.grid), P.n, _p(P.R, _D), _p(P.z, _D), _p(P.alive, _I32),
+                              self.sp[s].q ** 2 / self.sp[s].m * self.sp[s].w, _p(acc, _D))
+        return 0.5 * wl.dt ** 2 / wl.eps0 * acc / node_volume(wl.nr, wl.nz, wl.dr, wl.dz)
+
+    def predict(self, n):
+        Et = np.ascontiguousarray(self.etheta(n), dtype=np.float64)
+        self.I = np.zeros(self.shape)
+        self.absorbed = []
+        for s in range(2):
+            P = self.parts[s]
+            ab = np.zeros(P.n, np.int32)
+            lib().ora_di_predict(ctypes.byref(self.grid), ctypes.byref(self.sp[s]), P.n,
+                                 _p(P.R, _D), _p(P.z, _D), _p(P.vr, _D), _p(P.vt, _D), _p(P.vz, _D),
+                                 _p(P.ar, _D), _p(P.at, _D), _p(P.az, _D), _p(P.alive, _I32), _p(ab, _I32),
+                                 _p(Et, _D), _p(self.I, _D), _p(self.surf, _D))
+            self.absorbed.append(ab)
+
+    def correct(self):
+        Er, Ez = (np.ascontiguousarray(a) for a in e_from_phi(self.phi, self.wl.dr, self.wl.dz))
+        for s in range(2):
+            P = self.parts[s]
+            ab = np.zeros(P.n, np.int32)
+            lib().ora_di_correct(ctypes.byref(self.grid), ctypes.byref(self.sp[s]), P.n,
+                                 _p(P.R, _D), _p(P.z, _D), _p(P.vr, _D), _p(P.vt, _D), _p(P.vz, _D),
+                                 _p(P.ar, _D), _p(P.at, _D), _p(P.az, _D), _p(P.alive, _I32), _p(ab, _I32),
+                                 _p(Er, _D), _p(Ez, _D), _p(self.surf, _D))
 
     # -- harmonics ----------------------------------------------------------------
     def reset_harmonics(self):
@@ -632,6 +724,8 @@ class OraclePIC:
 
     # -- one whole step -----------------------------------------------------------
     def step(self):
+        if self.implicit:
+            return self.step_implicit()
         n = self.n
         self.gather_push(n)
         self.harmonic(n)
@@ -640,6 +734,26 @@ class OraclePIC:
         if self.fc is not None and (n + 1) % self.nrf == 0:
             self.period_update()
         self.solve(n + 1)
+        self.n = n + 1
+        for P in self.parts:
+            P.compact()
+
+    def step_implicit(self):
+        """Direct-implicit step n: predictor (with J_theta^n), harmonics,
+        charge and susceptibility at the predicted positions, the period
+        update when due, the Poisson solve with chi, corrector, MCC on the
+        corrected v^{n+1/2} at x^{n+1} (births join with zero filtered
+        acceleration)."""
+        n = self.n
+        self.predict(n)
+        self.harmonic(n)
+        self.Q = self.deposit()
+        self.chi = self.susceptibility()
+        if self.fc is not None and (n + 1) % self.nrf == 0:
+            self.period_update()
+        self.solve(n + 1)
+        self.correct()
+        self.mcc(n)
         self.n = n + 1
         for P in self.parts:
             P.compact()

@@ -144,6 +144,7 @@ class Workload:
     circuit: CircuitParams = None     # None: prescribed E_theta and turn potentials
     bfield: tuple = (0.0, 0.0, 0.0)   # uniform (B_r, B_theta, B_z), tests only
     rf_bfield: bool = False           # the RF magnetic field of the applied E_theta in the Boris rotation
+    implicit: bool = False            # direct-implicit electrostatic update (D1 filter) instead of explicit
     xs: CrossSections = dataclasses.field(default_factory=CrossSections)
     capacity_factor: float = 1.5
     eps0: float = EPS0                # vacuum permittivity of the Poisson operator

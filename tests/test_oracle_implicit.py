@@ -1,0 +1,150 @@
+"""Pins of the oracle's direct-implicit electrostatic update (the paper's
+Sec. 2.3: Eqs. poisson, implicit_charge_relation, epseff; the D1 time
+filter of the direct implicit method it cites):
+
+* the D1 velocity and position recurrence in a uniform static field, in
+  closed form;
+* the susceptibility against (omega_pe dt)^2 / 2 for a uniform load;
+* the chi-operator: chi = 0 is the explicit operator exactly; a uniform chi
+  scales the potential of a fixed charge by 1 / (1 + chi) and the conductor
+  charges of fixed conductor potentials by 1 + chi (Eqs. poisson, epseff,
+  facecharge);
+* the linearised charge relation: after the implicit solve, the charge the
+  corrected particles deposit is the charge A_0 phi (the operator without
+  chi applied to the new potential) far more closely than the predicted
+  charge is: the numerical polarisation accounts for the correction.
+"""
+import ctypes
+import math
+
+import numpy as np
+import pytest
+
+from oracle import pic
+from oracle.circuit import node_volume
+from paper_2609_15043_amd import workloads as W
+
+
+def _raw(fn, g, S, P, *arrays):
+    ab = np.zeros(P.n, np.int32)
+    _p, _D, _I32 = pic._p, pic._D, pic._I32
+    getattr(pic.lib(), fn)(ctypes.byref(g), ctypes.byref(S), P.n, _p(P.R, _D), _p(P.z, _D), _p(P.vr, _D),
+                           _p(P.vt, _D), _p(P.vz, _D), _p(P.ar, _D), _p(P.at, _D), _p(P.az, _D),
+                           _p(P.alive, _I32), _p(ab, _I32), *[_p(a, _D) for a in arrays])
+    return ab
+
+
+def test_d1_recurrence_in_a_uniform_field():
+    """Uniform E_z, particles moving along z: abar^n = a (1 - 2^-(n+1)),
+    v^{n+1/2} = v^{-1/2} + a dt (n + 2^-(n+1)), x^{n+1} = x^n + dt v^{n+1/2}."""
+    g = pic.make_grid(8, 64, 0.1, 1.0)
+    dt, E = 1e-9, 300.0
+    S = pic.make_species(-W.QE, W.ME, 1.0, dt)
+    a = -W.QE / W.ME * E
+    P = pic.Particles(3)
+    P.R[:] = [0.01, 0.05, 0.07]
+    P.z[:] = [0.4, 0.5, 0.6]
+    P.vz[:] = [1e4, -2e4, 0.0]
+    P.id[:] = np.arange(3)
+    v0, z0 = P.vz.copy(), P.z.copy()
+    shape = (65, 9)
+    zero, Ez = np.zeros(shape), np.full(shape, E)
+    I, surf = np.zeros(shape), np.zeros(shape)
+    z = z0.copy()
+    for n in range(12):
+        _raw("ora_di_predict", g, S, P, zero, I, surf)
+        _raw("ora_di_correct", g, S, P, zero, Ez, surf)
+        v = v0 + a * dt * (n + 2.0 ** -(n + 1))
+        z = z + dt * v
+        np.testing.assert_allclose(P.vz, v, rtol=1e-13)
+        np.testing.assert_allclose(P.az, a * (1 - 2.0 ** -(n + 1)), rtol=1e-13)
+        np.testing.assert_allclose(P.z, z, rtol=1e-13)
+        assert np.all(P.vr == 0) and np.all(P.vt == 0) and np.all(P.R == [0.01, 0.05, 0.07])
+
+
+def test_susceptibility_of_a_uniform_load():
+    wl = W.small(n_per_species=200_000)
+    wl.implicit = True
+    ora = pic.OraclePIC(wl)
+    chi = ora.susceptibility()
+    wpe2 = wl.n0 * W.QE ** 2 / (W.EPS0 * W.ME)
+    wpi2 = wl.n0 * W.QE ** 2 / (W.EPS0 * W.M_AR)
+    expect = 0.5 * (wpe2 + wpi2) * wl.dt ** 2
+    assert chi[5:-5, 5:-5].mean() == pytest.approx(expect, rel=0.01)
+
+
+def test_chi_operator_identities():
+    wl = W.cell(n_per_species=10, circuit=False)
+    Pn = pic.Poisson(wl.nr, wl.nz, wl.dr, wl.dz, wl.eps_cell, wl.node_tag, W.EPS0)
+    rng = np.random.default_rng(5)
+    shape = (wl.nz + 1, wl.nr + 1)
+    Q = np.zeros(shape)
+    Q[: wl.ip] = rng.normal(size=(wl.ip, wl.nr + 1)) * 1e-15
+    zero_v = np.zeros(wl.nturns)
+    phi0 = Pn.solve(Q, zero_v)
+    # chi = 0: the explicit operator
+    assert np.array_equal(Pn.solve(Q, zero_v, chi=np.zeros(shape)), phi0)
+    # uniform chi, fixed charge, grounded conductors: phi / (1 + chi)
+    c = 0.37
+    phic = Pn.solve(Q, zero_v, chi=np.full(shape, c))
+    assert np.max(np.abs(phic * (1 + c) - phi0)) <= 1e-12 * np.max(np.abs(phi0))
+    # uniform chi, no charge, fixed turn potentials: phi unchanged, Q_k x (1 + chi)
+    V = rng.uniform(50, 300, wl.nturns)
+    p0 = Pn.solve(np.zeros(shape), V)
+    pc = Pn.solve(np.zeros(shape), V, chi=np.full(shape, c))
+    assert np.max(np.abs(pc - p0)) <= 1e-12 * np.max(np.abs(p0))
+    q0 = Pn.turn_charges(p0, wl.nturns)
+    qc = Pn.turn_charges(pc, wl.nturns, chi=np.full(shape, c))
+    np.testing.assert_allclose(qc, (1 + c) * q0, rtol=1e-11)
+
+
+def _apply_op(Pn, phi, chi=None):
+    """(A phi)_p = sum_f c_f (phi_p - phi_nb) on every node."""
+    ph = phi.reshape(-1)
+    fc = Pn.fc if chi is None else Pn.fc * Pn.face_factor(chi)
+    out = np.zeros(ph.size)
+    d = fc * (ph[Pn.fa] - ph[Pn.fb])
+    np.add.at(out, Pn.fa, d)
+    np.add.at(out, Pn.fb, -d)
+    return out.reshape(phi.shape)
+
+
+def test_linearised_charge_relation():
+    """The susceptibility is the particles' own linear response (Eq.
+    implicit_charge_relation): electrons on a quiet lattice (uniform in
+    volume), a prescribed smooth potential phi; the charge change the
+    corrector's displacements make, Q(x^{n+1}) - Q(x~), projects onto the
+    chi operator's prediction -(A_chi - A_0) phi with a ratio of 1 within
+    3 % for three axial modes (a chi off by a factor 2 gives 0.5 or 2).
+    The projection, not the pointwise difference, is compared: the lattice
+    and the grid interfere at the grid scale."""
+    wl = W.small(n_per_species=10)
+    wl.implicit = True
+    wl.dt = 2e-10
+    nu, nzl = 400, 800
+    n = nu * nzl
+    ora = pic.OraclePIC(wl, load=False)
+    P = pic.Particles(n)
+    u = (np.arange(nu) + 0.5) / nu
+    zz = (np.arange(nzl) + 0.5) / nzl * wl.zmax
+    U, Z = np.meshgrid(u, zz, indexing="ij")
+    P.R[:] = (wl.rmax * np.sqrt(U)).ravel()
+    P.z[:] = Z.ravel()
+    P.id[:] = np.arange(n)
+    ora.parts = [P, pic.Particles(0)]
+    chi = ora.susceptibility()
+    Q0 = ora.deposit()
+    R = np.arange(wl.nr + 1) * wl.dr
+    z = np.arange(wl.nz + 1) * wl.dz
+    m = np.zeros(Q0.shape, bool)
+    m[4:-4, 1:-4] = True
+    save = {k: getattr(P, k).copy() for k in ("R", "z", "vr", "vt", "vz", "ar", "at", "az", "alive")}
+    for mode in (1, 2, 4):
+        for k, v in save.items():
+            setattr(P, k, v.copy())
+        ora.phi = 50.0 * np.outer(np.sin(mode * math.pi * z / wl.zmax), np.cos(0.5 * math.pi * R / wl.rmax))
+        ora.correct()
+        dQ = (ora.deposit() - Q0)[m]
+        pred = -(_apply_op(ora.poisson, ora.phi, chi) - _apply_op(ora.poisson, ora.phi))[m]
+        ratio = float(dQ @ pred / (pred @ pred))
+        assert abs(ratio - 1.0) < 0.03, (mode, ratio)
