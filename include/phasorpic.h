@@ -28,6 +28,10 @@
  *       pic_gather_push(n); harmonic_accumulate(n); mcc_collide(n);
  *       pic_deposit(n+1); [circuit_period_update() when (n+1) % N_RF == 0];
  *       poisson_solve_rz(n+1, ...)
+ *   and with the direct-implicit update (pic_config.implicit), where the
+ *   particles' correction follows the field solve:
+ *       pic_gather_push(n); harmonic_accumulate(n); pic_deposit(n+1);
+ *       [circuit_period_update()]; poisson_solve_rz(n+1, ...); mcc_collide(n)
  */
 #ifndef PHASORPIC_H
 #define PHASORPIC_H
@@ -75,6 +79,7 @@ enum {
     PIC_GRID_ES_PLASMA = 12,  /* plasma-only E_s^sto,p of the last circuit update */
     PIC_GRID_BR = 13,      /* staged RF B_r of the last pic_gather_push (T), cfg->rf_bfield only */
     PIC_GRID_BZ = 14,      /* staged RF B_z (T) */
+    PIC_GRID_CHI = 15,     /* direct-implicit susceptibility of the last pic_deposit, cfg->implicit only */
     PIC_GRID_UNIT = 16     /* + k: unit-current field U_k of turn k+1 (V/m per A) */
 };
 
@@ -156,6 +161,22 @@ typedef struct pic_config {
      * B_z = -(1/R) d(R F)/dR at t_n, staged per node by central differences and gathered with the
      * particle weights (the paper leaves the push's magnetic field unstated) */
     int32_t rf_bfield;
+    /* 1: direct-implicit electrostatic update (Sec. 2.3: the charge and the susceptibility chi of
+     * Eqs. poisson and epseff from predicted positions), with the D1 time filter of the direct
+     * implicit method the paper cites (see the step order above).  Per step:
+     *   pic_gather_push(n): predictor -- the electrostatic kick is each particle's filtered half kick
+     *     (dt/2) abar^{n-1}, the inductive kick dt (q/m) E_theta(t_n) explicit, J_theta^n deposited,
+     *     move to the predicted positions x~, whose charge is deposited;
+     *   harmonic_accumulate(n);
+     *   pic_deposit(n+1): rho~ and chi = (dt^2 / 2) sum_s q_s^2 n_s / (m_s eps0) at the nodes from
+     *     x~, and the level-0 operator with face coefficients eps_r (1 + (chi_a + chi_b) / 2);
+     *   [circuit_period_update()];
+     *   poisson_solve_rz(n+1): phi^{n+1} with chi (the coarse multigrid levels keep the chi = 0
+     *     operator as CG preconditioner; Q_k with the same face coefficients, Eq. facecharge);
+     *   mcc_collide(n): corrector -- x += dt (dt/2) a^{n+1}(x~), v += (dt/2) a^{n+1}, abar =
+     *     (a^{n+1} + abar) / 2 -- then the collisions of v^{n+1/2} at x^{n+1} and the births.
+     * No magnetic field (bfield, rf_bfield) in this mode. */
+    int32_t implicit;
 } pic_config;
 
 typedef struct pic_solve_info {

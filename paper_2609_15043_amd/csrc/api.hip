@@ -35,7 +35,7 @@ struct Carver {
     }
 };
 
-template <typename T> void carve_parts(Carver &c, Parts<T> &p, int64_t cap)
+template <typename T> void carve_parts(Carver &c, Parts<T> &p, int64_t cap, bool implicit)
 {
     cap = (cap + PAD - 1) / PAD * PAD;   // the pass reads and writes whole blocks of particles
     p.cell = c.take<int32_t>(cap);
@@ -46,6 +46,12 @@ template <typename T> void carve_parts(Carver &c, Parts<T> &p, int64_t cap)
     p.vz = c.take<T>(cap);
     p.id = c.take<uint32_t>(cap);
     p.next = c.take<int32_t>(cap);
+    p.fr = p.ft = p.fz = nullptr;
+    if (implicit) {
+        p.fr = c.take<T>(cap);
+        p.ft = c.take<T>(cap);
+        p.fz = c.take<T>(cap);
+    }
 }
 
 template <typename T> void carve_births(Carver &c, Births<T> &b, int cap)
@@ -96,6 +102,7 @@ struct pic_ctx {
     int64_t last_push = -1;
     int64_t last_harm = -1;
     int64_t last_mcc = -1;
+    int64_t last_dep = 0;
     bool pushed_since_sort = false;
 
     // particles (ping-pong per species)
@@ -123,6 +130,8 @@ struct pic_ctx {
     double *phi = nullptr, *Q = nullptr, *I = nullptr, *d_ec = nullptr, *d_es = nullptr;
     int32_t *d_tag = nullptr;
     double *dbasis = nullptr;     // manufactured Dirichlet basis, nturns x nodes (or none)
+    // direct-implicit update: node susceptibility and the chi = 0 level-0 conductances
+    double *chi = nullptr, *cw0 = nullptr, *ce0 = nullptr, *cs0 = nullptr, *cn0 = nullptr;
     double *d_vc = nullptr, *d_vs = nullptr;
     double *Jc = nullptr, *Jcc = nullptr, *Js = nullptr, *Jsc = nullptr, *hpartial = nullptr;
     HarmState *harm = nullptr;
@@ -142,7 +151,12 @@ struct pic_ctx {
     MGState *mg_host = nullptr;   // pinned ring
     int mg_ring = 0;
     int mg_budget = 8;
-    bool mg_fresh = false;        // next solve runs max_cycles (the turn potentials just changed)
+    // a circuit update moves the turn potentials by a whole period's
+    // correction: the solves until the start-value extrapolation again spans
+    // only solutions after the jump run max_cycles, and the extrapolation
+    // restarts from the first of them
+    int mg_fresh = 0;             // solves left at max_cycles
+    bool mg_restart = false;      // the stored solutions predate the jump
     int32_t *fp = nullptr, *fq = nullptr, *fk = nullptr;
     double *fc = nullptr, *Qk = nullptr;
     int nfaces = 0;
@@ -455,9 +469,9 @@ static void layout(pic_ctx &c, Carver &cv)
     for (int s = 0; s < 2; ++s)
         for (int b = 0; b < 2; ++b) {
             if (c.mixed)
-                carve_parts(cv, c.pf[s][b], f.capacity[s]);
+                carve_parts(cv, c.pf[s][b], f.capacity[s], f.implicit != 0);
             else
-                carve_parts(cv, c.pd[s][b], f.capacity[s]);
+                carve_parts(cv, c.pd[s][b], f.capacity[s], f.implicit != 0);
         }
     const int bcap = f.birth_capacity > 0 ? f.birth_capacity : 65536;
     if (c.mixed)
@@ -495,6 +509,13 @@ static void layout(pic_ctx &c, Carver &cv)
     c.d_es = cv.take<double>(nodes);
     c.d_tag = cv.take<int32_t>(nodes);
     if (f.dir_basis && f.nturns > 0) c.dbasis = cv.take<double>((size_t)f.nturns * nodes);
+    if (f.implicit) {
+        c.chi = cv.take<double>(nodes);
+        c.cw0 = cv.take<double>(nodes);
+        c.ce0 = cv.take<double>(nodes);
+        c.cs0 = cv.take<double>(nodes);
+        c.cn0 = cv.take<double>(nodes);
+    }
     c.d_vc = cv.take<double>(MAX_TURNS);
     c.d_vs = cv.take<double>(MAX_TURNS);
     c.Jc = cv.take<double>(nodes);
@@ -636,6 +657,8 @@ static pic_status check_config(const pic_config *f, pic_ctx *c)
     if (f->sort_every < 1) return fail(c, PIC_EINVAL, "sort_every must be >= 1");
     if (f->sort_every_ion < 0) return fail(c, PIC_EINVAL, "sort_every_ion must be >= 0");
     if (f->birth_capacity < 0) return fail(c, PIC_EINVAL, "birth_capacity < 0");
+    if (f->implicit && (f->rf_bfield || f->bfield[0] != 0.0 || f->bfield[1] != 0.0 || f->bfield[2] != 0.0))
+        return fail(c, PIC_EINVAL, "the direct-implicit update runs without magnetic field");
     return PIC_OK;
 }
 
@@ -777,11 +800,22 @@ template <typename T> static void run_births(pic_ctx &c, bool deposit)
                      c.errw, c.stats, c.cq[0].count, c.cq[1].count, c.stream);
 }
 
-static void finalize_charge(pic_ctx &c)
+// with_chi: the direct-implicit susceptibility of the deposited (predicted)
+// particles joins the operator; the initial solve at the loaded positions is
+// the plain Poisson problem (no push precedes it)
+static void finalize_charge(pic_ctx &c, bool with_chi)
 {
     const pic_config &f = c.cfg;
     launch_finalize_q(c.accQ, c.accW, c.accS, 1.0 / c.qscale, f.q[0] * f.w[0] / c.qscale, f.q[1] * f.w[1] / c.qscale,
                       f.q[0] * f.w[0], f.q[1] * f.w[1], c.Q, c.g.nodes, c.stream);
+    if (c.chi && with_chi) {
+        // susceptibility of the deposited (predicted) particles and the
+        // level-0 operator with it; the coarse levels keep the chi = 0
+        // Galerkin operators as the preconditioner of the CG
+        const double k = 0.5 * f.dt * f.dt / f.eps0 / c.qscale;
+        launch_chi(c.accQ, k * f.q[0] * f.q[0] / f.m[0] * f.w[0], k * f.q[1] * f.q[1] / f.m[1] * f.w[1], c.chi,
+                   c.cw0, c.ce0, c.cs0, c.cn0, c.lv.L[0], c.g, c.stream);
+    }
 }
 
 // V-cycle on the correction (level 0: right-hand side = the CG residual r,
@@ -873,17 +907,20 @@ static pic_status solve(pic_ctx &c, int64_t n, double rtol, int max_cycles, pic_
             c.mg_budget = std::min(max_cycles, seen + 1);
         }
         budget = std::max(2, std::min(max_cycles, c.mg_budget));
-        // a circuit update moves the turn potentials by a whole period's
-        // correction and the time extrapolation of the start value no
-        // longer holds: that solve gets the full budget (iterations past
+        // after a circuit update (or a restore) the recent counts say
+        // nothing about this start value: full budget (iterations past
         // convergence are no-ops)
-        if (c.mg_fresh) budget = max_cycles;
+        if (c.mg_fresh > 0) budget = max_cycles;
+        // the direct-implicit operator changes with chi every step while the
+        // coarse levels precondition with the chi = 0 operator: the counts
+        // of earlier solves do not bound this one
+        if (c.cfg.implicit) budget = max_cycles;
     }
-    c.mg_fresh = false;
-    // extrapolate only across consecutive steps of a running sequence
+    c.mg_fresh = std::max(0, c.mg_fresh - 1);
     // extrapolate only across consecutive steps of a running sequence: linear
     // once two previous solutions are stored, quadratic once three are
-    c.run = (n == c.last_solve + 1 && !full && !info) ? c.run + 1 : 0;
+    c.run = (n == c.last_solve + 1 && !full && !info && !c.mg_restart) ? c.run + 1 : 0;
+    c.mg_restart = false;
     const int order = c.run >= 3 ? 2 : c.run >= 2 ? 1 : 0;
     launch_pcg_begin(L0, v, c.d_tag, c.d_vc, c.d_vs, std::cos(th), std::sin(th), c.mgs, c.phi_prev, order, c.stream,
                      c.dbasis, c.cfg.nturns);
@@ -897,7 +934,7 @@ static pic_status solve(pic_ctx &c, int64_t n, double rtol, int max_cycles, pic_
     for (int k = 0; k < budget; ++k)
         pcg_iteration(c, c.lv, c.mgs, v, rtol, k, k == budget - 1 ? c.stats + ST_MGUNCONV : nullptr);
     if (c.cfg.nturns > 0)
-        launch_face_charge(c.phi, c.fp, c.fq, c.fk, c.fc, c.nfaces, c.Qk, c.cfg.nturns, c.stream);
+        launch_face_charge(c.phi, c.fp, c.fq, c.fk, c.fc, c.nfaces, c.Qk, c.cfg.nturns, c.stream, c.chi);
     timer_stop(c, c.t_poisson);
     if (c.mg_host) {
         (void)hipMemcpyAsync(c.mg_host + c.mg_ring, c.mgs, sizeof(MGState), hipMemcpyDeviceToHost, c.stream);
@@ -1229,6 +1266,15 @@ template <typename T> static pic_status init_impl(pic_ctx &c)
         }
         pic_status bs = build_levels(c, c.lv, co, dir);
         if (bs) return bs;
+        if (c.chi) {
+            // chi = 0 conductances, from which every step's operator is formed
+            const size_t nb = (size_t)nodes * sizeof(double);
+            HIPCHK(&c, cpy(c.stream, c.cw0, co.cw.data(), nb, hipMemcpyHostToDevice));
+            HIPCHK(&c, cpy(c.stream, c.ce0, co.ce.data(), nb, hipMemcpyHostToDevice));
+            HIPCHK(&c, cpy(c.stream, c.cs0, co.cs.data(), nb, hipMemcpyHostToDevice));
+            HIPCHK(&c, cpy(c.stream, c.cn0, co.cn.data(), nb, hipMemcpyHostToDevice));
+            HIPCHK(&c, mset(c.stream, c.chi, 0, nb));
+        }
         for (double *v : {c.pr, c.pz, c.pp, c.pp2, c.pAp, c.phi_prev, c.phi_prev + nodes})
             HIPCHK(&c, mset(c.stream, v, 0, (size_t)nodes * sizeof(double)));
     }
@@ -1300,7 +1346,7 @@ template <typename T> static pic_status init_impl(pic_ctx &c)
     }
     stage<T>(c, 0);
     run_pass<T>(c, 0, false, true);
-    finalize_charge(c);
+    finalize_charge(c, false);
     pic_status s = solve(c, 0, f.mg_rtol, f.mg_max_cycles, nullptr, true);
     if (s) return s;
     HIPCHK(&c, hipStreamSynchronize(st));
@@ -1362,6 +1408,9 @@ extern "C" pic_status pic_gather_push(pic_ctx *c, int64_t n)
     if (n != c->last_push + 1) return fail(c, PIC_ESTATE, "pic_gather_push(%lld) after step %lld", (long long)n,
                                            (long long)c->last_push);
     if (n > 2147483000ll) return fail(c, PIC_EINVAL, "step index too large");
+    if (c->cfg.implicit && c->last_push >= 0 && c->last_mcc != c->last_push)
+        return fail(c, PIC_ESTATE, "pic_gather_push(%lld) before the corrector of step %lld (mcc_collide)",
+                    (long long)n, (long long)c->last_push);
     const bool fuse = c->cfg.fuse != 0;
     const int every_ion = c->cfg.sort_every_ion > 0 ? c->cfg.sort_every_ion : c->cfg.sort_every;
     const bool sort_e = n > 0 && n % c->cfg.sort_every == 0, sort_i = n > 0 && n % every_ion == 0;
@@ -1380,10 +1429,34 @@ extern "C" pic_status pic_gather_push(pic_ctx *c, int64_t n)
     return hipGetLastError() == hipSuccess ? PIC_OK : fail(c, PIC_EDEVICE, "kernel launch failed");
 }
 
+// Direct-implicit step n after the field solve: E^{n+1} staged from
+// phi^{n+1}, the corrector (positions, velocities, filter, absorption,
+// collision candidates), then the collisions and births (their charge
+// joins the next step's predicted deposit).
+template <typename T> static void implicit_correct_collide(pic_ctx &c, int64_t n)
+{
+    launch_stage<T>(c.phi, c.d_ec, c.d_es, 1.0, 0.0, reinterpret_cast<typename Field4<T>::type *>(c.ef), c.accJ,
+                    c.accQ, false, c.g, c.stream);
+    launch_correct<T>(pass_args<T>(c, 0, n), pass_args<T>(c, 1, n), c.cfg.capacity[0], c.cfg.capacity[1], c.stream);
+    run_collide<T>(c, n);
+    run_births<T>(c, false);
+}
+
 extern "C" pic_status mcc_collide(pic_ctx *c, int64_t n)
 {
     if (!c) return PIC_EINVAL;
     if (n != c->last_push || c->last_mcc == n) return fail(c, PIC_ESTATE, "mcc_collide(%lld) out of order", (long long)n);
+    if (c->cfg.implicit) {
+        if (c->last_solve != n + 1 || c->last_dep != n + 1)
+            return fail(c, PIC_ESTATE, "direct-implicit mcc_collide(%lld) before pic_deposit and poisson_solve_rz(%lld)",
+                        (long long)n, (long long)(n + 1));
+        if (c->mixed)
+            implicit_correct_collide<float>(*c, n);
+        else
+            implicit_correct_collide<double>(*c, n);
+        c->last_mcc = n;
+        return hipGetLastError() == hipSuccess ? PIC_OK : fail(c, PIC_EDEVICE, "kernel launch failed");
+    }
     const bool fuse = c->cfg.fuse != 0;
     if (c->mixed) {
         run_collide<float>(*c, n);
@@ -1399,15 +1472,19 @@ extern "C" pic_status mcc_collide(pic_ctx *c, int64_t n)
 extern "C" pic_status pic_deposit(pic_ctx *c, int64_t n1)
 {
     if (!c) return PIC_EINVAL;
-    if (n1 != c->last_push + 1 || c->last_mcc != c->last_push)
-        return fail(c, PIC_ESTATE, "pic_deposit(%lld) out of order", (long long)n1);
+    // explicit: after the collisions of step n1 - 1; direct-implicit: before them
+    // (the corrector follows the field solve)
+    const bool ok = c->cfg.implicit ? (n1 == c->last_push + 1 && c->last_mcc != c->last_push && c->last_dep != n1)
+                                    : (n1 == c->last_push + 1 && c->last_mcc == c->last_push);
+    if (!ok) return fail(c, PIC_ESTATE, "pic_deposit(%lld) out of order", (long long)n1);
+    c->last_dep = n1;
     if (!c->cfg.fuse) {
         if (c->mixed)
             run_pass<float>(*c, n1 - 1, false, true);
         else
             run_pass<double>(*c, n1 - 1, false, true);
     }
-    finalize_charge(*c);
+    finalize_charge(*c, true);
     return hipGetLastError() == hipSuccess ? PIC_OK : fail(c, PIC_EDEVICE, "kernel launch failed");
 }
 
@@ -1705,8 +1782,11 @@ extern "C" pic_status circuit_period_update(pic_ctx *c, const pic_circuit_overri
         }
     }
     // the turn potentials move by a whole period's correction: the next
-    // Poisson solve gets its full iteration budget
-    c->mg_fresh = true;
+    // Poisson solves restart the start-value extrapolation at full budget
+    // (three of them: until the quadratic extrapolation again spans only
+    // solutions after the jump)
+    c->mg_fresh = 3;
+    c->mg_restart = true;
     return reset_period(c);
 }
 
@@ -1724,7 +1804,7 @@ struct CkptHead {
     int32_t precision, nr, nz, nturns, circuit, nrf;
     int64_t capacity[2], count[2];
     int64_t last_push, last_harm, last_mcc, last_solve;
-    int32_t run, mg_budget;
+    int32_t run, mg_budget, mg_fresh, mg_restart;
     double qscale, jscale;
     uint64_t total;
 };
@@ -1758,6 +1838,14 @@ static std::vector<Seg> state_segments(pic_ctx &c, const int64_t count[2])
         for (int k = 0; k < 5; ++k) v.push_back({p[k], n * es});
         v.push_back({id, n * 4});
         v.push_back({next, n * 4});
+        if (c.cfg.implicit) {
+            void *f[3];
+            if (c.mixed)
+                f[0] = c.pf[s][c.cur[s]].fr, f[1] = c.pf[s][c.cur[s]].ft, f[2] = c.pf[s][c.cur[s]].fz;
+            else
+                f[0] = c.pd[s][c.cur[s]].fr, f[1] = c.pd[s][c.cur[s]].ft, f[2] = c.pd[s][c.cur[s]].fz;
+            for (int k = 0; k < 3; ++k) v.push_back({f[k], n * es});
+        }
     }
     const size_t nb = (size_t)nodes * sizeof(double);
     v.push_back({c.ctl, 8 * sizeof(int64_t)});
@@ -1808,6 +1896,8 @@ extern "C" pic_status pic_checkpoint(pic_ctx *c, void *buf, size_t cap, size_t *
     h.last_solve = c->last_solve;
     h.run = c->run;
     h.mg_budget = c->mg_budget;
+    h.mg_fresh = c->mg_fresh;
+    h.mg_restart = c->mg_restart;
     h.qscale = c->qscale;
     h.jscale = c->jscale;
     const std::vector<Seg> segs = state_segments(*c, h.count);
@@ -1861,7 +1951,8 @@ extern "C" pic_status pic_restore(pic_ctx *c, const void *buf, size_t bytes)
     c->last_solve = h.last_solve;
     c->run = h.run;
     c->mg_budget = h.mg_budget;
-    c->mg_fresh = true;
+    c->mg_fresh = std::max(h.mg_fresh, 1);
+    c->mg_restart = h.mg_restart != 0;
     // host mirrors of what the device arrays now hold
     HIPCHK(c, cpy(c->stream, c->vc.data(), c->d_vc, MAX_TURNS * sizeof(double), hipMemcpyDeviceToHost));
     HIPCHK(c, cpy(c->stream, c->vs.data(), c->d_vs, MAX_TURNS * sizeof(double), hipMemcpyDeviceToHost));
@@ -2108,6 +2199,10 @@ extern "C" pic_status pic_get_grid(pic_ctx *c, int32_t which, double *out)
             field_component<float>(c, which - PIC_GRID_ER, out);
         else
             field_component<double>(c, which - PIC_GRID_ER, out);
+        break;
+    case PIC_GRID_CHI:
+        if (!c->chi) return fail(c, PIC_EINVAL, "the configuration has no direct-implicit update");
+        HIPCHK(c, cpy(c->stream, out, c->chi, nodes * 8, hipMemcpyDeviceToHost));
         break;
     case PIC_GRID_BR:
     case PIC_GRID_BZ:

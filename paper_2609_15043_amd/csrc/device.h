@@ -152,6 +152,9 @@ template <typename T> struct Parts {
     T *vr, *vt, *vz; // velocity in the local (r, theta, z) frame (m/s)
     uint32_t *id;    // particle id (Philox counter word 0)
     int32_t *next;   // step of the next null-collision candidate
+    // direct-implicit update only (else null): the D1 filter's running
+    // electrostatic half kick (dt/2) abar in the local frame (m/s)
+    T *fr, *ft, *fz;
 };
 
 }  // namespace pic

@@ -82,6 +82,49 @@ __global__ void k_stage_b(const double *ec, const double *es, double cs, double 
     eb[n] = b;
 }
 
+// Direct-implicit susceptibility at the nodes from the predicted particles'
+// weights accQ_s (fixed point, per species): chi = (dt^2 / 2) / eps0 sum_s
+// (q_s^2 / m_s) w_s (accQ_s / 2^kQ) / V_node, i.e. half the squared plasma
+// frequency times dt^2 (the D1 scheme's susceptibility in Eq. poisson).
+// c0, c1 carry every factor but the node volume.
+__global__ void k_chi(const long long *accQ, double c0, double c1, double *chi, GridC g)
+{
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= g.nodes) return;
+    const int i = n / g.nr1, j = n - i * g.nr1;
+    chi[n] = (c0 * (double)accQ[n] + c1 * (double)accQ[g.nodes + n]) / node_volume(g, i, j);
+}
+
+// Level-0 Poisson operator with the susceptibility: every face conductance
+// of the chi = 0 operator (base arrays) times 1 + (chi_a + chi_b) / 2 (Eq.
+// epseff), the diagonal their sum.
+__global__ void k_chi_operator(const double *cw0, const double *ce0, const double *cs0, const double *cn0,
+                               const double *chi, double *cw, double *ce, double *cs, double *cn, double *cc, GridC g)
+{
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= g.nodes) return;
+    const int i = n / g.nr1, j = n - i * g.nr1;
+    const double x = chi[n];
+    const double w = j > 0 ? cw0[n] * (1.0 + 0.5 * (x + chi[n - 1])) : 0.0;
+    const double e = j < g.nr ? ce0[n] * (1.0 + 0.5 * (x + chi[n + 1])) : 0.0;
+    const double s = i > 0 ? cs0[n] * (1.0 + 0.5 * (x + chi[n - g.nr1])) : 0.0;
+    const double t = i < g.nz ? cn0[n] * (1.0 + 0.5 * (x + chi[n + g.nr1])) : 0.0;
+    cw[n] = w;
+    ce[n] = e;
+    cs[n] = s;
+    cn[n] = t;
+    cc[n] = w + e + s + t;
+}
+
+void launch_chi(const long long *accQ, double c0, double c1, double *chi, const double *cw0, const double *ce0,
+                const double *cs0, const double *cn0, const MGLevel &L0, const GridC &g, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_chi, dim3((g.nodes + 255) / 256), dim3(256), 0, st, accQ, c0, c1, chi, g);
+    hipLaunchKernelGGL(k_chi_operator, dim3((g.nodes + 255) / 256), dim3(256), 0, st, cw0, ce0, cs0, cn0,
+                       (const double *)chi, const_cast<double *>(L0.cw), const_cast<double *>(L0.ce),
+                       const_cast<double *>(L0.cs), const_cast<double *>(L0.cn), const_cast<double *>(L0.cc), g);
+}
+
 // node charge = sum_s q_s w_s (accQ_s / 2^kQ + accS_s), after the step's
 // window charge accW_s / 2^kQ (fixed point) has joined the persistent FP64
 // window sums accS_s (one add per node and step, in a fixed order)
@@ -643,13 +686,17 @@ __global__ __launch_bounds__(256) void k_pcg_update(MGLevel L, PCGVec v, const d
 // fixed order (the face list is sorted by turn-node index on the host)
 __global__ __launch_bounds__(256) void k_face_charge(const double *phi, const int32_t *fp, const int32_t *fq,
                                                      const int32_t *fk, const double *fc, int nfaces, double *Qk,
-                                                     int nturns)
+                                                     int nturns, const double *chi)
 {
     __shared__ double red[256];
     for (int k = 0; k < nturns; ++k) {
         double s = 0.0;
         for (int f = threadIdx.x; f < nfaces; f += 256)
-            if (fk[f] == k) s += fc[f] * (phi[fp[f]] - phi[fq[f]]);
+            if (fk[f] == k) {
+                // the solve's own face coefficient, the susceptibility included (Eq. facecharge)
+                const double x = chi ? 1.0 + 0.5 * (chi[fp[f]] + chi[fq[f]]) : 1.0;
+                s += fc[f] * x * (phi[fp[f]] - phi[fq[f]]);
+            }
         red[threadIdx.x] = s;
         __syncthreads();
         for (int off = 128; off > 0; off >>= 1) {
@@ -790,9 +837,9 @@ void launch_pcg_update(const MGLevel &L, const PCGVec &v, const double *p, const
                        (int)red_grid(L.nodes));
 }
 void launch_face_charge(const double *phi, const int32_t *fp, const int32_t *fq, const int32_t *fk, const double *fc,
-                        int nfaces, double *Qk, int nturns, hipStream_t s)
+                        int nfaces, double *Qk, int nturns, hipStream_t s, const double *chi)
 {
-    hipLaunchKernelGGL(k_face_charge, dim3(1), dim3(256), 0, s, phi, fp, fq, fk, fc, nfaces, Qk, nturns);
+    hipLaunchKernelGGL(k_face_charge, dim3(1), dim3(256), 0, s, phi, fp, fq, fk, fc, nfaces, Qk, nturns, chi);
 }
 
 }  // namespace pic

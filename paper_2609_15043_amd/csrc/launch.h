@@ -23,6 +23,8 @@ void launch_live_index(const int32_t *cell, const int64_t *count, int64_t *index
 template <typename T>
 void launch_pass(const PassArgs<T> &e, const PassArgs<T> &i, int64_t cap_e, int64_t cap_i, bool push, bool depq,
                  hipStream_t st);
+template <typename T>
+void launch_correct(const PassArgs<T> &e, const PassArgs<T> &i, int64_t cap_e, int64_t cap_i, hipStream_t st);
 template <typename T> void launch_collide(const PassArgs<T> &a, hipStream_t st);
 template <typename T>
 void launch_births(const Births<T> &b, const Parts<T> &pe, const Parts<T> &pi, int64_t *count, int64_t *next_id,
@@ -40,6 +42,8 @@ template <typename T>
 void launch_stage(const double *phi, const double *ec, const double *es, double cs, double sn,
                   typename Field4<T>::type *ef, long long *accJ, long long *accQ, bool clear_q, const GridC &g,
                   hipStream_t st);
+void launch_chi(const long long *accQ, double c0, double c1, double *chi, const double *cw0, const double *ce0,
+                const double *cs0, const double *cn0, const MGLevel &L0, const GridC &g, hipStream_t st);
 void launch_finalize_q(const long long *accQ, long long *accW, double *accS, double inv_scale, double cq0, double cq1,
                        double cs0, double cs1, double *Q, int nodes, hipStream_t st);
 void launch_harmonic(const long long *accJ, double cj0, double cj1, const double *ec, const double *es, double cs,
@@ -97,6 +101,7 @@ void launch_compose(const double *ecp, const double *esp, const double *U, int64
                     double *ec, double *es, int nodes, hipStream_t s);
 void mlp_shape(const mlp_ctx *c, int *n_in, int *n_out, void **stream);
 void launch_face_charge(const double *phi, const int32_t *fp, const int32_t *fq, const int32_t *fk, const double *fc,
-                        int nfaces, double *Qk, int nturns, hipStream_t s);
+                        int nfaces, double *Qk, int nturns, hipStream_t s,
+                        const double *chi = nullptr);
 
 }  // namespace pic

@@ -126,6 +126,7 @@ __global__ void k_load(Parts<T> p, int64_t n, uint32_t seed, int s, double rmax,
     p.vz[k] = (T)(vth * g2);
     p.id[k] = (uint32_t)k;
     p.next[k] = next_candidate(-1, b.z, lq);   // first candidate: G - 1
+    if (p.fr) p.fr[k] = p.ft[k] = p.fz[k] = (T)0;
 }
 
 // Host-given particles (R, z in metres) -> store
@@ -146,6 +147,7 @@ __global__ void k_place(Parts<T> p, int64_t n, const double *R, const double *z,
     p.vz[k] = (T)vz[k];
     p.id[k] = id[k];
     p.next[k] = next[k];
+    if (p.fr) p.fr[k] = p.ft[k] = p.fz[k] = (T)0;
 }
 
 // store -> host representation (only live particles, order of the store)
@@ -442,8 +444,13 @@ template <typename T> struct PassOcc {
 };
 #define PIC_PASS_OCCUPANCY __attribute__((amdgpu_waves_per_eu(PassOcc<T>::min_waves, 8)))
 // RFB: the RF magnetic field staged per node (eb) joins the uniform field
-// in the Boris rotation, with the rotation vector formed per particle
-template <typename T, bool PUSH, bool DEPQ, bool RFB>
+// in the Boris rotation, with the rotation vector formed per particle.
+// DI: the predictor of the direct-implicit update: the electrostatic kick is
+// the particle's filtered half kick (dt/2) abar^{n-1} (arrays fr, ft, fz),
+// the inductive kick dt (q/m) E_theta(t_n) is explicit, and the filter turns
+// with the velocity at the move; no collision candidates (the corrector
+// takes them).
+template <typename T, bool PUSH, bool DEPQ, bool RFB, bool DI>
 __global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassPair<T> pp)
 {
     // one grid for both species: blocks [0, nb0) take the electrons' chunks,
@@ -479,6 +486,7 @@ __global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassPair<T> p
     const int64_t wbase = c0 + (int64_t)(tid >> 6) * (RUN * RUNS * 64);
     int32_t cell[RUN], nxt[RUN];
     T dr[RUN], dz[RUN], vr[RUN], vt[RUN], vz[RUN];
+    T kr[DI ? RUN : 1], kt[DI ? RUN : 1], kz[DI ? RUN : 1];   // direct-implicit filter
     // a run's particles; the next run's loads are issued right after this
     // run's stores (its registers are free then), so that their latency
     // overlaps this run's deposit reductions
@@ -491,6 +499,11 @@ __global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassPair<T> p
             ld4(a.p.vt + q, vt);
             ld4(a.p.vz + q, vz);
             ld4(a.p.next + q, nxt);
+            if constexpr (DI) {
+                ld4(a.p.fr + q, kr);
+                ld4(a.p.ft + q, kt);
+                ld4(a.p.fz + q, kz);
+            }
         }
     };
     // the first run's loads do not depend on the window: issued first, their
@@ -562,7 +575,12 @@ __global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassPair<T> p
                 const T et = w00 * f00.z + w01 * f01.z + w10 * f10.z + w11 * f11.z;
                 const T h = sc_val<T>(a.sc.h, a.sc.hf);
                 T ur = vr[k] + h * er, ut = vt[k] + h * et, uz = vz[k] + h * ez;
-                if constexpr (RFB) {
+                if constexpr (DI) {
+                    // electrostatic part from the filter, inductive part explicit
+                    ur = vr[k] + kr[k];
+                    ut = vt[k] + kt[k] + (T)2 * h * et;
+                    uz = vz[k] + kz[k];
+                } else if constexpr (RFB) {
                     using F2 = typename Field2<T>::type;
                     const F2 b00 = a.eb[key], b01 = a.eb[key + 1], b10 = a.eb[key + g.nr1], b11 = a.eb[key + g.nr1 + 1];
                     const T br = w00 * b00.x + w01 * b01.x + w10 * b10.x + w11 * b11.x;
@@ -586,9 +604,11 @@ __global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassPair<T> p
                     ut += pz * s0 - pr * s2;
                     uz += pr * s1 - pt * s0;
                 }
-                ur += h * er;
-                ut += h * et;
-                uz += h * ez;
+                if constexpr (!DI) {
+                    ur += h * er;
+                    ut += h * et;
+                    uz += h * ez;
+                }
                 // azimuthal current at x^n with the time-centred v_theta
                 const T jv = (T)0.5 * (vt[k] + ut) * sc_val<T>(a.sc.inv_vref, a.sc.inv_vreff);
                 if (iJ < 0) iJ = i, jJ = j;
@@ -615,6 +635,11 @@ __global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassPair<T> p
                 }
                 const T vrn = c * ur + sn * ut;
                 const T vtn = -sn * ur + c * ut;
+                if constexpr (DI) {
+                    const T k0 = kr[k], k1 = kt[k];
+                    kr[k] = c * k0 + sn * k1;
+                    kt[k] = -sn * k0 + c * k1;
+                }
                 const T fr = floor(rel);
                 int jn = j + (int)fr;
                 T drn = rel - fr;
@@ -666,7 +691,7 @@ __global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassPair<T> p
                 vr[k] = vrn;
                 vt[k] = vtn;
                 vz[k] = uz;
-                if (live[k] && nxt[k] == a.step) cand_bits |= 1u << k;
+                if (!DI && live[k] && nxt[k] == a.step) cand_bits |= 1u << k;
             }
             if (DEPQ && live[k]) {
                 int i, j;
@@ -693,6 +718,11 @@ __global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassPair<T> p
             st4(a.p.vr + q0, vr);
             st4(a.p.vt + q0, vt);
             st4(a.p.vz + q0, vz);
+            if constexpr (DI) {
+                st4(a.p.fr + q0, kr);
+                st4(a.p.ft + q0, kt);
+                st4(a.p.fz + q0, kz);
+            }
             // this step's collision candidates -> block-local list (LDS), one
             // global reservation per block at the end
             // candidates of the lanes below this one and of the whole wave,
@@ -787,6 +817,111 @@ __global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassPair<T> p
         }
     }
     if (tid < ST_NSTAT && sstat[tid]) atomicAdd(&a.stats[tid], sstat[tid]);
+}
+
+// ---------------------------------------------------------------------------
+// Corrector of the direct-implicit update, step n: the new electrostatic
+// field E^{n+1} (staged per node from phi^{n+1}) gathered at the predicted
+// position x~ gives the half kick h E = (dt/2) a^{n+1}; the position moves by
+// dt h E (radially and axially: the frame does not turn), the velocity by
+// h E, and the filter becomes (h E + filter) / 2.  A radius corrected below
+// zero passes through the axis (radial and azimuthal components reversed).
+// Absorption as in the push, the window crossing taken on the correction
+// segment; the step's collision candidates are queued here (the velocity
+// is final only now).  One thread per particle slot; one grid for both
+// species, the first nb0 blocks the electrons'.
+// ---------------------------------------------------------------------------
+template <typename T> __global__ __launch_bounds__(256) void k_correct(PassPair<T> pp)
+{
+    const int sp = (int)blockIdx.x >= pp.nb0 ? 1 : 0;
+    const PassArgs<T> &a = pp.a[sp];
+    const int64_t p = ((int64_t)blockIdx.x - (sp ? pp.nb0 : 0)) * blockDim.x + threadIdx.x;
+    if (p >= *a.count) return;
+    const int32_t cl = a.p.cell[p];
+    if (cl < 0) return;
+    using F4 = typename Field4<T>::type;
+    const GridC g = a.g;
+    int i, j;
+    split_cell(g, cl, i, j);
+    const T dr0 = a.p.dr[p], dz0 = a.p.dz[p];
+    T w00, w01, w10, w11;
+    node_weights<T>(j, dr0, dz0, w00, w01, w10, w11);
+    const int key = i * g.nr1 + j;
+    const F4 f00 = a.ef[key], f01 = a.ef[key + 1], f10 = a.ef[key + g.nr1], f11 = a.ef[key + g.nr1 + 1];
+    const T er = w00 * f00.x + w01 * f01.x + w10 * f10.x + w11 * f11.x;
+    const T ez = w00 * f00.y + w01 * f01.y + w10 * f10.y + w11 * f11.y;
+    const T h = sc_val<T>(a.sc.h, a.sc.hf);
+    const T kr = h * er, kz = h * ez;
+    const T dtr = sc_val<T>(a.sc.dtr, a.sc.dtrf), dtz = sc_val<T>(a.sc.dtz, a.sc.dtzf);
+    T rel = (T)j + (dr0 + kr * dtr);
+    const T bz = dz0 + kz * dtz;
+    T vr = a.p.vr[p] + kr, vt = a.p.vt[p], vz = a.p.vz[p] + kz;
+    T fr = (T)0.5 * (kr + a.p.fr[p]), ft = (T)0.5 * a.p.ft[p], fz = (T)0.5 * (kz + a.p.fz[p]);
+    if (rel < (T)0) {
+        rel = -rel;
+        vr = -vr;
+        vt = -vt;
+        fr = -fr;
+        ft = -ft;
+    }
+    const T fj = floor(rel);
+    int jn = (int)fj;
+    T drn = rel - fj;
+    if (drn >= (T)1) {
+        drn -= (T)1;
+        jn += 1;
+    }
+    const T fzz = floor(bz);
+    int in = i + (int)fzz;
+    T dzn = bz - fzz;
+    if (dzn >= (T)1) {
+        dzn -= (T)1;
+        in += 1;
+    }
+    int absorbed = 0;
+    if (!(rel == rel) || !(bz == bz) || in < 0) {
+        absorbed = 1;
+    } else if (in >= g.ip) {
+        absorbed = 1;
+        if (g.window && kz > (T)0) {
+            // crossing of z = zp on the correction segment (FP64)
+            const double frac = ((double)g.ip - ((double)i + (double)dz0)) / ((double)kz * a.sc.dtz);
+            const double Rs = fabs((double)j + (double)dr0 + frac * (double)kr * a.sc.dtr);
+            if (Rs < (double)g.nr) {
+                int js = (int)floor(Rs);
+                js = min(js, g.nr - 1);
+                const double w1 = (Rs * Rs - (double)js * js) / (2.0 * js + 1.0);
+                const int nd = g.ip * g.nr1 + js;
+                atomic_add_i64(&a.accW[nd], to_fixed(1.0 - w1, a.sc.qscale));
+                atomic_add_i64(&a.accW[nd + 1], to_fixed(w1, a.sc.qscale));
+            }
+        }
+    } else if (jn >= g.nr) {
+        absorbed = 1;
+    }
+    a.p.cell[p] = absorbed ? -1 : in * g.nr + jn;
+    a.p.dr[p] = drn;
+    a.p.dz[p] = dzn;
+    a.p.vr[p] = vr;
+    a.p.vt[p] = vt;
+    a.p.vz[p] = vz;
+    a.p.fr[p] = fr;
+    a.p.ft[p] = ft;
+    a.p.fz[p] = fz;
+    if (absorbed) {
+        atomicAdd(&a.stats[ST_ABS0 + a.sc.s], 1ull);
+    } else if (a.p.next[p] == a.step) {
+        const int gs = atomicAdd(a.q.count, 1);
+        if (gs < a.q.cap) {
+            T *qv = static_cast<T *>(a.q.vel);
+            a.q.idx[gs] = (int32_t)p;
+            qv[gs] = vr;
+            qv[a.q.cap + gs] = vt;
+            qv[2 * a.q.cap + gs] = vz;
+        } else {
+            atomicOr(a.err, (int)ERR_QUEUE_OVERFLOW);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -934,6 +1069,10 @@ __global__ __launch_bounds__(256) void k_births(Births<T> b, Parts<T> pe, Parts<
     pi.vz[oi] = b.vi[3 * t + 2];
     pi.id[oi] = (uint32_t)(next_id[1] + rank);
     pi.next[oi] = b.next[2 * t + 1];
+    if (pe.fr) {
+        pe.fr[oe] = pe.ft[oe] = pe.fz[oe] = (T)0;
+        pi.fr[oi] = pi.ft[oi] = pi.fz[oi] = (T)0;
+    }
     if (deposit) {
         const int ii = c / g.nr, jj = c - ii * g.nr;
         const T fj = (T)jj;
@@ -1115,6 +1254,7 @@ __global__ __launch_bounds__(256) void k_sort_scatter(Parts<T> src, Parts<T> dst
     __shared__ int s_lo, s_wt[BLOCK / 64];
     __shared__ int32_t sg_cell[SORT_PER], sg_next[SORT_PER];
     __shared__ uint32_t sg_id[SORT_PER];
+    __shared__ int32_t sg_src[SORT_PER];   // source slot (for the direct-implicit filter arrays)
     __shared__ T sg_dr[SORT_PER], sg_dz[SORT_PER], sg_vr[SORT_PER], sg_vt[SORT_PER], sg_vz[SORT_PER];
     constexpr int Q = SORT_PER / 256;
     constexpr int BPT = SORT_WIN / 256;   // window cells per thread in the scan
@@ -1219,6 +1359,7 @@ __global__ __launch_bounds__(256) void k_sort_scatter(Parts<T> src, Parts<T> dst
             sg_vz[L] = vz[q];
             sg_id[L] = id[q];
             sg_next[L] = nx[q];
+            sg_src[L] = q * 256 + tid;
         } else {
             const int64_t o = pos[q];
             dst.cell[o] = c[q];
@@ -1229,6 +1370,12 @@ __global__ __launch_bounds__(256) void k_sort_scatter(Parts<T> src, Parts<T> dst
             dst.vz[o] = vz[q];
             dst.id[o] = id[q];
             dst.next[o] = nx[q];
+            if (src.fr) {
+                const int64_t sp = p0 + q * 256 + tid;
+                dst.fr[o] = src.fr[sp];
+                dst.ft[o] = src.ft[sp];
+                dst.fz[o] = src.fz[sp];
+            }
         }
     }
     __syncthreads();
@@ -1250,6 +1397,12 @@ __global__ __launch_bounds__(256) void k_sort_scatter(Parts<T> src, Parts<T> dst
         dst.vz[o] = sg_vz[k];
         dst.id[o] = sg_id[k];
         dst.next[o] = sg_next[k];
+        if (src.fr) {
+            const int64_t sp = p0 + sg_src[k];
+            dst.fr[o] = src.fr[sp];
+            dst.ft[o] = src.ft[sp];
+            dst.fz[o] = src.fz[sp];
+        }
     }
 }
 
@@ -1346,17 +1499,31 @@ void launch_pass(const PassArgs<T> &e, const PassArgs<T> &i, int64_t cap_e, int6
     pp.a[1] = i;
     pp.nb0 = blocks_for(cap_e, CHUNK);
     const dim3 grid(pp.nb0 + blocks_for(cap_i, CHUNK)), blk(BLOCK);
-    const bool rfb = e.eb != nullptr;
-    if (push && depq && rfb)
-        hipLaunchKernelGGL((k_pass<T, true, true, true>), grid, blk, 0, st, pp);
+    const bool rfb = e.eb != nullptr, di = e.p.fr != nullptr;
+    if (push && depq && di)
+        hipLaunchKernelGGL((k_pass<T, true, true, false, true>), grid, blk, 0, st, pp);
+    else if (push && di)
+        hipLaunchKernelGGL((k_pass<T, true, false, false, true>), grid, blk, 0, st, pp);
+    else if (push && depq && rfb)
+        hipLaunchKernelGGL((k_pass<T, true, true, true, false>), grid, blk, 0, st, pp);
     else if (push && depq)
-        hipLaunchKernelGGL((k_pass<T, true, true, false>), grid, blk, 0, st, pp);
+        hipLaunchKernelGGL((k_pass<T, true, true, false, false>), grid, blk, 0, st, pp);
     else if (push && rfb)
-        hipLaunchKernelGGL((k_pass<T, true, false, true>), grid, blk, 0, st, pp);
+        hipLaunchKernelGGL((k_pass<T, true, false, true, false>), grid, blk, 0, st, pp);
     else if (push)
-        hipLaunchKernelGGL((k_pass<T, true, false, false>), grid, blk, 0, st, pp);
+        hipLaunchKernelGGL((k_pass<T, true, false, false, false>), grid, blk, 0, st, pp);
     else if (depq)
-        hipLaunchKernelGGL((k_pass<T, false, true, false>), grid, blk, 0, st, pp);
+        hipLaunchKernelGGL((k_pass<T, false, true, false, false>), grid, blk, 0, st, pp);
+}
+
+template <typename T>
+void launch_correct(const PassArgs<T> &e, const PassArgs<T> &i, int64_t cap_e, int64_t cap_i, hipStream_t st)
+{
+    PassPair<T> pp;
+    pp.a[0] = e;
+    pp.a[1] = i;
+    pp.nb0 = blocks_for(cap_e, 256);
+    hipLaunchKernelGGL(k_correct<T>, dim3(pp.nb0 + blocks_for(cap_i, 256)), dim3(256), 0, st, pp);
 }
 
 template <typename T> void launch_collide(const PassArgs<T> &a, hipStream_t st)
@@ -1402,6 +1569,7 @@ int sort_scan_blocks(int ncells) { return (int)blocks_for(ncells, SCAN_BLOCK); }
     template void launch_pass<T>(const PassArgs<T> &, const PassArgs<T> &, int64_t, int64_t, bool, bool,          \
                                  hipStream_t);                                                                      \
     template void launch_collide<T>(const PassArgs<T> &, hipStream_t);                                              \
+    template void launch_correct<T>(const PassArgs<T> &, const PassArgs<T> &, int64_t, int64_t, hipStream_t);       \
     template void launch_births<T>(const Births<T> &, const Parts<T> &, const Parts<T> &, int64_t *, int64_t *,     \
                                    int64_t, int64_t, long long *, long long *, bool, double, const GridC &,         \
                                    int32_t *, unsigned long long *, int32_t *, int32_t *, hipStream_t);             \

@@ -23,7 +23,7 @@ PIC_FIELD_FULL, PIC_FIELD_MQS = 0, 1
 PIC_RRF_GIVEN, PIC_RRF_SKIN = 0, 1
 (PIC_GRID_PHI, PIC_GRID_CHARGE, PIC_GRID_CURRENT, PIC_GRID_ER, PIC_GRID_EZ, PIC_GRID_ETHETA,
  PIC_GRID_SURFACE, PIC_GRID_JC, PIC_GRID_JS, PIC_GRID_EC, PIC_GRID_ES, PIC_GRID_EC_PLASMA,
- PIC_GRID_ES_PLASMA, PIC_GRID_BR, PIC_GRID_BZ) = range(15)
+ PIC_GRID_ES_PLASMA, PIC_GRID_BR, PIC_GRID_BZ, PIC_GRID_CHI) = range(16)
 PIC_GRID_UNIT = 16
 
 _D, _I32, _I64, _U32 = ctypes.c_double, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
@@ -51,6 +51,7 @@ class PicConfig(ctypes.Structure):
         ("p_target", _D), ("gamma", _D), ("n_trend", _D), ("eps_p", _D), ("alpha_v", _D), ("f_step", _D),
         ("v_min", _D), ("v_max", _D), ("alpha", _D), ("helm_rtol", _D), ("helm_max_cycles", _I32),
         ("sort_every_ion", _I32), ("dir_basis", _PD), ("unit_bvals", _PD), ("rf_bfield", _I32),
+        ("implicit", _I32),
     ]
 
 
@@ -208,6 +209,7 @@ def config_from_workload(wl, precision="mixed", fuse=True, load=True, mg_rtol=No
     c.mg_rtol, c.mg_max_cycles, c.sort_every, c.load = mg_rtol, mg_max_cycles, sort_every, 1 if load else 0
     c.sort_every_ion = sort_every_ion
     c.rf_bfield = 1 if wl.rf_bfield else 0
+    c.implicit = 1 if wl.implicit else 0
     c.birth_capacity = birth_capacity
     cp = wl.circuit
     if cp is not None:
@@ -468,6 +470,11 @@ def step(ctx, n):
     """One whole PIC step n in the library's order (without the period update)."""
     pic_gather_push(ctx, n)
     harmonic_accumulate(ctx, n)
+    if ctx.cfg.implicit:
+        pic_deposit(ctx, n + 1)
+        poisson_solve_rz(ctx, n + 1)
+        mcc_collide(ctx, n)
+        return
     mcc_collide(ctx, n)
     pic_deposit(ctx, n + 1)
     poisson_solve_rz(ctx, n + 1)

@@ -98,12 +98,13 @@ CELL_SEEDS = tuple(range(1, 9))
 CELL_NPS = 100_000
 CELL_PERIODS = 2
 CELL_VG_START = 300.0
+CELL_N0 = 1e14
 
 
 def _cell_gpu_run(seed, prec):
     import paper_2609_15043_amd.phasorpic as pp
     from paper_2609_15043_amd import workloads as W
-    wl = W.cell(seed=seed, n_per_species=CELL_NPS, vg_start=CELL_VG_START)
+    wl = W.cell(seed=seed, n_per_species=CELL_NPS, vg_start=CELL_VG_START, n0=CELL_N0)
     cfg, keep = pp.config_from_workload(wl, precision=prec, load=True)
     ctx = pp.pic_init(cfg, keep)
     nrf = pp.nrf(wl)
@@ -127,8 +128,8 @@ def _cell_gpu_run(seed, prec):
 def test_coupled_cell_period_moments_match_oracle():
     """The coupled coil cell (128 x 256 cells, argon 20 mTorr, 2000 steps
     per RF period, coil on the external network with the power controller
-    towards 60 W, source from 300 V), 1e5 electrons + 1e5 Ar+ from seeds
-    1..8, two whole RF periods
+    towards 60 W, source from 300 V), 1e5 electrons + 1e5 Ar+ at 1e14 m^-3
+    (Debye length above the cell size) from seeds 1..8, two whole RF periods
     in FP64 and FP32-mixed: per period the volume-mean electron density,
     T_e, and the closed period's inductive and capacitive powers (Eqs. pind,
     pcap).  The oracle's values for the same seeds are stored in
