@@ -253,6 +253,210 @@ def stationary_circuit(targets=(60.0, 100.0), plain_periods=100, sur_periods=40,
             "training": {"pairs": len(X), "adam_steps": adam_steps, "final_loss": float(loss), "wall_s": t_train}}
 
 
+def stationary_q27(reps, p_target, tol=0.01, window=10):
+    """First period i (0-based) such that over the window [i, i + window)
+    every period's port power lies within tol of the target, and for every
+    turn the window mean of |I_k| and of |V_k| moves by less than tol
+    against the preceding window [i - window, i); None if no such period.
+    The plasma keeps evolving (density, temperature), so stationarity is
+    judged on window means rather than on single periods."""
+    N = (len(reps[0]["x"]) - 1) // 2
+    mags = np.array([np.abs(r["x"][1:]) for r in reps])   # |I_k|, |V_k| per period
+    for i in range(window, len(reps) - window + 1):
+        if not all(abs(reps[j]["p_port"] - p_target) / p_target <= tol for j in range(i, i + window)):
+            continue
+        cur, prev = mags[i:i + window].mean(0), mags[i - window:i].mean(0)
+        if np.all(np.abs(cur - prev) <= tol * np.abs(cur)):
+            return i
+    return None
+
+
+PLASMA_N0 = 1e14          # m^-3: Debye length (1 mm at 3 eV) about the cell size
+PLASMA_NRF = 400          # steps per RF period
+PLASMA_VG_START = 300.0   # V
+
+
+def plasma_cell(seed, nps, p_target, pressure_mtorr=20.0):
+    """The coupled coil cell (128 x 256 cells, quartz window, 5 turns)
+    loaded with plasma at PLASMA_N0, PLASMA_NRF steps per RF period, the
+    controller driving the port power towards p_target from PLASMA_VG_START."""
+    from paper_2609_15043_amd import workloads as W
+    wl = W.cell(seed=seed, n_per_species=nps, vg_start=PLASMA_VG_START, n0=PLASMA_N0)
+    wl.dt = 1.0 / (PLASMA_NRF * wl.freq)
+    wl.pressure_pa = pressure_mtorr * 1e-3 * W.TORR
+    wl.capacity_factor = 3.0
+    wl.circuit.p_target = float(p_target)
+    return wl
+
+
+def _plasma_periods(ctx, periods, nrf, after_period=None):
+    """Whole RF periods of the explicit cycle with the period update; the
+    reports and the wall time at the end of each period (after_period(rep),
+    when given, runs at each period's end and is timed with it)."""
+    import paper_2609_15043_amd.phasorpic as pp
+    reps, times = [], []
+    n = 0
+    t0 = time.perf_counter()
+    for _ in range(periods):
+        for _ in range(nrf):
+            pp.pic_gather_push(ctx, n)
+            pp.harmonic_accumulate(ctx, n)
+            pp.mcc_collide(ctx, n)
+            pp.pic_deposit(ctx, n + 1)
+            if (n + 1) % nrf == 0:
+                st, rep, _, _ = pp.circuit_period_update(ctx)   # synchronises
+                if st != 0:
+                    raise RuntimeError(f"period update status {st}")
+                reps.append(rep)
+                if after_period is not None:
+                    after_period(rep)
+                times.append(time.perf_counter() - t0)
+            pp.poisson_solve_rz(ctx, n + 1)
+            n += 1
+    return reps, times
+
+
+class OnlineRefinement:
+    """The surrogate-assisted run's own (state, response) pairs join the
+    training set as the periods close: after each period update the
+    network takes `steps` Adam steps over the base set and the run's pairs
+    so far (normalisation fixed by the base set).  The plasma keeps
+    evolving during the run (the density grows by about half a per cent
+    per period here), which carries its state out of the base set's range;
+    the pairs the run measures keep the network's prediction at the states
+    it visits within the fallback threshold."""
+
+    def __init__(self, net, X, Y, N, steps=100):
+        import torch
+        self.net, self.N, self.steps = net, N, steps
+        self.X, self.Y = [X.astype(np.float32)], [Y.astype(np.float32)]
+        self.torch = torch
+
+    def __call__(self, rep):
+        import paper_2609_15043_amd.phasorpic as pp
+        torch = self.torch
+        self.X.append(pp.surrogate_features(rep, self.N)[None, :].astype(np.float32))
+        self.Y.append(pp.surrogate_targets(rep, self.N)[None, :].astype(np.float32))
+        xd = torch.from_numpy(np.concatenate(self.X)).cuda()
+        yd = torch.from_numpy(np.concatenate(self.Y)).cuda()
+        for _ in range(self.steps):
+            self.net.train_step(xd, yd, want_loss=False)
+        self.net.sync()
+
+
+def plasma_training_pairs(runs=12, periods=10, nps=2_000_000, power_w=(1.0, 7.5), pressure_mtorr=(5.0, 50.0)):
+    """The network's training set from PIC periods with plasma: `runs` runs
+    of the plasma cell, run r with port power target ~ U(power_w) and
+    pressure ~ logU(pressure_mtorr) drawn by numpy's generator seeded
+    1000 + r and its particles loaded with seed 1000 + r, each `periods` RF
+    periods from the start (the controller transient sweeps the state);
+    every period gives one (state, response) pair.  Returns X, Y and a
+    summary."""
+    import paper_2609_15043_amd.phasorpic as pp
+    t0 = time.perf_counter()
+    X, Y = [], []
+    for r in range(runs):
+        u = np.random.default_rng(1000 + r).uniform(size=2)
+        pt = power_w[0] + (power_w[1] - power_w[0]) * u[0]
+        lo, hi = math.log(pressure_mtorr[0]), math.log(pressure_mtorr[1])
+        wl = plasma_cell(1000 + r, nps, pt, math.exp(lo + (hi - lo) * u[1]))
+        cfg, keep = pp.config_from_workload(wl, precision="fp64", load=True)
+        ctx = pp.pic_init(cfg, keep)
+        reps, _ = _plasma_periods(ctx, periods, pp.nrf(wl))
+        del ctx
+        X += [pp.surrogate_features(rep, wl.nturns) for rep in reps]
+        Y += [pp.surrogate_targets(rep, wl.nturns) for rep in reps]
+    return np.array(X), np.array(Y), {"runs": runs, "periods_per_run": periods, "particles_per_species": nps,
+                                      "pairs": len(X), "port_power_w": list(power_w),
+                                      "pressure_mtorr": list(pressure_mtorr), "data_wall_s": time.perf_counter() - t0}
+
+
+def train_plasma_surrogate(X, Y, adam_steps=5000, extra_rows=256):
+    """Adam on the GPU over the whole training set (inputs and outputs
+    standardised by the set's own means and scales).  Returns the network
+    and a summary."""
+    import torch
+    import paper_2609_15043_amd.phasorpic as pp
+    from paper_2609_15043_amd import workloads as W
+    t0 = time.perf_counter()
+    norm = (X.mean(0), feature_scale(X), Y.mean(0), feature_scale(Y))
+    net = pp.Mlp(norm=norm, lr=1e-3, max_batch=max(256, len(X) + extra_rows))
+    net.set_params(W.mlp_init_params(seed=22))
+    xd = torch.from_numpy(X.astype(np.float32)).cuda()
+    yd = torch.from_numpy(Y.astype(np.float32)).cuda()
+    for it in range(adam_steps):
+        loss = net.train_step(xd, yd, want_loss=(it == adam_steps - 1))
+    net.sync()
+    return net, {"adam_steps": adam_steps, "final_loss": float(loss), "train_wall_s": time.perf_counter() - t0}
+
+
+
+
+
+def stationary_plasma(targets=(3.0, 5.0), periods=70, nps=2_000_000, window=10, refine_steps=100, training=None):
+    """Wall-seconds to the stationary circuit on the plasma-loaded coil cell:
+    the plain FP64 GPU run against the surrogate-assisted run in FP32-mixed
+    and in FP64, at each port power target, 20 mTorr, nps electrons + nps
+    Ar+ (seed 0).  The network is trained first on plasma_training_pairs
+    (its cost reported, not counted in either run); each surrogate-assisted
+    run starts from those weights and refines them online on its own
+    periods (OnlineRefinement, counted in its wall time).  Stationary:
+    stationary_q27.  Reported per run: periods and wall-seconds to
+    stationary, periods in which the surrogate's update was applied, and
+    over the last `window` periods the mean port, inductive and capacitive
+    powers, the field-versus-circuit power imbalance and the electron
+    density and temperature; the deviation of each run's final window-mean
+    state from the plain run's over the same periods (every run lasts
+    `periods` periods: the plasma density keeps growing, so states are
+    compared at the same time)."""
+    import paper_2609_15043_amd.phasorpic as pp
+    if training is None:
+        X, Y, dinfo = plasma_training_pairs()
+        net, tinfo = train_plasma_surrogate(X, Y, extra_rows=periods)
+        training = dict(net=net, X=X, Y=Y, info={**dinfo, **tinfo})
+    net, X, Y = training["net"], training["X"], training["Y"]
+    theta0 = net.get_params()
+    out = []
+    for target in targets:
+        runs = {}
+        for mode, prec in (("plain", "fp64"), ("surrogate", "mixed"), ("surrogate", "fp64")):
+            wl = plasma_cell(0, nps, target)
+            cfg, keep = pp.config_from_workload(wl, precision=prec, load=True)
+            ctx = pp.pic_init(cfg, keep)
+            refine = None
+            if mode == "surrogate":
+                net.set_params(theta0)
+                pp.pic_attach_surrogate(ctx, net, err_max=0.02, tol=1e-6, max_iter=50)
+                refine = OnlineRefinement(net, X, Y, wl.nturns, refine_steps) if refine_steps else None
+            reps, times = _plasma_periods(ctx, periods, pp.nrf(wl), after_period=refine)
+            st = pp.pic_get_stats(ctx)
+            del ctx
+            i = stationary_q27(reps, target, window=window)
+            tail = reps[-window:]
+            runs[f"{mode}_{prec}"] = {
+                "periods": None if i is None else i + 1, "wall_s": None if i is None else times[i],
+                "wall_s_run": times[-1], "surrogate_periods": int(sum(r["sur_used"] for r in reps)),
+                "final": {k: float(np.mean([r[k] for r in tail])) for k in ("p_port", "p_ind", "p_cap", "p_cu",
+                                                                            "eps_bal")},
+                "final_n_e": float(np.mean([r["moments"][0] for r in tail])),
+                "final_T_e_ev": float(np.mean([2.0 / 3.0 * r["moments"][3] for r in tail])),
+                "mg_unconverged": int(st.mg_unconverged),
+                "_x": np.mean([r["x"] for r in tail], axis=0)}
+        x_ref = runs["plain_fp64"]["_x"]
+        for k in runs:
+            runs[k]["final_state_deviation"] = float(np.linalg.norm(runs[k].pop("_x") - x_ref) / np.linalg.norm(x_ref))
+        out.append({"p_target_w": target, **runs})
+    net.set_params(theta0)
+    return {"workload": f"plasma-loaded coil cell 128x256, argon 20 mTorr, {nps:.3g} e + {nps:.3g} Ar+ at "
+                        f"{PLASMA_N0:g} m^-3, 13.56 MHz at {PLASMA_NRF} steps per RF period, controller from "
+                        f"{PLASMA_VG_START:g} V, port power targets " + ", ".join(f"{t:g}" for t in targets) + " W",
+            "criterion": f"first period from which, for {window} periods, the port power stays within 1 % of the "
+                         f"target and every turn's window-mean |I_k| and |V_k| moves by under 1 % against the "
+                         f"preceding {window} periods",
+            "periods_per_run": periods, "online_refinement_adam_steps_per_period": refine_steps,
+            "runs": out, "training": training["info"]}
+
+
 def surrogate_mlp(batch=4096, steps=200, warmup=20):
     """The surrogate network's kernels at their training configuration: MLP
     29-256-256-256-20 (GELU; BF16 operands, FP32 accumulation on MFMA),
@@ -400,15 +604,24 @@ def main():
         print(f"[bench] surrogate MLP, batch {mlp['batch']}: forward {mlp['forward']['ms']:.3f} ms "
               f"({mlp['forward']['tflops']:.1f} TFLOP/s), training step {mlp['train_step']['ms']:.3f} ms "
               f"({mlp['train_step']['tflops']:.1f} TFLOP/s)", file=sys.stderr, flush=True)
-    stat = None
+    stat = stat_vac = None
     if not args.no_stationary:
-        print("[bench] wall-s to stationary circuit: plain FP64 vs surrogate-assisted FP64", file=sys.stderr,
-              flush=True)
-        stat = stationary_circuit()
+        print("[bench] wall-s to stationary circuit, plasma-loaded cell: training pairs from PIC periods, then "
+              "plain FP64 vs surrogate-assisted FP32-mixed and FP64", file=sys.stderr, flush=True)
+        stat = stationary_plasma()
+        t = stat["training"]
+        print(f"[bench] training set: {t['pairs']} pairs from {t['runs']} runs in {t['data_wall_s']:.1f} s, "
+              f"{t['adam_steps']} Adam steps in {t['train_wall_s']:.2f} s", file=sys.stderr, flush=True)
         for run in stat["runs"]:
-            print(f"[bench] stationary at {run['p_target_w']:g} W: plain {run['plain']}, surrogate "
-                  f"{run['surrogate_assisted']}, final deviation {run['final_state_deviation']:.2e}",
-                  file=sys.stderr, flush=True)
+            for k in ("plain_fp64", "surrogate_mixed", "surrogate_fp64"):
+                r = run[k]
+                print(f"[bench] {run['p_target_w']:g} W {k}: stationary after {r['periods']} periods "
+                      f"({r['wall_s']} s), surrogate used in {r['surrogate_periods']}, final P_ind "
+                      f"{r['final']['p_ind']:.3f} W P_cap {r['final']['p_cap']:.3f} W eps_bal "
+                      f"{r['final']['eps_bal']:.2e}, state deviation {r['final_state_deviation']:.2e}",
+                      file=sys.stderr, flush=True)
+        print("[bench] wall-s to stationary circuit, coil cell without plasma (extra)", file=sys.stderr, flush=True)
+        stat_vac = stationary_circuit()
     cpu = None
     if not args.no_cpu_baseline:
         print(f"[bench] cpu baseline: oracle on 1/{args.cpu_scale} of {wl.name}, {args.cpu_steps} steps",
@@ -421,7 +634,8 @@ def main():
         "config": {"workload": describe(wl, prec), "particles": r["mean_live"], "grid": [wl.nr, wl.nz],
                    "parallelism": "1 GPU", "sort_every": SORT_EVERY, "sort_every_ion": SORT_EVERY_ION,
                    "fused": not args.split},
-        "roofline": roofline, "step_hbm": step_hbm, "stationary_circuit": stat, "surrogate_mlp": mlp,
+        "roofline": roofline, "step_hbm": step_hbm, "stationary_circuit": stat,
+        "stationary_circuit_vacuum": stat_vac, "surrogate_mlp": mlp,
         "cpu_baseline": cpu,
         "breakdown_ms": {"pass": r["pass_ms"], "poisson": r["poisson_ms"], "sort_per_species": r["sort_ms"],
                          "window_fallback_atomics": r["window_out"],

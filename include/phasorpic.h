@@ -326,7 +326,8 @@ typedef struct pic_period_report {
     double pressure;         /* gas pressure (Pa) */
     /* plasma moments at the end of the period: <n_e>, <n_i> (m^-3, over the
      * particle box), max n_e (m^-3, nodes), <eps_e>, <eps_i> (eV), electron
-     * centroid R, z (m), ionizations during the period */
+     * centroid R, z (m), ionizations during the period (real particles:
+     * macro-particle births times the electron weight) */
     double moments[8];
     int32_t sur_used;        /* 1: the surrogate-assisted update was applied */
     int32_t sur_iters;       /* its inner fixed-point iterations */

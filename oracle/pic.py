@@ -671,7 +671,9 @@ class OraclePIC:
         """Plasma moments of the current particles: <n_e>, <n_i> over the
         particle box (m^-3), the largest electron node density (m^-3, node
         weights over the node control volume), <eps_e>, <eps_i> (eV), the
-        electron centroid R, z (m) and the ionizations since the last call."""
+        electron centroid R, z (m) and the ionizations since the last call
+        in real particles (macro-particle births times the electron weight,
+        so that the value does not depend on the macro-particle count)."""
         from .circuit import node_volume
         wl = self.wl
         vol = math.pi * wl.rmax ** 2 * wl.zp
@@ -696,7 +698,7 @@ class OraclePIC:
         self.births_prev = self.births_total
         return np.array([ne * we / vol, ni * wi / vol, nmax, energy(Pe, ae, me), energy(Pi, ai, mi),
                          float(np.mean(Pe.R[ae])) if ne else 0.0, float(np.mean(Pe.z[ae])) if ne else 0.0,
-                         float(ion)])
+                         float(ion) * we])
 
     def period_update(self):
         """Close the RF period: finalise the harmonics and, when coupled,

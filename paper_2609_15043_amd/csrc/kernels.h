@@ -224,7 +224,7 @@ struct CircuitDev {
     // surrogate-assisted update: plasma moments of the completed period,
     // the correction y_n - yhat(x^n), the inner fixed-point iterate
     double pressure;
-    double moments[8];          // <n_e>, <n_i>, max n_e, <eps_e>, <eps_i> (eV), R_e, z_e (m), ionizations
+    double moments[8];          // <n_e>, <n_i>, max n_e, <eps_e>, <eps_i> (eV), R_e, z_e (m), ionizations (real particles)
     double births_prev;
     int32_t sur_max_iter, sur_iters, sur_used, sur_done;
     double sur_err_max, sur_tol, sur_err;

@@ -1588,7 +1588,7 @@ namespace pic {
 // per-block FP64 sums over live electrons (count, kinetic energy, R, z) and
 // ions (count, kinetic energy), then one workgroup folds them in block
 // order, adds the electron node-density maximum from this step's charge
-// accumulator and the period's ionizations.
+// accumulator and the period's ionizations (real particles).
 // ---------------------------------------------------------------------------
 constexpr int MOM_BLOCKS = 512;
 
@@ -1665,7 +1665,9 @@ __global__ __launch_bounds__(256) void k_moments_fold(const double *partial, int
     c.moments[5] = ne > 0 ? sums[2] / ne : 0.0;
     c.moments[6] = ne > 0 ? sums[3] / ne : 0.0;
     const double births = (double)stats[ST_BIRTHS];
-    c.moments[7] = births - c.births_prev;
+    // ionizations of the period in real particles (births times the
+    // electron weight): independent of how many macro-particles carry them
+    c.moments[7] = (births - c.births_prev) * we;
     c.births_prev = births;
 }
 

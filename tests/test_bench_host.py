@@ -37,3 +37,31 @@ def test_feature_scale_treats_constant_columns_as_unit_scale():
     s = bench.feature_scale(a)
     assert s[0] == 1.0 and s[2] == 1.0
     assert abs(s[1] - np.std(np.linspace(0.0, 3.0, 240))) < 1e-15
+
+
+def _reps_x(powers, mags):
+    """Reports whose state x = (I_f, I_1, V_1): turn magnitudes as given."""
+    return [dict(p_port=p, x=np.array([1.0, m, 2.0 * m], complex)) for p, m in zip(powers, mags)]
+
+
+def test_stationary_q27_compares_window_means_with_the_preceding_window():
+    # a settled run: power in the band and magnitudes flat from period 3
+    r = _reps_x([50, 55, 58] + [60] * 30, [1.5, 1.4, 1.3] + [1.0] * 30)
+    # window 10: the preceding window [i-10, i) must be settled too, so the
+    # first index is 13 (its preceding window starts at 3)
+    assert bench.stationary_q27(r, 60.0, window=10) == 13
+
+
+def test_stationary_q27_rejects_a_drift_above_one_percent_per_window():
+    # magnitudes grow 0.2 % per period: window means move 2 % per window
+    r = _reps_x([60] * 40, [1.0 + 0.002 * k for k in range(40)])
+    assert bench.stationary_q27(r, 60.0, window=10) is None
+    # 0.05 % per period: 0.5 % per window passes from the first possible index
+    r = _reps_x([60] * 40, [1.0 + 0.0005 * k for k in range(40)])
+    assert bench.stationary_q27(r, 60.0, window=10) == 10
+
+
+def test_stationary_q27_needs_the_power_band_over_the_whole_window():
+    r = _reps_x([60] * 15 + [61] + [60] * 24, [1.0] * 40)
+    # period 15 is 1.7 % off: windows containing it fail
+    assert bench.stationary_q27(r, 60.0, window=10) == 16

@@ -71,7 +71,7 @@ def test_moments_match_oracle():
     g = _run_periods(ctx, ora, 16, 1)[-1]
     o = ora.last_report
     e = [abs(a - b) / max(abs(b), 1e-300) for a, b in zip(g["moments"], o["moments"])]
-    say("    moments " + " ".join(f"{v:.1e}" for v in e) + f" (ionizations {g['moments'][7]:.0f})")
+    say("    moments " + " ".join(f"{v:.1e}" for v in e) + f" (ionizations {g['moments'][7]:.4g})")
     assert max(e[:7]) <= 1e-10 and g["moments"][7] == o["moments"][7]
     assert abs(g["pressure"] - wl.pressure_pa) <= 1e-12 * wl.pressure_pa
 
@@ -172,3 +172,38 @@ def test_trained_surrogate_reaches_stationary_circuit_in_fewer_periods():
         assert p["periods"] is not None and s["periods"] is not None
         assert s["periods"] < p["periods"]
         assert run["final_state_deviation"] < 0.01
+
+
+def test_surrogate_on_plasma_cell_reaches_stationary_circuit_sooner():
+    """The plasma-loaded coil cell (128 x 256 cells, 2e6 e + 2e6 Ar+ at
+    1e14 m^-3, 20 mTorr, 400 steps per RF period, controller towards 3 W
+    from 300 V): the network trained on 120 (state, response) pairs from 12
+    PIC runs at scanned port power (1-7.5 W) and pressure (5-50 mTorr),
+    then refined online on each run's own periods.  The surrogate-assisted
+    FP32-mixed and FP64 runs reach the stationary circuit (bench's
+    stationary_q27, 10-period windows) in fewer periods than the plain FP64
+    run, and over the last 10 of 70 periods their mean state lies within 1 %
+    of the plain run's, every Poisson solve converged."""
+    _need_gpu()
+    import os
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+    say("[gpu] surrogate gain, plasma-loaded coil cell, 3 W: training pairs from 12 PIC runs")
+    X, Y, dinfo = bench.plasma_training_pairs(runs=12, periods=10)
+    net, tinfo = bench.train_plasma_surrogate(X, Y, extra_rows=70)
+    say(f"    {len(X)} pairs in {dinfo['data_wall_s']:.1f} s, final loss {tinfo['final_loss']:.2e}")
+    res = bench.stationary_plasma(targets=(3.0,), periods=70, training=dict(net=net, X=X, Y=Y, info=dinfo))
+    run = res["runs"][0]
+    for k in ("plain_fp64", "surrogate_mixed", "surrogate_fp64"):
+        r = run[k]
+        say(f"    {k}: stationary after {r['periods']} periods ({r['wall_s']} s), surrogate used in "
+            f"{r['surrogate_periods']} of 70, final P_ind {r['final']['p_ind']:.3f} W P_cap "
+            f"{r['final']['p_cap']:.3f} W eps_bal {r['final']['eps_bal']:.1e}, deviation "
+            f"{r['final_state_deviation']:.1e}, unconverged solves {r['mg_unconverged']}")
+    p = run["plain_fp64"]["periods"]
+    assert p is not None
+    for k in ("surrogate_mixed", "surrogate_fp64"):
+        r = run[k]
+        assert r["periods"] is not None and r["periods"] < p, k
+        assert r["final_state_deviation"] < 0.01, k
+    assert all(run[k]["mg_unconverged"] == 0 for k in ("plain_fp64", "surrogate_mixed", "surrogate_fp64"))

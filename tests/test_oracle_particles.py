@@ -577,6 +577,10 @@ def test_moments_of_placed_and_uniform_plasmas():
     assert m[4] == pytest.approx(0.5 * W.M_AR * speed ** 2 / W.QE, rel=1e-13)
     assert m[5] == pytest.approx(R0, rel=1e-14) and m[6] == pytest.approx(z0, rel=1e-14)
     assert m[7] == 0.0
+    # ionizations: births since the last call, in real particles
+    ora.births_total += 7
+    assert ora.moments()[7] == 7 * wl.weight[0]
+    assert ora.moments()[7] == 0.0
     # the same particles on the axis node: its weight integrates to pi dR^2 dz / 2
     for s in range(2):
         ora.parts[s].R[:] = 0.0
