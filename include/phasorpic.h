@@ -58,6 +58,10 @@ enum {
 enum { PIC_FP64 = 0, PIC_MIXED = 1 };
 /* poisson_solve_rz operators */
 enum { PIC_OP_POISSON = 0, PIC_OP_HELMHOLTZ_C = 1, PIC_OP_HELMHOLTZ_S = 2 };
+/* Poisson solver (pic_config.poisson_solver): AUTO takes the direct solve
+ * when the operator separates (below) and multigrid-CG otherwise; DIRECT
+ * fails pic_init with PIC_EINVAL when it does not separate. */
+enum { PIC_POISSON_AUTO = 0, PIC_POISSON_MULTIGRID = 1, PIC_POISSON_DIRECT = 2 };
 enum { PIC_FIELD_FULL = 0, PIC_FIELD_MQS = 1 };   /* inductive operator with / without displacement term */
 enum { PIC_RRF_GIVEN = 0, PIC_RRF_SKIN = 1 };     /* turn RF resistance: given / round-wire skin model */
 #define PIC_MAX_TURNS 16
@@ -177,6 +181,14 @@ typedef struct pic_config {
      *     (a^{n+1} + abar) / 2 -- then the collisions of v^{n+1/2} at x^{n+1} and the births.
      * No magnetic field (bfield, rf_bfield) in this mode. */
     int32_t implicit;
+    /* PIC_POISSON_*.  The direct solve applies when every node of the bottom row, the top row and the
+     * outer radius is Dirichlet, the permittivity of every row of cells is uniform in R (so the
+     * finite-volume operator on the block of remaining nodes is Z (x) L_R + L_Z (x) D), at most 512
+     * Dirichlet nodes lie inside that block, and the update is explicit (implicit == 0: chi changes
+     * the operator every step).  It transforms the block by the radial eigenvectors, solves one
+     * tridiagonal system in z per radial mode, and imposes the interior Dirichlet values (the turns)
+     * through their capacitance matrix: one pass, FP64, with no iteration and no tolerance. */
+    int32_t poisson_solver;
 } pic_config;
 
 typedef struct pic_solve_info {
@@ -262,15 +274,17 @@ pic_status mcc_collide(pic_ctx *ctx, int64_t n);
  * exact 64-bit fixed point, plus the accumulated window surface charge. */
 pic_status pic_deposit(pic_ctx *ctx, int64_t n1);
 
-/* Field solves on the grid, FP64 multigrid-preconditioned CG.
+/* Field solves on the grid, FP64: multigrid-preconditioned CG, or for a
+ * separable Poisson operator the direct solve (pic_config.poisson_solver).
  *
  * op = PIC_OP_POISSON: the finite-volume RZ Poisson problem
  * sum_f eps0 eps_f A_f (phi_p - phi_nb) / d_f = Q_p (Eqs. poisson with
  * chi = 0, epseff, areas; Neumann axis, Eq. axis_electrostatic_bc) with
  * Dirichlet 0 on grounded nodes and phi_k(t_n) = V_c,k cos th_n +
- * V_s,k sin th_n on turn k (Eq. dirichlet), warm-started from the last
- * phi (extrapolated in time along a running sequence of steps).  Then the
- * turn charges Q_k(t_n) from the operator's face fluxes (Eq. facecharge).
+ * V_s,k sin th_n on turn k (Eq. dirichlet); the multigrid-CG solve is
+ * warm-started from the last phi (extrapolated in time along a running
+ * sequence of steps).  Then the turn charges Q_k(t_n) from the operator's
+ * face fluxes (Eq. facecharge).
  *
  * op = PIC_OP_HELMHOLTZ_C / _S (coupled contexts only, else PIC_EINVAL):
  * one of the two real plasma-only inductive solves of the period update
@@ -286,7 +300,9 @@ pic_status pic_deposit(pic_ctx *ctx, int64_t n1);
  * without it a Poisson solve runs an iteration budget adapted to the
  * recent solves and a short solve is only counted (pic_stats.
  * mg_unconverged), while the inductive solves always synchronise and
- * return PIC_ENOTCONV when they miss rtol. */
+ * return PIC_ENOTCONV when they miss rtol.  The direct Poisson solve
+ * ignores rtol and max_cycles except that info, when given, reports its
+ * relative residual (cycles = 0) and PIC_ENOTCONV if that exceeds rtol. */
 pic_status poisson_solve_rz(pic_ctx *ctx, int64_t n, int32_t op, double rtol, int32_t max_cycles,
                             pic_solve_info *info);
 
@@ -476,6 +492,10 @@ pic_status pic_get_stats(pic_ctx *ctx, pic_stats *out);
 /* Release the context (not the caller's workspace). */
 void pic_destroy(pic_ctx *ctx);
 
+/* The message of the context's last failure; with ctx == NULL, why the
+ * last pic_init on the calling thread failed ("null context" if it did
+ * not).  The string stays valid until the next call on that context (or,
+ * for NULL, the next pic_init on the thread). */
 const char *pic_last_error(const pic_ctx *ctx);
 
 /* ------------------------------------------------------------------------

@@ -4,7 +4,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["api.hip", "particles.hip", "fields.hip", "circuit.hip", "mlp.hip"]
+SOURCES = ["api.hip", "particles.hip", "fields.hip", "direct.hip", "circuit.hip", "mlp.hip"]
 LIB = os.path.join(HERE, "libphasorpic.so")
 
 

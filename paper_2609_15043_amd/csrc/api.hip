@@ -15,6 +15,7 @@
 #include "../../include/phasorpic.h"
 #include "kernels.h"
 #include "launch.h"
+#include "separable.h"
 
 using namespace pic;
 
@@ -155,6 +156,10 @@ struct pic_ctx {
     // correction: the solves until the start-value extrapolation again spans
     // only solutions after the jump run max_cycles, and the extrapolation
     // restarts from the first of them
+    // direct solve of a separable operator (poisson_solver), when it applies
+    bool direct = false;
+    bool direct_carved = false;   // the workspace holds the plan's arrays
+    DirectArgs da{};
     int mg_fresh = 0;             // solves left at max_cycles
     bool mg_restart = false;      // the stored solutions predate the jump
     int32_t *fp = nullptr, *fq = nullptr, *fk = nullptr;
@@ -462,6 +467,15 @@ static int mg_levels(int nr, int nz)
     return n;
 }
 
+static_assert(DP_MAX_DIRICHLET == DP_MAX_DIRICHLET_DEV, "interior Dirichlet limit differs between host and device");
+
+// the configuration may take the direct Poisson solve (whether the operator
+// separates is decided at pic_init)
+static bool direct_candidate(const pic_config &f)
+{
+    return f.poisson_solver != PIC_POISSON_MULTIGRID && !f.implicit && f.nr >= 2 && f.nz >= 3;
+}
+
 static void layout(pic_ctx &c, Carver &cv)
 {
     const pic_config &f = c.cfg;
@@ -518,6 +532,29 @@ static void layout(pic_ctx &c, Carver &cv)
     }
     c.d_vc = cv.take<double>(MAX_TURNS);
     c.d_vs = cv.take<double>(MAX_TURNS);
+    if (direct_candidate(f)) {
+        // direct solve of a separable operator (whether it separates is
+        // decided at pic_init; the interior Dirichlet nodes size the plan)
+        int m, nrow;
+        interior_dirichlet(c.tag, f.nr, f.nz, m, nrow);
+        if (m <= DP_MAX_DIRICHLET && nrow <= DP_MAX_ROWS && f.nz - 1 <= DP_MAX_NI) {
+            const int ni = f.nz - 1, nj = f.nr;
+            DirectArgs &d = c.da;
+            d.v = cv.take<double>((size_t)nj * nj);
+            d.lam = cv.take<double>(nj);
+            d.zrow = cv.take<double>(ni);
+            d.erow = cv.take<double>(ni + 1);
+            d.cinv = cv.take<double>((size_t)m * m);
+            d.g = cv.take<double>((size_t)nrow * ni * nj);
+            d.dnode = cv.take<int32_t>(m);
+            d.drow = cv.take<int32_t>(m);
+            d.rows = cv.take<int32_t>(nrow);
+            d.b = cv.take<double>((size_t)ni * nj);
+            d.u = cv.take<double>((size_t)ni * nj);
+            d.w = cv.take<double>((size_t)std::max(nrow, 1) * nj);
+            c.direct_carved = true;
+        }
+    }
     c.Jc = cv.take<double>(nodes);
     c.Jcc = cv.take<double>(nodes);
     c.Js = cv.take<double>(nodes);
@@ -884,8 +921,11 @@ static void pcg_iteration(pic_ctx &c, const MGLevels &lv, MGState *st, const PCG
 
 // Preconditioned CG on the free nodes (x = phi, b = node charge), one
 // V-cycle per iteration; scalars stay on the device.
+static pic_status solve_direct(pic_ctx &c, int64_t n, double rtol, pic_solve_info *info);
+
 static pic_status solve(pic_ctx &c, int64_t n, double rtol, int max_cycles, pic_solve_info *info, bool full = false)
 {
+    if (c.direct && !c.chi) return solve_direct(c, n, rtol, info);
     const double th = TWO_PI * (double)(n % c.nrf) / (double)c.nrf;
     timer_start(c, c.t_poisson);
     const MGLevel &L0 = c.lv.L[0];
@@ -949,6 +989,83 @@ static pic_status solve(pic_ctx &c, int64_t n, double rtol, int max_cycles, pic_
         info->rel_residual = s.rel;
         if (!s.done) return fail(&c, PIC_ENOTCONV, "multigrid-CG: rel residual %.3e after %d iterations", s.rel,
                                  s.cycles);
+    }
+    return PIC_OK;
+}
+
+// Device copy of a separable plan; the direct solve's fixed arguments.
+static pic_status upload_direct(pic_ctx &c, const SeparablePlan &sp)
+{
+    DirectArgs &d = c.da;
+    const pic_config &f = c.cfg;
+    const MGLevel &L0 = c.lv.L[0];
+    d.nr = f.nr;
+    d.nz = f.nz;
+    d.nodes = c.g.nodes;
+    d.ni = sp.ni;
+    d.nj = sp.nj;
+    d.m = sp.m;
+    d.nrow = (int)sp.rows.size();
+    d.nturns = f.nturns;
+    d.tag = c.d_tag;
+    d.vc = c.d_vc;
+    d.vs = c.d_vs;
+    d.basis = c.dbasis;
+    d.phi = c.phi;
+    d.Q = c.Q;
+    d.cw = L0.cw;
+    d.ce = L0.ce;
+    d.cs = L0.cs;
+    d.cn = L0.cn;
+    auto up = [&](const void *dst, const void *src, size_t bytes) {
+        return bytes ? cpy(c.stream, const_cast<void *>(dst), src, bytes, hipMemcpyHostToDevice) : hipSuccess;
+    };
+    if (!c.direct_carved) return fail(&c, PIC_EINVAL, "direct Poisson solve: workspace holds no plan");
+    HIPCHK(&c, up(d.v, sp.v.data(), sp.v.size() * 8));
+    HIPCHK(&c, up(d.lam, sp.lam.data(), sp.lam.size() * 8));
+    HIPCHK(&c, up(d.zrow, sp.zrow.data(), sp.zrow.size() * 8));
+    HIPCHK(&c, up(d.erow, sp.erow.data(), sp.erow.size() * 8));
+    HIPCHK(&c, up(d.cinv, sp.cinv.data(), sp.cinv.size() * 8));
+    HIPCHK(&c, up(d.g, sp.g.data(), sp.g.size() * 8));
+    HIPCHK(&c, up(d.dnode, sp.dnode.data(), sp.dnode.size() * 4));
+    HIPCHK(&c, up(d.drow, sp.drow.data(), sp.drow.size() * 4));
+    HIPCHK(&c, up(d.rows, sp.rows.data(), sp.rows.size() * 4));
+    c.direct = true;
+    return PIC_OK;
+}
+
+// The direct solve of step n (phase th_n): phi on every node, then the turn
+// charges; info gets the relative residual from the multigrid's residual
+// and check kernels (scale as for the iterative solve).
+static pic_status solve_direct(pic_ctx &c, int64_t n, double rtol, pic_solve_info *info)
+{
+    const double th = TWO_PI * (double)(n % c.nrf) / (double)c.nrf;
+    timer_start(c, c.t_poisson);
+    DirectArgs a = c.da;
+    a.cth = std::cos(th);
+    a.sth = std::sin(th);
+    launch_direct_solve(a, c.stream);
+    c.last_solve = n;
+    c.run = 0;
+    c.mg_fresh = 0;
+    c.mg_restart = false;
+    if (c.cfg.nturns > 0)
+        launch_face_charge(c.phi, c.fp, c.fq, c.fk, c.fc, c.nfaces, c.Qk, c.cfg.nturns, c.stream, c.chi);
+    timer_stop(c, c.t_poisson);
+    if (info) {
+        const MGLevel &L0 = c.lv.L[0];
+        const PCGVec v{c.phi, c.Q, c.pr, c.pz, c.pp, c.pAp};
+        launch_pcg_begin(L0, v, c.d_tag, c.d_vc, c.d_vs, a.cth, a.sth, c.mgs, nullptr, 0, c.stream, c.dbasis,
+                         c.cfg.nturns);
+        launch_pcg_resid(L0, v, c.mgpartial, c.stream);
+        launch_pcg_check(c.mgs, c.mgpartial, pcg_blocks(L0.nodes), rtol, true, c.stream);
+        MGState s;
+        HIPCHK(&c, hipMemcpyAsync(&s, c.mgs, sizeof s, hipMemcpyDeviceToHost, c.stream));
+        HIPCHK(&c, hipStreamSynchronize(c.stream));
+        info->cycles = 0;
+        info->converged = s.done;
+        info->rel_residual = s.rel;
+        if (!s.done) return fail(&c, PIC_ENOTCONV, "direct Poisson solve: rel residual %.3e", s.rel);
     }
     return PIC_OK;
 }
@@ -1266,6 +1383,19 @@ template <typename T> static pic_status init_impl(pic_ctx &c)
         }
         pic_status bs = build_levels(c, c.lv, co, dir);
         if (bs) return bs;
+        if (f.poisson_solver == PIC_POISSON_DIRECT && !direct_candidate(f))
+            return fail(&c, PIC_EINVAL, "direct Poisson solve requested for a direct-implicit or tiny grid");
+        if (direct_candidate(f)) {
+            SeparablePlan sp;
+            // (plan_separable also refuses what the layout did not carve for)
+            const std::string why = plan_separable(co.cw, co.ce, co.cs, co.cn, co.cc, c.tag, f.nr, f.nz, sp);
+            if (why.empty()) {
+                pic_status ds = upload_direct(c, sp);
+                if (ds) return ds;
+            } else if (f.poisson_solver == PIC_POISSON_DIRECT) {
+                return fail(&c, PIC_EINVAL, "direct Poisson solve: %s", why.c_str());
+            }
+        }
         if (c.chi) {
             // chi = 0 conductances, from which every step's operator is formed
             const size_t nb = (size_t)nodes * sizeof(double);
@@ -1353,21 +1483,27 @@ template <typename T> static pic_status init_impl(pic_ctx &c)
     return PIC_OK;
 }
 
+// why the last pic_init on this thread failed (pic_last_error(NULL))
+static thread_local std::string init_error;
+
 extern "C" pic_status pic_init(const pic_config *cfg, void *workspace, size_t workspace_bytes, void *stream,
                                pic_ctx **out)
 {
     if (!out) return PIC_EINVAL;
     *out = nullptr;
+    init_error.clear();
     pic_ctx *c = new pic_ctx();
     pic_status st = check_config(cfg, c);
     if (!st) st = prepare_host(*c, cfg);
     if (st) {
+        init_error = c->err;
         delete c;
         return st;
     }
     Carver dry{nullptr};
     layout(*c, dry);
     if (!workspace || workspace_bytes < dry.off) {
+        init_error = "workspace smaller than pic_workspace_bytes()";
         delete c;
         return PIC_ENOMEM;
     }
@@ -1384,6 +1520,7 @@ extern "C" pic_status pic_init(const pic_config *cfg, void *workspace, size_t wo
     }
     st = c->mixed ? init_impl<float>(*c) : init_impl<double>(*c);
     if (st) {
+        init_error = c->err;
         pic_destroy(c);
         return st;
     }
@@ -2336,4 +2473,8 @@ extern "C" void pic_destroy(pic_ctx *c)
     delete c;
 }
 
-extern "C" const char *pic_last_error(const pic_ctx *c) { return c ? c->err.c_str() : "null context"; }
+extern "C" const char *pic_last_error(const pic_ctx *c)
+{
+    if (c) return c->err.c_str();
+    return init_error.empty() ? "null context" : init_error.c_str();
+}

@@ -242,6 +242,28 @@ struct CircuitDev {
     double ovr_vp_re[MAX_TURNS], ovr_vp_im[MAX_TURNS], ovr_icap_re[MAX_TURNS], ovr_icap_im[MAX_TURNS];
 };
 
+// Direct Poisson solve of a separable operator (direct.hip): the grid and
+// phase, the level-0 conductances, the plan's device arrays and the work
+// arrays.  Block row r is node row r + 1; block column j is node column j.
+constexpr int DP_MAX_DIRICHLET_DEV = 512;   // interior Dirichlet nodes at most
+struct DirectArgs {
+    int nr, nz, nodes, ni, nj, m, nrow, nturns;
+    double cth, sth;                        // cos, sin of the step's phase
+    const int32_t *tag;
+    const double *vc, *vs, *basis;
+    double *phi;
+    const double *Q;
+    const double *cw, *ce, *cs, *cn;
+    const double *v;                        // nj x nj radial eigenvectors, v[j * nj + k]
+    const double *lam;                      // nj radial eigenvalues
+    const double *zrow;                     // ni: radial conductance factor of block row r
+    const double *erow;                     // ni + 1: axial coupling of node rows r and r + 1
+    const double *cinv;                     // m x m inverse capacitance matrix
+    const double *g;                        // nrow x ni x nj: responses of the modes to unit sources on rows[q]
+    const int32_t *dnode, *drow, *rows;     // interior Dirichlet nodes, their row index, the distinct rows
+    double *b, *u, *w;                      // ni x nj right-hand side, ni x nj modes, nrow x nj sources
+};
+
 // features of the surrogate network: (I_k re, im), (V_k re, im), pressure,
 // the eight moments; outputs: (V_p,k re, im), (I_cap,k re, im)
 constexpr int SUR_MAX_TURNS = 5;

@@ -75,6 +75,7 @@ int pcg_blocks(int nodes);
 void launch_pcg_begin(const MGLevel &L, const PCGVec &v, const int32_t *tag, const double *vc, const double *vs,
                       double cs, double sn, MGState *st, double *prev, int order, hipStream_t s,
                       const double *basis = nullptr, int nturns = 0);
+void launch_direct_solve(const DirectArgs &a, hipStream_t st);
 void launch_pcg_resid(const MGLevel &L, const PCGVec &v, double *partial, hipStream_t s);
 void launch_pcg_check(MGState *st, const double *partial, int np, double rtol, bool first, hipStream_t s,
                       unsigned long long *unconv = nullptr);

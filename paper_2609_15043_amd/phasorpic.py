@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libphasorpic.so")
 PIC_OK, PIC_EINVAL, PIC_ENOMEM, PIC_EDEVICE, PIC_ENOTCONV, PIC_EPHASE, PIC_ESTATE = 0, -1, -2, -3, -4, -5, -6
 PIC_FP64, PIC_MIXED = 0, 1
 PIC_OP_POISSON, PIC_OP_HELMHOLTZ_C, PIC_OP_HELMHOLTZ_S = 0, 1, 2
+PIC_POISSON_AUTO, PIC_POISSON_MULTIGRID, PIC_POISSON_DIRECT = 0, 1, 2
 PIC_FIELD_FULL, PIC_FIELD_MQS = 0, 1
 PIC_RRF_GIVEN, PIC_RRF_SKIN = 0, 1
 (PIC_GRID_PHI, PIC_GRID_CHARGE, PIC_GRID_CURRENT, PIC_GRID_ER, PIC_GRID_EZ, PIC_GRID_ETHETA,
@@ -51,7 +52,7 @@ class PicConfig(ctypes.Structure):
         ("p_target", _D), ("gamma", _D), ("n_trend", _D), ("eps_p", _D), ("alpha_v", _D), ("f_step", _D),
         ("v_min", _D), ("v_max", _D), ("alpha", _D), ("helm_rtol", _D), ("helm_max_cycles", _I32),
         ("sort_every_ion", _I32), ("dir_basis", _PD), ("unit_bvals", _PD), ("rf_bfield", _I32),
-        ("implicit", _I32),
+        ("implicit", _I32), ("poisson_solver", _I32),
     ]
 
 
@@ -166,9 +167,10 @@ def _ptr(a, t):
 # ---------------------------------------------------------------------------
 def config_from_workload(wl, precision="mixed", fuse=True, load=True, mg_rtol=None, mg_max_cycles=30,
                          sort_every=16, sort_every_ion=0, birth_capacity=65536, nscan=200_000, helm_rtol=1e-12,
-                         helm_max_cycles=60):
+                         helm_max_cycles=60, poisson_solver="auto"):
     """(PicConfig, keep-alive list).  precision: 'fp64' or 'mixed'.  A
-    workload with a ``circuit`` couples its turns to the external network."""
+    workload with a ``circuit`` couples its turns to the external network.
+    poisson_solver: 'auto', 'multigrid' or 'direct' (PIC_POISSON_*)."""
     keep = []
     c = PicConfig()
     c.nr, c.nz, c.ip, c.window = wl.nr, wl.nz, wl.ip, 1 if wl.window else 0
@@ -210,6 +212,8 @@ def config_from_workload(wl, precision="mixed", fuse=True, load=True, mg_rtol=No
     c.sort_every_ion = sort_every_ion
     c.rf_bfield = 1 if wl.rf_bfield else 0
     c.implicit = 1 if wl.implicit else 0
+    c.poisson_solver = {"auto": PIC_POISSON_AUTO, "multigrid": PIC_POISSON_MULTIGRID,
+                        "direct": PIC_POISSON_DIRECT}[poisson_solver]
     c.birth_capacity = birth_capacity
     cp = wl.circuit
     if cp is not None:
@@ -277,7 +281,7 @@ def pic_init(cfg, keep=(), device="cuda", stream=None):
     st = lib().pic_init(ctypes.byref(cfg), ctypes.c_void_p(ws.data_ptr()), nbytes, ctypes.c_void_p(stream),
                         ctypes.byref(h))
     if st:
-        raise PicError(st, "pic_init failed (see configuration)")
+        raise PicError(st, "pic_init: " + lib().pic_last_error(None).decode())
     return Context(h, ws, list(keep), cfg)
 
 

@@ -123,3 +123,28 @@ def test_particle_capacity_overflow_reports_enomem():
     with pytest.raises(pp.PicError) as e:
         _run_until_error(ctx, 200)
     assert e.value.status == pp.PIC_ENOMEM and "capacity" in str(e.value)
+
+
+def test_direct_poisson_solver_refuses_a_non_separable_operator():
+    """poisson_solver = direct needs permittivity uniform along every row of
+    cells: one cell off that makes pic_init fail with PIC_EINVAL and says
+    why; 'auto' takes multigrid-CG for the same workload."""
+    _need_gpu()
+    import paper_2609_15043_amd.phasorpic as pp
+    from paper_2609_15043_amd import workloads as W
+    wl = W.small(n_per_species=1000)
+    wl.eps_cell = wl.eps_cell.copy()
+    wl.eps_cell[10, 5] = 2.0
+    say("[gpu] direct Poisson solve on a non-separable operator")
+    cfg, keep = pp.config_from_workload(wl, precision="fp64", load=False, poisson_solver="direct")
+    with pytest.raises(pp.PicError) as e:
+        pp.pic_init(cfg, keep)
+    say(f"    {e.value}")
+    assert e.value.status == pp.PIC_EINVAL and "permittivity" in str(e.value)
+    # auto: multigrid-CG (it iterates from a zero start; the direct solve reports no cycles)
+    cfg, keep = pp.config_from_workload(wl, precision="fp64", load=True)
+    ctx = pp.pic_init(cfg, keep)
+    pp.pic_set_phi(ctx, np.zeros((wl.nz + 1, wl.nr + 1)))
+    info = pp.poisson_solve_rz(ctx, 0, info=True)
+    say(f"    auto on the same workload: {info}")
+    assert info["converged"] and info["cycles"] > 0
