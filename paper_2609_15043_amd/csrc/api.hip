@@ -549,6 +549,9 @@ static void layout(pic_ctx &c, Carver &cv)
             d.dnode = cv.take<int32_t>(m);
             d.drow = cv.take<int32_t>(m);
             d.rows = cv.take<int32_t>(nrow);
+            d.rowstart = cv.take<int32_t>(nrow + 1);
+            d.res = cv.take<double>(m);
+            d.src = cv.take<double>(m);
             d.b = cv.take<double>((size_t)ni * nj);
             d.u = cv.take<double>((size_t)ni * nj);
             d.w = cv.take<double>((size_t)std::max(nrow, 1) * nj);
@@ -1030,6 +1033,12 @@ static pic_status upload_direct(pic_ctx &c, const SeparablePlan &sp)
     HIPCHK(&c, up(d.dnode, sp.dnode.data(), sp.dnode.size() * 4));
     HIPCHK(&c, up(d.drow, sp.drow.data(), sp.drow.size() * 4));
     HIPCHK(&c, up(d.rows, sp.rows.data(), sp.rows.size() * 4));
+    {
+        std::vector<int32_t> rs(sp.rows.size() + 1, 0);
+        for (int32_t r : sp.drow) ++rs[r + 1];
+        for (size_t q = 0; q < sp.rows.size(); ++q) rs[q + 1] += rs[q];
+        HIPCHK(&c, up(d.rowstart, rs.data(), rs.size() * 4));
+    }
     c.direct = true;
     return PIC_OK;
 }

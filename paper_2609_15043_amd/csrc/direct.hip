@@ -11,8 +11,8 @@
 //   k_dp_gemm    B~ = B V (rows of the block times the radial eigenvectors);
 //   k_dp_pcr     the tridiagonal system of each mode by parallel cyclic
 //                reduction in LDS (one workgroup per mode);
-//   k_dp_cap     (S b)_D, s = C^{-1} (phi_D - (S b)_D), and the sources
-//                transformed by V^T, in one workgroup;
+//   k_dp_xd, k_dp_src, k_dp_w: (S b)_D, s = C^{-1} (phi_D - (S b)_D), and
+//                the sources transformed by V^T;
 //   k_dp_correct the modes' response to those sources (precomputed unit
 //                responses g), added;
 //   k_dp_gemm    phi = U V^T on the block (Dirichlet nodes get their values).
@@ -62,42 +62,55 @@ __global__ __launch_bounds__(256) void k_dp_rhs(DirectArgs a)
 }
 
 // C = A op(B) with A m x kk (row-major), op(B) kk x nn: B as stored
-// (B[k * nn + c]) or transposed (B[c * kk + k]).  32 x 32 tiles of C per
-// 256-thread workgroup, 2 x 2 per thread, kk in slices of 16 through LDS.
-// to_phi: C row r is block row r + 1 of phi (columns 0..nr-1), Dirichlet
-// nodes of the block taking their values.
-constexpr int GT = 32, GK = 16;
+// (B[k * nn + c]) or transposed (B[c * kk + k]).  One wave per 16 x 16 tile
+// of C (2 x 2 per lane), kk in slices of 64 through LDS; the next slice's
+// loads are issued before the current slice is multiplied, so their latency
+// hides behind the arithmetic.  to_phi: C row r is block row r + 1 of phi
+// (columns 0..nr-1), Dirichlet nodes of the block taking their values.
+constexpr int GT = 16, GK = 64, GE = GT * GK / 64;   // tile, slice, elements per lane and operand
 template <bool TRANS_B, bool TO_PHI>
-__global__ __launch_bounds__(256) void k_dp_gemm(const double *A, const double *B, double *C, int m, int nn, int kk,
-                                                 DirectArgs a)
+__global__ __launch_bounds__(64) void k_dp_gemm(const double *A, const double *B, double *C, int m, int nn, int kk,
+                                                DirectArgs a)
 {
-    __shared__ double As[GT][GK + 1];
-    __shared__ double Bs[GK][GT + 1];
-    const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
+    __shared__ double As[GT][GK + 1];   // [row][k]
+    __shared__ double Bs[GK][GT + 1];   // [k][column]
+    const int lane = threadIdx.x, tx = lane % 8, ty = lane / 8;
     const int r0 = blockIdx.y * GT, c0 = blockIdx.x * GT;
-    double acc00 = 0.0, acc01 = 0.0, acc10 = 0.0, acc11 = 0.0;
-    for (int k0 = 0; k0 < kk; k0 += GK) {
-        for (int e = tid; e < GT * GK; e += 256) {
-            const int rr = e / GK, q = e % GK;
+    double ra[GE], rb[GE];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int e = 0; e < GE; ++e) {
+            const int idx = e * 64 + lane;
+            const int rr = idx / GK, q = idx % GK;   // A: consecutive lanes, consecutive k
             const int gr = r0 + rr, gk = k0 + q;
-            As[rr][q] = (gr < m && gk < kk) ? A[(size_t)gr * kk + gk] : 0.0;
-        }
-        for (int e = tid; e < GT * GK; e += 256) {
-            int q, cc;
-            if (TRANS_B) {
-                cc = e / GK;
-                q = e % GK;
-            } else {
-                q = e / GT;
-                cc = e % GT;
+            ra[e] = (gr < m && gk < kk) ? A[(size_t)gr * kk + gk] : 0.0;
+            int bq, bc;
+            if (TRANS_B) {   // consecutive lanes, consecutive k of one column
+                bc = idx / GK;
+                bq = idx % GK;
+            } else {         // consecutive lanes, consecutive columns of one k
+                bq = idx / GT;
+                bc = idx % GT;
             }
-            const int gk = k0 + q, gc = c0 + cc;
-            double v = 0.0;
-            if (gk < kk && gc < nn) v = TRANS_B ? B[(size_t)gc * kk + gk] : B[(size_t)gk * nn + gc];
-            Bs[q][cc] = v;
+            const int hk = k0 + bq, hc = c0 + bc;
+            rb[e] = (hk < kk && hc < nn) ? (TRANS_B ? B[(size_t)hc * kk + hk] : B[(size_t)hk * nn + hc]) : 0.0;
+        }
+    };
+    double acc00 = 0.0, acc01 = 0.0, acc10 = 0.0, acc11 = 0.0;
+    fetch(0);
+    for (int k0 = 0; k0 < kk; k0 += GK) {
+#pragma unroll
+        for (int e = 0; e < GE; ++e) {
+            const int idx = e * 64 + lane;
+            As[idx / GK][idx % GK] = ra[e];
+            if (TRANS_B)
+                Bs[idx % GK][idx / GK] = rb[e];
+            else
+                Bs[idx / GT][idx % GT] = rb[e];
         }
         __syncthreads();
-#pragma unroll
+        if (k0 + GK < kk) fetch(k0 + GK);
+#pragma unroll 16
         for (int q = 0; q < GK; ++q) {
             const double x0 = As[2 * ty][q], x1 = As[2 * ty + 1][q];
             const double y0 = Bs[q][2 * tx], y1 = Bs[q][2 * tx + 1];
@@ -173,40 +186,51 @@ __global__ __launch_bounds__(256) void k_dp_pcr(DirectArgs a)
     for (int r = threadIdx.x; r < ni; r += blockDim.x) a.u[(size_t)r * nj + k] = D0[r] / B0[r];
 }
 
-// The capacitance step in one workgroup: x_D = (V u)_D at the interior
-// Dirichlet nodes, s = C^{-1} (phi_D - x_D), and w(q, k) = sum over the
-// nodes d of row rows[q] of s_d V(j_d, k).
-__global__ __launch_bounds__(256) void k_dp_cap(DirectArgs a)
+// The capacitance step, spread over the chip in three kernels (each a
+// fixed-order reduction per output, so the result is the same every run):
+// k_dp_xd: res_d = phi_D - (V u)_d at each interior Dirichlet node (one
+// wave per node); k_dp_src: s = C^{-1} res (one wave per row of C^{-1});
+// k_dp_w: w(q, k) = sum over the nodes d of row rows[q] of s_d V(j_d, k)
+// (one lane per (q, k); the nodes of a row are a contiguous range).
+__device__ __forceinline__ double wave_sum(double x)
 {
-    __shared__ double res[DP_MAX_DIRICHLET_DEV];
-    __shared__ double src[DP_MAX_DIRICHLET_DEV];
-    const int nj = a.nj, m = a.m, nr1 = a.nr + 1;
-    for (int d = threadIdx.x; d < m; d += blockDim.x) {
-        const int n = a.dnode[d], i = n / nr1, j = n - i * nr1;
-        const double *u = a.u + (size_t)(i - 1) * nj;
-        const double *v = a.v + (size_t)j * nj;
-        double x = 0.0;
-        for (int k = 0; k < nj; ++k) x = fma(v[k], u[k], x);
-        res[d] = dirichlet_value(a, n) - x;
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+__global__ __launch_bounds__(64) void k_dp_xd(DirectArgs a)
+{
+    const int d = blockIdx.x, lane = threadIdx.x, nj = a.nj, nr1 = a.nr + 1;
+    const int n = a.dnode[d], i = n / nr1, j = n - i * nr1;
+    const double *u = a.u + (size_t)(i - 1) * nj;
+    const double *v = a.v + (size_t)j * nj;
+    double x = 0.0;
+    for (int k = lane; k < nj; k += 64) x = fma(v[k], u[k], x);
+    x = wave_sum(x);
+    if (lane == 0) a.res[d] = dirichlet_value(a, n) - x;
+}
+
+__global__ __launch_bounds__(64) void k_dp_src(DirectArgs a)
+{
+    const int d = blockIdx.x, lane = threadIdx.x, m = a.m;
+    const double *ci = a.cinv + (size_t)d * m;
+    double s = 0.0;
+    for (int e = lane; e < m; e += 64) s = fma(ci[e], a.res[e], s);
+    s = wave_sum(s);
+    if (lane == 0) a.src[d] = s;
+}
+
+__global__ __launch_bounds__(256) void k_dp_w(DirectArgs a)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x, nj = a.nj, nr1 = a.nr + 1;
+    if (t >= a.nrow * nj) return;
+    const int q = t / nj, k = t - q * nj;
+    double w = 0.0;
+    for (int d = a.rowstart[q]; d < a.rowstart[q + 1]; ++d) {
+        const int n = a.dnode[d], j = n - (n / nr1) * nr1;
+        w = fma(a.src[d], a.v[(size_t)j * nj + k], w);
     }
-    __syncthreads();
-    for (int d = threadIdx.x; d < m; d += blockDim.x) {
-        const double *ci = a.cinv + (size_t)d * m;
-        double s = 0.0;
-        for (int e = 0; e < m; ++e) s = fma(ci[e], res[e], s);
-        src[d] = s;
-    }
-    __syncthreads();
-    for (int t = threadIdx.x; t < a.nrow * nj; t += blockDim.x) {
-        const int q = t / nj, k = t - q * nj;
-        double w = 0.0;
-        for (int d = 0; d < m; ++d) {
-            if (a.drow[d] != q) continue;
-            const int n = a.dnode[d], j = n - (n / nr1) * nr1;
-            w = fma(src[d], a.v[(size_t)j * nj + k], w);
-        }
-        a.w[t] = w;
-    }
+    a.w[t] = w;
 }
 
 // u += sum_q g_q w_q: the modes' response to the capacitance sources
@@ -227,15 +251,17 @@ void launch_direct_solve(const DirectArgs &a, hipStream_t st)
     hipLaunchKernelGGL(k_dp_rhs, dim3((a.nodes + 255) / 256), dim3(256), 0, st, a);
     const dim3 g((a.nj + GT - 1) / GT, (a.ni + GT - 1) / GT);
     // B~ = B V into u, then the mode solves in place
-    hipLaunchKernelGGL((k_dp_gemm<false, false>), g, dim3(256), 0, st, (const double *)a.b, a.v, a.u, a.ni, a.nj,
+    hipLaunchKernelGGL((k_dp_gemm<false, false>), g, dim3(64), 0, st, (const double *)a.b, a.v, a.u, a.ni, a.nj,
                        a.nj, a);
     hipLaunchKernelGGL(k_dp_pcr, dim3(a.nj), dim3(256), 8 * (size_t)a.ni * sizeof(double), st, a);
     if (a.m > 0) {
-        hipLaunchKernelGGL(k_dp_cap, dim3(1), dim3(256), 0, st, a);
+        hipLaunchKernelGGL(k_dp_xd, dim3(a.m), dim3(64), 0, st, a);
+        hipLaunchKernelGGL(k_dp_src, dim3(a.m), dim3(64), 0, st, a);
+        hipLaunchKernelGGL(k_dp_w, dim3((a.nrow * a.nj + 255) / 256), dim3(256), 0, st, a);
         const size_t tot = (size_t)a.ni * a.nj;
         hipLaunchKernelGGL(k_dp_correct, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, a);
     }
-    hipLaunchKernelGGL((k_dp_gemm<true, true>), g, dim3(256), 0, st, (const double *)a.u, a.v, (double *)nullptr,
+    hipLaunchKernelGGL((k_dp_gemm<true, true>), g, dim3(64), 0, st, (const double *)a.u, a.v, (double *)nullptr,
                        a.ni, a.nj, a.nj, a);
 }
 

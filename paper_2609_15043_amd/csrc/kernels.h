@@ -261,7 +261,9 @@ struct DirectArgs {
     const double *cinv;                     // m x m inverse capacitance matrix
     const double *g;                        // nrow x ni x nj: responses of the modes to unit sources on rows[q]
     const int32_t *dnode, *drow, *rows;     // interior Dirichlet nodes, their row index, the distinct rows
+    const int32_t *rowstart;                // nrow + 1: the nodes of row q are dnode[rowstart[q] .. rowstart[q+1])
     double *b, *u, *w;                      // ni x nj right-hand side, ni x nj modes, nrow x nj sources
+    double *res, *src;                      // m: phi_D - (S b)_D, and the capacitance sources
 };
 
 // features of the surrogate network: (I_k re, im), (V_k re, im), pressure,
