@@ -65,3 +65,14 @@ def test_stationary_q27_needs_the_power_band_over_the_whole_window():
     r = _reps_x([60] * 15 + [61] + [60] * 24, [1.0] * 40)
     # period 15 is 1.7 % off: windows containing it fail
     assert bench.stationary_q27(r, 60.0, window=10) == 16
+
+
+def test_settled_index_needs_the_band_to_the_end():
+    r = _reps_x([50, 58, 60.5, 59.5, 60.2] + [60] * 10, [1.0] * 15)
+    assert bench.settled_index(r, 60.0) == 2
+    # a late excursion moves the settling period past it
+    r = _reps_x([60] * 5 + [61] + [60] * 12, [1.0] * 18)
+    assert bench.settled_index(r, 60.0) == 6
+    # in band only over the last 9 periods: too short to count
+    r = _reps_x([50] * 6 + [60] * 9, [1.0] * 15)
+    assert bench.settled_index(r, 60.0) is None
