@@ -388,7 +388,8 @@ class FieldCircuit:
         return dict(p_port=pp, p_ind=h["P_ind"], p_cap=h["P_cap"], p_cap_ph=h["P_cap_ph"], p_cu=pcu,
                     eps_bal=eps_bal, vp=vp, icap=icap, x_prev=x_n, x_target=xt, x=self.x.copy(),
                     vg=self.vg, vg_old=vg_old, pf=pf, pc=pc,
-                    kcl=float(np.max(np.abs(rI))) / iscale, kvl=float(np.max(np.abs(rV))) / abs(self.vg))
+                    kcl=float(np.max(np.abs(rI))) / iscale,
+                    kvl=float(np.max(np.abs(rV))) / (abs(self.vg) if self.vg != 0 else 1.0))
 
     def features(self, x, pressure, moments):
         """Surrogate input: (I_k re, im), (V_k re, im), pressure, moments."""
@@ -484,3 +485,98 @@ class FieldCircuit:
         Harmonics.finalize).  Returns the period report."""
         x_n, vp, icap, pp, pcu, eps_bal = self._measure(h)
         return self._plain(h, x_n, vp, icap, pp, pcu, eps_bal, self.vg_amp)
+
+
+# ---------------------------------------------------------------------------
+# Multiharmonic extension (the paper's outlook, Sec. 5): the same network at
+# each retained frequency m w, with the field responses, conductor and
+# matching-network impedances of that frequency; plasma-current and
+# conductor-charge harmonics of order m supply its loads, with
+# I_cap^(m) = i m w Q^(m).  The source's harmonics keep fixed ratios to the
+# fundamental, V_g^(m) = rho_m exp(i phi_m) V_g, and the power controller
+# acts on V_g with the total port power sum_m P_port^(m).
+# ---------------------------------------------------------------------------
+class MultiHarmonicCircuit:
+    """One FieldCircuit per retained order m = 1..M (frequency m f).  The
+    orders above the fundamental run without their own controller; their
+    source amplitude follows the fundamental's through the fixed ratio."""
+
+    def __init__(self, nr, nz, dr, dz, tag, eps_cell, freq, eps0, params, unit_bvals=None):
+        import dataclasses
+        self.p = params
+        self.M = 1 + len(params.harmonics)
+        self.ratio = [1.0 + 0.0j] + [a * complex(math.cos(ph), math.sin(ph)) for a, ph in params.harmonics]
+        self.fcs = []
+        for m in range(1, self.M + 1):
+            pm = dataclasses.replace(params, controller=params.controller and m == 1, vg_from_target=False,
+                                     vg_amp=1.0)
+            self.fcs.append(FieldCircuit(nr, nz, dr, dz, tag, eps_cell, freq * m, eps0, pm, unit_bvals))
+        f1 = self.fcs[0]
+        self.N = f1.N
+        self.ctrl = f1.ctrl
+        ph = complex(math.cos(params.vg_phase), math.sin(params.vg_phase))
+        # the networks are linear in their sources: the start amplitude that
+        # puts p_target into the vacuum networks together
+        zeros = np.zeros(self.N, complex)
+        vg = params.vg_amp
+        if params.vg_from_target:
+            p1 = sum(p_port(np.linalg.solve(fc.A, network_rhs(r * ph, zeros, zeros)), self.N)
+                     for fc, r in zip(self.fcs, self.ratio))
+            vg = math.sqrt(params.p_target / p1)
+        self.vg_amp = vg
+        self._apply_sources(vg)
+        for fc in self.fcs:
+            fc.x = np.linalg.solve(fc.A, network_rhs(fc.vg, zeros, zeros))
+            fc.Ec, fc.Es = compose(fc.Ec_p, fc.Es_p, fc.U, fc.x[1:1 + self.N])
+
+    def _apply_sources(self, vg):
+        ph = complex(math.cos(self.p.vg_phase), math.sin(self.p.vg_phase))
+        for fc, r in zip(self.fcs, self.ratio):
+            fc.vg = vg * r * ph
+            fc.vg_amp = abs(fc.vg)
+
+    @property
+    def turn_vc(self):
+        return [fc.turn_vc for fc in self.fcs]
+
+    @property
+    def turn_vs(self):
+        return [fc.turn_vs for fc in self.fcs]
+
+    @property
+    def Ec(self):
+        return [fc.Ec for fc in self.fcs]
+
+    @property
+    def Es(self):
+        return [fc.Es for fc in self.fcs]
+
+    def update(self, hs):
+        """Closed-period update from the finalised harmonics of every order
+        (hs[m - 1] from the accumulator of order m; the time-domain powers
+        P_ind and P_cap are those of the fundamental's accumulator, which
+        sums over all orders).  Returns the report: totals, and per order
+        the fundamental's report fields under "orders"."""
+        N = self.N
+        meas = [fc._measure(h) for fc, h in zip(self.fcs, hs)]
+        p_tot = sum(m[3] for m in meas)
+        pcu_tot = sum(m[4] for m in meas)
+        vg_old = self.vg_amp
+        pf = pc = None
+        if self.ctrl is not None:
+            self.vg_amp, pf, pc = self.ctrl.step(vg_old, p_tot)
+        self._apply_sources(self.vg_amp)
+        reps = []
+        for fc, h, (x_n, vp, icap, pp, pcu, _) in zip(self.fcs, hs, meas):
+            xt = np.linalg.solve(fc.A, network_rhs(fc.vg, icap, vp))
+            a = fc.p.alpha
+            fc.x = (1 - a) * x_n + a * xt
+            reps.append(fc._report(h, x_n, vp, icap, pp, pcu, 0.0, xt, vg_old, None, None))
+        h1 = hs[0]
+        pbal = h1["P_ind"] + h1["P_cap"] + pcu_tot
+        eps_bal = abs(p_tot - pbal) / abs(p_tot) if p_tot != 0 else float("inf")
+        rep = dict(reps[0])
+        rep.update(p_port=p_tot, p_cu=pcu_tot, eps_bal=eps_bal, vg_old=vg_old, pf=pf, pc=pc,
+                   vg=self.fcs[0].vg, p_cap_ph=sum(r["p_cap_ph"] for r in reps),
+                   kcl=max(r["kcl"] for r in reps), kvl=max(r["kvl"] for r in reps), orders=reps)
+        return rep

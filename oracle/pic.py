@@ -431,10 +431,13 @@ class Poisson:
 # Period accumulators (Eqs. fourier, icap, pind, pcap, pcap_phasor)
 # ---------------------------------------------------------------------------
 class Harmonics:
-    """Fundamental-harmonic and power accumulators over one RF period."""
+    """Harmonic and power accumulators over one RF period: the projections
+    on cos(m th_n), sin(m th_n) of order m (the fundamental by default;
+    freq is then the order's frequency m f), the time-domain inductive power
+    and the trapezoid of V_k dQ_k."""
 
-    def __init__(self, shape, nturns, nrf, freq):
-        self.shape, self.N, self.nrf, self.freq = shape, nturns, nrf, freq
+    def __init__(self, shape, nturns, nrf, freq, order=1):
+        self.shape, self.N, self.nrf, self.freq, self.order = shape, nturns, nrf, freq, order
         self.reset()
 
     def reset(self):
@@ -451,7 +454,7 @@ class Harmonics:
     def add(self, n, I, Et, Qk, Vk):
         """Sample of step n: node current I^n, node E_theta(t_n), turn
         charges Q_k(t_n) and turn potentials V_k(t_n)."""
-        th = theta(n, self.nrf)
+        th = theta(n, self.nrf) * self.order
         c, s = math.cos(th), math.sin(th)
         self.Jc += I * c
         self.Js += I * s
@@ -519,7 +522,14 @@ class OraclePIC:
         self.sur_cfg = dict(err_max=0.02, tol=1e-6, max_iter=50)
         self.births_total = 0
         self.births_prev = 0
-        if wl.circuit is not None:
+        # retained source harmonics (orders 2..M) of a coupled cell
+        self.M = 1 + (len(wl.circuit.harmonics) if wl.circuit is not None else 0)
+        if wl.circuit is not None and self.M > 1:
+            from .circuit import MultiHarmonicCircuit
+            self.fc = MultiHarmonicCircuit(wl.nr, wl.nz, wl.dr, wl.dz, wl.node_tag, wl.eps_cell, wl.freq, W.EPS0,
+                                           wl.circuit)
+            self.vc, self.vs, self.ec, self.es = self.fc.turn_vc, self.fc.turn_vs, self.fc.Ec, self.fc.Es
+        elif wl.circuit is not None:
             from .circuit import FieldCircuit
             self.fc = FieldCircuit(wl.nr, wl.nz, wl.dr, wl.dz, wl.node_tag, wl.eps_cell, wl.freq, W.EPS0,
                                    wl.circuit)
@@ -543,10 +553,16 @@ class OraclePIC:
     # -- fields -----------------------------------------------------------
     def turn_phi(self, n):
         th = theta(n, self.nrf)
+        if self.M > 1:   # sum over the retained orders m: V_c^(m) cos(m th) + V_s^(m) sin(m th)
+            return sum(vc * math.cos(m * th) + vs * math.sin(m * th)
+                       for m, (vc, vs) in enumerate(zip(self.vc, self.vs), start=1))
         return self.vc * math.cos(th) + self.vs * math.sin(th)
 
     def etheta(self, n):
         th = theta(n, self.nrf)
+        if self.M > 1:
+            return sum(ec * math.cos(m * th) - es * math.sin(m * th)
+                       for m, (ec, es) in enumerate(zip(self.ec, self.es), start=1))
         return self.ec * math.cos(th) - self.es * math.sin(th)
 
     # -- particle operations ------------------------------------------------
@@ -556,6 +572,7 @@ class OraclePIC:
         Er, Ez, Et = (np.ascontiguousarray(a, dtype=np.float64) for a in (Er, Ez, Et))
         Br = Bz = None
         if self.wl.rf_bfield:
+            assert self.M == 1, "the RF magnetic field is formed from the fundamental only"
             Br, Bz = rf_bfield(self.ec, self.es, self.wl.dr, self.wl.dz, 2 * math.pi * self.wl.freq,
                                theta(n, self.nrf))
         self.I = np.zeros(self.shape)
@@ -663,9 +680,15 @@ class OraclePIC:
     # -- harmonics ----------------------------------------------------------------
     def reset_harmonics(self):
         self.harm = Harmonics(self.shape, self.wl.nturns, self.nrf, self.wl.freq)
+        # orders 2..M of a multiharmonic circuit
+        self.harm_hi = [Harmonics(self.shape, self.wl.nturns, self.nrf, self.wl.freq * m, order=m)
+                        for m in range(2, getattr(self, "M", 1) + 1)]
 
     def harmonic(self, n):
-        self.harm.add(n, self.I, self.etheta(n), self.Qk, self.turn_phi(n))
+        I, Et, Vk = self.I, self.etheta(n), self.turn_phi(n)
+        self.harm.add(n, I, Et, self.Qk, Vk)
+        for h in self.harm_hi:
+            h.add(n, I, Et, self.Qk, Vk)
 
     def moments(self):
         """Plasma moments of the current particles: <n_e>, <n_i> over the
@@ -706,6 +729,18 @@ class OraclePIC:
         is set) and the next period's turn potentials and field.  Returns
         the report (None and restart of the accumulators when the sample
         count is not N_RF)."""
+        if self.M > 1:
+            hs = [h.finalize(vc, vs) for h, vc, vs in zip([self.harm] + self.harm_hi, self.vc, self.vs)]
+            self.reset_harmonics()
+            if any(h is None for h in hs):
+                return None
+            rep = self.fc.update(hs)
+            rep["moments"] = self.moments()
+            rep["pressure"] = self.wl.pressure_pa
+            self.vc, self.vs, self.ec, self.es = self.fc.turn_vc, self.fc.turn_vs, self.fc.Ec, self.fc.Es
+            r = {**hs[0], **rep, "harmonics": hs}
+            self.last_report = r
+            return r
         r = self.harm.finalize(self.vc, self.vs)
         self.reset_harmonics()
         if r is None:

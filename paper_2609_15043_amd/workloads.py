@@ -116,6 +116,9 @@ class CircuitParams:
     v_min: float = 1.0
     v_max: float = 5000.0
     alpha: float = 0.3                # state relaxation of the circuit update
+    # retained higher harmonics of the source (orders 2, 3, ...): each
+    # (amplitude ratio to the fundamental, phase in rad); empty: fundamental only
+    harmonics: tuple = ()
 
 
 @dataclasses.dataclass
