@@ -77,9 +77,9 @@ enum {
     PIC_GRID_SURFACE = 6,  /* window surface charge accumulated up to the last pic_deposit (C) */
     PIC_GRID_JC = 7,       /* running sum of I^n cos(theta_n) of the open period */
     PIC_GRID_JS = 8,       /* running sum of I^n sin(theta_n) of the open period */
-    PIC_GRID_EC = 9,       /* E_c of the applied azimuthal field (V/m) */
-    PIC_GRID_ES = 10,      /* stored sine array E_s^sto = -E_s of the applied field (V/m) */
-    PIC_GRID_EC_PLASMA = 11,  /* plasma-only E_c^p of the last circuit update */
+    PIC_GRID_EC = 9,       /* E_c of the applied azimuthal field (V/m; the fundamental's with nharm > 0) */
+    PIC_GRID_ES = 10,      /* stored sine array E_s^sto = -E_s of the applied field (V/m; likewise) */
+    PIC_GRID_EC_PLASMA = 11,  /* plasma-only E_c^p of the last circuit update (fundamental) */
     PIC_GRID_ES_PLASMA = 12,  /* plasma-only E_s^sto,p of the last circuit update */
     PIC_GRID_BR = 13,      /* staged RF B_r of the last pic_gather_push (T), cfg->rf_bfield only */
     PIC_GRID_BZ = 14,      /* staged RF B_z (T) */
@@ -189,6 +189,21 @@ typedef struct pic_config {
      * tridiagonal system in z per radial mode, and imposes the interior Dirichlet values (the turns)
      * through their capacitance matrix: one pass, FP64, with no iteration and no tolerance. */
     int32_t poisson_solver;
+    /* Multiharmonic circuit (the outlook of the paper's conclusions): nharm orders above the fundamental
+     * (0..3) are retained, order m = 2..nharm+1 at frequency m freq.  Each order runs the circuit
+     * network of Sec. 2.2 at m w -- its own unit fields, Z_vac, source and matching impedance and skin
+     * resistance at m w, plasma-only fields from the order-m current harmonic J^(m) = (2 / N_RF)
+     * sum_n I^n (cos, sin)(m th_n), and I_cap^(m) = i m w Q^(m) from the turn-charge harmonic of order
+     * m -- and the fields, turn potentials and gathers take the sum over the orders, E_theta(t_n) =
+     * sum_m E_c^(m) cos(m th_n) - E_s^sto,(m) sin(m th_n) and phi_k(t_n) = sum_m V_c,k^(m) cos(m th_n)
+     * + V_s,k^(m) sin(m th_n).  The source of order m is harm_ratio[m-2] exp(i harm_phase[m-2]) times
+     * the fundamental's V_g; the controller and the target-power start act on the total port power
+     * (sum over the orders).  Requires circuit = 1 and field_mode = PIC_FIELD_MQS (one inductive
+     * operator for every order); excludes rf_bfield, pic_set_source, prescribed loads and the
+     * surrogate.  harm_ratio > 0 and finite phases for the first nharm entries. */
+    int32_t nharm;
+    double harm_ratio[3];
+    double harm_phase[3];    /* rad */
 } pic_config;
 
 typedef struct pic_solve_info {
@@ -349,6 +364,7 @@ typedef struct pic_period_report {
     int32_t sur_iters;       /* its inner fixed-point iterations */
     double sur_err;          /* scaled prediction error at the applied state */
     double sur_steps[64];    /* |x_{i+1} - x_i| / |x_{i+1}| of each inner iterate (first sur_iters) */
+    double vg_phase;         /* phase of the Thevenin source V_g (rad) */
 } pic_period_report;
 
 /* Surrogate-assisted circuit update (the learned predictor of the load
@@ -414,20 +430,39 @@ typedef struct pic_circuit_override {
  * relaxation, the residuals, and the next period's turn potentials and
  * field (Eq. compose).  PIC_EINVAL for an override that does not fit the
  * context (turn data on a coupled one, loads on an uncoupled one or with a
- * surrogate); PIC_ENOTCONV if an inductive solve misses helm_rtol.  The
- * accumulators are reset. */
+ * surrogate, or loads with cfg->nharm > 0); PIC_ENOTCONV if an inductive
+ * solve misses helm_rtol.  The accumulators are reset.
+ *
+ * With cfg->nharm > 0 every retained order runs that update at its own
+ * frequency (two inductive solves per order, its own loads and network),
+ * the controller acts on the total port power, and *report holds the
+ * fundamental's harmonics, loads and states with the totals over the orders
+ * in p_port, p_cu, p_cap_ph, eps_bal and kcl / kvl (largest); p_ind and
+ * p_cap are time-domain powers of the whole waveform; jc, js receive the
+ * fundamental's harmonics. */
 pic_status circuit_period_update(pic_ctx *ctx, const pic_circuit_override *ovr, pic_period_report *report,
                                  double *jc, double *js);
 
+/* The last circuit update's fields of retained order `order` (1 = the
+ * fundamental .. cfg->nharm + 1): its charge harmonics and I_cap^(m), p_port
+ * and p_cu of its own network state, p_cap_ph, V_p^(m), the target, applied
+ * and previous states, its source amplitude and phase and its residuals; the
+ * time-domain p_ind, p_cap are those of the whole waveform.  accepted = 0
+ * before the first update.  Synchronises.  PIC_EINVAL without
+ * cfg->circuit or for an order outside 1..nharm + 1. */
+pic_status circuit_order_report(pic_ctx *ctx, int32_t order, pic_period_report *report);
+
 /* Set the Thevenin source amplitude (V, > 0) and phase (rad) used by the
  * next circuit update of a coupled context (the controller, when on, starts
- * from this amplitude).  For scans of the operating point. */
+ * from this amplitude).  For scans of the operating point.  PIC_EINVAL with
+ * cfg->nharm > 0 (the orders' sources follow from the configuration). */
 pic_status pic_set_source(pic_ctx *ctx, double vg_amp, double vg_phase);
 
 /* Attach (net != NULL) or detach (NULL) a surrogate network: n_in = 4 N + 9
  * (turn current and voltage phasors, pressure, the eight moments), n_out =
  * 4 N (V_p and I_cap phasors), N <= 5, same stream as the context.  The
- * network stays owned by the caller and must outlive the attachment. */
+ * network stays owned by the caller and must outlive the attachment.
+ * PIC_EINVAL with cfg->nharm > 0. */
 pic_status pic_attach_surrogate(pic_ctx *ctx, mlp_ctx *net, const pic_surrogate_config *cfg);
 
 /* Copy the inductive-port data and the applied circuit state of a coupled
@@ -493,9 +528,10 @@ pic_status pic_get_stats(pic_ctx *ctx, pic_stats *out);
 void pic_destroy(pic_ctx *ctx);
 
 /* The message of the context's last failure; with ctx == NULL, why the
- * last pic_init on the calling thread failed ("null context" if it did
- * not).  The string stays valid until the next call on that context (or,
- * for NULL, the next pic_init on the thread). */
+ * last pic_workspace_bytes or pic_init on the calling thread failed ("null
+ * context" if it did not).  The string stays valid until the next call on
+ * that context (or, for NULL, the next pic_workspace_bytes / pic_init on the
+ * thread). */
 const char *pic_last_error(const pic_ctx *ctx);
 
 /* ------------------------------------------------------------------------

@@ -432,9 +432,11 @@ class Poisson:
 # ---------------------------------------------------------------------------
 class Harmonics:
     """Harmonic and power accumulators over one RF period: the projections
-    on cos(m th_n), sin(m th_n) of order m (the fundamental by default;
-    freq is then the order's frequency m f), the time-domain inductive power
-    and the trapezoid of V_k dQ_k."""
+    on cos(m th_n), sin(m th_n) of order m (the fundamental by default), the
+    time-domain inductive power and the trapezoid of V_k dQ_k.  freq is the
+    fundamental's: the period sampled is 1 / freq for every order, and the
+    order's charge harmonic gives I_cap at its own angular frequency
+    2 pi m freq."""
 
     def __init__(self, shape, nturns, nrf, freq, order=1):
         self.shape, self.N, self.nrf, self.freq, self.order = shape, nturns, nrf, freq, order
@@ -481,7 +483,7 @@ class Harmonics:
         V0, Q0 = self.first
         Vl, Ql = self.prev
         W = self.W + 0.5 * (V0 + Vl) * (Q0 - Ql)          # periodic closure
-        w = 2 * math.pi * self.freq
+        w = 2 * math.pi * (self.freq * self.order)
         Qc, Qs = 2.0 / N * self.Qc, 2.0 / N * self.Qs
         Icap = w * Qs + 1j * w * Qc
         Vhat = np.asarray(Vc) - 1j * np.asarray(Vs)
@@ -681,7 +683,7 @@ class OraclePIC:
     def reset_harmonics(self):
         self.harm = Harmonics(self.shape, self.wl.nturns, self.nrf, self.wl.freq)
         # orders 2..M of a multiharmonic circuit
-        self.harm_hi = [Harmonics(self.shape, self.wl.nturns, self.nrf, self.wl.freq * m, order=m)
+        self.harm_hi = [Harmonics(self.shape, self.wl.nturns, self.nrf, self.wl.freq, order=m)
                         for m in range(2, getattr(self, "M", 1) + 1)]
 
     def harmonic(self, n):

@@ -173,8 +173,13 @@ struct pic_ctx {
     double *U = nullptr;          // unit-current fields, nturns * nodes
     double *Ep = nullptr;         // plasma-only E_c^p and E_s^sto,p (2 * nodes)
     double *hb = nullptr;         // right-hand side of an inductive solve
-    CircuitDev *cd = nullptr;     // device circuit state (also the period finalisation)
-    CircuitDev cdh{};             // host copy after the last update
+    CircuitDev *cd = nullptr;     // device circuit state (also the period finalisation), one per retained order
+    CircuitDev cdh{};             // host copy of the fundamental's after the last update
+    // retained orders m = 1..M of the multiharmonic circuit (1: the
+    // fundamental alone); per-order arrays (cd, harm, U, Ep, d_ec / d_es,
+    // d_vc / d_vs, J_c / J_s) hold the orders one after the other
+    int M = 1;
+    std::vector<double> xp_ord;   // state applied during the completed period, per order (re then im, MAX_X each)
     int32_t *plist = nullptr, *pturn = nullptr;   // turn nodes in node order, their turn index
     double *gval = nullptr;       // s_k / A_k
     int nlist = 0;
@@ -476,6 +481,9 @@ static bool direct_candidate(const pic_config &f)
     return f.poisson_solver != PIC_POISSON_MULTIGRID && !f.implicit && f.nr >= 2 && f.nz >= 3;
 }
 
+// retained orders of the circuit (the fundamental and nharm above it)
+static int norders(const pic_config &f) { return 1 + (f.nharm > 0 ? f.nharm : 0); }
+
 static void layout(pic_ctx &c, Carver &cv)
 {
     const pic_config &f = c.cfg;
@@ -519,8 +527,9 @@ static void layout(pic_ctx &c, Carver &cv)
     c.phi = cv.take<double>(nodes);
     c.Q = cv.take<double>(nodes);
     c.I = cv.take<double>(nodes);
-    c.d_ec = cv.take<double>(nodes);
-    c.d_es = cv.take<double>(nodes);
+    const int M = norders(f);
+    c.d_ec = cv.take<double>((size_t)M * nodes);
+    c.d_es = cv.take<double>((size_t)M * nodes);
     c.d_tag = cv.take<int32_t>(nodes);
     if (f.dir_basis && f.nturns > 0) c.dbasis = cv.take<double>((size_t)f.nturns * nodes);
     if (f.implicit) {
@@ -530,8 +539,8 @@ static void layout(pic_ctx &c, Carver &cv)
         c.cs0 = cv.take<double>(nodes);
         c.cn0 = cv.take<double>(nodes);
     }
-    c.d_vc = cv.take<double>(MAX_TURNS);
-    c.d_vs = cv.take<double>(MAX_TURNS);
+    c.d_vc = cv.take<double>((size_t)M * MAX_TURNS);
+    c.d_vs = cv.take<double>((size_t)M * MAX_TURNS);
     if (direct_candidate(f)) {
         // direct solve of a separable operator (whether it separates is
         // decided at pic_init; the interior Dirichlet nodes size the plan)
@@ -558,12 +567,12 @@ static void layout(pic_ctx &c, Carver &cv)
             c.direct_carved = true;
         }
     }
-    c.Jc = cv.take<double>(nodes);
-    c.Jcc = cv.take<double>(nodes);
-    c.Js = cv.take<double>(nodes);
-    c.Jsc = cv.take<double>(nodes);
+    c.Jc = cv.take<double>((size_t)M * nodes);
+    c.Jcc = cv.take<double>((size_t)M * nodes);
+    c.Js = cv.take<double>((size_t)M * nodes);
+    c.Jsc = cv.take<double>((size_t)M * nodes);
     c.hpartial = cv.take<double>(harmonic_blocks(nodes));
-    c.harm = cv.take<HarmState>(1);
+    c.harm = cv.take<HarmState>(M);
     // multigrid: level 0 holds the CG correction (z) and residual (r); the
     // hierarchy stops at the first level of at most BOTTOM_NODES nodes, which
     // is solved with a dense inverse (inverted in FP64, applied from an FP32 copy)
@@ -628,7 +637,7 @@ static void layout(pic_ctx &c, Carver &cv)
     c.fk = cv.take<int32_t>(fmax);
     c.fc = cv.take<double>(fmax);
     c.Qk = cv.take<double>(MAX_TURNS);
-    c.cd = cv.take<CircuitDev>(1);
+    c.cd = cv.take<CircuitDev>(M);
     c.gval = cv.take<double>(MAX_TURNS);
     c.plist = cv.take<int32_t>(nturn_nodes + 1);
     c.pturn = cv.take<int32_t>(nturn_nodes + 1);
@@ -638,8 +647,8 @@ static void layout(pic_ctx &c, Carver &cv)
     if (f.circuit) {
         c.hgs = cv.take<MGState>(1);
         c.htag = cv.take<int32_t>(nodes);
-        c.U = cv.take<double>((size_t)f.nturns * nodes);
-        c.Ep = cv.take<double>(2 * (size_t)nodes);
+        c.U = cv.take<double>((size_t)M * f.nturns * nodes);
+        c.Ep = cv.take<double>(2 * (size_t)M * nodes);
         c.hb = cv.take<double>(nodes);
         c.hlv.n = nl;
         for (int l = 0; l < nl; ++l) {
@@ -699,6 +708,17 @@ static pic_status check_config(const pic_config *f, pic_ctx *c)
     if (f->birth_capacity < 0) return fail(c, PIC_EINVAL, "birth_capacity < 0");
     if (f->implicit && (f->rf_bfield || f->bfield[0] != 0.0 || f->bfield[1] != 0.0 || f->bfield[2] != 0.0))
         return fail(c, PIC_EINVAL, "the direct-implicit update runs without magnetic field");
+    if (f->nharm < 0 || f->nharm > MAX_HARM - 1)
+        return fail(c, PIC_EINVAL, "nharm outside 0..%d", MAX_HARM - 1);
+    if (f->nharm > 0) {
+        if (!f->circuit) return fail(c, PIC_EINVAL, "the multiharmonic circuit needs circuit coupling");
+        if (f->field_mode != PIC_FIELD_MQS)
+            return fail(c, PIC_EINVAL, "the multiharmonic circuit needs the magnetoquasistatic inductive operator");
+        if (f->rf_bfield) return fail(c, PIC_EINVAL, "the RF magnetic field is formed from the fundamental only");
+        for (int q = 0; q < f->nharm; ++q)
+            if (!(f->harm_ratio[q] > 0.0 && std::isfinite(f->harm_ratio[q])) || !std::isfinite(f->harm_phase[q]))
+                return fail(c, PIC_EINVAL, "harm_ratio[%d] must be positive and harm_phase[%d] finite", q, q);
+    }
     return PIC_OK;
 }
 
@@ -713,8 +733,12 @@ static pic_status prepare_host(pic_ctx &c, const pic_config *f)
     c.es.assign(nodes, 0.0);
     if (f->ec) c.ec.assign(f->ec, f->ec + nodes);
     if (f->es_sto) c.es.assign(f->es_sto, f->es_sto + nodes);
-    c.vc.assign(MAX_TURNS, 0.0);
-    c.vs.assign(MAX_TURNS, 0.0);
+    c.M = norders(*f);
+    c.vc.assign((size_t)c.M * MAX_TURNS, 0.0);
+    c.vs.assign((size_t)c.M * MAX_TURNS, 0.0);
+    c.ec.resize((size_t)c.M * nodes, 0.0);
+    c.es.resize((size_t)c.M * nodes, 0.0);
+    c.xp_ord.assign((size_t)c.M * 2 * MAX_X, 0.0);
     for (int k = 0; k < f->nturns; ++k) {
         c.vc[k] = f->turn_vc ? f->turn_vc[k] : 0.0;
         c.vs[k] = f->turn_vs ? f->turn_vs[k] : 0.0;
@@ -754,14 +778,21 @@ static pic_status prepare_host(pic_ctx &c, const pic_config *f)
     return PIC_OK;
 }
 
+// message of the last failed pic_workspace_bytes / pic_init of this thread
+// (pic_last_error(NULL))
+static thread_local std::string init_error;
+
 extern "C" pic_status pic_workspace_bytes(const pic_config *cfg, size_t *bytes)
 {
     if (!bytes) return PIC_EINVAL;
     pic_ctx c;
+    init_error.clear();
     pic_status st = check_config(cfg, &c);
-    if (st) return st;
-    st = prepare_host(c, cfg);
-    if (st) return st;
+    if (!st) st = prepare_host(c, cfg);
+    if (st) {
+        init_error = c.err;
+        return st;
+    }
     Carver cv{nullptr};
     layout(c, cv);
     *bytes = cv.off + 256;
@@ -809,10 +840,24 @@ template <typename T> static void sort_species(pic_ctx &c, int s)
     c.cur[s] = to;
 }
 
+// cos, sin of m th_n for the retained orders m = 1..M (Eq. et_reconstruct
+// at every order's frequency)
+static Orders step_orders(const pic_ctx &c, int64_t n)
+{
+    const double th = TWO_PI * (double)(n % c.nrf) / (double)c.nrf;
+    Orders o{};
+    o.n = c.M;
+    for (int m = 0; m < c.M; ++m) {
+        o.cs[m] = std::cos((m + 1) * th);
+        o.sn[m] = std::sin((m + 1) * th);
+    }
+    return o;
+}
+
 template <typename T> static void stage(pic_ctx &c, int64_t n)
 {
     const double th = TWO_PI * (double)(n % c.nrf) / (double)c.nrf;
-    launch_stage<T>(c.phi, c.d_ec, c.d_es, std::cos(th), std::sin(th),
+    launch_stage<T>(c.phi, c.d_ec, c.d_es, step_orders(c, n),
                     reinterpret_cast<typename Field4<T>::type *>(c.ef), c.accJ, c.accQ, true, c.g, c.stream);
     if (c.eb)
         launch_stage_b<T>(c.d_ec, c.d_es, std::cos(th), std::sin(th), 1.0 / (TWO_PI * c.cfg.freq),
@@ -965,7 +1010,7 @@ static pic_status solve(pic_ctx &c, int64_t n, double rtol, int max_cycles, pic_
     c.run = (n == c.last_solve + 1 && !full && !info && !c.mg_restart) ? c.run + 1 : 0;
     c.mg_restart = false;
     const int order = c.run >= 3 ? 2 : c.run >= 2 ? 1 : 0;
-    launch_pcg_begin(L0, v, c.d_tag, c.d_vc, c.d_vs, std::cos(th), std::sin(th), c.mgs, c.phi_prev, order, c.stream,
+    launch_pcg_begin(L0, v, c.d_tag, c.d_vc, c.d_vs, step_orders(c, n), c.mgs, c.phi_prev, order, c.stream,
                      c.dbasis, c.cfg.nturns);
     c.last_solve = n;
     const int np = pcg_blocks(L0.nodes);
@@ -1048,11 +1093,9 @@ static pic_status upload_direct(pic_ctx &c, const SeparablePlan &sp)
 // and check kernels (scale as for the iterative solve).
 static pic_status solve_direct(pic_ctx &c, int64_t n, double rtol, pic_solve_info *info)
 {
-    const double th = TWO_PI * (double)(n % c.nrf) / (double)c.nrf;
     timer_start(c, c.t_poisson);
     DirectArgs a = c.da;
-    a.cth = std::cos(th);
-    a.sth = std::sin(th);
+    a.o = step_orders(c, n);
     launch_direct_solve(a, c.stream);
     c.last_solve = n;
     c.run = 0;
@@ -1064,7 +1107,7 @@ static pic_status solve_direct(pic_ctx &c, int64_t n, double rtol, pic_solve_inf
     if (info) {
         const MGLevel &L0 = c.lv.L[0];
         const PCGVec v{c.phi, c.Q, c.pr, c.pz, c.pp, c.pAp};
-        launch_pcg_begin(L0, v, c.d_tag, c.d_vc, c.d_vs, a.cth, a.sth, c.mgs, nullptr, 0, c.stream, c.dbasis,
+        launch_pcg_begin(L0, v, c.d_tag, c.d_vc, c.d_vs, a.o, c.mgs, nullptr, 0, c.stream, c.dbasis,
                          c.cfg.nturns);
         launch_pcg_resid(L0, v, c.mgpartial, c.stream);
         launch_pcg_check(c.mgs, c.mgpartial, pcg_blocks(L0.nodes), rtol, true, c.stream);
@@ -1154,7 +1197,7 @@ static pic_status helm_solve(pic_ctx &c, double *x, int *cycles, double *rel, do
     const PCGVec v{x, c.hb, c.pr, c.pz, c.pp, c.pAp};
     if (rtol <= 0.0) rtol = c.cfg.helm_rtol;
     maxc = std::min(maxc > 0 ? maxc : c.cfg.helm_max_cycles, MAX_CG);
-    launch_pcg_begin(L0, v, c.htag, nullptr, nullptr, 0.0, 0.0, c.hgs, nullptr, 0, c.stream);
+    launch_pcg_begin(L0, v, c.htag, nullptr, nullptr, Orders{1, {0.0}, {0.0}}, c.hgs, nullptr, 0, c.stream);
     launch_pcg_resid(L0, v, c.mgpartial, c.stream);
     launch_pcg_check(c.hgs, c.mgpartial, pcg_blocks(L0.nodes), rtol, true, c.stream);
     MGState s{};
@@ -1207,6 +1250,19 @@ static void helm_operator(const pic_ctx &c, Coeffs &co, std::vector<uint8_t> &di
         }
 }
 
+// Next period's azimuthal field of every order from its plasma-only part
+// and the applied turn currents (Eq. compose)
+static void compose_fields(pic_ctx &c)
+{
+    const int nodes = c.g.nodes;
+    const size_t un = (size_t)c.cfg.nturns * nodes;
+    for (int m = 0; m < c.M; ++m) {
+        const double *ep = c.Ep + (size_t)2 * m * nodes;
+        launch_compose(ep, ep + nodes, c.U + m * un, nodes, c.cd + m, c.d_ec + (size_t)m * nodes,
+                       c.d_es + (size_t)m * nodes, nodes, c.stream);
+    }
+}
+
 // Initialisation of the coupling (Sec. 2.2 and the workflow's
 // initialisation): shape functions, unit fields, Z_vac, network constants,
 // the first applied state, its turn potentials and azimuthal field.
@@ -1251,26 +1307,34 @@ static pic_status circuit_init(pic_ctx &c)
         HIPCHK(&c, cpy(c.stream, c.pturn, lturn.data(), lturn.size() * 4, hipMemcpyHostToDevice));
     }
     HIPCHK(&c, cpy(c.stream, c.gval, g.data(), MAX_TURNS * 8, hipMemcpyHostToDevice));
+    h.order = 1;
+    h.vg_ratio = 1.0;
     if (!f.circuit) {
         HIPCHK(&c, cpy(c.stream, c.cd, &h, sizeof h, hipMemcpyHostToDevice));
         return PIC_OK;
     }
-    // network constants (Eqs. zsource, skin, zturn_field)
-    h.alpha = f.alpha;
-    h.zs_re = f.r_g + f.r_m;
-    h.zs_im = w * f.l_m - (f.c_m > 0.0 ? 1.0 / (w * f.c_m) : 0.0);
+    // network constants (Eqs. zsource, skin, zturn_field) of order m (1 =
+    // the fundamental) at its angular frequency m w
     const double rho = f.rho20 * (1.0 + f.alpha_cu * (f.temp_c - 20.0));
-    const double delta = std::sqrt(2.0 * rho / (w * f.mu0));
-    for (int k = 0; k < N; ++k) {
-        if (f.rrf_mode == PIC_RRF_SKIN) {
-            const double rw = std::sqrt(c.area[k] / M_PI), rmean = rsum[k] / count[k];
-            const double inner = std::max(rw - delta, 0.0);
-            h.rrf[k] = rho * TWO_PI * rmean / (M_PI * (rw * rw - inner * inner));
-        } else {
-            h.rrf[k] = f.r_rf[k];
+    auto network_constants = [&](CircuitDev &o, int m) {
+        const double wm = m == 1 ? w : TWO_PI * (f.freq * m);
+        o.omega = wm;
+        o.alpha = f.alpha;
+        o.zs_re = f.r_g + f.r_m;
+        o.zs_im = wm * f.l_m - (f.c_m > 0.0 ? 1.0 / (wm * f.c_m) : 0.0);
+        const double delta = std::sqrt(2.0 * rho / (wm * f.mu0));
+        for (int k = 0; k < N; ++k) {
+            if (f.rrf_mode == PIC_RRF_SKIN) {
+                const double rw = std::sqrt(c.area[k] / M_PI), rmean = rsum[k] / count[k];
+                const double inner = std::max(rw - delta, 0.0);
+                o.rrf[k] = rho * TWO_PI * rmean / (M_PI * (rw * rw - inner * inner));
+            } else {
+                o.rrf[k] = f.r_rf[k];
+            }
+            o.cstray[k] = f.c_stray ? f.c_stray[k] : 0.0;
         }
-        h.cstray[k] = f.c_stray ? f.c_stray[k] : 0.0;
-    }
+    };
+    network_constants(h, 1);
     h.controller = f.controller;
     h.vg_from_target = f.vg_from_target;
     h.p_target = f.p_target;
@@ -1285,6 +1349,20 @@ static pic_status circuit_init(pic_ctx &c)
     h.vg_phase = f.vg_phase;
     h.pressure = f.ngas * f.tgas_ev * f.qe;
     HIPCHK(&c, cpy(c.stream, c.cd, &h, sizeof h, hipMemcpyHostToDevice));
+    // the orders above the fundamental: the same network at m w without a
+    // controller of their own; the source of order m is rho_m exp(i phi_m)
+    // times the fundamental's
+    for (int m = 2; m <= c.M; ++m) {
+        CircuitDev o = h;
+        network_constants(o, m);
+        o.order = m;
+        o.controller = 0;
+        o.vg_from_target = 0;
+        o.vg_ratio = f.harm_ratio[m - 2];
+        o.vg_amp = f.vg_amp * o.vg_ratio;
+        o.vg_phase = f.vg_phase + f.harm_phase[m - 2];
+        HIPCHK(&c, cpy(c.stream, c.cd + (m - 1), &o, sizeof o, hipMemcpyHostToDevice));
+    }
     // inductive operator hierarchy
     Coeffs co;
     std::vector<uint8_t> dir;
@@ -1294,31 +1372,41 @@ static pic_status circuit_init(pic_ctx &c)
     std::vector<int32_t> htag(nodes);
     for (int n = 0; n < nodes; ++n) htag[n] = dir[n] ? 0 : -1;
     HIPCHK(&c, cpy(c.stream, c.htag, htag.data(), nodes * 4, hipMemcpyHostToDevice));
-    HIPCHK(&c, mset(c.stream, c.U, 0, (size_t)N * nodes * 8));
+    const size_t un = (size_t)N * nodes;
+    HIPCHK(&c, mset(c.stream, c.U, 0, c.M * un * 8));
     // manufactured boundary values of the unit fields (the solves keep the
     // Dirichlet entries of their start value)
     if (f.unit_bvals) {
-        std::vector<double> ub((size_t)N * nodes, 0.0);
+        std::vector<double> ub(un, 0.0);
         for (int k = 0; k < N; ++k)
             for (int n = 0; n < nodes; ++n)
                 if (dir[n]) ub[(size_t)k * nodes + n] = f.unit_bvals[(size_t)k * nodes + n];
-        HIPCHK(&c, cpy(c.stream, c.U, ub.data(), ub.size() * 8, hipMemcpyHostToDevice));
+        for (int m = 0; m < c.M; ++m)
+            HIPCHK(&c, cpy(c.stream, c.U + m * un, ub.data(), ub.size() * 8, hipMemcpyHostToDevice));
     }
-    HIPCHK(&c, mset(c.stream, c.Ep, 0, 2 * (size_t)nodes * 8));
+    HIPCHK(&c, mset(c.stream, c.Ep, 0, 2 * (size_t)c.M * nodes * 8));
     HIPCHK(&c, mset(c.stream, c.hgs, 0, sizeof(MGState)));
-    // unit-current fields K U_k = g_k (Eq. unitfield)
-    const double mw = f.mu0 * w;
-    for (int k = 0; k < N; ++k) {
-        launch_unit_rhs(c.d_tag, k, g[k], c.hlv.L[0].dir, mw, c.hb, c.g, c.stream);
-        st = helm_solve(c, c.U + (size_t)k * nodes, nullptr, nullptr);
-        if (st) return st;
+    // unit-current fields K U_k = g_k (Eq. unitfield) at every order's
+    // frequency (the magnetoquasistatic operator is the same for all; the
+    // right-hand side scales with m w), and Z_vac of every order (Eq. zvac)
+    for (int m = 1; m <= c.M; ++m) {
+        const double mw = f.mu0 * (m == 1 ? w : TWO_PI * (f.freq * m));
+        double *Um = c.U + (m - 1) * un;
+        for (int k = 0; k < N; ++k) {
+            launch_unit_rhs(c.d_tag, k, g[k], c.hlv.L[0].dir, mw, c.hb, c.g, c.stream);
+            st = helm_solve(c, Um + (size_t)k * nodes, nullptr, nullptr);
+            if (st) return st;
+        }
+        launch_project(Um, N, nodes, c.plist, c.pturn, c.nlist, c.gval, N,
+                       reinterpret_cast<double *>(reinterpret_cast<char *>(c.cd + (m - 1)) + offsetof(CircuitDev, mvac)),
+                       MAX_TURNS, c.g, c.stream);
     }
-    // Z_vac (Eq. zvac), first state, turn potentials and field
-    launch_project(c.U, N, nodes, c.plist, c.pturn, c.nlist, c.gval, N,
-                   reinterpret_cast<double *>(reinterpret_cast<char *>(c.cd) + offsetof(CircuitDev, mvac)), MAX_TURNS,
-                   c.g, c.stream);
-    launch_circuit(c.cd, c.harm, c.d_vc, c.d_vs, 0, c.stream);
-    launch_compose(c.Ep, c.Ep + nodes, c.U, nodes, c.cd, c.d_ec, c.d_es, nodes, c.stream);
+    // first state, turn potentials and field
+    if (c.M == 1)
+        launch_circuit(c.cd, c.harm, c.d_vc, c.d_vs, 0, c.stream);
+    else
+        launch_circuit_orders(c.cd, c.M, c.d_vc, c.d_vs, 0, c.stream);
+    compose_fields(c);
     HIPCHK(&c, cpy(c.stream, &h, c.cd, sizeof h, hipMemcpyDeviceToHost));
     if (h.singular) return fail(&c, PIC_EINVAL, "singular circuit network");
     return PIC_OK;
@@ -1341,21 +1429,22 @@ template <typename T> static pic_status init_impl(pic_ctx &c)
     HIPCHK(&c, hipMemsetAsync(c.accW, 0, 2 * (size_t)nodes * sizeof(long long), st));
     HIPCHK(&c, hipMemsetAsync(c.phi, 0, nodes * sizeof(double), st));
     HIPCHK(&c, hipMemsetAsync(c.I, 0, nodes * sizeof(double), st));
-    HIPCHK(&c, hipMemsetAsync(c.Jc, 0, nodes * sizeof(double), st));
-    HIPCHK(&c, hipMemsetAsync(c.Jcc, 0, nodes * sizeof(double), st));
-    HIPCHK(&c, hipMemsetAsync(c.Js, 0, nodes * sizeof(double), st));
-    HIPCHK(&c, hipMemsetAsync(c.Jsc, 0, nodes * sizeof(double), st));
-    HIPCHK(&c, hipMemsetAsync(c.harm, 0, sizeof(HarmState), st));
+    const size_t mn = (size_t)c.M * nodes;
+    HIPCHK(&c, hipMemsetAsync(c.Jc, 0, mn * sizeof(double), st));
+    HIPCHK(&c, hipMemsetAsync(c.Jcc, 0, mn * sizeof(double), st));
+    HIPCHK(&c, hipMemsetAsync(c.Js, 0, mn * sizeof(double), st));
+    HIPCHK(&c, hipMemsetAsync(c.Jsc, 0, mn * sizeof(double), st));
+    HIPCHK(&c, hipMemsetAsync(c.harm, 0, c.M * sizeof(HarmState), st));
     HIPCHK(&c, hipMemsetAsync(c.Qk, 0, MAX_TURNS * sizeof(double), st));
     HIPCHK(&c, hipMemsetAsync(c.mgs, 0, sizeof(MGState), st));
-    HIPCHK(&c, hipMemcpyAsync(c.d_ec, c.ec.data(), nodes * sizeof(double), hipMemcpyHostToDevice, st));
-    HIPCHK(&c, hipMemcpyAsync(c.d_es, c.es.data(), nodes * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(&c, hipMemcpyAsync(c.d_ec, c.ec.data(), mn * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(&c, hipMemcpyAsync(c.d_es, c.es.data(), mn * sizeof(double), hipMemcpyHostToDevice, st));
     HIPCHK(&c, hipMemcpyAsync(c.d_tag, c.tag.data(), nodes * sizeof(int32_t), hipMemcpyHostToDevice, st));
     if (c.dbasis)
         HIPCHK(&c, hipMemcpyAsync(c.dbasis, f.dir_basis, (size_t)f.nturns * nodes * sizeof(double),
                                   hipMemcpyHostToDevice, st));
-    HIPCHK(&c, hipMemcpyAsync(c.d_vc, c.vc.data(), MAX_TURNS * sizeof(double), hipMemcpyHostToDevice, st));
-    HIPCHK(&c, hipMemcpyAsync(c.d_vs, c.vs.data(), MAX_TURNS * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(&c, hipMemcpyAsync(c.d_vc, c.vc.data(), c.M * MAX_TURNS * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(&c, hipMemcpyAsync(c.d_vs, c.vs.data(), c.M * MAX_TURNS * sizeof(double), hipMemcpyHostToDevice, st));
 
     // multigrid hierarchy: finite-volume fine operator, Galerkin coarse levels
     {
@@ -1492,9 +1581,6 @@ template <typename T> static pic_status init_impl(pic_ctx &c)
     return PIC_OK;
 }
 
-// why the last pic_init on this thread failed (pic_last_error(NULL))
-static thread_local std::string init_error;
-
 extern "C" pic_status pic_init(const pic_config *cfg, void *workspace, size_t workspace_bytes, void *stream,
                                pic_ctx **out)
 {
@@ -1581,8 +1667,9 @@ extern "C" pic_status pic_gather_push(pic_ctx *c, int64_t n)
 // joins the next step's predicted deposit).
 template <typename T> static void implicit_correct_collide(pic_ctx &c, int64_t n)
 {
-    launch_stage<T>(c.phi, c.d_ec, c.d_es, 1.0, 0.0, reinterpret_cast<typename Field4<T>::type *>(c.ef), c.accJ,
-                    c.accQ, false, c.g, c.stream);
+    // the corrector takes E_r, E_z only
+    launch_stage<T>(c.phi, c.d_ec, c.d_es, Orders{1, {1.0}, {0.0}},
+                    reinterpret_cast<typename Field4<T>::type *>(c.ef), c.accJ, c.accQ, false, c.g, c.stream);
     launch_correct<T>(pass_args<T>(c, 0, n), pass_args<T>(c, 1, n), c.cfg.capacity[0], c.cfg.capacity[1], c.stream);
     run_collide<T>(c, n);
     run_births<T>(c, false);
@@ -1636,15 +1723,18 @@ extern "C" pic_status pic_deposit(pic_ctx *c, int64_t n1)
 
 // one plasma-only inductive field from the open period's harmonics:
 // which = 0: K E_c^p = J_s / V, which = 1: K E_s^sto,p = J_c / V
-static pic_status plasma_field(pic_ctx &c, int which, double rtol, int max_cycles, int *cycles, double *rel)
+// Plasma-only field of order m (0: the fundamental) from that order's
+// current harmonic, at its frequency (m + 1) w
+static pic_status plasma_field(pic_ctx &c, int which, double rtol, int max_cycles, int *cycles, double *rel, int m = 0)
 {
-    const double mw = c.cfg.mu0 * TWO_PI * c.cfg.freq;
+    const double mw = c.cfg.mu0 * (m == 0 ? TWO_PI * c.cfg.freq : TWO_PI * (c.cfg.freq * (m + 1)));
     const uint8_t *hdir = c.hlv.L[0].dir;
+    const size_t o = (size_t)m * c.g.nodes;
     if (which == 0)
-        launch_helm_rhs(c.Js, c.Jsc, 2.0 / c.nrf, hdir, mw, c.hb, c.g, c.stream);
+        launch_helm_rhs(c.Js + o, c.Jsc + o, 2.0 / c.nrf, hdir, mw, c.hb, c.g, c.stream);
     else
-        launch_helm_rhs(c.Jc, c.Jcc, 2.0 / c.nrf, hdir, mw, c.hb, c.g, c.stream);
-    return helm_solve(c, c.Ep + (size_t)which * c.g.nodes, cycles, rel, rtol, max_cycles);
+        launch_helm_rhs(c.Jc + o, c.Jcc + o, 2.0 / c.nrf, hdir, mw, c.hb, c.g, c.stream);
+    return helm_solve(c, c.Ep + (size_t)(2 * m + which) * c.g.nodes, cycles, rel, rtol, max_cycles);
 }
 
 extern "C" pic_status poisson_solve_rz(pic_ctx *c, int64_t n, int32_t op, double rtol, int32_t max_cycles,
@@ -1679,10 +1769,9 @@ extern "C" pic_status harmonic_accumulate(pic_ctx *c, int64_t n)
     if (n != c->last_push || c->last_harm == n)
         return fail(c, PIC_ESTATE, "harmonic_accumulate(%lld) out of order", (long long)n);
     const pic_config &f = c->cfg;
-    const double th = TWO_PI * (double)(n % c->nrf) / (double)c->nrf;
     const double cj0 = f.q[0] * f.w[0] * c->sc[0].vref / c->jscale, cj1 = f.q[1] * f.w[1] * c->sc[1].vref / c->jscale;
-    launch_harmonic(c->accJ, cj0, cj1, c->d_ec, c->d_es, std::cos(th), std::sin(th), c->I, c->Jc, c->Jcc, c->Js,
-                    c->Jsc, c->hpartial, c->harm, c->Qk, c->d_vc, c->d_vs, f.nturns, c->g.nodes, c->stream);
+    launch_harmonic(c->accJ, cj0, cj1, c->d_ec, c->d_es, step_orders(*c, n), c->I, c->Jc, c->Jcc, c->Js, c->Jsc,
+                    c->hpartial, c->harm, c->Qk, c->d_vc, c->d_vs, f.nturns, c->g.nodes, c->stream);
     c->last_harm = n;
     return hipGetLastError() == hipSuccess ? PIC_OK : fail(c, PIC_EDEVICE, "kernel launch failed");
 }
@@ -1718,6 +1807,7 @@ extern "C" pic_status pic_set_source(pic_ctx *c, double vg_amp, double vg_phase)
 {
     if (!c) return PIC_EINVAL;
     if (!c->cfg.circuit) return fail(c, PIC_EINVAL, "context without circuit coupling");
+    if (c->M > 1) return fail(c, PIC_EINVAL, "the multiharmonic circuit sets its sources from the configuration");
     if (!(vg_amp > 0.0)) return fail(c, PIC_EINVAL, "vg_amp must be positive");
     char *d = reinterpret_cast<char *>(c->cd);
     HIPCHK(c, cpy(c->stream, d + offsetof(CircuitDev, vg_amp), &vg_amp, 8, hipMemcpyHostToDevice));
@@ -1733,6 +1823,7 @@ extern "C" pic_status pic_attach_surrogate(pic_ctx *c, mlp_ctx *net, const pic_s
         return PIC_OK;
     }
     if (!c->cfg.circuit) return fail(c, PIC_EINVAL, "surrogate needs a coupled context");
+    if (c->M > 1) return fail(c, PIC_EINVAL, "the surrogate predicts the fundamental's loads only");
     if (!sc || !(sc->err_max > 0.0) || !(sc->tol > 0.0) || sc->max_iter < 1 || sc->max_iter > SUR_MAX_ITER)
         return fail(c, PIC_EINVAL, "surrogate settings invalid (max_iter 1..%d)", SUR_MAX_ITER);
     const int N = c->cfg.nturns;
@@ -1757,12 +1848,12 @@ extern "C" pic_status pic_attach_surrogate(pic_ctx *c, mlp_ctx *net, const pic_s
 
 static pic_status reset_period(pic_ctx *c)
 {
-    const int nodes = c->g.nodes;
-    HIPCHK(c, mset(c->stream, c->Jc, 0, nodes * 8));
-    HIPCHK(c, mset(c->stream, c->Jcc, 0, nodes * 8));
-    HIPCHK(c, mset(c->stream, c->Js, 0, nodes * 8));
-    HIPCHK(c, mset(c->stream, c->Jsc, 0, nodes * 8));
-    HIPCHK(c, mset(c->stream, c->harm, 0, sizeof(HarmState)));
+    const size_t mn = (size_t)c->M * c->g.nodes;
+    HIPCHK(c, mset(c->stream, c->Jc, 0, mn * 8));
+    HIPCHK(c, mset(c->stream, c->Jcc, 0, mn * 8));
+    HIPCHK(c, mset(c->stream, c->Js, 0, mn * 8));
+    HIPCHK(c, mset(c->stream, c->Jsc, 0, mn * 8));
+    HIPCHK(c, mset(c->stream, c->harm, 0, c->M * sizeof(HarmState)));
     return PIC_OK;
 }
 
@@ -1778,6 +1869,7 @@ extern "C" pic_status circuit_period_update(pic_ctx *c, const pic_circuit_overri
         return fail(c, PIC_EINVAL, "a coupled context derives turn potentials and field itself");
     if (loads && !coupled) return fail(c, PIC_EINVAL, "prescribed loads need a coupled context");
     if (loads && c->net) return fail(c, PIC_EINVAL, "prescribed loads and an attached surrogate exclude each other");
+    if (loads && c->M > 1) return fail(c, PIC_EINVAL, "prescribed loads are for a single-frequency circuit");
     pic_status st = sticky(c);
     if (st) return st;
     int32_t samples = 0;
@@ -1796,14 +1888,21 @@ extern "C" pic_status circuit_period_update(pic_ctx *c, const pic_circuit_overri
     }
     timer_start(*c, c->t_circuit);
     if (coupled) {
-        // plasma-only fields from the current harmonics (Eq. helmholtz_two_real)
-        for (int q = 0; q < 2; ++q) {
-            st = plasma_field(*c, q, 0.0, 0, &c->helm_cycles[q], &c->helm_rel[q]);
-            if (st) return st;
+        // plasma-only fields from the current harmonics of every order
+        // (Eq. helmholtz_two_real at the order's frequency), projected on
+        // the turns
+        for (int m = 0; m < c->M; ++m) {
+            for (int q = 0; q < 2; ++q) {
+                int cyc = 0;
+                double rel = 0.0;
+                st = plasma_field(*c, q, 0.0, 0, m == 0 ? &c->helm_cycles[q] : &cyc, m == 0 ? &c->helm_rel[q] : &rel,
+                                  m);
+                if (st) return st;
+            }
+            launch_project(c->Ep + (size_t)2 * m * nodes, 2, nodes, c->plist, c->pturn, c->nlist, c->gval, K,
+                           reinterpret_cast<double *>(reinterpret_cast<char *>(c->cd + m) + offsetof(CircuitDev, proj)),
+                           2, c->g, c->stream);
         }
-        launch_project(c->Ep, 2, nodes, c->plist, c->pturn, c->nlist, c->gval, K,
-                       reinterpret_cast<double *>(reinterpret_cast<char *>(c->cd) + offsetof(CircuitDev, proj)), 2,
-                       c->g, c->stream);
         // plasma moments of the completed period (surrogate features, report)
         {
             const pic_config &f = c->cfg;
@@ -1817,10 +1916,11 @@ extern "C" pic_status circuit_period_update(pic_ctx *c, const pic_circuit_overri
                                        c->g, c->stream);
         }
         // the state applied during the completed period, for the report
-        HIPCHK(c, cpy(c->stream, c->cdh.x_re, reinterpret_cast<char *>(c->cd) + offsetof(CircuitDev, x_re),
-                      sizeof(c->cdh.x_re) + sizeof(c->cdh.x_im), hipMemcpyDeviceToHost));
-        double xp[2 * MAX_X];
-        std::memcpy(xp, c->cdh.x_re, sizeof xp);
+        for (int m = 0; m < c->M; ++m)
+            HIPCHK(c, cpy(c->stream, c->xp_ord.data() + (size_t)2 * MAX_X * m,
+                          reinterpret_cast<char *>(c->cd + m) + offsetof(CircuitDev, x_re),
+                          sizeof(c->cdh.x_re) + sizeof(c->cdh.x_im), hipMemcpyDeviceToHost));
+        const double *xp = c->xp_ord.data();
         if (loads) {
             // prescribed loads, taken by the update kernel in place of the measured ones
             CircuitDev &h = c->cdh;
@@ -1838,10 +1938,17 @@ extern "C" pic_status circuit_period_update(pic_ctx *c, const pic_circuit_overri
         if (c->net) {
             st = surrogate_update(*c);
             if (st) return st;
-        } else {
+        } else if (c->M == 1) {
             launch_circuit(c->cd, c->harm, c->d_vc, c->d_vs, 1, c->stream);
+        } else {
+            // every order finalises its harmonics and measures its loads,
+            // then the joint update (controller on the total port power)
+            for (int m = 0; m < c->M; ++m)
+                launch_circuit(c->cd + m, c->harm + m, c->d_vc + m * MAX_TURNS, c->d_vs + m * MAX_TURNS, 3,
+                               c->stream);
+            launch_circuit_orders(c->cd, c->M, c->d_vc, c->d_vs, 1, c->stream);
         }
-        launch_compose(c->Ep, c->Ep + nodes, c->U, nodes, c->cd, c->d_ec, c->d_es, nodes, c->stream);
+        compose_fields(*c);
         if (rep)
             for (int r = 0; r < 2 * K + 1; ++r) {
                 rep->xp_re[r] = xp[r];
@@ -1871,8 +1978,17 @@ extern "C" pic_status circuit_period_update(pic_ctx *c, const pic_circuit_overri
             rep->eps_bal = h.eps_bal;
             rep->kcl = h.kcl;
             rep->kvl = h.kvl;
+            if (c->M > 1) {   // totals over the retained orders
+                rep->p_port = h.tot_p_port;
+                rep->p_cu = h.tot_p_cu;
+                rep->p_cap_ph = h.tot_p_cap_ph;
+                rep->eps_bal = h.tot_eps_bal;
+                rep->kcl = h.tot_kcl;
+                rep->kvl = h.tot_kvl;
+            }
             rep->vg_old = h.vg_old;
             rep->vg_amp = h.vg_amp;
+            rep->vg_phase = h.vg_phase;
             rep->pf = h.pf;
             rep->pc = h.pc;
             for (int k = 0; k < K; ++k) {
@@ -1936,6 +2052,51 @@ extern "C" pic_status circuit_period_update(pic_ctx *c, const pic_circuit_overri
     return reset_period(c);
 }
 
+extern "C" pic_status circuit_order_report(pic_ctx *c, int32_t order, pic_period_report *rep)
+{
+    if (!c || !rep) return PIC_EINVAL;
+    if (!c->cfg.circuit) return fail(c, PIC_EINVAL, "context without circuit coupling");
+    if (order < 1 || order > c->M) return fail(c, PIC_EINVAL, "order %d outside 1..%d", order, c->M);
+    pic_status st = sticky(c);
+    if (st) return st;
+    CircuitDev h;
+    HIPCHK(c, cpy(c->stream, &h, c->cd + (order - 1), sizeof h, hipMemcpyDeviceToHost));
+    std::memset(rep, 0, sizeof *rep);
+    const int K = c->cfg.nturns;
+    rep->samples = h.samples;
+    rep->accepted = h.samples == c->nrf;
+    rep->p_ind = h.p_ind;
+    rep->p_cap = h.p_cap;
+    rep->p_cap_ph = h.p_cap_ph;
+    rep->p_port = h.p_port;
+    rep->p_cu = h.p_cu;
+    rep->eps_bal = h.eps_bal;
+    rep->kcl = h.kcl;
+    rep->kvl = h.kvl;
+    rep->vg_old = h.vg_old;
+    rep->vg_amp = h.vg_amp;
+    rep->vg_phase = h.vg_phase;
+    for (int k = 0; k < K; ++k) {
+        rep->qc[k] = h.qc[k];
+        rep->qs[k] = h.qs[k];
+        rep->icap_re[k] = h.icap_re[k];
+        rep->icap_im[k] = h.icap_im[k];
+        rep->vp_re[k] = h.vp_re[k];
+        rep->vp_im[k] = h.vp_im[k];
+    }
+    const double *xp = c->xp_ord.data() + (size_t)2 * MAX_X * (order - 1);
+    for (int r = 0; r < 2 * K + 1; ++r) {
+        rep->xt_re[r] = h.xt_re[r];
+        rep->xt_im[r] = h.xt_im[r];
+        rep->x_re[r] = h.x_re[r];
+        rep->x_im[r] = h.x_im[r];
+        rep->xp_re[r] = xp[r];
+        rep->xp_im[r] = xp[MAX_X + r];
+    }
+    rep->pressure = h.pressure;
+    return PIC_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Checkpoint / restore of the whole time-dependent state at a step boundary
 // (the restart of the paper's Appendix A checks).  Everything pic_init
@@ -1951,6 +2112,7 @@ struct CkptHead {
     int64_t capacity[2], count[2];
     int64_t last_push, last_harm, last_mcc, last_solve;
     int32_t run, mg_budget, mg_fresh, mg_restart;
+    int32_t norders, pad;
     double qscale, jscale;
     uint64_t total;
 };
@@ -2002,18 +2164,19 @@ static std::vector<Seg> state_segments(pic_ctx &c, const int64_t count[2])
     v.push_back({c.I, nb});
     v.push_back({c.accS, 2 * nb});
     v.push_back({c.Qk, MAX_TURNS * sizeof(double)});
-    v.push_back({c.Jc, nb});
-    v.push_back({c.Jcc, nb});
-    v.push_back({c.Js, nb});
-    v.push_back({c.Jsc, nb});
-    v.push_back({c.harm, sizeof(HarmState)});
-    v.push_back({c.d_vc, MAX_TURNS * sizeof(double)});
-    v.push_back({c.d_vs, MAX_TURNS * sizeof(double)});
-    v.push_back({c.d_ec, nb});
-    v.push_back({c.d_es, nb});
+    const size_t M = c.M;
+    v.push_back({c.Jc, M * nb});
+    v.push_back({c.Jcc, M * nb});
+    v.push_back({c.Js, M * nb});
+    v.push_back({c.Jsc, M * nb});
+    v.push_back({c.harm, M * sizeof(HarmState)});
+    v.push_back({c.d_vc, M * MAX_TURNS * sizeof(double)});
+    v.push_back({c.d_vs, M * MAX_TURNS * sizeof(double)});
+    v.push_back({c.d_ec, M * nb});
+    v.push_back({c.d_es, M * nb});
     if (c.cfg.circuit) {
-        v.push_back({c.Ep, 2 * nb});
-        v.push_back({c.cd, sizeof(CircuitDev)});
+        v.push_back({c.Ep, 2 * M * nb});
+        v.push_back({c.cd, M * sizeof(CircuitDev)});
     }
     return v;
 }
@@ -2034,6 +2197,7 @@ extern "C" pic_status pic_checkpoint(pic_ctx *c, void *buf, size_t cap, size_t *
     h.nturns = c->cfg.nturns;
     h.circuit = c->cfg.circuit;
     h.nrf = c->nrf;
+    h.norders = c->M;
     HIPCHK(c, cpy(c->stream, h.count, c->ctl, 2 * sizeof(int64_t), hipMemcpyDeviceToHost));
     for (int s = 0; s < 2; ++s) h.capacity[s] = c->cfg.capacity[s];
     h.last_push = c->last_push;
@@ -2074,7 +2238,7 @@ extern "C" pic_status pic_restore(pic_ctx *c, const void *buf, size_t bytes)
     if (h.total != bytes) return fail(c, PIC_EINVAL, "checkpoint of %llu bytes given %zu", (unsigned long long)h.total, bytes);
     const pic_config &f = c->cfg;
     if (h.precision != f.precision || h.nr != f.nr || h.nz != f.nz || h.nturns != f.nturns || h.circuit != f.circuit ||
-        h.nrf != c->nrf || h.qscale != c->qscale || h.jscale != c->jscale)
+        h.nrf != c->nrf || h.norders != c->M || h.qscale != c->qscale || h.jscale != c->jscale)
         return fail(c, PIC_EINVAL, "checkpoint taken with another configuration");
     for (int s = 0; s < 2; ++s)
         if (h.count[s] > f.capacity[s]) return fail(c, PIC_ENOMEM, "checkpoint holds %lld slots of species %d, capacity %lld",
@@ -2100,10 +2264,11 @@ extern "C" pic_status pic_restore(pic_ctx *c, const void *buf, size_t bytes)
     c->mg_fresh = std::max(h.mg_fresh, 1);
     c->mg_restart = h.mg_restart != 0;
     // host mirrors of what the device arrays now hold
-    HIPCHK(c, cpy(c->stream, c->vc.data(), c->d_vc, MAX_TURNS * sizeof(double), hipMemcpyDeviceToHost));
-    HIPCHK(c, cpy(c->stream, c->vs.data(), c->d_vs, MAX_TURNS * sizeof(double), hipMemcpyDeviceToHost));
-    HIPCHK(c, cpy(c->stream, c->ec.data(), c->d_ec, (size_t)c->g.nodes * sizeof(double), hipMemcpyDeviceToHost));
-    HIPCHK(c, cpy(c->stream, c->es.data(), c->d_es, (size_t)c->g.nodes * sizeof(double), hipMemcpyDeviceToHost));
+    const size_t M = c->M;
+    HIPCHK(c, cpy(c->stream, c->vc.data(), c->d_vc, M * MAX_TURNS * sizeof(double), hipMemcpyDeviceToHost));
+    HIPCHK(c, cpy(c->stream, c->vs.data(), c->d_vs, M * MAX_TURNS * sizeof(double), hipMemcpyDeviceToHost));
+    HIPCHK(c, cpy(c->stream, c->ec.data(), c->d_ec, M * c->g.nodes * sizeof(double), hipMemcpyDeviceToHost));
+    HIPCHK(c, cpy(c->stream, c->es.data(), c->d_es, M * c->g.nodes * sizeof(double), hipMemcpyDeviceToHost));
     if (f.circuit) {
         // the surrogate settings belong to the attachment, not the state
         const int32_t mi = c->cdh.sur_max_iter;

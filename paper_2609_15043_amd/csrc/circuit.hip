@@ -298,12 +298,12 @@ __device__ void measure_period(CircuitDev &c)
 }
 
 // filtered, trend-extrapolated power controller (Eqs. pfilter, ptrend,
-// pcontrol, limiter, bounds), thread 0
-__device__ void controller_step(CircuitDev &c)
+// pcontrol, limiter, bounds) fed with the measured port power p; thread 0
+__device__ void controller_step(CircuitDev &c, double p)
 {
     if (!c.controller) return;
-    const double prev = c.have_pf ? c.pf_prev : c.p_port;
-    const double pf = c.gamma * c.p_port + (1.0 - c.gamma) * prev;
+    const double prev = c.have_pf ? c.pf_prev : p;
+    const double pf = c.gamma * p + (1.0 - c.gamma) * prev;
     const double pc = fmax(pf + c.n_trend * (pf - prev), c.eps_p);
     const double vold = c.vg_amp;
     double vn = vold + c.alpha_v * (vold * sqrt(c.p_target / pc) - vold);
@@ -353,7 +353,7 @@ __global__ __launch_bounds__(64) void k_circuit(CircuitDev *cdp, const HarmState
     if (mode == 2) return;
     if (t == 0 && (mode == 1 || mode == 3)) measure_period(c);
     if (mode == 3) return;
-    if (t == 0 && mode == 1) controller_step(c);
+    if (t == 0 && mode == 1) controller_step(c, c.p_port);
     __syncthreads();
     if (mode == 0) {
         // first state: zero load responses; with the target-power start the
@@ -465,7 +465,7 @@ __global__ __launch_bounds__(64) void k_surrogate(CircuitDev *cdp, const float *
             if (!(c.sur_err <= c.sur_err_max)) {
                 c.sur_used = 0;
                 c.sur_done = 1;
-                controller_step(c);
+                controller_step(c, c.p_port);
                 mode = 0;
             } else {
                 c.sur_used = 1;
@@ -556,7 +556,7 @@ __global__ __launch_bounds__(64) void k_surrogate(CircuitDev *cdp, const float *
     }
     if (stage == 2 && c.sur_used == 2) {
         // diverged inner iteration: plain update with the measured loads
-        if (t == 0) controller_step(c);
+        if (t == 0) controller_step(c, c.p_port);
         __syncthreads();
         if (!network_solve(c, vg_phasor(c, c.vg_amp), c.icap_re, c.icap_im, c.vp_re, c.vp_im, c.xt_re, c.xt_im, S)) {
             if (t == 0) c.singular = 1;
@@ -592,6 +592,109 @@ __global__ __launch_bounds__(64) void k_surrogate(CircuitDev *cdp, const float *
         network_residuals(c, vg_phasor(c, c.vg_amp), lre2, lim2, vre2, vim2);
         write_turn_potentials(c, vc, vs);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Multiharmonic circuit: the same network at every retained order m (its
+// own record cd[m - 1]: impedances at m w, vacuum coupling from the unit
+// fields of order m, loads from the order-m harmonics).  The source of order
+// m is V_g,m = rho_m exp(i phi_m) V_g with the fundamental's amplitude V_g;
+// the controller acts on the total port power.
+// mode 0: first states with zero load responses; with the target-power
+//         start V_g puts p_target into the vacuum networks together (they
+//         are linear in V_g: solved for V_g = 1, then scaled);
+// mode 1: after every order's finalisation and measurement (k_circuit
+//         mode 3): totals, controller, each order's target solve,
+//         relaxation and residuals.
+// Turn potentials of order m go to vc / vs + (m - 1) MAX_TURNS.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double port_power(const CircuitDev &c, const double *xr, const double *xi)
+{
+    return 0.5 * (xr[1 + c.N] * xr[0] + xi[1 + c.N] * xi[0]);
+}
+
+__global__ __launch_bounds__(64) void k_circuit_orders(CircuitDev *cd, int M, double *vc, double *vs, int mode)
+{
+    __shared__ NetSmem S;
+    __shared__ double zero[MAX_TURNS];
+    const int t = threadIdx.x;
+    CircuitDev &f = cd[0];
+    const int N = f.N, X = 2 * N + 1;
+    if (mode == 0) {
+        if (t < MAX_TURNS) zero[t] = 0.0;
+        __syncthreads();
+        const double base = f.vg_from_target ? 1.0 : f.vg_amp;
+        double p1 = 0.0;
+        for (int m = 0; m < M; ++m) {
+            CircuitDev &c = cd[m];
+            if (!network_solve(c, vg_phasor(c, base * c.vg_ratio), zero, zero, zero, zero, c.xt_re, c.xt_im, S)) {
+                if (t == 0) f.singular = c.singular = 1;
+                return;
+            }
+            if (t == 0) p1 += port_power(c, c.xt_re, c.xt_im);
+        }
+        if (t != 0) return;
+        double scale = 1.0;
+        if (f.vg_from_target) {
+            f.vg_amp = sqrt(f.p_target / p1);
+            scale = f.vg_amp;
+        }
+        for (int m = 0; m < M; ++m) {
+            CircuitDev &c = cd[m];
+            if (m > 0) c.vg_amp = f.vg_amp * c.vg_ratio;
+            for (int r = 0; r < X; ++r) {
+                c.x_re[r] = c.xt_re[r] = scale * c.xt_re[r];
+                c.x_im[r] = c.xt_im[r] = scale * c.xt_im[r];
+            }
+            double num = 0.0, den = 0.0;   // Eq. reciprocity, per order
+            for (int k = 0; k < N; ++k)
+                for (int l = 0; l < N; ++l) {
+                    num = fmax(num, fabs(c.mvac[k * MAX_TURNS + l] - c.mvac[l * MAX_TURNS + k]));
+                    den = fmax(den, fabs(c.mvac[k * MAX_TURNS + l]));
+                }
+            c.eps_rec = den > 0.0 ? num / den : 0.0;
+            write_turn_potentials(c, vc + m * MAX_TURNS, vs + m * MAX_TURNS);
+        }
+        return;
+    }
+    if (t == 0) {
+        double pp = 0.0, pcu = 0.0;
+        for (int m = 0; m < M; ++m) {
+            pp += cd[m].p_port;
+            pcu += cd[m].p_cu;
+        }
+        f.tot_p_port = pp;
+        f.tot_p_cu = pcu;
+        controller_step(f, pp);
+        for (int m = 1; m < M; ++m) cd[m].vg_amp = f.vg_amp * cd[m].vg_ratio;
+    }
+    __syncthreads();
+    for (int m = 0; m < M; ++m) {
+        CircuitDev &c = cd[m];
+        if (!network_solve(c, vg_phasor(c, c.vg_amp), c.icap_re, c.icap_im, c.vp_re, c.vp_im, c.xt_re, c.xt_im, S)) {
+            if (t == 0) f.singular = c.singular = 1;
+            return;
+        }
+        if (t == 0) {
+            relax_and_check(c, c.icap_re, c.icap_im, c.vp_re, c.vp_im);
+            write_turn_potentials(c, vc + m * MAX_TURNS, vs + m * MAX_TURNS);
+        }
+        __syncthreads();
+    }
+    if (t != 0) return;
+    // totals: the time-domain P_ind and P_cap of any order's accumulator
+    // are those of the whole waveform (the fundamental's record holds them)
+    double pph = 0.0, kcl = 0.0, kvl = 0.0;
+    for (int m = 0; m < M; ++m) {
+        pph += cd[m].p_cap_ph;
+        kcl = fmax(kcl, cd[m].kcl);
+        kvl = fmax(kvl, cd[m].kvl);
+    }
+    f.tot_p_cap_ph = pph;
+    f.tot_kcl = kcl;
+    f.tot_kvl = kvl;
+    const double bal = f.p_ind + f.p_cap + f.tot_p_cu;
+    f.tot_eps_bal = f.tot_p_port != 0.0 ? fabs(f.tot_p_port - bal) / fabs(f.tot_p_port) : INFINITY;
 }
 
 // E_c = E_c^p + sum I_s,k U_k, E_s^sto = E_s^sto,p + sum I_c,k U_k with
@@ -644,6 +747,10 @@ void launch_features(const CircuitDev *cd, float *f, bool iterate, hipStream_t s
 void launch_surrogate(CircuitDev *cd, const float *pred, double *vc, double *vs, int stage, hipStream_t s)
 {
     hipLaunchKernelGGL(k_surrogate, dim3(1), dim3(64), 0, s, cd, pred, vc, vs, stage);
+}
+void launch_circuit_orders(CircuitDev *cd, int M, double *vc, double *vs, int mode, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_circuit_orders, dim3(1), dim3(64), 0, s, cd, M, vc, vs, mode);
 }
 void launch_compose(const double *ecp, const double *esp, const double *U, int64_t stride, const CircuitDev *cd,
                     double *ec, double *es, int nodes, hipStream_t s)

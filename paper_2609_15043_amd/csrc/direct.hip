@@ -23,16 +23,23 @@
 
 namespace pic {
 
+// Potential of turn q at the step's phase: the sum over the retained orders.
+__device__ __forceinline__ double turn_value(const DirectArgs &a, int q)
+{
+    double V = a.vc[q] * a.o.cs[0] + a.vs[q] * a.o.sn[0];
+    for (int r = 1; r < a.o.n; ++r) V += a.vc[r * MAX_TURNS + q] * a.o.cs[r] + a.vs[r * MAX_TURNS + q] * a.o.sn[r];
+    return V;
+}
+
 // Dirichlet value of node n at the step's phase: turn k: phi_k(t); a
 // grounded node: the manufactured boundary when given, else phi as it is.
 __device__ __forceinline__ double dirichlet_value(const DirectArgs &a, int n)
 {
     const int k = a.tag[n];
-    if (k >= 1) return a.vc[k - 1] * a.cth + a.vs[k - 1] * a.sth;
+    if (k >= 1) return turn_value(a, k - 1);
     if (a.basis) {
         double s = 0.0;
-        for (int q = 0; q < a.nturns; ++q)
-            s += a.basis[(size_t)q * a.nodes + n] * (a.vc[q] * a.cth + a.vs[q] * a.sth);
+        for (int q = 0; q < a.nturns; ++q) s += a.basis[(size_t)q * a.nodes + n] * turn_value(a, q);
         return s;
     }
     return a.phi[n];

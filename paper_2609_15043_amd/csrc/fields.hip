@@ -13,7 +13,7 @@ namespace pic {
 // per node for the gather; the step's deposit accumulators are cleared.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void k_stage(const double *phi, const double *ec, const double *es, double cs, double sn,
+__global__ void k_stage(const double *phi, const double *ec, const double *es, Orders o,
                         typename Field4<T>::type *ef, long long *accJ, long long *accQ, int clear_q, GridC g)
 {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
@@ -32,7 +32,9 @@ __global__ void k_stage(const double *phi, const double *ec, const double *es, d
         er = -(phi[n] - phi[n - 1]) / g.dr;
     else
         er = -(phi[n + 1] - phi[n - 1]) / (2.0 * g.dr);
-    const double et = ec[n] * cs - es[n] * sn;
+    double et = ec[n] * o.cs[0] - es[n] * o.sn[0];
+    for (int m = 1; m < o.n; ++m)   // retained orders m + 1 (arrays order after order)
+        et += ec[(size_t)m * g.nodes + n] * o.cs[m] - es[(size_t)m * g.nodes + n] * o.sn[m];
     typename Field4<T>::type f;
     f.x = (T)er;
     f.y = (T)ez;
@@ -162,8 +164,8 @@ __device__ __forceinline__ void neumaier(double &sum, double &comp, double x)
 // the turn sums, so the result does not depend on block scheduling.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_harmonic(const long long *accJ, double cj0, double cj1, const double *ec,
-                                                  const double *es, double cs, double sn, double *I, double *Jc,
-                                                  double *Jcc, double *Js, double *Jsc, double *partial, int nodes)
+                                                  const double *es, Orders o, double *I, double *Jc, double *Jcc,
+                                                  double *Js, double *Jsc, double *partial, int nodes)
 {
     __shared__ double red[256];
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
@@ -171,16 +173,22 @@ __global__ __launch_bounds__(256) void k_harmonic(const long long *accJ, double 
     if (n < nodes) {
         const double cur = cj0 * (double)accJ[n] + cj1 * (double)accJ[nodes + n];
         I[n] = cur;
-        const double et = ec[n] * cs - es[n] * sn;
+        double et = ec[n] * o.cs[0] - es[n] * o.sn[0];
+        for (int m = 1; m < o.n; ++m)
+            et += ec[(size_t)m * nodes + n] * o.cs[m] - es[(size_t)m * nodes + n] * o.sn[m];
         pw = cur * et;
-        double a = Jc[n], ac = Jcc[n];
-        neumaier(a, ac, cur * cs);
-        Jc[n] = a;
-        Jcc[n] = ac;
-        double b = Js[n], bc = Jsc[n];
-        neumaier(b, bc, cur * sn);
-        Js[n] = b;
-        Jsc[n] = bc;
+        // the current's harmonic of every retained order (arrays order after order)
+        for (int m = 0; m < o.n; ++m) {
+            const size_t q = (size_t)m * nodes + n;
+            double a = Jc[q], ac = Jcc[q];
+            neumaier(a, ac, cur * o.cs[m]);
+            Jc[q] = a;
+            Jcc[q] = ac;
+            double b = Js[q], bc = Jsc[q];
+            neumaier(b, bc, cur * o.sn[m]);
+            Js[q] = b;
+            Jsc[q] = bc;
+        }
     }
     red[threadIdx.x] = pw;
     __syncthreads();
@@ -191,9 +199,12 @@ __global__ __launch_bounds__(256) void k_harmonic(const long long *accJ, double 
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
-__global__ __launch_bounds__(256) void k_harmonic_fold(const double *partial, int nparts, double cs, double sn,
-                                                       HarmState *h, const double *Qk, const double *vc,
-                                                       const double *vs, int nturns)
+// Every retained order keeps its own accumulator: the turn-charge
+// harmonics of its order, and the same time-domain inductive power and
+// V dQ trapezoid (of the total potentials) in each.
+__global__ __launch_bounds__(256) void k_harmonic_fold(const double *partial, int nparts, Orders o, HarmState *hs,
+                                                       const double *Qk, const double *vc, const double *vs,
+                                                       int nturns)
 {
     __shared__ double red[256];
     {
@@ -206,13 +217,16 @@ __global__ __launch_bounds__(256) void k_harmonic_fold(const double *partial, in
         if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
         __syncthreads();
     }
-    if (threadIdx.x != 0) return;
+    if (threadIdx.x >= o.n) return;
+    const int m = threadIdx.x;
+    HarmState *h = hs + m;
     neumaier(h->pind, h->pind_c, red[0]);
     for (int k = 0; k < nturns; ++k) {
-        const double V = vc[k] * cs + vs[k] * sn;
+        double V = vc[k] * o.cs[0] + vs[k] * o.sn[0];
+        for (int r = 1; r < o.n; ++r) V += vc[r * MAX_TURNS + k] * o.cs[r] + vs[r * MAX_TURNS + k] * o.sn[r];
         const double q = Qk[k];
-        neumaier(h->qc[k], h->qc_c[k], q * cs);
-        neumaier(h->qs[k], h->qs_c[k], q * sn);
+        neumaier(h->qc[k], h->qc_c[k], q * o.cs[m]);
+        neumaier(h->qs[k], h->qs_c[k], q * o.sn[m]);
         if (h->samples == 0) {
             h->v_first[k] = V;
             h->q_first[k] = q;
@@ -536,8 +550,8 @@ __device__ __forceinline__ double fold_partials(const double *part, int np, int 
 // two arrays, phi^{n-1} then phi^{n-2}): order 1 gives 2 phi^n - phi^{n-1},
 // order 2 gives 3 phi^n - 3 phi^{n-1} + phi^{n-2}; the stored solutions then
 // shift by one; state reset.
-__global__ void k_pcg_begin(MGLevel L, PCGVec v, const int32_t *tag, const double *vc, const double *vs, double cs,
-                            double sn, MGState *st, double *prev, int order, const double *basis, int nturns)
+__global__ void k_pcg_begin(MGLevel L, PCGVec v, const int32_t *tag, const double *vc, const double *vs, Orders o,
+                            MGState *st, double *prev, int order, const double *basis, int nturns)
 {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n == 0) {
@@ -548,12 +562,18 @@ __global__ void k_pcg_begin(MGLevel L, PCGVec v, const int32_t *tag, const doubl
     }
     if (n >= L.nodes) return;
     const int k = tag[n];
+    // turn potential at t_n: the sum over the retained orders
+    auto turn = [&](int q) {
+        double V = vc[q] * o.cs[0] + vs[q] * o.sn[0];
+        for (int r = 1; r < o.n; ++r) V += vc[r * MAX_TURNS + q] * o.cs[r] + vs[r * MAX_TURNS + q] * o.sn[r];
+        return V;
+    };
     if (k >= 1) {
-        v.x[n] = vc[k - 1] * cs + vs[k - 1] * sn;
+        v.x[n] = turn(k - 1);
     } else if (k == 0 && basis) {
         // manufactured boundary: linear in the turn potentials
         double s = 0.0;
-        for (int q = 0; q < nturns; ++q) s += basis[(size_t)q * L.nodes + n] * (vc[q] * cs + vs[q] * sn);
+        for (int q = 0; q < nturns; ++q) s += basis[(size_t)q * L.nodes + n] * turn(q);
         v.x[n] = s;
     } else if (k < 0 && prev) {
         double *prev2 = prev + L.nodes;
@@ -714,11 +734,11 @@ __global__ __launch_bounds__(256) void k_face_charge(const double *phi, const in
 static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 template <typename T>
-void launch_stage(const double *phi, const double *ec, const double *es, double cs, double sn,
+void launch_stage(const double *phi, const double *ec, const double *es, const Orders &o,
                   typename Field4<T>::type *ef, long long *accJ, long long *accQ, bool clear_q, const GridC &g,
                   hipStream_t st)
 {
-    hipLaunchKernelGGL(k_stage<T>, dim3(nblk(g.nodes, 256)), dim3(256), 0, st, phi, ec, es, cs, sn, ef, accJ, accQ,
+    hipLaunchKernelGGL(k_stage<T>, dim3(nblk(g.nodes, 256)), dim3(256), 0, st, phi, ec, es, o, ef, accJ, accQ,
                        clear_q ? 1 : 0, g);
 }
 template <typename T>
@@ -731,9 +751,9 @@ template void launch_stage_b<float>(const double *, const double *, double, doub
                                     hipStream_t);
 template void launch_stage_b<double>(const double *, const double *, double, double, double, double2 *,
                                      const GridC &, hipStream_t);
-template void launch_stage<float>(const double *, const double *, const double *, double, double, float4 *,
+template void launch_stage<float>(const double *, const double *, const double *, const Orders &, float4 *,
                                   long long *, long long *, bool, const GridC &, hipStream_t);
-template void launch_stage<double>(const double *, const double *, const double *, double, double, double4 *,
+template void launch_stage<double>(const double *, const double *, const double *, const Orders &, double4 *,
                                    long long *, long long *, bool, const GridC &, hipStream_t);
 
 void launch_finalize_q(const long long *accQ, long long *accW, double *accS, double inv_scale, double cq0, double cq1,
@@ -743,15 +763,15 @@ void launch_finalize_q(const long long *accQ, long long *accW, double *accS, dou
                        cs0, cs1, Q, nodes);
 }
 
-void launch_harmonic(const long long *accJ, double cj0, double cj1, const double *ec, const double *es, double cs,
-                     double sn, double *I, double *Jc, double *Jcc, double *Js, double *Jsc, double *partial,
+void launch_harmonic(const long long *accJ, double cj0, double cj1, const double *ec, const double *es,
+                     const Orders &o, double *I, double *Jc, double *Jcc, double *Js, double *Jsc, double *partial,
                      HarmState *h, const double *Qk, const double *vc, const double *vs, int nturns, int nodes,
                      hipStream_t st)
 {
     const int nb = (int)nblk(nodes, 256);
-    hipLaunchKernelGGL(k_harmonic, dim3(nb), dim3(256), 0, st, accJ, cj0, cj1, ec, es, cs, sn, I, Jc, Jcc, Js, Jsc,
+    hipLaunchKernelGGL(k_harmonic, dim3(nb), dim3(256), 0, st, accJ, cj0, cj1, ec, es, o, I, Jc, Jcc, Js, Jsc,
                        partial, nodes);
-    hipLaunchKernelGGL(k_harmonic_fold, dim3(1), dim3(256), 0, st, partial, nb, cs, sn, h, Qk, vc, vs, nturns);
+    hipLaunchKernelGGL(k_harmonic_fold, dim3(1), dim3(256), 0, st, partial, nb, o, h, Qk, vc, vs, nturns);
 }
 
 int harmonic_blocks(int nodes) { return (int)nblk(nodes, 256); }
@@ -806,11 +826,11 @@ void launch_gauss_jordan(double *A, int n, double *rowk, double *colk, hipStream
 }
 int pcg_blocks(int nodes) { return (int)red_grid(nodes); }
 void launch_pcg_begin(const MGLevel &L, const PCGVec &v, const int32_t *tag, const double *vc, const double *vs,
-                      double cs, double sn, MGState *st, double *prev, int order, hipStream_t s, const double *basis,
+                      const Orders &o, MGState *st, double *prev, int order, hipStream_t s, const double *basis,
                       int nturns)
 {
-    hipLaunchKernelGGL(k_pcg_begin, dim3(nblk(L.nodes, 256)), dim3(256), 0, s, L, v, tag, vc, vs, cs, sn, st, prev,
-                       order, basis, nturns);
+    hipLaunchKernelGGL(k_pcg_begin, dim3(nblk(L.nodes, 256)), dim3(256), 0, s, L, v, tag, vc, vs, o, st, prev, order,
+                       basis, nturns);
 }
 void launch_pcg_resid(const MGLevel &L, const PCGVec &v, double *partial, hipStream_t s)
 {

@@ -190,6 +190,14 @@ struct MGState {
 };
 
 constexpr int MAX_TURNS = 16;
+// Retained orders of the multiharmonic circuit (order m at frequency m f):
+// arrays of per-order data are stored order after order (the fundamental
+// first), and a step's phase reaches the kernels as cos, sin of m th_n.
+constexpr int MAX_HARM = 4;
+struct Orders {
+    int n;                          // retained orders (1: fundamental only)
+    double cs[MAX_HARM], sn[MAX_HARM];
+};
 constexpr int SUR_MAX_ITER = 64;        // inner iterations of the surrogate-assisted update at most
 // Open-period accumulators (compensated sums: value + correction).
 struct HarmState {
@@ -238,7 +246,14 @@ struct CircuitDev {
     int32_t sur_navg, pad2;
     double sur_hist[SUR_MAX_ITER];          // relative step of each inner iterate
     // prescribed load responses of the next update (circuit override)
-    int32_t ovr_loads, pad3;
+    int32_t ovr_loads, order;               // order: m of this network (1 = fundamental)
+    // multiharmonic circuit: this order's source amplitude relative to the
+    // fundamental's (its phase offset is folded into vg_phase); in the
+    // fundamental's record, the totals over the retained orders of the last
+    // update (port power, copper loss, phasor capacitive power, imbalance,
+    // largest KCL / KVL residual)
+    double vg_ratio;
+    double tot_p_port, tot_p_cu, tot_p_cap_ph, tot_eps_bal, tot_kcl, tot_kvl;
     double ovr_vp_re[MAX_TURNS], ovr_vp_im[MAX_TURNS], ovr_icap_re[MAX_TURNS], ovr_icap_im[MAX_TURNS];
 };
 
@@ -248,7 +263,7 @@ struct CircuitDev {
 constexpr int DP_MAX_DIRICHLET_DEV = 512;   // interior Dirichlet nodes at most
 struct DirectArgs {
     int nr, nz, nodes, ni, nj, m, nrow, nturns;
-    double cth, sth;                        // cos, sin of the step's phase
+    Orders o;                               // the step's phase per retained order
     const int32_t *tag;
     const double *vc, *vs, *basis;
     double *phi;

@@ -39,15 +39,15 @@ template <typename T>
 void launch_stage_b(const double *ec, const double *es, double cs, double sn, double inv_w,
                     typename Field2<T>::type *eb, const GridC &g, hipStream_t st);
 template <typename T>
-void launch_stage(const double *phi, const double *ec, const double *es, double cs, double sn,
+void launch_stage(const double *phi, const double *ec, const double *es, const Orders &o,
                   typename Field4<T>::type *ef, long long *accJ, long long *accQ, bool clear_q, const GridC &g,
                   hipStream_t st);
 void launch_chi(const long long *accQ, double c0, double c1, double *chi, const double *cw0, const double *ce0,
                 const double *cs0, const double *cn0, const MGLevel &L0, const GridC &g, hipStream_t st);
 void launch_finalize_q(const long long *accQ, long long *accW, double *accS, double inv_scale, double cq0, double cq1,
                        double cs0, double cs1, double *Q, int nodes, hipStream_t st);
-void launch_harmonic(const long long *accJ, double cj0, double cj1, const double *ec, const double *es, double cs,
-                     double sn, double *I, double *Jc, double *Jcc, double *Js, double *Jsc, double *partial,
+void launch_harmonic(const long long *accJ, double cj0, double cj1, const double *ec, const double *es,
+                     const Orders &o, double *I, double *Jc, double *Jcc, double *Js, double *Jsc, double *partial,
                      HarmState *h, const double *Qk, const double *vc, const double *vs, int nturns, int nodes,
                      hipStream_t st);
 int harmonic_blocks(int nodes);
@@ -73,7 +73,7 @@ int dense_ld(int n);
 void launch_gauss_jordan(double *A, int n, double *rowk, double *colk, hipStream_t s);
 int pcg_blocks(int nodes);
 void launch_pcg_begin(const MGLevel &L, const PCGVec &v, const int32_t *tag, const double *vc, const double *vs,
-                      double cs, double sn, MGState *st, double *prev, int order, hipStream_t s,
+                      const Orders &o, MGState *st, double *prev, int order, hipStream_t s,
                       const double *basis = nullptr, int nturns = 0);
 void launch_direct_solve(const DirectArgs &a, hipStream_t st);
 void launch_pcg_resid(const MGLevel &L, const PCGVec &v, double *partial, hipStream_t s);
@@ -91,6 +91,7 @@ void launch_unit_rhs(const int32_t *tag, int turn, double gval, const uint8_t *d
 void launch_project(const double *fields, int nf, int64_t stride, const int32_t *list, const int32_t *lturn, int nlist,
                     const double *gval, int nturns, double *out, int ostride, const GridC &g, hipStream_t s);
 void launch_circuit(CircuitDev *cd, const HarmState *h, double *vc, double *vs, int mode, hipStream_t s);
+void launch_circuit_orders(CircuitDev *cd, int M, double *vc, double *vs, int mode, hipStream_t s);
 void launch_features(const CircuitDev *cd, float *f, bool iterate, hipStream_t s);
 void launch_surrogate(CircuitDev *cd, const float *pred, double *vc, double *vs, int stage, hipStream_t s);
 template <typename T>

@@ -53,6 +53,7 @@ class PicConfig(ctypes.Structure):
         ("v_min", _D), ("v_max", _D), ("alpha", _D), ("helm_rtol", _D), ("helm_max_cycles", _I32),
         ("sort_every_ion", _I32), ("dir_basis", _PD), ("unit_bvals", _PD), ("rf_bfield", _I32),
         ("implicit", _I32), ("poisson_solver", _I32),
+        ("nharm", _I32), ("harm_ratio", _D * 3), ("harm_phase", _D * 3),
     ]
 
 
@@ -81,7 +82,8 @@ class PicPeriodReport(ctypes.Structure):
                 ("vp_re", _D * 16), ("vp_im", _D * 16), ("xt_re", _D * 33), ("xt_im", _D * 33),
                 ("x_re", _D * 33), ("x_im", _D * 33), ("helm_cycles", _I32 * 2), ("helm_rel", _D * 2),
                 ("xp_re", _D * 33), ("xp_im", _D * 33), ("pressure", _D), ("moments", _D * 8),
-                ("sur_used", _I32), ("sur_iters", _I32), ("sur_err", _D), ("sur_steps", _D * 64)]
+                ("sur_used", _I32), ("sur_iters", _I32), ("sur_err", _D), ("sur_steps", _D * 64),
+                ("vg_phase", _D)]
 
 
 class PicSurrogateConfig(ctypes.Structure):
@@ -109,7 +111,8 @@ _LIB = None
 
 # exported C symbols, in header order
 SYMBOLS = ["pic_workspace_bytes", "pic_init", "pic_gather_push", "mcc_collide", "pic_deposit",
-           "poisson_solve_rz", "harmonic_accumulate", "circuit_period_update", "pic_set_source",
+           "poisson_solve_rz", "harmonic_accumulate", "circuit_period_update", "circuit_order_report",
+           "pic_set_source",
            "pic_attach_surrogate",
            "pic_get_circuit", "pic_sync",
            "pic_clear_error", "pic_get_particles", "pic_set_particles", "pic_set_step", "pic_set_phi",
@@ -133,6 +136,7 @@ def lib():
         L.poisson_solve_rz.argtypes = [P, _I64, _I32, _D, _I32, ctypes.POINTER(PicSolveInfo)]
         L.circuit_period_update.argtypes = [P, ctypes.POINTER(PicCircuitOverride), ctypes.POINTER(PicPeriodReport),
                                             _PD, _PD]
+        L.circuit_order_report.argtypes = [P, _I32, ctypes.POINTER(PicPeriodReport)]
         L.pic_get_circuit.argtypes = [P, ctypes.POINTER(PicCircuitInfo)]
         L.pic_attach_surrogate.argtypes = [P, P, ctypes.POINTER(PicSurrogateConfig)]
         L.pic_set_source.argtypes = [P, _D, _D]
@@ -232,6 +236,10 @@ def config_from_workload(wl, precision="mixed", fuse=True, load=True, mg_rtol=No
         c.alpha_v, c.f_step, c.v_min, c.v_max = cp.alpha_v, cp.f_step, cp.v_min, cp.v_max
         c.alpha = cp.alpha
         c.helm_rtol, c.helm_max_cycles = helm_rtol, helm_max_cycles
+        # orders above the fundamental of a multiharmonic circuit: (ratio, phase) each
+        c.nharm = len(cp.harmonics)
+        for q, (a, ph) in enumerate(cp.harmonics):
+            c.harm_ratio[q], c.harm_phase[q] = a, ph
     return c, keep
 
 
@@ -267,7 +275,7 @@ def pic_workspace_bytes(cfg):
     n = ctypes.c_size_t()
     st = lib().pic_workspace_bytes(ctypes.byref(cfg), ctypes.byref(n))
     if st:
-        raise PicError(st, "pic_workspace_bytes")
+        raise PicError(st, "pic_workspace_bytes: " + lib().pic_last_error(None).decode())
     return n.value
 
 
@@ -333,6 +341,13 @@ def circuit_period_update(ctx, new_vc=None, new_vs=None, new_ec=None, new_es_sto
                 ovr.icap_re[k], ovr.icap_im[k] = icap[k].real, icap[k].imag
     st = lib().circuit_period_update(ctx.handle, ctypes.byref(ovr) if ovr is not None else None, ctypes.byref(rep),
                                      _ptr(jc, _D), _ptr(js, _D))
+    out = _report_dict(ctx, rep)
+    if ctx.cfg.circuit and ctx.cfg.nharm > 0 and st == PIC_OK:
+        out["orders"] = [circuit_order_report(ctx, m) for m in range(1, ctx.cfg.nharm + 2)]
+    return st, out, jc, js
+
+
+def _report_dict(ctx, rep):
     K = ctx.cfg.nturns
     out = dict(accepted=rep.accepted, samples=rep.samples, p_ind=rep.p_ind, p_cap=rep.p_cap, p_cap_ph=rep.p_cap_ph,
                qc=np.array(rep.qc[:K]), qs=np.array(rep.qs[:K]),
@@ -341,6 +356,7 @@ def circuit_period_update(ctx, new_vc=None, new_vs=None, new_ec=None, new_es_sto
         M = 2 * K + 1
         out.update(p_port=rep.p_port, p_cu=rep.p_cu, eps_bal=rep.eps_bal, kcl=rep.kcl, kvl=rep.kvl,
                    vg_old=rep.vg_old, vg_amp=rep.vg_amp, pf=rep.pf, pc=rep.pc,
+                   vg=rep.vg_amp * complex(math.cos(rep.vg_phase), math.sin(rep.vg_phase)),
                    vp=np.array(rep.vp_re[:K]) + 1j * np.array(rep.vp_im[:K]),
                    x_target=np.array(rep.xt_re[:M]) + 1j * np.array(rep.xt_im[:M]),
                    x=np.array(rep.x_re[:M]) + 1j * np.array(rep.x_im[:M]),
@@ -348,7 +364,16 @@ def circuit_period_update(ctx, new_vc=None, new_vs=None, new_ec=None, new_es_sto
                    x_prev=np.array(rep.xp_re[:M]) + 1j * np.array(rep.xp_im[:M]), pressure=rep.pressure,
                    moments=np.array(rep.moments[:]), sur_used=rep.sur_used, sur_iters=rep.sur_iters,
                    sur_err=rep.sur_err, sur_steps=np.array(rep.sur_steps[:min(rep.sur_iters, 64)]))
-    return st, out, jc, js
+    return out
+
+
+def circuit_order_report(ctx, order):
+    """The last update's report fields of retained order `order` (1 = the
+    fundamental) of a multiharmonic circuit, as a dict like the period
+    report's."""
+    rep = PicPeriodReport()
+    ctx.check(lib().circuit_order_report(ctx.handle, order, ctypes.byref(rep)))
+    return _report_dict(ctx, rep)
 
 
 def pic_set_source(ctx, vg_amp, vg_phase=0.0):

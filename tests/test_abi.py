@@ -4,6 +4,8 @@ import ctypes
 import os
 import re
 
+import numpy as np
+
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -45,3 +47,77 @@ def test_workspace_query_and_config_validation():
     bad.sort_every = 0
     with pytest.raises(pp.PicError):
         pp.pic_workspace_bytes(bad)
+
+
+def test_multiharmonic_configuration_is_validated():
+    """The multiharmonic circuit's configuration checks (host side, before
+    any device work): at most three orders above the fundamental, circuit
+    coupling, the magnetoquasistatic operator, no RF magnetic field, positive
+    ratios; each refusal names its reason."""
+    import dataclasses
+    import paper_2609_15043_amd.phasorpic as pp
+    from paper_2609_15043_amd import workloads as W
+    wl = W.cell(n_per_species=1000)
+    wl.circuit = dataclasses.replace(wl.circuit, field_mode=W.FIELD_MQS, harmonics=((0.5, 0.7),))
+    cfg, keep = pp.config_from_workload(wl, precision="fp64", load=False)
+    assert pp.pic_workspace_bytes(cfg) > 0
+    one, _ = pp.config_from_workload(dataclasses.replace(wl, circuit=dataclasses.replace(wl.circuit, harmonics=())),
+                                     precision="fp64", load=False)
+    # per-order arrays: the second order adds its unit fields, fields and harmonics
+    assert pp.pic_workspace_bytes(cfg) > pp.pic_workspace_bytes(one)
+    cases = [
+        ("nharm", dict(nharm=4), "nharm outside"),
+        ("full-wave", dict(field_mode=W.FIELD_FULL), "magnetoquasistatic"),
+        ("uncoupled", dict(circuit=0), "needs circuit coupling"),
+        ("rf_bfield", dict(rf_bfield=1), "fundamental only"),
+    ]
+    for label, fields, msg in cases:
+        bad, keep2 = pp.config_from_workload(wl, precision="fp64", load=False)
+        for k, v in fields.items():
+            setattr(bad, k, v)
+        if label == "uncoupled":
+            vc = np.zeros(wl.nturns)
+            keep2.append(vc)
+            bad.turn_vc = bad.turn_vs = vc.ctypes.data_as(pp._PD)
+        with pytest.raises(pp.PicError, match=msg):
+            pp.pic_workspace_bytes(bad)
+    bad, _ = pp.config_from_workload(wl, precision="fp64", load=False)
+    bad.harm_ratio[0] = 0.0
+    with pytest.raises(pp.PicError, match="harm_ratio"):
+        pp.pic_workspace_bytes(bad)
+    bad.harm_ratio[0] = 0.5
+    bad.harm_phase[0] = float("nan")
+    with pytest.raises(pp.PicError, match="harm_phase"):
+        pp.pic_workspace_bytes(bad)
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The binding's ctypes structures have the header's sizes and field
+    offsets (compiled with the host C compiler)."""
+    import ctypes
+    import os
+    import subprocess
+    import paper_2609_15043_amd.phasorpic as pp
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    structs = {"pic_config": pp.PicConfig, "pic_period_report": pp.PicPeriodReport,
+               "pic_stats": pp.PicStats, "pic_circuit_override": pp.PicCircuitOverride,
+               "pic_circuit_info": pp.PicCircuitInfo, "pic_surrogate_config": pp.PicSurrogateConfig,
+               "pic_solve_info": pp.PicSolveInfo}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "phasorpic.h"', 'int main(void) {']
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-I", inc, "-o", str(exe), str(src)])
+    got = {}
+    for line in subprocess.check_output([str(exe)]).decode().splitlines():
+        cname, key, val = line.split()
+        got[(cname, key)] = int(val)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)

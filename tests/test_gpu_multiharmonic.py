@@ -1,0 +1,211 @@
+"""GPU parity of the multiharmonic circuit (retained orders m = 1..M at
+frequency m f, each with its own unit fields, impedances, loads and network,
+the controller on the total port power; the outlook of the paper's
+conclusions) against the oracle's MultiHarmonicCircuit, through the C ABI.
+
+The GPU's inductive solves are iterative (relative residual 1e-12) where the
+oracle's are direct, so the vacuum comparisons hold to ~1e-10 as for the
+single-frequency circuit; a period with particles separates by rounding as
+in the single-frequency plasma test (1e-8 FP64, 1e-3 FP32-mixed).
+"""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    s = float(np.max(np.abs(b)))
+    return float(np.max(np.abs(a - b))) / s if s > 0 else float(np.max(np.abs(a - b)))
+
+
+def _vacuum_cell(**kw):
+    """Particle-free coil cell at 13.56 MHz, 16 samples per period, MQS."""
+    from paper_2609_15043_amd import workloads as W
+    wl = W.cell(n_per_species=1000)
+    wl.dt = 1.0 / (16 * wl.freq)
+    prm = dict(field_mode=W.FIELD_MQS)
+    prm.update(kw)
+    wl.circuit = dataclasses.replace(wl.circuit, **prm)
+    return wl
+
+
+def _run(ctx, ora, nrf, periods, n=0):
+    """periods whole periods from step n (a period boundary)."""
+    import paper_2609_15043_amd.phasorpic as pp
+    reps = []
+    for _ in range(periods):
+        for _ in range(nrf):
+            pp.pic_gather_push(ctx, n)
+            pp.harmonic_accumulate(ctx, n)
+            pp.mcc_collide(ctx, n)
+            pp.pic_deposit(ctx, n + 1)
+            if (n + 1) % nrf == 0:
+                st, rep, _, _ = pp.circuit_period_update(ctx)
+                assert st == 0 and rep["accepted"] == 1
+                reps.append(rep)
+            pp.poisson_solve_rz(ctx, n + 1)
+            ora.step()
+            n += 1
+    return reps
+
+
+def _compare(g, o, tol, label):
+    """GPU report (or order report) g against the oracle's o."""
+    errs = {}
+    K = len(o["icap"])
+    qscale = 0.5 * float(np.sum(np.abs(o["x_prev"][1 + K:]) * np.abs(o["icap"])))
+    for key in ("p_port", "p_cu", "p_cap", "p_cap_ph"):
+        den = abs(o[key]) if key in ("p_port", "p_cu") else max(abs(o[key]), qscale)
+        errs[key] = abs(g[key] - o[key]) / den
+    errs["vg"] = abs(g["vg"] - o["vg"]) / abs(o["vg"])
+    for key in ("icap", "x_target", "x", "x_prev"):
+        errs[key] = rel(g[key], o[key])
+    if np.max(np.abs(o["vp"])) > 0:
+        errs["vp"] = rel(g["vp"], o["vp"])
+    # the residuals are already relative (to |I_f|, |V_g|): compared
+    # absolutely, since an exactly satisfied KVL leaves rounding noise only
+    for key in ("kcl", "kvl"):
+        errs[key] = abs(g[key] - o[key]) / max(o[key], 1.0)
+    say(f"    {label}: " + " ".join(f"{k}={v:.1e}" for k, v in errs.items()))
+    for k, v in errs.items():
+        assert v <= tol, (label, k, v)
+
+
+def _compare_all(ctx, rep, o, tol, label):
+    import paper_2609_15043_amd.phasorpic as pp
+    _compare(rep, o, tol, f"{label} totals")
+    assert abs(rep["eps_bal"] - o["eps_bal"]) <= max(tol * o["eps_bal"], 1e-9), (rep["eps_bal"], o["eps_bal"])
+    for m, om in enumerate(o["orders"], start=1):
+        gm = pp.circuit_order_report(ctx, m)
+        assert gm["accepted"] == 1
+        _compare(gm, om, tol, f"{label} order {m}")
+        assert rep["orders"][m - 1]["p_port"] == gm["p_port"]
+
+
+@pytest.mark.parametrize("solver", ["direct", "multigrid"])
+def test_vacuum_orders_match_oracle(solver):
+    """Two retained orders, the controller from the target-power start,
+    relaxation 0.3, four 16-sample periods without plasma: the start state of
+    each order, every period's totals and per-order reports, the
+    fundamental's field and the potential (the turn Dirichlet values sum over
+    the orders)."""
+    _need_gpu()
+    import paper_2609_15043_amd.phasorpic as pp
+    from oracle import pic as O
+    wl = _vacuum_cell(harmonics=((0.6, -0.4),), controller=True, vg_from_target=True, p_target=60.0, alpha=0.3)
+    say(f"[gpu] multiharmonic vacuum periods, 2 orders, cell, fp64, {solver}")
+    cfg, keep = pp.config_from_workload(wl, precision="fp64", load=False, poisson_solver=solver)
+    ctx = pp.pic_init(cfg, keep)
+    ora = O.OraclePIC(wl, load=False)
+    for m, fc in enumerate(ora.fc.fcs, start=1):
+        e = rel(pp.circuit_order_report(ctx, m)["x"], fc.x)
+        say(f"    start state order {m}: rel {e:.1e}")
+        assert e <= 1e-10, (m, e)
+    info = pp.pic_get_circuit(ctx)
+    assert abs(info["vg_amp"] - ora.fc.vg_amp) <= 1e-12 * ora.fc.vg_amp
+    for p in range(4):
+        reps = _run(ctx, ora, 16, 1, n=16 * p)
+        _compare_all(ctx, reps[-1], ora.last_report, 1e-9, f"period {p + 1}")
+    for name, grid, ref in (("Ec", pp.PIC_GRID_EC, ora.ec[0]), ("Es", pp.PIC_GRID_ES, ora.es[0])):
+        e = rel(pp.pic_get_grid(ctx, grid), ref)
+        say(f"    fundamental {name} rel {e:.1e}")
+        assert e <= 1e-9, (name, e)
+    e = rel(pp.pic_get_grid(ctx, pp.PIC_GRID_PHI), ora.phi)
+    say(f"    phi rel {e:.1e}")
+    assert e <= 1e-9, e
+
+
+def test_three_orders_balance_on_the_gpu():
+    """Three retained orders at alpha = 1 without the controller: after
+    sixteen periods the GPU's total port power is the sum of the orders' and
+    closes the balance with the copper losses (the dielectric takes no
+    active power), as the oracle's does."""
+    _need_gpu()
+    import paper_2609_15043_amd.phasorpic as pp
+    from oracle import pic as O
+    wl = _vacuum_cell(harmonics=((0.5, 0.7), (0.25, -1.1)), controller=False, vg_from_target=False,
+                      vg_amp=2000.0, alpha=1.0)
+    say("[gpu] multiharmonic vacuum, 3 orders, 16 periods")
+    cfg, keep = pp.config_from_workload(wl, precision="fp64", load=False)
+    ctx = pp.pic_init(cfg, keep)
+    ora = O.OraclePIC(wl, load=False)
+    reps = _run(ctx, ora, 16, 16)
+    last = reps[-1]
+    _compare_all(ctx, last, ora.last_report, 1e-9, "period 16")
+    orders = last["orders"]
+    assert len(orders) == 3
+    assert abs(last["p_port"] - sum(o["p_port"] for o in orders)) <= 1e-12 * last["p_port"]
+    assert abs(last["p_cu"] - sum(o["p_cu"] for o in orders)) <= 1e-12 * last["p_cu"]
+    say(f"    eps_bal {last['eps_bal']:.2e}")
+    assert last["eps_bal"] < 1e-6
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_period_with_plasma_matches_oracle(prec):
+    """One 16-step period with 60k particles per species (the cell's particle
+    time step, f = 1 / (16 dt), MQS, 30 V source) and a second order at
+    ratio 0.5, phase 0.7: the plasma current's harmonics of both orders,
+    their plasma-only fields and reaction voltages, powers, target and
+    relaxed states, and the fundamental's composed field."""
+    _need_gpu()
+    import paper_2609_15043_amd.phasorpic as pp
+    from paper_2609_15043_amd import workloads as W
+    from oracle import pic as O
+    wl = W.cell(n_per_species=60_000)
+    wl.freq = 1.0 / (16 * wl.dt)
+    wl.circuit = dataclasses.replace(wl.circuit, field_mode=W.FIELD_MQS, vg_from_target=False, vg_amp=30.0,
+                                     harmonics=((0.5, 0.7),))
+    say(f"[gpu] multiharmonic period with plasma, cell 60k/species, {prec}")
+    cfg, keep = pp.config_from_workload(wl, precision=prec, load=True)
+    ctx = pp.pic_init(cfg, keep)
+    ora = O.OraclePIC(wl)
+    reps = _run(ctx, ora, 16, 1)
+    tol = 1e-8 if prec == "fp64" else 1e-3
+    o = ora.last_report
+    _compare_all(ctx, reps[-1], o, tol, prec)
+    e = abs(reps[-1]["p_ind"] - o["P_ind"]) / abs(o["P_ind"])
+    assert e <= tol, e
+    for m in (1, 2):
+        assert np.all(np.abs(pp.circuit_order_report(ctx, m)["vp"]) > 0), m
+    for name, grid, ref in (("Ecp", pp.PIC_GRID_EC_PLASMA, ora.fc.fcs[0].Ec_p),
+                            ("Ec", pp.PIC_GRID_EC, ora.ec[0]), ("Es", pp.PIC_GRID_ES, ora.es[0])):
+        e = rel(pp.pic_get_grid(ctx, grid), ref)
+        say(f"    {name} rel {e:.1e}")
+        assert e <= tol, (name, e)
+
+
+def test_multiharmonic_runtime_refusals():
+    """At run time a multiharmonic context refuses pic_set_source (its
+    orders' sources follow from the configuration), prescribed loads and an
+    order outside 1..M, each with PIC_EINVAL and a message, and keeps
+    working afterwards."""
+    _need_gpu()
+    import paper_2609_15043_amd.phasorpic as pp
+    say("[gpu] multiharmonic refusals")
+    cfg, keep = pp.config_from_workload(_vacuum_cell(harmonics=((0.5, 0.7),)), precision="fp64", load=False)
+    ctx = pp.pic_init(cfg, keep)
+    with pytest.raises(pp.PicError, match="configuration"):
+        pp.pic_set_source(ctx, 100.0, 0.0)
+    with pytest.raises(pp.PicError, match="order 3 outside"):
+        pp.circuit_order_report(ctx, 3)
+    st, _, _, _ = pp.circuit_period_update(ctx, loads=(np.zeros(5, complex), np.zeros(5, complex)))
+    assert st == pp.PIC_EINVAL
+    assert "single-frequency" in pp.lib().pic_last_error(ctx.handle).decode()
+    pp.pic_clear_error(ctx)
+    assert pp.circuit_order_report(ctx, 2)["accepted"] == 0
