@@ -1,7 +1,7 @@
 // Surrogate network of the coil-plasma response: three GELU hidden layers
 // of width H between 32-column (padded) inputs and outputs.  BF16 weights
-// and activations on the matrix cores (v_mfma_f32_16x16x16_bf16, FP32
-// accumulation), FP32 master weights, Adam (Kingma & Ba) in FP32.
+// and activations on the matrix cores (gfx950's v_mfma_f32_16x16x32_bf16,
+// FP32 accumulation), FP32 master weights, Adam (Kingma & Ba) in FP32.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -21,7 +21,10 @@ constexpr int PAD = 32;        // padded input / output width
 constexpr int TM = 64, TN = 64, TK = 32, KP = 40;   // GEMM tile and LDS row pitch (bf16 elements)
 constexpr int SPLITK = 16;     // K splits of the weight-gradient products
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+// MFMA operands: eight BF16 values along K per lane (lane l holds row or
+// column l % 16 and the K octet l / 16 of a 32-wide slice; A and B take the
+// same K order, so the dot products do not depend on it)
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 // FP32 -> BF16, round to nearest, ties to even (finite inputs)
@@ -128,17 +131,17 @@ template <typename TA, typename TB, int EPI> __global__ __launch_bounds__(256) v
         }
         __syncthreads();
 #pragma unroll
-        for (int kk = 0; kk < TK; kk += 16) {
-            bf16x4 a[2], b[2];
+        for (int kk = 0; kk < TK; kk += 32) {
+            bf16x8 a[2], b[2];
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
-                a[i] = *reinterpret_cast<const bf16x4 *>(&As[(wm + 16 * i + (lane & 15)) * KP + kk + 4 * (lane >> 4)]);
-                b[i] = *reinterpret_cast<const bf16x4 *>(&Bs[(wn + 16 * i + (lane & 15)) * KP + kk + 4 * (lane >> 4)]);
+                a[i] = *reinterpret_cast<const bf16x8 *>(&As[(wm + 16 * i + (lane & 15)) * KP + kk + 8 * (lane >> 4)]);
+                b[i] = *reinterpret_cast<const bf16x8 *>(&Bs[(wn + 16 * i + (lane & 15)) * KP + kk + 8 * (lane >> 4)]);
             }
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+                for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
         }
         __syncthreads();
     }
@@ -252,18 +255,18 @@ template <typename TA, int EPI, bool AK, bool BK> __global__ __launch_bounds__(2
         if (k0 + VTK < ke) load(k0 + VTK);
         const int kend = ke - k0;   // K blocks past the end hold zeros only
 #pragma unroll
-        for (int kk = 0; kk < VTK; kk += 16) {
+        for (int kk = 0; kk < VTK; kk += 32) {
             if (kk >= kend) break;
-            bf16x4 a[2], b[2];
+            bf16x8 a[2], b[2];
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
-                a[i] = *reinterpret_cast<const bf16x4 *>(&As[(wm + 16 * i + (lane & 15)) * VKP + kk + 4 * (lane >> 4)]);
-                b[i] = *reinterpret_cast<const bf16x4 *>(&Bs[(wn + 16 * i + (lane & 15)) * VKP + kk + 4 * (lane >> 4)]);
+                a[i] = *reinterpret_cast<const bf16x8 *>(&As[(wm + 16 * i + (lane & 15)) * VKP + kk + 8 * (lane >> 4)]);
+                b[i] = *reinterpret_cast<const bf16x8 *>(&Bs[(wn + 16 * i + (lane & 15)) * VKP + kk + 8 * (lane >> 4)]);
             }
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+                for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
         }
         __syncthreads();
     }

@@ -5,6 +5,10 @@ table or passage) and the closed forms of the benchmark definitions:
 
 * Test 1 (single ideal solenoid, Sec. 3.1): the field-derived inductance
   and the current of the series circuit;
+* Test 2 (two coaxial solenoids, Sec. 3.2): the self and mutual inductances
+  from the device's unit fields and projections, and the two-loop phasors
+  (Eqs. S2loops to S2ports) from them, against every printed digit of the
+  model column of its results table;
 * Test 3 (five nested sheets, Sec. 3.3 and its appendix): the extracted
   inductance matrix (relative error against Eq. t7M, reciprocity defect),
   the capacitance matrix from five Laplace basis runs (error against Eq.
@@ -103,6 +107,38 @@ def test_t1_solenoid_inductance_and_current():
     assert abs(Z.imag - T1["ImZ_num_ohm"]) / T1["ImZ_num_ohm"] < 2e-4
     assert abs(abs(I) - T1["I_num_abs_A"]) < 2e-3
     assert abs(math.degrees(np.angle(I)) - T1["I_num_deg"]) < 0.01
+
+
+def test_t2_two_solenoids_mutual_inductance_and_loops():
+    _need_gpu()
+    import paper_2609_15043_amd.phasorpic as pp
+    from paper_2609_15043_amd import workloads as W
+    t = _scalars("test2_solenoids.txt")
+    wl = W.test2()
+    say("[gpu] Test 2: two coaxial solenoids, 120 x 1240 cells, two unit solves through the C ABI")
+    cfg, keep = pp.config_from_workload(wl, precision="fp64", load=False)
+    ctx = pp.pic_init(cfg, keep)
+    ci = pp.pic_get_circuit(ctx)
+    Z, w = ci["zvac"], ci["omega"]
+    assert np.max(np.abs(Z.real)) == 0.0
+    assert abs(Z[0, 1] - Z[1, 0]) <= 1e-10 * abs(Z[0, 1])
+    L = Z.imag / w * 1e9
+    k = L[0, 1] / math.sqrt(L[0, 0] * L[1, 1])
+    # Eqs. S2loops, S2zab, S2solution, S2ports: isolated primary (1 V, 0.1 ohm),
+    # passive secondary (0.1 ohm, 10 nF)
+    ZA, ZB, Zm = 0.1 + Z[0, 0], Z[1, 1] + 0.1 - 1j / (w * 10e-9), Z[0, 1]
+    det = ZA * ZB - Zm * Zm
+    I1, I2 = ZB / det, -Zm / det
+    ph = dict(I1=I1, I2=I2, U1=Z[0, 0] * I1 + Z[0, 1] * I2, U2=Z[1, 0] * I1 + Z[1, 1] * I2)
+    say(f"    L1 {L[0, 0]:.6f} L2 {L[1, 1]:.6f} M {L[0, 1]:.6f} nH, k {k:.6f}; " +
+        " ".join(f"{n} {abs(x):.6g} at {math.degrees(np.angle(x)):.4f}" for n, x in ph.items()))
+    for name, v in (("L1", L[0, 0]), ("L2", L[1, 1]), ("M", L[0, 1])):
+        assert abs(v - t[f"{name}_num_nH"]) <= 1e-6, (name, v)
+    assert abs(k - t["k_num"]) <= 1e-6, k
+    for name, x in ph.items():
+        ulp = 10.0 ** (math.floor(math.log10(t[f"{name}_num_abs"])) - 5)
+        assert abs(abs(x) - t[f"{name}_num_abs"]) <= ulp, (name, abs(x))
+        assert abs(math.degrees(np.angle(x)) - t[f"{name}_num_deg"]) <= 1e-4, name
 
 
 def test_t3_inductance_matrix():
