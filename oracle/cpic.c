@@ -298,6 +298,50 @@ void ora_gather_push(const ora_grid *g, const ora_species *s, int64_t n,
 }
 
 /* ---------------------------------------------------------------------- */
+/* Ion-induced secondary electron emission at the grounded metal walls     */
+/* (the inherited GEC module the paper names without its yields; read here */
+/* as a constant yield per absorbed ion and a flux-weighted Maxwellian      */
+/* electron).  For the m absorbed ions given in ascending id order, at     */
+/* their positions before the step's move (R0, z0) and with the wall they  */
+/* crossed (1 bottom z = 0, 2 top z = zp without a window, 3 outer         */
+/* R = rmax), block (id, n, 4, 0) of the ion stream decides the emission,  */
+/* u0 < gamma, and draws the electron's velocity: normal speed             */
+/* sigma sqrt(-2 ln u1) into the domain (the normal component of a         */
+/* Maxwellian flux through the wall), two tangential components            */
+/* sigma sqrt(-2 ln u2) (cos, sin)(2 pi u3), sigma = sqrt(T e / m_e).      */
+/* Block (id, n, 5, 0) draws the electron's first collision candidate      */
+/* n + G.  Emitted electrons are written in order; returns their count.    */
+/* ---------------------------------------------------------------------- */
+int64_t ora_see(uint32_t seed, uint32_t n, double gamma, double sigma, double lq_e, int64_t m,
+                const uint32_t *id, const double *R0, const double *z0, const int32_t *wall,
+                double *R, double *z, double *v, int32_t *next)
+{
+    int64_t k = 0;
+    for (int64_t p = 0; p < m; ++p) {
+        uint32_t b[4], c[4];
+        draw(seed, 1, id[p], n, 4u, b);
+        if (!(u01(b[0]) < gamma)) continue;
+        const double vn = sigma * sqrt(-2.0 * log(u01(b[1])));
+        const double rt = sigma * sqrt(-2.0 * log(u01(b[2])));
+        const double t1 = rt * cos(2.0 * M_PI * u01(b[3])), t2 = rt * sin(2.0 * M_PI * u01(b[3]));
+        double *o = v + 3 * k;
+        if (wall[p] == 1) {          /* bottom: +z */
+            o[0] = t1; o[1] = t2; o[2] = vn;
+        } else if (wall[p] == 2) {   /* top: -z */
+            o[0] = t1; o[1] = t2; o[2] = -vn;
+        } else {                     /* outer: -R */
+            o[0] = -vn; o[1] = t1; o[2] = t2;
+        }
+        draw(seed, 1, id[p], n, 5u, c);
+        next[k] = clamp_step((int64_t)n + geo_gap(c[0], lq_e));
+        R[k] = R0[p];
+        z[k] = z0[p];
+        ++k;
+    }
+    return k;
+}
+
+/* ---------------------------------------------------------------------- */
 /* Charge deposit at the current positions                                 */
 /* ---------------------------------------------------------------------- */
 void ora_deposit(const ora_grid *g, int64_t n, const double *R, const double *z,

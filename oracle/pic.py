@@ -111,6 +111,10 @@ def lib():
             [ctypes.POINTER(_I32)] * 2
         L.ora_di_predict.argtypes = di + [ctypes.POINTER(_D)] * 3
         L.ora_di_correct.argtypes = di + [ctypes.POINTER(_D)] * 3
+        L.ora_see.argtypes = [_U32, _U32, _D, _D, _D, _I64, ctypes.POINTER(_U32), ctypes.POINTER(_D),
+                              ctypes.POINTER(_D), ctypes.POINTER(_I32), ctypes.POINTER(_D), ctypes.POINTER(_D),
+                              ctypes.POINTER(_D), ctypes.POINTER(_I32)]
+        L.ora_see.restype = _I64
         _LIB = L
     return _LIB
 
@@ -579,14 +583,24 @@ class OraclePIC:
                                theta(n, self.nrf))
         self.I = np.zeros(self.shape)
         self.absorbed = []
+        self.see_pending = None
         for s in range(2):
             P = self.parts[s]
             ab = np.zeros(P.n, np.int32)
+            if s == 1 and self.wl.see_gamma > 0:
+                R0, z0 = P.R.copy(), P.z.copy()
             lib().ora_gather_push(ctypes.byref(self.grid), ctypes.byref(self.sp[s]), P.n,
                                   _p(P.R, _D), _p(P.z, _D), _p(P.vr, _D), _p(P.vt, _D), _p(P.vz, _D),
                                   _p(P.alive, _I32), _p(ab, _I32), _p(Er, _D), _p(Ez, _D), _p(Et, _D),
                                   _p(Br, _D), _p(Bz, _D), _p(self.I, _D), _p(self.surf, _D))
             self.absorbed.append(ab)
+            if s == 1 and self.wl.see_gamma > 0:
+                # ions absorbed at a metal wall (code 1; 2 is the window):
+                # the wall from the position after the move
+                k = np.nonzero(ab == 1)[0]
+                zn = P.z[k]
+                wall = np.where(zn < 0, 1, np.where(zn >= self.wl.zp, 3 if self.wl.window else 2, 3))
+                self.see_pending = (P.id[k].copy(), R0[k], z0[k], wall.astype(np.int32))
 
     def mcc(self, n):
         births = []
@@ -621,6 +635,30 @@ class OraclePIC:
             self.next_id[1] += nb
         self.last_births = (bp, ide if nb else np.zeros(0), idi if nb else np.zeros(0))
         self.births_total += nb
+        self.secondary_emission(n)
+
+    def secondary_emission(self, n):
+        """Electrons emitted by the ions absorbed at metal walls during step
+        n (cpic.c ora_see), in ascending parent-ion id order after the
+        step's ionization births; ids continue the electron counter."""
+        self.see_absorbed, self.see_emitted = np.zeros(0, np.uint32), 0
+        if self.see_pending is None or len(self.see_pending[0]) == 0:
+            return
+        pid, R0, z0, wall = self.see_pending
+        o = np.argsort(pid, kind="stable")
+        pid, R0, z0, wall = (np.ascontiguousarray(a[o]) for a in (pid, R0, z0, wall))
+        m = len(pid)
+        R, z, v, nx = np.zeros(m), np.zeros(m), np.zeros((m, 3)), np.zeros(m, np.int32)
+        sigma = math.sqrt(self.wl.see_temp_ev * self.W.QE / self.W.ME)
+        k = lib().ora_see(_U32(self.wl.seed), _U32(n), float(self.wl.see_gamma), sigma, float(self.lq[0]), m,
+                          _p(pid, _U32), _p(R0, _D), _p(z0, _D), _p(wall, _I32), _p(R, _D), _p(z, _D),
+                          _p(v, _D), _p(nx, _I32))
+        if k:
+            ids = np.arange(self.next_id[0], self.next_id[0] + k, dtype=np.uint64)
+            self.parts[0].append(R[:k], z[:k], v[:k], ids, nx[:k])
+            self.next_id[0] += k
+        self.see_total = getattr(self, "see_total", 0) + k
+        self.see_absorbed, self.see_emitted = pid, k
 
     def deposit(self):
         Q = np.zeros(self.shape)
@@ -764,6 +802,7 @@ class OraclePIC:
     # -- one whole step -----------------------------------------------------------
     def step(self):
         if self.implicit:
+            assert self.wl.see_gamma == 0, "secondary emission runs with the explicit step only"
             return self.step_implicit()
         n = self.n
         self.gather_push(n)
@@ -829,6 +868,19 @@ def gather_push_raw(grid, species, P, Er, Ez, Et):
                           _p(P.vr, _D), _p(P.vt, _D), _p(P.vz, _D), _p(P.alive, _I32), _p(ab, _I32),
                           _p(Er, _D), _p(Ez, _D), _p(Et, _D), None, None, _p(I, _D), _p(surf, _D))
     return I, surf, ab
+
+
+def see_raw(seed, n, gamma, sigma, lq_e, ids, R0, z0, wall):
+    """ora_see on arrays (ids in the order given); returns (R, z, v, next)
+    of the emitted electrons."""
+    ids = np.ascontiguousarray(ids, dtype=np.uint32)
+    R0, z0 = (np.ascontiguousarray(a, dtype=np.float64) for a in (R0, z0))
+    wall = np.ascontiguousarray(wall, dtype=np.int32)
+    m = len(ids)
+    R, z, v, nx = np.zeros(m), np.zeros(m), np.zeros((m, 3)), np.zeros(m, np.int32)
+    k = lib().ora_see(_U32(seed), _U32(n), float(gamma), float(sigma), float(lq_e), m, _p(ids, _U32), _p(R0, _D),
+                      _p(z0, _D), _p(wall, _I32), _p(R, _D), _p(z, _D), _p(v, _D), _p(nx, _I32))
+    return R[:k], z[:k], v[:k], nx[:k]
 
 
 def deposit_raw(grid, P, qw):

@@ -148,6 +148,8 @@ class Workload:
     bfield: tuple = (0.0, 0.0, 0.0)   # uniform (B_r, B_theta, B_z), tests only
     rf_bfield: bool = False           # the RF magnetic field of the applied E_theta in the Boris rotation
     implicit: bool = False            # direct-implicit electrostatic update (D1 filter) instead of explicit
+    see_gamma: float = 0.0            # ion-induced secondary electron yield at the metal walls (0: off)
+    see_temp_ev: float = 2.0          # temperature of the emitted electrons' Maxwellian flux (eV)
     xs: CrossSections = dataclasses.field(default_factory=CrossSections)
     capacity_factor: float = 1.5
     eps0: float = EPS0                # vacuum permittivity of the Poisson operator

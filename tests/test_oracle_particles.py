@@ -703,3 +703,102 @@ def test_push_in_rf_magnetic_field_conserves_speed():
                         _p(np.zeros(shape), _D), _p(np.zeros(shape), _D))
     for k in ("vr", "vt", "vz", "R", "z"):
         np.testing.assert_allclose(getattr(P2, k), getattr(P1, k), rtol=2e-14, atol=1e-300)
+
+
+# ---------------------------------------------------------------------------
+# Ion-induced secondary electron emission (the GEC cell's inherited module;
+# constant yield, flux-weighted Maxwellian electrons)
+# ---------------------------------------------------------------------------
+def test_secondary_emission_yield_and_velocity_laws():
+    """Per absorbed ion an electron is emitted with probability gamma (the
+    emitted count is Binomial(m, gamma)); the decisions are those of block
+    (id, n, 4, 0) of the ion stream (word 0 below gamma); the emitted
+    electron moves into the domain, its normal speed is Rayleigh (mean
+    square 2 sigma^2), its tangential components are N(0, sigma^2), so its
+    mean energy is 2 kT (a Maxwellian flux through a wall); it starts at the
+    ion's position and its first candidate lies after the step."""
+    m, n, seed, gamma, T = 120_000, 37, 11, 0.3, 2.0
+    sigma = math.sqrt(T * W.QE / W.ME)
+    rng = np.random.default_rng(5)
+    ids = np.sort(rng.choice(2 ** 31, m, replace=False)).astype(np.uint32)
+    wall = np.repeat(np.array([1, 2, 3], np.int32), m // 3)
+    R0, z0 = rng.uniform(0, 0.1, m), rng.uniform(0, 0.1, m)
+    lq_e = math.log(1 - 0.02)
+    R, z, v, nx = pic.see_raw(seed, n, gamma, sigma, lq_e, ids, R0, z0, wall)
+    k = len(R)
+    assert abs(k - gamma * m) < 5 * math.sqrt(m * gamma * (1 - gamma))
+    # the decisions, from the pinned generator directly
+    ctr = np.stack([ids, np.full(m, n), np.full(m, 4), np.zeros(m)], axis=1).astype(np.uint32)
+    u0 = (pic.philox(ctr, (seed, 1))[:, 0].astype(np.float64) + 0.5) / 2 ** 32
+    emit = u0 < gamma
+    assert emit.sum() == k
+    np.testing.assert_array_equal(R, R0[emit])
+    np.testing.assert_array_equal(z, z0[emit])
+    we = wall[emit]
+    normal = np.where(we == 1, v[:, 2], np.where(we == 2, -v[:, 2], -v[:, 0]))
+    tang = np.concatenate([v[we != 3][:, :2].ravel(), v[we == 3][:, 1:].ravel()])
+    assert np.all(normal > 0)
+    se = 2 * sigma ** 2 * math.sqrt(1.0 / k)                    # the Rayleigh v_n^2 has std 2 sigma^2
+    assert abs(np.mean(normal ** 2) - 2 * sigma ** 2) < 5 * se
+    assert abs(np.mean(tang)) < 5 * sigma / math.sqrt(len(tang))
+    assert abs(np.var(tang) / sigma ** 2 - 1) < 5 * math.sqrt(2.0 / len(tang))
+    eps = 0.5 * W.ME * np.sum(v ** 2, axis=1) / W.QE
+    assert abs(eps.mean() / (2 * T) - 1) < 5 * math.sqrt(2.0 / k)   # energy 2 kT, std 2 kT / sqrt(2)
+    assert np.all(nx >= n + 1)
+    # gamma = 0 emits nothing, gamma = 1 every absorbed ion
+    assert len(pic.see_raw(seed, n, 0.0, sigma, lq_e, ids, R0, z0, wall)[0]) == 0
+    assert len(pic.see_raw(seed, n, 1.0, sigma, lq_e, ids, R0, z0, wall)[0]) == m
+
+
+def see_workload(gamma=0.5, n_per_species=100_000):
+    """The small instance with hot ions (200 eV), dt = 1 ns and 1e13 m^-3, so
+    that some hundred ions reach the bottom, top and outer walls within a
+    few steps (no window: the top is metal)."""
+    wl = W.small(n_per_species=n_per_species)
+    wl.dt, wl.n0 = 1e-9, 1e13
+    wl.temp_ev = (3.0, 200.0)
+    wl.see_gamma, wl.see_temp_ev = gamma, 2.0
+    return wl
+
+
+def test_secondary_emission_in_the_step():
+    """In the whole step: the electrons emitted in step n sit at the
+    positions the absorbed ions had before the move, take the ids after the
+    step's ionization births in ascending parent-ion id order, and their
+    count is the electrons gained beyond ionization; with gamma = 0 the
+    first step is the plain one, and with gamma > 0 it differs from it by the
+    emitted electrons alone."""
+    wl = see_workload()
+    ora = pic.OraclePIC(wl)
+    plain = pic.OraclePIC(see_workload(0.0))
+    total = 0
+    for n in range(3):
+        Pi = ora.parts[1]
+        pre = {int(i): (r, z) for i, r, z in zip(Pi.id, Pi.R, Pi.z)}
+        ne0 = ora.next_id[0]
+        ora.step()
+        if n == 0:
+            plain.step()
+            np.testing.assert_array_equal(plain.parts[1].id, ora.parts[1].id)
+            np.testing.assert_array_equal(plain.parts[1].R, ora.parts[1].R)
+            Pe, Qe = plain.parts[0], ora.parts[0]
+            assert Qe.n == Pe.n + ora.see_emitted
+            np.testing.assert_array_equal(Pe.R, Qe.R[:Pe.n])
+            np.testing.assert_array_equal(Pe.vz, Qe.vz[:Pe.n])
+        nb = len(ora.last_births[0])
+        k = ora.see_emitted
+        total += k
+        assert ora.next_id[0] == ne0 + nb + k
+        if k:
+            Pe = ora.parts[0]
+            new = (Pe.id >= ne0 + nb) & (Pe.id < ne0 + nb + k)
+            assert new.sum() == k
+            o = np.argsort(Pe.id[new])
+            Rn, zn = Pe.R[new][o], Pe.z[new][o]
+            # each emitted electron at the absorbed ion's pre-move position, in parent order
+            cand = [pre[int(i)] for i in ora.see_absorbed]
+            emitted = [c for c in cand if any(abs(c[0] - r) == 0 and abs(c[1] - zz) == 0 for r, zz in zip(Rn, zn))]
+            assert len(emitted) == k
+            order = [next(t for t, c in enumerate(cand) if c[0] == r and c[1] == zz) for r, zz in zip(Rn, zn)]
+            assert order == sorted(order)
+    assert total > 50
