@@ -204,6 +204,19 @@ typedef struct pic_config {
     int32_t nharm;
     double harm_ratio[3];
     double harm_phase[3];    /* rad */
+    /* Ion-induced secondary electron emission at the grounded metal walls (the GEC cell's inherited
+     * module, Sec. 3.4; its yields are not given): each ion absorbed at the bottom (z = 0), at the top
+     * (z = zp, metal when window == 0) or at the outer wall (R = rmax) emits an electron with probability
+     * see_gamma (0 = off; [0, 1]) -- Philox block (ion id, n, 4, 0) of the ion stream, word 0 below
+     * see_gamma.  The electron starts at the ion's position before the step's move, with a
+     * flux-weighted Maxwellian velocity at see_temp_ev (eV): normal speed sigma sqrt(-2 ln u1) into
+     * the domain, tangential components sigma sqrt(-2 ln u2) (cos, sin)(2 pi u3), sigma = sqrt(T e /
+     * m_e); block (id, n, 5, 0) draws its first collision candidate.  mcc_collide(n) appends the
+     * step's emitted electrons after its ionization births, in ascending parent-ion id order, with
+     * ids continuing the electron counter, and deposits their charge in the fused mode.  At most 65536
+     * ions per step reach a metal wall (PIC_ENOMEM beyond).  Not with implicit. */
+    double see_gamma;
+    double see_temp_ev;
 } pic_config;
 
 typedef struct pic_solve_info {
@@ -245,6 +258,7 @@ typedef struct pic_stats {
     int64_t mg_unconverged;  /* Poisson solves since init that used up their iteration budget before
                                 rtol (the stepping path's budget adapts to the recent counts; a solve
                                 given an info record runs max_cycles and returns PIC_ENOTCONV instead) */
+    int64_t see_emitted;     /* secondary electrons emitted since init (cfg->see_gamma) */
 } pic_stats;
 
 typedef struct pic_ctx pic_ctx;

@@ -528,6 +528,7 @@ class OraclePIC:
         self.sur_cfg = dict(err_max=0.02, tol=1e-6, max_iter=50)
         self.births_total = 0
         self.births_prev = 0
+        self.see_pending = None          # ions of the step at metal walls (secondary emission)
         # retained source harmonics (orders 2..M) of a coupled cell
         self.M = 1 + (len(wl.circuit.harmonics) if wl.circuit is not None else 0)
         if wl.circuit is not None and self.M > 1:

@@ -55,6 +55,26 @@ template <typename T> void carve_parts(Carver &c, Parts<T> &p, int64_t cap, bool
     }
 }
 
+// queue of the ions absorbed at metal walls in one step (secondary emission)
+constexpr int SEE_CAP = 65536;
+template <typename T> void carve_see(Carver &c, SeeQueue<T> &q, const pic_config &f)
+{
+    q = SeeQueue<T>{};
+    if (!(f.see_gamma > 0.0)) return;
+    q.parent = c.take<uint32_t>(SEE_CAP);
+    q.cell = c.take<int32_t>(SEE_CAP);
+    q.dr = c.take<T>(SEE_CAP);
+    q.dz = c.take<T>(SEE_CAP);
+    q.wall = c.take<int32_t>(SEE_CAP);
+    q.rank = c.take<int32_t>(SEE_CAP);
+    q.count = c.take<int32_t>(2);
+    q.cap = SEE_CAP;
+    // emit iff word x < thr: (x + 1/2) 2^-32 < gamma <=> x < ceil(gamma 2^32 - 1/2)
+    const double y = f.see_gamma * 4294967296.0 - 0.5;
+    q.thr = y <= 0.0 ? 0ull : (unsigned long long)std::ceil(y);
+    q.sigma = std::sqrt(f.see_temp_ev * f.qe / f.m[0]);
+}
+
 template <typename T> void carve_births(Carver &c, Births<T> &b, int cap)
 {
     b.parent = c.take<uint32_t>(cap);
@@ -111,6 +131,8 @@ struct pic_ctx {
     Parts<double> pd[2][2];
     int cur[2] = {0, 0};
     Births<float> bf{};
+    SeeQueue<float> sqf{};       // ions at metal walls of the step (secondary emission; cap 0: off)
+    SeeQueue<double> sqd{};
     Births<double> bd{};
     CandQueue cq[2]{};
     int64_t *ctl = nullptr;      // count[2], count_old[2], next_id[2], nlive, pad
@@ -496,10 +518,13 @@ static void layout(pic_ctx &c, Carver &cv)
                 carve_parts(cv, c.pd[s][b], f.capacity[s], f.implicit != 0);
         }
     const int bcap = f.birth_capacity > 0 ? f.birth_capacity : 65536;
-    if (c.mixed)
+    if (c.mixed) {
         carve_births(cv, c.bf, bcap);
-    else
+        carve_see(cv, c.sqf, f);
+    } else {
         carve_births(cv, c.bd, bcap);
+        carve_see(cv, c.sqd, f);
+    }
     for (int s = 0; s < 2; ++s) {
         const double expect = c.pnull[s] * (double)f.capacity[s];
         const int64_t qc = std::min<int64_t>(f.capacity[s], (int64_t)(4.0 * expect + 16.0 * std::sqrt(expect + 1.0)) + 4096);
@@ -708,6 +733,13 @@ static pic_status check_config(const pic_config *f, pic_ctx *c)
     if (f->birth_capacity < 0) return fail(c, PIC_EINVAL, "birth_capacity < 0");
     if (f->implicit && (f->rf_bfield || f->bfield[0] != 0.0 || f->bfield[1] != 0.0 || f->bfield[2] != 0.0))
         return fail(c, PIC_EINVAL, "the direct-implicit update runs without magnetic field");
+    if (!(f->see_gamma >= 0.0 && f->see_gamma <= 1.0))
+        return fail(c, PIC_EINVAL, "see_gamma must lie in [0, 1]");
+    if (f->see_gamma > 0.0) {
+        if (!(f->see_temp_ev > 0.0 && std::isfinite(f->see_temp_ev)))
+            return fail(c, PIC_EINVAL, "see_temp_ev must be positive");
+        if (f->implicit) return fail(c, PIC_EINVAL, "secondary emission runs with the explicit step only");
+    }
     if (f->nharm < 0 || f->nharm > MAX_HARM - 1)
         return fail(c, PIC_EINVAL, "nharm outside 0..%d", MAX_HARM - 1);
     if (f->nharm > 0) {
@@ -808,6 +840,9 @@ template <> Parts<double> &parts<double>(pic_ctx &c, int s, int b) { return c.pd
 template <typename T> static Births<T> &births(pic_ctx &c);
 template <> Births<float> &births<float>(pic_ctx &c) { return c.bf; }
 template <> Births<double> &births<double>(pic_ctx &c) { return c.bd; }
+template <typename T> static SeeQueue<T> &see_queue(pic_ctx &c);
+template <> SeeQueue<float> &see_queue<float>(pic_ctx &c) { return c.sqf; }
+template <> SeeQueue<double> &see_queue<double>(pic_ctx &c) { return c.sqd; }
 
 template <typename T> static PassArgs<T> pass_args(pic_ctx &c, int s, int64_t step)
 {
@@ -826,6 +861,7 @@ template <typename T> static PassArgs<T> pass_args(pic_ctx &c, int s, int64_t st
     a.sc = c.sc[s];
     a.mc = c.mc;
     a.b = births<T>(c);
+    if (s == 1) a.see = see_queue<T>(c);   // ions only; cap 0 keeps emission off
     a.step = (int32_t)step;
     return a;
 }
@@ -878,11 +914,17 @@ template <typename T> static void run_collide(pic_ctx &c, int64_t n)
     for (int s = 0; s < 2; ++s) launch_collide<T>(pass_args<T>(c, s, n), c.stream);
 }
 
-template <typename T> static void run_births(pic_ctx &c, bool deposit)
+template <typename T> static void run_births(pic_ctx &c, bool deposit, int64_t n = 0)
 {
     launch_births<T>(births<T>(c), parts<T>(c, 0, c.cur[0]), parts<T>(c, 1, c.cur[1]), c.ctl, c.ctl + 4,
                      c.cfg.capacity[0], c.cfg.capacity[1], c.accQ, c.accQ + c.g.nodes, deposit, c.qscale, c.g,
                      c.errw, c.stats, c.cq[0].count, c.cq[1].count, c.stream);
+    // secondary electrons of the step's ions at metal walls, after the
+    // ionization births
+    const SeeQueue<T> &q = see_queue<T>(c);
+    if (q.cap > 0)
+        launch_see<T>(q, parts<T>(c, 0, c.cur[0]), c.ctl, c.ctl + 4, c.cfg.capacity[0], c.accQ, deposit, c.qscale,
+                      c.g, c.errw, c.stats, c.cfg.seed, (int32_t)n, c.lq[0], c.stream);
 }
 
 // with_chi: the direct-implicit susceptibility of the deposited (predicted)
@@ -1424,6 +1466,10 @@ template <typename T> static pic_status init_impl(pic_ctx &c)
     HIPCHK(&c, hipMemsetAsync(c.hist, 0, (c.g.ncells + 1) * sizeof(int32_t), st));
     HIPCHK(&c, hipMemsetAsync(births<T>(c).count, 0, sizeof(int32_t), st));
     HIPCHK(&c, hipMemsetAsync(births<T>(c).rank, 0, (size_t)births<T>(c).cap * sizeof(int32_t), st));
+    if (see_queue<T>(c).cap > 0) {
+        HIPCHK(&c, hipMemsetAsync(see_queue<T>(c).count, 0, 2 * sizeof(int32_t), st));
+        HIPCHK(&c, hipMemsetAsync(see_queue<T>(c).rank, 0, (size_t)see_queue<T>(c).cap * sizeof(int32_t), st));
+    }
     for (int s2 = 0; s2 < 2; ++s2) HIPCHK(&c, hipMemsetAsync(c.cq[s2].count, 0, sizeof(int32_t), st));
     HIPCHK(&c, hipMemsetAsync(c.accS, 0, 2 * (size_t)nodes * sizeof(double), st));
     HIPCHK(&c, hipMemsetAsync(c.accW, 0, 2 * (size_t)nodes * sizeof(long long), st));
@@ -1629,6 +1675,7 @@ static pic_status sticky(pic_ctx *c)
     HIPCHK(c, hipMemcpyAsync(&e, c->errw, sizeof e, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if (e & ERR_BIRTH_OVERFLOW) return fail(c, PIC_ENOMEM, "birth buffer overflow (raise birth_capacity)");
+    if (e & ERR_SEE_OVERFLOW) return fail(c, PIC_ENOMEM, "more than 65536 ions reached a metal wall in one step");
     if (e & ERR_CAPACITY) return fail(c, PIC_ENOMEM, "particle capacity exceeded");
     if (e & ERR_QUEUE_OVERFLOW) return fail(c, PIC_ENOMEM, "collision-candidate queue overflow");
     return PIC_OK;
@@ -1693,10 +1740,10 @@ extern "C" pic_status mcc_collide(pic_ctx *c, int64_t n)
     const bool fuse = c->cfg.fuse != 0;
     if (c->mixed) {
         run_collide<float>(*c, n);
-        run_births<float>(*c, fuse);
+        run_births<float>(*c, fuse, n);
     } else {
         run_collide<double>(*c, n);
-        run_births<double>(*c, fuse);
+        run_births<double>(*c, fuse, n);
     }
     c->last_mcc = n;
     return hipGetLastError() == hipSuccess ? PIC_OK : fail(c, PIC_EDEVICE, "kernel launch failed");
@@ -2618,6 +2665,7 @@ extern "C" pic_status pic_get_stats(pic_ctx *c, pic_stats *o)
     o->births = (int64_t)st[ST_BIRTHS];
     o->window_out = (int64_t)st[ST_WINOUT];
     o->mg_unconverged = (int64_t)st[ST_MGUNCONV];
+    o->see_emitted = (int64_t)st[ST_SEE];
     HarmState h;
     HIPCHK(c, cpy(c->stream, &h, c->harm, sizeof h, hipMemcpyDeviceToHost));
     o->samples = h.samples;

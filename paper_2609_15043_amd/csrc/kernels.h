@@ -46,11 +46,12 @@ enum StatSlot {
     ST_OVER0, ST_OVER1,
     ST_WINOUT,
     ST_MGUNCONV,                        // Poisson solves that ended before rtol
+    ST_SEE,                             // secondary electrons emitted
     ST_NSTAT
 };
 
 // Device flags (int32) of the error word.
-enum ErrFlag { ERR_BIRTH_OVERFLOW = 1, ERR_CAPACITY = 2, ERR_MG_NOTCONV = 4, ERR_QUEUE_OVERFLOW = 8 };
+enum ErrFlag { ERR_BIRTH_OVERFLOW = 1, ERR_CAPACITY = 2, ERR_MG_NOTCONV = 4, ERR_QUEUE_OVERFLOW = 8, ERR_SEE_OVERFLOW = 16 };
 
 struct GridC {
     int nr, nz, nr1, nodes, ncells, ip, window;
@@ -130,6 +131,23 @@ struct CandQueue {
     int32_t cap;
 };
 
+// Ions absorbed at a metal wall during the step (ion-induced secondary
+// emission): parent id, cell and offsets before the move, the wall (1 bottom,
+// 2 top without a window, 3 outer).  count[0]: records queued by the pass,
+// count[1]: emitters among them.  cap == 0: emission off.
+template <typename T> struct SeeQueue {
+    uint32_t *parent;
+    int32_t *cell;
+    T *dr, *dz;
+    int32_t *wall;
+    int32_t *rank;          // ranks being counted; zero between steps
+    int32_t *count;
+    int32_t cap;
+    uint32_t pad;
+    unsigned long long thr; // emit iff Philox word 0 < thr, i.e. (x + 1/2) 2^-32 < gamma
+    double sigma;           // sqrt(T e / m_e) of the emitted electrons
+};
+
 template <typename T> struct PassArgs {
     Parts<T> p;
     CandQueue q;
@@ -145,6 +163,7 @@ template <typename T> struct PassArgs {
     SpeciesC sc;
     MccC mc;
     Births<T> b;
+    SeeQueue<T> see;
     int32_t step;
 };
 

@@ -31,6 +31,10 @@ void launch_births(const Births<T> &b, const Parts<T> &pe, const Parts<T> &pi, i
                    int64_t cap_e, int64_t cap_i, long long *accQe, long long *accQi, bool deposit, double qscale,
                    const GridC &g, int32_t *err, unsigned long long *stats, int32_t *q0, int32_t *q1, hipStream_t st);
 template <typename T>
+void launch_see(const SeeQueue<T> &q, const Parts<T> &pe, int64_t *count, int64_t *next_id, int64_t cap_e,
+                long long *accQe, bool deposit, double qscale, const GridC &g, int32_t *err, unsigned long long *stats,
+                uint32_t seed, int32_t step, double lq_e, hipStream_t st);
+template <typename T>
 void launch_sort(const Parts<T> &src, const Parts<T> &dst, int64_t *count, int64_t *count_old, int32_t *hist,
                  int32_t *cursor, int64_t *scanpart, int ncells, int64_t cap, hipStream_t st);
 int sort_scan_blocks(int ncells);

@@ -681,6 +681,20 @@ __global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassPair<T> p
                 } else if (jn >= g.nr || jn < 0) {
                     absorbed = 1;
                 }
+                if (absorbed == 1 && a.see.cap > 0 && hyp == hyp && bz == bz) {
+                    // an ion at a metal wall: queued for secondary emission
+                    // with its position before the move
+                    const int slot = atomicAdd(a.see.count, 1);
+                    if (slot < a.see.cap) {
+                        a.see.parent[slot] = a.p.id[q0 + k];
+                        a.see.cell[slot] = i * g.nr + j;
+                        a.see.dr[slot] = dr[k];
+                        a.see.dz[slot] = dz[k];
+                        a.see.wall[slot] = in < 0 ? 1 : (in >= g.ip && !g.window ? 2 : 3);
+                    } else {
+                        atomicOr(a.err, (int)ERR_SEE_OVERFLOW);
+                    }
+                }
                 if (absorbed) abs_bits |= 1u << k;
                 live[k] = absorbed == 0;
                 const int32_t cn = live[k] ? in * g.nr + jn : -1;
@@ -1086,6 +1100,98 @@ __global__ __launch_bounds__(256) void k_births(Births<T> b, Parts<T> pe, Parts<
             atomic_add_i64(&accQi[nd[q]], f);
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Ion-induced secondary electron emission (constant yield gamma per ion
+// absorbed at a metal wall; flux-weighted Maxwellian electron).  Block (ion
+// id, n, 4, 0) of the ion stream decides (word 0 below gamma) and draws the
+// velocity: normal speed sigma sqrt(-2 ln u1) into the domain, tangential
+// sigma sqrt(-2 ln u2) (cos, sin)(2 pi u3); block (id, n, 5, 0) the first
+// candidate.  The electrons are appended after the step's ionization births
+// in ascending parent-ion id order (k_birth_rank over the queued ids, the
+// non-emitters' ids replaced by the largest value) at the position the ion
+// had before the move, and their charge is deposited with `deposit`.
+// ---------------------------------------------------------------------------
+template <typename T> __global__ void k_see_decide(SeeQueue<T> q, uint32_t seed, int32_t step)
+{
+    const int S = min(q.count[0], q.cap);
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= S) return;
+    const U4 b = philox10(U4{q.parent[t], (uint32_t)step, 4u, 0u}, seed, 1u);
+    if ((unsigned long long)b.x < q.thr)
+        atomicAdd(&q.count[1], 1);
+    else
+        q.parent[t] = 0xFFFFFFFFu;
+}
+
+template <typename T>
+__global__ void k_see_births(SeeQueue<T> q, Parts<T> pe, const int64_t *count, const int64_t *next_id, int64_t cap_e,
+                             long long *accQe, int deposit, double qscale, GridC g, int32_t *err, uint32_t seed,
+                             int32_t step, double lq_e)
+{
+    const int S = min(q.count[0], q.cap);
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= S) return;
+    const int rank = q.rank[t];
+    q.rank[t] = 0;   // zero again for the next step
+    const uint32_t id = q.parent[t];
+    if (id == 0xFFFFFFFFu) return;
+    const int E = q.count[1];
+    if (count[0] + E > cap_e) {
+        atomicOr(err, (int)ERR_CAPACITY);
+        return;
+    }
+    const U4 b = philox10(U4{id, (uint32_t)step, 4u, 0u}, seed, 1u);
+    const U4 c = philox10(U4{id, (uint32_t)step, 5u, 0u}, seed, 1u);
+    const double vn = q.sigma * sqrt(-2.0 * log(unit(b.y)));
+    const double rt = q.sigma * sqrt(-2.0 * log(unit(b.z)));
+    double sp, cp;
+    sincos(2.0 * PI * unit(b.w), &sp, &cp);
+    const double t1 = rt * cp, t2 = rt * sp;
+    const int wall = q.wall[t];
+    double v[3];
+    if (wall == 1) {
+        v[0] = t1, v[1] = t2, v[2] = vn;
+    } else if (wall == 2) {
+        v[0] = t1, v[1] = t2, v[2] = -vn;
+    } else {
+        v[0] = -vn, v[1] = t1, v[2] = t2;
+    }
+    const int64_t o = count[0] + rank;
+    const int32_t cl = q.cell[t];
+    const T dr = q.dr[t], dz = q.dz[t];
+    pe.cell[o] = cl;
+    pe.dr[o] = dr;
+    pe.dz[o] = dz;
+    pe.vr[o] = (T)v[0];
+    pe.vt[o] = (T)v[1];
+    pe.vz[o] = (T)v[2];
+    pe.id[o] = (uint32_t)(next_id[0] + rank);
+    pe.next[o] = next_candidate(step, c.x, lq_e);
+    if (pe.fr) pe.fr[o] = pe.ft[o] = pe.fz[o] = (T)0;
+    if (deposit) {
+        const int ii = cl / g.nr, jj = cl - ii * g.nr;
+        const T fj = (T)jj;
+        const T wr1 = dr * ((T)2 * fj + dr) / ((T)2 * fj + (T)1);
+        const T w[4] = {((T)1 - dz) * ((T)1 - wr1), ((T)1 - dz) * wr1, dz * ((T)1 - wr1), dz * wr1};
+        const int k0 = ii * g.nr1 + jj;
+        const int nd[4] = {k0, k0 + 1, k0 + g.nr1, k0 + g.nr1 + 1};
+        for (int e = 0; e < 4; ++e) atomic_add_i64(&accQe[nd[e]], to_fixed((double)w[e], qscale));
+    }
+}
+
+__global__ void k_see_commit(int32_t *qcount, int64_t *count, int64_t *next_id, int64_t cap_e,
+                             unsigned long long *stats)
+{
+    const int E = qcount[1];
+    if (E > 0 && count[0] + E <= cap_e) {
+        count[0] += E;
+        next_id[0] += E;
+        stats[ST_SEE] += (unsigned long long)E;
+    }
+    qcount[0] = 0;
+    qcount[1] = 0;
 }
 
 // Commit of the step's births, and the collision queues emptied for the
@@ -1545,6 +1651,19 @@ void launch_births(const Births<T> &b, const Parts<T> &pe, const Parts<T> &pi, i
 }
 
 template <typename T>
+void launch_see(const SeeQueue<T> &q, const Parts<T> &pe, int64_t *count, int64_t *next_id, int64_t cap_e,
+                long long *accQe, bool deposit, double qscale, const GridC &g, int32_t *err, unsigned long long *stats,
+                uint32_t seed, int32_t step, double lq_e, hipStream_t st)
+{
+    const unsigned nb = blocks_for(q.cap, 256);
+    hipLaunchKernelGGL(k_see_decide<T>, dim3(nb), dim3(256), 0, st, q, seed, step);
+    hipLaunchKernelGGL(k_birth_rank, dim3(nb, BIRTH_SLICES), dim3(256), 0, st, q.parent, q.count, q.cap, q.rank);
+    hipLaunchKernelGGL(k_see_births<T>, dim3(nb), dim3(256), 0, st, q, pe, count, next_id, cap_e, accQe,
+                       deposit ? 1 : 0, qscale, g, err, seed, step, lq_e);
+    hipLaunchKernelGGL(k_see_commit, dim3(1), dim3(1), 0, st, q.count, count, next_id, cap_e, stats);
+}
+
+template <typename T>
 void launch_sort(const Parts<T> &src, const Parts<T> &dst, int64_t *count, int64_t *count_old, int32_t *hist,
                  int32_t *cursor, int64_t *scanpart, int ncells, int64_t cap, hipStream_t st)
 {
@@ -1574,7 +1693,10 @@ int sort_scan_blocks(int ncells) { return (int)blocks_for(ncells, SCAN_BLOCK); }
                                    int64_t, int64_t, long long *, long long *, bool, double, const GridC &,         \
                                    int32_t *, unsigned long long *, int32_t *, int32_t *, hipStream_t);             \
     template void launch_sort<T>(const Parts<T> &, const Parts<T> &, int64_t *, int64_t *, int32_t *, int32_t *,    \
-                                 int64_t *, int, int64_t, hipStream_t);
+                                 int64_t *, int, int64_t, hipStream_t);                                             \
+    template void launch_see<T>(const SeeQueue<T> &, const Parts<T> &, int64_t *, int64_t *, int64_t, long long *,   \
+                                bool, double, const GridC &, int32_t *, unsigned long long *, uint32_t, int32_t,     \
+                                double, hipStream_t);
 
 PIC_INSTANTIATE(float)
 PIC_INSTANTIATE(double)

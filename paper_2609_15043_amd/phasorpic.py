@@ -54,6 +54,7 @@ class PicConfig(ctypes.Structure):
         ("sort_every_ion", _I32), ("dir_basis", _PD), ("unit_bvals", _PD), ("rf_bfield", _I32),
         ("implicit", _I32), ("poisson_solver", _I32),
         ("nharm", _I32), ("harm_ratio", _D * 3), ("harm_phase", _D * 3),
+        ("see_gamma", _D), ("see_temp_ev", _D),
     ]
 
 
@@ -70,7 +71,7 @@ class PicStats(ctypes.Structure):
         ("qc", _D * 16), ("qs", _D * 16), ("wk", _D * 16), ("qk", _D * 16),
         ("pass_ms", _D), ("pass_count", _I64), ("poisson_ms", _D), ("poisson_count", _I64),
         ("sort_ms", _D), ("sort_count", _I64), ("circuit_ms", _D), ("circuit_count", _I64),
-        ("mg_cycles", _I64), ("mg_rel", _D), ("mg_unconverged", _I64),
+        ("mg_cycles", _I64), ("mg_rel", _D), ("mg_unconverged", _I64), ("see_emitted", _I64),
     ]
 
 
@@ -216,6 +217,7 @@ def config_from_workload(wl, precision="mixed", fuse=True, load=True, mg_rtol=No
     c.sort_every_ion = sort_every_ion
     c.rf_bfield = 1 if wl.rf_bfield else 0
     c.implicit = 1 if wl.implicit else 0
+    c.see_gamma, c.see_temp_ev = wl.see_gamma, wl.see_temp_ev
     c.poisson_solver = {"auto": PIC_POISSON_AUTO, "multigrid": PIC_POISSON_MULTIGRID,
                         "direct": PIC_POISSON_DIRECT}[poisson_solver]
     c.birth_capacity = birth_capacity

@@ -148,3 +148,25 @@ def test_linearised_charge_relation():
         pred = -(_apply_op(ora.poisson, ora.phi, chi) - _apply_op(ora.poisson, ora.phi))[m]
         ratio = float(dQ @ pred / (pred @ pred))
         assert abs(ratio - 1.0) < 0.03, (mode, ratio)
+
+
+def test_whole_implicit_steps_conserve_charge_and_ids():
+    """Three whole direct-implicit steps of the small instance (predictor,
+    charge and chi at the predicted positions, solve with chi, corrector,
+    collisions and births): the node charge is the live particles' charge
+    (no window, so sum Q = q_e w N_e + q_i w N_i), and every birth adds one
+    electron and one ion with fresh ids."""
+    wl = W.small(n_per_species=20_000)
+    wl.implicit = True
+    ora = pic.OraclePIC(wl)
+    for _ in range(3):
+        ne0, ni0 = ora.next_id
+        ora.step()
+        nb = len(ora.last_births[0])
+        assert ora.next_id == [ne0 + nb, ni0 + nb]
+        ids = [ora.live(s)["id"] for s in range(2)]
+        assert all(len(np.unique(i)) == len(i) for i in ids)
+    Q = ora.deposit()
+    live = [ora.live(s) for s in range(2)]
+    tot = sum(wl.charge[s] * wl.weight[s] * len(live[s]["id"]) for s in range(2))
+    assert abs(Q.sum() - tot) <= 1e-12 * wl.weight[0] * W.QE * (len(live[0]["id"]) + len(live[1]["id"]))
