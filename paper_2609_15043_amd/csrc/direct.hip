@@ -11,8 +11,8 @@
 //   k_dp_gemm    B~ = B V (rows of the block times the radial eigenvectors);
 //   k_dp_pcr     the tridiagonal system of each mode by parallel cyclic
 //                reduction in LDS (one workgroup per mode);
-//   k_dp_xd, k_dp_src, k_dp_w: (S b)_D, s = C^{-1} (phi_D - (S b)_D), and
-//                the sources transformed by V^T;
+//   k_dp_cap     (S b)_D, s = C^{-1} (phi_D - (S b)_D), and the sources
+//                transformed by V^T (one workgroup);
 //   k_dp_correct the modes' response to those sources (precomputed unit
 //                responses g), added;
 //   k_dp_gemm    phi = U V^T on the block (Dirichlet nodes get their values).
@@ -69,20 +69,30 @@ __global__ __launch_bounds__(256) void k_dp_rhs(DirectArgs a)
 }
 
 // C = A op(B) with A m x kk (row-major), op(B) kk x nn: B as stored
-// (B[k * nn + c]) or transposed (B[c * kk + k]).  One wave per 16 x 16 tile
-// of C (2 x 2 per lane), kk in slices of 64 through LDS; the next slice's
-// loads are issued before the current slice is multiplied, so their latency
-// hides behind the arithmetic.  to_phi: C row r is block row r + 1 of phi
-// (columns 0..nr-1), Dirichlet nodes of the block taking their values.
-constexpr int GT = 16, GK = 64, GE = GT * GK / 64;   // tile, slice, elements per lane and operand
+// (B[k * nn + c]) or transposed (B[c * kk + k]).  One workgroup of GW waves
+// per 16 x 16 tile of C (2 x 2 per lane): wave w takes the w-th of GW
+// contiguous parts of kk in slices of GK through its own LDS, the next
+// slice's loads issued before the current slice is multiplied; the partial
+// sums are added in wave order at the end, so the result does not depend on
+// timing.  Splitting kk shortens each lane's chain of dependent FMAs by GW
+// and puts GW times as many waves on the chip (the products are small:
+// latency, not arithmetic, bounds them).  to_phi: C row r is block row
+// r + 1 of phi (columns 0..nr-1), Dirichlet nodes of the block taking their
+// values.
+constexpr int GT = 16, GK = 32, GW = 4, GE = GT * GK / 64;   // tile, slice, waves, elements per lane and operand
 template <bool TRANS_B, bool TO_PHI>
-__global__ __launch_bounds__(64) void k_dp_gemm(const double *A, const double *B, double *C, int m, int nn, int kk,
-                                                DirectArgs a)
+__global__ __launch_bounds__(GW * 64) void k_dp_gemm(const double *A, const double *B, double *C, int m, int nn,
+                                                     int kk, DirectArgs a)
 {
-    __shared__ double As[GT][GK + 1];   // [row][k]
-    __shared__ double Bs[GK][GT + 1];   // [k][column]
-    const int lane = threadIdx.x, tx = lane % 8, ty = lane / 8;
+    __shared__ double As[GW][GT][GK + 1];   // [wave][row][k]
+    __shared__ double Bs[GW][GK][GT + 1];   // [wave][k][column]
+    __shared__ double red[GW - 1][GT * GT];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, tx = lane % 8, ty = lane / 8;
     const int r0 = blockIdx.y * GT, c0 = blockIdx.x * GT;
+    // this wave's part of kk; every wave runs the same number of slices (a
+    // slice past the part's end holds zeros)
+    const int part = (kk + GW - 1) / GW, nsl = (part + GK - 1) / GK;
+    const int kb = wave * part, ke = min(kk, kb + part);
     double ra[GE], rb[GE];
     auto fetch = [&](int k0) {
 #pragma unroll
@@ -90,7 +100,7 @@ __global__ __launch_bounds__(64) void k_dp_gemm(const double *A, const double *B
             const int idx = e * 64 + lane;
             const int rr = idx / GK, q = idx % GK;   // A: consecutive lanes, consecutive k
             const int gr = r0 + rr, gk = k0 + q;
-            ra[e] = (gr < m && gk < kk) ? A[(size_t)gr * kk + gk] : 0.0;
+            ra[e] = (gr < m && gk < ke) ? A[(size_t)gr * kk + gk] : 0.0;
             int bq, bc;
             if (TRANS_B) {   // consecutive lanes, consecutive k of one column
                 bc = idx / GK;
@@ -100,27 +110,28 @@ __global__ __launch_bounds__(64) void k_dp_gemm(const double *A, const double *B
                 bc = idx % GT;
             }
             const int hk = k0 + bq, hc = c0 + bc;
-            rb[e] = (hk < kk && hc < nn) ? (TRANS_B ? B[(size_t)hc * kk + hk] : B[(size_t)hk * nn + hc]) : 0.0;
+            rb[e] = (hk < ke && hc < nn) ? (TRANS_B ? B[(size_t)hc * kk + hk] : B[(size_t)hk * nn + hc]) : 0.0;
         }
     };
     double acc00 = 0.0, acc01 = 0.0, acc10 = 0.0, acc11 = 0.0;
-    fetch(0);
-    for (int k0 = 0; k0 < kk; k0 += GK) {
+    fetch(kb);
+    for (int sl = 0; sl < nsl; ++sl) {
+        const int k0 = kb + sl * GK;
 #pragma unroll
         for (int e = 0; e < GE; ++e) {
             const int idx = e * 64 + lane;
-            As[idx / GK][idx % GK] = ra[e];
+            As[wave][idx / GK][idx % GK] = ra[e];
             if (TRANS_B)
-                Bs[idx % GK][idx / GK] = rb[e];
+                Bs[wave][idx % GK][idx / GK] = rb[e];
             else
-                Bs[idx / GT][idx % GT] = rb[e];
+                Bs[wave][idx / GT][idx % GT] = rb[e];
         }
         __syncthreads();
-        if (k0 + GK < kk) fetch(k0 + GK);
+        if (sl + 1 < nsl) fetch(k0 + GK);
 #pragma unroll 16
         for (int q = 0; q < GK; ++q) {
-            const double x0 = As[2 * ty][q], x1 = As[2 * ty + 1][q];
-            const double y0 = Bs[q][2 * tx], y1 = Bs[q][2 * tx + 1];
+            const double x0 = As[wave][2 * ty][q], x1 = As[wave][2 * ty + 1][q];
+            const double y0 = Bs[wave][q][2 * tx], y1 = Bs[wave][q][2 * tx + 1];
             acc00 = fma(x0, y0, acc00);
             acc01 = fma(x0, y1, acc01);
             acc10 = fma(x1, y0, acc10);
@@ -128,7 +139,20 @@ __global__ __launch_bounds__(64) void k_dp_gemm(const double *A, const double *B
         }
         __syncthreads();
     }
-    const double acc[2][2] = {{acc00, acc01}, {acc10, acc11}};
+    const int e0 = 2 * ty * GT + 2 * tx;
+    if (wave > 0) {
+        double *rw = red[wave - 1];
+        rw[e0] = acc00;
+        rw[e0 + 1] = acc01;
+        rw[e0 + GT] = acc10;
+        rw[e0 + GT + 1] = acc11;
+    }
+    __syncthreads();
+    if (wave > 0) return;
+    double acc[2][2] = {{acc00, acc01}, {acc10, acc11}};
+    for (int v = 0; v < GW - 1; ++v)
+        for (int u = 0; u < 2; ++u)
+            for (int w = 0; w < 2; ++w) acc[u][w] += red[v][e0 + u * GT + w];
     for (int u = 0; u < 2; ++u)
         for (int w = 0; w < 2; ++w) {
             const int gr = r0 + 2 * ty + u, gc = c0 + 2 * tx + w;
@@ -193,51 +217,53 @@ __global__ __launch_bounds__(256) void k_dp_pcr(DirectArgs a)
     for (int r = threadIdx.x; r < ni; r += blockDim.x) a.u[(size_t)r * nj + k] = D0[r] / B0[r];
 }
 
-// The capacitance step, spread over the chip in three kernels (each a
-// fixed-order reduction per output, so the result is the same every run):
-// k_dp_xd: res_d = phi_D - (V u)_d at each interior Dirichlet node (one
-// wave per node); k_dp_src: s = C^{-1} res (one wave per row of C^{-1});
-// k_dp_w: w(q, k) = sum over the nodes d of row rows[q] of s_d V(j_d, k)
-// (one lane per (q, k); the nodes of a row are a contiguous range).
+// sum over the wave in a fixed butterfly order (the same result every run)
 __device__ __forceinline__ double wave_sum(double x)
 {
     for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
     return x;
 }
 
-__global__ __launch_bounds__(64) void k_dp_xd(DirectArgs a)
+// The capacitance step in one workgroup (the three stages are small and
+// depend on each other as a whole): (S b)_D at every Dirichlet node and the
+// residual phi_D - (S b)_D (one wave per node, lane-strided dot product and
+// a fixed butterfly); the sources s = C^{-1} res (one wave per row of
+// C^{-1}); their transforms w_q = sum over the nodes d of row q of
+// s_d V[j_d, :] (one lane per coefficient, nodes in order).  res and s stay
+// in LDS.
+__global__ __launch_bounds__(1024) void k_dp_cap(DirectArgs a)
 {
-    const int d = blockIdx.x, lane = threadIdx.x, nj = a.nj, nr1 = a.nr + 1;
-    const int n = a.dnode[d], i = n / nr1, j = n - i * nr1;
-    const double *u = a.u + (size_t)(i - 1) * nj;
-    const double *v = a.v + (size_t)j * nj;
-    double x = 0.0;
-    for (int k = lane; k < nj; k += 64) x = fma(v[k], u[k], x);
-    x = wave_sum(x);
-    if (lane == 0) a.res[d] = dirichlet_value(a, n) - x;
-}
-
-__global__ __launch_bounds__(64) void k_dp_src(DirectArgs a)
-{
-    const int d = blockIdx.x, lane = threadIdx.x, m = a.m;
-    const double *ci = a.cinv + (size_t)d * m;
-    double s = 0.0;
-    for (int e = lane; e < m; e += 64) s = fma(ci[e], a.res[e], s);
-    s = wave_sum(s);
-    if (lane == 0) a.src[d] = s;
-}
-
-__global__ __launch_bounds__(256) void k_dp_w(DirectArgs a)
-{
-    const int t = blockIdx.x * blockDim.x + threadIdx.x, nj = a.nj, nr1 = a.nr + 1;
-    if (t >= a.nrow * nj) return;
-    const int q = t / nj, k = t - q * nj;
-    double w = 0.0;
-    for (int d = a.rowstart[q]; d < a.rowstart[q + 1]; ++d) {
-        const int n = a.dnode[d], j = n - (n / nr1) * nr1;
-        w = fma(a.src[d], a.v[(size_t)j * nj + k], w);
+    __shared__ double sres[DP_MAX_DIRICHLET_DEV], ssrc[DP_MAX_DIRICHLET_DEV];
+    __shared__ int scol[DP_MAX_DIRICHLET_DEV];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    const int nj = a.nj, nr1 = a.nr + 1, m = a.m;
+    for (int d = wave; d < m; d += nw) {
+        const int n = a.dnode[d], i = n / nr1, j = n - i * nr1;
+        const double *u = a.u + (size_t)(i - 1) * nj;
+        const double *v = a.v + (size_t)j * nj;
+        double x = 0.0;
+        for (int k = lane; k < nj; k += 64) x = fma(v[k], u[k], x);
+        x = wave_sum(x);
+        if (lane == 0) {
+            sres[d] = dirichlet_value(a, n) - x;
+            scol[d] = j;
+        }
     }
-    a.w[t] = w;
+    __syncthreads();
+    for (int d = wave; d < m; d += nw) {
+        const double *ci = a.cinv + (size_t)d * m;
+        double s = 0.0;
+        for (int e = lane; e < m; e += 64) s = fma(ci[e], sres[e], s);
+        s = wave_sum(s);
+        if (lane == 0) ssrc[d] = s;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < a.nrow * nj; t += blockDim.x) {
+        const int q = t / nj, k = t - q * nj;
+        double w = 0.0;
+        for (int d = a.rowstart[q]; d < a.rowstart[q + 1]; ++d) w = fma(ssrc[d], a.v[(size_t)scol[d] * nj + k], w);
+        a.w[t] = w;
+    }
 }
 
 // u += sum_q g_q w_q: the modes' response to the capacitance sources
@@ -258,18 +284,16 @@ void launch_direct_solve(const DirectArgs &a, hipStream_t st)
     hipLaunchKernelGGL(k_dp_rhs, dim3((a.nodes + 255) / 256), dim3(256), 0, st, a);
     const dim3 g((a.nj + GT - 1) / GT, (a.ni + GT - 1) / GT);
     // B~ = B V into u, then the mode solves in place
-    hipLaunchKernelGGL((k_dp_gemm<false, false>), g, dim3(64), 0, st, (const double *)a.b, a.v, a.u, a.ni, a.nj,
-                       a.nj, a);
+    hipLaunchKernelGGL((k_dp_gemm<false, false>), g, dim3(GW * 64), 0, st, (const double *)a.b, a.v, a.u, a.ni,
+                       a.nj, a.nj, a);
     hipLaunchKernelGGL(k_dp_pcr, dim3(a.nj), dim3(256), 8 * (size_t)a.ni * sizeof(double), st, a);
     if (a.m > 0) {
-        hipLaunchKernelGGL(k_dp_xd, dim3(a.m), dim3(64), 0, st, a);
-        hipLaunchKernelGGL(k_dp_src, dim3(a.m), dim3(64), 0, st, a);
-        hipLaunchKernelGGL(k_dp_w, dim3((a.nrow * a.nj + 255) / 256), dim3(256), 0, st, a);
+        hipLaunchKernelGGL(k_dp_cap, dim3(1), dim3(1024), 0, st, a);
         const size_t tot = (size_t)a.ni * a.nj;
         hipLaunchKernelGGL(k_dp_correct, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, a);
     }
-    hipLaunchKernelGGL((k_dp_gemm<true, true>), g, dim3(64), 0, st, (const double *)a.u, a.v, (double *)nullptr,
-                       a.ni, a.nj, a.nj, a);
+    hipLaunchKernelGGL((k_dp_gemm<true, true>), g, dim3(GW * 64), 0, st, (const double *)a.u, a.v,
+                       (double *)nullptr, a.ni, a.nj, a.nj, a);
 }
 
 }  // namespace pic

@@ -704,28 +704,25 @@ __global__ __launch_bounds__(256) void k_pcg_update(MGLevel L, PCGVec v, const d
 // Q_k = sum over faces (turn-k node p, outside node q) of c (phi_p - phi_q);
 // one workgroup, per-thread partial sums per turn, tree reduction in a
 // fixed order (the face list is sorted by turn-node index on the host)
-__global__ __launch_bounds__(256) void k_face_charge(const double *phi, const int32_t *fp, const int32_t *fq,
-                                                     const int32_t *fk, const double *fc, int nfaces, double *Qk,
-                                                     int nturns, const double *chi)
+// One wave per turn (nturns waves in one workgroup): each lane sums its
+// share of the turn's faces in list order, then a fixed butterfly across the
+// wave; no barriers.
+__global__ __launch_bounds__(1024) void k_face_charge(const double *phi, const int32_t *fp, const int32_t *fq,
+                                                      const int32_t *fk, const double *fc, int nfaces, double *Qk,
+                                                      int nturns, const double *chi)
 {
-    __shared__ double red[256];
-    for (int k = 0; k < nturns; ++k) {
-        double s = 0.0;
-        for (int f = threadIdx.x; f < nfaces; f += 256)
-            if (fk[f] == k) {
-                // the solve's own face coefficient, the susceptibility included (Eq. facecharge)
-                const double x = chi ? 1.0 + 0.5 * (chi[fp[f]] + chi[fq[f]]) : 1.0;
-                s += fc[f] * x * (phi[fp[f]] - phi[fq[f]]);
-            }
-        red[threadIdx.x] = s;
-        __syncthreads();
-        for (int off = 128; off > 0; off >>= 1) {
-            if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-            __syncthreads();
+    const int k = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (k >= nturns) return;
+    double s = 0.0;
+    for (int f = lane; f < nfaces; f += 64)
+        if (fk[f] == k) {
+            // the solve's own face coefficient, the susceptibility included (Eq. facecharge)
+            const double x = chi ? 1.0 + 0.5 * (chi[fp[f]] + chi[fq[f]]) : 1.0;
+            s += fc[f] * x * (phi[fp[f]] - phi[fq[f]]);
         }
-        if (threadIdx.x == 0) Qk[k] = red[0];
-        __syncthreads();
-    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) Qk[k] = s;
 }
 
 // ---------------------------------------------------------------------------
@@ -859,7 +856,8 @@ void launch_pcg_update(const MGLevel &L, const PCGVec &v, const double *p, const
 void launch_face_charge(const double *phi, const int32_t *fp, const int32_t *fq, const int32_t *fk, const double *fc,
                         int nfaces, double *Qk, int nturns, hipStream_t s, const double *chi)
 {
-    hipLaunchKernelGGL(k_face_charge, dim3(1), dim3(256), 0, s, phi, fp, fq, fk, fc, nfaces, Qk, nturns, chi);
+    hipLaunchKernelGGL(k_face_charge, dim3(1), dim3(64 * (nturns > 0 ? nturns : 1)), 0, s, phi, fp, fq, fk, fc, nfaces,
+                       Qk, nturns, chi);
 }
 
 }  // namespace pic
