@@ -584,6 +584,8 @@ static void layout(pic_ctx &c, Carver &cv)
             d.drow = cv.take<int32_t>(m);
             d.rows = cv.take<int32_t>(nrow);
             d.rowstart = cv.take<int32_t>(nrow + 1);
+            d.res = cv.take<double>(m);
+            d.src = cv.take<double>(m);
             d.b = cv.take<double>((size_t)ni * nj);
             d.u = cv.take<double>((size_t)ni * nj);
             d.w = cv.take<double>((size_t)std::max(nrow, 1) * nj);

@@ -11,8 +11,8 @@
 //   k_dp_gemm    B~ = B V (rows of the block times the radial eigenvectors);
 //   k_dp_pcr     the tridiagonal system of each mode by parallel cyclic
 //                reduction in LDS (one workgroup per mode);
-//   k_dp_cap     (S b)_D, s = C^{-1} (phi_D - (S b)_D), and the sources
-//                transformed by V^T (one workgroup);
+//   k_dp_xd, k_dp_src, k_dp_w: (S b)_D, s = C^{-1} (phi_D - (S b)_D), and
+//                the sources transformed by V^T;
 //   k_dp_correct the modes' response to those sources (precomputed unit
 //                responses g), added;
 //   k_dp_gemm    phi = U V^T on the block (Dirichlet nodes get their values).
@@ -217,53 +217,63 @@ __global__ __launch_bounds__(256) void k_dp_pcr(DirectArgs a)
     for (int r = threadIdx.x; r < ni; r += blockDim.x) a.u[(size_t)r * nj + k] = D0[r] / B0[r];
 }
 
-// sum over the wave in a fixed butterfly order (the same result every run)
+// The capacitance step, spread over the chip in three kernels (each a
+// fixed-order reduction per output, so the result is the same every run):
+// k_dp_xd: res_d = phi_D - (V u)_d at each interior Dirichlet node (one
+// wave per node); k_dp_src: s = C^{-1} res (one wave per row of C^{-1});
+// k_dp_w: w(q, k) = sum over the nodes d of row rows[q] of s_d V(j_d, k)
+// (one lane per (q, k); the nodes of a row are a contiguous range).
 __device__ __forceinline__ double wave_sum(double x)
 {
     for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
     return x;
 }
 
-// The capacitance step in one workgroup (the three stages are small and
-// depend on each other as a whole): (S b)_D at every Dirichlet node and the
-// residual phi_D - (S b)_D (one wave per node, lane-strided dot product and
-// a fixed butterfly); the sources s = C^{-1} res (one wave per row of
-// C^{-1}); their transforms w_q = sum over the nodes d of row q of
-// s_d V[j_d, :] (one lane per coefficient, nodes in order).  res and s stay
-// in LDS.
-__global__ __launch_bounds__(1024) void k_dp_cap(DirectArgs a)
+__global__ __launch_bounds__(64) void k_dp_xd(DirectArgs a)
 {
-    __shared__ double sres[DP_MAX_DIRICHLET_DEV], ssrc[DP_MAX_DIRICHLET_DEV];
-    __shared__ int scol[DP_MAX_DIRICHLET_DEV];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
-    const int nj = a.nj, nr1 = a.nr + 1, m = a.m;
-    for (int d = wave; d < m; d += nw) {
-        const int n = a.dnode[d], i = n / nr1, j = n - i * nr1;
-        const double *u = a.u + (size_t)(i - 1) * nj;
-        const double *v = a.v + (size_t)j * nj;
-        double x = 0.0;
-        for (int k = lane; k < nj; k += 64) x = fma(v[k], u[k], x);
-        x = wave_sum(x);
-        if (lane == 0) {
-            sres[d] = dirichlet_value(a, n) - x;
-            scol[d] = j;
+    const int d = blockIdx.x, lane = threadIdx.x, nj = a.nj, nr1 = a.nr + 1;
+    const int n = a.dnode[d], i = n / nr1, j = n - i * nr1;
+    const double *u = a.u + (size_t)(i - 1) * nj;
+    const double *v = a.v + (size_t)j * nj;
+    double x = 0.0;
+    for (int k = lane; k < nj; k += 64) x = fma(v[k], u[k], x);
+    x = wave_sum(x);
+    if (lane == 0) a.res[d] = dirichlet_value(a, n) - x;
+}
+
+__global__ __launch_bounds__(64) void k_dp_src(DirectArgs a)
+{
+    const int d = blockIdx.x, lane = threadIdx.x, m = a.m;
+    const double *ci = a.cinv + (size_t)d * m;
+    double s = 0.0;
+    for (int e = lane; e < m; e += 64) s = fma(ci[e], a.res[e], s);
+    s = wave_sum(s);
+    if (lane == 0) a.src[d] = s;
+}
+
+__global__ __launch_bounds__(256) void k_dp_w(DirectArgs a)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x, nj = a.nj, nr1 = a.nr + 1;
+    if (t >= a.nrow * nj) return;
+    const int q = t / nj, k = t - q * nj;
+    const int d0 = a.rowstart[q], d1 = a.rowstart[q + 1];
+    double w = 0.0;
+    // the row's nodes in batches of 8: all loads of a batch are issued
+    // before its FMAs (which keep the node order)
+    for (int d = d0; d < d1; d += 8) {
+        double sv[8], vv[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int dd = d + e < d1 ? d + e : d0;
+            const int n = a.dnode[dd], j = n - (n / nr1) * nr1;
+            sv[e] = a.src[dd];
+            vv[e] = a.v[(size_t)j * nj + k];
         }
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+            if (d + e < d1) w = fma(sv[e], vv[e], w);
     }
-    __syncthreads();
-    for (int d = wave; d < m; d += nw) {
-        const double *ci = a.cinv + (size_t)d * m;
-        double s = 0.0;
-        for (int e = lane; e < m; e += 64) s = fma(ci[e], sres[e], s);
-        s = wave_sum(s);
-        if (lane == 0) ssrc[d] = s;
-    }
-    __syncthreads();
-    for (int t = threadIdx.x; t < a.nrow * nj; t += blockDim.x) {
-        const int q = t / nj, k = t - q * nj;
-        double w = 0.0;
-        for (int d = a.rowstart[q]; d < a.rowstart[q + 1]; ++d) w = fma(ssrc[d], a.v[(size_t)scol[d] * nj + k], w);
-        a.w[t] = w;
-    }
+    a.w[t] = w;
 }
 
 // u += sum_q g_q w_q: the modes' response to the capacitance sources
@@ -288,7 +298,9 @@ void launch_direct_solve(const DirectArgs &a, hipStream_t st)
                        a.nj, a.nj, a);
     hipLaunchKernelGGL(k_dp_pcr, dim3(a.nj), dim3(256), 8 * (size_t)a.ni * sizeof(double), st, a);
     if (a.m > 0) {
-        hipLaunchKernelGGL(k_dp_cap, dim3(1), dim3(1024), 0, st, a);
+        hipLaunchKernelGGL(k_dp_xd, dim3(a.m), dim3(64), 0, st, a);
+        hipLaunchKernelGGL(k_dp_src, dim3(a.m), dim3(64), 0, st, a);
+        hipLaunchKernelGGL(k_dp_w, dim3((a.nrow * a.nj + 255) / 256), dim3(256), 0, st, a);
         const size_t tot = (size_t)a.ni * a.nj;
         hipLaunchKernelGGL(k_dp_correct, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, a);
     }

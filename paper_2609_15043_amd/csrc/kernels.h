@@ -297,6 +297,7 @@ struct DirectArgs {
     const int32_t *dnode, *drow, *rows;     // interior Dirichlet nodes, their row index, the distinct rows
     const int32_t *rowstart;                // nrow + 1: the nodes of row q are dnode[rowstart[q] .. rowstart[q+1])
     double *b, *u, *w;                      // ni x nj right-hand side, ni x nj modes, nrow x nj sources
+    double *res, *src;                      // m: phi_D - (S b)_D, and the capacitance sources
 };
 
 // features of the surrogate network: (I_k re, im), (V_k re, im), pressure,
