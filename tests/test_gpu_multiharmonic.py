@@ -209,3 +209,50 @@ def test_multiharmonic_runtime_refusals():
     assert "single-frequency" in pp.lib().pic_last_error(ctx.handle).decode()
     pp.pic_clear_error(ctx)
     assert pp.circuit_order_report(ctx, 2)["accepted"] == 0
+
+
+def test_checkpoint_restore_with_retained_orders():
+    """A two-order run on the vacuum coil cell stopped mid-period (after one
+    update), checkpointed and resumed in a fresh context gives the second
+    update bit for bit: every order's network record, accumulators, fields
+    and turn potentials travel in the checkpoint; a context with another
+    number of orders refuses it."""
+    _need_gpu()
+    import paper_2609_15043_amd.phasorpic as pp
+    wl = _vacuum_cell(harmonics=((0.6, -0.4),), controller=True, vg_from_target=True, p_target=60.0, alpha=0.3)
+    say("[gpu] multiharmonic checkpoint at step 24 and restore")
+    cfg, keep = pp.config_from_workload(wl, precision="fp64", load=False)
+
+    def steps(ctx, n0, n1):
+        rep = None
+        for n in range(n0, n1):
+            pp.pic_gather_push(ctx, n)
+            pp.harmonic_accumulate(ctx, n)
+            pp.mcc_collide(ctx, n)
+            pp.pic_deposit(ctx, n + 1)
+            if (n + 1) % 16 == 0:
+                st, rep, _, _ = pp.circuit_period_update(ctx)
+                assert st == 0
+            pp.poisson_solve_rz(ctx, n + 1)
+        return rep
+
+    a = pp.pic_init(cfg, keep)
+    steps(a, 0, 24)
+    ck = pp.pic_checkpoint(a)
+    ra = steps(a, 24, 32)
+    b = pp.pic_init(cfg, keep)
+    pp.pic_restore(b, ck)
+    rb = steps(b, 24, 32)
+    for m in range(2):
+        oa, ob = ra["orders"][m], rb["orders"][m]
+        for k in ("x", "x_target", "x_prev", "icap", "vg"):
+            assert np.array_equal(oa[k], ob[k]), (m, k)
+        assert oa["p_port"] == ob["p_port"]
+    assert ra["p_port"] == rb["p_port"] and ra["eps_bal"] == rb["eps_bal"]
+    assert np.array_equal(pp.pic_get_grid(a, pp.PIC_GRID_PHI), pp.pic_get_grid(b, pp.PIC_GRID_PHI))
+    say(f"    checkpoint {len(ck) / 1e6:.2f} MB; second update identical")
+    one, keep1 = pp.config_from_workload(_vacuum_cell(controller=True, vg_from_target=True, p_target=60.0,
+                                                       alpha=0.3), precision="fp64", load=False)
+    c = pp.pic_init(one, keep1)
+    with pytest.raises(pp.PicError):
+        pp.pic_restore(c, ck)
