@@ -62,13 +62,16 @@ def run_gpu(wl, prec, steps, warmup, fuse=True):
     def one(n):
         pp.pic_gather_push(ctx, n)
         pp.harmonic_accumulate(ctx, n)
-        pp.mcc_collide(ctx, n)
+        if not wl.implicit:
+            pp.mcc_collide(ctx, n)
         pp.pic_deposit(ctx, n + 1)
         if (n + 1) % nrf == 0:
             st, rep, _, _ = pp.circuit_period_update(ctx)
             if st != 0:
                 raise RuntimeError(f"period update status {st}")
         pp.poisson_solve_rz(ctx, n + 1)
+        if wl.implicit:   # corrector, collisions and births after the solve with chi
+            pp.mcc_collide(ctx, n)
 
     for _ in range(warmup):
         one(n)
@@ -658,6 +661,40 @@ def accuracy(name="large"):
     return out
 
 
+def next_steps(name, steps, warmup):
+    """The widened rows on the benchmark workload, FP32-mixed, each timed like
+    the main run over `steps` steps: the direct-implicit update (predictor,
+    chi, multigrid-CG with chi, corrector), the RF magnetic field in the push,
+    the multiharmonic circuit (a second order at half the fundamental's
+    amplitude, magnetoquasistatic operator; the first period update falls
+    after 2000 steps, so the timed steps take the order sums in the gathers,
+    the harmonics and the Poisson boundary values) and secondary emission
+    (yield 0.1).  For the explicit legs the pass moves the same 52 B per
+    particle as the main run."""
+    import dataclasses
+    from paper_2609_15043_amd import workloads as W
+    out = {}
+    legs = [("direct_implicit", dict(implicit=True)), ("rf_bfield", dict(rf_bfield=True)),
+            ("multiharmonic", dict(harmonics=((0.5, 0.7),))), ("secondary_emission", dict(see_gamma=0.1))]
+    for leg, kw in legs:
+        wl = workload(name)
+        if "harmonics" in kw:
+            wl.circuit = dataclasses.replace(wl.circuit, field_mode=W.FIELD_MQS, harmonics=kw["harmonics"])
+        else:
+            for k, v in kw.items():
+                setattr(wl, k, v)
+        r = run_gpu(wl, "mixed", steps, warmup)
+        q = {"value": r["rate"], "unit": "particle-steps/s", "ms_per_step": r["ms_per_step"], "steps": steps,
+             "pass_ms": r["pass_ms"], "poisson_ms": r["poisson_ms"], "mg_cycles_last_solve": r["mg_cycles"]}
+        if leg != "direct_implicit":
+            q["pass_hbm_frac"] = BYTES_PER_PARTICLE_STEP["mixed"] * r["mean_live"] / (r["pass_ms"] * 1e-3) / 1e9 \
+                / HBM_PEAK_GBS
+        out[leg] = q
+        print(f"[bench] next step {leg}: {r['rate']:.4g} particle-steps/s, {r['ms_per_step']:.3f} ms/step, "
+              f"pass {r['pass_ms']:.3f} ms, poisson {r['poisson_ms']:.3f} ms", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -670,6 +707,9 @@ def main():
     ap.add_argument("--no-stationary", action="store_true", help="skip the wall-seconds-to-stationary leg")
     ap.add_argument("--no-mlp", action="store_true", help="skip the surrogate network's kernel timing")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the mixed-against-FP64 accuracy block")
+    ap.add_argument("--next-steps", type=int, default=400, metavar="STEPS",
+                    help="timed steps of each widened row (direct-implicit, RF magnetic field, multiharmonic, "
+                         "secondary emission); 0 skips them")
     ap.add_argument("--cpu-scale", type=int, default=4)
     ap.add_argument("--cpu-steps", type=int, default=15)
     ap.add_argument("--split", action="store_true", help="unfused pass (parity-isolation mode)")
@@ -765,6 +805,9 @@ def main():
         acc = accuracy(args.workload)
         print("[bench] accuracy: " + " ".join(f"{k} {v:.2e}" for k, v in acc.items() if isinstance(v, float)),
               file=sys.stderr, flush=True)
+    nxt = None
+    if args.next_steps > 0:
+        nxt = next_steps(args.workload, args.next_steps, args.warmup)
     cpu = None
     if not args.no_cpu_baseline:
         print(f"[bench] cpu baseline: oracle on 1/{args.cpu_scale} of {wl.name}, {args.cpu_steps} steps",
@@ -779,7 +822,7 @@ def main():
                    "fused": not args.split},
         "roofline": roofline, "step_hbm": step_hbm, "stationary_circuit": stat,
         "stationary_circuit_vacuum": stat_vac, "surrogate_mlp": mlp,
-        "cpu_baseline": cpu, "accuracy": acc,
+        "cpu_baseline": cpu, "accuracy": acc, "next_steps": nxt,
         "breakdown_ms": {"pass": r["pass_ms"], "poisson": r["poisson_ms"], "sort_per_species": r["sort_ms"],
                          "window_fallback_atomics": r["window_out"],
                          "species_sorts_per_step": r["sort_count"] / max(1, r["steps"]),

@@ -842,99 +842,163 @@ __global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassPair<T> p
 // zero passes through the axis (radial and azimuthal components reversed).
 // Absorption as in the push, the window crossing taken on the correction
 // segment; the step's collision candidates are queued here (the velocity
-// is final only now).  One thread per particle slot; one grid for both
-// species, the first nb0 blocks the electrons'.
+// is final only now).  Four consecutive particle slots per lane; one grid
+// for both species, the first nb0 blocks the electrons'.
 // ---------------------------------------------------------------------------
 template <typename T> __global__ __launch_bounds__(256) void k_correct(PassPair<T> pp)
 {
     const int sp = (int)blockIdx.x >= pp.nb0 ? 1 : 0;
     const PassArgs<T> &a = pp.a[sp];
-    const int64_t p = ((int64_t)blockIdx.x - (sp ? pp.nb0 : 0)) * blockDim.x + threadIdx.x;
-    if (p >= *a.count) return;
-    const int32_t cl = a.p.cell[p];
-    if (cl < 0) return;
+    // four consecutive particles per lane (16-byte vector loads and stores;
+    // capacities are whole chunks, so the four slots exist)
+    const int64_t b0 = 4 * ((int64_t)blockIdx.x - (sp ? pp.nb0 : 0)) * blockDim.x;
+    const int64_t p0 = b0 + 4 * (int64_t)threadIdx.x;
+    const int64_t n = *a.count;
+    if (b0 >= n) return;   // the whole block past the live slots
     using F4 = typename Field4<T>::type;
     const GridC g = a.g;
-    int i, j;
-    split_cell(g, cl, i, j);
-    const T dr0 = a.p.dr[p], dz0 = a.p.dz[p];
-    T w00, w01, w10, w11;
-    node_weights<T>(j, dr0, dz0, w00, w01, w10, w11);
-    const int key = i * g.nr1 + j;
-    const F4 f00 = a.ef[key], f01 = a.ef[key + 1], f10 = a.ef[key + g.nr1], f11 = a.ef[key + g.nr1 + 1];
-    const T er = w00 * f00.x + w01 * f01.x + w10 * f10.x + w11 * f11.x;
-    const T ez = w00 * f00.y + w01 * f01.y + w10 * f10.y + w11 * f11.y;
-    const T h = sc_val<T>(a.sc.h, a.sc.hf);
-    const T kr = h * er, kz = h * ez;
-    const T dtr = sc_val<T>(a.sc.dtr, a.sc.dtrf), dtz = sc_val<T>(a.sc.dtz, a.sc.dtzf);
-    T rel = (T)j + (dr0 + kr * dtr);
-    const T bz = dz0 + kz * dtz;
-    T vr = a.p.vr[p] + kr, vt = a.p.vt[p], vz = a.p.vz[p] + kz;
-    T fr = (T)0.5 * (kr + a.p.fr[p]), ft = (T)0.5 * a.p.ft[p], fz = (T)0.5 * (kz + a.p.fz[p]);
-    if (rel < (T)0) {
-        rel = -rel;
-        vr = -vr;
-        vt = -vt;
-        fr = -fr;
-        ft = -ft;
-    }
-    const T fj = floor(rel);
-    int jn = (int)fj;
-    T drn = rel - fj;
-    if (drn >= (T)1) {
-        drn -= (T)1;
-        jn += 1;
-    }
-    const T fzz = floor(bz);
-    int in = i + (int)fzz;
-    T dzn = bz - fzz;
-    if (dzn >= (T)1) {
-        dzn -= (T)1;
-        in += 1;
-    }
-    int absorbed = 0;
-    if (!(rel == rel) || !(bz == bz) || in < 0) {
-        absorbed = 1;
-    } else if (in >= g.ip) {
-        absorbed = 1;
-        if (g.window && kz > (T)0) {
-            // crossing of z = zp on the correction segment (FP64)
-            const double frac = ((double)g.ip - ((double)i + (double)dz0)) / ((double)kz * a.sc.dtz);
-            const double Rs = fabs((double)j + (double)dr0 + frac * (double)kr * a.sc.dtr);
-            if (Rs < (double)g.nr) {
-                int js = (int)floor(Rs);
-                js = min(js, g.nr - 1);
-                const double w1 = (Rs * Rs - (double)js * js) / (2.0 * js + 1.0);
-                const int nd = g.ip * g.nr1 + js;
-                atomic_add_i64(&a.accW[nd], to_fixed(1.0 - w1, a.sc.qscale));
-                atomic_add_i64(&a.accW[nd + 1], to_fixed(w1, a.sc.qscale));
+    // every lane reaches the block-aggregated counts at the end
+    bool absd[4] = {false, false, false, false}, cand[4] = {false, false, false, false};
+    T vr[4], vt[4], vz[4];
+    if (p0 < n) {
+        int32_t cell[4], nxt[4];
+        T dr[4], dz[4], fr[4], ft[4], fz[4];
+        ld4(a.p.cell + p0, cell);
+        ld4(a.p.dr + p0, dr);
+        ld4(a.p.dz + p0, dz);
+        ld4(a.p.vr + p0, vr);
+        ld4(a.p.vt + p0, vt);
+        ld4(a.p.vz + p0, vz);
+        ld4(a.p.fr + p0, fr);
+        ld4(a.p.ft + p0, ft);
+        ld4(a.p.fz + p0, fz);
+        ld4(a.p.next + p0, nxt);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (p0 + k >= n || cell[k] < 0) continue;
+            int i, j;
+            split_cell(g, cell[k], i, j);
+            const T dr0 = dr[k], dz0 = dz[k];
+            T w00, w01, w10, w11;
+            node_weights<T>(j, dr0, dz0, w00, w01, w10, w11);
+            const int key = i * g.nr1 + j;
+            const F4 f00 = a.ef[key], f01 = a.ef[key + 1], f10 = a.ef[key + g.nr1], f11 = a.ef[key + g.nr1 + 1];
+            const T er = w00 * f00.x + w01 * f01.x + w10 * f10.x + w11 * f11.x;
+            const T ez = w00 * f00.y + w01 * f01.y + w10 * f10.y + w11 * f11.y;
+            const T h = sc_val<T>(a.sc.h, a.sc.hf);
+            const T kr = h * er, kz = h * ez;
+            const T dtr = sc_val<T>(a.sc.dtr, a.sc.dtrf), dtz = sc_val<T>(a.sc.dtz, a.sc.dtzf);
+            T rel = (T)j + (dr0 + kr * dtr);
+            const T bz = dz0 + kz * dtz;
+            vr[k] += kr;
+            vz[k] += kz;
+            fr[k] = (T)0.5 * (kr + fr[k]);
+            ft[k] = (T)0.5 * ft[k];
+            fz[k] = (T)0.5 * (kz + fz[k]);
+            if (rel < (T)0) {
+                rel = -rel;
+                vr[k] = -vr[k];
+                vt[k] = -vt[k];
+                fr[k] = -fr[k];
+                ft[k] = -ft[k];
             }
+            const T fj = floor(rel);
+            int jn = (int)fj;
+            T drn = rel - fj;
+            if (drn >= (T)1) {
+                drn -= (T)1;
+                jn += 1;
+            }
+            const T fzz = floor(bz);
+            int in = i + (int)fzz;
+            T dzn = bz - fzz;
+            if (dzn >= (T)1) {
+                dzn -= (T)1;
+                in += 1;
+            }
+            // absorption as one flat predicate and the cell as a plain select
+            // (a nested if/else chain here let the compiler store the column
+            // index in place of -1 for particles past the outer wall)
+            const bool finite = rel == rel && bz == bz;
+            const bool absorbed = !finite || in < 0 || in >= g.ip || jn >= g.nr;
+            if (finite && in >= g.ip && g.window && kz > (T)0) {
+                // crossing of z = zp on the correction segment (FP64)
+                const double frac = ((double)g.ip - ((double)i + (double)dz0)) / ((double)kz * a.sc.dtz);
+                const double Rs = fabs((double)j + (double)dr0 + frac * (double)kr * a.sc.dtr);
+                if (Rs < (double)g.nr) {
+                    int js = (int)floor(Rs);
+                    js = min(js, g.nr - 1);
+                    const double w1 = (Rs * Rs - (double)js * js) / (2.0 * js + 1.0);
+                    const int nd = g.ip * g.nr1 + js;
+                    atomic_add_i64(&a.accW[nd], to_fixed(1.0 - w1, a.sc.qscale));
+                    atomic_add_i64(&a.accW[nd + 1], to_fixed(w1, a.sc.qscale));
+                }
+            }
+            cell[k] = absorbed ? -1 : in * g.nr + jn;
+            dr[k] = drn;
+            dz[k] = dzn;
+            absd[k] = absorbed;
+            cand[k] = !absorbed && nxt[k] == a.step;
         }
-    } else if (jn >= g.nr) {
-        absorbed = 1;
+        st4(a.p.cell + p0, cell);
+        st4(a.p.dr + p0, dr);
+        st4(a.p.dz + p0, dz);
+        st4(a.p.vr + p0, vr);
+        st4(a.p.vt + p0, vt);
+        st4(a.p.vz + p0, vz);
+        st4(a.p.fr + p0, fr);
+        st4(a.p.ft + p0, ft);
+        st4(a.p.fz + p0, fz);
     }
-    a.p.cell[p] = absorbed ? -1 : in * g.nr + jn;
-    a.p.dr[p] = drn;
-    a.p.dz[p] = dzn;
-    a.p.vr[p] = vr;
-    a.p.vt[p] = vt;
-    a.p.vz[p] = vz;
-    a.p.fr[p] = fr;
-    a.p.ft[p] = ft;
-    a.p.fz[p] = fz;
-    if (absorbed) {
-        atomicAdd(&a.stats[ST_ABS0 + a.sc.s], 1ull);
-    } else if (a.p.next[p] == a.step) {
-        const int gs = atomicAdd(a.q.count, 1);
+    // absorbed count and queue slots: one global atomic per block (a counter
+    // taken per lane, or per wave and run position, serialises the grid on
+    // one address); the lane's candidates take consecutive slots after those
+    // of the lanes below it
+    __shared__ int s_wq[4];
+    __shared__ unsigned s_wa[4];
+    __shared__ int s_qbase;
+    const int wv = (int)threadIdx.x >> 6;
+    int before = 0, wtot = 0;
+    unsigned atot = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint64_t cm = ballot(cand[k]);
+        before += (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(cm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)cm, 0u));
+        wtot += (int)__popcll(cm);
+        atot += (unsigned)__popcll(ballot(absd[k]));
+    }
+    if (lane_id() == 0) {
+        s_wq[wv] = wtot;
+        s_wa[wv] = atot;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int tot = 0;
+        unsigned ab = 0;
+        for (int w = 0; w < 4; ++w) {
+            const int c = s_wq[w];
+            s_wq[w] = tot;
+            tot += c;
+            ab += s_wa[w];
+        }
+        s_qbase = tot ? atomicAdd(a.q.count, tot) : 0;
+        if (ab) atomicAdd(&a.stats[ST_ABS0 + a.sc.s], (unsigned long long)ab);
+    }
+    __syncthreads();
+    int gs = s_qbase + s_wq[wv] + before;
+    T *qv = static_cast<T *>(a.q.vel);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (!cand[k]) continue;
         if (gs < a.q.cap) {
-            T *qv = static_cast<T *>(a.q.vel);
-            a.q.idx[gs] = (int32_t)p;
-            qv[gs] = vr;
-            qv[a.q.cap + gs] = vt;
-            qv[2 * a.q.cap + gs] = vz;
+            a.q.idx[gs] = (int32_t)(p0 + k);
+            qv[gs] = vr[k];
+            qv[a.q.cap + gs] = vt[k];
+            qv[2 * a.q.cap + gs] = vz[k];
         } else {
             atomicOr(a.err, (int)ERR_QUEUE_OVERFLOW);
         }
+        ++gs;
     }
 }
 
@@ -1628,8 +1692,10 @@ void launch_correct(const PassArgs<T> &e, const PassArgs<T> &i, int64_t cap_e, i
     PassPair<T> pp;
     pp.a[0] = e;
     pp.a[1] = i;
-    pp.nb0 = blocks_for(cap_e, 256);
-    hipLaunchKernelGGL(k_correct<T>, dim3(pp.nb0 + blocks_for(cap_i, 256)), dim3(256), 0, st, pp);
+    // four particles per lane (the arrays are padded to whole 4096-particle
+    // chunks, so the last lane's four slots exist)
+    pp.nb0 = blocks_for((cap_e + 3) / 4, 256);
+    hipLaunchKernelGGL(k_correct<T>, dim3(pp.nb0 + blocks_for((cap_i + 3) / 4, 256)), dim3(256), 0, st, pp);
 }
 
 template <typename T> void launch_collide(const PassArgs<T> &a, hipStream_t st)
