@@ -450,9 +450,16 @@ template <typename T> struct PassOcc {
 // the inductive kick dt (q/m) E_theta(t_n) is explicit, and the filter turns
 // with the velocity at the move; no collision candidates (the corrector
 // takes them).
+#ifndef PIC_PASS_GATHER_AHEAD
+#define PIC_PASS_GATHER_AHEAD 1
+#endif
+#ifndef PIC_PASS_PREFETCH_RUN
+#define PIC_PASS_PREFETCH_RUN 1
+#endif
 template <typename T, bool PUSH, bool DEPQ, bool RFB, bool DI>
 __global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassPair<T> pp)
 {
+    constexpr bool GATHER_AHEAD = PIC_PASS_GATHER_AHEAD != 0 && sizeof(T) == 4;   // FP64: no registers to spare
     // one grid for both species: blocks [0, nb0) take the electrons' chunks,
     // the rest the ions', so the ions' blocks fill the CUs as the electrons'
     // drain instead of waiting for a second launch
@@ -551,6 +558,7 @@ __global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassPair<T> p
 
     for (int r = 0; r < RUNS; ++r) {
         const int64_t q0 = wbase + (int64_t)r * (RUN * 64) + RUN * lane;
+        if (!PIC_PASS_PREFETCH_RUN && r > 0) load_run(q0);
         bool live[RUN];
 #pragma unroll
         for (int k = 0; k < RUN; ++k) live[k] = q0 + k < c1 && cell[k] >= 0;
@@ -561,15 +569,42 @@ __global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassPair<T> p
         uint32_t abs_bits = 0;    // bit k: particle k of the run was absorbed
         uint32_t cand_bits = 0;
         bool moved = false;   // a particle of the run changed cell (or was absorbed)
+        // field nodes one particle ahead: the next particle's four node loads
+        // are in flight while this one is pushed and deposited, so a run
+        // waits on one cache round trip instead of four
+        F4 n00, n01, n10, n11;
+        auto gather_nodes = [&](int k) {
+            int key = 0;   // a dead slot reads node 0 and ignores it
+            if (live[k]) {
+                int i, j;
+                split_cell(g, cell[k], i, j);
+                key = i * g.nr1 + j;
+            }
+            n00 = a.ef[key];
+            n01 = a.ef[key + 1];
+            n10 = a.ef[key + g.nr1];
+            n11 = a.ef[key + g.nr1 + 1];
+        };
+        if constexpr (PUSH && GATHER_AHEAD) gather_nodes(0);
 #pragma unroll
         for (int k = 0; k < RUN; ++k) {
+            F4 c00, c01, c10, c11;
+            if constexpr (PUSH && GATHER_AHEAD) {
+                c00 = n00, c01 = n01, c10 = n10, c11 = n11;
+                if (k + 1 < RUN) gather_nodes(k + 1);
+            }
             if (PUSH && live[k]) {
                 int i, j;
                 split_cell(g, cell[k], i, j);
                 T w00, w01, w10, w11;
                 node_weights<T>(j, dr[k], dz[k], w00, w01, w10, w11);
                 const int key = i * g.nr1 + j;
-                const F4 f00 = a.ef[key], f01 = a.ef[key + 1], f10 = a.ef[key + g.nr1], f11 = a.ef[key + g.nr1 + 1];
+                F4 f00, f01, f10, f11;
+                if constexpr (GATHER_AHEAD) {
+                    f00 = c00, f01 = c01, f10 = c10, f11 = c11;
+                } else {
+                    f00 = a.ef[key], f01 = a.ef[key + 1], f10 = a.ef[key + g.nr1], f11 = a.ef[key + g.nr1 + 1];
+                }
                 const T er = w00 * f00.x + w01 * f01.x + w10 * f10.x + w11 * f11.x;
                 const T ez = w00 * f00.y + w01 * f01.y + w10 * f10.y + w11 * f11.y;
                 const T et = w00 * f00.z + w01 * f01.z + w10 * f10.z + w11 * f11.z;
@@ -774,7 +809,7 @@ __global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassPair<T> p
                 ++slot;
             }
         }
-        if (r + 1 < RUNS) load_run(q0 + RUN * 64);
+        if (PIC_PASS_PREFETCH_RUN && r + 1 < RUNS) load_run(q0 + RUN * 64);
         if constexpr (PUSH) {
             deposit4<T>(iJ >= 0, iJ, jJ, aJ[0], aJ[1], aJ[2], aJ[3], winJ, w, a.accJ, g.nr1, jscale, nout);
             // absorbed count of the wave, from one ballot per run position
