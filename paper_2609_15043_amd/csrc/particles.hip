@@ -459,7 +459,9 @@ template <typename T> struct PassOcc {
 template <typename T, bool PUSH, bool DEPQ, bool RFB, bool DI>
 __global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassPair<T> pp)
 {
-    constexpr bool GATHER_AHEAD = PIC_PASS_GATHER_AHEAD != 0 && sizeof(T) == 4;   // FP64: no registers to spare
+    // FP64: no registers to spare; RF magnetic field: its node loads would
+    // still wait per particle, and the ahead registers slowed that pass
+    constexpr bool GATHER_AHEAD = PIC_PASS_GATHER_AHEAD != 0 && sizeof(T) == 4 && !RFB;
     // one grid for both species: blocks [0, nb0) take the electrons' chunks,
     // the rest the ions', so the ions' blocks fill the CUs as the electrons'
     // drain instead of waiting for a second launch
