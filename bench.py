@@ -99,6 +99,7 @@ def run_gpu(wl, prec, steps, warmup, fuse=True):
                poisson_ms=s1.poisson_ms / max(1, s1.poisson_count),
                sort_ms=s1.sort_ms / max(1, s1.sort_count), sort_count=s1.sort_count,
                mg_cycles=int(s1.mg_cycles), mg_rel=s1.mg_rel, window_out=int(s1.window_out),
+               mg_unconverged=int(s1.mg_unconverged - s0.mg_unconverged),
                births=int(s1.births - s0.births))
     del ctx
     torch.cuda.empty_cache()
@@ -685,7 +686,8 @@ def next_steps(name, steps, warmup):
                 setattr(wl, k, v)
         r = run_gpu(wl, "mixed", steps, warmup)
         q = {"value": r["rate"], "unit": "particle-steps/s", "ms_per_step": r["ms_per_step"], "steps": steps,
-             "pass_ms": r["pass_ms"], "poisson_ms": r["poisson_ms"], "mg_cycles_last_solve": r["mg_cycles"]}
+             "pass_ms": r["pass_ms"], "poisson_ms": r["poisson_ms"], "mg_cycles_last_solve": r["mg_cycles"],
+             "mg_unconverged": r["mg_unconverged"]}
         if leg != "direct_implicit":
             q["pass_hbm_frac"] = BYTES_PER_PARTICLE_STEP["mixed"] * r["mean_live"] / (r["pass_ms"] * 1e-3) / 1e9 \
                 / HBM_PEAK_GBS
@@ -826,7 +828,7 @@ def main():
         "breakdown_ms": {"pass": r["pass_ms"], "poisson": r["poisson_ms"], "sort_per_species": r["sort_ms"],
                          "window_fallback_atomics": r["window_out"],
                          "species_sorts_per_step": r["sort_count"] / max(1, r["steps"]),
-                         "mg_cycles_last_solve": r["mg_cycles"]},
+                         "mg_cycles_last_solve": r["mg_cycles"], "mg_unconverged": r["mg_unconverged"]},
         "other_precision": other,
     }
     print(json.dumps(line), flush=True)

@@ -174,6 +174,10 @@ struct pic_ctx {
     MGState *mg_host = nullptr;   // pinned ring
     int mg_ring = 0;
     int mg_budget = 8;
+    // direct-implicit solves still to run at the full budget: the ring holds
+    // counts of solves with chi only after four of them (the solve at the
+    // load has chi = 0 and needs far fewer iterations)
+    int di_full = 4;
     // a circuit update moves the turn potentials by a whole period's
     // correction: the solves until the start-value extrapolation again spans
     // only solutions after the jump run max_cycles, and the extrapolation
@@ -1040,11 +1044,17 @@ static pic_status solve(pic_ctx &c, int64_t n, double rtol, int max_cycles, pic_
         // after a circuit update (or a restore) the recent counts say
         // nothing about this start value: full budget (iterations past
         // convergence are no-ops)
-        if (c.mg_fresh > 0) budget = max_cycles;
         // the direct-implicit operator changes with chi every step while the
-        // coarse levels precondition with the chi = 0 operator: the counts
-        // of earlier solves do not bound this one
-        if (c.cfg.implicit) budget = max_cycles;
+        // coarse levels precondition with the chi = 0 operator: one
+        // iteration beyond the explicit margin, and the full budget until a
+        // finished solve has been seen or after one that ran short (a full
+        // budget every step spent most of the solve in iterations past
+        // convergence, each a dozen launches that find the solve done)
+        if (c.cfg.implicit) {
+            budget = (c.di_full <= 0 && seen > 0 && !short_run) ? std::min(max_cycles, budget + 1) : max_cycles;
+            c.di_full = std::max(0, c.di_full - 1);
+        }
+        if (c.mg_fresh > 0) budget = max_cycles;
     }
     c.mg_fresh = std::max(0, c.mg_fresh - 1);
     // extrapolate only across consecutive steps of a running sequence: linear
@@ -2309,6 +2319,7 @@ extern "C" pic_status pic_restore(pic_ctx *c, const void *buf, size_t bytes)
     c->run = h.run;
     c->mg_budget = h.mg_budget;
     c->mg_fresh = std::max(h.mg_fresh, 1);
+    c->di_full = 4;   // the ring does not travel with the checkpoint
     c->mg_restart = h.mg_restart != 0;
     // host mirrors of what the device arrays now hold
     const size_t M = c->M;

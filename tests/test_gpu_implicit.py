@@ -139,3 +139,53 @@ def test_implicit_call_order():
     cfg, keep = pp.config_from_workload(wl, precision="fp64", load=False)
     with pytest.raises(pp.PicError):
         pp.pic_init(cfg, keep)
+
+
+def test_implicit_stepping_budget_converges():
+    """The stepping solves (no info requested) take their iteration budget
+    from the counts of recent solves: the full budget for the first four
+    solves with chi, then one iteration beyond the explicit path's margin.
+    Over 24 steps of the small instance in the implicit regime (dt = 2e-10 s,
+    chi up to 3.2) no solve may end short of rtol, and the particles must
+    agree with a run whose every solve has the full budget (requested with
+    info).  The two runs differ in the solves' start values (the stepping
+    solves extrapolate from the previous solutions), so they agree to the
+    solve tolerance carried through the steps, not bitwise; a solve that ran
+    short leaves errors of 1e-4 and more."""
+    _need_gpu()
+    import paper_2609_15043_amd.phasorpic as pp
+    from paper_2609_15043_amd import workloads as W
+    from test_gpu_parity import _compare_particles
+    wl = W.small(n_per_species=60_000)
+    wl.dt = 2e-10
+    wl.implicit = True
+    steps = 24
+    say(f"[gpu] direct-implicit stepping budget, small instance, {steps} steps")
+    ctxs = []
+    for full in (False, True):
+        cfg, keep = pp.config_from_workload(wl, precision="fp64", load=True, mg_rtol=1e-15, mg_max_cycles=60)
+        ctx = pp.pic_init(cfg, keep)
+        cycles = []
+        for n in range(steps):
+            pp.pic_gather_push(ctx, n)
+            pp.harmonic_accumulate(ctx, n)
+            pp.pic_deposit(ctx, n + 1)
+            if full:
+                info = pp.poisson_solve_rz(ctx, n + 1, info=True)
+                assert info["converged"], (n, info)
+                cycles.append(info["cycles"])
+            else:
+                pp.poisson_solve_rz(ctx, n + 1)
+            pp.mcc_collide(ctx, n)
+        pp.pic_sync(ctx)
+        ctxs.append((ctx, cycles))
+    st = pp.pic_get_stats(ctxs[0][0])
+    say(f"    full-budget iterations per solve: {ctxs[1][1]}; stepping run: unconverged solves {st.mg_unconverged}")
+    assert st.mg_unconverged == 0
+    worst = 0.0
+    for s in range(2):
+        a, b = pp.pic_get_particles(ctxs[0][0], s), pp.pic_get_particles(ctxs[1][0], s)
+        errs, _ = _compare_particles(a, b, "fp64", f"s={s}", tol=math.inf)
+        worst = max(worst, max(errs.values()))
+    say(f"    largest particle difference between the two runs {worst:.1e}")
+    assert worst <= 1e-8
