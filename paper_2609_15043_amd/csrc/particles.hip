@@ -1753,8 +1753,8 @@ void launch_correct(const PassArgs<T> &e, const PassArgs<T> &i, int64_t cap_e, i
     PassPair<T> pp;
     pp.a[0] = e;
     pp.a[1] = i;
-    // four particles per lane (the arrays are padded to whole 4096-particle
-    // chunks, so the last lane's four slots exist)
+    // four particles per lane (the arrays are padded to whole pass chunks,
+    // so the last lane's four slots exist)
     pp.nb0 = blocks_for((cap_e + 3) / 4, 256);
     hipLaunchKernelGGL(k_correct<T>, dim3(pp.nb0 + blocks_for((cap_i + 3) / 4, 256)), dim3(256), 0, st, pp);
 }
