@@ -35,9 +35,20 @@ constexpr int RUN = 4;                  // consecutive particles per lane per ve
 #ifndef PIC_PASS_RUNS
 #define PIC_PASS_RUNS 8
 #endif
-constexpr int RUNS = PIC_PASS_RUNS;     // runs per wave per block
-constexpr int CHUNK = BLOCK * RUN * RUNS;   // particles per pass block (8192)
-constexpr int PAD = CHUNK;              // particle capacities are padded to this multiple
+// the FP64 pass (3 waves per SIMD, plain stream accesses) is fastest at 4
+#ifndef PIC_PASS_RUNS_F64
+#define PIC_PASS_RUNS_F64 4
+#endif
+// runs per wave per block and particles per pass block, per precision
+template <typename T> struct PassShape {
+    static constexpr int runs = sizeof(T) == 4 ? PIC_PASS_RUNS : PIC_PASS_RUNS_F64;
+    static constexpr int chunk = BLOCK * RUN * runs;
+};
+// particle capacities are padded to a multiple of both chunks
+constexpr int PAD = PassShape<float>::chunk > PassShape<double>::chunk ? PassShape<float>::chunk
+                                                                        : PassShape<double>::chunk;
+static_assert(PAD % PassShape<float>::chunk == 0 && PAD % PassShape<double>::chunk == 0,
+              "the padding must hold whole chunks of either precision");
 
 // Counter slots (int64) in the device statistics block.
 enum StatSlot {

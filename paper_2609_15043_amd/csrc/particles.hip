@@ -408,10 +408,27 @@ __device__ __forceinline__ void ld4(const float *p, float (&o)[4])
     const f4 v = ldv(reinterpret_cast<const f4 *>(p));
     o[0] = v.x, o[1] = v.y, o[2] = v.z, o[3] = v.w;
 }
+// FP64 stream: plain loads and stores (pass 1.428 ms per launch against 1.453
+// with the hint on both and 1.470 with it on the loads alone; its two
+// 16-byte stores per run wrote 9 % more to HBM with the hint)
+#ifndef PIC_STREAM_NT_F64_LOAD
+#define PIC_STREAM_NT_F64_LOAD 0
+#endif
+#ifndef PIC_STREAM_NT_F64_STORE
+#define PIC_STREAM_NT_F64_STORE 0
+#endif
 __device__ __forceinline__ void ld4(const double *p, double (&o)[4])
 {
     typedef double d2 __attribute__((ext_vector_type(2)));
-    const d2 u = ldv(reinterpret_cast<const d2 *>(p)), v = ldv(reinterpret_cast<const d2 *>(p + 2));
+    const d2 *q = reinterpret_cast<const d2 *>(p);
+    d2 u, v;
+    if constexpr (PIC_STREAM_NT_F64_LOAD != 0) {
+        u = ldv(q);
+        v = ldv(q + 1);
+    } else {
+        u = q[0];
+        v = q[1];
+    }
     o[0] = u.x, o[1] = u.y, o[2] = v.x, o[3] = v.y;
 }
 __device__ __forceinline__ void ld4(const int32_t *p, int32_t (&o)[4])
@@ -428,8 +445,14 @@ __device__ __forceinline__ void st4(float *p, const float (&o)[4])
 __device__ __forceinline__ void st4(double *p, const double (&o)[4])
 {
     typedef double d2 __attribute__((ext_vector_type(2)));
-    stv(reinterpret_cast<d2 *>(p), d2{o[0], o[1]});
-    stv(reinterpret_cast<d2 *>(p + 2), d2{o[2], o[3]});
+    d2 *q = reinterpret_cast<d2 *>(p);
+    if constexpr (PIC_STREAM_NT_F64_STORE != 0) {
+        stv(q, d2{o[0], o[1]});
+        stv(q + 1, d2{o[2], o[3]});
+    } else {
+        q[0] = d2{o[0], o[1]};
+        q[1] = d2{o[2], o[3]};
+    }
 }
 __device__ __forceinline__ void st4(int32_t *p, const int32_t (&o)[4])
 {
@@ -486,6 +509,7 @@ __global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassPair<T> p
     // FP64: no registers to spare; RF magnetic field: its node loads would
     // still wait per particle, and the ahead registers slowed that pass
     constexpr bool GATHER_AHEAD = PIC_PASS_GATHER_AHEAD != 0 && sizeof(T) == 4 && !RFB;
+    constexpr int RUNS = PassShape<T>::runs, CHUNK = PassShape<T>::chunk;
     // one grid for both species: blocks [0, nb0) take the electrons' chunks,
     // the rest the ions', so the ions' blocks fill the CUs as the electrons'
     // drain instead of waiting for a second launch
@@ -1728,8 +1752,8 @@ void launch_pass(const PassArgs<T> &e, const PassArgs<T> &i, int64_t cap_e, int6
     PassPair<T> pp;
     pp.a[0] = e;
     pp.a[1] = i;
-    pp.nb0 = blocks_for(cap_e, CHUNK);
-    const dim3 grid(pp.nb0 + blocks_for(cap_i, CHUNK)), blk(BLOCK);
+    pp.nb0 = blocks_for(cap_e, PassShape<T>::chunk);
+    const dim3 grid(pp.nb0 + blocks_for(cap_i, PassShape<T>::chunk)), blk(BLOCK);
     const bool rfb = e.eb != nullptr, di = e.p.fr != nullptr;
     if (push && depq && di)
         hipLaunchKernelGGL((k_pass<T, true, true, false, true>), grid, blk, 0, st, pp);
