@@ -958,16 +958,32 @@ template <typename T> __global__ __launch_bounds__(256) void k_correct(PassPair<
         ld4(a.p.ft + p0, ft);
         ld4(a.p.fz + p0, fz);
         ld4(a.p.next + p0, nxt);
+        // field nodes one particle ahead, as in the pass (the next particle's
+        // node loads are in flight while this one is corrected)
+        F4 n00, n01, n10, n11;
+        auto gather_nodes = [&](int k) {
+            int key = 0;   // a dead slot reads node 0 and ignores it
+            if (p0 + k < n && cell[k] >= 0) {
+                int i, j;
+                split_cell(g, cell[k], i, j);
+                key = i * g.nr1 + j;
+            }
+            n00 = a.ef[key];
+            n01 = a.ef[key + 1];
+            n10 = a.ef[key + g.nr1];
+            n11 = a.ef[key + g.nr1 + 1];
+        };
+        gather_nodes(0);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
+            const F4 f00 = n00, f01 = n01, f10 = n10, f11 = n11;
+            if (k + 1 < 4) gather_nodes(k + 1);
             if (p0 + k >= n || cell[k] < 0) continue;
             int i, j;
             split_cell(g, cell[k], i, j);
             const T dr0 = dr[k], dz0 = dz[k];
             T w00, w01, w10, w11;
             node_weights<T>(j, dr0, dz0, w00, w01, w10, w11);
-            const int key = i * g.nr1 + j;
-            const F4 f00 = a.ef[key], f01 = a.ef[key + 1], f10 = a.ef[key + g.nr1], f11 = a.ef[key + g.nr1 + 1];
             const T er = w00 * f00.x + w01 * f01.x + w10 * f10.x + w11 * f11.x;
             const T ez = w00 * f00.y + w01 * f01.y + w10 * f10.y + w11 * f11.y;
             const T h = sc_val<T>(a.sc.h, a.sc.hf);
