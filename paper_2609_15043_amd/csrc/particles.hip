@@ -503,6 +503,9 @@ template <typename T> struct PassOcc {
 #ifndef PIC_PASS_PREFETCH_RUN
 #define PIC_PASS_PREFETCH_RUN 1
 #endif
+#ifndef PIC_PASS_WINDOW_FROM_RUN
+#define PIC_PASS_WINDOW_FROM_RUN 1
+#endif
 template <typename T, bool PUSH, bool DEPQ, bool RFB, bool DI>
 __global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassPair<T> pp)
 {
@@ -568,10 +571,18 @@ __global__ __launch_bounds__(BLOCK) PIC_PASS_OCCUPANCY void k_pass(PassPair<T> p
     load_run(wbase + RUN * lane);
 
     if (tid < 64) {
-        // window centre: mean row of 64 particles sampled across the chunk
-        // (one hot particle far from the rest cannot shift it by much)
-        const int64_t q = c0 + (int64_t)tid * (CHUNK / 64);
-        const int cl = q < c1 ? a.p.cell[q] : -1;
+        // window centre: mean row of 64 particles (one hot particle far from
+        // the rest cannot shift it by much).  Taken from the first particle
+        // of each lane's first run, already loaded by wave 0, rather than from
+        // 64 extra scattered loads across the chunk (one 128-byte line each,
+        // about 1 B per particle of extra traffic)
+        int cl;
+        if constexpr (PIC_PASS_WINDOW_FROM_RUN != 0) {
+            cl = c0 + RUN * tid < c1 ? cell[0] : -1;
+        } else {
+            const int64_t q = c0 + (int64_t)tid * (CHUNK / 64);
+            cl = q < c1 ? a.p.cell[q] : -1;
+        }
         int ci = 0, cj = 0;
         if (cl >= 0) split_cell(g, cl, ci, cj);
         const float sr = wave_total(cl >= 0 ? (float)ci : 0.f);
